@@ -1,0 +1,222 @@
+/*
+ * pf.h -- C ABI of the MI355X (gfx950) library for one explicit time step of
+ * the 3D time-dependent Ginzburg-Landau (TDGL) equation of a ferroelectric
+ * film, after Ashraf & Salahuddin, "A Massively Parallel Time Domain Phase
+ * Field Model for Multi-domain Ferroelectric Device Simulation",
+ * arXiv:1202.6116.
+ *
+ * The step (Sec. II and III of the paper) combines
+ *   - the Landau bulk force (Eq. 1),
+ *   - the gradient (domain-wall) force, a 7-point Laplacian (Eq. 2-3),
+ *   - the electrostatic field E = -grad phi with eps Lap phi = div P (Eq. 4-5,
+ *     17-18), solved by Jacobi-preconditioned conjugate gradients,
+ *   - the elastic force of the electrostrictive eigenstrain (Eq. 6, 15),
+ *     with the displacement from a trilinear-hex FEM solve K u = f (Eq. 8-16),
+ *     also by Jacobi-preconditioned conjugate gradients,
+ *   - the predictor-corrector of Eq. 19 (rate carried as state) or forward
+ *     Euler.
+ *
+ * Conventions.
+ *   Grid: nodes (i, j, k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz, spacing h,
+ *   linear index n = i + nx (j + ny k) (the paper's natural numbering, x
+ *   fastest).  Periodic in x and y.  k = 0 is the substrate side (mechanically
+ *   clamped), k = nz - 1 the free top surface.
+ *   Vector fields (P, V, u, forces) are structure-of-arrays: component c of
+ *   node n at element c*N + n, N = nx ny nz.  Scalar fields (phi) have N
+ *   elements.
+ *   Potential boundary values live on two ghost planes one spacing outside
+ *   the film: k = -1 holds phi_bottom, k = nz holds phi_top except where an
+ *   electrode covers it (Sec. III.C, Dirichlet electrodes).
+ *   Voigt order (xx, yy, zz, xy, yz, zx) with engineering shear (Eq. 12).
+ *
+ * Precision.  PF_FP64: every array is double.  PF_FP32_REFINE: P, V and
+ *   forces are float, phi and u are double (the refined masters); the sweeps
+ *   run in float, dot products and the outer residuals in double.
+ *
+ * Memory.  The caller owns all device memory: the state arrays it passes in
+ *   and one workspace of pf_workspace_size() bytes (256-byte aligned).  The
+ *   library never allocates or frees device memory.  It allocates a small
+ *   pinned host block per context (status read-back).
+ *
+ * Streams.  Every call enqueues on the stream given to pf_init and returns
+ *   without waiting, except calls that return host values (pf_step and the
+ *   solves, which read back iteration counts; pf_energy), which synchronise
+ *   that stream.
+ *
+ * Errors.  Every call returns a pf_status; nothing is thrown across the ABI.
+ *   pf_last_error() describes the last failure of a context.  A context is
+ *   not thread-safe: use one per host thread.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PF_OK = 0,
+  PF_EINVAL = -1,      /* invalid argument or configuration */
+  PF_ENOMEM = -2,      /* workspace too small */
+  PF_EHIP = -3,        /* HIP runtime error */
+  PF_ENOCONV = -4,     /* a CG solve hit maxit; results are the last iterate */
+  PF_ENONFINITE = -5,  /* NaN/Inf found in a reduction; results are undefined */
+  PF_ESTATE = -6       /* call out of order (e.g. pf_step before pf_set_state) */
+} pf_status;
+
+/* terms: which contributions enter the force (tests switch terms off) */
+enum { PF_TERM_LANDAU = 1, PF_TERM_GRAD = 2, PF_TERM_ELEC = 4, PF_TERM_ELAS = 8, PF_TERM_ALL = 15 };
+/* integrator */
+enum { PF_INT_PC = 0, PF_INT_EULER = 1 };
+/* precision */
+enum { PF_FP64 = 0, PF_FP32_REFINE = 1 };
+
+/* An electrode: the half-open node rectangle [x0, x1) x [y0, y1) of the top
+ * ghost plane held at `volts` (Sec. III.C).  Electrodes must not overlap. */
+typedef struct {
+  int32_t x0, x1, y0, y1;
+  double volts;
+} pf_electrode;
+
+typedef struct {
+  int32_t nx, ny, nz;           /* nx, ny >= 3, nz >= 3 */
+  double h;                     /* grid spacing (> 0) */
+  double a1, a11, a12;          /* Landau coefficients, Eq. 1 */
+  double G;                     /* gradient coefficient G11, Eq. 2-3 */
+  double L;                     /* mobility: dP/dt = -L dF/dP, Eq. 7 */
+  double dt;                    /* time step (> 0), Eq. 19 */
+  double eps_b;                 /* permittivity in Eq. 18 (> 0) */
+  double phi_bottom, phi_top;   /* ghost-plane potentials */
+  int32_t n_electrodes;         /* 0..64 */
+  const pf_electrode *electrodes;  /* host array, copied by pf_init */
+  double C11, C12, C44;         /* cubic elastic stiffness (Eq. 13 generalised) */
+  double Q11, Q12, Q44;         /* electrostriction, Eq. 15 */
+  int32_t integrator;           /* PF_INT_PC (default) or PF_INT_EULER */
+  int32_t precision;            /* PF_FP64 or PF_FP32_REFINE */
+  double tol_phi, tol_u;        /* CG stop: ||b - A x||_2 <= tol ||b||_2 */
+  int32_t maxit;                /* CG iteration cap per solve (> 0) */
+  int32_t warm_start;           /* 1: each solve starts from the previous solution */
+  uint32_t terms;               /* PF_TERM_* mask */
+  int32_t nonlocal_every;       /* refresh phi and u every k steps (<= 1: every
+                                   step), the paper's Fig. 3d option */
+} pf_config;
+
+typedef struct {
+  int32_t iters;      /* CG iterations (FP32_REFINE: inner iterations, summed) */
+  int32_t outer;      /* refinement sweeps (FP32_REFINE), 1 in FP64 */
+  double relres;      /* final ||b - A x|| / ||b|| (recursive residual) */
+} pf_solve_stats;
+
+typedef struct {
+  int32_t steps;                 /* steps taken by the call */
+  int64_t iters_phi, iters_u;    /* CG iterations summed over the call */
+  int32_t last_iters_phi, last_iters_u;
+  int32_t solves_phi, solves_u;  /* solves performed (nonlocal_every skips some) */
+  double relres_phi, relres_u;   /* largest final relative residual */
+} pf_step_stats;
+
+typedef struct pf_ctx pf_ctx;
+
+/* Bytes of device workspace a context for `cfg` needs (for all calls,
+ * including pf_energy and the adjoint).  Validates cfg. */
+pf_status pf_workspace_size(const pf_config *cfg, size_t *bytes);
+
+/* Binds a context to cfg, a device workspace of at least
+ * pf_workspace_size() bytes (256-byte aligned, owned by the caller, must
+ * outlive the context) and a HIP stream (NULL: the null stream).  Builds the
+ * FEM operator tables and solves the electrode basis potentials (one Poisson
+ * solve per electrode plus one for the fixed boundary values), then waits
+ * for the stream.  *out is set on success. */
+pf_status pf_init(const pf_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream, pf_ctx **out);
+
+/* Loads the polarisation P (device, 3N) as the current state, with optional
+ * initial guesses phi0 (N doubles) and u0 (3N doubles) for the first solves
+ * (NULL: zero).  For the predictor-corrector it solves phi and u at P and
+ * sets the carried rate V0 = F(P) (the paper does not state V0; this is the
+ * reading taken).  Synchronises.  Resets the step counter to 0. */
+pf_status pf_set_state(pf_ctx *ctx, const void *P, const void *phi0, const void *u0);
+
+/* Restores a full state saved by pf_get_state (P, V: state precision; phi,
+ * u: double; none may be NULL) and the step counter.  Asynchronous. */
+pf_status pf_restore_state(pf_ctx *ctx, const void *P, const void *V, const void *phi, const void *u, int64_t step);
+
+/* Copies the current state into caller arrays (any may be NULL): P and V
+ * (3N, state precision), phi (N doubles), u (3N doubles).  Asynchronous. */
+pf_status pf_get_state(const pf_ctx *ctx, void *P, void *V, void *phi, void *u, int64_t *step);
+
+/* Advances the state by nsteps (Eq. 19 or forward Euler): per step one
+ * Poisson solve and one FEM solve (both warm-started when configured; every
+ * nonlocal_every steps only), and one fused force + update sweep.
+ * Synchronises at least once per solve to read convergence.  stats may be
+ * NULL.  Returns PF_ENOCONV if some solve hit maxit (the step still
+ * completes), PF_ENONFINITE on NaN/Inf (the state is then undefined). */
+pf_status pf_step(pf_ctx *ctx, int32_t nsteps, pf_step_stats *stats);
+
+/* Poisson solve for a given polarisation P (device, 3N, state precision):
+ * eps_b Lap_h phi = div_h P with the ghost-plane boundary values.  phi
+ * (device, N doubles) is the initial guess when warm_start is set and
+ * receives the solution.  Synchronises. */
+pf_status pf_solve_phi(pf_ctx *ctx, const void *P, void *phi, pf_solve_stats *stats);
+
+/* FEM solve K u = f(P) for a given polarisation (Eq. 15-16): clamped k = 0
+ * (u = 0 there), free top, periodic x and y.  u (device, 3N doubles) is the
+ * initial guess when warm_start is set and receives the solution.
+ * Synchronises. */
+pf_status pf_solve_u(pf_ctx *ctx, const void *P, void *u, pf_solve_stats *stats);
+
+/* Force F = -L dF/dP at P (Eq. 7 without noise) for given phi (N doubles)
+ * and u (3N doubles), written to F (3N, state precision).  No solves.
+ * Asynchronous. */
+pf_status pf_force(pf_ctx *ctx, const void *P, const void *phi, const void *u, void *F);
+
+/* Free energy of the current P: out[0..4] = bulk, gradient, electrostatic,
+ * elastic, total (host doubles).  Solves phi and u at P (warm-started from
+ * the state's solutions, to the configured tolerances) and splits the
+ * electrostatic energy into the polarisation part and the applied part
+ * (linear superposition with the electrode basis).  Synchronises. */
+pf_status pf_energy(pf_ctx *ctx, double out[5]);
+
+/* Changes electrode voltages (n_electrodes host doubles, NULL: keep) and
+ * the Landau coefficient a1 (used by the differentiable layer). */
+pf_status pf_set_params(pf_ctx *ctx, const double *volts, double a1);
+
+/* One reverse step of the discrete adjoint of pf_step.  In: the state
+ * (P_n, V_n) before forward step n (device, 3N each, state precision; V_n is
+ * ignored for Euler) and the adjoints (lamP, lamV) of the state after it;
+ * out: lamP, lamV overwritten by the adjoints of the state before it, and
+ * dtheta (host, n_electrodes + 1 doubles: dJ/dV_1..dJ/dV_ne, dJ/da1)
+ * accumulated.  Re-solves u at the linearisation point (warm-started), then
+ * one adjoint Poisson and one adjoint FEM solve.  Synchronises. */
+pf_status pf_adjoint_step(pf_ctx *ctx, const void *P_n, const void *V_n, void *lamP, void *lamV, double *dtheta);
+
+/* Folds the initial rate V0 = F(P0) of the predictor-corrector into the
+ * adjoints: lamP += (dF/dP)(P0) lamV, dtheta += lamV . dF/dtheta(P0),
+ * lamV = 0.  No-op for Euler.  Synchronises. */
+pf_status pf_adjoint_initial_rate(pf_ctx *ctx, const void *P0, void *lamP, void *lamV, double *dtheta);
+
+/* Diagnostic (host only, no GPU needed): the constant 27-point operator
+ * tables the kernels use for cfg, as doubles in this order:
+ *   K[2][3][3][27]   stiffness rows, interior planes then the top plane:
+ *                    (K u)_c = sum_e sum_o K[z][c][e][o] u_e(n + o)
+ *   Bf[2][3][6][27]  body force of a nodal Voigt stress sigma0 = C eps0
+ *   Su[3][6][3][27]  int N_n eps_v(u) for bottom, interior, top planes
+ *   Ms[3][27]        consistent mass for bottom, interior, top planes
+ * with offset o = (dx+1) + 3 (dy+1) + 9 (dz+1).  `count` is the capacity of
+ * out in doubles; needs at least pf_fem_table_size() of them. */
+size_t pf_fem_table_size(void);
+pf_status pf_fem_tables(const pf_config *cfg, double *out, size_t count);
+
+const char *pf_status_str(pf_status s);
+const char *pf_last_error(const pf_ctx *ctx);
+
+/* Releases the context's host state (not the caller's device memory). */
+void pf_destroy(pf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_H */

@@ -1,0 +1,93 @@
+// Internal declarations shared by the host layer (pf_api.cpp) and the HIP
+// kernels (pf_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pf {
+
+// Threads per block of the node kernels: 64 along x (one wavefront per
+// x-row segment, coalesced), 4 rows along y.  Grid: (ceil(nx/64),
+// ceil(ny/4), nz), one thread per node.
+constexpr int kBX = 64;
+constexpr int kBY = 4;
+constexpr int kThreads = kBX * kBY;
+
+// Offsets of a 27-point stencil are numbered o = (dx+1) + 3 (dy+1) + 9 (dz+1).
+constexpr int kTaps = 27;
+
+// Row types along z.  The clamped plane k = 0 has only the element above it
+// (kLow), planes 1..nz-2 are interior, the free top plane k = nz-1 has only
+// the element below it (kHigh).
+enum ZType { kLow = 0, kInterior = 1, kHigh = 2 };
+
+// Constant operator tables of the trilinear-hex FEM on the uniform grid,
+// built on the host from 1D element integrals.  Stored in the workspace and
+// read by the kernels with uniform (scalar) loads.
+struct FemTables {
+  // Stiffness stencil K^{cd}(o): rows of interior planes [0], top plane [1].
+  double K[2][3][3][kTaps];
+  // Body force of a nodal stress field sigma0 = C eps0 (Voigt v):
+  // f_c = sum_v Bf[.][c][v](o) sigma0_v; interior [0], top [1].
+  double Bf[2][3][6][kTaps];
+  // Weighted strain of a displacement field: (int N_n eps_v(u)) =
+  // sum_c Su[z][v][c](o) u_c, z in {kLow, kInterior, kHigh}.
+  double Su[3][6][3][kTaps];
+  // Consistent mass M x M x M, z in {kLow, kInterior, kHigh}.
+  double Ms[3][kTaps];
+  // Inverse Jacobi diagonal of K for interior and top rows (all components).
+  double inv_diag[2];
+};
+
+// Scalars of one conjugate-gradient solve, resident in device memory.  The
+// last block of each reduction kernel updates them; every kernel of a solve
+// reads them at entry and returns at once when `done` is set.
+struct CgScalars {
+  double rho;            // r.z of the current residual
+  double alpha;          // step length, applied to x lazily by the next kernel
+  double beta;           // conjugation factor for the next direction
+  double bnorm2;         // ||b||^2
+  double rnorm2;         // ||r||^2 of the current residual
+  double tol;            // relative tolerance
+  int32_t iter;          // iterations completed
+  int32_t maxit;
+  int32_t done;          // 0 running, 1 converged, 2 iteration cap, 3 non-finite
+  int32_t zero_rhs;      // b == 0: the solution is x = 0
+  uint32_t counter;      // last-block ticket counter (reset by the last block)
+  int32_t pad;
+};
+
+enum CgDone { kRunning = 0, kConverged = 1, kMaxIt = 2, kNonFinite = 3 };
+
+// Per-call description of the node grid.
+struct Dims {
+  int nx, ny, nz;
+  int64_t N;        // nodes
+  int64_t plane;    // nx * ny
+};
+
+// Material and model coefficients used inside kernels.
+template <typename T>
+struct Coefs {
+  T a1, a11, a12;       // Landau
+  T G, L, dt;           // gradient, mobility, time step
+  T h, inv_h2, inv_2h, inv_h3;
+  T eps_over_h2;        // eps_b / h^2
+  T inv_diag_poisson;   // h^2 / (6 eps_b)
+  T C11, C12, C44, Q11, Q12, Q44;
+  T phi_bottom;
+  uint32_t terms;
+};
+
+enum Terms { kLandau = 1, kGrad = 2, kElec = 4, kElas = 8 };
+
+// What the force kernel does with the force F at the evaluation point.
+enum ForceMode {
+  kForceOut = 0,     // F written to an output array
+  kPcInit = 1,       // V = F
+  kPcStep = 2,       // V' = (V + F)/2, P' = P + dt V'
+  kEulerStep = 3,    // P' = P + dt F
+};
+
+}  // namespace pf

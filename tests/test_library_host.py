@@ -1,0 +1,142 @@
+"""Host-side checks of the HIP library (no GPU needed): exported symbols,
+configuration validation, and the constant FEM stencil tables the kernels
+use, compared with the oracle's element-by-element assembly (Eq. 8-16)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1202_6116_amd import pf
+from paper_1202_6116_amd.workloads import PFConfig, Electrode, random_field
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "pf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pf.lib()
+    syms = header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(pf.EXPORTS) == syms
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nz=2), dict(nx=2), dict(dt=0.0), dict(h=-1.0), dict(eps_b=0.0), dict(tol_phi=0.0), dict(maxit=0),
+    dict(electrodes=[Electrode(0, 4, 0, 4, 1.0), Electrode(2, 6, 1, 3, -1.0)]),     # overlap
+    dict(electrodes=[Electrode(30, 40, 0, 4, 1.0)]),                                # out of range
+    dict(electrodes=[Electrode(5, 5, 0, 4, 1.0)]),                                  # empty
+    dict(C12=2.0), dict(terms=16), dict(integrator="leapfrog"),
+])
+def test_invalid_configurations_are_rejected(bad):
+    cfg = PFConfig(nx=32, ny=8, nz=4)
+    if "integrator" in bad:
+        c, keep = pf.make_config(cfg)
+        c.integrator = 7
+        n = ctypes.c_size_t()
+        assert pf.lib().pf_workspace_size(ctypes.byref(c), ctypes.byref(n)) == pf.PF_EINVAL
+        return
+    with pytest.raises(pf.PFError) as ei:
+        pf.pf_workspace_size(cfg.replace(**bad))
+    assert ei.value.status == pf.PF_EINVAL
+
+
+def test_workspace_size_scales_with_grid():
+    a = pf.pf_workspace_size(PFConfig(nx=32, ny=32, nz=8))
+    b = pf.pf_workspace_size(PFConfig(nx=64, ny=32, nz=8))
+    assert 1.8 < b / a < 2.2
+    assert a % 256 == 0
+
+
+def test_status_strings():
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert pf.status_str(s)
+
+
+# ---------------------------------------------------------------------------
+# FEM tables vs the oracle
+# ---------------------------------------------------------------------------
+
+def tap(o):
+    return (o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1)
+
+
+def voigt_C(cfg):
+    C = np.zeros((6, 6))
+    C[:3, :3] = cfg.C12
+    np.fill_diagonal(C[:3, :3], cfg.C11)
+    C[3, 3] = C[4, 4] = C[5, 5] = cfg.C44
+    return C
+
+
+@pytest.mark.parametrize("h", [1.0, 0.6])
+def test_stiffness_table_matches_oracle_assembly(oracle_mod, h):
+    cfg = PFConfig(nx=5, ny=5, nz=5, h=h, C11=1.7, C12=0.8, C44=0.5)
+    K = oracle_mod.Oracle(cfg).fem_assemble("nodewise")
+    t = pf.pf_fem_tables(cfg)["K"]
+    N = cfg.nodes
+    for zt, k in ((0, 2), (1, 4)):
+        n = 2 + 5 * (2 + 5 * k)
+        for c in range(3):
+            row = K[c * N + n]
+            ref = np.zeros((3, 27))
+            for e in range(3):
+                for o in range(27):
+                    dx, dy, dz = tap(o)
+                    if not 0 <= k + dz < cfg.nz:
+                        continue
+                    m = (2 + dx) + 5 * ((2 + dy) + 5 * (k + dz))
+                    ref[e, o] = row[e * N + m]
+            np.testing.assert_allclose(t[zt, c], ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+
+
+def test_body_force_table_matches_oracle(oracle_mod):
+    cfg = PFConfig(nx=5, ny=4, nz=5, h=0.8)
+    o = oracle_mod.Oracle(cfg)
+    e0 = random_field((6,) + cfg.shape, 21)
+    f = o.fem_rhs_e0(e0)
+    sig = np.einsum("vw,wzyx->vzyx", voigt_C(cfg), e0)
+    Bf = pf.pf_fem_tables(cfg)["Bf"]
+    for zt, k in ((0, 1), (0, 3), (1, 4)):
+        for j in range(cfg.ny):
+            for i in range(cfg.nx):
+                acc = np.zeros(3)
+                for oo in range(27):
+                    dx, dy, dz = tap(oo)
+                    if not 0 <= k + dz < cfg.nz:
+                        continue
+                    acc += Bf[zt, :, :, oo] @ sig[:, k + dz, (j + dy) % cfg.ny, (i + dx) % cfg.nx]
+                np.testing.assert_allclose(acc, f[:, k, j, i], rtol=0, atol=1e-13)
+
+
+def test_stress_tables_match_oracle(oracle_mod):
+    cfg = PFConfig(nx=4, ny=5, nz=5, h=1.3)
+    o = oracle_mod.Oracle(cfg)
+    e0 = random_field((6,) + cfg.shape, 31)
+    u = random_field((3,) + cfg.shape, 32)
+    u[:, 0] = 0
+    from oracle.pf_oracle import _ptr
+    s = np.zeros((6,) + cfg.shape)
+    o.lib.or_stress_gather_e0.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    o.lib.or_stress_gather_e0(o.pp, e0.ctypes.data, u.ctypes.data, s.ctypes.data)
+    tb = pf.pf_fem_tables(cfg)
+    C = voigt_C(cfg)
+    for zt, k in ((0, 0), (1, 2), (2, 4)):
+        for j in range(cfg.ny):
+            for i in range(cfg.nx):
+                w = np.zeros(6)
+                for oo in range(27):
+                    dx, dy, dz = tap(oo)
+                    if not 0 <= k + dz < cfg.nz:
+                        continue
+                    m = (k + dz, (j + dy) % cfg.ny, (i + dx) % cfg.nx)
+                    w += tb["Su"][zt, :, :, oo] @ u[(slice(None),) + m] - tb["Ms"][zt, oo] * e0[(slice(None),) + m]
+                np.testing.assert_allclose(C @ w, s[:, k, j, i], rtol=0, atol=1e-12)
