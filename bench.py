@@ -1,0 +1,173 @@
+"""Throughput of the TDGL step (Landau + gradient + Poisson PCG + hex8-FEM PCG
++ predictor-corrector) on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+Prints one JSON line: cell-steps/s over K timed steps (inputs resident in
+HBM, warm-started solves), the roofline position of the kernel class that
+takes the most time (algorithmic bytes per launch / mean launch duration,
+HIP events on the library's stream over the timed region), and the FP64
+CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TDGL cell-steps/s incl. Poisson+FEM solves; HBM GB/s vs peak; adjoint/fwd ratio"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic (compulsory) HBM bytes per node of one launch of each kernel
+# class, FP64 state (stencil neighbours counted once as cached re-reads).
+#   poisson_setup  P, V (48) + phi (8) read; r, p (16) written
+#   poisson_a      r, p_old, x (24) read; p_new, x (16) written
+#   poisson_b      p, r (16) read; r (8) written
+#   fem_setup      P, V (48) + u (24) read; r, p (48) written
+#   fem_a          r, p_old, x (72) read; p_new, x (48) written   (rows k >= 1)
+#   fem_b          p, r (48) read; r (24) written                 (rows k >= 1)
+#   force          P, V (48) + phi (8) + u (24) read; P, V (48) written
+#   finish         x, p read, x written (Poisson 24, FEM 72 per node)
+BYTES_PER_NODE_FP64 = {
+    "poisson_setup": 72, "poisson_a": 40, "poisson_b": 24, "fem_setup": 120, "fem_a": 120, "fem_b": 72,
+    "force": 128,
+}
+
+
+def nodes_per_launch(cls, cfg):
+    if cls in ("fem_a", "fem_b"):
+        return cfg.nodes - cfg.nx * cfg.ny
+    return cfg.nodes
+
+
+def cpu_baseline(w, iters_phi, iters_u):
+    """The FP64 oracle as it stands, on a bounded sample: one step's three
+    oracle calls (Poisson solve, FEM solve, force) on a 128 x 128 x nz slab
+    of the same workload, with each CG run for exactly the GPU's mean
+    iteration count per step at full size; time scaled by the cell count
+    (every oracle sweep costs the same per node)."""
+    import numpy as np
+    from oracle.pf_oracle import Oracle
+    from paper_1202_6116_amd.workloads import centred_strips, domain_polarisation
+
+    cfg = w.cfg
+    sx, sy = min(cfg.nx, 128), min(cfg.ny, 128)
+    scfg = cfg.replace(nx=sx, ny=sy, electrodes=centred_strips(sx, sy) if cfg.electrodes else [],
+                       tol_phi=1e-300, tol_u=1e-300, warm_start=False, precision="fp64")
+    P = domain_polarisation(scfg, w.seed)
+    t_phi = t_u = 0.0
+    op = Oracle(scfg.replace(maxit=max(1, int(round(iters_phi)))))
+    t0 = time.perf_counter()
+    phi, _, _, _ = op.solve_phi(P)
+    t_phi = time.perf_counter() - t0
+    ou = Oracle(scfg.replace(maxit=max(1, int(round(iters_u)))))
+    t0 = time.perf_counter()
+    u, _, _, _ = ou.solve_u(P)
+    t_u = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    op.force(P, phi, u)
+    t_f = time.perf_counter() - t0
+    t_sample = t_phi + t_u + t_f
+    t_full = t_sample * cfg.nodes / scfg.nodes
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": cfg.nodes / t_full, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+        "sample": (f"one step (Poisson solve {int(round(iters_phi))} it, FEM solve {int(round(iters_u))} it, force) "
+                   f"of the FP64 oracle on a {sx}x{sy}x{cfg.nz} slab of the workload, {t_sample:.1f} s, "
+                   f"scaled by cell count x{cfg.nodes / scfg.nodes:.0f}"),
+        "seconds_sample": round(t_sample, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="lateral_256x256x64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time the steps without per-launch events (the roofline is then omitted)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; the path's sharding across GPUs is described in the "
+              "design notes, not implemented", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1202_6116_amd import pf
+    from paper_1202_6116_amd.workloads import initial_polarisation, workloads
+
+    w = workloads()[args.workload]
+    cfg = w.cfg
+    dev = torch.device("cuda:0")
+    ctx = pf.Context(cfg, "cuda:0")
+    P0 = torch.from_numpy(initial_polarisation(w)).to(device=dev, dtype=ctx.state_dtype)
+    ctx.set_state(P0)
+    if args.warmup:
+        ctx.step(args.warmup)
+    torch.cuda.synchronize()
+
+    timing = not args.no_kernel_timing
+    ctx.timing(timing)                      # reset the accumulators, switch per-launch events on
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    stats = ctx.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.timing(False)
+    gpu_s = e0.elapsed_time(e1) / 1e3
+    secs = max(wall, gpu_s)
+    value = cfg.nodes * args.steps / secs
+
+    it_phi = stats["iters_phi"] / max(1, stats["solves_phi"])
+    it_u = stats["iters_u"] / max(1, stats["solves_u"])
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * secs / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if cfg.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "cells": cfg.nodes,
+                   "integrator": cfg.integrator, "tol_phi": cfg.tol_phi, "tol_u": cfg.tol_u,
+                   "electrodes": len(cfg.electrodes), "init": w.init, "seed": w.seed, "warm_start": cfg.warm_start},
+        "cg_iters_per_step": {"phi": round(it_phi, 2), "u": round(it_u, 2)},
+    }
+    if timing:
+        per = {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in kt.items() if v[1]}
+        dom = max((k for k in BYTES_PER_NODE_FP64 if kt[k][1]), key=lambda k: kt[k][0])
+        ms, n = kt[dom]
+        avg_s = ms / n / 1e3
+        nbytes = BYTES_PER_NODE_FP64[dom] * nodes_per_launch(dom, cfg)
+        if cfg.precision != "fp64":
+            nbytes //= 2
+        achieved = nbytes / avg_s / 1e9
+        # whole-step algorithmic bandwidth over all timed kernels
+        tot_bytes = sum(BYTES_PER_NODE_FP64[k] * nodes_per_launch(k, cfg) * kt[k][1] for k in BYTES_PER_NODE_FP64)
+        tot_ms = sum(v[0] for v in kt.values())
+        out["roofline"] = {
+            "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": nbytes, "avg_launch_us": round(avg_s * 1e6, 2),
+            "step_alg_GBps": round(tot_bytes / (tot_ms / 1e3) / 1e9, 1),
+        }
+        out["kernel_ms"] = per
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(w, it_phi, it_u)
+        except Exception as e:  # the oracle is test infrastructure; report, don't fail the bench
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -197,6 +197,28 @@ pf_status pf_adjoint_step(pf_ctx *ctx, const void *P_n, const void *V_n, void *l
  * lamV = 0.  No-op for Euler.  Synchronises. */
 pf_status pf_adjoint_initial_rate(pf_ctx *ctx, const void *P0, void *lamP, void *lamV, double *dtheta);
 
+/* Kernel classes for pf_timing. */
+enum {
+  PF_KC_POISSON_SETUP = 0, /* Poisson rhs + initial residual */
+  PF_KC_POISSON_A,         /* Poisson direction update + operator + p.q */
+  PF_KC_POISSON_B,         /* Poisson residual update + r.z */
+  PF_KC_FEM_SETUP,         /* FEM body force + initial residual */
+  PF_KC_FEM_A,             /* FEM direction update + operator + p.q */
+  PF_KC_FEM_B,             /* FEM residual update + r.z */
+  PF_KC_FORCE,             /* force + time update */
+  PF_KC_FINISH,            /* deferred solution update of a solve */
+  PF_KC_REDUCE,            /* single-block reductions of the CG scalars */
+  PF_KC_OTHER,             /* fills, copies, energy and adjoint sweeps */
+  PF_KC_COUNT
+};
+
+/* Per-kernel-class timing with HIP events recorded around every launch on
+ * the context's stream (launches that return at entry after a solve has
+ * converged are not counted).  Returns the accumulated milliseconds and
+ * launch counts since the last call (arrays of PF_KC_COUNT, may be NULL),
+ * resets them, and turns timing on (enable = 1) or off (0). */
+pf_status pf_timing(pf_ctx *ctx, int enable, double *ms, int64_t *launches);
+
 /* Diagnostic (host only, no GPU needed): the constant 27-point operator
  * tables the kernels use for cfg, as doubles in this order:
  *   K[2][3][3][27]   stiffness rows, interior planes then the top plane:

@@ -22,33 +22,37 @@ namespace pf {
 
 // kernel launchers (pf_kernels.hip)
 int node_blocks(const Dims& d);
+TileMap make_tile_map(const Dims& d);
 template <typename T> hipError_t launch_fill(T* a, int64_t n, T v, hipStream_t s);
 template <typename T, typename U> hipError_t launch_convert(const T* a, U* b, int64_t n, hipStream_t s);
 template <typename T> hipError_t launch_cg_finish(T* x, const T* p, int64_t n, const CgScalars* sc, hipStream_t s);
-template <typename T>
-hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const T* P, const T* V, T cdt, int with_P,
+hipError_t launch_cg_reduce(const double* partials, int nblocks, int nv, CgScalars* sc, int mode, double tol,
+                            int maxit, hipStream_t s);
+template <typename T, typename S>
+hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
                                 int with_bc, const T* ghost_top, T phi_bottom, const T* x, T* r, T* p,
-                                CgScalars* sc, double* partials, double tol, int maxit, hipStream_t s);
+                                double* partials, hipStream_t s);
 template <typename T>
-hipError_t launch_poisson_cg_a(const Dims& d, const Coefs<T>& cf, const T* r, const T* p_old, T* p_new, T* x,
-                               CgScalars* sc, double* partials, hipStream_t s);
+hipError_t launch_poisson_cg_a(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* r, const T* p_old,
+                               T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T>
-hipError_t launch_poisson_cg_b(const Dims& d, const Coefs<T>& cf, const T* p, T* r, CgScalars* sc, double* partials,
-                               hipStream_t s);
+hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* p, T* r,
+                               const CgScalars* sc, double* partials, hipStream_t s);
+template <typename T, typename S>
+hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const S* P, const S* V, T cdt,
+                            T* x, T* r, T* p0, T* p1, double* partials, hipStream_t s);
 template <typename T>
-hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* P, const T* V, T cdt,
-                            T* x, T* r, T* p0, T* p1, CgScalars* sc, double* partials, double tol, int maxit,
-                            hipStream_t s);
+hipError_t launch_fem_cg_a(const Dims& d, const TileMap& tm, const FemTables* tb, const T* r, const T* p_old,
+                           T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T>
-hipError_t launch_fem_cg_a(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* r, const T* p_old,
-                           T* p_new, T* x, CgScalars* sc, double* partials, hipStream_t s);
-template <typename T>
-hipError_t launch_fem_cg_b(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* p, T* r, CgScalars* sc,
-                           double* partials, hipStream_t s);
+hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb, const T* p, T* r,
+                           const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* P, const T* V, T cdt,
                         const T* phi, const T* ghost_top, const T* u, int mode, T* Pn, T* Vn, T* Fout,
                         hipStream_t s);
+
+enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2 };
 
 // ---------------------------------------------------------------------------
 // FEM operator tables from 1D element integrals
@@ -186,7 +190,7 @@ struct Layout {
 constexpr int kNumScalars = 4;   // Poisson, FEM, two spares
 constexpr int kPartialsPerBlock = 4;
 
-Layout make_layout(const pf_config& c, int nblocks) {
+Layout make_layout(const pf_config& c, int npartials) {
   const size_t N = (size_t)c.nx * c.ny * c.nz;
   const size_t es = c.precision == PF_FP32_REFINE ? 4 : 8;
   const size_t plane = (size_t)c.nx * c.ny;
@@ -223,7 +227,7 @@ Layout make_layout(const pf_config& c, int nblocks) {
   for (int t = 0; t < 8; t++) L.adj[t] = take(3 * N * 8);
   L.tables = take(sizeof(FemTables));
   L.scalars = take(sizeof(CgScalars) * kNumScalars);
-  L.partials = take((size_t)nblocks * kPartialsPerBlock * 8 * kNumScalars);
+  L.partials = take((size_t)npartials * kPartialsPerBlock * 8 * kNumScalars);
   L.total = o;
   return L;
 }
@@ -241,7 +245,9 @@ struct pf_ctx {
   char* ws;
   size_t ws_bytes;
   hipStream_t stream;
-  int nblocks;
+  int nblocks;              // node-kernel blocks
+  pf::TileMap tm;           // tile-kernel geometry
+  int npartials;            // partial slots per solver (max of both block counts)
   pf::CgScalars* host_sc;   // pinned read-back buffer
   std::string err;
   bool have_state;
@@ -249,6 +255,15 @@ struct pf_ctx {
   int64_t step;
   int cur;                  // which P/V buffer is current
   int last_iters_phi, last_iters_u;
+  // per-kernel-class event timing
+  bool timing;
+  std::vector<hipEvent_t> events;
+  struct TimedLaunch {
+    int cls, slot, solver, k;
+  };
+  std::vector<TimedLaunch> pending;
+  double kc_ms[PF_KC_COUNT];
+  int64_t kc_n[PF_KC_COUNT];
 };
 
 namespace pf {
@@ -341,7 +356,44 @@ Coefs<T> make_coefs(const pf_ctx* c) {
 
 CgScalars* dev_sc(pf_ctx* c, int which) { return at<CgScalars>(c, c->lay.scalars) + which; }
 double* dev_partials(pf_ctx* c, int which) {
-  return at<double>(c, c->lay.partials) + (size_t)which * c->nblocks * kPartialsPerBlock;
+  return at<double>(c, c->lay.partials) + (size_t)which * c->npartials * kPartialsPerBlock;
+}
+
+// Event timing of one launch: `launch` is called between two event records
+// when timing is on.  solver/k tag CG iterations (solver -1: always counted).
+template <typename F>
+hipError_t timed(pf_ctx* c, int cls, int solver, int k, F&& launch) {
+  if (!c->timing) return launch();
+  const int slot = (int)c->pending.size();
+  while ((int)c->events.size() < 2 * (slot + 1)) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    c->events.push_back(e);
+  }
+  hipError_t err = hipEventRecord(c->events[2 * slot], c->stream);
+  if (err != hipSuccess) return err;
+  err = launch();
+  if (err != hipSuccess) return err;
+  err = hipEventRecord(c->events[2 * slot + 1], c->stream);
+  if (err != hipSuccess) return err;
+  c->pending.push_back({cls, slot, solver, k});
+  return hipSuccess;
+}
+
+// After a stream synchronisation: accumulates the pending launches.  CG
+// iterations at or beyond `iters` of `solver` returned at entry and are
+// dropped.
+void collect_timing(pf_ctx* c, int solver, int iters) {
+  for (const auto& t : c->pending) {
+    if (t.solver >= 0 && t.solver == solver && t.k >= iters) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->events[2 * t.slot], c->events[2 * t.slot + 1]) == hipSuccess) {
+      c->kc_ms[t.cls] += ms;
+      c->kc_n[t.cls] += 1;
+    }
+  }
+  c->pending.clear();
 }
 
 // Reads back the scalars of one solver (synchronises the stream).
@@ -349,6 +401,13 @@ pf_status read_scalars(pf_ctx* c, int which, CgScalars* out) {
   PF_HIP(c, hipMemcpyAsync(c->host_sc, dev_sc(c, which), sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
   PF_HIP(c, hipStreamSynchronize(c->stream));
   *out = *c->host_sc;
+  if (c->timing) collect_timing(c, which, out->iter);
+  return PF_OK;
+}
+
+pf_status sync(pf_ctx* c) {
+  PF_HIP(c, hipStreamSynchronize(c->stream));
+  if (c->timing) collect_timing(c, -1, 0);
   return PF_OK;
 }
 
@@ -395,7 +454,9 @@ pf_status run_cg(pf_ctx* c, int which, int predicted, T* x, T* const pbuf[2], in
     if (k >= maxit) return fail(c, PF_EHIP, "%s: solver state did not advance", what);
     batch = std::max(4, predicted / 8);
   }
-  if (h.done != kNonFinite) PF_HIP(c, launch_cg_finish<T>(x, pbuf[h.iter & 1], n, dev_sc(c, which), c->stream));
+  if (h.done != kNonFinite)
+    PF_HIP(c, timed(c, PF_KC_FINISH, -1, -1,
+                    [&] { return launch_cg_finish<T>(x, pbuf[h.iter & 1], n, dev_sc(c, which), c->stream); }));
   return finish_solve(c, which, h, res, what);
 }
 
@@ -411,12 +472,28 @@ pf_status solve_poisson(pf_ctx* c, const T* P, const T* V, T cdt, int with_P, in
   T* r = at<T>(c, c->lay.pr);
   T* pb[2] = {at<T>(c, c->lay.pp[0]), at<T>(c, c->lay.pp[1])};
   if (!warm) PF_HIP(c, launch_fill<T>(x, d.N, (T)0, c->stream));
-  PF_HIP(c, launch_poisson_setup<T>(d, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, x, r, pb[0], sc, part,
-                                    tol, c->cfg.maxit, c->stream));
+  const TileMap& tm = c->tm;
+  const int nb = c->nblocks, tb_ = tm.nblocks, maxit = c->cfg.maxit;
+  PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
+    return launch_poisson_setup<T, T>(d, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, x, r, pb[0], part,
+                                      c->stream);
+  }));
+  PF_HIP(c, timed(c, PF_KC_REDUCE, -1, -1,
+                  [&] { return launch_cg_reduce(part, nb, 3, sc, kRedSetup, tol, maxit, c->stream); }));
   auto iteration = [&](int k) -> hipError_t {
-    hipError_t e = launch_poisson_cg_a<T>(d, cf, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
-    if (e != hipSuccess) return e;
-    return launch_poisson_cg_b<T>(d, cf, pb[(k + 1) & 1], r, sc, part, c->stream);
+    hipError_t e = timed(c, PF_KC_POISSON_A, 0, k, [&] {
+      return launch_poisson_cg_a<T>(d, tm, cf, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
+    });
+    if (e == hipSuccess)
+      e = timed(c, PF_KC_REDUCE, 0, k,
+                [&] { return launch_cg_reduce(part, tb_, 1, sc, kRedAlpha, tol, maxit, c->stream); });
+    if (e == hipSuccess)
+      e = timed(c, PF_KC_POISSON_B, 0, k,
+                [&] { return launch_poisson_cg_b<T>(d, tm, cf, pb[(k + 1) & 1], r, sc, part, c->stream); });
+    if (e == hipSuccess)
+      e = timed(c, PF_KC_REDUCE, 0, k,
+                [&] { return launch_cg_reduce(part, tb_, 2, sc, kRedBeta, tol, maxit, c->stream); });
+    return e;
   };
   return run_cg<T>(c, 0, c->last_iters_phi, x, pb, d.N, iteration, res, "Poisson solve");
 }
@@ -431,11 +508,27 @@ pf_status solve_fem(pf_ctx* c, const T* P, const T* V, T cdt, T* x, double tol, 
   T* r = at<T>(c, c->lay.fr);
   T* pb[2] = {at<T>(c, c->lay.fp[0]), at<T>(c, c->lay.fp[1])};
   if (!warm) PF_HIP(c, launch_fill<T>(x, 3 * d.N, (T)0, c->stream));
-  PF_HIP(c, launch_fem_setup<T>(d, cf, tb, P, V, cdt, x, r, pb[0], pb[1], sc, part, tol, c->cfg.maxit, c->stream));
+  const TileMap& tm = c->tm;
+  const int nb = c->nblocks, tb_ = tm.nblocks, maxit = c->cfg.maxit;
+  PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
+    return launch_fem_setup<T, T>(d, cf, tb, P, V, cdt, x, r, pb[0], pb[1], part, c->stream);
+  }));
+  PF_HIP(c, timed(c, PF_KC_REDUCE, -1, -1,
+                  [&] { return launch_cg_reduce(part, nb, 3, sc, kRedSetup, tol, maxit, c->stream); }));
   auto iteration = [&](int k) -> hipError_t {
-    hipError_t e = launch_fem_cg_a<T>(d, cf, tb, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
-    if (e != hipSuccess) return e;
-    return launch_fem_cg_b<T>(d, cf, tb, pb[(k + 1) & 1], r, sc, part, c->stream);
+    hipError_t e = timed(c, PF_KC_FEM_A, 1, k, [&] {
+      return launch_fem_cg_a<T>(d, tm, tb, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
+    });
+    if (e == hipSuccess)
+      e = timed(c, PF_KC_REDUCE, 1, k,
+                [&] { return launch_cg_reduce(part, tb_, 1, sc, kRedAlpha, tol, maxit, c->stream); });
+    if (e == hipSuccess)
+      e = timed(c, PF_KC_FEM_B, 1, k,
+                [&] { return launch_fem_cg_b<T>(d, tm, tb, pb[(k + 1) & 1], r, sc, part, c->stream); });
+    if (e == hipSuccess)
+      e = timed(c, PF_KC_REDUCE, 1, k,
+                [&] { return launch_cg_reduce(part, tb_, 2, sc, kRedBeta, tol, maxit, c->stream); });
+    return e;
   };
   return run_cg<T>(c, 1, c->last_iters_u, x, pb, 3 * d.N, iteration, res, "FEM solve");
 }
@@ -512,7 +605,7 @@ pf_status pf_workspace_size(const pf_config* cfg, size_t* bytes) {
   pf_status s = validate(cfg, nullptr);
   if (s != PF_OK) return s;
   Dims d{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz, (int64_t)cfg->nx * cfg->ny};
-  *bytes = make_layout(*cfg, node_blocks(d)).total;
+  *bytes = make_layout(*cfg, std::max(node_blocks(d), make_tile_map(d).nblocks)).total;
   return PF_OK;
 }
 
@@ -539,7 +632,9 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   for (auto& e : c->electrodes) c->volts.push_back(e.volts);
   c->dims = Dims{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz, (int64_t)cfg->nx * cfg->ny};
   c->nblocks = node_blocks(c->dims);
-  c->lay = make_layout(*cfg, c->nblocks);
+  c->tm = make_tile_map(c->dims);
+  c->npartials = std::max(c->nblocks, c->tm.nblocks);
+  c->lay = make_layout(*cfg, c->npartials);
   if (bytes < c->lay.total) {
     fprintf(stderr, "pf_init: workspace of %zu bytes, %zu needed\n", bytes, c->lay.total);
     delete c;
@@ -553,6 +648,9 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->step = 0;
   c->cur = 0;
   c->last_iters_phi = c->last_iters_u = 16;
+  c->timing = false;
+  std::memset(c->kc_ms, 0, sizeof(c->kc_ms));
+  std::memset(c->kc_n, 0, sizeof(c->kc_n));
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host_sc), sizeof(CgScalars), hipHostMallocDefault) != hipSuccess) {
     fprintf(stderr, "pf_init: pinned host allocation failed\n");
     delete c;
@@ -594,6 +692,7 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
 
 void pf_destroy(pf_ctx* c) {
   if (!c) return;
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
   delete c;
 }
@@ -672,14 +771,17 @@ pf_status pf_step(pf_ctx* c, int32_t nsteps, pf_step_stats* st) {
       if (r != PF_OK && r != PF_ENOCONV) return r;
       out = worst(out, r);
     }
-    PF_HIP(c, launch_force<double>(c->dims, cf, tb, P, pc ? V : nullptr, pc ? c->cfg.dt : 0.0,
-                                   at<double>(c, c->lay.phi), at<double>(c, c->lay.ghost64),
-                                   at<double>(c, c->lay.u), pc ? kPcStep : kEulerStep, Pn, Vn, nullptr, c->stream));
+    PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
+      return launch_force<double>(c->dims, cf, tb, P, pc ? V : nullptr, pc ? c->cfg.dt : 0.0,
+                                  at<double>(c, c->lay.phi), at<double>(c, c->lay.ghost64), at<double>(c, c->lay.u),
+                                  pc ? kPcStep : kEulerStep, Pn, Vn, nullptr, c->stream);
+    }));
     c->cur ^= 1;
     c->step++;
     if (st) st->steps++;
   }
-  PF_HIP(c, hipStreamSynchronize(c->stream));
+  pf_status ss = sync(c);
+  if (ss != PF_OK) return ss;
   return out;
 }
 
@@ -723,6 +825,20 @@ pf_status pf_force(pf_ctx* c, const void* P, const void* phi, const void* u, voi
                                  nullptr, 0.0, static_cast<const double*>(phi), at<double>(c, c->lay.ghost64),
                                  static_cast<const double*>(u), kForceOut, nullptr, nullptr,
                                  static_cast<double*>(F), c->stream));
+  return PF_OK;
+}
+
+pf_status pf_timing(pf_ctx* c, int enable, double* ms, int64_t* launches) {
+  if (!c) return PF_EINVAL;
+  pf_status s = sync(c);
+  if (s != PF_OK) return s;
+  for (int t = 0; t < PF_KC_COUNT; t++) {
+    if (ms) ms[t] = c->kc_ms[t];
+    if (launches) launches[t] = c->kc_n[t];
+    c->kc_ms[t] = 0;
+    c->kc_n[t] = 0;
+  }
+  c->timing = enable != 0;
   return PF_OK;
 }
 

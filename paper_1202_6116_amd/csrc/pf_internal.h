@@ -54,11 +54,16 @@ struct CgScalars {
   int32_t maxit;
   int32_t done;          // 0 running, 1 converged, 2 iteration cap, 3 non-finite
   int32_t zero_rhs;      // b == 0: the solution is x = 0
-  uint32_t counter;      // last-block ticket counter (reset by the last block)
-  int32_t pad;
+  int32_t pad[2];
 };
 
 enum CgDone { kRunning = 0, kConverged = 1, kMaxIt = 2, kNonFinite = 3 };
+
+// Tiles of the z-marching kernels: ntx x nty columns of 64 x 4 nodes, each
+// cut into nkz chunks of kz planes; one block per (column, chunk).
+struct TileMap {
+  int ntx, nty, kz, nkz, nblocks;
+};
 
 // Per-call description of the node grid.
 struct Dims {

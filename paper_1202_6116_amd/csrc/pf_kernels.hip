@@ -1,11 +1,24 @@
-// HIP kernels of the TDGL step on gfx950: Poisson and FEM conjugate-gradient
-// sweeps with fused reductions, the FEM body force, and the fused force +
-// time-integration sweep.  One thread per grid node; blocks of 64 x 4 nodes
-// in the x-y plane, one z-plane per block row of the grid.
+// HIP kernels of the TDGL step on gfx950.
 //
 // Numbering: node n = i + nx (j + ny k), fields are structure-of-arrays
 // (component c of node n at c*N + n), periodic in x and y, k = 0 the clamped
 // substrate side, k = nz-1 the free top (Sec. III.A-B of the paper).
+//
+// Two launch shapes:
+//  * node kernels (right-hand sides, force sweep, reductions over fields):
+//    one thread per node, blocks of 64 x 4 nodes of one z-plane;
+//  * tile kernels (the conjugate-gradient iterations, which carry all the
+//    time): a block owns a 64 x 4 column of nodes and marches it through a
+//    chunk of z-planes, staging each plane with a one-node halo in LDS (a
+//    ring of three planes), so every stencil neighbour is read from HBM/L2
+//    about once.  Blocks are numbered so that consecutive tiles run on the
+//    same XCD (work-groups are dealt round-robin to the 8 XCDs), keeping
+//    neighbouring tiles' halos in one L2.
+//
+// Reductions are deterministic: a fixed shuffle tree per wavefront, waves
+// in order, one partial per block written with plain stores, then a
+// single-block reduce kernel that sums the partials in a fixed order and
+// updates the conjugate-gradient scalars on the device.
 #include "pf_internal.h"
 
 #include <math.h>
@@ -18,23 +31,16 @@ __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >=
 
 __device__ __forceinline__ int tid_flat() { return threadIdx.x + threadIdx.y * blockDim.x; }
 
-__device__ __forceinline__ int block_flat() {
-  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-// Deterministic block reduction of NV values into partials[bid*NV + t],
-// then a ticket on `counter`.  Returns true (in every thread) in the block
-// that finishes last; that block may then read all partials.
-template <int NV>
-__device__ bool reduce_to_partials(double (&v)[NV], double* partials, uint32_t* counter, int nblocks) {
-  __shared__ double red[NV][kThreads / 64];
-  __shared__ int is_last;
+// Block partial sums of NV values into partials[bid*NV + t].
+template <int NV, int NT>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* partials, int bid) {
+  __shared__ double red[NV][NT / 64];
   const int tid = tid_flat();
   const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
@@ -44,36 +50,105 @@ __device__ bool reduce_to_partials(double (&v)[NV], double* partials, uint32_t* 
   }
   __syncthreads();
   if (tid == 0) {
-    const int bid = block_flat();
 #pragma unroll
     for (int t = 0; t < NV; t++) {
       double s = 0.0;
-      for (int w = 0; w < kThreads / 64; w++) s += red[t][w];
+      for (int w = 0; w < NT / 64; w++) s += red[t][w];
       partials[(int64_t)bid * NV + t] = s;
     }
-    __threadfence();
-    const uint32_t ticket = atomicAdd(counter, 1u);
-    is_last = (ticket == (uint32_t)(nblocks - 1));
   }
-  __syncthreads();
-  const bool last = is_last != 0;
-  if (last) __threadfence();
-  return last;
 }
 
-// In the last block: sum of all partials in a fixed order (thread t takes
-// blocks t, t + 256, ...; then a fixed tree).  Result valid in thread 0.
+__device__ __forceinline__ int node_block_id() { return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z); }
+
+__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+// ||r|| <= tol ||b||
+__device__ __forceinline__ bool converged(double rnorm2, double bnorm2, double tol) {
+  return sqrt(rnorm2) <= tol * sqrt(bnorm2);
+}
+
+// ---------------------------------------------------------------------------
+// Tile geometry of the z-marching kernels
+// ---------------------------------------------------------------------------
+constexpr int kHX = kBX + 2, kHY = kBY + 2, kHP = kHX * kHY;
+
+// Logical tile of this block: work-groups go round-robin to the 8 XCDs, so
+// XCD x receives physical blocks x, x+8, ...; they are given the contiguous
+// logical range [start_x, start_x + count_x).
+__device__ __forceinline__ int logical_block(int nblocks) {
+  const int b = blockIdx.x;
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int x = b & 7, w = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + w;
+}
+
+struct TileCoord {
+  int i0, j0, k0, k1, lid;
+};
+
+__device__ __forceinline__ TileCoord tile_coord(const Dims& d, const TileMap& tm) {
+  const int lid = logical_block(tm.nblocks);
+  TileCoord t;
+  const int tx = lid % tm.ntx;
+  const int ty = (lid / tm.ntx) % tm.nty;
+  const int kc = lid / (tm.ntx * tm.nty);
+  t.i0 = tx * kBX;
+  t.j0 = ty * kBY;
+  t.k0 = kc * tm.kz;
+  t.k1 = min(d.nz, t.k0 + tm.kz);
+  t.lid = lid;
+  return t;
+}
+
+__device__ __forceinline__ int slot_of(int k) { return (k + 3) % 3; }
+
+// Fills ring slot s with plane k of a tile (and its one-node halo) using
+// f(n, k, out[NC]) for the values; points outside the grid in z, and tile
+// points beyond the ragged edges, hold zero.
+template <typename T, int NC, typename F>
+__device__ __forceinline__ void load_plane(T (&ring)[3][NC][kHY][kHX], const Dims& d, int i0, int j0, int k, F f) {
+  const int s = slot_of(k);
+  for (int t = tid_flat(); t < kHP; t += kThreads) {
+    const int hx = t % kHX, hy = t / kHX;
+    int gi = i0 + hx - 1, gj = j0 + hy - 1;
+    T val[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) val[c] = 0;
+    if (k >= 0 && k < d.nz && gi >= -1 && gi <= d.nx && gj >= -1 && gj <= d.ny) {
+      gi = wrap(gi, d.nx);
+      gj = wrap(gj, d.ny);
+      f(gi + (int64_t)d.nx * gj + d.plane * k, k, val);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) ring[s][c][hy][hx] = val[c];
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Reduce kernel: sums the block partials in a fixed order and advances the
+// conjugate-gradient scalars.
+//   kRedSetup  (b.b, r.z, r.r) of the initial residual
+//   kRedAlpha  p.q            -> alpha = rho / p.q
+//   kRedBeta   (r.z, r.r)     -> beta, iteration count, convergence
+// ---------------------------------------------------------------------------
+enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2 };
+constexpr int kRedThreads = 1024;
+
 template <int NV>
-__device__ void sum_partials(const double* partials, int nblocks, double (&out)[NV]) {
-  __shared__ double red[NV][kThreads / 64];
-  const int tid = tid_flat();
-  const int lane = tid & 63, wv = tid >> 6;
+__global__ __launch_bounds__(kRedThreads) void cg_reduce_kernel(const double* __restrict__ partials, int nblocks,
+                                                                CgScalars* sc, int mode, double tol, int maxit) {
+  if (mode != kRedSetup && sc->done) return;
+  __shared__ double red[NV][kRedThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double s[NV];
 #pragma unroll
   for (int t = 0; t < NV; t++) s[t] = 0.0;
-  for (int b = tid; b < nblocks; b += kThreads) {
+  for (int b = tid; b < nblocks; b += kRedThreads) {
 #pragma unroll
-    for (int t = 0; t < NV; t++) s[t] += __builtin_nontemporal_load(partials + (int64_t)b * NV + t);
+    for (int t = 0; t < NV; t++) s[t] += partials[(int64_t)b * NV + t];
   }
 #pragma unroll
   for (int t = 0; t < NV; t++) {
@@ -81,25 +156,47 @@ __device__ void sum_partials(const double* partials, int nblocks, double (&out)[
     if (lane == 0) red[t][wv] = w;
   }
   __syncthreads();
-  if (tid == 0) {
+  if (tid != 0) return;
+  double a[NV];
 #pragma unroll
-    for (int t = 0; t < NV; t++) {
-      double a = 0.0;
-      for (int w = 0; w < kThreads / 64; w++) a += red[t][w];
-      out[t] = a;
-    }
+  for (int t = 0; t < NV; t++) {
+    a[t] = 0.0;
+    for (int w = 0; w < kRedThreads / 64; w++) a[t] += red[t][w];
+  }
+  if (mode == kRedSetup) {
+    // a = (b.b, r.z, r.r)
+    sc->bnorm2 = a[0];
+    sc->rho = a[NV > 1 ? 1 : 0];
+    sc->rnorm2 = a[NV > 2 ? 2 : 0];
+    sc->alpha = 0.0;
+    sc->beta = 0.0;
+    sc->iter = 0;
+    sc->tol = tol;
+    sc->maxit = maxit;
+    sc->zero_rhs = 0;
+    const double rn2 = sc->rnorm2;
+    if (!finite(a[0]) || !finite(sc->rho) || !finite(rn2)) sc->done = kNonFinite;
+    else if (a[0] == 0.0) {
+      sc->done = kConverged;
+      sc->zero_rhs = 1;
+      sc->rnorm2 = 0.0;
+    } else if (converged(rn2, a[0], tol)) sc->done = kConverged;
+    else sc->done = maxit <= 0 ? kMaxIt : kRunning;
+  } else if (mode == kRedAlpha) {
+    if (!finite(a[0]) || !(a[0] > 0.0)) sc->done = kNonFinite;
+    else sc->alpha = sc->rho / a[0];
+  } else {
+    const double rz = a[0], rr = a[NV > 1 ? 1 : 0];
+    const int it = sc->iter + 1;
+    sc->iter = it;
+    sc->beta = rz / sc->rho;
+    sc->rho = rz;
+    sc->rnorm2 = rr;
+    if (!finite(rz) || !finite(rr)) sc->done = kNonFinite;
+    else if (converged(rr, sc->bnorm2, sc->tol)) sc->done = kConverged;
+    else if (it >= sc->maxit) sc->done = kMaxIt;
   }
 }
-
-__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
-
-// Convergence test shared by the setup and update kernels:
-// ||r|| <= tol ||b||.
-__device__ __forceinline__ bool converged(double rnorm2, double bnorm2, double tol) {
-  return sqrt(rnorm2) <= tol * sqrt(bnorm2);
-}
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
 // Utility kernels
@@ -108,24 +205,24 @@ __device__ __forceinline__ bool converged(double rnorm2, double bnorm2, double t
 template <typename T>
 __global__ void fill_kernel(T* a, int64_t n, T v) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; t < n; t += stride) a[t] = v;
 }
 
 template <typename T, typename U>
 __global__ void convert_kernel(const T* a, U* b, int64_t n) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; t < n; t += stride) b[t] = (U)a[t];
 }
 
-// x += alpha * p (alpha read from the CG scalars); x = 0 for a zero rhs.
+// x += alpha p with alpha from the solver scalars; x = 0 for a zero rhs.
 template <typename T>
 __global__ void cg_finish_kernel(T* x, const T* p, int64_t n, const CgScalars* sc) {
   const T alpha = (T)sc->alpha;
   const bool zero = sc->zero_rhs != 0;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; t < n; t += stride) x[t] = zero ? (T)0 : x[t] + alpha * p[t];
 }
 
@@ -133,13 +230,14 @@ __global__ void cg_finish_kernel(T* x, const T* p, int64_t n, const CgScalars* s
 // Poisson: A phi = -eps_b Lap_h phi (zero ghosts), b = -D_h P + ghost terms
 // ---------------------------------------------------------------------------
 
-// b from the polarisation Pp = P + cdt V (V may be null) and the Dirichlet
-// ghost planes; r = b - A x; p = r / diag; partial (b.b, r.z, r.r).
-template <typename T>
+// b from Pp = P + cdt V (V may be null) and the ghost planes; r = b - A x;
+// p = r / diag; partial (b.b, r.z, r.r).  T: arithmetic and r, x, p;
+// S: storage of P and V.
+template <typename T, typename S>
 __global__ __launch_bounds__(kThreads) void poisson_setup_kernel(
-    Dims d, Coefs<T> cf, const T* __restrict__ P, const T* __restrict__ V, T cdt, int with_P, int with_bc,
+    Dims d, Coefs<T> cf, const S* __restrict__ P, const S* __restrict__ V, T cdt, int with_P, int with_bc,
     const T* __restrict__ ghost_top, T phi_bottom, const T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
-    CgScalars* sc, double* partials, int nblocks, double tol, int maxit) {
+    double* partials) {
   const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
   double v[3] = {0.0, 0.0, 0.0};
   if (i < d.nx && j < d.ny) {
@@ -150,20 +248,13 @@ __global__ __launch_bounds__(kThreads) void poisson_setup_kernel(
     const int64_t nyp = i + (int64_t)d.nx * wrap(j + 1, d.ny) + pl * k;
     const int64_t nym = i + (int64_t)d.nx * wrap(j - 1, d.ny) + pl * k;
     const bool up = k + 1 < d.nz, dn = k > 0;
+    auto pp = [&](int c, int64_t m) -> T { return (T)P[c * N + m] + (V ? cdt * (T)V[c * N + m] : (T)0); };
     T b = 0;
     if (with_P) {
-      T dx, dy, zp = 0, zm = 0;
-      if (V) {
-        dx = (P[nxp] + cdt * V[nxp]) - (P[nxm] + cdt * V[nxm]);
-        dy = (P[N + nyp] + cdt * V[N + nyp]) - (P[N + nym] + cdt * V[N + nym]);
-        if (up) zp = P[2 * N + n + pl] + cdt * V[2 * N + n + pl];
-        if (dn) zm = P[2 * N + n - pl] + cdt * V[2 * N + n - pl];
-      } else {
-        dx = P[nxp] - P[nxm];
-        dy = P[N + nyp] - P[N + nym];
-        if (up) zp = P[2 * N + n + pl];
-        if (dn) zm = P[2 * N + n - pl];
-      }
+      const T dx = pp(0, nxp) - pp(0, nxm);
+      const T dy = pp(1, nyp) - pp(1, nym);
+      const T zp = up ? pp(2, n + pl) : (T)0;
+      const T zm = dn ? pp(2, n - pl) : (T)0;
       b = -(dx + dy + (zp - zm)) * cf.inv_2h;
     }
     if (with_bc) {
@@ -182,120 +273,94 @@ __global__ __launch_bounds__(kThreads) void poisson_setup_kernel(
     v[1] = (double)rr * z;
     v[2] = (double)rr * rr;
   }
-  if (reduce_to_partials<3>(v, partials, &sc->counter, nblocks)) {
-    double s[3];
-    sum_partials<3>(partials, nblocks, s);
-    if (tid_flat() == 0) {
-      sc->bnorm2 = s[0];
-      sc->rho = s[1];
-      sc->rnorm2 = s[2];
-      sc->alpha = 0.0;
-      sc->beta = 0.0;
-      sc->iter = 0;
-      sc->tol = tol;
-      sc->maxit = maxit;
-      sc->zero_rhs = 0;
-      if (!finite(s[0]) || !finite(s[1]) || !finite(s[2])) sc->done = kNonFinite;
-      else if (s[0] == 0.0) { sc->done = kConverged; sc->zero_rhs = 1; sc->rnorm2 = 0.0; }
-      else if (converged(s[2], s[0], tol)) sc->done = kConverged;
-      else sc->done = maxit <= 0 ? kMaxIt : kRunning;
-      sc->counter = 0;
-    }
-  }
+  block_partials<3, kThreads>(v, partials, node_block_id());
 }
 
-// Direction update fused with the operator: p_new = z + beta p_old at every
-// stencil point, q = A p_new, x += alpha_prev p_old (deferred update);
-// partial (p_new . q) -> alpha = rho / (p.q).
+// Iteration kernel A: p_new = z + beta p_old on the tile and its halo, q =
+// A p_new, x += alpha_prev p_old (the deferred update of the previous
+// iteration); partial p_new . q.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(
-    Dims d, Coefs<T> cf, const T* __restrict__ r, const T* __restrict__ p_old, T* __restrict__ p_new,
-    T* __restrict__ x, CgScalars* sc, double* partials, int nblocks) {
+__global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap tm, Coefs<T> cf,
+                                                                const T* __restrict__ r, const T* __restrict__ p_old,
+                                                                T* __restrict__ p_new, T* __restrict__ x,
+                                                                const CgScalars* sc, double* partials) {
   if (sc->done) return;
-  const T beta = (T)sc->beta, alpha = (T)sc->alpha, w = cf.inv_diag_poisson;
-  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
-  double v[1] = {0.0};
-  if (i < d.nx && j < d.ny) {
-    const int64_t pl = d.plane;
-    const int64_t n = i + (int64_t)d.nx * j + pl * k;
-    const int64_t nxp = wrap(i + 1, d.nx) + (int64_t)d.nx * j + pl * k;
-    const int64_t nxm = wrap(i - 1, d.nx) + (int64_t)d.nx * j + pl * k;
-    const int64_t nyp = i + (int64_t)d.nx * wrap(j + 1, d.ny) + pl * k;
-    const int64_t nym = i + (int64_t)d.nx * wrap(j - 1, d.ny) + pl * k;
-    auto pn = [&](int64_t m) { return r[m] * w + beta * p_old[m]; };
-    const T po = p_old[n];
-    const T pc = r[n] * w + beta * po;
-    T s = pn(nxp) + pn(nxm) + pn(nyp) + pn(nym);
-    if (k + 1 < d.nz) s += pn(n + pl);
-    if (k > 0) s += pn(n - pl);
-    const T q = cf.eps_over_h2 * (6 * pc - s);
-    p_new[n] = pc;
-    x[n] += alpha * po;
-    v[0] = (double)pc * q;
-  }
-  if (reduce_to_partials<1>(v, partials, &sc->counter, nblocks)) {
-    double s[1];
-    sum_partials<1>(partials, nblocks, s);
-    if (tid_flat() == 0) {
-      if (!finite(s[0]) || !(s[0] > 0.0)) sc->done = kNonFinite;
-      else sc->alpha = sc->rho / s[0];
-      sc->counter = 0;
+  __shared__ T ring[3][1][kHY][kHX];
+  const T beta = (T)sc->beta, alpha = (T)sc->alpha, w = cf.inv_diag_poisson, c6 = cf.eps_over_h2;
+  const TileCoord tc = tile_coord(d, tm);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
+  auto f = [&](int64_t m, int, T* out) { out[0] = r[m] * w + beta * p_old[m]; };
+  load_plane<T, 1>(ring, d, tc.i0, tc.j0, tc.k0 - 1, f);
+  load_plane<T, 1>(ring, d, tc.i0, tc.j0, tc.k0, f);
+  double acc = 0.0;
+  for (int k = tc.k0; k < tc.k1; k++) {
+    load_plane<T, 1>(ring, d, tc.i0, tc.j0, k + 1, f);
+    __syncthreads();
+    if (valid) {
+      const int sm = slot_of(k - 1), s0 = slot_of(k), sp = slot_of(k + 1);
+      const T pc = ring[s0][0][ly + 1][lx + 1];
+      const T s = ring[s0][0][ly + 1][lx] + ring[s0][0][ly + 1][lx + 2] + ring[s0][0][ly][lx + 1] +
+                  ring[s0][0][ly + 2][lx + 1] + ring[sm][0][ly + 1][lx + 1] + ring[sp][0][ly + 1][lx + 1];
+      const T q = c6 * (6 * pc - s);
+      const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
+      p_new[n] = pc;
+      x[n] += alpha * p_old[n];
+      acc += (double)pc * q;
     }
+    __syncthreads();
   }
+  double v[1] = {acc};
+  block_partials<1, kThreads>(v, partials, tc.lid);
 }
 
-// Residual update with the operator recomputed: r -= alpha A p; partial
-// (r.z, r.r) -> beta, convergence test.
+// Iteration kernel B: r -= alpha A p (operator recomputed); partial (r.z, r.r).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void poisson_cg_b_kernel(
-    Dims d, Coefs<T> cf, const T* __restrict__ p, T* __restrict__ r, CgScalars* sc, double* partials, int nblocks) {
+__global__ __launch_bounds__(kThreads) void poisson_cg_b_kernel(Dims d, TileMap tm, Coefs<T> cf,
+                                                                const T* __restrict__ p, T* __restrict__ r,
+                                                                const CgScalars* sc, double* partials) {
   if (sc->done) return;
-  const T alpha = (T)sc->alpha;
-  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
-  double v[2] = {0.0, 0.0};
-  if (i < d.nx && j < d.ny) {
-    const int64_t pl = d.plane;
-    const int64_t n = i + (int64_t)d.nx * j + pl * k;
-    const int64_t nxp = wrap(i + 1, d.nx) + (int64_t)d.nx * j + pl * k;
-    const int64_t nxm = wrap(i - 1, d.nx) + (int64_t)d.nx * j + pl * k;
-    const int64_t nyp = i + (int64_t)d.nx * wrap(j + 1, d.ny) + pl * k;
-    const int64_t nym = i + (int64_t)d.nx * wrap(j - 1, d.ny) + pl * k;
-    T s = p[nxp] + p[nxm] + p[nyp] + p[nym];
-    if (k + 1 < d.nz) s += p[n + pl];
-    if (k > 0) s += p[n - pl];
-    const T q = cf.eps_over_h2 * (6 * p[n] - s);
-    const T rn = r[n] - alpha * q;
-    const T z = rn * cf.inv_diag_poisson;
-    r[n] = rn;
-    v[0] = (double)rn * z;
-    v[1] = (double)rn * rn;
-  }
-  if (reduce_to_partials<2>(v, partials, &sc->counter, nblocks)) {
-    double s[2];
-    sum_partials<2>(partials, nblocks, s);
-    if (tid_flat() == 0) {
-      const int it = sc->iter + 1;
-      sc->iter = it;
-      sc->beta = s[0] / sc->rho;
-      sc->rho = s[0];
-      sc->rnorm2 = s[1];
-      if (!finite(s[0]) || !finite(s[1])) sc->done = kNonFinite;
-      else if (converged(s[1], sc->bnorm2, sc->tol)) sc->done = kConverged;
-      else if (it >= sc->maxit) sc->done = kMaxIt;
-      sc->counter = 0;
+  __shared__ T ring[3][1][kHY][kHX];
+  const T alpha = (T)sc->alpha, w = cf.inv_diag_poisson, c6 = cf.eps_over_h2;
+  const TileCoord tc = tile_coord(d, tm);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
+  auto f = [&](int64_t m, int, T* out) { out[0] = p[m]; };
+  load_plane<T, 1>(ring, d, tc.i0, tc.j0, tc.k0 - 1, f);
+  load_plane<T, 1>(ring, d, tc.i0, tc.j0, tc.k0, f);
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = tc.k0; k < tc.k1; k++) {
+    load_plane<T, 1>(ring, d, tc.i0, tc.j0, k + 1, f);
+    __syncthreads();
+    if (valid) {
+      const int sm = slot_of(k - 1), s0 = slot_of(k), sp = slot_of(k + 1);
+      const T pc = ring[s0][0][ly + 1][lx + 1];
+      const T s = ring[s0][0][ly + 1][lx] + ring[s0][0][ly + 1][lx + 2] + ring[s0][0][ly][lx + 1] +
+                  ring[s0][0][ly + 2][lx + 1] + ring[sm][0][ly + 1][lx + 1] + ring[sp][0][ly + 1][lx + 1];
+      const T q = c6 * (6 * pc - s);
+      const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
+      const T rn = r[n] - alpha * q;
+      r[n] = rn;
+      a0 += (double)rn * (rn * w);
+      a1 += (double)rn * rn;
     }
+    __syncthreads();
   }
+  double v[2] = {a0, a1};
+  block_partials<2, kThreads>(v, partials, tc.lid);
 }
 
 // ---------------------------------------------------------------------------
-// FEM: 27-point block stencils from the trilinear hex element
+// FEM: 27-point block stencils of the trilinear hex element
 // ---------------------------------------------------------------------------
 
 namespace {
 
 // K u at a row of type zt (0 interior, 1 top) for a neighbour loader
 // ld(dx, dy, dz, out[3]).  Interior rows skip the structurally zero taps of
-// the coupling blocks (the 1D derivative factor vanishes at offset 0).
+// the coupling blocks (their 1D derivative factor vanishes at offset 0).
 template <typename T, typename Load>
 __device__ __forceinline__ void fem_K_apply(const FemTables* __restrict__ tb, int zt, Load ld, T out[3]) {
   out[0] = out[1] = out[2] = 0;
@@ -336,12 +401,6 @@ __device__ __forceinline__ void fem_K_apply(const FemTables* __restrict__ tb, in
   }
 }
 
-template <typename T>
-struct Node3 {
-  int64_t n;        // linear index
-  int i, j, k;
-};
-
 // Linear index of the neighbour (i+dx, j+dy, k+dz), periodic in x and y.
 __device__ __forceinline__ int64_t nbr(const Dims& d, int i, int j, int k, int dx, int dy, int dz) {
   return wrap(i + dx, d.nx) + (int64_t)d.nx * wrap(j + dy, d.ny) + d.plane * (k + dz);
@@ -372,13 +431,12 @@ __device__ __forceinline__ void cubic_stress(const Coefs<T>& cf, const T e[6], T
 }  // namespace
 
 // f = body force of the eigenstrain of Pp = P + cdt V (Eq. 15); r = f - K x;
-// p = r / diag.  Row k = 0 is clamped: x = r = p = 0 there (both direction
+// p = r / diag.  The clamped plane k = 0 has x = r = p = 0 (both direction
 // buffers).  Partial (f.f, r.z, r.r).
-template <typename T>
+template <typename T, typename S>
 __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
-    Dims d, Coefs<T> cf, const FemTables* __restrict__ tb, const T* __restrict__ P, const T* __restrict__ V, T cdt,
-    T* __restrict__ x, T* __restrict__ r, T* __restrict__ p0, T* __restrict__ p1, CgScalars* sc, double* partials,
-    int nblocks, double tol, int maxit) {
+    Dims d, Coefs<T> cf, const FemTables* __restrict__ tb, const S* __restrict__ P, const S* __restrict__ V, T cdt,
+    T* __restrict__ x, T* __restrict__ r, T* __restrict__ p0, T* __restrict__ p1, double* partials) {
   const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
   double v[3] = {0.0, 0.0, 0.0};
   if (i < d.nx && j < d.ny) {
@@ -403,11 +461,11 @@ __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
           for (int dx = -1; dx <= 1; dx++) {
             const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
             const int64_t m = nbr(d, i, j, k, dx, dy, dz);
-            T px = P[m], py = P[N + m], pz = P[2 * N + m];
+            T px = (T)P[m], py = (T)P[N + m], pz = (T)P[2 * N + m];
             if (V) {
-              px += cdt * V[m];
-              py += cdt * V[N + m];
-              pz += cdt * V[2 * N + m];
+              px += cdt * (T)V[m];
+              py += cdt * (T)V[N + m];
+              pz += cdt * (T)V[2 * N + m];
             }
             T e[6], s[6];
             eigenstrain(cf, px, py, pz, e);
@@ -442,122 +500,110 @@ __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
       }
     }
   }
-  if (reduce_to_partials<3>(v, partials, &sc->counter, nblocks)) {
-    double s[3];
-    sum_partials<3>(partials, nblocks, s);
-    if (tid_flat() == 0) {
-      sc->bnorm2 = s[0];
-      sc->rho = s[1];
-      sc->rnorm2 = s[2];
-      sc->alpha = 0.0;
-      sc->beta = 0.0;
-      sc->iter = 0;
-      sc->tol = tol;
-      sc->maxit = maxit;
-      sc->zero_rhs = 0;
-      if (!finite(s[0]) || !finite(s[1]) || !finite(s[2])) sc->done = kNonFinite;
-      else if (s[0] == 0.0) { sc->done = kConverged; sc->zero_rhs = 1; sc->rnorm2 = 0.0; }
-      else if (converged(s[2], s[0], tol)) sc->done = kConverged;
-      else sc->done = maxit <= 0 ? kMaxIt : kRunning;
-      sc->counter = 0;
-    }
-  }
+  block_partials<3, kThreads>(v, partials, node_block_id());
 }
 
-// x after the setup kernel must be zero on k = 0 before it is read as a
-// neighbour; the setup kernel's own reads of x skip that plane.
-
+// Iteration kernel A: p_new = z + beta p_old on the tile and its halo (zero
+// on the clamped plane), q = K p_new, x += alpha_prev p_old; partial p.q.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void fem_cg_a_kernel(
-    Dims d, Coefs<T> cf, const FemTables* __restrict__ tb, const T* __restrict__ r, const T* __restrict__ p_old,
-    T* __restrict__ p_new, T* __restrict__ x, CgScalars* sc, double* partials, int nblocks) {
+__global__ __launch_bounds__(kThreads) void fem_cg_a_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
+                                                            const T* __restrict__ r, const T* __restrict__ p_old,
+                                                            T* __restrict__ p_new, T* __restrict__ x,
+                                                            const CgScalars* sc, double* partials) {
   if (sc->done) return;
+  __shared__ T ring[3][3][kHY][kHX];
   const T beta = (T)sc->beta, alpha = (T)sc->alpha;
   const T w_int = (T)tb->inv_diag[0], w_top = (T)tb->inv_diag[1];
-  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
-  double v[1] = {0.0};
-  if (i < d.nx && j < d.ny && k > 0) {
-    const int64_t N = d.N;
-    const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
-    const int zt = (k == d.nz - 1) ? 1 : 0;
-    auto ld = [&](int dx, int dy, int dz, T u[3]) {
-      const int kk = k + dz;
-      const int64_t m = nbr(d, i, j, k, dx, dy, dz);
-      const T w = (kk == d.nz - 1) ? w_top : w_int;
-      if (kk == 0) {
-        u[0] = u[1] = u[2] = 0;
-      } else {
+  const TileCoord tc = tile_coord(d, tm);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
+  const int64_t N = d.N;
+  auto f = [&](int64_t m, int k, T* out) {
+    if (k == 0) return;  // clamped plane: zero
+    const T w = (k == d.nz - 1) ? w_top : w_int;
 #pragma unroll
-        for (int c = 0; c < 3; c++) u[c] = r[c * N + m] * w + beta * p_old[c * N + m];
+    for (int c = 0; c < 3; c++) out[c] = r[c * N + m] * w + beta * p_old[c * N + m];
+  };
+  load_plane<T, 3>(ring, d, tc.i0, tc.j0, tc.k0 - 1, f);
+  load_plane<T, 3>(ring, d, tc.i0, tc.j0, tc.k0, f);
+  double acc = 0.0;
+  for (int k = tc.k0; k < tc.k1; k++) {
+    load_plane<T, 3>(ring, d, tc.i0, tc.j0, k + 1, f);
+    __syncthreads();
+    if (valid && k > 0) {
+      const int zt = (k == d.nz - 1) ? 1 : 0;
+      auto ld = [&](int dx, int dy, int dz, T u[3]) {
+        const int s = slot_of(k + dz);
+#pragma unroll
+        for (int c = 0; c < 3; c++) u[c] = ring[s][c][ly + 1 + dy][lx + 1 + dx];
+      };
+      T q[3];
+      fem_K_apply<T>(tb, zt, ld, q);
+      const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
+      const int s0 = slot_of(k);
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        const T pc = ring[s0][c][ly + 1][lx + 1];
+        p_new[c * N + n] = pc;
+        x[c * N + n] += alpha * p_old[c * N + n];
+        acc += (double)pc * q[c];
       }
-    };
-    T q[3];
-    fem_K_apply<T>(tb, zt, ld, q);
-    const T w = zt ? w_top : w_int;
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      const T po = p_old[c * N + n];
-      const T pc = r[c * N + n] * w + beta * po;
-      p_new[c * N + n] = pc;
-      x[c * N + n] += alpha * po;
-      v[0] += (double)pc * q[c];
     }
+    __syncthreads();
   }
-  if (reduce_to_partials<1>(v, partials, &sc->counter, nblocks)) {
-    double s[1];
-    sum_partials<1>(partials, nblocks, s);
-    if (tid_flat() == 0) {
-      if (!finite(s[0]) || !(s[0] > 0.0)) sc->done = kNonFinite;
-      else sc->alpha = sc->rho / s[0];
-      sc->counter = 0;
-    }
-  }
+  double v[1] = {acc};
+  block_partials<1, kThreads>(v, partials, tc.lid);
 }
 
+// Iteration kernel B: r -= alpha K p (operator recomputed); partial (r.z, r.r).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void fem_cg_b_kernel(
-    Dims d, Coefs<T> cf, const FemTables* __restrict__ tb, const T* __restrict__ p, T* __restrict__ r, CgScalars* sc,
-    double* partials, int nblocks) {
+__global__ __launch_bounds__(kThreads) void fem_cg_b_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
+                                                            const T* __restrict__ p, T* __restrict__ r,
+                                                            const CgScalars* sc, double* partials) {
   if (sc->done) return;
+  __shared__ T ring[3][3][kHY][kHX];
   const T alpha = (T)sc->alpha;
-  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
-  double v[2] = {0.0, 0.0};
-  if (i < d.nx && j < d.ny && k > 0) {
-    const int64_t N = d.N;
-    const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
-    const int zt = (k == d.nz - 1) ? 1 : 0;
-    auto ld = [&](int dx, int dy, int dz, T u[3]) {
-      const int64_t m = nbr(d, i, j, k, dx, dy, dz);
+  const T w_int = (T)tb->inv_diag[0], w_top = (T)tb->inv_diag[1];
+  const TileCoord tc = tile_coord(d, tm);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
+  const int64_t N = d.N;
+  auto f = [&](int64_t m, int k, T* out) {
+    if (k == 0) return;
 #pragma unroll
-      for (int c = 0; c < 3; c++) u[c] = p[c * N + m];
-    };
-    T q[3];
-    fem_K_apply<T>(tb, zt, ld, q);
-    const T w = (T)tb->inv_diag[zt];
+    for (int c = 0; c < 3; c++) out[c] = p[c * N + m];
+  };
+  load_plane<T, 3>(ring, d, tc.i0, tc.j0, tc.k0 - 1, f);
+  load_plane<T, 3>(ring, d, tc.i0, tc.j0, tc.k0, f);
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = tc.k0; k < tc.k1; k++) {
+    load_plane<T, 3>(ring, d, tc.i0, tc.j0, k + 1, f);
+    __syncthreads();
+    if (valid && k > 0) {
+      const int zt = (k == d.nz - 1) ? 1 : 0;
+      auto ld = [&](int dx, int dy, int dz, T u[3]) {
+        const int s = slot_of(k + dz);
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      const T rn = r[c * N + n] - alpha * q[c];
-      const T z = rn * w;
-      r[c * N + n] = rn;
-      v[0] += (double)rn * z;
-      v[1] += (double)rn * rn;
+        for (int c = 0; c < 3; c++) u[c] = ring[s][c][ly + 1 + dy][lx + 1 + dx];
+      };
+      T q[3];
+      fem_K_apply<T>(tb, zt, ld, q);
+      const T w = zt ? w_top : w_int;
+      const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        const T rn = r[c * N + n] - alpha * q[c];
+        r[c * N + n] = rn;
+        a0 += (double)rn * (rn * w);
+        a1 += (double)rn * rn;
+      }
     }
+    __syncthreads();
   }
-  if (reduce_to_partials<2>(v, partials, &sc->counter, nblocks)) {
-    double s[2];
-    sum_partials<2>(partials, nblocks, s);
-    if (tid_flat() == 0) {
-      const int it = sc->iter + 1;
-      sc->iter = it;
-      sc->beta = s[0] / sc->rho;
-      sc->rho = s[0];
-      sc->rnorm2 = s[1];
-      if (!finite(s[0]) || !finite(s[1])) sc->done = kNonFinite;
-      else if (converged(s[1], sc->bnorm2, sc->tol)) sc->done = kConverged;
-      else if (it >= sc->maxit) sc->done = kMaxIt;
-      sc->counter = 0;
-    }
-  }
+  double v[2] = {a0, a1};
+  block_partials<2, kThreads>(v, partials, tc.lid);
 }
 
 // ---------------------------------------------------------------------------
@@ -585,14 +631,12 @@ __global__ __launch_bounds__(kThreads) void force_kernel(
   T p0[3];
   pp(n, p0);
   T F[3] = {0, 0, 0};
-  // Landau (Eq. 1)
   if (cf.terms & kLandau) {
     const T x2 = p0[0] * p0[0], y2 = p0[1] * p0[1], z2 = p0[2] * p0[2];
     F[0] += 2 * cf.a1 * p0[0] + 4 * cf.a11 * x2 * p0[0] + 2 * cf.a12 * p0[0] * (y2 + z2);
     F[1] += 2 * cf.a1 * p0[1] + 4 * cf.a11 * y2 * p0[1] + 2 * cf.a12 * p0[1] * (z2 + x2);
     F[2] += 2 * cf.a1 * p0[2] + 4 * cf.a11 * z2 * p0[2] + 2 * cf.a12 * p0[2] * (x2 + y2);
   }
-  // gradient term: -G Lap_h Pp, zero-flux in z
   if (cf.terms & kGrad) {
     T a[3], lap[3] = {0, 0, 0};
     const int64_t ms[4] = {nbr(d, i, j, k, 1, 0, 0), nbr(d, i, j, k, -1, 0, 0), nbr(d, i, j, k, 0, 1, 0),
@@ -616,7 +660,6 @@ __global__ __launch_bounds__(kThreads) void force_kernel(
 #pragma unroll
     for (int c = 0; c < 3; c++) F[c] -= cf.G * cf.inv_h2 * lap[c];
   }
-  // electrostatic term: -E, E = -G_h phi with Dirichlet ghosts
   if (cf.terms & kElec) {
     const T zp = (k + 1 < d.nz) ? phi[n + pl] : ghost_top[i + (int64_t)d.nx * j];
     const T zm = (k > 0) ? phi[n - pl] : cf.phi_bottom;
@@ -624,7 +667,6 @@ __global__ __launch_bounds__(kThreads) void force_kernel(
     F[1] += (phi[nbr(d, i, j, k, 0, 1, 0)] - phi[nbr(d, i, j, k, 0, -1, 0)]) * cf.inv_2h;
     F[2] += (zp - zm) * cf.inv_2h;
   }
-  // elastic term: -h^-3 s . deps0/dP
   if (cf.terms & kElas) {
     const int zt = (k == 0) ? kLow : ((k == d.nz - 1) ? kHigh : kInterior);
     const int dzmin = (k == 0) ? 0 : -1, dzmax = (k == d.nz - 1) ? 0 : 1;
@@ -651,7 +693,6 @@ __global__ __launch_bounds__(kThreads) void force_kernel(
         }
     T s[6];
     cubic_stress(cf, w, s);
-    // deps0/dP contracted with s
     const T g0 = 2 * p0[0] * (cf.Q11 * s[0] + cf.Q12 * (s[1] + s[2])) + 2 * cf.Q44 * (p0[1] * s[3] + p0[2] * s[5]);
     const T g1 = 2 * p0[1] * (cf.Q11 * s[1] + cf.Q12 * (s[2] + s[0])) + 2 * cf.Q44 * (p0[0] * s[3] + p0[2] * s[4]);
     const T g2 = 2 * p0[2] * (cf.Q11 * s[2] + cf.Q12 * (s[0] + s[1])) + 2 * cf.Q44 * (p0[1] * s[4] + p0[0] * s[5]);
@@ -703,6 +744,22 @@ int node_blocks(const Dims& d) {
   return (int)(g.x * g.y * g.z);
 }
 
+// z-chunk length: enough blocks to fill the chip (about 8 per CU), chunks
+// of 4..32 planes.
+TileMap make_tile_map(const Dims& d) {
+  TileMap t;
+  t.ntx = (d.nx + kBX - 1) / kBX;
+  t.nty = (d.ny + kBY - 1) / kBY;
+  const int64_t cols = (int64_t)t.ntx * t.nty;
+  int64_t kz = (int64_t)d.nz * cols / 2048;
+  kz = kz < 4 ? 4 : (kz > 32 ? 32 : kz);
+  if (kz > d.nz) kz = d.nz;
+  t.kz = (int)kz;
+  t.nkz = (d.nz + t.kz - 1) / t.kz;
+  t.nblocks = (int)(cols * t.nkz);
+  return t;
+}
+
 template <typename T>
 hipError_t launch_fill(T* a, int64_t n, T v, hipStream_t s) {
   fill_kernel<T><<<flat_blocks(n), 256, 0, s>>>(a, n, v);
@@ -721,52 +778,57 @@ hipError_t launch_cg_finish(T* x, const T* p, int64_t n, const CgScalars* sc, hi
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const T* P, const T* V, T cdt, int with_P,
+hipError_t launch_cg_reduce(const double* partials, int nblocks, int nv, CgScalars* sc, int mode, double tol,
+                            int maxit, hipStream_t s) {
+  switch (nv) {
+    case 1: cg_reduce_kernel<1><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit); break;
+    case 2: cg_reduce_kernel<2><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit); break;
+    default: cg_reduce_kernel<3><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, typename S>
+hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
                                 int with_bc, const T* ghost_top, T phi_bottom, const T* x, T* r, T* p,
-                                CgScalars* sc, double* partials, double tol, int maxit, hipStream_t s) {
-  poisson_setup_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, cf, P, V, cdt, with_P, with_bc, ghost_top,
-                                                                phi_bottom, x, r, p, sc, partials, node_blocks(d),
-                                                                tol, maxit);
+                                double* partials, hipStream_t s) {
+  poisson_setup_kernel<T, S><<<node_grid(d), node_block(), 0, s>>>(d, cf, P, V, cdt, with_P, with_bc, ghost_top,
+                                                                   phi_bottom, x, r, p, partials);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_poisson_cg_a(const Dims& d, const Coefs<T>& cf, const T* r, const T* p_old, T* p_new, T* x,
-                               CgScalars* sc, double* partials, hipStream_t s) {
-  poisson_cg_a_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, cf, r, p_old, p_new, x, sc, partials,
-                                                               node_blocks(d));
+hipError_t launch_poisson_cg_a(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* r, const T* p_old,
+                               T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s) {
+  poisson_cg_a_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, r, p_old, p_new, x, sc, partials);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_poisson_cg_b(const Dims& d, const Coefs<T>& cf, const T* p, T* r, CgScalars* sc, double* partials,
-                               hipStream_t s) {
-  poisson_cg_b_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, cf, p, r, sc, partials, node_blocks(d));
+hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* p, T* r,
+                               const CgScalars* sc, double* partials, hipStream_t s) {
+  poisson_cg_b_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, p, r, sc, partials);
+  return hipGetLastError();
+}
+
+template <typename T, typename S>
+hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const S* P, const S* V, T cdt,
+                            T* x, T* r, T* p0, T* p1, double* partials, hipStream_t s) {
+  fem_setup_kernel<T, S><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, x, r, p0, p1, partials);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* P, const T* V, T cdt,
-                            T* x, T* r, T* p0, T* p1, CgScalars* sc, double* partials, double tol, int maxit,
-                            hipStream_t s) {
-  fem_setup_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, x, r, p0, p1, sc, partials,
-                                                            node_blocks(d), tol, maxit);
+hipError_t launch_fem_cg_a(const Dims& d, const TileMap& tm, const FemTables* tb, const T* r, const T* p_old,
+                           T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s) {
+  fem_cg_a_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, r, p_old, p_new, x, sc, partials);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fem_cg_a(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* r, const T* p_old,
-                           T* p_new, T* x, CgScalars* sc, double* partials, hipStream_t s) {
-  fem_cg_a_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, r, p_old, p_new, x, sc, partials,
-                                                           node_blocks(d));
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_fem_cg_b(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* p, T* r, CgScalars* sc,
-                           double* partials, hipStream_t s) {
-  fem_cg_b_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, p, r, sc, partials, node_blocks(d));
+hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb, const T* p, T* r,
+                           const CgScalars* sc, double* partials, hipStream_t s) {
+  fem_cg_b_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, p, r, sc, partials);
   return hipGetLastError();
 }
 
@@ -782,24 +844,30 @@ hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, 
 #define PF_INSTANTIATE(T)                                                                                        \
   template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                                               \
   template hipError_t launch_cg_finish<T>(T*, const T*, int64_t, const CgScalars*, hipStream_t);                 \
-  template hipError_t launch_poisson_setup<T>(const Dims&, const Coefs<T>&, const T*, const T*, T, int, int,     \
-                                              const T*, T, const T*, T*, T*, CgScalars*, double*, double, int,   \
-                                              hipStream_t);                                                      \
-  template hipError_t launch_poisson_cg_a<T>(const Dims&, const Coefs<T>&, const T*, const T*, T*, T*,           \
-                                             CgScalars*, double*, hipStream_t);                                  \
-  template hipError_t launch_poisson_cg_b<T>(const Dims&, const Coefs<T>&, const T*, T*, CgScalars*, double*,    \
-                                             hipStream_t);                                                       \
-  template hipError_t launch_fem_setup<T>(const Dims&, const Coefs<T>&, const FemTables*, const T*, const T*, T, \
-                                          T*, T*, T*, T*, CgScalars*, double*, double, int, hipStream_t);        \
-  template hipError_t launch_fem_cg_a<T>(const Dims&, const Coefs<T>&, const FemTables*, const T*, const T*, T*, \
-                                         T*, CgScalars*, double*, hipStream_t);                                  \
-  template hipError_t launch_fem_cg_b<T>(const Dims&, const Coefs<T>&, const FemTables*, const T*, T*,           \
-                                         CgScalars*, double*, hipStream_t);                                      \
+  template hipError_t launch_poisson_cg_a<T>(const Dims&, const TileMap&, const Coefs<T>&, const T*, const T*,   \
+                                             T*, T*, const CgScalars*, double*, hipStream_t);                    \
+  template hipError_t launch_poisson_cg_b<T>(const Dims&, const TileMap&, const Coefs<T>&, const T*, T*,         \
+                                             const CgScalars*, double*, hipStream_t);                            \
+  template hipError_t launch_fem_cg_a<T>(const Dims&, const TileMap&, const FemTables*, const T*, const T*, T*,  \
+                                         T*, const CgScalars*, double*, hipStream_t);                            \
+  template hipError_t launch_fem_cg_b<T>(const Dims&, const TileMap&, const FemTables*, const T*, T*,            \
+                                         const CgScalars*, double*, hipStream_t);                                \
   template hipError_t launch_force<T>(const Dims&, const Coefs<T>&, const FemTables*, const T*, const T*, T,     \
                                       const T*, const T*, const T*, int, T*, T*, T*, hipStream_t);
 
 PF_INSTANTIATE(double)
 PF_INSTANTIATE(float)
+
+#define PF_INSTANTIATE_SETUP(T, S)                                                                               \
+  template hipError_t launch_poisson_setup<T, S>(const Dims&, const Coefs<T>&, const S*, const S*, T, int, int,  \
+                                                 const T*, T, const T*, T*, T*, double*, hipStream_t);           \
+  template hipError_t launch_fem_setup<T, S>(const Dims&, const Coefs<T>&, const FemTables*, const S*, const S*, \
+                                             T, T*, T*, T*, T*, double*, hipStream_t);
+
+PF_INSTANTIATE_SETUP(double, double)
+PF_INSTANTIATE_SETUP(double, float)
+PF_INSTANTIATE_SETUP(float, float)
+
 template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
 template hipError_t launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
 

@@ -21,12 +21,14 @@ LIB_PATH = os.path.join(_PKG, "libpf.so")
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ENOCONV, PF_ENONFINITE, PF_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PF_INT_PC, PF_INT_EULER = 0, 1
 PF_FP64, PF_FP32_REFINE = 0, 1
+KERNEL_CLASSES = ["poisson_setup", "poisson_a", "poisson_b", "fem_setup", "fem_a", "fem_b", "force", "finish",
+                  "reduce", "other"]
 
 # Every symbol declared in include/pf.h.
 EXPORTS = [
     "pf_workspace_size", "pf_init", "pf_set_state", "pf_restore_state", "pf_get_state", "pf_step",
     "pf_solve_phi", "pf_solve_u", "pf_force", "pf_energy", "pf_set_params", "pf_adjoint_step",
-    "pf_adjoint_initial_rate", "pf_fem_table_size", "pf_fem_tables", "pf_status_str", "pf_last_error",
+    "pf_adjoint_initial_rate", "pf_timing", "pf_fem_table_size", "pf_fem_tables", "pf_status_str", "pf_last_error",
     "pf_destroy",
 ]
 
@@ -106,6 +108,7 @@ def lib() -> ctypes.CDLL:
             "pf_set_params": (ctypes.c_int, [vp, dp, ctypes.c_double]),
             "pf_adjoint_step": (ctypes.c_int, [vp, vp, vp, vp, vp, dp]),
             "pf_adjoint_initial_rate": (ctypes.c_int, [vp, vp, vp, vp, dp]),
+            "pf_timing": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)]),
             "pf_fem_table_size": (sz, []),
             "pf_fem_tables": (ctypes.c_int, [cfgp, dp, sz]),
             "pf_status_str": (ctypes.c_char_p, [ctypes.c_int]),
@@ -293,6 +296,15 @@ class Context:
         F = self.new_field(3)
         self._check(self.L.pf_force(self.ctx, _ptr(P), _ptr(phi), _ptr(u), _ptr(F)), "pf_force")
         return F
+
+    def timing(self, enable: bool):
+        """Returns {class: (ms, launches)} accumulated since the last call and
+        switches per-launch event timing on or off."""
+        n = len(KERNEL_CLASSES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        self._check(self.L.pf_timing(self.ctx, 1 if enable else 0, ms, cnt), "pf_timing")
+        return {k: (ms[t], cnt[t]) for t, k in enumerate(KERNEL_CLASSES)}
 
     def energy(self):
         out = (ctypes.c_double * 5)()
