@@ -127,9 +127,10 @@ pf_status pf_workspace_size(const pf_config *cfg, size_t *bytes);
 /* Binds a context to cfg, a device workspace of at least
  * pf_workspace_size() bytes (256-byte aligned, owned by the caller, must
  * outlive the context) and a HIP stream (NULL: the null stream).  Builds the
- * FEM operator tables and solves the electrode basis potentials (one Poisson
- * solve per electrode plus one for the fixed boundary values), then waits
- * for the stream.  *out is set on success. */
+ * FEM operator tables and the ghost planes, then waits for the stream.  The
+ * potential of the boundary values alone (for pf_energy) and the electrode
+ * basis potentials (for the adjoint) are solved on first use, to
+ * min(tol_phi, 1e-12).  *out is set on success. */
 pf_status pf_init(const pf_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream, pf_ctx **out);
 
 /* Loads the polarisation P (device, 3N) as the current state, with optional
@@ -168,22 +169,29 @@ pf_status pf_solve_phi(pf_ctx *ctx, const void *P, void *phi, pf_solve_stats *st
 pf_status pf_solve_u(pf_ctx *ctx, const void *P, void *u, pf_solve_stats *stats);
 
 /* Force F = -L dF/dP at P (Eq. 7 without noise) for given phi (N doubles)
- * and u (3N doubles), written to F (3N, state precision).  No solves.
+ * and u (3N doubles), written to F (3N, state precision).  No solves.  In
+ * PF_FP32_REFINE the force is evaluated in float from rounded phi and u.
  * Asynchronous. */
 pf_status pf_force(pf_ctx *ctx, const void *P, const void *phi, const void *u, void *F);
 
 /* Free energy of the current P: out[0..4] = bulk, gradient, electrostatic,
- * elastic, total (host doubles).  Solves phi and u at P (warm-started from
- * the state's solutions, to the configured tolerances) and splits the
- * electrostatic energy into the polarisation part and the applied part
- * (linear superposition with the electrode basis).  Synchronises. */
+ * elastic, total (host doubles), evaluated in FP64.  Solves phi and u at P
+ * in FP64 (warm-started from the state's solutions, configured
+ * tolerances); the electrostatic energy is split into the polarisation
+ * part, (h^3/2) rho^T A^-1 rho, and the applied part -h^3 P . E_app (linear
+ * superposition with the potential of the boundary values).  The
+ * polarisation and elastic parts are evaluated as the stationary values of
+ * their quadratic forms, so their error is second order in the solve
+ * error.  Synchronises. */
 pf_status pf_energy(pf_ctx *ctx, double out[5]);
 
 /* Changes electrode voltages (n_electrodes host doubles, NULL: keep) and
  * the Landau coefficient a1 (used by the differentiable layer). */
 pf_status pf_set_params(pf_ctx *ctx, const double *volts, double a1);
 
-/* One reverse step of the discrete adjoint of pf_step.  In: the state
+/* One reverse step of the discrete adjoint of pf_step (needs
+ * nonlocal_every <= 1; the linearised solves run in FP64 in both
+ * precisions, warm-started from the previous adjoint step's solutions).  In: the state
  * (P_n, V_n) before forward step n (device, 3N each, state precision; V_n is
  * ignored for Euler) and the adjoints (lamP, lamV) of the state after it;
  * out: lamP, lamV overwritten by the adjoints of the state before it, and

@@ -27,10 +27,11 @@ template <typename T> hipError_t launch_fill(T* a, int64_t n, T v, hipStream_t s
 template <typename T, typename U> hipError_t launch_convert(const T* a, U* b, int64_t n, hipStream_t s);
 template <typename T> hipError_t launch_cg_finish(T* x, const T* p, int64_t n, const CgScalars* sc, hipStream_t s);
 hipError_t launch_cg_reduce(const double* partials, int nblocks, int nv, CgScalars* sc, int mode, double tol,
-                            int maxit, hipStream_t s);
-template <typename T, typename S>
+                            int maxit, hipStream_t s, double tol2, double* out);
+hipError_t launch_refine_update(double* x64, float* x32, const float* d, int64_t n, hipStream_t s);
+template <typename T, typename S, typename R>
 hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
-                                int with_bc, const T* ghost_top, T phi_bottom, const T* x, T* r, T* p,
+                                int with_bc, const T* ghost_top, T phi_bottom, const T* x, R* r, R* p, R* dz,
                                 double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_poisson_cg_a(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* r, const T* p_old,
@@ -38,9 +39,9 @@ hipError_t launch_poisson_cg_a(const Dims& d, const TileMap& tm, const Coefs<T>&
 template <typename T>
 hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* p, T* r,
                                const CgScalars* sc, double* partials, hipStream_t s);
-template <typename T, typename S>
+template <typename T, typename S, typename R>
 hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const S* P, const S* V, T cdt,
-                            T* x, T* r, T* p0, T* p1, double* partials, hipStream_t s);
+                            const T* W, T* x, R* r, R* p0, R* p1, R* dz, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_fem_cg_a(const Dims& d, const TileMap& tm, const FemTables* tb, const T* r, const T* p_old,
                            T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s);
@@ -51,8 +52,24 @@ template <typename T>
 hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* P, const T* V, T cdt,
                         const T* phi, const T* ghost_top, const T* u, int mode, T* Pn, T* Vn, T* Fout,
                         hipStream_t s);
+template <typename S>
+hipError_t launch_energy(const Dims& d, const Coefs<double>& cf, const FemTables* tb, const S* P, const double* phi,
+                         const double* phi_bc, const double* ghost_top, const double* u, double* partials,
+                         hipStream_t s);
+template <typename S>
+hipError_t launch_hvp(const Dims& d, const Coefs<double>& cf, const FemTables* tb, const S* P, const S* V,
+                      double cdt, const double* w, const double* u, const double* psi, const double* du, double* Hw,
+                      hipStream_t s);
+template <typename S>
+hipError_t launch_adjoint_axpy(int mode, double dt, S* lamP, S* lamV, double* w, const double* Hw, int64_t n,
+                               hipStream_t s);
+template <typename S>
+hipError_t launch_theta_dot(const Dims& d, const Coefs<double>& cf, const double* w, const double* phi_e, int x0,
+                            int x1, int y0, int y1, const S* P, const S* V, double cdt, double* partials,
+                            hipStream_t s);
 
-enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2 };
+enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2, kRedOuter = 3, kRedSum = 4 };
+enum { kAdjPrepPc = 0, kAdjPrepEuler, kAdjPrepInit, kAdjUpdPc, kAdjUpdEuler, kAdjUpdInit };
 
 // ---------------------------------------------------------------------------
 // FEM operator tables from 1D element integrals
@@ -170,6 +187,7 @@ void build_tables(const pf_config& c, FemTables* t) {
   t->inv_diag[1] = 1.0 / t->K[1][0][0][13];
 }
 
+
 // ---------------------------------------------------------------------------
 // Context and workspace
 // ---------------------------------------------------------------------------
@@ -179,16 +197,21 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   // byte offsets into the workspace
-  size_t P[2], V[2], phi, u, phi32, u32, ghost64, ghost32, ghost_unit64, phi_bc, basis;
-  size_t pr, pp[2], fr, fp[2];          // Poisson / FEM CG vectors (state precision)
-  size_t rr64, fr64, dphi64, du64;       // FP32_REFINE outer residuals and corrections
-  size_t adj[8];                         // adjoint / energy scratch
-  size_t tables, scalars, partials;
+  size_t P[2], V[2];           // state (state precision), double-buffered
+  size_t phi, u;               // solutions (FP64 masters)
+  size_t phi32, u32;           // FP32 working copies (FP32_REFINE)
+  size_t ghost64, ghost32, ghost_unit;
+  size_t phi_bc, basis;        // boundary potential and electrode basis (FP64)
+  size_t pr, pp[2], fr, fp[2]; // CG vectors, sized for FP64 (FP32 solves use half)
+  size_t dphi, du;             // refinement corrections (FP32)
+  size_t scratch[8];           // 3N doubles each: adjoint, energy, conversions
+  size_t tables, scalars, result, partials;
   size_t total;
 };
 
-constexpr int kNumScalars = 4;   // Poisson, FEM, two spares
+constexpr int kNumScalars = 4;
 constexpr int kPartialsPerBlock = 4;
+constexpr int kResultSlots = 128;
 
 Layout make_layout(const pf_config& c, int npartials) {
   const size_t N = (size_t)c.nx * c.ny * c.nz;
@@ -205,32 +228,46 @@ Layout make_layout(const pf_config& c, int npartials) {
   for (int b = 0; b < 2; b++) L.V[b] = take(3 * N * es);
   L.phi = take(N * 8);
   L.u = take(3 * N * 8);
-  L.phi32 = c.precision == PF_FP32_REFINE ? take(N * 4) : 0;
-  L.u32 = c.precision == PF_FP32_REFINE ? take(3 * N * 4) : 0;
+  L.phi32 = take(N * 4);
+  L.u32 = take(3 * N * 4);
   L.ghost64 = take(plane * 8);
   L.ghost32 = take(plane * 4);
-  L.ghost_unit64 = take(plane * 8);
+  L.ghost_unit = take(plane * 8);
   L.phi_bc = take(N * 8);
   L.basis = take((size_t)std::max(c.n_electrodes, 1) * N * 8);
-  L.pr = take(N * es);
-  for (int b = 0; b < 2; b++) L.pp[b] = take(N * es);
-  L.fr = take(3 * N * es);
-  for (int b = 0; b < 2; b++) L.fp[b] = take(3 * N * es);
-  if (c.precision == PF_FP32_REFINE) {
-    L.rr64 = take(N * 8);
-    L.fr64 = take(3 * N * 8);
-    L.dphi64 = take(N * 8);
-    L.du64 = take(3 * N * 8);
-  } else {
-    L.rr64 = L.fr64 = L.dphi64 = L.du64 = 0;
-  }
-  for (int t = 0; t < 8; t++) L.adj[t] = take(3 * N * 8);
+  L.pr = take(N * 8);
+  for (int b = 0; b < 2; b++) L.pp[b] = take(N * 8);
+  L.fr = take(3 * N * 8);
+  for (int b = 0; b < 2; b++) L.fp[b] = take(3 * N * 8);
+  L.dphi = take(N * 4);
+  L.du = take(3 * N * 4);
+  for (int t = 0; t < 8; t++) L.scratch[t] = take(3 * N * 8);
   L.tables = take(sizeof(FemTables));
   L.scalars = take(sizeof(CgScalars) * kNumScalars);
+  L.result = take(kResultSlots * 8);
   L.partials = take((size_t)npartials * kPartialsPerBlock * 8 * kNumScalars);
   L.total = o;
   return L;
 }
+
+// Scratch slots (3N doubles each).
+enum {
+  kScrW = 0,      // adjoint direction w
+  kScrHw,         // H w
+  kScrULin,       // displacement at the linearisation point
+  kScrDu,         // adjoint displacement
+  kScrPsi,        // adjoint potential (N)
+  kScrPhiE,       // energy: phi at P (N)
+  kScrUE,         // energy: u at P
+  kScrTmp,        // conversions
+};
+
+// Iteration-count predictions (one per kind of solve), used to size the
+// first batch of iterations enqueued before the first read-back.
+enum { kPredPhi = 0, kPredU, kPredPhiIn, kPredUIn, kPredAux, kPredAdjPsi, kPredAdjU, kPredAdjDu, kPredCount };
+
+constexpr double kInnerTol = 1e-5;  // FP32 inner solves of a refinement sweep
+constexpr int kMaxOuter = 30;
 
 }  // namespace
 
@@ -239,7 +276,6 @@ Layout make_layout(const pf_config& c, int npartials) {
 struct pf_ctx {
   pf_config cfg;
   std::vector<pf_electrode> electrodes;
-  std::vector<double> volts;
   pf::Dims dims;
   pf::Layout lay;
   char* ws;
@@ -249,12 +285,15 @@ struct pf_ctx {
   pf::TileMap tm;           // tile-kernel geometry
   int npartials;            // partial slots per solver (max of both block counts)
   pf::CgScalars* host_sc;   // pinned read-back buffer
+  double* host_res;         // pinned read-back of reduction results
   std::string err;
   bool have_state;
-  bool have_basis;
+  bool phi_bc_valid;
+  bool basis_valid;
+  bool adj_warm;            // adjoint scratch holds earlier adjoint solutions
   int64_t step;
   int cur;                  // which P/V buffer is current
-  int last_iters_phi, last_iters_u;
+  int pred[pf::kPredCount];
   // per-kernel-class event timing
   bool timing;
   std::vector<hipEvent_t> events;
@@ -274,6 +313,11 @@ T* at(pf_ctx* c, size_t off) {
   return reinterpret_cast<T*>(c->ws + off);
 }
 
+template <typename T>
+T* scratch(pf_ctx* c, int slot) {
+  return at<T>(c, c->lay.scratch[slot]);
+}
+
 pf_status fail(pf_ctx* c, pf_status s, const char* fmt, ...) {
   if (c) {
     char buf[512];
@@ -286,12 +330,18 @@ pf_status fail(pf_ctx* c, pf_status s, const char* fmt, ...) {
   return s;
 }
 
-#define PF_HIP(ctx, call)                                                                 \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess)                                                                 \
-      return fail(ctx, PF_EHIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
-                  __LINE__);                                                              \
+#define PF_HIP(ctx, ...)                                                                         \
+  do {                                                                                           \
+    hipError_t e_ = (__VA_ARGS__);                                                               \
+    if (e_ != hipSuccess)                                                                        \
+      return fail(ctx, PF_EHIP, "%s: %s (%s:%d)", #__VA_ARGS__, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                                     \
+  } while (0)
+
+#define PF_TRY(expr)                          \
+  do {                                        \
+    pf_status s_ = (expr);                    \
+    if (s_ != PF_OK) return s_;               \
   } while (0)
 
 pf_status validate(const pf_config* c, std::string* why) {
@@ -354,13 +404,19 @@ Coefs<T> make_coefs(const pf_ctx* c) {
   return k;
 }
 
+bool fp32(const pf_ctx* c) { return c->cfg.precision == PF_FP32_REFINE; }
+size_t state_bytes(const pf_ctx* c) { return fp32(c) ? 4 : 8; }
+
 CgScalars* dev_sc(pf_ctx* c, int which) { return at<CgScalars>(c, c->lay.scalars) + which; }
 double* dev_partials(pf_ctx* c, int which) {
   return at<double>(c, c->lay.partials) + (size_t)which * c->npartials * kPartialsPerBlock;
 }
+double* dev_result(pf_ctx* c) { return at<double>(c, c->lay.result); }
 
-// Event timing of one launch: `launch` is called between two event records
-// when timing is on.  solver/k tag CG iterations (solver -1: always counted).
+// ---------------------------------------------------------------------------
+// Event timing of launches
+// ---------------------------------------------------------------------------
+
 template <typename F>
 hipError_t timed(pf_ctx* c, int cls, int solver, int k, F&& launch) {
   if (!c->timing) return launch();
@@ -396,7 +452,6 @@ void collect_timing(pf_ctx* c, int solver, int iters) {
   c->pending.clear();
 }
 
-// Reads back the scalars of one solver (synchronises the stream).
 pf_status read_scalars(pf_ctx* c, int which, CgScalars* out) {
   PF_HIP(c, hipMemcpyAsync(c->host_sc, dev_sc(c, which), sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
   PF_HIP(c, hipStreamSynchronize(c->stream));
@@ -411,36 +466,34 @@ pf_status sync(pf_ctx* c) {
   return PF_OK;
 }
 
+hipError_t reduce(pf_ctx* c, const double* part, int nb, int nv, int which, int mode, double tol, double tol2,
+                  double* out, int solver = -1, int k = -1) {
+  const int maxit = c->cfg.maxit;
+  return timed(c, PF_KC_REDUCE, solver, k, [&] {
+    return launch_cg_reduce(part, nb, nv, dev_sc(c, which), mode, tol, maxit, c->stream, tol2, out);
+  });
+}
+
 // ---------------------------------------------------------------------------
 // Conjugate-gradient drivers
 // ---------------------------------------------------------------------------
 // The setup kernel forms r = b - A x and the first direction; each iteration
 // is two fused kernels (direction update + operator + p.q; residual update
-// + r.z + convergence).  Step lengths live on the device; the host enqueues
-// iterations in batches and reads the scalars once per batch, kernels
-// enqueued after convergence return at entry.  A last kernel applies the
-// deferred update of x.
+// + r.z), each followed by a single-block reduce that advances the scalars
+// on the device.  The host enqueues iterations in batches and reads the
+// scalars once per batch; kernels enqueued after convergence return at
+// entry.  A last kernel applies the deferred update of x.
 
 struct SolveResult {
   int iters;
+  int outer;
   double relres;
   int done;
 };
 
-pf_status finish_solve(pf_ctx* c, int which, const CgScalars& h, SolveResult* res, const char* what) {
-  res->iters = h.iter;
-  res->done = h.done;
-  res->relres = h.zero_rhs ? 0.0 : std::sqrt(h.rnorm2 / h.bnorm2);
-  if (h.done == kNonFinite) return fail(c, PF_ENONFINITE, "%s: non-finite value in the CG reductions", what);
-  if (h.done == kMaxIt)
-    return fail(c, PF_ENOCONV, "%s: no convergence in %d iterations (relres %.3e)", what, h.iter, res->relres);
-  (void)which;
-  return PF_OK;
-}
-
 template <typename T>
 pf_status run_cg(pf_ctx* c, int which, int predicted, T* x, T* const pbuf[2], int64_t n,
-                 const std::function<hipError_t(int)>& iteration, SolveResult* res, const char* what) {
+                 const std::function<hipError_t(int)>& iteration, CgScalars* hout, const char* what) {
   CgScalars h;
   int k = 0;
   int batch = std::max(2, predicted);
@@ -448,8 +501,7 @@ pf_status run_cg(pf_ctx* c, int which, int predicted, T* x, T* const pbuf[2], in
   for (;;) {
     const int nb = std::min(batch, maxit - k);
     for (int t = 0; t < nb; t++, k++) PF_HIP(c, iteration(k));
-    pf_status st = read_scalars(c, which, &h);
-    if (st != PF_OK) return st;
+    PF_TRY(read_scalars(c, which, &h));
     if (h.done != kRunning) break;
     if (k >= maxit) return fail(c, PF_EHIP, "%s: solver state did not advance", what);
     batch = std::max(4, predicted / 8);
@@ -457,80 +509,160 @@ pf_status run_cg(pf_ctx* c, int which, int predicted, T* x, T* const pbuf[2], in
   if (h.done != kNonFinite)
     PF_HIP(c, timed(c, PF_KC_FINISH, -1, -1,
                     [&] { return launch_cg_finish<T>(x, pbuf[h.iter & 1], n, dev_sc(c, which), c->stream); }));
-  return finish_solve(c, which, h, res, what);
+  *hout = h;
+  if (h.done == kNonFinite) return fail(c, PF_ENONFINITE, "%s: non-finite value in the CG reductions", what);
+  return PF_OK;
 }
 
-// Poisson solve for Pp = P + cdt V (V may be null); boundary values from
-// ghost (top) and phi_bottom when with_bc.
+pf_status cg_status(pf_ctx* c, const CgScalars& h, SolveResult* res, const char* what) {
+  res->iters = h.iter;
+  res->outer = 1;
+  res->done = h.done;
+  res->relres = h.zero_rhs ? 0.0 : std::sqrt(h.rnorm2 / h.bnorm2);
+  if (h.done == kMaxIt)
+    return fail(c, PF_ENOCONV, "%s: no convergence in %d iterations (relres %.3e)", what, h.iter, res->relres);
+  return PF_OK;
+}
+
 template <typename T>
-pf_status solve_poisson(pf_ctx* c, const T* P, const T* V, T cdt, int with_P, int with_bc, const T* ghost,
-                        T phi_bottom, T* x, double tol, bool warm, SolveResult* res) {
-  const Dims& d = c->dims;
-  const Coefs<T> cf = make_coefs<T>(c);
-  CgScalars* sc = dev_sc(c, 0);
-  double* part = dev_partials(c, 0);
-  T* r = at<T>(c, c->lay.pr);
-  T* pb[2] = {at<T>(c, c->lay.pp[0]), at<T>(c, c->lay.pp[1])};
-  if (!warm) PF_HIP(c, launch_fill<T>(x, d.N, (T)0, c->stream));
-  const TileMap& tm = c->tm;
-  const int nb = c->nblocks, tb_ = tm.nblocks, maxit = c->cfg.maxit;
-  PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
-    return launch_poisson_setup<T, T>(d, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, x, r, pb[0], part,
-                                      c->stream);
-  }));
-  PF_HIP(c, timed(c, PF_KC_REDUCE, -1, -1,
-                  [&] { return launch_cg_reduce(part, nb, 3, sc, kRedSetup, tol, maxit, c->stream); }));
-  auto iteration = [&](int k) -> hipError_t {
+std::function<hipError_t(int)> poisson_iteration(pf_ctx* c, const Coefs<T>& cf, T* r, T* const pb[2], T* x,
+                                                 double tol) {
+  return [=](int k) -> hipError_t {
+    const Dims& d = c->dims;
+    CgScalars* sc = dev_sc(c, 0);
+    double* part = dev_partials(c, 0);
     hipError_t e = timed(c, PF_KC_POISSON_A, 0, k, [&] {
-      return launch_poisson_cg_a<T>(d, tm, cf, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
+      return launch_poisson_cg_a<T>(d, c->tm, cf, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
     });
-    if (e == hipSuccess)
-      e = timed(c, PF_KC_REDUCE, 0, k,
-                [&] { return launch_cg_reduce(part, tb_, 1, sc, kRedAlpha, tol, maxit, c->stream); });
+    if (e == hipSuccess) e = reduce(c, part, c->tm.nblocks, 1, 0, kRedAlpha, tol, 0, nullptr, 0, k);
     if (e == hipSuccess)
       e = timed(c, PF_KC_POISSON_B, 0, k,
-                [&] { return launch_poisson_cg_b<T>(d, tm, cf, pb[(k + 1) & 1], r, sc, part, c->stream); });
-    if (e == hipSuccess)
-      e = timed(c, PF_KC_REDUCE, 0, k,
-                [&] { return launch_cg_reduce(part, tb_, 2, sc, kRedBeta, tol, maxit, c->stream); });
+                [&] { return launch_poisson_cg_b<T>(d, c->tm, cf, pb[(k + 1) & 1], r, sc, part, c->stream); });
+    if (e == hipSuccess) e = reduce(c, part, c->tm.nblocks, 2, 0, kRedBeta, tol, 0, nullptr, 0, k);
     return e;
   };
-  return run_cg<T>(c, 0, c->last_iters_phi, x, pb, d.N, iteration, res, "Poisson solve");
 }
 
 template <typename T>
-pf_status solve_fem(pf_ctx* c, const T* P, const T* V, T cdt, T* x, double tol, bool warm, SolveResult* res) {
-  const Dims& d = c->dims;
-  const Coefs<T> cf = make_coefs<T>(c);
-  const FemTables* tb = at<FemTables>(c, c->lay.tables);
-  CgScalars* sc = dev_sc(c, 1);
-  double* part = dev_partials(c, 1);
-  T* r = at<T>(c, c->lay.fr);
-  T* pb[2] = {at<T>(c, c->lay.fp[0]), at<T>(c, c->lay.fp[1])};
-  if (!warm) PF_HIP(c, launch_fill<T>(x, 3 * d.N, (T)0, c->stream));
-  const TileMap& tm = c->tm;
-  const int nb = c->nblocks, tb_ = tm.nblocks, maxit = c->cfg.maxit;
-  PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
-    return launch_fem_setup<T, T>(d, cf, tb, P, V, cdt, x, r, pb[0], pb[1], part, c->stream);
-  }));
-  PF_HIP(c, timed(c, PF_KC_REDUCE, -1, -1,
-                  [&] { return launch_cg_reduce(part, nb, 3, sc, kRedSetup, tol, maxit, c->stream); }));
-  auto iteration = [&](int k) -> hipError_t {
+std::function<hipError_t(int)> fem_iteration(pf_ctx* c, T* r, T* const pb[2], T* x, double tol) {
+  return [=](int k) -> hipError_t {
+    const Dims& d = c->dims;
+    const FemTables* tb = at<FemTables>(c, c->lay.tables);
+    CgScalars* sc = dev_sc(c, 1);
+    double* part = dev_partials(c, 1);
     hipError_t e = timed(c, PF_KC_FEM_A, 1, k, [&] {
-      return launch_fem_cg_a<T>(d, tm, tb, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
+      return launch_fem_cg_a<T>(d, c->tm, tb, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
     });
-    if (e == hipSuccess)
-      e = timed(c, PF_KC_REDUCE, 1, k,
-                [&] { return launch_cg_reduce(part, tb_, 1, sc, kRedAlpha, tol, maxit, c->stream); });
+    if (e == hipSuccess) e = reduce(c, part, c->tm.nblocks, 1, 1, kRedAlpha, tol, 0, nullptr, 1, k);
     if (e == hipSuccess)
       e = timed(c, PF_KC_FEM_B, 1, k,
-                [&] { return launch_fem_cg_b<T>(d, tm, tb, pb[(k + 1) & 1], r, sc, part, c->stream); });
-    if (e == hipSuccess)
-      e = timed(c, PF_KC_REDUCE, 1, k,
-                [&] { return launch_cg_reduce(part, tb_, 2, sc, kRedBeta, tol, maxit, c->stream); });
+                [&] { return launch_fem_cg_b<T>(d, c->tm, tb, pb[(k + 1) & 1], r, sc, part, c->stream); });
+    if (e == hipSuccess) e = reduce(c, part, c->tm.nblocks, 2, 1, kRedBeta, tol, 0, nullptr, 1, k);
     return e;
   };
-  return run_cg<T>(c, 1, c->last_iters_u, x, pb, 3 * d.N, iteration, res, "FEM solve");
+}
+
+// FP64 Poisson solve of A x = -D_h Pp + ghost terms, Pp = P + cdt V (P of
+// storage S; V may be null; P unused when with_P = 0).
+template <typename S>
+pf_status solve_poisson64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, int with_P, int with_bc,
+                          const double* ghost, double phi_bottom, double* x, double tol, bool warm,
+                          SolveResult* res) {
+  const Dims& d = c->dims;
+  const Coefs<double> cf = make_coefs<double>(c);
+  double* part = dev_partials(c, 0);
+  double* r = at<double>(c, c->lay.pr);
+  double* const pb[2] = {at<double>(c, c->lay.pp[0]), at<double>(c, c->lay.pp[1])};
+  if (!warm) PF_HIP(c, launch_fill<double>(x, d.N, 0.0, c->stream));
+  PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
+    return launch_poisson_setup<double, S, double>(d, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, x, r,
+                                                   pb[0], nullptr, part, c->stream);
+  }));
+  PF_HIP(c, reduce(c, part, c->nblocks, 3, 0, kRedSetup, tol, 0, nullptr));
+  CgScalars h;
+  PF_TRY(run_cg<double>(c, 0, c->pred[pred], x, pb, d.N, poisson_iteration<double>(c, cf, r, pb, x, tol), &h,
+                        "Poisson solve"));
+  c->pred[pred] = h.iter;
+  return cg_status(c, h, res, "Poisson solve");
+}
+
+// FP64 FEM solve of K x = f(eps0(Pp)) (W null) or K x = f(deps0/dP(Pp) W).
+template <typename S>
+pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, const double* W, double* x,
+                      double tol, bool warm, SolveResult* res) {
+  const Dims& d = c->dims;
+  const Coefs<double> cf = make_coefs<double>(c);
+  const FemTables* tb = at<FemTables>(c, c->lay.tables);
+  double* part = dev_partials(c, 1);
+  double* r = at<double>(c, c->lay.fr);
+  double* const pb[2] = {at<double>(c, c->lay.fp[0]), at<double>(c, c->lay.fp[1])};
+  if (!warm) PF_HIP(c, launch_fill<double>(x, 3 * d.N, 0.0, c->stream));
+  PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
+    return launch_fem_setup<double, S, double>(d, cf, tb, P, V, cdt, W, x, r, pb[0], pb[1], nullptr, part,
+                                               c->stream);
+  }));
+  PF_HIP(c, reduce(c, part, c->nblocks, 3, 1, kRedSetup, tol, 0, nullptr));
+  CgScalars h;
+  PF_TRY(run_cg<double>(c, 1, c->pred[pred], x, pb, 3 * d.N, fem_iteration<double>(c, r, pb, x, tol), &h,
+                        "FEM solve"));
+  c->pred[pred] = h.iter;
+  return cg_status(c, h, res, "FEM solve");
+}
+
+// Iterative refinement (FP32_REFINE): each sweep forms the FP64 residual of
+// the FP64 iterate x64 (the outer test ||b - A x64|| <= tol ||b||), solves
+// the correction equation in FP32 (FP64 dot products) to kInnerTol, adds the
+// correction to x64 and refreshes the FP32 working copy x32.
+pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, double cdt, double* x64, float* x32,
+                        double tol, bool warm, SolveResult* res) {
+  const Dims& d = c->dims;
+  const int which = fem ? 1 : 0;
+  const int64_t n = fem ? 3 * d.N : d.N;
+  const Coefs<double> cf64 = make_coefs<double>(c);
+  const Coefs<float> cf32 = make_coefs<float>(c);
+  const FemTables* tb = at<FemTables>(c, c->lay.tables);
+  double* part = dev_partials(c, which);
+  float* r = at<float>(c, fem ? c->lay.fr : c->lay.pr);
+  float* const pb[2] = {at<float>(c, fem ? c->lay.fp[0] : c->lay.pp[0]),
+                        at<float>(c, fem ? c->lay.fp[1] : c->lay.pp[1])};
+  float* dz = at<float>(c, fem ? c->lay.du : c->lay.dphi);
+  const char* what = fem ? "FEM solve (refined)" : "Poisson solve (refined)";
+  const int pred = fem ? kPredUIn : kPredPhiIn;
+  if (!warm) PF_HIP(c, launch_fill<double>(x64, n, 0.0, c->stream));
+  res->iters = 0;
+  res->outer = 0;
+  res->relres = 0;
+  auto iteration = fem ? fem_iteration<float>(c, r, pb, dz, kInnerTol)
+                       : poisson_iteration<float>(c, cf32, r, pb, dz, kInnerTol);
+  for (;;) {
+    if (fem) {
+      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
+        return launch_fem_setup<double, float, float>(d, cf64, tb, P, V, cdt, nullptr, x64, r, pb[0], pb[1], dz,
+                                                      part, c->stream);
+      }));
+    } else {
+      PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
+        return launch_poisson_setup<double, float, float>(d, cf64, P, V, cdt, 1, 1, at<double>(c, c->lay.ghost64),
+                                                          c->cfg.phi_bottom, x64, r, pb[0], dz, part, c->stream);
+      }));
+    }
+    PF_HIP(c, reduce(c, part, c->nblocks, 3, which, kRedOuter, tol, kInnerTol, nullptr));
+    CgScalars h;
+    PF_TRY(run_cg<float>(c, which, c->pred[pred], dz, pb, n, iteration, &h, what));
+    res->iters += h.iter;
+    res->relres = h.outer_b2 > 0 ? std::sqrt(h.outer_r2 / h.outer_b2) : 0.0;
+    if (h.outer_done) {
+      if (h.zero_rhs) PF_HIP(c, launch_fill<double>(x64, n, 0.0, c->stream));
+      PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_convert<double, float>(x64, x32, n, c->stream); }));
+      return PF_OK;
+    }
+    if (h.iter > 0) c->pred[pred] = h.iter;
+    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_refine_update(x64, x32, dz, n, c->stream); }));
+    res->outer++;
+    if (res->outer >= kMaxOuter) {
+      return fail(c, PF_ENOCONV, "%s: %d refinement sweeps, relres %.3e", what, res->outer, res->relres);
+    }
+  }
 }
 
 pf_status worst(pf_status a, pf_status b) {
@@ -539,6 +671,8 @@ pf_status worst(pf_status a, pf_status b) {
   if (a == PF_ENOCONV) return b;
   return a;
 }
+
+bool fatal(pf_status s) { return s != PF_OK && s != PF_ENOCONV; }
 
 void stats_add(pf_step_stats* st, int which, const SolveResult& r) {
   if (!st) return;
@@ -555,27 +689,260 @@ void stats_add(pf_step_stats* st, int which, const SolveResult& r) {
   }
 }
 
-// Solves phi and u at Pp = P + cdt V into the state's phi and u.
-pf_status solve_nonlocal64(pf_ctx* c, const double* P, const double* V, double cdt, bool warm, pf_step_stats* st) {
+// Solves phi and u of the state at Pp = P + cdt V (state precision).
+pf_status solve_nonlocal(pf_ctx* c, const void* P, const void* V, double cdt, bool warm, pf_step_stats* st) {
   pf_status out = PF_OK;
+  double* phi = at<double>(c, c->lay.phi);
+  double* u = at<double>(c, c->lay.u);
   if (c->cfg.terms & PF_TERM_ELEC) {
     SolveResult r{};
-    pf_status s = solve_poisson<double>(c, P, V, cdt, 1, 1, at<double>(c, c->lay.ghost64), c->cfg.phi_bottom,
-                                        at<double>(c, c->lay.phi), c->cfg.tol_phi, warm, &r);
-    if (s != PF_OK && s != PF_ENOCONV) return s;
-    c->last_iters_phi = r.iters;
+    pf_status s;
+    if (fp32(c))
+      s = solve_refined(c, false, static_cast<const float*>(P), static_cast<const float*>(V), cdt, phi,
+                        at<float>(c, c->lay.phi32), c->cfg.tol_phi, warm, &r);
+    else
+      s = solve_poisson64<double>(c, kPredPhi, static_cast<const double*>(P), static_cast<const double*>(V), cdt, 1,
+                                  1, at<double>(c, c->lay.ghost64), c->cfg.phi_bottom, phi, c->cfg.tol_phi, warm,
+                                  &r);
+    if (fatal(s)) return s;
     stats_add(st, 0, r);
     out = worst(out, s);
   }
   if (c->cfg.terms & PF_TERM_ELAS) {
     SolveResult r{};
-    pf_status s = solve_fem<double>(c, P, V, cdt, at<double>(c, c->lay.u), c->cfg.tol_u, warm, &r);
-    if (s != PF_OK && s != PF_ENOCONV) return s;
-    c->last_iters_u = r.iters;
+    pf_status s;
+    if (fp32(c))
+      s = solve_refined(c, true, static_cast<const float*>(P), static_cast<const float*>(V), cdt, u,
+                        at<float>(c, c->lay.u32), c->cfg.tol_u, warm, &r);
+    else
+      s = solve_fem64<double>(c, kPredU, static_cast<const double*>(P), static_cast<const double*>(V), cdt, nullptr,
+                              u, c->cfg.tol_u, warm, &r);
+    if (fatal(s)) return s;
     stats_add(st, 1, r);
     out = worst(out, s);
   }
   return out;
+}
+
+// Force sweep on the state's buffers (state precision).
+pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt, int mode, void* Pn, void* Vn,
+                             void* F, const void* phi_override = nullptr, const void* u_override = nullptr) {
+  const FemTables* tb = at<FemTables>(c, c->lay.tables);
+  if (fp32(c)) {
+    const Coefs<float> cf = make_coefs<float>(c);
+    const float* phi = phi_override ? static_cast<const float*>(phi_override) : at<float>(c, c->lay.phi32);
+    const float* u = u_override ? static_cast<const float*>(u_override) : at<float>(c, c->lay.u32);
+    PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
+      return launch_force<float>(c->dims, cf, tb, static_cast<const float*>(P), static_cast<const float*>(V),
+                                 (float)cdt, phi, at<float>(c, c->lay.ghost32), u, mode, static_cast<float*>(Pn),
+                                 static_cast<float*>(Vn), static_cast<float*>(F), c->stream);
+    }));
+  } else {
+    const Coefs<double> cf = make_coefs<double>(c);
+    const double* phi = phi_override ? static_cast<const double*>(phi_override) : at<double>(c, c->lay.phi);
+    const double* u = u_override ? static_cast<const double*>(u_override) : at<double>(c, c->lay.u);
+    PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
+      return launch_force<double>(c->dims, cf, tb, static_cast<const double*>(P), static_cast<const double*>(V), cdt,
+                                  phi, at<double>(c, c->lay.ghost64), u, mode, static_cast<double*>(Pn),
+                                  static_cast<double*>(Vn), static_cast<double*>(F), c->stream);
+    }));
+  }
+  return PF_OK;
+}
+
+// Uploads the top ghost plane for the current electrode voltages.
+pf_status upload_ghosts(pf_ctx* c) {
+  const pf_config& g = c->cfg;
+  std::vector<double> g64((size_t)g.nx * g.ny, g.phi_top);
+  for (auto& e : c->electrodes)
+    for (int j = e.y0; j < e.y1; j++)
+      for (int i = e.x0; i < e.x1; i++) g64[(size_t)i + (size_t)g.nx * j] = e.volts;
+  std::vector<float> g32(g64.begin(), g64.end());
+  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.ghost64, g64.data(), g64.size() * 8, hipMemcpyHostToDevice, c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.ghost32, g32.data(), g32.size() * 4, hipMemcpyHostToDevice, c->stream));
+  PF_HIP(c, hipStreamSynchronize(c->stream));
+  return PF_OK;
+}
+
+double aux_tol(const pf_ctx* c) { return std::min(c->cfg.tol_phi, 1e-12); }
+
+// phi_bc: the potential of the boundary values with P = 0 (linear-dielectric
+// superposition of the applied field).
+pf_status ensure_phi_bc(pf_ctx* c) {
+  if (c->phi_bc_valid) return PF_OK;
+  SolveResult r{};
+  pf_status s = solve_poisson64<double>(c, kPredAux, nullptr, nullptr, 0.0, 0, 1, at<double>(c, c->lay.ghost64),
+                                        c->cfg.phi_bottom, at<double>(c, c->lay.phi_bc), aux_tol(c), false, &r);
+  if (fatal(s)) return s;
+  c->phi_bc_valid = true;
+  return s;
+}
+
+// Electrode basis: phi^(e) for unit voltage on electrode e, every other
+// boundary value zero, P = 0.
+pf_status ensure_basis(pf_ctx* c) {
+  if (c->basis_valid || c->cfg.n_electrodes == 0) return PF_OK;
+  const pf_config& g = c->cfg;
+  pf_status out = PF_OK;
+  for (int e = 0; e < g.n_electrodes; e++) {
+    std::vector<double> unit((size_t)g.nx * g.ny, 0.0);
+    const pf_electrode& el = c->electrodes[e];
+    for (int j = el.y0; j < el.y1; j++)
+      for (int i = el.x0; i < el.x1; i++) unit[(size_t)i + (size_t)g.nx * j] = 1.0;
+    PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.ghost_unit, unit.data(), unit.size() * 8, hipMemcpyHostToDevice,
+                             c->stream));
+    SolveResult r{};
+    pf_status s = solve_poisson64<double>(c, kPredAux, nullptr, nullptr, 0.0, 0, 1, at<double>(c, c->lay.ghost_unit),
+                                          0.0, at<double>(c, c->lay.basis) + (size_t)e * c->dims.N, aux_tol(c), false,
+                                          &r);
+    if (fatal(s)) return s;
+    out = worst(out, s);
+  }
+  c->basis_valid = true;
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint
+// ---------------------------------------------------------------------------
+
+// Hw = (dF/dP)(X) w, X = P + cdt V (storage S), w in scratch kScrW.
+template <typename S>
+pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt) {
+  const Dims& d = c->dims;
+  const Coefs<double> cf = make_coefs<double>(c);
+  const FemTables* tb = at<FemTables>(c, c->lay.tables);
+  double* w = scratch<double>(c, kScrW);
+  double* ulin = scratch<double>(c, kScrULin);
+  double* du = scratch<double>(c, kScrDu);
+  double* psi = scratch<double>(c, kScrPsi);
+  pf_status out = PF_OK;
+  if (c->cfg.terms & PF_TERM_ELAS) {
+    SolveResult r{};
+    pf_status s = solve_fem64<S>(c, kPredAdjU, P, V, cdt, nullptr, ulin, c->cfg.tol_u, c->adj_warm, &r);
+    if (fatal(s)) return s;
+    out = worst(out, s);
+    s = solve_fem64<S>(c, kPredAdjDu, P, V, cdt, w, du, c->cfg.tol_u, c->adj_warm, &r);
+    if (fatal(s)) return s;
+    out = worst(out, s);
+  }
+  if (c->cfg.terms & PF_TERM_ELEC) {
+    SolveResult r{};
+    pf_status s = solve_poisson64<double>(c, kPredAdjPsi, w, nullptr, 0.0, 1, 0, at<double>(c, c->lay.ghost64), 0.0,
+                                          psi, c->cfg.tol_phi, c->adj_warm, &r);
+    if (fatal(s)) return s;
+    out = worst(out, s);
+  }
+  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+    return launch_hvp<S>(d, cf, tb, P, V, cdt, w, ulin, psi, du, scratch<double>(c, kScrHw), c->stream);
+  }));
+  c->adj_warm = true;
+  return out;
+}
+
+// dtheta += scale * w . dF/dtheta(X), theta = (V_1..V_ne, a1).
+template <typename S>
+pf_status theta_accumulate(pf_ctx* c, const S* P, const S* V, double cdt, double scale, double* dtheta) {
+  const Dims& d = c->dims;
+  const Coefs<double> cf = make_coefs<double>(c);
+  const double* w = scratch<double>(c, kScrW);
+  double* part = dev_partials(c, 2);
+  const int ne = c->cfg.n_electrodes;
+  if ((c->cfg.terms & PF_TERM_ELEC) && ne > 0) {
+    PF_TRY(ensure_basis(c));
+    for (int e = 0; e < ne; e++) {
+      const pf_electrode& el = c->electrodes[e];
+      const double* phe = at<double>(c, c->lay.basis) + (size_t)e * d.N;
+      PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+        return launch_theta_dot<S>(d, cf, w, phe, el.x0, el.x1, el.y0, el.y1, P, V, cdt, part, c->stream);
+      }));
+      PF_HIP(c, reduce(c, part, c->nblocks, 1, 2, kRedSum, 0, 0, dev_result(c) + e));
+    }
+  }
+  if (c->cfg.terms & PF_TERM_LANDAU) {
+    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+      return launch_theta_dot<S>(d, cf, w, nullptr, 0, 0, 0, 0, P, V, cdt, part, c->stream);
+    }));
+    PF_HIP(c, reduce(c, part, c->nblocks, 1, 2, kRedSum, 0, 0, dev_result(c) + ne));
+  }
+  PF_HIP(c, hipMemcpyAsync(c->host_res, dev_result(c), (ne + 1) * 8, hipMemcpyDeviceToHost, c->stream));
+  PF_TRY(sync(c));
+  for (int e = 0; e < ne; e++)
+    if ((c->cfg.terms & PF_TERM_ELEC)) dtheta[e] += scale * c->host_res[e];
+  if (c->cfg.terms & PF_TERM_LANDAU) dtheta[ne] += scale * c->host_res[ne];
+  return PF_OK;
+}
+
+template <typename S>
+pf_status adjoint_step_t(pf_ctx* c, const S* Pn, const S* Vn, S* lamP, S* lamV, double* dtheta) {
+  const bool pc = c->cfg.integrator == PF_INT_PC;
+  const int64_t n3 = 3 * c->dims.N;
+  const double dt = c->cfg.dt;
+  double* w = scratch<double>(c, kScrW);
+  double* Hw = scratch<double>(c, kScrHw);
+  const S* V = pc ? Vn : nullptr;
+  const double cdt = pc ? dt : 0.0;
+  PF_HIP(c, launch_adjoint_axpy<S>(pc ? kAdjPrepPc : kAdjPrepEuler, dt, lamP, lamV, w, Hw, n3, c->stream));
+  pf_status s = hvp<S>(c, Pn, V, cdt);
+  if (fatal(s)) return s;
+  PF_TRY(theta_accumulate<S>(c, Pn, V, cdt, pc ? 1.0 : dt, dtheta));
+  PF_HIP(c, launch_adjoint_axpy<S>(pc ? kAdjUpdPc : kAdjUpdEuler, dt, lamP, lamV, w, Hw, n3, c->stream));
+  PF_TRY(sync(c));
+  return s;
+}
+
+template <typename S>
+pf_status adjoint_initial_t(pf_ctx* c, const S* P0, S* lamP, S* lamV, double* dtheta) {
+  const int64_t n3 = 3 * c->dims.N;
+  double* w = scratch<double>(c, kScrW);
+  double* Hw = scratch<double>(c, kScrHw);
+  PF_HIP(c, launch_adjoint_axpy<S>(kAdjPrepInit, 0.0, lamP, lamV, w, Hw, n3, c->stream));
+  pf_status s = hvp<S>(c, P0, nullptr, 0.0);
+  if (fatal(s)) return s;
+  PF_TRY(theta_accumulate<S>(c, P0, nullptr, 0.0, 1.0, dtheta));
+  PF_HIP(c, launch_adjoint_axpy<S>(kAdjUpdInit, 0.0, lamP, lamV, w, Hw, n3, c->stream));
+  PF_TRY(sync(c));
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Energy
+// ---------------------------------------------------------------------------
+
+template <typename S>
+pf_status energy_t(pf_ctx* c, const S* P, double out[5]) {
+  const Dims& d = c->dims;
+  const Coefs<double> cf = make_coefs<double>(c);
+  pf_status st = PF_OK;
+  double* phi = scratch<double>(c, kScrPhiE);
+  double* u = scratch<double>(c, kScrUE);
+  if (c->cfg.terms & PF_TERM_ELEC) {
+    PF_TRY(ensure_phi_bc(c));
+    PF_HIP(c, hipMemcpyAsync(phi, at<double>(c, c->lay.phi), d.N * 8, hipMemcpyDeviceToDevice, c->stream));
+    SolveResult r{};
+    pf_status s = solve_poisson64<S>(c, kPredAux, P, nullptr, 0.0, 1, 1, at<double>(c, c->lay.ghost64),
+                                     c->cfg.phi_bottom, phi, c->cfg.tol_phi, true, &r);
+    if (fatal(s)) return s;
+    st = worst(st, s);
+  }
+  if (c->cfg.terms & PF_TERM_ELAS) {
+    PF_HIP(c, hipMemcpyAsync(u, at<double>(c, c->lay.u), 3 * d.N * 8, hipMemcpyDeviceToDevice, c->stream));
+    SolveResult r{};
+    pf_status s = solve_fem64<S>(c, kPredAux, P, nullptr, 0.0, nullptr, u, c->cfg.tol_u, true, &r);
+    if (fatal(s)) return s;
+    st = worst(st, s);
+  }
+  double* part = dev_partials(c, 2);
+  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+    return launch_energy<S>(d, cf, at<FemTables>(c, c->lay.tables), P, phi, at<double>(c, c->lay.phi_bc),
+                            at<double>(c, c->lay.ghost64), u, part, c->stream);
+  }));
+  PF_HIP(c, reduce(c, part, c->nblocks, 4, 2, kRedSum, 0, 0, dev_result(c)));
+  PF_HIP(c, hipMemcpyAsync(c->host_res, dev_result(c), 4 * 8, hipMemcpyDeviceToHost, c->stream));
+  PF_TRY(sync(c));
+  for (int t = 0; t < 4; t++) out[t] = c->host_res[t];
+  out[4] = out[0] + out[1] + out[2] + out[3];
+  return st;
 }
 
 }  // namespace
@@ -617,10 +984,6 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
     fprintf(stderr, "pf_init: %s\n", why.c_str());
     return PF_EINVAL;
   }
-  if (cfg->precision != PF_FP64) {
-    fprintf(stderr, "pf_init: this build supports PF_FP64 only\n");
-    return PF_EINVAL;
-  }
   if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
     fprintf(stderr, "pf_init: workspace must be non-null and 256-byte aligned\n");
     return PF_EINVAL;
@@ -629,7 +992,6 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->cfg = *cfg;
   c->electrodes.assign(cfg->electrodes, cfg->electrodes + cfg->n_electrodes);
   c->cfg.electrodes = c->electrodes.data();
-  for (auto& e : c->electrodes) c->volts.push_back(e.volts);
   c->dims = Dims{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz, (int64_t)cfg->nx * cfg->ny};
   c->nblocks = node_blocks(c->dims);
   c->tm = make_tile_map(c->dims);
@@ -643,47 +1005,37 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->ws = static_cast<char*>(ws);
   c->ws_bytes = bytes;
   c->stream = static_cast<hipStream_t>(stream);
-  c->have_state = false;
-  c->have_basis = false;
+  c->have_state = c->phi_bc_valid = c->basis_valid = c->adj_warm = false;
   c->step = 0;
   c->cur = 0;
-  c->last_iters_phi = c->last_iters_u = 16;
+  for (int t = 0; t < kPredCount; t++) c->pred[t] = 16;
   c->timing = false;
   std::memset(c->kc_ms, 0, sizeof(c->kc_ms));
   std::memset(c->kc_n, 0, sizeof(c->kc_n));
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_sc), sizeof(CgScalars), hipHostMallocDefault) != hipSuccess) {
+  c->host_sc = nullptr;
+  c->host_res = nullptr;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_sc), sizeof(CgScalars), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->host_res), kResultSlots * 8, hipHostMallocDefault) != hipSuccess) {
     fprintf(stderr, "pf_init: pinned host allocation failed\n");
-    delete c;
+    pf_destroy(c);
     return PF_EHIP;
   }
-  // tables and ghost planes (host-built, copied once)
   FemTables tb;
   build_tables(c->cfg, &tb);
-  std::vector<double> g64((size_t)cfg->nx * cfg->ny, cfg->phi_top);
-  for (auto& e : c->electrodes)
-    for (int j = e.y0; j < e.y1; j++)
-      for (int i = e.x0; i < e.x1; i++) g64[(size_t)i + (size_t)cfg->nx * j] = e.volts;
-  std::vector<float> g32(g64.begin(), g64.end());
   pf_status st = PF_OK;
-  auto cp = [&](size_t off, const void* src, size_t n) {
-    if (st != PF_OK) return;
-    hipError_t e = hipMemcpyAsync(c->ws + off, src, n, hipMemcpyHostToDevice, c->stream);
-    if (e != hipSuccess) st = fail(c, PF_EHIP, "table upload: %s", hipGetErrorString(e));
-  };
-  cp(c->lay.tables, &tb, sizeof(tb));
-  cp(c->lay.ghost64, g64.data(), g64.size() * 8);
-  cp(c->lay.ghost32, g32.data(), g32.size() * 4);
+  hipError_t e = hipMemcpyAsync(c->ws + c->lay.tables, &tb, sizeof(tb), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) st = fail(c, PF_EHIP, "table upload: %s", hipGetErrorString(e));
+  if (st == PF_OK) st = upload_ghosts(c);
   if (st == PF_OK) {
     static_assert(sizeof(CgScalars) % 8 == 0, "scalars are cleared as doubles");
-    hipError_t e = launch_fill<double>(reinterpret_cast<double*>(c->ws + c->lay.scalars),
-                                       (int64_t)(sizeof(CgScalars) * kNumScalars / 8), 0.0, c->stream);
+    e = launch_fill<double>(reinterpret_cast<double*>(c->ws + c->lay.scalars),
+                            (int64_t)(sizeof(CgScalars) * kNumScalars / 8), 0.0, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) st = fail(c, PF_EHIP, "init: %s", hipGetErrorString(e));
   }
   if (st != PF_OK) {
     fprintf(stderr, "pf_init: %s\n", c->err.c_str());
-    (void)hipHostFree(c->host_sc);
-    delete c;
+    pf_destroy(c);
     return st;
   }
   *out = c;
@@ -694,33 +1046,39 @@ void pf_destroy(pf_ctx* c) {
   if (!c) return;
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
+  if (c->host_res) (void)hipHostFree(c->host_res);
   delete c;
 }
 
 pf_status pf_set_state(pf_ctx* c, const void* P, const void* phi0, const void* u0) {
   if (!c || !P) return fail(c, PF_EINVAL, "pf_set_state: null argument");
   const int64_t N = c->dims.N;
+  const size_t es = state_bytes(c);
   c->cur = 0;
   c->step = 0;
-  double* Pc = at<double>(c, c->lay.P[0]);
-  double* Vc = at<double>(c, c->lay.V[0]);
+  void* Pc = c->ws + c->lay.P[0];
+  void* Vc = c->ws + c->lay.V[0];
   double* phi = at<double>(c, c->lay.phi);
   double* u = at<double>(c, c->lay.u);
-  PF_HIP(c, hipMemcpyAsync(Pc, P, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+  PF_HIP(c, hipMemcpyAsync(Pc, P, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
   if (phi0) PF_HIP(c, hipMemcpyAsync(phi, phi0, N * 8, hipMemcpyDeviceToDevice, c->stream));
   else PF_HIP(c, launch_fill<double>(phi, N, 0.0, c->stream));
   if (u0) PF_HIP(c, hipMemcpyAsync(u, u0, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
   else PF_HIP(c, launch_fill<double>(u, 3 * N, 0.0, c->stream));
-  PF_HIP(c, launch_fill<double>(Vc, 3 * N, 0.0, c->stream));
+  if (fp32(c)) {
+    PF_HIP(c, launch_convert<double, float>(phi, at<float>(c, c->lay.phi32), N, c->stream));
+    PF_HIP(c, launch_convert<double, float>(u, at<float>(c, c->lay.u32), 3 * N, c->stream));
+    PF_HIP(c, launch_fill<float>(static_cast<float*>(Vc), 3 * N, 0.0f, c->stream));
+  } else {
+    PF_HIP(c, launch_fill<double>(static_cast<double*>(Vc), 3 * N, 0.0, c->stream));
+  }
   pf_status s = PF_OK;
   if (c->cfg.integrator == PF_INT_PC) {
-    s = solve_nonlocal64(c, Pc, nullptr, 0.0, true, nullptr);
-    if (s != PF_OK && s != PF_ENOCONV) return s;
-    const Coefs<double> cf = make_coefs<double>(c);
-    PF_HIP(c, launch_force<double>(c->dims, cf, at<FemTables>(c, c->lay.tables), Pc, nullptr, 0.0, phi,
-                                   at<double>(c, c->lay.ghost64), u, kPcInit, nullptr, Vc, nullptr, c->stream));
+    s = solve_nonlocal(c, Pc, nullptr, 0.0, true, nullptr);
+    if (fatal(s)) return s;
+    PF_TRY(launch_state_force(c, Pc, nullptr, 0.0, kPcInit, nullptr, Vc, nullptr));
   }
-  PF_HIP(c, hipStreamSynchronize(c->stream));
+  PF_TRY(sync(c));
   c->have_state = true;
   return s;
 }
@@ -728,11 +1086,16 @@ pf_status pf_set_state(pf_ctx* c, const void* P, const void* phi0, const void* u
 pf_status pf_restore_state(pf_ctx* c, const void* P, const void* V, const void* phi, const void* u, int64_t step) {
   if (!c || !P || !V || !phi || !u) return fail(c, PF_EINVAL, "pf_restore_state: null argument");
   const int64_t N = c->dims.N;
+  const size_t es = state_bytes(c);
   c->cur = 0;
-  PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.P[0]), P, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
-  PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.V[0]), V, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.P[0], P, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.V[0], V, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
   PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.phi), phi, N * 8, hipMemcpyDeviceToDevice, c->stream));
   PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.u), u, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+  if (fp32(c)) {
+    PF_HIP(c, launch_convert<double, float>(at<double>(c, c->lay.phi), at<float>(c, c->lay.phi32), N, c->stream));
+    PF_HIP(c, launch_convert<double, float>(at<double>(c, c->lay.u), at<float>(c, c->lay.u32), 3 * N, c->stream));
+  }
   c->step = step;
   c->have_state = true;
   return PF_OK;
@@ -743,8 +1106,9 @@ pf_status pf_get_state(const pf_ctx* cc, void* P, void* V, void* phi, void* u, i
   if (!c) return PF_EINVAL;
   if (!c->have_state) return fail(c, PF_ESTATE, "pf_get_state: no state (call pf_set_state first)");
   const int64_t N = c->dims.N;
-  if (P) PF_HIP(c, hipMemcpyAsync(P, at<double>(c, c->lay.P[c->cur]), 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
-  if (V) PF_HIP(c, hipMemcpyAsync(V, at<double>(c, c->lay.V[c->cur]), 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+  const size_t es = state_bytes(c);
+  if (P) PF_HIP(c, hipMemcpyAsync(P, c->ws + c->lay.P[c->cur], 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
+  if (V) PF_HIP(c, hipMemcpyAsync(V, c->ws + c->lay.V[c->cur], 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
   if (phi) PF_HIP(c, hipMemcpyAsync(phi, at<double>(c, c->lay.phi), N * 8, hipMemcpyDeviceToDevice, c->stream));
   if (u) PF_HIP(c, hipMemcpyAsync(u, at<double>(c, c->lay.u), 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
   if (step) *step = c->step;
@@ -756,82 +1120,131 @@ pf_status pf_step(pf_ctx* c, int32_t nsteps, pf_step_stats* st) {
   if (nsteps < 0) return fail(c, PF_EINVAL, "pf_step: nsteps < 0");
   if (!c->have_state) return fail(c, PF_ESTATE, "pf_step: no state (call pf_set_state first)");
   if (st) std::memset(st, 0, sizeof(*st));
-  const Coefs<double> cf = make_coefs<double>(c);
-  const FemTables* tb = at<FemTables>(c, c->lay.tables);
   const bool pc = c->cfg.integrator == PF_INT_PC;
   const int every = c->cfg.nonlocal_every <= 1 ? 1 : c->cfg.nonlocal_every;
   pf_status out = PF_OK;
   for (int s = 0; s < nsteps; s++) {
-    double* P = at<double>(c, c->lay.P[c->cur]);
-    double* V = at<double>(c, c->lay.V[c->cur]);
-    double* Pn = at<double>(c, c->lay.P[c->cur ^ 1]);
-    double* Vn = at<double>(c, c->lay.V[c->cur ^ 1]);
+    void* P = c->ws + c->lay.P[c->cur];
+    void* V = c->ws + c->lay.V[c->cur];
+    void* Pn = c->ws + c->lay.P[c->cur ^ 1];
+    void* Vn = c->ws + c->lay.V[c->cur ^ 1];
     if (c->step % every == 0) {
-      pf_status r = solve_nonlocal64(c, P, pc ? V : nullptr, pc ? c->cfg.dt : 0.0, c->cfg.warm_start != 0, st);
-      if (r != PF_OK && r != PF_ENOCONV) return r;
+      pf_status r = solve_nonlocal(c, P, pc ? V : nullptr, pc ? c->cfg.dt : 0.0, c->cfg.warm_start != 0, st);
+      if (fatal(r)) return r;
       out = worst(out, r);
     }
-    PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
-      return launch_force<double>(c->dims, cf, tb, P, pc ? V : nullptr, pc ? c->cfg.dt : 0.0,
-                                  at<double>(c, c->lay.phi), at<double>(c, c->lay.ghost64), at<double>(c, c->lay.u),
-                                  pc ? kPcStep : kEulerStep, Pn, Vn, nullptr, c->stream);
-    }));
+    PF_TRY(launch_state_force(c, P, pc ? V : nullptr, pc ? c->cfg.dt : 0.0, pc ? kPcStep : kEulerStep, Pn, Vn,
+                              nullptr));
     c->cur ^= 1;
     c->step++;
     if (st) st->steps++;
   }
-  pf_status ss = sync(c);
-  if (ss != PF_OK) return ss;
+  PF_TRY(sync(c));
   return out;
 }
 
 pf_status pf_solve_phi(pf_ctx* c, const void* P, void* phi, pf_solve_stats* st) {
   if (!c || !P || !phi) return fail(c, PF_EINVAL, "pf_solve_phi: null argument");
   SolveResult r{};
-  pf_status s = solve_poisson<double>(c, static_cast<const double*>(P), nullptr, 0.0, 1, 1,
-                                      at<double>(c, c->lay.ghost64), c->cfg.phi_bottom, static_cast<double*>(phi),
-                                      c->cfg.tol_phi, c->cfg.warm_start != 0, &r);
+  pf_status s;
+  if (fp32(c))
+    s = solve_refined(c, false, static_cast<const float*>(P), nullptr, 0.0, static_cast<double*>(phi),
+                      scratch<float>(c, kScrTmp), c->cfg.tol_phi, c->cfg.warm_start != 0, &r);
+  else
+    s = solve_poisson64<double>(c, kPredAux, static_cast<const double*>(P), nullptr, 0.0, 1, 1,
+                                at<double>(c, c->lay.ghost64), c->cfg.phi_bottom, static_cast<double*>(phi),
+                                c->cfg.tol_phi, c->cfg.warm_start != 0, &r);
   if (st) {
     st->iters = r.iters;
-    st->outer = 1;
+    st->outer = r.outer;
     st->relres = r.relres;
   }
-  hipError_t e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return fail(c, PF_EHIP, "pf_solve_phi: %s", hipGetErrorString(e));
-  return s;
+  pf_status e = sync(c);
+  return fatal(e) ? e : s;
 }
 
 pf_status pf_solve_u(pf_ctx* c, const void* P, void* u, pf_solve_stats* st) {
   if (!c || !P || !u) return fail(c, PF_EINVAL, "pf_solve_u: null argument");
   SolveResult r{};
-  pf_status s = solve_fem<double>(c, static_cast<const double*>(P), nullptr, 0.0, static_cast<double*>(u),
-                                  c->cfg.tol_u, c->cfg.warm_start != 0, &r);
+  pf_status s;
+  if (fp32(c))
+    s = solve_refined(c, true, static_cast<const float*>(P), nullptr, 0.0, static_cast<double*>(u),
+                      scratch<float>(c, kScrTmp), c->cfg.tol_u, c->cfg.warm_start != 0, &r);
+  else
+    s = solve_fem64<double>(c, kPredAux, static_cast<const double*>(P), nullptr, 0.0, nullptr,
+                            static_cast<double*>(u), c->cfg.tol_u, c->cfg.warm_start != 0, &r);
   if (st) {
     st->iters = r.iters;
-    st->outer = 1;
+    st->outer = r.outer;
     st->relres = r.relres;
   }
-  hipError_t e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return fail(c, PF_EHIP, "pf_solve_u: %s", hipGetErrorString(e));
-  return s;
+  pf_status e = sync(c);
+  return fatal(e) ? e : s;
 }
 
 pf_status pf_force(pf_ctx* c, const void* P, const void* phi, const void* u, void* F) {
   if (!c || !P || !F) return fail(c, PF_EINVAL, "pf_force: null argument");
   if ((c->cfg.terms & PF_TERM_ELEC) && !phi) return fail(c, PF_EINVAL, "pf_force: phi needed");
   if ((c->cfg.terms & PF_TERM_ELAS) && !u) return fail(c, PF_EINVAL, "pf_force: u needed");
-  const Coefs<double> cf = make_coefs<double>(c);
-  PF_HIP(c, launch_force<double>(c->dims, cf, at<FemTables>(c, c->lay.tables), static_cast<const double*>(P),
-                                 nullptr, 0.0, static_cast<const double*>(phi), at<double>(c, c->lay.ghost64),
-                                 static_cast<const double*>(u), kForceOut, nullptr, nullptr,
-                                 static_cast<double*>(F), c->stream));
+  const int64_t N = c->dims.N;
+  if (fp32(c)) {
+    float* phi32 = scratch<float>(c, kScrTmp);
+    float* u32 = phi32 + N;
+    if (phi) PF_HIP(c, launch_convert<double, float>(static_cast<const double*>(phi), phi32, N, c->stream));
+    if (u) PF_HIP(c, launch_convert<double, float>(static_cast<const double*>(u), u32, 3 * N, c->stream));
+    return launch_state_force(c, P, nullptr, 0.0, kForceOut, nullptr, nullptr, F, phi32, u32);
+  }
+  return launch_state_force(c, P, nullptr, 0.0, kForceOut, nullptr, nullptr, F, phi, u);
+}
+
+pf_status pf_energy(pf_ctx* c, double out[5]) {
+  if (!c || !out) return fail(c, PF_EINVAL, "pf_energy: null argument");
+  if (!c->have_state) return fail(c, PF_ESTATE, "pf_energy: no state (call pf_set_state first)");
+  const void* P = c->ws + c->lay.P[c->cur];
+  if (fp32(c)) return energy_t<float>(c, static_cast<const float*>(P), out);
+  return energy_t<double>(c, static_cast<const double*>(P), out);
+}
+
+pf_status pf_set_params(pf_ctx* c, const double* volts, double a1) {
+  if (!c) return PF_EINVAL;
+  if (!std::isfinite(a1)) return fail(c, PF_EINVAL, "pf_set_params: a1 not finite");
+  c->cfg.a1 = a1;
+  if (volts) {
+    for (int e = 0; e < c->cfg.n_electrodes; e++) {
+      if (!std::isfinite(volts[e])) return fail(c, PF_EINVAL, "pf_set_params: voltage not finite");
+      c->electrodes[e].volts = volts[e];
+    }
+    c->phi_bc_valid = false;
+    PF_TRY(upload_ghosts(c));
+  }
   return PF_OK;
+}
+
+pf_status pf_adjoint_step(pf_ctx* c, const void* P_n, const void* V_n, void* lamP, void* lamV, double* dtheta) {
+  if (!c || !P_n || !lamP || !lamV || !dtheta) return fail(c, PF_EINVAL, "pf_adjoint_step: null argument");
+  if (c->cfg.integrator == PF_INT_PC && !V_n) return fail(c, PF_EINVAL, "pf_adjoint_step: V_n needed");
+  if (c->cfg.nonlocal_every > 1)
+    return fail(c, PF_EINVAL, "pf_adjoint_step: the adjoint needs phi and u refreshed every step");
+  if (fp32(c))
+    return adjoint_step_t<float>(c, static_cast<const float*>(P_n), static_cast<const float*>(V_n),
+                                 static_cast<float*>(lamP), static_cast<float*>(lamV), dtheta);
+  return adjoint_step_t<double>(c, static_cast<const double*>(P_n), static_cast<const double*>(V_n),
+                                static_cast<double*>(lamP), static_cast<double*>(lamV), dtheta);
+}
+
+pf_status pf_adjoint_initial_rate(pf_ctx* c, const void* P0, void* lamP, void* lamV, double* dtheta) {
+  if (!c || !P0 || !lamP || !lamV || !dtheta) return fail(c, PF_EINVAL, "pf_adjoint_initial_rate: null argument");
+  if (c->cfg.integrator != PF_INT_PC) return PF_OK;
+  if (fp32(c))
+    return adjoint_initial_t<float>(c, static_cast<const float*>(P0), static_cast<float*>(lamP),
+                                    static_cast<float*>(lamV), dtheta);
+  return adjoint_initial_t<double>(c, static_cast<const double*>(P0), static_cast<double*>(lamP),
+                                   static_cast<double*>(lamV), dtheta);
 }
 
 pf_status pf_timing(pf_ctx* c, int enable, double* ms, int64_t* launches) {
   if (!c) return PF_EINVAL;
-  pf_status s = sync(c);
-  if (s != PF_OK) return s;
+  PF_TRY(sync(c));
   for (int t = 0; t < PF_KC_COUNT; t++) {
     if (ms) ms[t] = c->kc_ms[t];
     if (launches) launches[t] = c->kc_n[t];
@@ -861,26 +1274,6 @@ pf_status pf_fem_tables(const pf_config* cfg, double* out, size_t count) {
   o += sizeof(t.Su) / 8;
   std::memcpy(o, t.Ms, sizeof(t.Ms));
   return PF_OK;
-}
-
-pf_status pf_energy(pf_ctx* c, double out[5]) {
-  (void)out;
-  return fail(c, PF_EINVAL, "pf_energy: not available in this build");
-}
-
-pf_status pf_set_params(pf_ctx* c, const double* volts, double a1) {
-  if (!c) return PF_EINVAL;
-  (void)volts;
-  (void)a1;
-  return fail(c, PF_EINVAL, "pf_set_params: not available in this build");
-}
-
-pf_status pf_adjoint_step(pf_ctx* c, const void*, const void*, void*, void*, double*) {
-  return fail(c, PF_EINVAL, "pf_adjoint_step: not available in this build");
-}
-
-pf_status pf_adjoint_initial_rate(pf_ctx* c, const void*, void*, void*, double*) {
-  return fail(c, PF_EINVAL, "pf_adjoint_initial_rate: not available in this build");
 }
 
 }  // extern "C"

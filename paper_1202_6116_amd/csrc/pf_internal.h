@@ -54,7 +54,10 @@ struct CgScalars {
   int32_t maxit;
   int32_t done;          // 0 running, 1 converged, 2 iteration cap, 3 non-finite
   int32_t zero_rhs;      // b == 0: the solution is x = 0
-  int32_t pad[2];
+  int32_t outer_done;    // refinement: the FP64 residual met the tolerance
+  double outer_b2;       // refinement: ||b||^2 of the FP64 system
+  double outer_r2;       // refinement: ||b - A x||^2 of the FP64 iterate
+  double pad;
 };
 
 enum CgDone { kRunning = 0, kConverged = 1, kMaxIt = 2, kNonFinite = 3 };

@@ -134,13 +134,18 @@ __device__ __forceinline__ void load_plane(T (&ring)[3][NC][kHY][kHX], const Dim
 //   kRedAlpha  p.q            -> alpha = rho / p.q
 //   kRedBeta   (r.z, r.r)     -> beta, iteration count, convergence
 // ---------------------------------------------------------------------------
-enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2 };
+//   kRedOuter  (b.b, r.z, r.r) of the FP64 residual of an iterative
+//              refinement sweep: records the outer test and starts the
+//              inner (FP32) solve for the correction with tolerance tol2
+//   kRedSum    plain sums written to out[0..NV-1]
+enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2, kRedOuter = 3, kRedSum = 4 };
 constexpr int kRedThreads = 1024;
 
 template <int NV>
 __global__ __launch_bounds__(kRedThreads) void cg_reduce_kernel(const double* __restrict__ partials, int nblocks,
-                                                                CgScalars* sc, int mode, double tol, int maxit) {
-  if (mode != kRedSetup && sc->done) return;
+                                                                CgScalars* sc, int mode, double tol, int maxit,
+                                                                double tol2, double* out) {
+  if ((mode == kRedAlpha || mode == kRedBeta) && sc->done) return;
   __shared__ double red[NV][kRedThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double s[NV];
@@ -163,6 +168,40 @@ __global__ __launch_bounds__(kRedThreads) void cg_reduce_kernel(const double* __
     a[t] = 0.0;
     for (int w = 0; w < kRedThreads / 64; w++) a[t] += red[t][w];
   }
+  if (mode == kRedSum) {
+#pragma unroll
+    for (int t = 0; t < NV; t++) out[t] = a[t];
+    return;
+  }
+  if (mode == kRedOuter) {
+    const double b2 = a[0], rz = a[NV > 1 ? 1 : 0], r2 = a[NV > 2 ? 2 : 0];
+    sc->outer_b2 = b2;
+    sc->outer_r2 = r2;
+    sc->alpha = 0.0;
+    sc->beta = 0.0;
+    sc->iter = 0;
+    sc->maxit = maxit;
+    sc->zero_rhs = 0;
+    sc->bnorm2 = r2;  // the inner system's right-hand side is the residual
+    sc->rho = rz;
+    sc->rnorm2 = r2;
+    sc->tol = tol2;
+    if (!finite(b2) || !finite(rz) || !finite(r2)) {
+      sc->done = kNonFinite;
+      sc->outer_done = 0;
+    } else if (b2 == 0.0) {
+      sc->done = kConverged;
+      sc->outer_done = 1;
+      sc->zero_rhs = 1;
+    } else if (converged(r2, b2, tol)) {
+      sc->done = kConverged;
+      sc->outer_done = 1;
+    } else {
+      sc->done = kRunning;
+      sc->outer_done = 0;
+    }
+    return;
+  }
   if (mode == kRedSetup) {
     // a = (b.b, r.z, r.r)
     sc->bnorm2 = a[0];
@@ -174,6 +213,7 @@ __global__ __launch_bounds__(kRedThreads) void cg_reduce_kernel(const double* __
     sc->tol = tol;
     sc->maxit = maxit;
     sc->zero_rhs = 0;
+    sc->outer_done = 0;
     const double rn2 = sc->rnorm2;
     if (!finite(a[0]) || !finite(sc->rho) || !finite(rn2)) sc->done = kNonFinite;
     else if (a[0] == 0.0) {
@@ -226,18 +266,30 @@ __global__ void cg_finish_kernel(T* x, const T* p, int64_t n, const CgScalars* s
   for (; t < n; t += stride) x[t] = zero ? (T)0 : x[t] + alpha * p[t];
 }
 
+// Iterative refinement: x64 += d, x32 = x64 (rounded working copy).
+__global__ void refine_update_kernel(double* x64, float* x32, const float* d, int64_t n) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; t < n; t += stride) {
+    const double v = x64[t] + (double)d[t];
+    x64[t] = v;
+    x32[t] = (float)v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Poisson: A phi = -eps_b Lap_h phi (zero ghosts), b = -D_h P + ghost terms
 // ---------------------------------------------------------------------------
 
 // b from Pp = P + cdt V (V may be null) and the ghost planes; r = b - A x;
-// p = r / diag; partial (b.b, r.z, r.r).  T: arithmetic and r, x, p;
-// S: storage of P and V.
-template <typename T, typename S>
+// p = r / diag; partial (b.b, r.z, r.r).  T: arithmetic and x; S: storage
+// of P and V; R: storage of r and p (FP32 for the inner solve of a
+// refinement sweep, which also clears its correction dz).
+template <typename T, typename S, typename R>
 __global__ __launch_bounds__(kThreads) void poisson_setup_kernel(
     Dims d, Coefs<T> cf, const S* __restrict__ P, const S* __restrict__ V, T cdt, int with_P, int with_bc,
-    const T* __restrict__ ghost_top, T phi_bottom, const T* __restrict__ x, T* __restrict__ r, T* __restrict__ p,
-    double* partials) {
+    const T* __restrict__ ghost_top, T phi_bottom, const T* __restrict__ x, R* __restrict__ r, R* __restrict__ p,
+    R* __restrict__ dz, double* partials) {
   const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
   double v[3] = {0.0, 0.0, 0.0};
   if (i < d.nx && j < d.ny) {
@@ -267,8 +319,9 @@ __global__ __launch_bounds__(kThreads) void poisson_setup_kernel(
     const T Ax = cf.eps_over_h2 * (6 * x[n] - s);
     const T rr = b - Ax;
     const T z = rr * cf.inv_diag_poisson;
-    r[n] = rr;
-    p[n] = z;
+    r[n] = (R)rr;
+    p[n] = (R)z;
+    if (dz) dz[n] = 0;
     v[0] = (double)b * b;
     v[1] = (double)rr * z;
     v[2] = (double)rr * rr;
@@ -428,15 +481,38 @@ __device__ __forceinline__ void cubic_stress(const Coefs<T>& cf, const T e[6], T
   s[5] = cf.C44 * e[5];
 }
 
+// (d eps0/dP)(p) w: the eigenstrain linearised at p in direction w.
+template <typename T>
+__device__ __forceinline__ void eigenstrain_lin(const Coefs<T>& cf, T x, T y, T z, T wx, T wy, T wz, T e[6]) {
+  e[0] = 2 * (cf.Q11 * x * wx + cf.Q12 * (y * wy + z * wz));
+  e[1] = 2 * (cf.Q11 * y * wy + cf.Q12 * (z * wz + x * wx));
+  e[2] = 2 * (cf.Q11 * z * wz + cf.Q12 * (x * wx + y * wy));
+  e[3] = 2 * cf.Q44 * (x * wy + y * wx);
+  e[4] = 2 * cf.Q44 * (y * wz + z * wy);
+  e[5] = 2 * cf.Q44 * (z * wx + x * wz);
+}
+
+// s . (d eps0/dP)(p): the elastic driving force of a nodal stress s.
+template <typename T>
+__device__ __forceinline__ void stress_pull(const Coefs<T>& cf, const T p[3], const T s[6], T g[3]) {
+  g[0] = 2 * p[0] * (cf.Q11 * s[0] + cf.Q12 * (s[1] + s[2])) + 2 * cf.Q44 * (p[1] * s[3] + p[2] * s[5]);
+  g[1] = 2 * p[1] * (cf.Q11 * s[1] + cf.Q12 * (s[2] + s[0])) + 2 * cf.Q44 * (p[0] * s[3] + p[2] * s[4]);
+  g[2] = 2 * p[2] * (cf.Q11 * s[2] + cf.Q12 * (s[0] + s[1])) + 2 * cf.Q44 * (p[1] * s[4] + p[0] * s[5]);
+}
+
 }  // namespace
 
 // f = body force of the eigenstrain of Pp = P + cdt V (Eq. 15); r = f - K x;
 // p = r / diag.  The clamped plane k = 0 has x = r = p = 0 (both direction
 // buffers).  Partial (f.f, r.z, r.r).
-template <typename T, typename S>
+// With W non-null the eigenstrain is replaced by its linearisation at Pp in
+// the direction W, deps0 = (d eps0/dP)(Pp) W (the right-hand side of the
+// adjoint FEM solve).
+template <typename T, typename S, typename R>
 __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
     Dims d, Coefs<T> cf, const FemTables* __restrict__ tb, const S* __restrict__ P, const S* __restrict__ V, T cdt,
-    T* __restrict__ x, T* __restrict__ r, T* __restrict__ p0, T* __restrict__ p1, double* partials) {
+    const T* __restrict__ W, T* __restrict__ x, R* __restrict__ r, R* __restrict__ p0, R* __restrict__ p1,
+    R* __restrict__ dz, double* partials) {
   const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
   double v[3] = {0.0, 0.0, 0.0};
   if (i < d.nx && j < d.ny) {
@@ -449,6 +525,7 @@ __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
         r[c * N + n] = 0;
         p0[c * N + n] = 0;
         p1[c * N + n] = 0;
+        if (dz) dz[c * N + n] = 0;
       }
     } else {
       const int zt = (k == d.nz - 1) ? 1 : 0;
@@ -468,7 +545,8 @@ __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
               pz += cdt * (T)V[2 * N + m];
             }
             T e[6], s[6];
-            eigenstrain(cf, px, py, pz, e);
+            if (W) eigenstrain_lin(cf, px, py, pz, W[m], W[N + m], W[2 * N + m], e);
+            else eigenstrain(cf, px, py, pz, e);
             cubic_stress(cf, e, s);
 #pragma unroll
             for (int c = 0; c < 3; c++)
@@ -492,8 +570,9 @@ __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
       for (int c = 0; c < 3; c++) {
         const T rr = f[c] - Kx[c];
         const T z = rr * wdiag;
-        r[c * N + n] = rr;
-        p0[c * N + n] = z;
+        r[c * N + n] = (R)rr;
+        p0[c * N + n] = (R)z;
+        if (dz) dz[c * N + n] = 0;
         v[0] += (double)f[c] * f[c];
         v[1] += (double)rr * z;
         v[2] += (double)rr * rr;
@@ -727,6 +806,267 @@ __global__ __launch_bounds__(kThreads) void force_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Free energy (Eq. 1-6 on the grid), per-block partial sums
+// ---------------------------------------------------------------------------
+// Energies of the state P (storage S), evaluated in FP64:
+//  bulk   h^3 fL(P_n)
+//  grad   (G/2) h |P_m - P_n|^2 over the +x, +y, +z edges of n
+//  elec   h^3 [ b_n phiP_n - phiP_n (A phiP)_n / 2 ] - h^3 P_n . E_app_n
+//         with b = -D_h P, phiP = phi - phi_bc (phi solved at P with the
+//         boundary values, phi_bc with P = 0); the first bracket is the
+//         stationary value of the quadratic form, (h^3/2) rho^T A^-1 rho,
+//         so its error is second order in the solve error
+//  elas   u.K u / 2 - u.f + eps0^T C M eps0 / 2 at the solved u (again the
+//         quadratic form, min over u of the elastic energy)
+template <typename S>
+__global__ __launch_bounds__(kThreads) void energy_kernel(Dims d, Coefs<double> cf, const FemTables* __restrict__ tb,
+                                                          const S* __restrict__ P, const double* __restrict__ phi,
+                                                          const double* __restrict__ phi_bc,
+                                                          const double* __restrict__ ghost_top,
+                                                          const double* __restrict__ u, double* partials) {
+  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < d.nx && j < d.ny) {
+    const int64_t N = d.N, pl = d.plane;
+    const int64_t n = i + (int64_t)d.nx * j + pl * k;
+    const double h3 = cf.h * cf.h * cf.h;
+    auto Pc = [&](int c, int64_t m) -> double { return (double)P[c * N + m]; };
+    const double p[3] = {Pc(0, n), Pc(1, n), Pc(2, n)};
+    if (cf.terms & kLandau) {
+      const double x2 = p[0] * p[0], y2 = p[1] * p[1], z2 = p[2] * p[2];
+      v[0] = h3 * (cf.a1 * (x2 + y2 + z2) + cf.a11 * (x2 * x2 + y2 * y2 + z2 * z2) +
+                   cf.a12 * (x2 * y2 + y2 * z2 + z2 * x2));
+    }
+    if (cf.terms & kGrad) {
+      double s = 0.0;
+      const int64_t ms[3] = {nbr(d, i, j, k, 1, 0, 0), nbr(d, i, j, k, 0, 1, 0), k + 1 < d.nz ? n + pl : -1};
+#pragma unroll
+      for (int e = 0; e < 3; e++) {
+        if (ms[e] < 0) continue;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          const double df = Pc(c, ms[e]) - p[c];
+          s += df * df;
+        }
+      }
+      v[1] = 0.5 * cf.G * cf.h * s;
+    }
+    if (cf.terms & kElec) {
+      const bool up = k + 1 < d.nz, dn = k > 0;
+      const int64_t nxp = nbr(d, i, j, k, 1, 0, 0), nxm = nbr(d, i, j, k, -1, 0, 0);
+      const int64_t nyp = nbr(d, i, j, k, 0, 1, 0), nym = nbr(d, i, j, k, 0, -1, 0);
+      const double rho = (Pc(0, nxp) - Pc(0, nxm) + Pc(1, nyp) - Pc(1, nym) + (up ? Pc(2, n + pl) : 0.0) -
+                          (dn ? Pc(2, n - pl) : 0.0)) * cf.inv_2h;
+      auto fp = [&](int64_t m) { return phi[m] - phi_bc[m]; };
+      const double f0 = fp(n);
+      const double sn = fp(nxp) + fp(nxm) + fp(nyp) + fp(nym) + (up ? fp(n + pl) : 0.0) + (dn ? fp(n - pl) : 0.0);
+      const double Af = cf.eps_over_h2 * (6 * f0 - sn);
+      const double zp = up ? phi_bc[n + pl] : ghost_top[i + (int64_t)d.nx * j];
+      const double zm = dn ? phi_bc[n - pl] : cf.phi_bottom;
+      const double E[3] = {-(phi_bc[nxp] - phi_bc[nxm]) * cf.inv_2h, -(phi_bc[nyp] - phi_bc[nym]) * cf.inv_2h,
+                           -(zp - zm) * cf.inv_2h};
+      v[2] = h3 * (-rho * f0 - 0.5 * f0 * Af) - h3 * (p[0] * E[0] + p[1] * E[1] + p[2] * E[2]);
+    }
+    if (cf.terms & kElas) {
+      // eps0^T C (M eps0) / 2 on every row
+      const int zt3 = (k == 0) ? kLow : ((k == d.nz - 1) ? kHigh : kInterior);
+      const int dzmin = (k == 0) ? 0 : -1, dzmax = (k == d.nz - 1) ? 0 : 1;
+      double me[6] = {0, 0, 0, 0, 0, 0};
+      for (int dz = dzmin; dz <= dzmax; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+          for (int dx = -1; dx <= 1; dx++) {
+            const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+            const int64_t m = nbr(d, i, j, k, dx, dy, dz);
+            double e[6];
+            eigenstrain(cf, Pc(0, m), Pc(1, m), Pc(2, m), e);
+            for (int q = 0; q < 6; q++) me[q] += tb->Ms[zt3][o] * e[q];
+          }
+      double e0[6], cme[6];
+      eigenstrain(cf, p[0], p[1], p[2], e0);
+      cubic_stress(cf, me, cme);
+      double el = 0.0;
+      for (int q = 0; q < 6; q++) el += 0.5 * e0[q] * cme[q];
+      if (k > 0) {
+        const int zt = (k == d.nz - 1) ? 1 : 0;
+        double f[3] = {0, 0, 0};
+        for (int dz = -1; dz <= (zt ? 0 : 1); dz++)
+          for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+              const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+              const int64_t m = nbr(d, i, j, k, dx, dy, dz);
+              double e[6], sg[6];
+              eigenstrain(cf, Pc(0, m), Pc(1, m), Pc(2, m), e);
+              cubic_stress(cf, e, sg);
+              for (int c = 0; c < 3; c++)
+                for (int q = 0; q < 6; q++) f[c] += tb->Bf[zt][c][q][o] * sg[q];
+            }
+        auto ld = [&](int dx, int dy, int dz, double uu[3]) {
+          const int64_t m = nbr(d, i, j, k, dx, dy, dz);
+          for (int c = 0; c < 3; c++) uu[c] = (k + dz == 0) ? 0.0 : u[c * N + m];
+        };
+        double Ku[3];
+        fem_K_apply<double>(tb, zt, ld, Ku);
+        for (int c = 0; c < 3; c++) el += 0.5 * u[c * N + n] * Ku[c] - u[c * N + n] * f[c];
+      }
+      v[3] = el;
+    }
+  }
+  block_partials<4, kThreads>(v, partials, node_block_id());
+}
+
+// ---------------------------------------------------------------------------
+// Linearised force and the adjoint step
+// ---------------------------------------------------------------------------
+// H w = (dF/dP)(X) w at the linearisation point X = P + cdt V, with u the
+// displacement solved at X, psi the adjoint potential (A psi = -D_h w, zero
+// boundary values) and du the adjoint displacement (K du = f(deps0),
+// deps0 = (d eps0/dP)(X) w):
+//   H w = -L [ Hess fL(X) w - G Lap_h w - E(psi) - h^-3 (ds . deps0/dP(X)
+//              + s . d2eps0/dP2 w) ],  E(psi) = -G_h psi,
+//   s = C (int N eps(u) - int N eps0(X)),  ds = C (int N eps(du) - int N deps0).
+template <typename S>
+__global__ __launch_bounds__(kThreads) void hvp_kernel(Dims d, Coefs<double> cf, const FemTables* __restrict__ tb,
+                                                       const S* __restrict__ P, const S* __restrict__ V, double cdt,
+                                                       const double* __restrict__ w, const double* __restrict__ u,
+                                                       const double* __restrict__ psi, const double* __restrict__ du,
+                                                       double* __restrict__ Hw) {
+  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
+  if (i >= d.nx || j >= d.ny) return;
+  const int64_t N = d.N, pl = d.plane;
+  const int64_t n = i + (int64_t)d.nx * j + pl * k;
+  auto X = [&](int64_t m, double out[3]) {
+    for (int c = 0; c < 3; c++) out[c] = (double)P[c * N + m] + (V ? cdt * (double)V[c * N + m] : 0.0);
+  };
+  double x0[3], w0[3] = {w[n], w[N + n], w[2 * N + n]};
+  X(n, x0);
+  double acc[3] = {0, 0, 0};
+  if (cf.terms & kLandau) {
+    const double x2 = x0[0] * x0[0], y2 = x0[1] * x0[1], z2 = x0[2] * x0[2];
+    const double H00 = 2 * cf.a1 + 12 * cf.a11 * x2 + 2 * cf.a12 * (y2 + z2);
+    const double H11 = 2 * cf.a1 + 12 * cf.a11 * y2 + 2 * cf.a12 * (z2 + x2);
+    const double H22 = 2 * cf.a1 + 12 * cf.a11 * z2 + 2 * cf.a12 * (x2 + y2);
+    const double H01 = 4 * cf.a12 * x0[0] * x0[1], H12 = 4 * cf.a12 * x0[1] * x0[2], H02 = 4 * cf.a12 * x0[0] * x0[2];
+    acc[0] += H00 * w0[0] + H01 * w0[1] + H02 * w0[2];
+    acc[1] += H01 * w0[0] + H11 * w0[1] + H12 * w0[2];
+    acc[2] += H02 * w0[0] + H12 * w0[1] + H22 * w0[2];
+  }
+  if (cf.terms & kGrad) {
+    const int64_t ms[6] = {nbr(d, i, j, k, 1, 0, 0), nbr(d, i, j, k, -1, 0, 0), nbr(d, i, j, k, 0, 1, 0),
+                           nbr(d, i, j, k, 0, -1, 0), k + 1 < d.nz ? n + pl : -1, k > 0 ? n - pl : -1};
+    for (int c = 0; c < 3; c++) {
+      double lap = 0.0;
+      for (int t = 0; t < 6; t++)
+        if (ms[t] >= 0) lap += w[c * N + ms[t]] - w0[c];
+      acc[c] -= cf.G * cf.inv_h2 * lap;
+    }
+  }
+  if (cf.terms & kElec) {
+    const double zp = (k + 1 < d.nz) ? psi[n + pl] : 0.0;
+    const double zm = (k > 0) ? psi[n - pl] : 0.0;
+    acc[0] += (psi[nbr(d, i, j, k, 1, 0, 0)] - psi[nbr(d, i, j, k, -1, 0, 0)]) * cf.inv_2h;
+    acc[1] += (psi[nbr(d, i, j, k, 0, 1, 0)] - psi[nbr(d, i, j, k, 0, -1, 0)]) * cf.inv_2h;
+    acc[2] += (zp - zm) * cf.inv_2h;
+  }
+  if (cf.terms & kElas) {
+    const int zt = (k == 0) ? kLow : ((k == d.nz - 1) ? kHigh : kInterior);
+    const int dzmin = (k == 0) ? 0 : -1, dzmax = (k == d.nz - 1) ? 0 : 1;
+    double ws_[6] = {0, 0, 0, 0, 0, 0}, wd[6] = {0, 0, 0, 0, 0, 0};
+    for (int dz = dzmin; dz <= dzmax; dz++)
+      for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+          const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+          const int64_t m = nbr(d, i, j, k, dx, dy, dz);
+          double a[3], e[6], de[6];
+          X(m, a);
+          eigenstrain(cf, a[0], a[1], a[2], e);
+          eigenstrain_lin(cf, a[0], a[1], a[2], w[m], w[N + m], w[2 * N + m], de);
+          const double ms = tb->Ms[zt][o];
+          for (int q = 0; q < 6; q++) {
+            double s1 = -ms * e[q], s2 = -ms * de[q];
+            for (int c = 0; c < 3; c++) {
+              s1 += tb->Su[zt][q][c][o] * u[c * N + m];
+              s2 += tb->Su[zt][q][c][o] * du[c * N + m];
+            }
+            ws_[q] += s1;
+            wd[q] += s2;
+          }
+        }
+    double s[6], ds[6], g[3], hs[3];
+    cubic_stress(cf, ws_, s);
+    cubic_stress(cf, wd, ds);
+    stress_pull(cf, x0, ds, g);
+    // s . d2eps0/dP2 w
+    hs[0] = 2 * (cf.Q11 * s[0] + cf.Q12 * (s[1] + s[2])) * w0[0] + 2 * cf.Q44 * (s[3] * w0[1] + s[5] * w0[2]);
+    hs[1] = 2 * (cf.Q11 * s[1] + cf.Q12 * (s[2] + s[0])) * w0[1] + 2 * cf.Q44 * (s[3] * w0[0] + s[4] * w0[2]);
+    hs[2] = 2 * (cf.Q11 * s[2] + cf.Q12 * (s[0] + s[1])) * w0[2] + 2 * cf.Q44 * (s[4] * w0[1] + s[5] * w0[0]);
+    for (int c = 0; c < 3; c++) acc[c] -= cf.inv_h3 * (g[c] + hs[c]);
+  }
+  for (int c = 0; c < 3; c++) Hw[c * N + n] = -cf.L * acc[c];
+}
+
+// Adjoint bookkeeping (lam in state storage S, w and Hw in FP64):
+//   kAdjPrepPc    w = (lamV + dt lamP) / 2
+//   kAdjPrepEuler w = lamP
+//   kAdjPrepInit  w = lamV
+//   kAdjUpdPc     lamP += Hw, lamV = w + dt Hw
+//   kAdjUpdEuler  lamP += dt Hw
+//   kAdjUpdInit   lamP += Hw, lamV = 0
+enum { kAdjPrepPc = 0, kAdjPrepEuler, kAdjPrepInit, kAdjUpdPc, kAdjUpdEuler, kAdjUpdInit };
+
+template <typename S>
+__global__ void adjoint_axpy_kernel(int mode, double dt, S* lamP, S* lamV, double* w, const double* Hw, int64_t n) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; t < n; t += stride) {
+    switch (mode) {
+      case kAdjPrepPc: w[t] = 0.5 * ((double)lamV[t] + dt * (double)lamP[t]); break;
+      case kAdjPrepEuler: w[t] = (double)lamP[t]; break;
+      case kAdjPrepInit: w[t] = (double)lamV[t]; break;
+      case kAdjUpdPc:
+        lamP[t] = (S)((double)lamP[t] + Hw[t]);
+        lamV[t] = (S)(w[t] + dt * Hw[t]);
+        break;
+      case kAdjUpdEuler: lamP[t] = (S)((double)lamP[t] + dt * Hw[t]); break;
+      default:
+        lamP[t] = (S)((double)lamP[t] + Hw[t]);
+        lamV[t] = (S)0;
+        break;
+    }
+  }
+}
+
+// Partials of w . dF/dtheta:  electrode e (rectangle [x0,x1) x [y0,y1), unit
+// voltage, basis potential phi_e): L w . E^(e), E^(e) = -G_h phi_e with the
+// unit ghost values; a1 (phi_e null): -2 L w . X.
+template <typename S>
+__global__ __launch_bounds__(kThreads) void theta_dot_kernel(Dims d, Coefs<double> cf, const double* __restrict__ w,
+                                                             const double* __restrict__ phi_e, int x0, int x1, int y0,
+                                                             int y1, const S* __restrict__ P,
+                                                             const S* __restrict__ V, double cdt, double* partials) {
+  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
+  double v[1] = {0.0};
+  if (i < d.nx && j < d.ny) {
+    const int64_t N = d.N, pl = d.plane;
+    const int64_t n = i + (int64_t)d.nx * j + pl * k;
+    if (phi_e) {
+      const double ghost = (i >= x0 && i < x1 && j >= y0 && j < y1) ? 1.0 : 0.0;
+      const double zp = (k + 1 < d.nz) ? phi_e[n + pl] : ghost;
+      const double zm = (k > 0) ? phi_e[n - pl] : 0.0;
+      const double E0 = -(phi_e[nbr(d, i, j, k, 1, 0, 0)] - phi_e[nbr(d, i, j, k, -1, 0, 0)]) * cf.inv_2h;
+      const double E1 = -(phi_e[nbr(d, i, j, k, 0, 1, 0)] - phi_e[nbr(d, i, j, k, 0, -1, 0)]) * cf.inv_2h;
+      const double E2 = -(zp - zm) * cf.inv_2h;
+      v[0] = cf.L * (w[n] * E0 + w[N + n] * E1 + w[2 * N + n] * E2);
+    } else {
+      double s = 0.0;
+      for (int c = 0; c < 3; c++)
+        s += w[c * N + n] * ((double)P[c * N + n] + (V ? cdt * (double)V[c * N + n] : 0.0));
+      v[0] = -2.0 * cf.L * s;
+    }
+  }
+  block_partials<1, kThreads>(v, partials, node_block_id());
+}
+
+// ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
 
@@ -779,21 +1119,27 @@ hipError_t launch_cg_finish(T* x, const T* p, int64_t n, const CgScalars* sc, hi
 }
 
 hipError_t launch_cg_reduce(const double* partials, int nblocks, int nv, CgScalars* sc, int mode, double tol,
-                            int maxit, hipStream_t s) {
+                            int maxit, hipStream_t s, double tol2, double* out) {
   switch (nv) {
-    case 1: cg_reduce_kernel<1><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit); break;
-    case 2: cg_reduce_kernel<2><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit); break;
-    default: cg_reduce_kernel<3><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit); break;
+    case 1: cg_reduce_kernel<1><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit, tol2, out); break;
+    case 2: cg_reduce_kernel<2><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit, tol2, out); break;
+    case 3: cg_reduce_kernel<3><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit, tol2, out); break;
+    default: cg_reduce_kernel<4><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit, tol2, out); break;
   }
   return hipGetLastError();
 }
 
-template <typename T, typename S>
+hipError_t launch_refine_update(double* x64, float* x32, const float* d, int64_t n, hipStream_t s) {
+  refine_update_kernel<<<flat_blocks(n), 256, 0, s>>>(x64, x32, d, n);
+  return hipGetLastError();
+}
+
+template <typename T, typename S, typename R>
 hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
-                                int with_bc, const T* ghost_top, T phi_bottom, const T* x, T* r, T* p,
+                                int with_bc, const T* ghost_top, T phi_bottom, const T* x, R* r, R* p, R* dz,
                                 double* partials, hipStream_t s) {
-  poisson_setup_kernel<T, S><<<node_grid(d), node_block(), 0, s>>>(d, cf, P, V, cdt, with_P, with_bc, ghost_top,
-                                                                   phi_bottom, x, r, p, partials);
+  poisson_setup_kernel<T, S, R><<<node_grid(d), node_block(), 0, s>>>(d, cf, P, V, cdt, with_P, with_bc, ghost_top,
+                                                                      phi_bottom, x, r, p, dz, partials);
   return hipGetLastError();
 }
 
@@ -811,10 +1157,11 @@ hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>&
   return hipGetLastError();
 }
 
-template <typename T, typename S>
+template <typename T, typename S, typename R>
 hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const S* P, const S* V, T cdt,
-                            T* x, T* r, T* p0, T* p1, double* partials, hipStream_t s) {
-  fem_setup_kernel<T, S><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, x, r, p0, p1, partials);
+                            const T* W, T* x, R* r, R* p0, R* p1, R* dz, double* partials, hipStream_t s) {
+  fem_setup_kernel<T, S, R><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, W, x, r, p0, p1, dz,
+                                                                  partials);
   return hipGetLastError();
 }
 
@@ -841,6 +1188,51 @@ hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, 
   return hipGetLastError();
 }
 
+template <typename S>
+hipError_t launch_energy(const Dims& d, const Coefs<double>& cf, const FemTables* tb, const S* P, const double* phi,
+                         const double* phi_bc, const double* ghost_top, const double* u, double* partials,
+                         hipStream_t s) {
+  energy_kernel<S><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, phi, phi_bc, ghost_top, u, partials);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_hvp(const Dims& d, const Coefs<double>& cf, const FemTables* tb, const S* P, const S* V,
+                      double cdt, const double* w, const double* u, const double* psi, const double* du, double* Hw,
+                      hipStream_t s) {
+  hvp_kernel<S><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, w, u, psi, du, Hw);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_adjoint_axpy(int mode, double dt, S* lamP, S* lamV, double* w, const double* Hw, int64_t n,
+                               hipStream_t s) {
+  adjoint_axpy_kernel<S><<<flat_blocks(n), 256, 0, s>>>(mode, dt, lamP, lamV, w, Hw, n);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_theta_dot(const Dims& d, const Coefs<double>& cf, const double* w, const double* phi_e, int x0,
+                            int x1, int y0, int y1, const S* P, const S* V, double cdt, double* partials,
+                            hipStream_t s) {
+  theta_dot_kernel<S><<<node_grid(d), node_block(), 0, s>>>(d, cf, w, phi_e, x0, x1, y0, y1, P, V, cdt, partials);
+  return hipGetLastError();
+}
+
+#define PF_INSTANTIATE_ADJ(S)                                                                                    \
+  template hipError_t launch_energy<S>(const Dims&, const Coefs<double>&, const FemTables*, const S*,            \
+                                       const double*, const double*, const double*, const double*, double*,      \
+                                       hipStream_t);                                                             \
+  template hipError_t launch_hvp<S>(const Dims&, const Coefs<double>&, const FemTables*, const S*, const S*,     \
+                                    double, const double*, const double*, const double*, const double*, double*, \
+                                    hipStream_t);                                                                \
+  template hipError_t launch_adjoint_axpy<S>(int, double, S*, S*, double*, const double*, int64_t, hipStream_t); \
+  template hipError_t launch_theta_dot<S>(const Dims&, const Coefs<double>&, const double*, const double*, int,  \
+                                          int, int, int, const S*, const S*, double, double*, hipStream_t);
+
+PF_INSTANTIATE_ADJ(double)
+PF_INSTANTIATE_ADJ(float)
+
 #define PF_INSTANTIATE(T)                                                                                        \
   template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                                               \
   template hipError_t launch_cg_finish<T>(T*, const T*, int64_t, const CgScalars*, hipStream_t);                 \
@@ -858,15 +1250,16 @@ hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, 
 PF_INSTANTIATE(double)
 PF_INSTANTIATE(float)
 
-#define PF_INSTANTIATE_SETUP(T, S)                                                                               \
-  template hipError_t launch_poisson_setup<T, S>(const Dims&, const Coefs<T>&, const S*, const S*, T, int, int,  \
-                                                 const T*, T, const T*, T*, T*, double*, hipStream_t);           \
-  template hipError_t launch_fem_setup<T, S>(const Dims&, const Coefs<T>&, const FemTables*, const S*, const S*, \
-                                             T, T*, T*, T*, T*, double*, hipStream_t);
+#define PF_INSTANTIATE_SETUP(T, S, R)                                                                            \
+  template hipError_t launch_poisson_setup<T, S, R>(const Dims&, const Coefs<T>&, const S*, const S*, T, int,    \
+                                                    int, const T*, T, const T*, R*, R*, R*, double*,             \
+                                                    hipStream_t);                                                \
+  template hipError_t launch_fem_setup<T, S, R>(const Dims&, const Coefs<T>&, const FemTables*, const S*,        \
+                                                const S*, T, const T*, T*, R*, R*, R*, R*, double*, hipStream_t);
 
-PF_INSTANTIATE_SETUP(double, double)
-PF_INSTANTIATE_SETUP(double, float)
-PF_INSTANTIATE_SETUP(float, float)
+PF_INSTANTIATE_SETUP(double, double, double)
+PF_INSTANTIATE_SETUP(double, float, float)
+PF_INSTANTIATE_SETUP(double, float, double)
 
 template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
 template hipError_t launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);

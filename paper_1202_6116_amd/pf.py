@@ -335,6 +335,7 @@ class Context:
         return s
 
     def adjoint_initial_rate(self, P0, lamP, lamV, dtheta):
+        """Folds the initial rate V0 = F(P0) into the adjoints (no-op for Euler)."""
         self._field(P0, 3, self.state_dtype, "P0")
         arr = (ctypes.c_double * len(dtheta))(*dtheta)
         s = self.L.pf_adjoint_initial_rate(self.ctx, _ptr(P0), _ptr(lamP), _ptr(lamV), arr)

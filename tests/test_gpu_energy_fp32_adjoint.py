@@ -1,0 +1,184 @@
+"""GPU tests of the free energy, the FP32 + FP64-refinement path and the
+discrete adjoint, against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1202_6116_amd.workloads import (
+    PFConfig, Electrode, TERM_ALL, TERM_LANDAU, TERM_GRAD, TERM_ELEC, TERM_ELAS, workloads, initial_polarisation,
+    domain_polarisation, noise_polarisation, random_field,
+)
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0").to(dtype)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def pf():
+    from paper_1202_6116_amd import pf as m
+    return m
+
+
+def small_cfg(**kw):
+    base = dict(nx=70, ny=13, nz=6, tol_phi=1e-13, tol_u=1e-13, phi_bottom=0.1, phi_top=-0.2,
+                electrodes=[Electrode(5, 20, 0, 13, 2.0), Electrode(40, 56, 2, 11, -1.5)])
+    base.update(kw)
+    return PFConfig(**base)
+
+
+# ---------------------------------------------------------------------------
+# Energy
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("terms", [TERM_LANDAU, TERM_GRAD, TERM_ELEC, TERM_ELAS, TERM_ALL])
+def test_energy_matches_oracle(pf, oracle_mod, terms):
+    cfg = small_cfg(terms=terms, integrator="euler")
+    print(f"case: energy terms={terms}", flush=True)
+    P = domain_polarisation(cfg, 21, block=4, std=0.1)
+    ref = oracle_mod.Oracle(cfg).energy(P, tol=1e-13)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P))
+    e = np.array(ctx.energy())
+    scale = np.abs(ref).max()
+    assert np.abs(e - ref).max() <= 1e-10 * scale, (e, ref)
+
+
+def test_energy_decreases_on_gpu_at_zero_bias(pf):
+    w = workloads()["film_32x32x8"]
+    cfg = w.cfg.replace(integrator="euler")
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(noise_polarisation(cfg, 3, std=0.1)))
+    prev = ctx.energy()[4]
+    for _ in range(10):
+        ctx.step(5)
+        e = ctx.energy()[4]
+        assert e < prev
+        prev = e
+
+
+# ---------------------------------------------------------------------------
+# FP32 sweeps + FP64 refinement
+# ---------------------------------------------------------------------------
+
+def test_refined_solves_reach_fp64_accuracy(pf, oracle_mod):
+    """The FP64 masters of the refined solves satisfy the FP64 tolerance, so
+    they agree with the FP64 oracle (given the same, FP32-rounded P) to
+    FP64-level accuracy."""
+    cfg = small_cfg(precision="fp32_refine", tol_phi=1e-12, tol_u=1e-12)
+    print("case: refined solves", flush=True)
+    P = domain_polarisation(cfg, 22, block=4).astype(np.float32).astype(np.float64)
+    o = oracle_mod.Oracle(cfg.replace(precision="fp64", tol_phi=1e-13, tol_u=1e-13))
+    ctx = pf.Context(cfg)
+    Pf = dev(P, torch.float32)
+    phi, st = ctx.solve_phi(Pf)
+    assert st["status"] == 0 and st["relres"] <= 1e-12 and st["outer"] >= 1
+    assert rel(host(phi), o.solve_phi(P)[0]) < 1e-9
+    u, st = ctx.solve_u(Pf)
+    assert st["status"] == 0 and st["relres"] <= 1e-12
+    assert rel(host(u), o.solve_u(P)[0]) < 1e-9
+
+
+def test_fp32_trajectory_error_per_field(pf, oracle_mod):
+    """FP32 sweeps with FP64 refinement against the FP64 oracle after 20
+    steps: relative error per field below 1e-4."""
+    cfg = small_cfg(precision="fp32_refine", tol_phi=1e-9, tol_u=1e-9)
+    print("case: fp32 trajectory", flush=True)
+    P0 = domain_polarisation(cfg, 23, block=4)
+    o = oracle_mod.Oracle(cfg.replace(precision="fp64"))
+    P = P0.astype(np.float32).astype(np.float64)
+    V, phi, u, _ = o.set_state(P)
+    o.step(P, V, phi, u, 20)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P0, torch.float32))
+    ctx.step(20)
+    Pg, Vg, phig, ug, _ = ctx.get_state()
+    errs = {"P": rel(host(Pg), P), "V": rel(host(Vg), V), "phi": rel(host(phig), phi), "u": rel(host(ug), u)}
+    print("fp32 errors vs fp64 oracle:", errs, flush=True)
+    for k, v in errs.items():
+        assert v < 1e-4, (k, v)
+
+
+# ---------------------------------------------------------------------------
+# Adjoint
+# ---------------------------------------------------------------------------
+
+def adjoint_cfg(**kw):
+    base = dict(nx=20, ny=9, nz=5, tol_phi=1e-13, tol_u=1e-13, dt=0.05,
+                electrodes=[Electrode(2, 6, 0, 9, 1.0), Electrode(12, 16, 0, 9, -1.0)],
+                Q11=0.5, Q12=-0.15, Q44=0.2)
+    base.update(kw)
+    return PFConfig(**base)
+
+
+@pytest.mark.parametrize("integrator", ["pc", "euler"])
+def test_adjoint_gradient_matches_oracle(pf, oracle_mod, integrator):
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    cfg = adjoint_cfg(integrator=integrator)
+    print(f"case: adjoint {integrator}", flush=True)
+    nsteps = 6
+    P0 = domain_polarisation(cfg, 31, block=3, std=0.2)
+    wgt = np.zeros((3,) + cfg.shape)
+    wgt[2, 2:, 2:6, 3:10] = 1.0 / 3 / 4 / 7
+    J_ref, dth_ref, dP_ref = oracle_mod.Oracle(cfg).gradient(P0, nsteps, wgt)
+    ctx = pf.Context(cfg)
+    P0t = dev(P0).requires_grad_(True)
+    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+    PN = tdgl_steps(P0t, volts, a1, ctx, nsteps, checkpoint_every=4)
+    J = (PN * dev(wgt)).sum()
+    J.backward()
+    assert abs(float(J.detach()) - J_ref) <= 1e-10 * abs(J_ref)
+    g = np.concatenate([volts.grad.cpu().numpy(), [a1.grad.item()]])
+    assert rel(g, dth_ref) < 1e-7, (g, dth_ref)
+    assert rel(host(P0t.grad), dP_ref) < 1e-7
+
+
+def test_adjoint_full_size_vs_central_differences(pf):
+    """The 128x128x32 adjoint case: dJ/dV_1, dJ/dV_2, dJ/da1 of the mean Pz
+    over the 32x32x8 box after 50 steps (checkpoint every 10) against
+    central differences of the GPU forward (step 1e-6)."""
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    w = workloads()["adjoint_128x128x32"]
+    cfg = w.cfg
+    print("case: adjoint_128x128x32", flush=True)
+    P0 = dev(initial_polarisation(w))
+    x0, x1, y0, y1, z0, z1 = w.region
+    wgt = torch.zeros((3,) + cfg.shape, dtype=torch.float64, device="cuda:0")
+    wgt[2, z0:z1, y0:y1, x0:x1] = 1.0 / ((x1 - x0) * (y1 - y0) * (z1 - z0))
+    ctx = pf.Context(cfg)
+    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+    PN = tdgl_steps(P0, volts, a1, ctx, w.steps, w.checkpoint_every)
+    J = (PN * wgt).sum()
+    J.backward()
+    g = [volts.grad[0].item(), volts.grad[1].item(), a1.grad.item()]
+
+    def run(vv, aa):
+        ctx.set_params(vv, aa)
+        ctx.set_state(P0)
+        ctx.step(w.steps)
+        return float((ctx.get_state()[0] * wgt).sum())
+
+    d = 1e-6
+    base_v = [e.volts for e in cfg.electrodes]
+    fd = []
+    for e in range(2):
+        vp = list(base_v); vp[e] += d
+        vm = list(base_v); vm[e] -= d
+        fd.append((run(vp, cfg.a1) - run(vm, cfg.a1)) / (2 * d))
+    fd.append((run(base_v, cfg.a1 + d) - run(base_v, cfg.a1 - d)) / (2 * d))
+    print("adjoint:", g, "central differences:", fd, flush=True)
+    for a, b in zip(g, fd):
+        assert abs(a - b) <= 1e-5 * max(abs(b), 1e-12) + 1e-9, (g, fd)
