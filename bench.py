@@ -21,6 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "TDGL cell-steps/s incl. Poisson+FEM solves; HBM GB/s vs peak; adjoint/fwd ratio"
+WARM_START_NAMES = {0: "zero", 1: "previous solution", 2: "extrapolated from the last three solutions"}
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic (compulsory) HBM bytes per node of one launch of each kernel
@@ -91,8 +92,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="lateral_256x256x64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm-start", type=int, default=2, choices=(0, 1, 2),
+                    help="initial guess of each solve: 0 zero, 1 previous solution, 2 extrapolated from the "
+                         "last three solutions (default 2)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without per-launch events (the roofline is then omitted)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy a 1 GiB device buffer 4 times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the path's sharding across GPUs is described in the "
@@ -105,6 +111,8 @@ def main():
     from paper_1202_6116_amd.workloads import initial_polarisation, workloads
 
     w = workloads()[args.workload]
+    if args.warm_start != w.cfg.warm_start:
+        w.cfg = w.cfg.replace(warm_start=args.warm_start)
     cfg = w.cfg
     dev = torch.device("cuda:0")
     ctx = pf.Context(cfg, "cuda:0")
@@ -114,20 +122,23 @@ def main():
         ctx.step(args.warmup)
     torch.cuda.synchronize()
 
-    timing = not args.no_kernel_timing
-    ctx.timing(timing)                      # reset the accumulators, switch per-launch events on
     stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    stats = ctx.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = ctx.timing(False)
-    gpu_s = e0.elapsed_time(e1) / 1e3
-    secs = max(wall, gpu_s)
+
+    def timed_steps(nsteps, per_launch_events):
+        ctx.timing(per_launch_events)       # reset the accumulators; per-launch events on/off
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        st = ctx.step(nsteps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kt = ctx.timing(False)
+        return max(wall, e0.elapsed_time(e1) / 1e3), st, kt
+
+    # throughput: K steps, no per-launch events
+    secs, stats, _ = timed_steps(args.steps, False)
     value = cfg.nodes * args.steps / secs
 
     it_phi = stats["iters_phi"] / max(1, stats["solves_phi"])
@@ -139,26 +150,31 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "cells": cfg.nodes,
                    "integrator": cfg.integrator, "tol_phi": cfg.tol_phi, "tol_u": cfg.tol_u,
-                   "electrodes": len(cfg.electrodes), "init": w.init, "seed": w.seed, "warm_start": cfg.warm_start},
+                   "electrodes": len(cfg.electrodes), "init": w.init, "seed": w.seed,
+                   "initial_guess": WARM_START_NAMES[int(cfg.warm_start)], "precision": cfg.precision},
         "cg_iters_per_step": {"phi": round(it_phi, 2), "u": round(it_u, 2)},
     }
-    if timing:
+    if not args.no_kernel_timing:
+        # roofline: a second timed region with HIP events around every launch
+        # on the library's stream; mean duration of the class taking the most time
+        ksteps = max(1, min(args.steps, 10))
+        ksecs, _, kt = timed_steps(ksteps, True)
         per = {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in kt.items() if v[1]}
         dom = max((k for k in BYTES_PER_NODE_FP64 if kt[k][1]), key=lambda k: kt[k][0])
         ms, n = kt[dom]
         avg_s = ms / n / 1e3
-        nbytes = BYTES_PER_NODE_FP64[dom] * nodes_per_launch(dom, cfg)
-        if cfg.precision != "fp64":
-            nbytes //= 2
+        scale = 0.5 if cfg.precision != "fp64" else 1.0
+        nbytes = int(BYTES_PER_NODE_FP64[dom] * nodes_per_launch(dom, cfg) * scale)
         achieved = nbytes / avg_s / 1e9
-        # whole-step algorithmic bandwidth over all timed kernels
-        tot_bytes = sum(BYTES_PER_NODE_FP64[k] * nodes_per_launch(k, cfg) * kt[k][1] for k in BYTES_PER_NODE_FP64)
+        tot_bytes = scale * sum(BYTES_PER_NODE_FP64[k] * nodes_per_launch(k, cfg) * kt[k][1]
+                                for k in BYTES_PER_NODE_FP64)
         tot_ms = sum(v[0] for v in kt.values())
         out["roofline"] = {
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_launch": nbytes, "avg_launch_us": round(avg_s * 1e6, 2),
             "step_alg_GBps": round(tot_bytes / (tot_ms / 1e3) / 1e9, 1),
+            "timed_steps": ksteps, "ms_per_step_with_events": round(1e3 * ksecs / ksteps, 2),
         }
         out["kernel_ms"] = per
     if not args.no_cpu_baseline:
@@ -167,6 +183,13 @@ def main():
         except Exception as e:  # the oracle is test infrastructure; report, don't fail the bench
             out["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each": src.numel() * 8, "copies": 4}), flush=True)
 
 
 if __name__ == "__main__":

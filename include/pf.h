@@ -98,7 +98,12 @@ typedef struct {
   int32_t precision;            /* PF_FP64 or PF_FP32_REFINE */
   double tol_phi, tol_u;        /* CG stop: ||b - A x||_2 <= tol ||b||_2 */
   int32_t maxit;                /* CG iteration cap per solve (> 0) */
-  int32_t warm_start;           /* 1: each solve starts from the previous solution */
+  int32_t warm_start;           /* 0: solves start from zero; 1: from the previous
+                                   solution (the paper's warm start); 2: from the
+                                   polynomial extrapolation of the last three
+                                   solutions (x, 2x - x1, 3x - 3x1 + x2 as history
+                                   accumulates after pf_set_state/pf_restore_state/
+                                   pf_set_params) */
   uint32_t terms;               /* PF_TERM_* mask */
   int32_t nonlocal_every;       /* refresh phi and u every k steps (<= 1: every
                                    step), the paper's Fig. 3d option */

@@ -60,7 +60,7 @@ typedef struct {
     int32_t integrator;           /* OR_INT_PC or OR_INT_EULER */
     int32_t maxit;                /* CG iteration cap */
     double tol_phi, tol_u;        /* relative residual tolerances */
-    int32_t warm_start;           /* 1: CG starts from the previous solution */
+    int32_t warm_start;           /* 0 cold, 1 previous solution, 2 extrapolated from the last three */
     uint32_t terms;               /* OR_TERM_* mask */
     int32_t nonlocal_every;       /* recompute phi and u every k steps (<= 1: every step) */
 } or_params;
@@ -850,18 +850,41 @@ int or_set_state(const or_params *p, const double *P, double *V, double *phi, do
     return force_with_solves(p, P, phi, u, V, 1, st);
 }
 
+/* Initial guess for the next solve from the last solutions (warm_start 2):
+ * with x the last solution and h1, h2 the two before it, the guess is the
+ * polynomial extrapolation of the available ones to the next step,
+ * x, 2x - h1 or 3x - 3h1 + h2; the history then shifts (h2 <- h1 <- x). */
+static void extrapolate(double *x, double *h1, double *h2, int64_t n, int nvalid) {
+    for (int64_t t = 0; t < n; t++) {
+        double g = x[t];
+        if (nvalid == 1) g = 2 * x[t] - h1[t];
+        else if (nvalid >= 2) g = 3 * x[t] - 3 * h1[t] + h2[t];
+        h2[t] = h1[t];
+        h1[t] = x[t];
+        x[t] = g;
+    }
+}
+
 /* step0 is the index of the first step (it decides, with nonlocal_every,
- * which steps refresh phi and u). */
+ * which steps refresh phi and u).  With warm_start 2 the solution history
+ * starts empty at the call (phi and u passed in are the last solutions). */
 int or_step(const or_params *p, double *P, double *V, double *phi, double *u, int32_t nsteps, int64_t step0,
             or_stats *st) {
-    int64_t N3 = 3 * nnodes(p);
+    int64_t N = nnodes(p), N3 = 3 * N;
     double *Pp = (double *)malloc(sizeof(double) * (size_t)N3);
     double *F = (double *)malloc(sizeof(double) * (size_t)N3);
-    if (!Pp || !F) { free(Pp); free(F); return OR_ENOMEM; }
+    double *hist = p->warm_start == 2 ? (double *)calloc((size_t)(8 * N), sizeof(double)) : NULL;
+    if (!Pp || !F || (p->warm_start == 2 && !hist)) { free(Pp); free(F); free(hist); return OR_ENOMEM; }
+    int nvalid = 0;
     int worst = OR_OK;
     for (int32_t s = 0; s < nsteps; s++) {
         int64_t step = step0 + s;
         int refresh = p->nonlocal_every <= 1 || (step % p->nonlocal_every) == 0;
+        if (refresh && hist) {
+            if (p->terms & OR_TERM_ELEC) extrapolate(phi, hist, hist + N, N, nvalid);
+            if (p->terms & OR_TERM_ELAS) extrapolate(u, hist + 2 * N, hist + 5 * N, N3, nvalid);
+            if (nvalid < 2) nvalid++;
+        }
         int rc;
         if (p->integrator == OR_INT_PC) {
             for (int64_t t = 0; t < N3; t++) Pp[t] = P[t] + p->dt * V[t];
@@ -877,7 +900,7 @@ int or_step(const or_params *p, double *P, double *V, double *phi, double *u, in
         if (rc == OR_ENONFINITE || rc == OR_ENOMEM) { worst = rc; break; }
         if (rc != OR_OK) worst = rc;
     }
-    free(Pp); free(F);
+    free(Pp); free(F); free(hist);
     return worst;
 }
 

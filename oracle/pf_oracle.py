@@ -156,7 +156,7 @@ class Oracle:
         p.el_volts = self._volts.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         p.integrator = 0 if cfg.integrator == "pc" else 1
         p.maxit = cfg.maxit
-        p.warm_start = 1 if cfg.warm_start else 0
+        p.warm_start = int(cfg.warm_start)
         p.terms = cfg.terms
         p.nonlocal_every = cfg.nonlocal_every
         self.p = p

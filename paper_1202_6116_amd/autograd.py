@@ -29,7 +29,12 @@ class PFSteps(torch.autograd.Function):
         checkpoints = []
         for s in range(nsteps):
             if s % k == 0:
-                checkpoints.append(pf.get_state())
+                cp = pf.get_state()
+                checkpoints.append(cp)
+                # restarting from the checkpoint here too keeps the forward
+                # identical to its recomputation (solver warm-start history
+                # starts afresh at every checkpoint)
+                pf.restore_state(*cp)
             pf.step(1)
         PN = pf.get_state()[0]
         fctx.pf = pf

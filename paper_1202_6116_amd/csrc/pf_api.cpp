@@ -29,6 +29,7 @@ template <typename T> hipError_t launch_cg_finish(T* x, const T* p, int64_t n, c
 hipError_t launch_cg_reduce(const double* partials, int nblocks, int nv, CgScalars* sc, int mode, double tol,
                             int maxit, hipStream_t s, double tol2, double* out);
 hipError_t launch_refine_update(double* x64, float* x32, const float* d, int64_t n, hipStream_t s);
+hipError_t launch_extrapolate(double* x, double* h1, double* h2, int64_t n, int nvalid, hipStream_t s);
 template <typename T, typename S, typename R>
 hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
                                 int with_bc, const T* ghost_top, T phi_bottom, const T* x, R* r, R* p, R* dz,
@@ -204,6 +205,7 @@ struct Layout {
   size_t phi_bc, basis;        // boundary potential and electrode basis (FP64)
   size_t pr, pp[2], fr, fp[2]; // CG vectors, sized for FP64 (FP32 solves use half)
   size_t dphi, du;             // refinement corrections (FP32)
+  size_t hist;                 // last solutions for extrapolated warm starts (8N doubles)
   size_t scratch[8];           // 3N doubles each: adjoint, energy, conversions
   size_t tables, scalars, result, partials;
   size_t total;
@@ -241,6 +243,7 @@ Layout make_layout(const pf_config& c, int npartials) {
   for (int b = 0; b < 2; b++) L.fp[b] = take(3 * N * 8);
   L.dphi = take(N * 4);
   L.du = take(3 * N * 4);
+  L.hist = c.warm_start == 2 ? take(8 * N * 8) : 0;
   for (int t = 0; t < 8; t++) L.scratch[t] = take(3 * N * 8);
   L.tables = take(sizeof(FemTables));
   L.scalars = take(sizeof(CgScalars) * kNumScalars);
@@ -291,6 +294,7 @@ struct pf_ctx {
   bool phi_bc_valid;
   bool basis_valid;
   bool adj_warm;            // adjoint scratch holds earlier adjoint solutions
+  int hist_valid;           // solutions held for extrapolated warm starts (0..2)
   int64_t step;
   int cur;                  // which P/V buffer is current
   int pred[pf::kPredCount];
@@ -371,6 +375,7 @@ pf_status validate(const pf_config* c, std::string* why) {
   if (c->precision != PF_FP64 && c->precision != PF_FP32_REFINE) return bad("unknown precision");
   if (!(c->tol_phi > 0) || !(c->tol_u > 0)) return bad("tolerances must be > 0");
   if (c->maxit <= 0) return bad("maxit must be > 0");
+  if (c->warm_start < 0 || c->warm_start > 2) return bad("warm_start must be 0, 1 or 2");
   if (c->terms & ~(uint32_t)PF_TERM_ALL) return bad("unknown term bits");
   if (!(c->C11 > 0) || !(c->C44 > 0) || !(c->C11 > std::fabs(c->C12)) || !(c->C11 + 2 * c->C12 > 0))
     return bad("stiffness must be positive definite");
@@ -687,6 +692,24 @@ void stats_add(pf_step_stats* st, int which, const SolveResult& r) {
     st->solves_u++;
     st->relres_u = std::max(st->relres_u, r.relres);
   }
+}
+
+// warm_start 2: replaces the state's phi and u by their extrapolation from
+// the last solutions (the first solves after a state change use what is
+// available).
+pf_status extrapolate_state(pf_ctx* c) {
+  const int64_t N = c->dims.N;
+  double* h = at<double>(c, c->lay.hist);
+  if (c->cfg.terms & PF_TERM_ELEC)
+    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+      return launch_extrapolate(at<double>(c, c->lay.phi), h, h + N, N, c->hist_valid, c->stream);
+    }));
+  if (c->cfg.terms & PF_TERM_ELAS)
+    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+      return launch_extrapolate(at<double>(c, c->lay.u), h + 2 * N, h + 5 * N, 3 * N, c->hist_valid, c->stream);
+    }));
+  if (c->hist_valid < 2) c->hist_valid++;
+  return PF_OK;
 }
 
 // Solves phi and u of the state at Pp = P + cdt V (state precision).
@@ -1006,6 +1029,7 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->ws_bytes = bytes;
   c->stream = static_cast<hipStream_t>(stream);
   c->have_state = c->phi_bc_valid = c->basis_valid = c->adj_warm = false;
+  c->hist_valid = 0;
   c->step = 0;
   c->cur = 0;
   for (int t = 0; t < kPredCount; t++) c->pred[t] = 16;
@@ -1056,6 +1080,7 @@ pf_status pf_set_state(pf_ctx* c, const void* P, const void* phi0, const void* u
   const size_t es = state_bytes(c);
   c->cur = 0;
   c->step = 0;
+  c->hist_valid = 0;
   void* Pc = c->ws + c->lay.P[0];
   void* Vc = c->ws + c->lay.V[0];
   double* phi = at<double>(c, c->lay.phi);
@@ -1088,6 +1113,7 @@ pf_status pf_restore_state(pf_ctx* c, const void* P, const void* V, const void* 
   const int64_t N = c->dims.N;
   const size_t es = state_bytes(c);
   c->cur = 0;
+  c->hist_valid = 0;
   PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.P[0], P, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
   PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.V[0], V, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
   PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.phi), phi, N * 8, hipMemcpyDeviceToDevice, c->stream));
@@ -1129,6 +1155,7 @@ pf_status pf_step(pf_ctx* c, int32_t nsteps, pf_step_stats* st) {
     void* Pn = c->ws + c->lay.P[c->cur ^ 1];
     void* Vn = c->ws + c->lay.V[c->cur ^ 1];
     if (c->step % every == 0) {
+      if (c->cfg.warm_start == 2) PF_TRY(extrapolate_state(c));
       pf_status r = solve_nonlocal(c, P, pc ? V : nullptr, pc ? c->cfg.dt : 0.0, c->cfg.warm_start != 0, st);
       if (fatal(r)) return r;
       out = worst(out, r);
@@ -1215,6 +1242,7 @@ pf_status pf_set_params(pf_ctx* c, const double* volts, double a1) {
       c->electrodes[e].volts = volts[e];
     }
     c->phi_bc_valid = false;
+    c->hist_valid = 0;
     PF_TRY(upload_ghosts(c));
   }
   return PF_OK;

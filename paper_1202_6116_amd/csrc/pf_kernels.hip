@@ -22,6 +22,7 @@
 #include "pf_internal.h"
 
 #include <math.h>
+#include <stdlib.h>
 
 namespace pf {
 
@@ -103,25 +104,51 @@ __device__ __forceinline__ TileCoord tile_coord(const Dims& d, const TileMap& tm
 
 __device__ __forceinline__ int slot_of(int k) { return (k + 3) % 3; }
 
-// Fills ring slot s with plane k of a tile (and its one-node halo) using
-// f(n, k, out[NC]) for the values; points outside the grid in z, and tile
-// points beyond the ragged edges, hold zero.
-template <typename T, int NC, typename F>
-__device__ __forceinline__ void load_plane(T (&ring)[3][NC][kHY][kHX], const Dims& d, int i0, int j0, int k, F f) {
-  const int s = slot_of(k);
-  for (int t = tid_flat(); t < kHP; t += kThreads) {
-    const int hx = t % kHX, hy = t / kHX;
-    int gi = i0 + hx - 1, gj = j0 + hy - 1;
-    T val[NC];
+// Software-pipelined staging of tile planes.  Each thread owns (up to) two
+// of the kHP halo-plane points.  stage_fetch issues the global loads of a
+// plane into registers (raw values, RAW per point); stage_store combines
+// them into the staged values (NC per point) and writes the ring slot.  The
+// z-march fetches plane k+2 while plane k is being computed, so the loads of
+// a block overlap its own arithmetic (the barrier waits for LDS only).
+static_assert(kHP <= 2 * kThreads, "two halo points per thread");
+
+template <typename T, int RAW>
+struct Stage {
+  T v[2][RAW];
+};
+
+template <typename T, int RAW, typename Fetch>
+__device__ __forceinline__ void stage_fetch(Stage<T, RAW>& st, const Dims& d, int i0, int j0, int k, Fetch f) {
 #pragma unroll
-    for (int c = 0; c < NC; c++) val[c] = 0;
-    if (k >= 0 && k < d.nz && gi >= -1 && gi <= d.nx && gj >= -1 && gj <= d.ny) {
-      gi = wrap(gi, d.nx);
-      gj = wrap(gj, d.ny);
-      f(gi + (int64_t)d.nx * gj + d.plane * k, k, val);
+  for (int q = 0; q < 2; q++) {
+    const int t = tid_flat() + q * kThreads;
+#pragma unroll
+    for (int c = 0; c < RAW; c++) st.v[q][c] = 0;
+    if (t < kHP) {
+      const int hx = t % kHX, hy = t / kHX;
+      int gi = i0 + hx - 1, gj = j0 + hy - 1;
+      if (k >= 0 && k < d.nz && gi >= -1 && gi <= d.nx && gj >= -1 && gj <= d.ny) {
+        gi = wrap(gi, d.nx);
+        gj = wrap(gj, d.ny);
+        f(gi + (int64_t)d.nx * gj + d.plane * k, k, st.v[q]);
+      }
     }
+  }
+}
+
+template <typename T, int NC, int RAW, typename Comb>
+__device__ __forceinline__ void stage_store(T (&ring)[3][NC][kHY][kHX], const Stage<T, RAW>& st, int k, Comb comb) {
+  const int s = slot_of(k);
 #pragma unroll
-    for (int c = 0; c < NC; c++) ring[s][c][hy][hx] = val[c];
+  for (int q = 0; q < 2; q++) {
+    const int t = tid_flat() + q * kThreads;
+    if (t < kHP) {
+      const int hx = t % kHX, hy = t / kHX;
+      T out[NC];
+      comb(k, st.v[q], out);
+#pragma unroll
+      for (int c = 0; c < NC; c++) ring[s][c][hy][hx] = out[c];
+    }
   }
 }
 
@@ -266,6 +293,24 @@ __global__ void cg_finish_kernel(T* x, const T* p, int64_t n, const CgScalars* s
   for (; t < n; t += stride) x[t] = zero ? (T)0 : x[t] + alpha * p[t];
 }
 
+// Initial guess for the next solve from the last solutions: with x the last
+// solution and h1, h2 the two before it, x becomes the polynomial
+// extrapolation of the nvalid+1 available ones (x, 2x - h1, 3x - 3h1 + h2)
+// and the history shifts (h2 <- h1 <- x).
+__global__ void extrapolate_kernel(double* x, double* h1, double* h2, int64_t n, int nvalid) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; t < n; t += stride) {
+    const double a = x[t], b = h1[t];
+    double g = a;
+    if (nvalid == 1) g = 2 * a - b;
+    else if (nvalid >= 2) g = 3 * a - 3 * b + h2[t];
+    h2[t] = b;
+    h1[t] = a;
+    x[t] = g;
+  }
+}
+
 // Iterative refinement: x64 += d, x32 = x64 (rounded working copy).
 __global__ void refine_update_kernel(double* x64, float* x32, const float* d, int64_t n) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -344,12 +389,32 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
   const bool valid = i < d.nx && j < d.ny;
-  auto f = [&](int64_t m, int, T* out) { out[0] = r[m] * w + beta * p_old[m]; };
-  load_plane<T, 1>(ring, d, tc.i0, tc.j0, tc.k0 - 1, f);
-  load_plane<T, 1>(ring, d, tc.i0, tc.j0, tc.k0, f);
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  auto fetch = [&](int64_t m, int, T* raw) {
+    raw[0] = r[m];
+    raw[1] = p_old[m];
+  };
+  auto comb = [&](int, const T* raw, T* out) { out[0] = raw[0] * w + beta * raw[1]; };
+  Stage<T, 2> st;
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store(ring, st, tc.k0 - 1, comb);
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store(ring, st, tc.k0, comb);
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  T cpo = 0, cx = 0;  // centre p_old, x of the plane being computed
+  if (valid) {
+    cpo = p_old[col + d.plane * tc.k0];
+    cx = x[col + d.plane * tc.k0];
+  }
   double acc = 0.0;
   for (int k = tc.k0; k < tc.k1; k++) {
-    load_plane<T, 1>(ring, d, tc.i0, tc.j0, k + 1, f);
+    stage_store(ring, st, k + 1, comb);
+    if (k + 2 <= tc.k1) stage_fetch(st, d, tc.i0, tc.j0, k + 2, fetch);
+    T npo = 0, nx_ = 0;
+    if (valid && k + 1 < tc.k1) {
+      npo = p_old[col + d.plane * (k + 1)];
+      nx_ = x[col + d.plane * (k + 1)];
+    }
     __syncthreads();
     if (valid) {
       const int sm = slot_of(k - 1), s0 = slot_of(k), sp = slot_of(k + 1);
@@ -357,11 +422,13 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
       const T s = ring[s0][0][ly + 1][lx] + ring[s0][0][ly + 1][lx + 2] + ring[s0][0][ly][lx + 1] +
                   ring[s0][0][ly + 2][lx + 1] + ring[sm][0][ly + 1][lx + 1] + ring[sp][0][ly + 1][lx + 1];
       const T q = c6 * (6 * pc - s);
-      const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
+      const int64_t n = col + d.plane * k;
       p_new[n] = pc;
-      x[n] += alpha * p_old[n];
+      x[n] = cx + alpha * cpo;
       acc += (double)pc * q;
     }
+    cpo = npo;
+    cx = nx_;
     __syncthreads();
   }
   double v[1] = {acc};
@@ -380,12 +447,21 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_b_kernel(Dims d, TileMap 
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
   const bool valid = i < d.nx && j < d.ny;
-  auto f = [&](int64_t m, int, T* out) { out[0] = p[m]; };
-  load_plane<T, 1>(ring, d, tc.i0, tc.j0, tc.k0 - 1, f);
-  load_plane<T, 1>(ring, d, tc.i0, tc.j0, tc.k0, f);
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  auto fetch = [&](int64_t m, int, T* raw) { raw[0] = p[m]; };
+  auto comb = [&](int, const T* raw, T* out) { out[0] = raw[0]; };
+  Stage<T, 1> st;
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store(ring, st, tc.k0 - 1, comb);
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store(ring, st, tc.k0, comb);
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  T cr = valid ? r[col + d.plane * tc.k0] : (T)0;
   double a0 = 0.0, a1 = 0.0;
   for (int k = tc.k0; k < tc.k1; k++) {
-    load_plane<T, 1>(ring, d, tc.i0, tc.j0, k + 1, f);
+    stage_store(ring, st, k + 1, comb);
+    if (k + 2 <= tc.k1) stage_fetch(st, d, tc.i0, tc.j0, k + 2, fetch);
+    const T nr = (valid && k + 1 < tc.k1) ? r[col + d.plane * (k + 1)] : (T)0;
     __syncthreads();
     if (valid) {
       const int sm = slot_of(k - 1), s0 = slot_of(k), sp = slot_of(k + 1);
@@ -393,12 +469,12 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_b_kernel(Dims d, TileMap 
       const T s = ring[s0][0][ly + 1][lx] + ring[s0][0][ly + 1][lx + 2] + ring[s0][0][ly][lx + 1] +
                   ring[s0][0][ly + 2][lx + 1] + ring[sm][0][ly + 1][lx + 1] + ring[sp][0][ly + 1][lx + 1];
       const T q = c6 * (6 * pc - s);
-      const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
-      const T rn = r[n] - alpha * q;
-      r[n] = rn;
+      const T rn = cr - alpha * q;
+      r[col + d.plane * k] = rn;
       a0 += (double)rn * (rn * w);
       a1 += (double)rn * rn;
     }
+    cr = nr;
     __syncthreads();
   }
   double v[2] = {a0, a1};
@@ -584,8 +660,10 @@ __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
 
 // Iteration kernel A: p_new = z + beta p_old on the tile and its halo (zero
 // on the clamped plane), q = K p_new, x += alpha_prev p_old; partial p.q.
+// At most 128 VGPRs: four waves per SIMD, so four 256-thread blocks per CU
+// and the whole tile grid resident at once.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void fem_cg_a_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
+__global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
                                                             const T* __restrict__ r, const T* __restrict__ p_old,
                                                             T* __restrict__ p_new, T* __restrict__ x,
                                                             const CgScalars* sc, double* partials) {
@@ -598,17 +676,47 @@ __global__ __launch_bounds__(kThreads) void fem_cg_a_kernel(Dims d, TileMap tm, 
   const int i = tc.i0 + lx, j = tc.j0 + ly;
   const bool valid = i < d.nx && j < d.ny;
   const int64_t N = d.N;
-  auto f = [&](int64_t m, int k, T* out) {
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  auto fetch = [&](int64_t m, int k, T* raw) {
     if (k == 0) return;  // clamped plane: zero
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      raw[c] = r[c * N + m];
+      raw[3 + c] = p_old[c * N + m];
+    }
+  };
+  auto comb = [&](int k, const T* raw, T* out) {
     const T w = (k == d.nz - 1) ? w_top : w_int;
 #pragma unroll
-    for (int c = 0; c < 3; c++) out[c] = r[c * N + m] * w + beta * p_old[c * N + m];
+    for (int c = 0; c < 3; c++) out[c] = raw[c] * w + beta * raw[3 + c];
   };
-  load_plane<T, 3>(ring, d, tc.i0, tc.j0, tc.k0 - 1, f);
-  load_plane<T, 3>(ring, d, tc.i0, tc.j0, tc.k0, f);
+  // centre values (p_old, x) of a plane
+  auto centre = [&](int k, T* cv) {
+#pragma unroll
+    for (int c = 0; c < 6; c++) cv[c] = 0;
+    if (valid && k > 0 && k < tc.k1) {
+      const int64_t n = col + d.plane * k;
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        cv[c] = p_old[c * N + n];
+        cv[3 + c] = x[c * N + n];
+      }
+    }
+  };
+  Stage<T, 6> st;
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store(ring, st, tc.k0 - 1, comb);
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store(ring, st, tc.k0, comb);
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  T cv[6];
+  centre(tc.k0, cv);
   double acc = 0.0;
   for (int k = tc.k0; k < tc.k1; k++) {
-    load_plane<T, 3>(ring, d, tc.i0, tc.j0, k + 1, f);
+    stage_store(ring, st, k + 1, comb);
+    if (k + 2 <= tc.k1) stage_fetch(st, d, tc.i0, tc.j0, k + 2, fetch);
+    T nv[6];
+    centre(k + 1, nv);
     __syncthreads();
     if (valid && k > 0) {
       const int zt = (k == d.nz - 1) ? 1 : 0;
@@ -619,16 +727,18 @@ __global__ __launch_bounds__(kThreads) void fem_cg_a_kernel(Dims d, TileMap tm, 
       };
       T q[3];
       fem_K_apply<T>(tb, zt, ld, q);
-      const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
+      const int64_t n = col + d.plane * k;
       const int s0 = slot_of(k);
 #pragma unroll
       for (int c = 0; c < 3; c++) {
         const T pc = ring[s0][c][ly + 1][lx + 1];
         p_new[c * N + n] = pc;
-        x[c * N + n] += alpha * p_old[c * N + n];
+        x[c * N + n] = cv[3 + c] + alpha * cv[c];
         acc += (double)pc * q[c];
       }
     }
+#pragma unroll
+    for (int c = 0; c < 6; c++) cv[c] = nv[c];
     __syncthreads();
   }
   double v[1] = {acc};
@@ -637,7 +747,7 @@ __global__ __launch_bounds__(kThreads) void fem_cg_a_kernel(Dims d, TileMap tm, 
 
 // Iteration kernel B: r -= alpha K p (operator recomputed); partial (r.z, r.r).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void fem_cg_b_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
+__global__ __launch_bounds__(kThreads, 4) void fem_cg_b_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
                                                             const T* __restrict__ p, T* __restrict__ r,
                                                             const CgScalars* sc, double* partials) {
   if (sc->done) return;
@@ -649,16 +759,39 @@ __global__ __launch_bounds__(kThreads) void fem_cg_b_kernel(Dims d, TileMap tm, 
   const int i = tc.i0 + lx, j = tc.j0 + ly;
   const bool valid = i < d.nx && j < d.ny;
   const int64_t N = d.N;
-  auto f = [&](int64_t m, int k, T* out) {
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  auto fetch = [&](int64_t m, int k, T* raw) {
     if (k == 0) return;
 #pragma unroll
-    for (int c = 0; c < 3; c++) out[c] = p[c * N + m];
+    for (int c = 0; c < 3; c++) raw[c] = p[c * N + m];
   };
-  load_plane<T, 3>(ring, d, tc.i0, tc.j0, tc.k0 - 1, f);
-  load_plane<T, 3>(ring, d, tc.i0, tc.j0, tc.k0, f);
+  auto comb = [&](int, const T* raw, T* out) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) out[c] = raw[c];
+  };
+  auto centre = [&](int k, T* cv) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) cv[c] = 0;
+    if (valid && k > 0 && k < tc.k1) {
+      const int64_t n = col + d.plane * k;
+#pragma unroll
+      for (int c = 0; c < 3; c++) cv[c] = r[c * N + n];
+    }
+  };
+  Stage<T, 3> st;
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store(ring, st, tc.k0 - 1, comb);
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store(ring, st, tc.k0, comb);
+  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  T cv[3];
+  centre(tc.k0, cv);
   double a0 = 0.0, a1 = 0.0;
   for (int k = tc.k0; k < tc.k1; k++) {
-    load_plane<T, 3>(ring, d, tc.i0, tc.j0, k + 1, f);
+    stage_store(ring, st, k + 1, comb);
+    if (k + 2 <= tc.k1) stage_fetch(st, d, tc.i0, tc.j0, k + 2, fetch);
+    T nv[3];
+    centre(k + 1, nv);
     __syncthreads();
     if (valid && k > 0) {
       const int zt = (k == d.nz - 1) ? 1 : 0;
@@ -670,15 +803,17 @@ __global__ __launch_bounds__(kThreads) void fem_cg_b_kernel(Dims d, TileMap tm, 
       T q[3];
       fem_K_apply<T>(tb, zt, ld, q);
       const T w = zt ? w_top : w_int;
-      const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
+      const int64_t n = col + d.plane * k;
 #pragma unroll
       for (int c = 0; c < 3; c++) {
-        const T rn = r[c * N + n] - alpha * q[c];
+        const T rn = cv[c] - alpha * q[c];
         r[c * N + n] = rn;
         a0 += (double)rn * (rn * w);
         a1 += (double)rn * rn;
       }
     }
+#pragma unroll
+    for (int c = 0; c < 3; c++) cv[c] = nv[c];
     __syncthreads();
   }
   double v[2] = {a0, a1};
@@ -1084,15 +1219,21 @@ int node_blocks(const Dims& d) {
   return (int)(g.x * g.y * g.z);
 }
 
-// z-chunk length: enough blocks to fill the chip (about 8 per CU), chunks
-// of 4..32 planes.
+// z-chunk length of the tile kernels: long enough that every block stays
+// resident (the whole grid in one round of about 4 blocks per CU), 4..64
+// planes.  PF_TILE_KZ overrides it (a tuning knob; results do not depend on
+// it beyond rounding order).
 TileMap make_tile_map(const Dims& d) {
   TileMap t;
   t.ntx = (d.nx + kBX - 1) / kBX;
   t.nty = (d.ny + kBY - 1) / kBY;
   const int64_t cols = (int64_t)t.ntx * t.nty;
-  int64_t kz = (int64_t)d.nz * cols / 2048;
-  kz = kz < 4 ? 4 : (kz > 32 ? 32 : kz);
+  int64_t kz = (int64_t)d.nz * cols / 1024;
+  kz = kz < 4 ? 4 : (kz > 64 ? 64 : kz);
+  if (const char* env = getenv("PF_TILE_KZ")) {
+    const long v = strtol(env, nullptr, 10);
+    if (v >= 1 && v <= 4096) kz = v;
+  }
   if (kz > d.nz) kz = d.nz;
   t.kz = (int)kz;
   t.nkz = (d.nz + t.kz - 1) / t.kz;
@@ -1126,6 +1267,11 @@ hipError_t launch_cg_reduce(const double* partials, int nblocks, int nv, CgScala
     case 3: cg_reduce_kernel<3><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit, tol2, out); break;
     default: cg_reduce_kernel<4><<<1, kRedThreads, 0, s>>>(partials, nblocks, sc, mode, tol, maxit, tol2, out); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_extrapolate(double* x, double* h1, double* h2, int64_t n, int nvalid, hipStream_t s) {
+  extrapolate_kernel<<<flat_blocks(n), 256, 0, s>>>(x, h1, h2, n, nvalid);
   return hipGetLastError();
 }
 

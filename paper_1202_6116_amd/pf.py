@@ -138,7 +138,7 @@ def make_config(cfg: PFConfig):
     c.integrator = PF_INT_PC if cfg.integrator == "pc" else PF_INT_EULER
     c.precision = PF_FP64 if cfg.precision == "fp64" else PF_FP32_REFINE
     c.maxit = cfg.maxit
-    c.warm_start = 1 if cfg.warm_start else 0
+    c.warm_start = int(cfg.warm_start)
     c.terms = cfg.terms
     c.nonlocal_every = cfg.nonlocal_every
     return c, els

@@ -73,7 +73,7 @@ class PFConfig:
     tol_phi: float = 1e-10
     tol_u: float = 1e-10
     maxit: int = 5000
-    warm_start: bool = True
+    warm_start: int = 1             # 0 cold, 1 previous solution, 2 extrapolated from the last three
     terms: int = TERM_ALL
     nonlocal_every: int = 1         # recompute phi and u every k steps
 

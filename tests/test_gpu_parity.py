@@ -254,3 +254,21 @@ def test_lateral_256_full_size_properties(pf, oracle_mod):
     F = host(ctx.force(Pd, phi, u))
     ref = o.force(P0, phi_h, u_h)
     assert rel(F, ref) < 1e-12
+
+
+def test_extrapolated_warm_start_matches_oracle(pf, oracle_mod):
+    cfg = ragged_cfg(warm_start=2)
+    print("case: trajectory 70x13x6 extrapolated warm start", flush=True)
+    P0 = domain_polarisation(cfg, 17, block=4)
+    o = oracle_mod.Oracle(cfg)
+    P = P0.copy()
+    V, phi, u, _ = o.set_state(P)
+    st_o = o.step(P, V, phi, u, 10)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P0))
+    st_g = ctx.step(10)
+    assert abs(st_g["iters_phi"] - st_o["iters_phi"]) <= 10 and abs(st_g["iters_u"] - st_o["iters_u"]) <= 10
+    Pg, Vg, phig, ug, _ = ctx.get_state()
+    assert rel(host(Pg), P) < TOL
+    assert rel(host(phig), phi) < TOL
+    assert rel(host(ug), u) < TOL

@@ -506,3 +506,21 @@ def test_adjoint_gradient_vs_central_differences(oracle_mod, integrator):
     v = random_field(P0.shape, 10)
     fdp = (run(cfg, P0 + d * v) - run(cfg, P0 - d * v)) / (2 * d)
     np.testing.assert_allclose(np.sum(dP0 * v), fdp, rtol=1e-5)
+
+
+def test_extrapolated_warm_start_same_solution_fewer_iterations(oracle_mod):
+    """Extrapolating the initial guess from the last solutions (warm_start 2)
+    changes only the starting point of each solve: trajectories agree with
+    the plain warm start to the solver tolerance, with fewer iterations."""
+    base = PFConfig(nx=24, ny=16, nz=6, tol_phi=1e-11, tol_u=1e-11,
+                    electrodes=[Electrode(2, 8, 0, 16, 2.0), Electrode(14, 20, 0, 16, -2.0)])
+    P0 = domain_polarisation(base, 12, block=4)
+    res = {}
+    for ws in (1, 2):
+        o = oracle_mod.Oracle(base.replace(warm_start=ws))
+        P = P0.copy()
+        V, phi, u, _ = o.set_state(P)
+        st = o.step(P, V, phi, u, 12)
+        res[ws] = (P, st["iters_phi"] + st["iters_u"])
+    np.testing.assert_allclose(res[2][0], res[1][0], rtol=0, atol=1e-8)
+    assert res[2][1] < 0.9 * res[1][1], (res[1][1], res[2][1])
