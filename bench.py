@@ -85,6 +85,66 @@ def cpu_baseline(w, iters_phi, iters_u):
     }
 
 
+def adjoint_leg(pf, torch, workloads, initial_polarisation, warm_start):
+    """Forward (50 steps, checkpoints every 10) and backward of the adjoint
+    case; returns timings and the gradient."""
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    w = workloads()["adjoint_128x128x32"]
+    cfg = w.cfg.replace(warm_start=warm_start)
+    ctx = pf.Context(cfg, "cuda:0")
+    P0 = torch.from_numpy(initial_polarisation(w)).to("cuda:0")
+    x0, x1, y0, y1, z0, z1 = w.region
+    wgt = torch.zeros((3,) + cfg.shape, dtype=torch.float64, device="cuda:0")
+    wgt[2, z0:z1, y0:y1, x0:x1] = 1.0 / ((x1 - x0) * (y1 - y0) * (z1 - z0))
+    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    PN = tdgl_steps(P0, volts, a1, ctx, w.steps, w.checkpoint_every)
+    J = (PN * wgt).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"workload": w.name, "steps": w.steps, "checkpoint_every": w.checkpoint_every,
+            "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+            "adjoint_fwd_ratio": round((t2 - t1) / (t1 - t0), 3),
+            "dJ_dV": [float(v) for v in volts.grad], "dJ_da1": float(a1.grad)}
+
+
+def precision_leg(pf, torch, workloads, initial_polarisation, warm_start, steps=4, warmup=2):
+    """The 512x512x128 lateral film for a few steps in FP32 sweeps with FP64
+    refinement and in plain FP64 from the same start; returns both step times
+    and the per-field relative difference after the steps."""
+    w = workloads()["lateral_512x512x128_fp32"]
+    res = {"workload": w.name, "steps": steps, "warmup": warmup}
+    states = {}
+    for prec in ("fp32_refine", "fp64"):
+        cfg = w.cfg.replace(precision=prec, warm_start=warm_start)
+        ctx = pf.Context(cfg, "cuda:0")
+        P0 = torch.from_numpy(initial_polarisation(w)).to("cuda:0").to(ctx.state_dtype)
+        ctx.set_state(P0)
+        ctx.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.step(steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[prec] = {"ms_per_step": round(1e3 * dt, 2), "cell_steps_per_s": cfg.nodes / dt,
+                     "cg_iters_per_step": {"phi": st["iters_phi"] / max(1, st["solves_phi"]),
+                                           "u": st["iters_u"] / max(1, st["solves_u"])}}
+        P, V, phi, u, _ = ctx.get_state()
+        states[prec] = [t.double() for t in (P, V, phi, u)]
+        del ctx
+        torch.cuda.empty_cache()
+    res["speedup_fp32_refine_vs_fp64"] = round(res["fp64"]["ms_per_step"] / res["fp32_refine"]["ms_per_step"], 3)
+    res["rel_diff_vs_fp64"] = {
+        name: float((a - b).abs().max() / b.abs().max())
+        for name, a, b in zip(("P", "V", "phi", "u"), states["fp32_refine"], states["fp64"])}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +157,8 @@ def main():
                          "last three solutions (default 2)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without per-launch events (the roofline is then omitted)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing leg")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP32+refinement vs FP64 leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 4 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -177,6 +239,12 @@ def main():
             "timed_steps": ksteps, "ms_per_step_with_events": round(1e3 * ksecs / ksteps, 2),
         }
         out["kernel_ms"] = per
+    del ctx
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
+    if not args.no_precision:
+        out["precision"] = precision_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(w, it_phi, it_u)

@@ -269,7 +269,9 @@ enum {
 // first batch of iterations enqueued before the first read-back.
 enum { kPredPhi = 0, kPredU, kPredPhiIn, kPredUIn, kPredAux, kPredAdjPsi, kPredAdjU, kPredAdjDu, kPredCount };
 
-constexpr double kInnerTol = 1e-5;  // FP32 inner solves of a refinement sweep
+// Floor of the relative tolerance of the FP32 inner solves (FP32 CG with
+// FP64 dot products tracks FP64 CG to about 1e-6 of its right-hand side).
+constexpr double kInnerTol = 1e-6;
 constexpr int kMaxOuter = 30;
 
 }  // namespace
@@ -616,8 +618,10 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
 
 // Iterative refinement (FP32_REFINE): each sweep forms the FP64 residual of
 // the FP64 iterate x64 (the outer test ||b - A x64|| <= tol ||b||), solves
-// the correction equation in FP32 (FP64 dot products) to kInnerTol, adds the
-// correction to x64 and refreshes the FP32 working copy x32.
+// the correction equation in FP32 (FP64 dot products) to the accuracy the
+// outer test still needs (no tighter than kInnerTol), adds the correction to
+// x64 and refreshes the FP32 working copy x32.  One sweep usually suffices,
+// so the Krylov space is rarely thrown away by a restart.
 pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, double cdt, double* x64, float* x32,
                         double tol, bool warm, SolveResult* res) {
   const Dims& d = c->dims;

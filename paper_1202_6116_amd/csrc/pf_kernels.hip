@@ -163,7 +163,9 @@ __device__ __forceinline__ void stage_store(T (&ring)[3][NC][kHY][kHX], const St
 // ---------------------------------------------------------------------------
 //   kRedOuter  (b.b, r.z, r.r) of the FP64 residual of an iterative
 //              refinement sweep: records the outer test and starts the
-//              inner (FP32) solve for the correction with tolerance tol2
+//              inner (FP32) solve for the correction, asked to reach what
+//              the outer test still needs, max(tol2, tol ||b|| / (2 ||r||)),
+//              tol2 being the floor that FP32 arithmetic can reach
 //   kRedSum    plain sums written to out[0..NV-1]
 enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2, kRedOuter = 3, kRedSum = 4 };
 constexpr int kRedThreads = 1024;
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(kRedThreads) void cg_reduce_kernel(const double* __
     sc->bnorm2 = r2;  // the inner system's right-hand side is the residual
     sc->rho = rz;
     sc->rnorm2 = r2;
-    sc->tol = tol2;
+    sc->tol = (r2 > 0.0) ? fmax(tol2, 0.5 * tol * sqrt(b2 / r2)) : tol2;
     if (!finite(b2) || !finite(rz) || !finite(r2)) {
       sc->done = kNonFinite;
       sc->outer_done = 0;
