@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "TDGL cell-steps/s incl. Poisson+FEM solves; HBM GB/s vs peak; adjoint/fwd ratio"
-WARM_START_NAMES = {0: "zero", 1: "previous solution", 2: "extrapolated from the last three solutions"}
+WARM_START_NAMES = {0: "zero", 1: "previous solution", 2: "extrapolated from earlier solutions"}
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic (compulsory) HBM bytes per node of one launch of each kernel
@@ -154,7 +154,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warm-start", type=int, default=2, choices=(0, 1, 2),
                     help="initial guess of each solve: 0 zero, 1 previous solution, 2 extrapolated from the "
-                         "last three solutions (default 2)")
+                         "last solutions (default 2)")
+    ap.add_argument("--extrap-order", type=int, default=None,
+                    help="with --warm-start 2: number of earlier solutions the polynomial goes through "
+                         "(0..8; default: the workload's)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without per-launch events (the roofline is then omitted)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing leg")
@@ -175,6 +178,8 @@ def main():
     w = workloads()[args.workload]
     if args.warm_start != w.cfg.warm_start:
         w.cfg = w.cfg.replace(warm_start=args.warm_start)
+    if args.extrap_order is not None:
+        w.cfg = w.cfg.replace(extrap_order=args.extrap_order)
     cfg = w.cfg
     dev = torch.device("cuda:0")
     ctx = pf.Context(cfg, "cuda:0")
@@ -213,7 +218,8 @@ def main():
         "config": {"workload": w.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "cells": cfg.nodes,
                    "integrator": cfg.integrator, "tol_phi": cfg.tol_phi, "tol_u": cfg.tol_u,
                    "electrodes": len(cfg.electrodes), "init": w.init, "seed": w.seed,
-                   "initial_guess": WARM_START_NAMES[int(cfg.warm_start)], "precision": cfg.precision},
+                   "initial_guess": WARM_START_NAMES[int(cfg.warm_start)],
+                   "extrap_order": cfg.extrap_order if cfg.warm_start == 2 else None, "precision": cfg.precision},
         "cg_iters_per_step": {"phi": round(it_phi, 2), "u": round(it_u, 2)},
     }
     if not args.no_kernel_timing:

@@ -100,13 +100,16 @@ typedef struct {
   int32_t maxit;                /* CG iteration cap per solve (> 0) */
   int32_t warm_start;           /* 0: solves start from zero; 1: from the previous
                                    solution (the paper's warm start); 2: from the
-                                   polynomial extrapolation of the last three
-                                   solutions (x, 2x - x1, 3x - 3x1 + x2 as history
-                                   accumulates after pf_set_state/pf_restore_state/
-                                   pf_set_params) */
+                                   polynomial extrapolation to the next step of the
+                                   last solutions (see extrap_order) */
   uint32_t terms;               /* PF_TERM_* mask */
   int32_t nonlocal_every;       /* refresh phi and u every k steps (<= 1: every
                                    step), the paper's Fig. 3d option */
+  int32_t extrap_order;         /* warm_start 2: the guess is the polynomial through
+                                   the last solution and up to extrap_order (0..8)
+                                   earlier ones, x_next = sum_t (-1)^t C(m+1,t+1)
+                                   x_{n-t}; the order grows with the history kept
+                                   since pf_set_state/pf_restore_state/pf_set_params */
 } pf_config;
 
 typedef struct {

@@ -60,9 +60,10 @@ typedef struct {
     int32_t integrator;           /* OR_INT_PC or OR_INT_EULER */
     int32_t maxit;                /* CG iteration cap */
     double tol_phi, tol_u;        /* relative residual tolerances */
-    int32_t warm_start;           /* 0 cold, 1 previous solution, 2 extrapolated from the last three */
+    int32_t warm_start;           /* 0 cold, 1 previous solution, 2 extrapolated from earlier solutions */
     uint32_t terms;               /* OR_TERM_* mask */
     int32_t nonlocal_every;       /* recompute phi and u every k steps (<= 1: every step) */
+    int32_t extrap_order;         /* warm_start 2: extrapolate from up to this many earlier solutions */
 } or_params;
 
 typedef struct {
@@ -851,39 +852,50 @@ int or_set_state(const or_params *p, const double *P, double *V, double *phi, do
 }
 
 /* Initial guess for the next solve from the last solutions (warm_start 2):
- * with x the last solution and h1, h2 the two before it, the guess is the
- * polynomial extrapolation of the available ones to the next step,
- * x, 2x - h1 or 3x - 3h1 + h2; the history then shifts (h2 <- h1 <- x). */
-static void extrapolate(double *x, double *h1, double *h2, int64_t n, int nvalid) {
-    for (int64_t t = 0; t < n; t++) {
-        double g = x[t];
-        if (nvalid == 1) g = 2 * x[t] - h1[t];
-        else if (nvalid >= 2) g = 3 * x[t] - 3 * h1[t] + h2[t];
-        h2[t] = h1[t];
-        h1[t] = x[t];
-        x[t] = g;
+ * with x the last solution and hist[0..m-1] the m solutions before it, newest
+ * first, the guess is the value at the next step of the polynomial through
+ * the m+1 equally spaced solutions,
+ *   x_next = sum_{t=0..m} (-1)^t C(m+1, t+1) x_{n-t}
+ * (m = 0: x; 1: 2x - x1; 2: 3x - 3x1 + x2; ...).  The history then shifts
+ * (the oldest drops out, x becomes the newest). */
+void or_extrapolate(double *x, double *hist, int64_t n, int m, int cap) {
+    double c[16];
+    for (int t = 0; t <= m; t++) {
+        double b = 1;                 /* C(m+1, t+1) */
+        for (int q = 0; q < t + 1; q++) b = b * (m + 1 - q) / (q + 1);
+        c[t] = (t % 2 ? -1.0 : 1.0) * b;
+    }
+    for (int64_t e = 0; e < n; e++) {
+        double g = c[0] * x[e];
+        for (int t = 1; t <= m; t++) g += c[t] * hist[(int64_t)(t - 1) * n + e];
+        for (int t = cap - 1; t > 0; t--) hist[(int64_t)t * n + e] = hist[(int64_t)(t - 1) * n + e];
+        if (cap > 0) hist[e] = x[e];
+        x[e] = g;
     }
 }
 
 /* step0 is the index of the first step (it decides, with nonlocal_every,
  * which steps refresh phi and u).  With warm_start 2 the solution history
- * starts empty at the call (phi and u passed in are the last solutions). */
+ * starts empty at the call (phi and u passed in are the last solutions) and
+ * the extrapolation order grows with it up to extrap_order. */
 int or_step(const or_params *p, double *P, double *V, double *phi, double *u, int32_t nsteps, int64_t step0,
             or_stats *st) {
     int64_t N = nnodes(p), N3 = 3 * N;
+    if (p->warm_start == 2 && (p->extrap_order < 0 || p->extrap_order > 15)) return OR_EINVAL;
     double *Pp = (double *)malloc(sizeof(double) * (size_t)N3);
     double *F = (double *)malloc(sizeof(double) * (size_t)N3);
-    double *hist = p->warm_start == 2 ? (double *)calloc((size_t)(8 * N), sizeof(double)) : NULL;
-    if (!Pp || !F || (p->warm_start == 2 && !hist)) { free(Pp); free(F); free(hist); return OR_ENOMEM; }
+    int cap = p->warm_start == 2 ? (p->extrap_order < 0 ? 0 : p->extrap_order) : 0;
+    double *hist = cap > 0 ? (double *)calloc((size_t)(4 * N * cap), sizeof(double)) : NULL;
+    if (!Pp || !F || (cap > 0 && !hist)) { free(Pp); free(F); free(hist); return OR_ENOMEM; }
     int nvalid = 0;
     int worst = OR_OK;
     for (int32_t s = 0; s < nsteps; s++) {
         int64_t step = step0 + s;
         int refresh = p->nonlocal_every <= 1 || (step % p->nonlocal_every) == 0;
         if (refresh && hist) {
-            if (p->terms & OR_TERM_ELEC) extrapolate(phi, hist, hist + N, N, nvalid);
-            if (p->terms & OR_TERM_ELAS) extrapolate(u, hist + 2 * N, hist + 5 * N, N3, nvalid);
-            if (nvalid < 2) nvalid++;
+            if (p->terms & OR_TERM_ELEC) or_extrapolate(phi, hist, N, nvalid, cap);
+            if (p->terms & OR_TERM_ELAS) or_extrapolate(u, hist + (int64_t)cap * N, N3, nvalid, cap);
+            if (nvalid < cap) nvalid++;
         }
         int rc;
         if (p->integrator == OR_INT_PC) {

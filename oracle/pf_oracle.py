@@ -51,6 +51,7 @@ class OrParams(ctypes.Structure):
         ("warm_start", ctypes.c_int32),
         ("terms", ctypes.c_uint32),
         ("nonlocal_every", ctypes.c_int32),
+        ("extrap_order", ctypes.c_int32),
     ]
 
 
@@ -108,6 +109,7 @@ def lib():
             "or_adjoint_step": (ctypes.c_int, [P, d, d, d, d, d, ctypes.c_double, d]),
             "or_adjoint_initial_rate": (ctypes.c_int, [P, d, d, d, d, ctypes.c_double, d]),
             "or_top_ghost": (ctypes.c_double, [P, ctypes.c_int, ctypes.c_int]),
+            "or_extrapolate": (None, [d, d, ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -159,6 +161,7 @@ class Oracle:
         p.warm_start = int(cfg.warm_start)
         p.terms = cfg.terms
         p.nonlocal_every = cfg.nonlocal_every
+        p.extrap_order = cfg.extrap_order
         self.p = p
         self.pp = ctypes.byref(p)
         self.N = cfg.nodes
@@ -297,6 +300,13 @@ class Oracle:
         st = self.lib.or_set_state(self.pp, _ptr(P), _ptr(V), _ptr(phi), _ptr(u), ctypes.byref(s))
         _check(st, "set_state", allow_noconv=True)
         return V, phi, u, s.as_dict()
+
+    @staticmethod
+    def extrapolate(x, hist, m):
+        """The warm-start guess from x and the m newest rows of hist (newest
+        first), in place; hist shifts and x becomes its newest row."""
+        assert x.dtype == np.float64 and hist.dtype == np.float64 and hist.shape[1:] == x.shape
+        lib().or_extrapolate(_ptr(x), _ptr(hist), x.size, m, hist.shape[0])
 
     def step(self, P, V, phi, u, nsteps, step0=0):
         """Advances (P, V, phi, u) in place by nsteps; returns the stats."""

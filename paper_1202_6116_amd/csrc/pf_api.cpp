@@ -22,14 +22,14 @@ namespace pf {
 
 // kernel launchers (pf_kernels.hip)
 int node_blocks(const Dims& d);
-TileMap make_tile_map(const Dims& d);
+TileMap make_tile_map(const Dims& d, int ty, int target);
 template <typename T> hipError_t launch_fill(T* a, int64_t n, T v, hipStream_t s);
 template <typename T, typename U> hipError_t launch_convert(const T* a, U* b, int64_t n, hipStream_t s);
 template <typename T> hipError_t launch_cg_finish(T* x, const T* p, int64_t n, const CgScalars* sc, hipStream_t s);
 hipError_t launch_cg_reduce(const double* partials, int nblocks, int nv, CgScalars* sc, int mode, double tol,
                             int maxit, hipStream_t s, double tol2, double* out);
 hipError_t launch_refine_update(double* x64, float* x32, const float* d, int64_t n, hipStream_t s);
-hipError_t launch_extrapolate(double* x, double* h1, double* h2, int64_t n, int nvalid, hipStream_t s);
+hipError_t launch_extrapolate(double* x, const ExtrapRing& ring, int64_t n, hipStream_t s);
 template <typename T, typename S, typename R>
 hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
                                 int with_bc, const T* ghost_top, T phi_bottom, const T* x, R* r, R* p, R* dz,
@@ -205,7 +205,8 @@ struct Layout {
   size_t phi_bc, basis;        // boundary potential and electrode basis (FP64)
   size_t pr, pp[2], fr, fp[2]; // CG vectors, sized for FP64 (FP32 solves use half)
   size_t dphi, du;             // refinement corrections (FP32)
-  size_t hist;                 // last solutions for extrapolated warm starts (8N doubles)
+  size_t hist;                 // ring of earlier solutions for extrapolated warm starts
+                               // (extrap_order slots of N (phi) then extrap_order of 3N (u))
   size_t scratch[8];           // 3N doubles each: adjoint, energy, conversions
   size_t tables, scalars, result, partials;
   size_t total;
@@ -243,7 +244,7 @@ Layout make_layout(const pf_config& c, int npartials) {
   for (int b = 0; b < 2; b++) L.fp[b] = take(3 * N * 8);
   L.dphi = take(N * 4);
   L.du = take(3 * N * 4);
-  L.hist = c.warm_start == 2 ? take(8 * N * 8) : 0;
+  L.hist = c.warm_start == 2 && c.extrap_order > 0 ? take(4 * N * 8 * (size_t)c.extrap_order) : 0;
   for (int t = 0; t < 8; t++) L.scratch[t] = take(3 * N * 8);
   L.tables = take(sizeof(FemTables));
   L.scalars = take(sizeof(CgScalars) * kNumScalars);
@@ -287,7 +288,8 @@ struct pf_ctx {
   size_t ws_bytes;
   hipStream_t stream;
   int nblocks;              // node-kernel blocks
-  pf::TileMap tm;           // tile-kernel geometry
+  pf::TileMap tm_p;         // tiles of the Poisson iteration kernels (64 x 4)
+  pf::TileMap tm_f;         // tiles of the FEM iteration kernels (64 x 4)
   int npartials;            // partial slots per solver (max of both block counts)
   pf::CgScalars* host_sc;   // pinned read-back buffer
   double* host_res;         // pinned read-back of reduction results
@@ -296,7 +298,8 @@ struct pf_ctx {
   bool phi_bc_valid;
   bool basis_valid;
   bool adj_warm;            // adjoint scratch holds earlier adjoint solutions
-  int hist_valid;           // solutions held for extrapolated warm starts (0..2)
+  int hist_valid;           // solutions held for extrapolated warm starts (0..extrap_order)
+  int hist_head;            // ring slot that the next stored solution goes to
   int64_t step;
   int cur;                  // which P/V buffer is current
   int pred[pf::kPredCount];
@@ -378,6 +381,7 @@ pf_status validate(const pf_config* c, std::string* why) {
   if (!(c->tol_phi > 0) || !(c->tol_u > 0)) return bad("tolerances must be > 0");
   if (c->maxit <= 0) return bad("maxit must be > 0");
   if (c->warm_start < 0 || c->warm_start > 2) return bad("warm_start must be 0, 1 or 2");
+  if (c->extrap_order < 0 || c->extrap_order > kMaxExtrap) return bad("extrap_order must be in 0..8");
   if (c->terms & ~(uint32_t)PF_TERM_ALL) return bad("unknown term bits");
   if (!(c->C11 > 0) || !(c->C44 > 0) || !(c->C11 > std::fabs(c->C12)) || !(c->C11 + 2 * c->C12 > 0))
     return bad("stiffness must be positive definite");
@@ -539,13 +543,13 @@ std::function<hipError_t(int)> poisson_iteration(pf_ctx* c, const Coefs<T>& cf, 
     CgScalars* sc = dev_sc(c, 0);
     double* part = dev_partials(c, 0);
     hipError_t e = timed(c, PF_KC_POISSON_A, 0, k, [&] {
-      return launch_poisson_cg_a<T>(d, c->tm, cf, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
+      return launch_poisson_cg_a<T>(d, c->tm_p, cf, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
     });
-    if (e == hipSuccess) e = reduce(c, part, c->tm.nblocks, 1, 0, kRedAlpha, tol, 0, nullptr, 0, k);
+    if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 1, 0, kRedAlpha, tol, 0, nullptr, 0, k);
     if (e == hipSuccess)
       e = timed(c, PF_KC_POISSON_B, 0, k,
-                [&] { return launch_poisson_cg_b<T>(d, c->tm, cf, pb[(k + 1) & 1], r, sc, part, c->stream); });
-    if (e == hipSuccess) e = reduce(c, part, c->tm.nblocks, 2, 0, kRedBeta, tol, 0, nullptr, 0, k);
+                [&] { return launch_poisson_cg_b<T>(d, c->tm_p, cf, pb[(k + 1) & 1], r, sc, part, c->stream); });
+    if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 2, 0, kRedBeta, tol, 0, nullptr, 0, k);
     return e;
   };
 }
@@ -558,13 +562,13 @@ std::function<hipError_t(int)> fem_iteration(pf_ctx* c, T* r, T* const pb[2], T*
     CgScalars* sc = dev_sc(c, 1);
     double* part = dev_partials(c, 1);
     hipError_t e = timed(c, PF_KC_FEM_A, 1, k, [&] {
-      return launch_fem_cg_a<T>(d, c->tm, tb, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
+      return launch_fem_cg_a<T>(d, c->tm_f, tb, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
     });
-    if (e == hipSuccess) e = reduce(c, part, c->tm.nblocks, 1, 1, kRedAlpha, tol, 0, nullptr, 1, k);
+    if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 1, 1, kRedAlpha, tol, 0, nullptr, 1, k);
     if (e == hipSuccess)
       e = timed(c, PF_KC_FEM_B, 1, k,
-                [&] { return launch_fem_cg_b<T>(d, c->tm, tb, pb[(k + 1) & 1], r, sc, part, c->stream); });
-    if (e == hipSuccess) e = reduce(c, part, c->tm.nblocks, 2, 1, kRedBeta, tol, 0, nullptr, 1, k);
+                [&] { return launch_fem_cg_b<T>(d, c->tm_f, tb, pb[(k + 1) & 1], r, sc, part, c->stream); });
+    if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 2, 1, kRedBeta, tol, 0, nullptr, 1, k);
     return e;
   };
 }
@@ -700,19 +704,39 @@ void stats_add(pf_step_stats* st, int which, const SolveResult& r) {
 
 // warm_start 2: replaces the state's phi and u by their extrapolation from
 // the last solutions (the first solves after a state change use what is
-// available).
+// available: the order grows by one per refresh up to extrap_order).  The
+// weights of the polynomial through m + 1 equally spaced values, evaluated
+// one step past the newest, are (-1)^t C(m+1, t+1), t = 0..m.
 pf_status extrapolate_state(pf_ctx* c) {
+  const int cap = c->cfg.extrap_order;
+  const int m = std::min(c->hist_valid, cap);
   const int64_t N = c->dims.N;
-  double* h = at<double>(c, c->lay.hist);
+  ExtrapRing ring[2];
+  for (int f = 0; f < 2; f++) {
+    ExtrapRing& r = ring[f];
+    const int64_t len = f == 0 ? N : 3 * N;
+    double* base = cap > 0 ? at<double>(c, c->lay.hist) + (f == 0 ? 0 : (int64_t)cap * N) : nullptr;
+    r.m = m;
+    for (int t = 0; t <= m; t++) {
+      double b = 1;
+      for (int q = 1; q <= t + 1; q++) b = b * (m + 2 - q) / q;
+      r.c[t] = (t & 1) ? -b : b;
+    }
+    for (int t = 0; t < m; t++) r.h[t] = base + (int64_t)((c->hist_head - 1 - t + 2 * cap) % cap) * len;
+    for (int t = m; t < kMaxExtrap; t++) r.h[t] = nullptr;
+    r.dest = cap > 0 ? base + (int64_t)c->hist_head * len : nullptr;
+  }
+  if (cap == 0) return PF_OK;  // the previous solution is the guess
   if (c->cfg.terms & PF_TERM_ELEC)
     PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-      return launch_extrapolate(at<double>(c, c->lay.phi), h, h + N, N, c->hist_valid, c->stream);
+      return launch_extrapolate(at<double>(c, c->lay.phi), ring[0], N, c->stream);
     }));
   if (c->cfg.terms & PF_TERM_ELAS)
     PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-      return launch_extrapolate(at<double>(c, c->lay.u), h + 2 * N, h + 5 * N, 3 * N, c->hist_valid, c->stream);
+      return launch_extrapolate(at<double>(c, c->lay.u), ring[1], 3 * N, c->stream);
     }));
-  if (c->hist_valid < 2) c->hist_valid++;
+  c->hist_head = (c->hist_head + 1) % cap;
+  if (c->hist_valid < cap) c->hist_valid++;
   return PF_OK;
 }
 
@@ -975,6 +999,19 @@ pf_status energy_t(pf_ctx* c, const S* P, double out[5]) {
 }  // namespace
 }  // namespace pf
 
+namespace pf {
+namespace {
+// Tile grids of 64 x 4-node tiles sized to what stays resident at once, four
+// 256-thread blocks per CU (the FEM iteration kernels are capped at 128
+// VGPRs for that; their FP64 ring takes 28.5 KB of LDS).
+TileMap poisson_tiles(const pf_config&, const Dims& d) { return make_tile_map(d, kBY, 1024); }
+TileMap fem_tiles(const pf_config&, const Dims& d) { return make_tile_map(d, kBY, 1024); }
+int partial_slots(const pf_config& c, const Dims& d) {
+  return std::max(node_blocks(d), std::max(poisson_tiles(c, d).nblocks, fem_tiles(c, d).nblocks));
+}
+}  // namespace
+}  // namespace pf
+
 using namespace pf;
 
 extern "C" {
@@ -999,7 +1036,7 @@ pf_status pf_workspace_size(const pf_config* cfg, size_t* bytes) {
   pf_status s = validate(cfg, nullptr);
   if (s != PF_OK) return s;
   Dims d{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz, (int64_t)cfg->nx * cfg->ny};
-  *bytes = make_layout(*cfg, std::max(node_blocks(d), make_tile_map(d).nblocks)).total;
+  *bytes = make_layout(*cfg, partial_slots(*cfg, d)).total;
   return PF_OK;
 }
 
@@ -1021,8 +1058,9 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->cfg.electrodes = c->electrodes.data();
   c->dims = Dims{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz, (int64_t)cfg->nx * cfg->ny};
   c->nblocks = node_blocks(c->dims);
-  c->tm = make_tile_map(c->dims);
-  c->npartials = std::max(c->nblocks, c->tm.nblocks);
+  c->tm_p = poisson_tiles(*cfg, c->dims);
+  c->tm_f = fem_tiles(*cfg, c->dims);
+  c->npartials = partial_slots(*cfg, c->dims);
   c->lay = make_layout(*cfg, c->npartials);
   if (bytes < c->lay.total) {
     fprintf(stderr, "pf_init: workspace of %zu bytes, %zu needed\n", bytes, c->lay.total);
@@ -1034,6 +1072,7 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->stream = static_cast<hipStream_t>(stream);
   c->have_state = c->phi_bc_valid = c->basis_valid = c->adj_warm = false;
   c->hist_valid = 0;
+  c->hist_head = 0;
   c->step = 0;
   c->cur = 0;
   for (int t = 0; t < kPredCount; t++) c->pred[t] = 16;
@@ -1085,6 +1124,7 @@ pf_status pf_set_state(pf_ctx* c, const void* P, const void* phi0, const void* u
   c->cur = 0;
   c->step = 0;
   c->hist_valid = 0;
+  c->hist_head = 0;
   void* Pc = c->ws + c->lay.P[0];
   void* Vc = c->ws + c->lay.V[0];
   double* phi = at<double>(c, c->lay.phi);
@@ -1118,6 +1158,7 @@ pf_status pf_restore_state(pf_ctx* c, const void* P, const void* V, const void* 
   const size_t es = state_bytes(c);
   c->cur = 0;
   c->hist_valid = 0;
+  c->hist_head = 0;
   PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.P[0], P, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
   PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.V[0], V, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
   PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.phi), phi, N * 8, hipMemcpyDeviceToDevice, c->stream));
@@ -1247,6 +1288,7 @@ pf_status pf_set_params(pf_ctx* c, const double* volts, double a1) {
     }
     c->phi_bc_valid = false;
     c->hist_valid = 0;
+    c->hist_head = 0;
     PF_TRY(upload_ghosts(c));
   }
   return PF_OK;

@@ -62,10 +62,22 @@ struct CgScalars {
 
 enum CgDone { kRunning = 0, kConverged = 1, kMaxIt = 2, kNonFinite = 3 };
 
-// Tiles of the z-marching kernels: ntx x nty columns of 64 x 4 nodes, each
+// Tiles of the z-marching kernels: ntx x nty columns of 64 x ty nodes, each
 // cut into nkz chunks of kz planes; one block per (column, chunk).
 struct TileMap {
-  int ntx, nty, kz, nkz, nblocks;
+  int ty, ntx, nty, kz, nkz, nblocks;
+};
+
+// Polynomial extrapolation of a solution to the next step from the current
+// value and up to kMaxExtrap earlier ones (newest first), with the
+// coefficients of the interpolating polynomial evaluated one step ahead;
+// the current value then replaces the oldest (or the next free) ring slot.
+constexpr int kMaxExtrap = 8;
+struct ExtrapRing {
+  const double* h[kMaxExtrap];  // earlier solutions, newest first (m used)
+  double* dest;                 // ring slot that receives the current value
+  double c[kMaxExtrap + 1];     // c[0] for the current value, c[t] for h[t-1]
+  int m;
 };
 
 // Per-call description of the node grid.

@@ -72,7 +72,15 @@ __device__ __forceinline__ bool converged(double rnorm2, double bnorm2, double t
 // ---------------------------------------------------------------------------
 // Tile geometry of the z-marching kernels
 // ---------------------------------------------------------------------------
-constexpr int kHX = kBX + 2, kHY = kBY + 2, kHP = kHX * kHY;
+// A tile is 64 x TY nodes of a plane (TY = 4: one node per thread; TY = 8:
+// two consecutive rows per thread), staged with a one-node halo.
+constexpr int kHX = kBX + 2;
+template <int TY>
+struct Halo {
+  static constexpr int HY = TY + 2;                        // halo rows
+  static constexpr int HP = kHX * HY;                      // halo points
+  static constexpr int NPT = (HP + kThreads - 1) / kThreads;  // points per thread
+};
 
 // Logical tile of this block: work-groups go round-robin to the 8 XCDs, so
 // XCD x receives physical blocks x, x+8, ...; they are given the contiguous
@@ -95,7 +103,7 @@ __device__ __forceinline__ TileCoord tile_coord(const Dims& d, const TileMap& tm
   const int ty = (lid / tm.ntx) % tm.nty;
   const int kc = lid / (tm.ntx * tm.nty);
   t.i0 = tx * kBX;
-  t.j0 = ty * kBY;
+  t.j0 = ty * tm.ty;
   t.k0 = kc * tm.kz;
   t.k1 = min(d.nz, t.k0 + tm.kz);
   t.lid = lid;
@@ -104,27 +112,27 @@ __device__ __forceinline__ TileCoord tile_coord(const Dims& d, const TileMap& tm
 
 __device__ __forceinline__ int slot_of(int k) { return (k + 3) % 3; }
 
-// Software-pipelined staging of tile planes.  Each thread owns (up to) two
-// of the kHP halo-plane points.  stage_fetch issues the global loads of a
-// plane into registers (raw values, RAW per point); stage_store combines
-// them into the staged values (NC per point) and writes the ring slot.  The
-// z-march fetches plane k+2 while plane k is being computed, so the loads of
-// a block overlap its own arithmetic (the barrier waits for LDS only).
-static_assert(kHP <= 2 * kThreads, "two halo points per thread");
-
-template <typename T, int RAW>
+// Software-pipelined staging of tile planes.  Each thread owns NPT of the
+// halo-plane points.  stage_fetch issues the global loads of a plane into
+// registers (raw values, RAW per point); stage_store combines them into the
+// staged values (NC per point) and writes the ring slot.  The z-march
+// fetches plane k+2 while plane k is being computed, so the loads of a block
+// overlap its own arithmetic (the barrier waits for LDS only).
+template <typename T, int RAW, int NPT>
 struct Stage {
-  T v[2][RAW];
+  T v[NPT][RAW];
 };
 
-template <typename T, int RAW, typename Fetch>
-__device__ __forceinline__ void stage_fetch(Stage<T, RAW>& st, const Dims& d, int i0, int j0, int k, Fetch f) {
+template <int TY, typename T, int RAW, int NPT, typename Fetch>
+__device__ __forceinline__ void stage_fetch(Stage<T, RAW, NPT>& st, const Dims& d, int i0, int j0, int k,
+                                            Fetch f) {
+  using H = Halo<TY>;
 #pragma unroll
-  for (int q = 0; q < 2; q++) {
+  for (int q = 0; q < NPT; q++) {
     const int t = tid_flat() + q * kThreads;
 #pragma unroll
     for (int c = 0; c < RAW; c++) st.v[q][c] = 0;
-    if (t < kHP) {
+    if (t < H::HP) {
       const int hx = t % kHX, hy = t / kHX;
       int gi = i0 + hx - 1, gj = j0 + hy - 1;
       if (k >= 0 && k < d.nz && gi >= -1 && gi <= d.nx && gj >= -1 && gj <= d.ny) {
@@ -136,13 +144,15 @@ __device__ __forceinline__ void stage_fetch(Stage<T, RAW>& st, const Dims& d, in
   }
 }
 
-template <typename T, int NC, int RAW, typename Comb>
-__device__ __forceinline__ void stage_store(T (&ring)[3][NC][kHY][kHX], const Stage<T, RAW>& st, int k, Comb comb) {
+template <int TY, typename T, int NC, int RAW, int NPT, typename Comb>
+__device__ __forceinline__ void stage_store(T (&ring)[3][NC][TY + 2][kHX], const Stage<T, RAW, NPT>& st, int k,
+                                            Comb comb) {
+  using H = Halo<TY>;
   const int s = slot_of(k);
 #pragma unroll
-  for (int q = 0; q < 2; q++) {
+  for (int q = 0; q < NPT; q++) {
     const int t = tid_flat() + q * kThreads;
-    if (t < kHP) {
+    if (t < H::HP) {
       const int hx = t % kHX, hy = t / kHX;
       T out[NC];
       comb(k, st.v[q], out);
@@ -295,20 +305,20 @@ __global__ void cg_finish_kernel(T* x, const T* p, int64_t n, const CgScalars* s
   for (; t < n; t += stride) x[t] = zero ? (T)0 : x[t] + alpha * p[t];
 }
 
-// Initial guess for the next solve from the last solutions: with x the last
-// solution and h1, h2 the two before it, x becomes the polynomial
-// extrapolation of the nvalid+1 available ones (x, 2x - h1, 3x - 3h1 + h2)
-// and the history shifts (h2 <- h1 <- x).
-__global__ void extrapolate_kernel(double* x, double* h1, double* h2, int64_t n, int nvalid) {
+// Initial guess for the next solve: x (the last solution) becomes the value
+// one step ahead of the polynomial through x and the M earlier solutions of
+// the ring (weights from the host), and x is stored into the ring slot that
+// drops out.  One read of x and of each history field, two writes.
+template <int M>
+__global__ void extrapolate_kernel(double* x, ExtrapRing ring, int64_t n) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; t < n; t += stride) {
-    const double a = x[t], b = h1[t];
-    double g = a;
-    if (nvalid == 1) g = 2 * a - b;
-    else if (nvalid >= 2) g = 3 * a - 3 * b + h2[t];
-    h2[t] = b;
-    h1[t] = a;
+    const double a = x[t];
+    double g = ring.c[0] * a;
+#pragma unroll
+    for (int k = 0; k < M; k++) g += ring.c[k + 1] * ring.h[k][t];
+    ring.dest[t] = a;
     x[t] = g;
   }
 }
@@ -385,7 +395,8 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
                                                                 T* __restrict__ p_new, T* __restrict__ x,
                                                                 const CgScalars* sc, double* partials) {
   if (sc->done) return;
-  __shared__ T ring[3][1][kHY][kHX];
+  constexpr int TY = kBY;
+  __shared__ T ring[3][1][TY + 2][kHX];
   const T beta = (T)sc->beta, alpha = (T)sc->alpha, w = cf.inv_diag_poisson, c6 = cf.eps_over_h2;
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
@@ -397,12 +408,12 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
     raw[1] = p_old[m];
   };
   auto comb = [&](int, const T* raw, T* out) { out[0] = raw[0] * w + beta * raw[1]; };
-  Stage<T, 2> st;
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
-  stage_store(ring, st, tc.k0 - 1, comb);
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0, fetch);
-  stage_store(ring, st, tc.k0, comb);
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  Stage<T, 2, Halo<TY>::NPT> st;
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store<TY>(ring, st, tc.k0 - 1, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store<TY>(ring, st, tc.k0, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
   T cpo = 0, cx = 0;  // centre p_old, x of the plane being computed
   if (valid) {
     cpo = p_old[col + d.plane * tc.k0];
@@ -410,8 +421,8 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
   }
   double acc = 0.0;
   for (int k = tc.k0; k < tc.k1; k++) {
-    stage_store(ring, st, k + 1, comb);
-    if (k + 2 <= tc.k1) stage_fetch(st, d, tc.i0, tc.j0, k + 2, fetch);
+    stage_store<TY>(ring, st, k + 1, comb);
+    if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
     T npo = 0, nx_ = 0;
     if (valid && k + 1 < tc.k1) {
       npo = p_old[col + d.plane * (k + 1)];
@@ -443,7 +454,8 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_b_kernel(Dims d, TileMap 
                                                                 const T* __restrict__ p, T* __restrict__ r,
                                                                 const CgScalars* sc, double* partials) {
   if (sc->done) return;
-  __shared__ T ring[3][1][kHY][kHX];
+  constexpr int TY = kBY;
+  __shared__ T ring[3][1][TY + 2][kHX];
   const T alpha = (T)sc->alpha, w = cf.inv_diag_poisson, c6 = cf.eps_over_h2;
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
@@ -452,17 +464,17 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_b_kernel(Dims d, TileMap 
   const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
   auto fetch = [&](int64_t m, int, T* raw) { raw[0] = p[m]; };
   auto comb = [&](int, const T* raw, T* out) { out[0] = raw[0]; };
-  Stage<T, 1> st;
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
-  stage_store(ring, st, tc.k0 - 1, comb);
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0, fetch);
-  stage_store(ring, st, tc.k0, comb);
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  Stage<T, 1, Halo<TY>::NPT> st;
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store<TY>(ring, st, tc.k0 - 1, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store<TY>(ring, st, tc.k0, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
   T cr = valid ? r[col + d.plane * tc.k0] : (T)0;
   double a0 = 0.0, a1 = 0.0;
   for (int k = tc.k0; k < tc.k1; k++) {
-    stage_store(ring, st, k + 1, comb);
-    if (k + 2 <= tc.k1) stage_fetch(st, d, tc.i0, tc.j0, k + 2, fetch);
+    stage_store<TY>(ring, st, k + 1, comb);
+    if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
     const T nr = (valid && k + 1 < tc.k1) ? r[col + d.plane * (k + 1)] : (T)0;
     __syncthreads();
     if (valid) {
@@ -670,7 +682,8 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
                                                             T* __restrict__ p_new, T* __restrict__ x,
                                                             const CgScalars* sc, double* partials) {
   if (sc->done) return;
-  __shared__ T ring[3][3][kHY][kHX];
+  constexpr int TY = kBY;
+  __shared__ T ring[3][3][TY + 2][kHX];
   const T beta = (T)sc->beta, alpha = (T)sc->alpha;
   const T w_int = (T)tb->inv_diag[0], w_top = (T)tb->inv_diag[1];
   const TileCoord tc = tile_coord(d, tm);
@@ -705,18 +718,18 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
       }
     }
   };
-  Stage<T, 6> st;
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
-  stage_store(ring, st, tc.k0 - 1, comb);
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0, fetch);
-  stage_store(ring, st, tc.k0, comb);
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  Stage<T, 6, Halo<TY>::NPT> st;
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store<TY>(ring, st, tc.k0 - 1, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store<TY>(ring, st, tc.k0, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
   T cv[6];
   centre(tc.k0, cv);
   double acc = 0.0;
   for (int k = tc.k0; k < tc.k1; k++) {
-    stage_store(ring, st, k + 1, comb);
-    if (k + 2 <= tc.k1) stage_fetch(st, d, tc.i0, tc.j0, k + 2, fetch);
+    stage_store<TY>(ring, st, k + 1, comb);
+    if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
     T nv[6];
     centre(k + 1, nv);
     __syncthreads();
@@ -753,7 +766,8 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_b_kernel(Dims d, TileMap t
                                                             const T* __restrict__ p, T* __restrict__ r,
                                                             const CgScalars* sc, double* partials) {
   if (sc->done) return;
-  __shared__ T ring[3][3][kHY][kHX];
+  constexpr int TY = kBY;
+  __shared__ T ring[3][3][TY + 2][kHX];
   const T alpha = (T)sc->alpha;
   const T w_int = (T)tb->inv_diag[0], w_top = (T)tb->inv_diag[1];
   const TileCoord tc = tile_coord(d, tm);
@@ -780,18 +794,18 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_b_kernel(Dims d, TileMap t
       for (int c = 0; c < 3; c++) cv[c] = r[c * N + n];
     }
   };
-  Stage<T, 3> st;
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
-  stage_store(ring, st, tc.k0 - 1, comb);
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0, fetch);
-  stage_store(ring, st, tc.k0, comb);
-  stage_fetch(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  Stage<T, 3, Halo<TY>::NPT> st;
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store<TY>(ring, st, tc.k0 - 1, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store<TY>(ring, st, tc.k0, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
   T cv[3];
   centre(tc.k0, cv);
   double a0 = 0.0, a1 = 0.0;
   for (int k = tc.k0; k < tc.k1; k++) {
-    stage_store(ring, st, k + 1, comb);
-    if (k + 2 <= tc.k1) stage_fetch(st, d, tc.i0, tc.j0, k + 2, fetch);
+    stage_store<TY>(ring, st, k + 1, comb);
+    if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
     T nv[3];
     centre(k + 1, nv);
     __syncthreads();
@@ -1221,17 +1235,19 @@ int node_blocks(const Dims& d) {
   return (int)(g.x * g.y * g.z);
 }
 
-// z-chunk length of the tile kernels: long enough that every block stays
-// resident (the whole grid in one round of about 4 blocks per CU), 4..64
-// planes.  PF_TILE_KZ overrides it (a tuning knob; results do not depend on
-// it beyond rounding order).
-TileMap make_tile_map(const Dims& d) {
+// Tile map for tiles of 64 x ty nodes: the z-chunk length is chosen so that
+// the grid has about `target` blocks (the number that stays resident on the
+// chip at once), chunks of at least 4 planes.  PF_TILE_KZ overrides the
+// chunk length (a tuning knob; results do not depend on it beyond rounding
+// order).
+TileMap make_tile_map(const Dims& d, int ty, int target) {
   TileMap t;
+  t.ty = ty;
   t.ntx = (d.nx + kBX - 1) / kBX;
-  t.nty = (d.ny + kBY - 1) / kBY;
+  t.nty = (d.ny + ty - 1) / ty;
   const int64_t cols = (int64_t)t.ntx * t.nty;
-  int64_t kz = (int64_t)d.nz * cols / 1024;
-  kz = kz < 4 ? 4 : (kz > 64 ? 64 : kz);
+  int64_t kz = ((int64_t)d.nz * cols + target - 1) / target;
+  if (kz < 4) kz = 4;
   if (const char* env = getenv("PF_TILE_KZ")) {
     const long v = strtol(env, nullptr, 10);
     if (v >= 1 && v <= 4096) kz = v;
@@ -1272,8 +1288,20 @@ hipError_t launch_cg_reduce(const double* partials, int nblocks, int nv, CgScala
   return hipGetLastError();
 }
 
-hipError_t launch_extrapolate(double* x, double* h1, double* h2, int64_t n, int nvalid, hipStream_t s) {
-  extrapolate_kernel<<<flat_blocks(n), 256, 0, s>>>(x, h1, h2, n, nvalid);
+hipError_t launch_extrapolate(double* x, const ExtrapRing& ring, int64_t n, hipStream_t s) {
+  const int nb = flat_blocks(n);
+  switch (ring.m) {
+    case 0: extrapolate_kernel<0><<<nb, 256, 0, s>>>(x, ring, n); break;
+    case 1: extrapolate_kernel<1><<<nb, 256, 0, s>>>(x, ring, n); break;
+    case 2: extrapolate_kernel<2><<<nb, 256, 0, s>>>(x, ring, n); break;
+    case 3: extrapolate_kernel<3><<<nb, 256, 0, s>>>(x, ring, n); break;
+    case 4: extrapolate_kernel<4><<<nb, 256, 0, s>>>(x, ring, n); break;
+    case 5: extrapolate_kernel<5><<<nb, 256, 0, s>>>(x, ring, n); break;
+    case 6: extrapolate_kernel<6><<<nb, 256, 0, s>>>(x, ring, n); break;
+    case 7: extrapolate_kernel<7><<<nb, 256, 0, s>>>(x, ring, n); break;
+    case 8: extrapolate_kernel<8><<<nb, 256, 0, s>>>(x, ring, n); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

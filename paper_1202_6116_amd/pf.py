@@ -58,6 +58,7 @@ class pf_config(ctypes.Structure):
         ("tol_phi", ctypes.c_double), ("tol_u", ctypes.c_double),
         ("maxit", ctypes.c_int32), ("warm_start", ctypes.c_int32),
         ("terms", ctypes.c_uint32), ("nonlocal_every", ctypes.c_int32),
+        ("extrap_order", ctypes.c_int32),
     ]
 
 
@@ -141,6 +142,7 @@ def make_config(cfg: PFConfig):
     c.warm_start = int(cfg.warm_start)
     c.terms = cfg.terms
     c.nonlocal_every = cfg.nonlocal_every
+    c.extrap_order = cfg.extrap_order
     return c, els
 
 

@@ -73,7 +73,8 @@ class PFConfig:
     tol_phi: float = 1e-10
     tol_u: float = 1e-10
     maxit: int = 5000
-    warm_start: int = 1             # 0 cold, 1 previous solution, 2 extrapolated from the last three
+    warm_start: int = 1             # 0 cold, 1 previous solution, 2 extrapolated from earlier solutions
+    extrap_order: int = 4           # warm_start 2: polynomial through up to 1 + this many solutions
     terms: int = TERM_ALL
     nonlocal_every: int = 1         # recompute phi and u every k steps
 

@@ -256,9 +256,10 @@ def test_lateral_256_full_size_properties(pf, oracle_mod):
     assert rel(F, ref) < 1e-12
 
 
-def test_extrapolated_warm_start_matches_oracle(pf, oracle_mod):
-    cfg = ragged_cfg(warm_start=2)
-    print("case: trajectory 70x13x6 extrapolated warm start", flush=True)
+@pytest.mark.parametrize("order", [0, 2, 5, 8])
+def test_extrapolated_warm_start_matches_oracle(pf, oracle_mod, order):
+    cfg = ragged_cfg(warm_start=2, extrap_order=order)
+    print(f"case: trajectory 70x13x6 extrapolated warm start order {order}", flush=True)
     P0 = domain_polarisation(cfg, 17, block=4)
     o = oracle_mod.Oracle(cfg)
     P = P0.copy()
@@ -272,3 +273,23 @@ def test_extrapolated_warm_start_matches_oracle(pf, oracle_mod):
     assert rel(host(Pg), P) < TOL
     assert rel(host(phig), phi) < TOL
     assert rel(host(ug), u) < TOL
+
+
+def test_extrapolation_history_spans_step_calls(pf):
+    """The solution history of the extrapolated warm start is kept across
+    pf_step calls, so split and single runs agree bitwise; set_state starts
+    it afresh."""
+    cfg = ragged_cfg(warm_start=2, extrap_order=6, tol_phi=1e-9, tol_u=1e-9)
+    P0 = dev(domain_polarisation(cfg, 18, block=4))
+    a = pf.Context(cfg)
+    a.set_state(P0)
+    sa = a.step(12)
+    b = pf.Context(cfg)
+    b.set_state(P0)
+    sb = b.step(5)
+    sb2 = b.step(7)
+    assert torch.equal(a.get_state()[0], b.get_state()[0])
+    assert sa["iters_phi"] == sb["iters_phi"] + sb2["iters_phi"]
+    b.set_state(P0)
+    sc = b.step(5)
+    assert sc["iters_phi"] == sb["iters_phi"] and sc["iters_u"] == sb["iters_u"]

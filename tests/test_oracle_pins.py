@@ -524,3 +524,47 @@ def test_extrapolated_warm_start_same_solution_fewer_iterations(oracle_mod):
         res[ws] = (P, st["iters_phi"] + st["iters_u"])
     np.testing.assert_allclose(res[2][0], res[1][0], rtol=0, atol=1e-8)
     assert res[2][1] < 0.9 * res[1][1], (res[1][1], res[2][1])
+
+
+@pytest.mark.parametrize("m", [0, 1, 2, 3, 5, 8])
+def test_extrapolation_reproduces_polynomials(oracle_mod, m):
+    """The warm-start guess from the last m + 1 solutions is the polynomial
+    through them taken one step ahead: it reproduces every polynomial in the
+    step index of degree <= m, and for t^(m+1) it misses by the (m+1)-th
+    forward difference, (m+1)!.  The history then shifts by one step."""
+    from math import factorial
+    cap = 8
+    t0 = 3
+    for deg, miss in [(d, 0.0) for d in range(m + 1)] + [(m + 1, float(factorial(m + 1)))]:
+        coef = np.array([0.5, -1.25, 2.0])
+        seq = [coef * (t0 + k) ** deg for k in range(m + 1)]       # values at steps t0 .. t0+m
+        x = seq[-1].copy()
+        hist = np.zeros((cap, 3))
+        for k in range(m):
+            hist[k] = seq[-2 - k]
+        oracle_mod.Oracle.extrapolate(x, hist, m)
+        want = coef * (t0 + m + 1) ** deg
+        np.testing.assert_allclose(want - x, coef * miss, rtol=1e-12, atol=1e-9 * np.abs(want).max())
+        np.testing.assert_array_equal(hist[0], seq[-1])
+        for k in range(min(m, cap - 1)):
+            np.testing.assert_array_equal(hist[k + 1], seq[-2 - k])
+
+
+def test_higher_order_extrapolation_cuts_iterations(oracle_mod):
+    """On a smooth trajectory more history gives a better first guess: the
+    iteration counts fall as the extrapolation order grows, and every order
+    reaches the same trajectory to the solver tolerance."""
+    base = PFConfig(nx=24, ny=16, nz=6, tol_phi=1e-11, tol_u=1e-11, warm_start=2,
+                    electrodes=[Electrode(2, 8, 0, 16, 2.0), Electrode(14, 20, 0, 16, -2.0)])
+    P0 = domain_polarisation(base, 12, block=4)
+    its, Ps = [], []
+    for m in (1, 3, 5):
+        o = oracle_mod.Oracle(base.replace(extrap_order=m))
+        P = P0.copy()
+        V, phi, u, _ = o.set_state(P)
+        st = o.step(P, V, phi, u, 16)
+        its.append(st["iters_phi"] + st["iters_u"])
+        Ps.append(P)
+    assert its[0] > its[1] > its[2], its
+    for P in Ps[1:]:
+        np.testing.assert_allclose(P, Ps[0], rtol=0, atol=1e-8)
