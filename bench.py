@@ -158,6 +158,8 @@ def main():
     ap.add_argument("--extrap-order", type=int, default=None,
                     help="with --warm-start 2: number of earlier solutions the polynomial goes through "
                          "(0..8; default: the workload's)")
+    ap.add_argument("--nonlocal-every", type=int, default=None,
+                    help="refresh phi and u every k steps (default: the workload's, every step)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without per-launch events (the roofline is then omitted)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing leg")
@@ -180,6 +182,8 @@ def main():
         w.cfg = w.cfg.replace(warm_start=args.warm_start)
     if args.extrap_order is not None:
         w.cfg = w.cfg.replace(extrap_order=args.extrap_order)
+    if args.nonlocal_every is not None:
+        w.cfg = w.cfg.replace(nonlocal_every=args.nonlocal_every)
     cfg = w.cfg
     dev = torch.device("cuda:0")
     ctx = pf.Context(cfg, "cuda:0")
@@ -219,7 +223,8 @@ def main():
                    "integrator": cfg.integrator, "tol_phi": cfg.tol_phi, "tol_u": cfg.tol_u,
                    "electrodes": len(cfg.electrodes), "init": w.init, "seed": w.seed,
                    "initial_guess": WARM_START_NAMES[int(cfg.warm_start)],
-                   "extrap_order": cfg.extrap_order if cfg.warm_start == 2 else None, "precision": cfg.precision},
+                   "extrap_order": cfg.extrap_order if cfg.warm_start == 2 else None,
+                   "nonlocal_every": max(1, cfg.nonlocal_every), "precision": cfg.precision},
         "cg_iters_per_step": {"phi": round(it_phi, 2), "u": round(it_u, 2)},
     }
     if not args.no_kernel_timing:

@@ -64,6 +64,8 @@ typedef struct {
     uint32_t terms;               /* OR_TERM_* mask */
     int32_t nonlocal_every;       /* recompute phi and u every k steps (<= 1: every step) */
     int32_t extrap_order;         /* warm_start 2: extrapolate from up to this many earlier solutions */
+    double noise_sigma;           /* thermal noise amplitude (zeta of Eq. 7), 0: none */
+    uint64_t noise_seed;          /* key of the noise generator */
 } or_params;
 
 typedef struct {
@@ -839,12 +841,66 @@ static int force_with_solves(const or_params *p, const double *P, double *phi, d
 }
 
 /* ------------------------------------------------------------------------ */
+/* Thermal noise (the random force zeta of Eq. 7)                             */
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011): a 4 x 32-bit counter and a 2 x 32-bit key;
+ * each of the ten rounds multiplies counter words 0 and 2 by two fixed
+ * odd constants, keeps the 64-bit products' halves, and mixes the high
+ * halves with words 1 and 3 and the round key; the key advances by two
+ * Weyl constants between rounds.                                            */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    const uint64_t mul0 = 0xD2511F53u, mul1 = 0xCD9E8D57u;
+    const uint32_t weyl0 = 0x9E3779B9u, weyl1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) { k0 += weyl0; k1 += weyl1; }
+        uint64_t prod0 = mul0 * (uint64_t)c0, prod1 = mul1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The standard normal variates xi (3N, component-major like P) of a step:
+ * node n draws one Philox block with counter (n low, n high, step low, step
+ * high) and key (seed low, seed high); Box-Muller turns words 0, 1 into
+ * xi_x, xi_y (cosine and sine branch) and words 2, 3 into xi_z (cosine), with
+ * u = (w + 1) 2^-32 in (0, 1] for the radius and 2 pi w 2^-32 for the angle. */
+void or_noise(const or_params *p, int64_t step, double *xi) {
+    int64_t N = nnodes(p);
+    const double two32 = 4294967296.0, two_pi = 6.283185307179586476925286766559;
+    uint32_t key[2] = {(uint32_t)p->noise_seed, (uint32_t)(p->noise_seed >> 32)};
+    #pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; n++) {
+        uint32_t ctr[4] = {(uint32_t)n, (uint32_t)((uint64_t)n >> 32), (uint32_t)step,
+                           (uint32_t)((uint64_t)step >> 32)};
+        uint32_t w[4];
+        or_philox4x32_10(ctr, key, w);
+        double r0 = sqrt(-2.0 * log(((double)w[0] + 1.0) / two32));
+        double a0 = two_pi * ((double)w[1] / two32);
+        double r1 = sqrt(-2.0 * log(((double)w[2] + 1.0) / two32));
+        double a1 = two_pi * ((double)w[3] / two32);
+        xi[n] = r0 * cos(a0);
+        xi[N + n] = r0 * sin(a0);
+        xi[2 * N + n] = r1 * cos(a1);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Time integration (Eq. 19)                                                  */
 /* ------------------------------------------------------------------------ */
 /* Predictor-corrector with the rate carried as state V ("velocity"):
  *   Pp = P + dt V;  V <- (V + F(Pp)) / 2;  P <- P + dt V.
  * Forward Euler: P <- P + dt F(P).  Each step does one force evaluation.
- * The initial rate is V0 = F(P0) (or_set_state).                             */
+ * The initial rate is V0 = F(P0) (or_set_state).  With thermal noise the
+ * force of step n is F + zeta_n, zeta_n = (sigma / sqrt(dt)) xi_n, so one
+ * Euler step adds sigma sqrt(dt) xi_n (Euler-Maruyama); V0 has no noise.    */
 
 int or_set_state(const or_params *p, const double *P, double *V, double *phi, double *u, or_stats *st) {
     if (p->integrator != OR_INT_PC) return OR_OK;
@@ -886,7 +942,12 @@ int or_step(const or_params *p, double *P, double *V, double *phi, double *u, in
     double *F = (double *)malloc(sizeof(double) * (size_t)N3);
     int cap = p->warm_start == 2 ? (p->extrap_order < 0 ? 0 : p->extrap_order) : 0;
     double *hist = cap > 0 ? (double *)calloc((size_t)(4 * N * cap), sizeof(double)) : NULL;
-    if (!Pp || !F || (cap > 0 && !hist)) { free(Pp); free(F); free(hist); return OR_ENOMEM; }
+    double *xi = p->noise_sigma != 0 ? (double *)malloc(sizeof(double) * (size_t)N3) : NULL;
+    if (!Pp || !F || (cap > 0 && !hist) || (p->noise_sigma != 0 && !xi)) {
+        free(Pp); free(F); free(hist); free(xi);
+        return OR_ENOMEM;
+    }
+    const double zeta_amp = p->noise_sigma / sqrt(p->dt);
     int nvalid = 0;
     int worst = OR_OK;
     for (int32_t s = 0; s < nsteps; s++) {
@@ -898,21 +959,24 @@ int or_step(const or_params *p, double *P, double *V, double *phi, double *u, in
             if (nvalid < cap) nvalid++;
         }
         int rc;
+        if (xi) or_noise(p, step, xi);
         if (p->integrator == OR_INT_PC) {
             for (int64_t t = 0; t < N3; t++) Pp[t] = P[t] + p->dt * V[t];
             rc = force_with_solves(p, Pp, phi, u, F, refresh, st);
+            if (xi) for (int64_t t = 0; t < N3; t++) F[t] += zeta_amp * xi[t];
             for (int64_t t = 0; t < N3; t++) {
                 V[t] = 0.5 * (V[t] + F[t]);
                 P[t] = P[t] + p->dt * V[t];
             }
         } else {
             rc = force_with_solves(p, P, phi, u, F, refresh, st);
+            if (xi) for (int64_t t = 0; t < N3; t++) F[t] += zeta_amp * xi[t];
             for (int64_t t = 0; t < N3; t++) P[t] = P[t] + p->dt * F[t];
         }
         if (rc == OR_ENONFINITE || rc == OR_ENOMEM) { worst = rc; break; }
         if (rc != OR_OK) worst = rc;
     }
-    free(Pp); free(F); free(hist);
+    free(Pp); free(F); free(hist); free(xi);
     return worst;
 }
 

@@ -52,6 +52,8 @@ class OrParams(ctypes.Structure):
         ("terms", ctypes.c_uint32),
         ("nonlocal_every", ctypes.c_int32),
         ("extrap_order", ctypes.c_int32),
+        ("noise_sigma", ctypes.c_double),
+        ("noise_seed", ctypes.c_uint64),
     ]
 
 
@@ -110,6 +112,9 @@ def lib():
             "or_adjoint_initial_rate": (ctypes.c_int, [P, d, d, d, d, ctypes.c_double, d]),
             "or_top_ghost": (ctypes.c_double, [P, ctypes.c_int, ctypes.c_int]),
             "or_extrapolate": (None, [d, d, ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
+            "or_philox4x32_10": (None, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                        ctypes.POINTER(ctypes.c_uint32)]),
+            "or_noise": (None, [P, ctypes.c_int64, d]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -162,6 +167,8 @@ class Oracle:
         p.terms = cfg.terms
         p.nonlocal_every = cfg.nonlocal_every
         p.extrap_order = cfg.extrap_order
+        p.noise_sigma = cfg.noise_sigma
+        p.noise_seed = cfg.noise_seed
         self.p = p
         self.pp = ctypes.byref(p)
         self.N = cfg.nodes
@@ -300,6 +307,22 @@ class Oracle:
         st = self.lib.or_set_state(self.pp, _ptr(P), _ptr(V), _ptr(phi), _ptr(u), ctypes.byref(s))
         _check(st, "set_state", allow_noconv=True)
         return V, phi, u, s.as_dict()
+
+    @staticmethod
+    def philox(ctr, key):
+        """Philox4x32-10 of one counter block: 4 words from 4 counter and 2 key words."""
+        c = (ctypes.c_uint32 * 4)(*ctr)
+        k = (ctypes.c_uint32 * 2)(*key)
+        out = (ctypes.c_uint32 * 4)()
+        lib().or_philox4x32_10(c, k, out)
+        return [int(x) for x in out]
+
+    def noise(self, step):
+        """The standard normal variates xi (3, nz, ny, nx) of the thermal
+        noise of a step."""
+        xi = self._vec(3)
+        self.lib.or_noise(self.pp, step, _ptr(xi))
+        return xi
 
     @staticmethod
     def extrapolate(x, hist, m):

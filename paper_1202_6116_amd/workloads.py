@@ -75,6 +75,8 @@ class PFConfig:
     maxit: int = 5000
     warm_start: int = 1             # 0 cold, 1 previous solution, 2 extrapolated from earlier solutions
     extrap_order: int = 4           # warm_start 2: polynomial through up to 1 + this many solutions
+    noise_sigma: float = 0.0        # thermal noise: one Euler step adds noise_sigma * sqrt(dt) * N(0, 1)
+    noise_seed: int = 0             # key of the counter-based noise generator
     terms: int = TERM_ALL
     nonlocal_every: int = 1         # recompute phi and u every k steps
 

@@ -293,3 +293,24 @@ def test_extrapolation_history_spans_step_calls(pf):
     b.set_state(P0)
     sc = b.step(5)
     assert sc["iters_phi"] == sb["iters_phi"] and sc["iters_u"] == sb["iters_u"]
+
+
+@pytest.mark.parametrize("integrator,ws", [("pc", 1), ("euler", 1), ("pc", 2)])
+def test_nonlocal_every_k_matches_oracle(pf, oracle_mod, integrator, ws):
+    """Non-local fields refreshed every 5 steps (the paper's Fig. 3d
+    option): phi and u stay frozen in between while P evolves."""
+    cfg = ragged_cfg(integrator=integrator, nonlocal_every=5, warm_start=ws)
+    print(f"case: nonlocal_every 5 {integrator} ws={ws}", flush=True)
+    P0 = domain_polarisation(cfg, 19, block=4)
+    o = oracle_mod.Oracle(cfg)
+    P = P0.copy()
+    V, phi, u, _ = o.set_state(P)
+    st_o = o.step(P, V, phi, u, 13)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P0))
+    st_g = ctx.step(13)
+    assert st_g["solves_phi"] == st_o["nsolves_phi"] == 3
+    Pg, Vg, phig, ug, _ = ctx.get_state()
+    assert rel(host(Pg), P) < TOL
+    assert rel(host(phig), phi) < TOL
+    assert rel(host(ug), u) < TOL
