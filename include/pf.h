@@ -110,6 +110,11 @@ typedef struct {
                                    earlier ones, x_next = sum_t (-1)^t C(m+1,t+1)
                                    x_{n-t}; the order grows with the history kept
                                    since pf_set_state/pf_restore_state/pf_set_params */
+  double noise_sigma;           /* thermal noise (the random force zeta of Eq. 7),
+                                   >= 0: the force of step s gains
+                                   zeta = (noise_sigma / sqrt(dt)) xi_s, so one Euler
+                                   step adds noise_sigma sqrt(dt) xi_s; V0 has none */
+  uint64_t noise_seed;          /* key of the noise generator (see pf_noise) */
 } pf_config;
 
 typedef struct {
@@ -181,6 +186,17 @@ pf_status pf_solve_u(pf_ctx *ctx, const void *P, void *u, pf_solve_stats *stats)
  * PF_FP32_REFINE the force is evaluated in float from rounded phi and u.
  * Asynchronous. */
 pf_status pf_force(pf_ctx *ctx, const void *P, const void *phi, const void *u, void *F);
+
+/* The standard normal variates xi_s of step s of the thermal noise, written
+ * to xi (device, 3N doubles, component-major like P), whatever noise_sigma
+ * is.  Node n = i + nx (j + ny k) of step s takes one Philox4x32-10 block
+ * (Salmon et al., SC 2011) with counter words (n mod 2^32, n / 2^32,
+ * s mod 2^32, s / 2^32) and key words (seed mod 2^32, seed / 2^32); with u_w
+ * = (w + 1) 2^-32 and a_w = 2 pi w 2^-32, Box-Muller gives xi_x =
+ * sqrt(-2 ln u_w0) cos a_w1, xi_y = sqrt(-2 ln u_w0) sin a_w1 and xi_z =
+ * sqrt(-2 ln u_w2) cos a_w3.  pf_step draws step s = the step counter before
+ * the step (pf_get_state).  Asynchronous. */
+pf_status pf_noise(pf_ctx *ctx, int64_t step, double *xi);
 
 /* Free energy of the current P: out[0..4] = bulk, gradient, electrostatic,
  * elastic, total (host doubles), evaluated in FP64.  Solves phi and u at P

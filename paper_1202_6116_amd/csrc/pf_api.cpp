@@ -51,8 +51,9 @@ hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb
                            const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* P, const T* V, T cdt,
-                        const T* phi, const T* ghost_top, const T* u, int mode, T* Pn, T* Vn, T* Fout,
-                        hipStream_t s);
+                        const T* phi, const T* ghost_top, const T* u, int mode, const NoiseSpec& ns, T* Pn,
+                        T* Vn, T* Fout, hipStream_t s);
+hipError_t launch_noise(const NoiseSpec& ns, int64_t N, double* xi, hipStream_t s);
 template <typename S>
 hipError_t launch_energy(const Dims& d, const Coefs<double>& cf, const FemTables* tb, const S* P, const double* phi,
                          const double* phi_bc, const double* ghost_top, const double* u, double* partials,
@@ -382,6 +383,7 @@ pf_status validate(const pf_config* c, std::string* why) {
   if (c->maxit <= 0) return bad("maxit must be > 0");
   if (c->warm_start < 0 || c->warm_start > 2) return bad("warm_start must be 0, 1 or 2");
   if (c->extrap_order < 0 || c->extrap_order > kMaxExtrap) return bad("extrap_order must be in 0..8");
+  if (!(c->noise_sigma >= 0) || !std::isfinite(c->noise_sigma)) return bad("noise_sigma must be finite and >= 0");
   if (c->terms & ~(uint32_t)PF_TERM_ALL) return bad("unknown term bits");
   if (!(c->C11 > 0) || !(c->C44 > 0) || !(c->C11 > std::fabs(c->C12)) || !(c->C11 + 2 * c->C12 > 0))
     return bad("stiffness must be positive definite");
@@ -776,16 +778,30 @@ pf_status solve_nonlocal(pf_ctx* c, const void* P, const void* V, double cdt, bo
 }
 
 // Force sweep on the state's buffers (state precision).
+// The noise of step `step` (amp = 0 when the configuration has none).
+NoiseSpec noise_spec(const pf_ctx* c, int64_t step, bool on) {
+  NoiseSpec ns;
+  ns.amp = on ? c->cfg.noise_sigma / std::sqrt(c->cfg.dt) : 0.0;
+  ns.key0 = (uint32_t)c->cfg.noise_seed;
+  ns.key1 = (uint32_t)(c->cfg.noise_seed >> 32);
+  ns.step0 = (uint32_t)(uint64_t)step;
+  ns.step1 = (uint32_t)((uint64_t)step >> 32);
+  return ns;
+}
+
+// Force at P (+ cdt V) and the update `mode`; the step modes add the thermal
+// noise of the current step.
 pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt, int mode, void* Pn, void* Vn,
                              void* F, const void* phi_override = nullptr, const void* u_override = nullptr) {
   const FemTables* tb = at<FemTables>(c, c->lay.tables);
+  const NoiseSpec ns = noise_spec(c, c->step, mode == kPcStep || mode == kEulerStep);
   if (fp32(c)) {
     const Coefs<float> cf = make_coefs<float>(c);
     const float* phi = phi_override ? static_cast<const float*>(phi_override) : at<float>(c, c->lay.phi32);
     const float* u = u_override ? static_cast<const float*>(u_override) : at<float>(c, c->lay.u32);
     PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
       return launch_force<float>(c->dims, cf, tb, static_cast<const float*>(P), static_cast<const float*>(V),
-                                 (float)cdt, phi, at<float>(c, c->lay.ghost32), u, mode, static_cast<float*>(Pn),
+                                 (float)cdt, phi, at<float>(c, c->lay.ghost32), u, mode, ns, static_cast<float*>(Pn),
                                  static_cast<float*>(Vn), static_cast<float*>(F), c->stream);
     }));
   } else {
@@ -794,7 +810,7 @@ pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt
     const double* u = u_override ? static_cast<const double*>(u_override) : at<double>(c, c->lay.u);
     PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
       return launch_force<double>(c->dims, cf, tb, static_cast<const double*>(P), static_cast<const double*>(V), cdt,
-                                  phi, at<double>(c, c->lay.ghost64), u, mode, static_cast<double*>(Pn),
+                                  phi, at<double>(c, c->lay.ghost64), u, mode, ns, static_cast<double*>(Pn),
                                   static_cast<double*>(Vn), static_cast<double*>(F), c->stream);
     }));
   }
@@ -1252,6 +1268,12 @@ pf_status pf_solve_u(pf_ctx* c, const void* P, void* u, pf_solve_stats* st) {
   }
   pf_status e = sync(c);
   return fatal(e) ? e : s;
+}
+
+pf_status pf_noise(pf_ctx* c, int64_t step, double* xi) {
+  if (!c || !xi) return fail(c, PF_EINVAL, "pf_noise: null argument");
+  PF_HIP(c, launch_noise(noise_spec(c, step, true), c->dims.N, xi, c->stream));
+  return PF_OK;
 }
 
 pf_status pf_force(pf_ctx* c, const void* P, const void* phi, const void* u, void* F) {

@@ -102,6 +102,14 @@ struct Coefs {
 
 enum Terms { kLandau = 1, kGrad = 2, kElec = 4, kElas = 8 };
 
+// Thermal noise of one step: the force gains amp * xi, xi the standard
+// normal variates keyed by (seed, step, node).  amp = 0: no noise.
+struct NoiseSpec {
+  double amp;
+  uint32_t key0, key1;      // seed words
+  uint32_t step0, step1;    // step words
+};
+
 // What the force kernel does with the force F at the evaluation point.
 enum ForceMode {
   kForceOut = 0,     // F written to an output array

@@ -844,10 +844,57 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_b_kernel(Dims d, TileMap t
 //   E = -G_h phi (Dirichlet ghosts), s = C (int N_n eps(u) - int N_n eps0(Pp))
 // then, by mode: write F; V = F; (V, P) <- ((V+F)/2, P + dt (V+F)/2);
 // P <- P + dt F.  Reads (P, V) and writes (Pn, Vn), distinct buffers.
+// Philox4x32-10 counter-based generator (Salmon et al., SC 2011): ten
+// rounds of two 32 x 32 -> 64-bit products of counter words 0 and 2, whose
+// high halves are mixed with words 1, 3 and the round key; the key moves by
+// the two Weyl increments between rounds.
+__device__ inline void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
+                                     uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Three standard normal variates of node n for one step: one Philox block,
+// Box-Muller on words (0, 1) for x, y and on words (2, 3) for z.
+__device__ inline void noise_variates(const NoiseSpec& ns, int64_t n, double xi[3]) {
+  uint32_t w0 = (uint32_t)n, w1 = (uint32_t)((uint64_t)n >> 32), w2 = ns.step0, w3 = ns.step1;
+  philox4x32_10(w0, w1, w2, w3, ns.key0, ns.key1);
+  constexpr double kTwoM32 = 2.3283064365386962890625e-10;  // 2^-32
+  constexpr double kTwoPi = 6.283185307179586476925286766559;
+  const double r0 = sqrt(-2.0 * log(((double)w0 + 1.0) * kTwoM32));
+  const double r1 = sqrt(-2.0 * log(((double)w2 + 1.0) * kTwoM32));
+  double s0, c0;
+  sincos(kTwoPi * ((double)w1 * kTwoM32), &s0, &c0);
+  xi[0] = r0 * c0;
+  xi[1] = r0 * s0;
+  xi[2] = r1 * cos(kTwoPi * ((double)w3 * kTwoM32));
+}
+
+__global__ void noise_kernel(NoiseSpec ns, int64_t N, double* __restrict__ xi) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; n < N; n += stride) {
+    double v[3];
+    noise_variates(ns, n, v);
+    xi[n] = v[0];
+    xi[N + n] = v[1];
+    xi[2 * N + n] = v[2];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void force_kernel(
     Dims d, Coefs<T> cf, const FemTables* __restrict__ tb, const T* __restrict__ P, const T* __restrict__ V, T cdt,
-    const T* __restrict__ phi, const T* __restrict__ ghost_top, const T* __restrict__ u, int mode,
+    const T* __restrict__ phi, const T* __restrict__ ghost_top, const T* __restrict__ u, int mode, NoiseSpec ns,
     T* __restrict__ Pn, T* __restrict__ Vn, T* __restrict__ Fout) {
   const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
   if (i >= d.nx || j >= d.ny) return;
@@ -932,6 +979,12 @@ __global__ __launch_bounds__(kThreads) void force_kernel(
   }
 #pragma unroll
   for (int c = 0; c < 3; c++) F[c] *= -cf.L;
+  if (ns.amp != 0.0 && (mode == kPcStep || mode == kEulerStep)) {
+    double xi[3];
+    noise_variates(ns, n, xi);
+#pragma unroll
+    for (int c = 0; c < 3; c++) F[c] += (T)(ns.amp * xi[c]);
+  }
   switch (mode) {
     case kForceOut:
 #pragma unroll
@@ -1305,6 +1358,11 @@ hipError_t launch_extrapolate(double* x, const ExtrapRing& ring, int64_t n, hipS
   return hipGetLastError();
 }
 
+hipError_t launch_noise(const NoiseSpec& ns, int64_t N, double* xi, hipStream_t s) {
+  noise_kernel<<<flat_blocks(N), 256, 0, s>>>(ns, N, xi);
+  return hipGetLastError();
+}
+
 hipError_t launch_refine_update(double* x64, float* x32, const float* d, int64_t n, hipStream_t s) {
   refine_update_kernel<<<flat_blocks(n), 256, 0, s>>>(x64, x32, d, n);
   return hipGetLastError();
@@ -1357,9 +1415,9 @@ hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb
 
 template <typename T>
 hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* P, const T* V, T cdt,
-                        const T* phi, const T* ghost_top, const T* u, int mode, T* Pn, T* Vn, T* Fout,
-                        hipStream_t s) {
-  force_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, phi, ghost_top, u, mode, Pn, Vn,
+                        const T* phi, const T* ghost_top, const T* u, int mode, const NoiseSpec& ns, T* Pn,
+                        T* Vn, T* Fout, hipStream_t s) {
+  force_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, phi, ghost_top, u, mode, ns, Pn, Vn,
                                                         Fout);
   return hipGetLastError();
 }
@@ -1421,7 +1479,7 @@ PF_INSTANTIATE_ADJ(float)
   template hipError_t launch_fem_cg_b<T>(const Dims&, const TileMap&, const FemTables*, const T*, T*,            \
                                          const CgScalars*, double*, hipStream_t);                                \
   template hipError_t launch_force<T>(const Dims&, const Coefs<T>&, const FemTables*, const T*, const T*, T,     \
-                                      const T*, const T*, const T*, int, T*, T*, T*, hipStream_t);
+                                      const T*, const T*, const T*, int, const NoiseSpec&, T*, T*, T*, hipStream_t);
 
 PF_INSTANTIATE(double)
 PF_INSTANTIATE(float)

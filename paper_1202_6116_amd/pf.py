@@ -27,7 +27,7 @@ KERNEL_CLASSES = ["poisson_setup", "poisson_a", "poisson_b", "fem_setup", "fem_a
 # Every symbol declared in include/pf.h.
 EXPORTS = [
     "pf_workspace_size", "pf_init", "pf_set_state", "pf_restore_state", "pf_get_state", "pf_step",
-    "pf_solve_phi", "pf_solve_u", "pf_force", "pf_energy", "pf_set_params", "pf_adjoint_step",
+    "pf_solve_phi", "pf_solve_u", "pf_force", "pf_noise", "pf_energy", "pf_set_params", "pf_adjoint_step",
     "pf_adjoint_initial_rate", "pf_timing", "pf_fem_table_size", "pf_fem_tables", "pf_status_str", "pf_last_error",
     "pf_destroy",
 ]
@@ -59,6 +59,7 @@ class pf_config(ctypes.Structure):
         ("maxit", ctypes.c_int32), ("warm_start", ctypes.c_int32),
         ("terms", ctypes.c_uint32), ("nonlocal_every", ctypes.c_int32),
         ("extrap_order", ctypes.c_int32),
+        ("noise_sigma", ctypes.c_double), ("noise_seed", ctypes.c_uint64),
     ]
 
 
@@ -105,6 +106,7 @@ def lib() -> ctypes.CDLL:
             "pf_solve_phi": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(pf_solve_stats)]),
             "pf_solve_u": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(pf_solve_stats)]),
             "pf_force": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+            "pf_noise": (ctypes.c_int, [vp, ctypes.c_int64, vp]),
             "pf_energy": (ctypes.c_int, [vp, dp]),
             "pf_set_params": (ctypes.c_int, [vp, dp, ctypes.c_double]),
             "pf_adjoint_step": (ctypes.c_int, [vp, vp, vp, vp, vp, dp]),
@@ -143,6 +145,8 @@ def make_config(cfg: PFConfig):
     c.terms = cfg.terms
     c.nonlocal_every = cfg.nonlocal_every
     c.extrap_order = cfg.extrap_order
+    c.noise_sigma = cfg.noise_sigma
+    c.noise_seed = cfg.noise_seed
     return c, els
 
 
@@ -299,6 +303,13 @@ class Context:
         self._check(self.L.pf_force(self.ctx, _ptr(P), _ptr(phi), _ptr(u), _ptr(F)), "pf_force")
         return F
 
+    def noise(self, step: int) -> torch.Tensor:
+        """The standard normal variates (3, nz, ny, nx), float64, of the
+        thermal noise of step `step`."""
+        xi = torch.empty((3,) + self.cfg.shape, dtype=torch.float64, device=self.device)
+        self._check(self.L.pf_noise(self.ctx, int(step), _ptr(xi)), "pf_noise")
+        return xi
+
     def timing(self, enable: bool):
         """Returns {class: (ms, launches)} accumulated since the last call and
         switches per-launch event timing on or off."""
@@ -374,6 +385,10 @@ def pf_solve_u(ctx: Context, P, u=None):
 
 def pf_force(ctx: Context, P, phi, u):
     return ctx.force(P, phi, u)
+
+
+def pf_noise(ctx: Context, step):
+    return ctx.noise(step)
 
 
 def pf_energy(ctx: Context):

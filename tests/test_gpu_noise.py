@@ -1,0 +1,133 @@
+"""GPU thermal noise (Eq. 7's random force) against the oracle, through the
+C ABI: the variates of pf_noise, noisy trajectories of both integrators,
+bitwise resume at a checkpoint, and the adjoint of a noisy trajectory."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1202_6116_amd.workloads import PFConfig, Electrode, domain_polarisation
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0").to(dtype)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def pf():
+    from paper_1202_6116_amd import pf as m
+    return m
+
+
+def noisy_cfg(**kw):
+    base = dict(nx=70, ny=13, nz=6, tol_phi=1e-13, tol_u=1e-13, phi_bottom=0.1, phi_top=-0.2,
+                electrodes=[Electrode(5, 20, 0, 13, 2.0), Electrode(40, 56, 2, 11, -1.5)],
+                noise_sigma=0.05, noise_seed=(3 << 32) | 2024)
+    base.update(kw)
+    return PFConfig(**base)
+
+
+@pytest.mark.parametrize("step", [0, 1, 37, (1 << 33) + 5])
+def test_noise_variates_match_oracle(pf, oracle_mod, step):
+    cfg = noisy_cfg()
+    print(f"case: noise variates step {step}", flush=True)
+    ref = oracle_mod.Oracle(cfg).noise(step)
+    xi = host(pf.Context(cfg).noise(step))
+    assert np.abs(xi - ref).max() <= 1e-13
+    assert abs(xi.std() - 1) < 0.05
+
+
+@pytest.mark.parametrize("integrator", ["pc", "euler"])
+def test_noisy_trajectory_matches_oracle(pf, oracle_mod, integrator):
+    cfg = noisy_cfg(integrator=integrator)
+    print(f"case: noisy trajectory {integrator}", flush=True)
+    P0 = domain_polarisation(cfg, 41, block=4)
+    o = oracle_mod.Oracle(cfg)
+    P = P0.copy()
+    V, phi, u, _ = o.set_state(P)
+    o.step(P, V, phi, u, 10)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P0))
+    ctx.step(10)
+    Pg, Vg, phig, ug, _ = ctx.get_state()
+    assert rel(host(Pg), P) < TOL
+    assert rel(host(phig), phi) < TOL
+    assert rel(host(ug), u) < TOL
+    # the noise changed the trajectory
+    o2 = oracle_mod.Oracle(cfg.replace(noise_sigma=0.0))
+    P2 = P0.copy()
+    V2, phi2, u2, _ = o2.set_state(P2)
+    o2.step(P2, V2, phi2, u2, 10)
+    assert rel(P2, P) > 1e-4
+
+
+def test_noisy_resume_is_bitwise(pf):
+    """The noise is keyed by the step counter, so a run restored from a
+    checkpoint draws the same variates as the uninterrupted run."""
+    cfg = noisy_cfg(tol_phi=1e-9, tol_u=1e-9)
+    P0 = dev(domain_polarisation(cfg, 42, block=4))
+    a = pf.Context(cfg)
+    a.set_state(P0)
+    a.step(6)
+    b = pf.Context(cfg)
+    b.set_state(P0)
+    b.step(3)
+    saved = b.get_state()
+    c = pf.Context(cfg)
+    c.restore_state(*saved[:4], saved[4])
+    c.step(3)
+    assert torch.equal(a.get_state()[0], c.get_state()[0])
+
+
+def test_noisy_fp32_trajectory(pf, oracle_mod):
+    cfg = noisy_cfg(precision="fp32_refine", tol_phi=1e-9, tol_u=1e-9)
+    print("case: noisy fp32 trajectory", flush=True)
+    P0 = domain_polarisation(cfg, 43, block=4)
+    o = oracle_mod.Oracle(cfg.replace(precision="fp64"))
+    P = P0.astype(np.float32).astype(np.float64)
+    V, phi, u, _ = o.set_state(P)
+    o.step(P, V, phi, u, 10)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P0, torch.float32))
+    ctx.step(10)
+    assert rel(host(ctx.get_state()[0]), P) < 1e-4
+
+
+@pytest.mark.parametrize("integrator", ["pc", "euler"])
+def test_noisy_adjoint_matches_oracle(pf, oracle_mod, integrator):
+    """The noise does not depend on P or the parameters, so the adjoint
+    equations are unchanged; the recomputed segments must redraw the same
+    variates (checkpoints carry the step counter)."""
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    cfg = PFConfig(nx=20, ny=9, nz=5, tol_phi=1e-13, tol_u=1e-13, dt=0.05, integrator=integrator,
+                   electrodes=[Electrode(2, 6, 0, 9, 1.0), Electrode(12, 16, 0, 9, -1.0)],
+                   Q11=0.5, Q12=-0.15, Q44=0.2, noise_sigma=0.1, noise_seed=9)
+    print(f"case: noisy adjoint {integrator}", flush=True)
+    nsteps = 6
+    P0 = domain_polarisation(cfg, 44, block=3, std=0.2)
+    wgt = np.zeros((3,) + cfg.shape)
+    wgt[2, 2:, 2:6, 3:10] = 1.0 / 3 / 4 / 7
+    J_ref, dth_ref, dP_ref = oracle_mod.Oracle(cfg).gradient(P0, nsteps, wgt)
+    ctx = pf.Context(cfg)
+    P0t = dev(P0).requires_grad_(True)
+    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+    PN = tdgl_steps(P0t, volts, a1, ctx, nsteps, checkpoint_every=4)
+    J = (PN * dev(wgt)).sum()
+    J.backward()
+    assert abs(float(J.detach()) - J_ref) <= 1e-10 * abs(J_ref)
+    g = np.concatenate([volts.grad.cpu().numpy(), [a1.grad.item()]])
+    assert rel(g, dth_ref) < 1e-7, (g, dth_ref)
+    assert rel(host(P0t.grad), dP_ref) < 1e-7

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
     dict(electrodes=[Electrode(30, 40, 0, 4, 1.0)]),                                # out of range
     dict(electrodes=[Electrode(5, 5, 0, 4, 1.0)]),                                  # empty
     dict(C12=2.0), dict(terms=16), dict(integrator="leapfrog"), dict(warm_start=3),
-    dict(extrap_order=9), dict(extrap_order=-1),
+    dict(extrap_order=9), dict(extrap_order=-1), dict(noise_sigma=-0.1), dict(noise_sigma=float("nan")),
 ])
 def test_invalid_configurations_are_rejected(bad):
     cfg = PFConfig(nx=32, ny=8, nz=4)
