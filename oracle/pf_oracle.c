@@ -42,6 +42,7 @@
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2, OR_ENOCONV = -4, OR_ENONFINITE = -5 };
 enum { OR_TERM_LANDAU = 1, OR_TERM_GRAD = 2, OR_TERM_ELEC = 4, OR_TERM_ELAS = 8 };
 enum { OR_INT_PC = 0, OR_INT_EULER = 1 };
+enum { OR_TOP_METAL = 0, OR_TOP_OPEN = 1 };
 
 typedef struct {
     int32_t nx, ny, nz;
@@ -66,6 +67,10 @@ typedef struct {
     int32_t extrap_order;         /* warm_start 2: extrapolate from up to this many earlier solutions */
     double noise_sigma;           /* thermal noise amplitude (zeta of Eq. 7), 0: none */
     uint64_t noise_seed;          /* key of the noise generator */
+    int32_t top_bc;               /* OR_TOP_METAL: Dirichlet ghost plane above the film;
+                                     OR_TOP_OPEN: n_air air planes, zero normal field on top */
+    int32_t n_air;                /* air planes of the potential grid (open top) */
+    double eps_air;               /* permittivity of the air planes (open top) */
 } or_params;
 
 typedef struct {
@@ -76,6 +81,13 @@ typedef struct {
 } or_stats;
 
 static inline int64_t nnodes(const or_params *p) { return (int64_t)p->nx * p->ny * p->nz; }
+
+/* The potential grid: the film planes k < nz and, with the open top, n_air
+ * air planes above them (Sec. III.C and IV: the open-circuit film carries
+ * air layers with a Neumann condition on top). */
+static inline int open_top(const or_params *p) { return p->top_bc == OR_TOP_OPEN; }
+static inline int phi_planes(const or_params *p) { return p->nz + (open_top(p) ? p->n_air : 0); }
+static inline int64_t nphi(const or_params *p) { return (int64_t)p->nx * p->ny * phi_planes(p); }
 
 static inline int64_t node(const or_params *p, int i, int j, int k) {
     int nx = p->nx, ny = p->ny;
@@ -584,7 +596,9 @@ double or_elastic_energy(const or_params *p, const double *P, const double *u) {
 /* ------------------------------------------------------------------------ */
 
 /* Value of the top ghost plane k = nz at column (i, j): the voltage of the
- * electrode covering it, otherwise phi_top (Sec. III.C, Dirichlet). */
+ * electrode covering it, otherwise phi_top (Sec. III.C, Dirichlet).  With
+ * the open top the plane k = nz is the first air plane and only its
+ * electrode nodes are Dirichlet (value: the electrode voltage). */
 double or_top_ghost(const or_params *p, int i, int j) {
     for (int e = 0; e < p->n_el; e++) {
         const int32_t *b = p->el_box + 4 * e;
@@ -593,30 +607,65 @@ double or_top_ghost(const or_params *p, int i, int j) {
     return p->phi_top;
 }
 
-/* rho = D_h P: central differences, P = 0 on the planes k = -1 and k = nz. */
+/* Node (i, j, k) of the potential grid is an electrode node of the open top. */
+static int is_electrode(const or_params *p, int i, int j, int k) {
+    if (!open_top(p) || k != p->nz) return 0;
+    i = ((i % p->nx) + p->nx) % p->nx;
+    j = ((j % p->ny) + p->ny) % p->ny;
+    for (int e = 0; e < p->n_el; e++) {
+        const int32_t *b = p->el_box + 4 * e;
+        if (i >= b[0] && i < b[1] && j >= b[2] && j < b[3]) return 1;
+    }
+    return 0;
+}
+
+/* Permittivity of plane k of the potential grid: eps_b in the film, eps_air
+ * above it. */
+static double plane_eps(const or_params *p, int k) { return k < p->nz ? p->eps_b : p->eps_air; }
+
+/* Permittivity of the z-face between planes k and k + 1: the harmonic mean
+ * of the two (flux continuity across a layered dielectric); k = -1 is the
+ * face to the bottom ghost plane; above the top plane it is the face to the
+ * top ghost plane (metal) or none (open: zero normal field). */
+static double face_eps(const or_params *p, int k) {
+    int top = phi_planes(p) - 1;
+    if (k < 0) return plane_eps(p, 0);
+    if (k >= top) return open_top(p) ? 0.0 : plane_eps(p, top);
+    double a = plane_eps(p, k), b = plane_eps(p, k + 1);
+    return a == b ? a : 2 * a * b / (a + b);
+}
+
+/* rho = D_h P on the potential grid: central differences, P = 0 outside the
+ * film (planes k = -1 and k >= nz). */
 void or_divergence(const or_params *p, const double *P, double *rho) {
-    int64_t N = nnodes(p);
+    int64_t N = nnodes(p), M = nphi(p);
     double h = p->h;
     #pragma omp parallel for schedule(static)
-    for (int64_t n = 0; n < N; n++) {
+    for (int64_t n = 0; n < M; n++) {
         int i = (int)(n % p->nx), j = (int)((n / p->nx) % p->ny), k = (int)(n / ((int64_t)p->nx * p->ny));
-        double dx = P[node(p, i + 1, j, k)] - P[node(p, i - 1, j, k)];
-        double dy = P[N + node(p, i, j + 1, k)] - P[N + node(p, i, j - 1, k)];
-        double zp = (k + 1 < p->nz) ? P[2 * N + node(p, i, j, k + 1)] : 0.0;
-        double zm = (k - 1 >= 0) ? P[2 * N + node(p, i, j, k - 1)] : 0.0;
+        double dx = 0, dy = 0, zp = 0, zm = 0;
+        if (k < p->nz) {
+            dx = P[node(p, i + 1, j, k)] - P[node(p, i - 1, j, k)];
+            dy = P[N + node(p, i, j + 1, k)] - P[N + node(p, i, j - 1, k)];
+        }
+        if (k + 1 < p->nz) zp = P[2 * N + node(p, i, j, k + 1)];
+        if (k - 1 >= 0 && k - 1 < p->nz) zm = P[2 * N + node(p, i, j, k - 1)];
         rho[n] = (dx + dy + zp - zm) / (2 * h);
     }
 }
 
-/* E = -G_h phi with central differences.  with_ghosts = 1 uses the Dirichlet
- * ghost values (phi_bottom below, top ghost plane above); 0 uses zero. */
+/* E = -G_h phi at the film nodes with central differences.  with_ghosts = 1
+ * uses the Dirichlet ghost values (phi_bottom below; above the film the top
+ * ghost plane, or with the open top the air plane k = nz of phi); 0 uses zero
+ * ghosts. */
 void or_efield(const or_params *p, const double *phi, int with_ghosts, double *E) {
     int64_t N = nnodes(p);
     double h = p->h;
+    int planes = phi_planes(p);
     #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++) {
         int i = (int)(n % p->nx), j = (int)((n / p->nx) % p->ny), k = (int)(n / ((int64_t)p->nx * p->ny));
-        double zp = (k + 1 < p->nz) ? phi[node(p, i, j, k + 1)] : (with_ghosts ? or_top_ghost(p, i, j) : 0.0);
+        double zp = (k + 1 < planes) ? phi[node(p, i, j, k + 1)] : (with_ghosts ? or_top_ghost(p, i, j) : 0.0);
         double zm = (k - 1 >= 0) ? phi[node(p, i, j, k - 1)] : (with_ghosts ? p->phi_bottom : 0.0);
         E[n] = -(phi[node(p, i + 1, j, k)] - phi[node(p, i - 1, j, k)]) / (2 * h);
         E[N + n] = -(phi[node(p, i, j + 1, k)] - phi[node(p, i, j - 1, k)]) / (2 * h);
@@ -624,35 +673,57 @@ void or_efield(const or_params *p, const double *phi, int with_ghosts, double *E
     }
 }
 
-/* A phi = -eps_b Lap_h phi with zero Dirichlet ghosts (SPD). */
+/* A phi = -div_h(eps grad_h phi) on the unknown nodes of the potential grid,
+ * with zero values on the Dirichlet ghost planes and electrode nodes (their
+ * values enter the right-hand side) and no flux through the open top; rows
+ * of electrode nodes are zero.  eps is constant (eps_b) with the metal top,
+ * so A = -eps_b Lap_h there. */
 void or_poisson_apply(const or_params *p, const double *phi, double *out) {
-    int64_t N = nnodes(p);
-    double c = p->eps_b / (p->h * p->h);
+    int64_t M = nphi(p);
+    double ih2 = 1.0 / (p->h * p->h);
+    int planes = phi_planes(p);
     #pragma omp parallel for schedule(static)
-    for (int64_t n = 0; n < N; n++) {
+    for (int64_t n = 0; n < M; n++) {
         int i = (int)(n % p->nx), j = (int)((n / p->nx) % p->ny), k = (int)(n / ((int64_t)p->nx * p->ny));
-        double s = phi[node(p, i + 1, j, k)] + phi[node(p, i - 1, j, k)]
-                 + phi[node(p, i, j + 1, k)] + phi[node(p, i, j - 1, k)];
-        if (k + 1 < p->nz) s += phi[node(p, i, j, k + 1)];
-        if (k - 1 >= 0) s += phi[node(p, i, j, k - 1)];
-        out[n] = c * (6 * phi[n] - s);
+        if (is_electrode(p, i, j, k)) { out[n] = 0; continue; }
+        double v = phi[n];
+        double exy = plane_eps(p, k), eup = face_eps(p, k), edn = face_eps(p, k - 1);
+        double sxy = 0;
+        const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
+        for (int t = 0; t < 4; t++)
+            if (!is_electrode(p, i + di[t], j + dj[t], k)) sxy += phi[node(p, i + di[t], j + dj[t], k)];
+        double up = (k + 1 < planes && !is_electrode(p, i, j, k + 1)) ? phi[node(p, i, j, k + 1)] : 0.0;
+        double dn = (k - 1 >= 0 && !is_electrode(p, i, j, k - 1)) ? phi[node(p, i, j, k - 1)] : 0.0;
+        out[n] = ih2 * (exy * (4 * v - sxy) + eup * (v - up) + edn * (v - dn));
     }
 }
 
-/* Right-hand side of A phi = -rho + (eps_b/h^2) * ghost values.  with_P and
- * with_bc select the polarisation and boundary parts. */
+/* Right-hand side of A phi = -rho + (Dirichlet values times the coupling
+ * eps_face / h^2): the bottom ghost plane (phi_bottom), the top ghost plane
+ * (metal top) or the electrode nodes (open top).  with_P and with_bc select
+ * the polarisation and boundary parts; zero on electrode nodes. */
 void or_poisson_rhs(const or_params *p, const double *P, int with_P, int with_bc, double *b) {
-    int64_t N = nnodes(p);
-    double c = p->eps_b / (p->h * p->h);
+    int64_t M = nphi(p);
+    double ih2 = 1.0 / (p->h * p->h);
     if (with_P) or_divergence(p, P, b);
-    else memset(b, 0, sizeof(double) * (size_t)N);
+    else memset(b, 0, sizeof(double) * (size_t)M);
     #pragma omp parallel for schedule(static)
-    for (int64_t n = 0; n < N; n++) {
+    for (int64_t n = 0; n < M; n++) {
         int i = (int)(n % p->nx), j = (int)((n / p->nx) % p->ny), k = (int)(n / ((int64_t)p->nx * p->ny));
+        if (is_electrode(p, i, j, k)) { b[n] = 0; continue; }
         double v = -b[n];
         if (with_bc) {
-            if (k == 0) v += c * p->phi_bottom;
-            if (k == p->nz - 1) v += c * or_top_ghost(p, i, j);
+            if (k == 0) v += ih2 * face_eps(p, -1) * p->phi_bottom;
+            if (!open_top(p) && k == p->nz - 1) v += ih2 * face_eps(p, k) * or_top_ghost(p, i, j);
+            if (open_top(p)) {
+                const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
+                for (int t = 0; t < 4; t++) {
+                    int ii = ((i + di[t]) % p->nx + p->nx) % p->nx, jj = ((j + dj[t]) % p->ny + p->ny) % p->ny;
+                    if (is_electrode(p, ii, jj, k)) v += ih2 * plane_eps(p, k) * or_top_ghost(p, ii, jj);
+                }
+                if (is_electrode(p, i, j, k + 1)) v += ih2 * face_eps(p, k) * or_top_ghost(p, i, j);
+                if (is_electrode(p, i, j, k - 1)) v += ih2 * face_eps(p, k - 1) * or_top_ghost(p, i, j);
+            }
         }
         b[n] = v;
     }
@@ -737,16 +808,28 @@ static void fem_apply_cb(const or_params *p, const void *ctx, const double *x, d
 }
 
 /* Poisson solve (Eq. 17-18) for the polarisation P with the boundary values,
- * warm-started from phi when warm != 0. */
+ * warm-started from phi when warm != 0.  Jacobi diagonal of A per plane,
+ * (4 eps_k + eps_face_above + eps_face_below) / h^2.  The electrode nodes of
+ * the open top are not unknowns: they receive their Dirichlet value (the
+ * electrode voltage, or zero without the boundary part). */
 int or_solve_poisson_parts(const or_params *p, const double *P, int with_P, int with_bc, double *phi,
                            double tol, int warm, int32_t *iters, double *relres) {
-    int64_t N = nnodes(p);
-    double *b = (double *)malloc(sizeof(double) * (size_t)N);
-    double *diag = (double *)malloc(sizeof(double) * (size_t)N);
+    int64_t M = nphi(p);
+    double *b = (double *)malloc(sizeof(double) * (size_t)M);
+    double *diag = (double *)malloc(sizeof(double) * (size_t)M);
     if (!b || !diag) { free(b); free(diag); return OR_ENOMEM; }
     or_poisson_rhs(p, P, with_P, with_bc, b);
-    for (int64_t n = 0; n < N; n++) diag[n] = 6 * p->eps_b / (p->h * p->h);
-    int st = pcg(p, poisson_apply_cb, NULL, diag, N, b, phi, tol, warm, iters, relres);
+    double ih2 = 1.0 / (p->h * p->h);
+    for (int64_t n = 0; n < M; n++) {
+        int k = (int)(n / ((int64_t)p->nx * p->ny));
+        diag[n] = ih2 * (4 * plane_eps(p, k) + face_eps(p, k) + face_eps(p, k - 1));
+    }
+    int st = pcg(p, poisson_apply_cb, NULL, diag, M, b, phi, tol, warm, iters, relres);
+    if (open_top(p))
+        for (int j = 0; j < p->ny; j++)
+            for (int i = 0; i < p->nx; i++)
+                if (is_electrode(p, i, j, p->nz))
+                    phi[node(p, i, j, p->nz)] = with_bc ? or_top_ghost(p, i, j) : 0.0;
     free(b); free(diag);
     return st;
 }
@@ -779,6 +862,7 @@ int or_solve_u(const or_params *p, const double *P, double *u, int32_t *iters, d
  * p->terms contribute nothing; phi / u may then be NULL. */
 int or_force(const or_params *p, const double *P, const double *phi, const double *u, double *F) {
     int64_t N = nnodes(p);
+    if (((p->terms & OR_TERM_ELEC) && !phi) || ((p->terms & OR_TERM_ELAS) && !u)) return OR_EINVAL;
     double *lap = (double *)calloc((size_t)(3 * N), sizeof(double));
     double *E = (double *)calloc((size_t)(3 * N), sizeof(double));
     double *s = (double *)calloc((size_t)(6 * N), sizeof(double));
@@ -940,8 +1024,9 @@ int or_step(const or_params *p, double *P, double *V, double *phi, double *u, in
     if (p->warm_start == 2 && (p->extrap_order < 0 || p->extrap_order > 15)) return OR_EINVAL;
     double *Pp = (double *)malloc(sizeof(double) * (size_t)N3);
     double *F = (double *)malloc(sizeof(double) * (size_t)N3);
+    int64_t M = nphi(p);
     int cap = p->warm_start == 2 ? (p->extrap_order < 0 ? 0 : p->extrap_order) : 0;
-    double *hist = cap > 0 ? (double *)calloc((size_t)(4 * N * cap), sizeof(double)) : NULL;
+    double *hist = cap > 0 ? (double *)calloc((size_t)((M + 3 * N) * cap), sizeof(double)) : NULL;
     double *xi = p->noise_sigma != 0 ? (double *)malloc(sizeof(double) * (size_t)N3) : NULL;
     if (!Pp || !F || (cap > 0 && !hist) || (p->noise_sigma != 0 && !xi)) {
         free(Pp); free(F); free(hist); free(xi);
@@ -954,8 +1039,8 @@ int or_step(const or_params *p, double *P, double *V, double *phi, double *u, in
         int64_t step = step0 + s;
         int refresh = p->nonlocal_every <= 1 || (step % p->nonlocal_every) == 0;
         if (refresh && hist) {
-            if (p->terms & OR_TERM_ELEC) or_extrapolate(phi, hist, N, nvalid, cap);
-            if (p->terms & OR_TERM_ELAS) or_extrapolate(u, hist + (int64_t)cap * N, N3, nvalid, cap);
+            if (p->terms & OR_TERM_ELEC) or_extrapolate(phi, hist, M, nvalid, cap);
+            if (p->terms & OR_TERM_ELAS) or_extrapolate(u, hist + (int64_t)cap * M, N3, nvalid, cap);
             if (nvalid < cap) nvalid++;
         }
         int rc;
@@ -1038,8 +1123,8 @@ int or_energy(const or_params *p, const double *P, double tol, double out[5]) {
     int32_t it;
     double rr;
     if (p->terms & OR_TERM_ELEC) {
-        double *phiP = (double *)calloc((size_t)N, sizeof(double));
-        double *phib = (double *)calloc((size_t)N, sizeof(double));
+        double *phiP = (double *)calloc((size_t)nphi(p), sizeof(double));
+        double *phib = (double *)calloc((size_t)nphi(p), sizeof(double));
         double *EP = (double *)calloc((size_t)(3 * N), sizeof(double));
         double *Eb = (double *)calloc((size_t)(3 * N), sizeof(double));
         int r1 = or_solve_poisson_parts(p, P, 1, 0, phiP, tol, 0, &it, &rr);
@@ -1083,10 +1168,9 @@ int or_energy(const or_params *p, const double *P, double tol, double out[5]) {
 /* Field of electrode e alone: P = 0, unit voltage on the strip of electrode
  * e, every other boundary value zero.  dF/dV_e = L E^(e). */
 int or_electrode_field(const or_params *p, int e, double tol, double *E) {
-    int64_t N = nnodes(p);
     if (e < 0 || e >= p->n_el) return OR_EINVAL;
     double *volts = (double *)calloc((size_t)p->n_el, sizeof(double));
-    double *phi = (double *)calloc((size_t)N, sizeof(double));
+    double *phi = (double *)calloc((size_t)nphi(p), sizeof(double));
     if (!volts || !phi) { free(volts); free(phi); return OR_ENOMEM; }
     volts[e] = 1.0;
     or_params q = *p;
@@ -1113,7 +1197,7 @@ int or_hvp(const or_params *p, const double *P, const double *u, const double *l
     if (!lap || !El || !el) { free(lap); free(El); free(el); return OR_ENOMEM; }
     if (p->terms & OR_TERM_GRAD) or_laplacian_neumann(p, lam, lap);
     if (p->terms & OR_TERM_ELEC) {
-        double *psi = (double *)calloc((size_t)N, sizeof(double));
+        double *psi = (double *)calloc((size_t)nphi(p), sizeof(double));
         int rc = or_solve_poisson_parts(p, lam, 1, 0, psi, tol, 0, &it, &rr);
         if (rc != OR_OK) status = rc;
         or_efield(p, psi, 0, El);

@@ -54,6 +54,9 @@ class OrParams(ctypes.Structure):
         ("extrap_order", ctypes.c_int32),
         ("noise_sigma", ctypes.c_double),
         ("noise_seed", ctypes.c_uint64),
+        ("top_bc", ctypes.c_int32),
+        ("n_air", ctypes.c_int32),
+        ("eps_air", ctypes.c_double),
     ]
 
 
@@ -169,14 +172,23 @@ class Oracle:
         p.extrap_order = cfg.extrap_order
         p.noise_sigma = cfg.noise_sigma
         p.noise_seed = cfg.noise_seed
+        p.top_bc = 1 if cfg.top == "open" else 0
+        p.n_air = cfg.n_air
+        p.eps_air = cfg.eps_air
         self.p = p
         self.pp = ctypes.byref(p)
         self.N = cfg.nodes
         self.shape = cfg.shape
+        self.phi_shape = cfg.phi_shape
 
     # --- helpers ---------------------------------------------------------
     def _vec(self, ncomp):
         return np.zeros((ncomp,) + self.shape) if ncomp > 1 else np.zeros(self.shape)
+
+    def _phi(self):
+        """A field on the potential grid (the film plus the air planes of the
+        open top)."""
+        return np.zeros(self.phi_shape)
 
     @staticmethod
     def _c(a):
@@ -231,7 +243,7 @@ class Oracle:
 
     # --- finite differences ----------------------------------------------
     def divergence(self, P):
-        out = self._vec(1)
+        out = self._phi()
         self.lib.or_divergence(self.pp, _ptr(self._c(P)), _ptr(out))
         return out
 
@@ -241,12 +253,12 @@ class Oracle:
         return out
 
     def poisson_apply(self, phi):
-        out = self._vec(1)
+        out = self._phi()
         self.lib.or_poisson_apply(self.pp, _ptr(self._c(phi)), _ptr(out))
         return out
 
     def poisson_rhs(self, P, with_P=True, with_bc=True):
-        out = self._vec(1)
+        out = self._phi()
         self.lib.or_poisson_rhs(self.pp, _ptr(None if P is None else self._c(P)), int(with_P), int(with_bc),
                                 _ptr(out))
         return out
@@ -261,7 +273,7 @@ class Oracle:
 
     # --- solves -------------------------------------------------------------
     def solve_poisson_parts(self, P, with_P, with_bc, tol, phi0=None):
-        phi = self._vec(1) if phi0 is None else self._c(phi0).copy()
+        phi = self._phi() if phi0 is None else self._c(phi0).copy()
         it = ctypes.c_int32()
         rr = ctypes.c_double()
         st = self.lib.or_solve_poisson_parts(self.pp, _ptr(None if P is None else self._c(P)), int(with_P),
@@ -273,7 +285,7 @@ class Oracle:
     def solve_phi(self, P, phi0=None):
         """Poisson solve with the boundary values; warm-started from phi0 when
         the configuration asks for warm starts."""
-        phi = self._vec(1) if phi0 is None else self._c(phi0).copy()
+        phi = self._phi() if phi0 is None else self._c(phi0).copy()
         it = ctypes.c_int32()
         rr = ctypes.c_double()
         st = self.lib.or_solve_phi(self.pp, _ptr(self._c(P)), _ptr(phi), ctypes.byref(it), ctypes.byref(rr))
@@ -301,7 +313,7 @@ class Oracle:
         predictor-corrector, zero for Euler)."""
         P = self._c(P)
         V = self._vec(3)
-        phi = self._vec(1) if phi0 is None else self._c(phi0).copy()
+        phi = self._phi() if phi0 is None else self._c(phi0).copy()
         u = self._vec(3) if u0 is None else self._c(u0).copy()
         s = OrStats()
         st = self.lib.or_set_state(self.pp, _ptr(P), _ptr(V), _ptr(phi), _ptr(u), ctypes.byref(s))

@@ -79,10 +79,22 @@ class PFConfig:
     noise_seed: int = 0             # key of the counter-based noise generator
     terms: int = TERM_ALL
     nonlocal_every: int = 1         # recompute phi and u every k steps
+    top: str = "metal"              # "metal": Dirichlet plane above the film; "open": air layers, Neumann top
+    n_air: int = 5                  # open top: air planes of the potential grid above the film
+    eps_air: float = 1.0            # open top: permittivity of the air planes
 
     @property
     def shape(self) -> Tuple[int, int, int]:
         return (self.nz, self.ny, self.nx)
+
+    @property
+    def phi_planes(self) -> int:
+        """Planes of the potential grid: the film, plus the air when open."""
+        return self.nz + (self.n_air if self.top == "open" else 0)
+
+    @property
+    def phi_shape(self) -> Tuple[int, int, int]:
+        return (self.phi_planes, self.ny, self.nx)
 
     @property
     def nodes(self) -> int:
