@@ -22,11 +22,18 @@
  *   fastest).  Periodic in x and y.  k = 0 is the substrate side (mechanically
  *   clamped), k = nz - 1 the free top surface.
  *   Vector fields (P, V, u, forces) are structure-of-arrays: component c of
- *   node n at element c*N + n, N = nx ny nz.  Scalar fields (phi) have N
- *   elements.
- *   Potential boundary values live on two ghost planes one spacing outside
- *   the film: k = -1 holds phi_bottom, k = nz holds phi_top except where an
- *   electrode covers it (Sec. III.C, Dirichlet electrodes).
+ *   node n at element c*N + n, N = nx ny nz.  The potential phi lives on the
+ *   potential grid of Np = nx ny nzp nodes, same ordering: nzp = nz with the
+ *   metal top, nz + n_air with the open top (the air planes follow the film
+ *   planes).
+ *   Potential boundary values: k = -1 is a ghost plane holding phi_bottom.
+ *   Metal top (PF_TOP_METAL): k = nz is a ghost plane holding phi_top except
+ *   where an electrode covers it (Sec. III.C, Dirichlet electrodes).  Open
+ *   top (PF_TOP_OPEN, the open-circuit film of Sec. IV): planes nz .. nzp-1
+ *   are air (permittivity eps_air; z-faces across the film/air interface take
+ *   the harmonic mean), the top of the air has a zero normal field, and the
+ *   electrode nodes of plane nz are Dirichlet nodes holding the electrode
+ *   voltage (phi_top is unused).
  *   Voigt order (xx, yy, zz, xy, yz, zx) with engineering shear (Eq. 12).
  *
  * Precision.  PF_FP64: every array is double.  PF_FP32_REFINE: P, V and
@@ -69,6 +76,8 @@ typedef enum {
 
 /* terms: which contributions enter the force (tests switch terms off) */
 enum { PF_TERM_LANDAU = 1, PF_TERM_GRAD = 2, PF_TERM_ELEC = 4, PF_TERM_ELAS = 8, PF_TERM_ALL = 15 };
+/* top_bc: electrostatic condition above the film */
+enum { PF_TOP_METAL = 0, PF_TOP_OPEN = 1 };
 /* integrator */
 enum { PF_INT_PC = 0, PF_INT_EULER = 1 };
 /* precision */
@@ -115,6 +124,9 @@ typedef struct {
                                    zeta = (noise_sigma / sqrt(dt)) xi_s, so one Euler
                                    step adds noise_sigma sqrt(dt) xi_s; V0 has none */
   uint64_t noise_seed;          /* key of the noise generator (see pf_noise) */
+  int32_t top_bc;               /* PF_TOP_METAL (ghost plane) or PF_TOP_OPEN (air) */
+  int32_t n_air;                /* PF_TOP_OPEN: air planes, 1 .. 4 nz */
+  double eps_air;               /* PF_TOP_OPEN: permittivity of the air (> 0) */
 } pf_config;
 
 typedef struct {
@@ -147,7 +159,7 @@ pf_status pf_workspace_size(const pf_config *cfg, size_t *bytes);
 pf_status pf_init(const pf_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream, pf_ctx **out);
 
 /* Loads the polarisation P (device, 3N) as the current state, with optional
- * initial guesses phi0 (N doubles) and u0 (3N doubles) for the first solves
+ * initial guesses phi0 (Np doubles) and u0 (3N doubles) for the first solves
  * (NULL: zero).  For the predictor-corrector it solves phi and u at P and
  * sets the carried rate V0 = F(P) (the paper does not state V0; this is the
  * reading taken).  Synchronises.  Resets the step counter to 0. */
@@ -158,7 +170,7 @@ pf_status pf_set_state(pf_ctx *ctx, const void *P, const void *phi0, const void 
 pf_status pf_restore_state(pf_ctx *ctx, const void *P, const void *V, const void *phi, const void *u, int64_t step);
 
 /* Copies the current state into caller arrays (any may be NULL): P and V
- * (3N, state precision), phi (N doubles), u (3N doubles).  Asynchronous. */
+ * (3N, state precision), phi (Np doubles), u (3N doubles).  Asynchronous. */
 pf_status pf_get_state(const pf_ctx *ctx, void *P, void *V, void *phi, void *u, int64_t *step);
 
 /* Advances the state by nsteps (Eq. 19 or forward Euler): per step one
@@ -170,9 +182,10 @@ pf_status pf_get_state(const pf_ctx *ctx, void *P, void *V, void *phi, void *u, 
 pf_status pf_step(pf_ctx *ctx, int32_t nsteps, pf_step_stats *stats);
 
 /* Poisson solve for a given polarisation P (device, 3N, state precision):
- * eps_b Lap_h phi = div_h P with the ghost-plane boundary values.  phi
- * (device, N doubles) is the initial guess when warm_start is set and
- * receives the solution.  Synchronises. */
+ * div_h(eps grad_h phi) = div_h P (eps = eps_b in the film, eps_air in the
+ * air of the open top) with the boundary values.  phi (device, Np doubles)
+ * is the initial guess when warm_start is set and receives the solution
+ * (electrode nodes of the open top: their voltage).  Synchronises. */
 pf_status pf_solve_phi(pf_ctx *ctx, const void *P, void *phi, pf_solve_stats *stats);
 
 /* FEM solve K u = f(P) for a given polarisation (Eq. 15-16): clamped k = 0
@@ -181,7 +194,7 @@ pf_status pf_solve_phi(pf_ctx *ctx, const void *P, void *phi, pf_solve_stats *st
  * Synchronises. */
 pf_status pf_solve_u(pf_ctx *ctx, const void *P, void *u, pf_solve_stats *stats);
 
-/* Force F = -L dF/dP at P (Eq. 7 without noise) for given phi (N doubles)
+/* Force F = -L dF/dP at P (Eq. 7 without noise) for given phi (Np doubles)
  * and u (3N doubles), written to F (3N, state precision).  No solves.  In
  * PF_FP32_REFINE the force is evaluated in float from rounded phi and u.
  * Asynchronous. */

@@ -32,14 +32,14 @@ hipError_t launch_refine_update(double* x64, float* x32, const float* d, int64_t
 hipError_t launch_extrapolate(double* x, const ExtrapRing& ring, int64_t n, hipStream_t s);
 template <typename T, typename S, typename R>
 hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
-                                int with_bc, const T* ghost_top, T phi_bottom, const T* x, R* r, R* p, R* dz,
-                                double* partials, hipStream_t s);
+                                int with_bc, const T* ghost_top, T phi_bottom, const uint8_t* emask, T* x, R* r,
+                                R* p, R* dz, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_poisson_cg_a(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* r, const T* p_old,
                                T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* p, T* r,
-                               const CgScalars* sc, double* partials, hipStream_t s);
+                               const uint8_t* emask, const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T, typename S, typename R>
 hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const S* P, const S* V, T cdt,
                             const T* W, T* x, R* r, R* p0, R* p1, R* dz, double* partials, hipStream_t s);
@@ -54,6 +54,9 @@ hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, 
                         const T* phi, const T* ghost_top, const T* u, int mode, const NoiseSpec& ns, T* Pn,
                         T* Vn, T* Fout, hipStream_t s);
 hipError_t launch_noise(const NoiseSpec& ns, int64_t N, double* xi, hipStream_t s);
+template <typename S>
+hipError_t launch_elec_quad(const Dims& dp, const Coefs<double>& cf, const S* P, const double* phi,
+                            const double* phi_bc, const uint8_t* emask, double* partials, hipStream_t s);
 template <typename S>
 hipError_t launch_energy(const Dims& d, const Coefs<double>& cf, const FemTables* tb, const S* P, const double* phi,
                          const double* phi_bc, const double* ghost_top, const double* u, double* partials,
@@ -195,20 +198,34 @@ void build_tables(const pf_config& c, FemTables* t) {
 // ---------------------------------------------------------------------------
 
 constexpr size_t kAlign = 256;
+
+// The film grid and the potential grid (the film plus, with the open top,
+// n_air air planes above it).
+int phi_planes(const pf_config& c) { return c.nz + (c.top_bc == PF_TOP_OPEN ? c.n_air : 0); }
+Dims film_dims(const pf_config& c) {
+  const int64_t plane = (int64_t)c.nx * c.ny;
+  return Dims{c.nx, c.ny, c.nz, plane * c.nz, plane, c.nz, plane * c.nz, phi_planes(c)};
+}
+Dims potential_dims(const pf_config& c) {
+  const int64_t plane = (int64_t)c.nx * c.ny;
+  const int nzp = phi_planes(c);
+  return Dims{c.nx, c.ny, nzp, plane * nzp, plane, c.nz, plane * c.nz, nzp};
+}
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   // byte offsets into the workspace
   size_t P[2], V[2];           // state (state precision), double-buffered
-  size_t phi, u;               // solutions (FP64 masters)
+  size_t phi, u;               // solutions (FP64 masters); phi on the potential grid
   size_t phi32, u32;           // FP32 working copies (FP32_REFINE)
   size_t ghost64, ghost32, ghost_unit;
+  size_t emask;                // open top: electrode nodes of the first air plane (bytes)
   size_t phi_bc, basis;        // boundary potential and electrode basis (FP64)
   size_t pr, pp[2], fr, fp[2]; // CG vectors, sized for FP64 (FP32 solves use half)
   size_t dphi, du;             // refinement corrections (FP32)
   size_t hist;                 // ring of earlier solutions for extrapolated warm starts
-                               // (extrap_order slots of N (phi) then extrap_order of 3N (u))
-  size_t scratch[8];           // 3N doubles each: adjoint, energy, conversions
+                               // (extrap_order slots of Np (phi) then extrap_order of 3N (u))
+  size_t scratch[8];           // max(3N, Np) doubles each: adjoint, energy, conversions
   size_t tables, scalars, result, partials;
   size_t total;
 };
@@ -219,6 +236,8 @@ constexpr int kResultSlots = 128;
 
 Layout make_layout(const pf_config& c, int npartials) {
   const size_t N = (size_t)c.nx * c.ny * c.nz;
+  const size_t Np = (size_t)c.nx * c.ny * phi_planes(c);  // potential grid
+  const size_t S = std::max(3 * N, Np);
   const size_t es = c.precision == PF_FP32_REFINE ? 4 : 8;
   const size_t plane = (size_t)c.nx * c.ny;
   Layout L;
@@ -230,23 +249,24 @@ Layout make_layout(const pf_config& c, int npartials) {
   };
   for (int b = 0; b < 2; b++) L.P[b] = take(3 * N * es);
   for (int b = 0; b < 2; b++) L.V[b] = take(3 * N * es);
-  L.phi = take(N * 8);
+  L.phi = take(Np * 8);
   L.u = take(3 * N * 8);
-  L.phi32 = take(N * 4);
+  L.phi32 = take(Np * 4);
   L.u32 = take(3 * N * 4);
   L.ghost64 = take(plane * 8);
   L.ghost32 = take(plane * 4);
   L.ghost_unit = take(plane * 8);
-  L.phi_bc = take(N * 8);
-  L.basis = take((size_t)std::max(c.n_electrodes, 1) * N * 8);
-  L.pr = take(N * 8);
-  for (int b = 0; b < 2; b++) L.pp[b] = take(N * 8);
+  L.emask = take(plane);
+  L.phi_bc = take(Np * 8);
+  L.basis = take((size_t)std::max(c.n_electrodes, 1) * Np * 8);
+  L.pr = take(Np * 8);
+  for (int b = 0; b < 2; b++) L.pp[b] = take(Np * 8);
   L.fr = take(3 * N * 8);
   for (int b = 0; b < 2; b++) L.fp[b] = take(3 * N * 8);
-  L.dphi = take(N * 4);
+  L.dphi = take(Np * 4);
   L.du = take(3 * N * 4);
-  L.hist = c.warm_start == 2 && c.extrap_order > 0 ? take(4 * N * 8 * (size_t)c.extrap_order) : 0;
-  for (int t = 0; t < 8; t++) L.scratch[t] = take(3 * N * 8);
+  L.hist = c.warm_start == 2 && c.extrap_order > 0 ? take((Np + 3 * N) * 8 * (size_t)c.extrap_order) : 0;
+  for (int t = 0; t < 8; t++) L.scratch[t] = take(S * 8);
   L.tables = take(sizeof(FemTables));
   L.scalars = take(sizeof(CgScalars) * kNumScalars);
   L.result = take(kResultSlots * 8);
@@ -261,8 +281,8 @@ enum {
   kScrHw,         // H w
   kScrULin,       // displacement at the linearisation point
   kScrDu,         // adjoint displacement
-  kScrPsi,        // adjoint potential (N)
-  kScrPhiE,       // energy: phi at P (N)
+  kScrPsi,        // adjoint potential (Np)
+  kScrPhiE,       // energy: phi at P (Np)
   kScrUE,         // energy: u at P
   kScrTmp,        // conversions
 };
@@ -283,12 +303,14 @@ constexpr int kMaxOuter = 30;
 struct pf_ctx {
   pf_config cfg;
   std::vector<pf_electrode> electrodes;
-  pf::Dims dims;
+  pf::Dims dims;             // film grid
+  pf::Dims dims_p;           // potential grid
   pf::Layout lay;
   char* ws;
   size_t ws_bytes;
   hipStream_t stream;
-  int nblocks;              // node-kernel blocks
+  int nblocks;              // node-kernel blocks (film grid)
+  int nblocks_p;            // node-kernel blocks (potential grid)
   pf::TileMap tm_p;         // tiles of the Poisson iteration kernels (64 x 4)
   pf::TileMap tm_f;         // tiles of the FEM iteration kernels (64 x 4)
   int npartials;            // partial slots per solver (max of both block counts)
@@ -384,6 +406,11 @@ pf_status validate(const pf_config* c, std::string* why) {
   if (c->warm_start < 0 || c->warm_start > 2) return bad("warm_start must be 0, 1 or 2");
   if (c->extrap_order < 0 || c->extrap_order > kMaxExtrap) return bad("extrap_order must be in 0..8");
   if (!(c->noise_sigma >= 0) || !std::isfinite(c->noise_sigma)) return bad("noise_sigma must be finite and >= 0");
+  if (c->top_bc != PF_TOP_METAL && c->top_bc != PF_TOP_OPEN) return bad("unknown top_bc");
+  if (c->top_bc == PF_TOP_OPEN) {
+    if (c->n_air < 1 || c->n_air > 4 * c->nz) return bad("n_air must be in [1, 4 nz] with the open top");
+    if (!(c->eps_air > 0) || !std::isfinite(c->eps_air)) return bad("eps_air must be > 0");
+  }
   if (c->terms & ~(uint32_t)PF_TERM_ALL) return bad("unknown term bits");
   if (!(c->C11 > 0) || !(c->C44 > 0) || !(c->C11 > std::fabs(c->C12)) || !(c->C11 + 2 * c->C12 > 0))
     return bad("stiffness must be positive definite");
@@ -406,6 +433,12 @@ Coefs<T> make_coefs(const pf_ctx* c) {
   k.inv_h3 = (T)(1.0 / (g.h * g.h * g.h));
   k.eps_over_h2 = (T)(g.eps_b / (g.h * g.h));
   k.inv_diag_poisson = (T)(g.h * g.h / (6.0 * g.eps_b));
+  const bool open = g.top_bc == PF_TOP_OPEN;
+  const double ea = open ? g.eps_air : g.eps_b;
+  const double ei = ea == g.eps_b ? g.eps_b : 2 * g.eps_b * ea / (g.eps_b + ea);
+  k.eps_air_over_h2 = (T)(ea / (g.h * g.h));
+  k.eps_iface_over_h2 = (T)(ei / (g.h * g.h));
+  k.open = open ? 1 : 0;
   k.C11 = (T)g.C11;
   k.C12 = (T)g.C12;
   k.C44 = (T)g.C44;
@@ -425,6 +458,7 @@ double* dev_partials(pf_ctx* c, int which) {
   return at<double>(c, c->lay.partials) + (size_t)which * c->npartials * kPartialsPerBlock;
 }
 double* dev_result(pf_ctx* c) { return at<double>(c, c->lay.result); }
+const uint8_t* emask(pf_ctx* c) { return c->cfg.top_bc == PF_TOP_OPEN ? at<uint8_t>(c, c->lay.emask) : nullptr; }
 
 // ---------------------------------------------------------------------------
 // Event timing of launches
@@ -541,7 +575,8 @@ template <typename T>
 std::function<hipError_t(int)> poisson_iteration(pf_ctx* c, const Coefs<T>& cf, T* r, T* const pb[2], T* x,
                                                  double tol) {
   return [=](int k) -> hipError_t {
-    const Dims& d = c->dims;
+    const Dims& d = c->dims_p;
+    const uint8_t* em = emask(c);
     CgScalars* sc = dev_sc(c, 0);
     double* part = dev_partials(c, 0);
     hipError_t e = timed(c, PF_KC_POISSON_A, 0, k, [&] {
@@ -550,7 +585,7 @@ std::function<hipError_t(int)> poisson_iteration(pf_ctx* c, const Coefs<T>& cf, 
     if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 1, 0, kRedAlpha, tol, 0, nullptr, 0, k);
     if (e == hipSuccess)
       e = timed(c, PF_KC_POISSON_B, 0, k,
-                [&] { return launch_poisson_cg_b<T>(d, c->tm_p, cf, pb[(k + 1) & 1], r, sc, part, c->stream); });
+                [&] { return launch_poisson_cg_b<T>(d, c->tm_p, cf, pb[(k + 1) & 1], r, em, sc, part, c->stream); });
     if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 2, 0, kRedBeta, tol, 0, nullptr, 0, k);
     return e;
   };
@@ -581,17 +616,17 @@ template <typename S>
 pf_status solve_poisson64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, int with_P, int with_bc,
                           const double* ghost, double phi_bottom, double* x, double tol, bool warm,
                           SolveResult* res) {
-  const Dims& d = c->dims;
+  const Dims& d = c->dims_p;
   const Coefs<double> cf = make_coefs<double>(c);
   double* part = dev_partials(c, 0);
   double* r = at<double>(c, c->lay.pr);
   double* const pb[2] = {at<double>(c, c->lay.pp[0]), at<double>(c, c->lay.pp[1])};
   if (!warm) PF_HIP(c, launch_fill<double>(x, d.N, 0.0, c->stream));
   PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
-    return launch_poisson_setup<double, S, double>(d, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, x, r,
-                                                   pb[0], nullptr, part, c->stream);
+    return launch_poisson_setup<double, S, double>(d, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, emask(c),
+                                                   x, r, pb[0], nullptr, part, c->stream);
   }));
-  PF_HIP(c, reduce(c, part, c->nblocks, 3, 0, kRedSetup, tol, 0, nullptr));
+  PF_HIP(c, reduce(c, part, c->nblocks_p, 3, 0, kRedSetup, tol, 0, nullptr));
   CgScalars h;
   PF_TRY(run_cg<double>(c, 0, c->pred[pred], x, pb, d.N, poisson_iteration<double>(c, cf, r, pb, x, tol), &h,
                         "Poisson solve"));
@@ -630,9 +665,10 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
 // so the Krylov space is rarely thrown away by a restart.
 pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, double cdt, double* x64, float* x32,
                         double tol, bool warm, SolveResult* res) {
-  const Dims& d = c->dims;
+  const Dims& d = fem ? c->dims : c->dims_p;
   const int which = fem ? 1 : 0;
   const int64_t n = fem ? 3 * d.N : d.N;
+  const int setup_blocks = fem ? c->nblocks : c->nblocks_p;
   const Coefs<double> cf64 = make_coefs<double>(c);
   const Coefs<float> cf32 = make_coefs<float>(c);
   const FemTables* tb = at<FemTables>(c, c->lay.tables);
@@ -658,10 +694,11 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
     } else {
       PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
         return launch_poisson_setup<double, float, float>(d, cf64, P, V, cdt, 1, 1, at<double>(c, c->lay.ghost64),
-                                                          c->cfg.phi_bottom, x64, r, pb[0], dz, part, c->stream);
+                                                          c->cfg.phi_bottom, emask(c), x64, r, pb[0], dz, part,
+                                                          c->stream);
       }));
     }
-    PF_HIP(c, reduce(c, part, c->nblocks, 3, which, kRedOuter, tol, kInnerTol, nullptr));
+    PF_HIP(c, reduce(c, part, setup_blocks, 3, which, kRedOuter, tol, kInnerTol, nullptr));
     CgScalars h;
     PF_TRY(run_cg<float>(c, which, c->pred[pred], dz, pb, n, iteration, &h, what));
     res->iters += h.iter;
@@ -712,12 +749,12 @@ void stats_add(pf_step_stats* st, int which, const SolveResult& r) {
 pf_status extrapolate_state(pf_ctx* c) {
   const int cap = c->cfg.extrap_order;
   const int m = std::min(c->hist_valid, cap);
-  const int64_t N = c->dims.N;
+  const int64_t N = c->dims.N, Np = c->dims_p.N;
   ExtrapRing ring[2];
   for (int f = 0; f < 2; f++) {
     ExtrapRing& r = ring[f];
-    const int64_t len = f == 0 ? N : 3 * N;
-    double* base = cap > 0 ? at<double>(c, c->lay.hist) + (f == 0 ? 0 : (int64_t)cap * N) : nullptr;
+    const int64_t len = f == 0 ? Np : 3 * N;
+    double* base = cap > 0 ? at<double>(c, c->lay.hist) + (f == 0 ? 0 : (int64_t)cap * Np) : nullptr;
     r.m = m;
     for (int t = 0; t <= m; t++) {
       double b = 1;
@@ -731,7 +768,7 @@ pf_status extrapolate_state(pf_ctx* c) {
   if (cap == 0) return PF_OK;  // the previous solution is the guess
   if (c->cfg.terms & PF_TERM_ELEC)
     PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-      return launch_extrapolate(at<double>(c, c->lay.phi), ring[0], N, c->stream);
+      return launch_extrapolate(at<double>(c, c->lay.phi), ring[0], Np, c->stream);
     }));
   if (c->cfg.terms & PF_TERM_ELAS)
     PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
@@ -825,8 +862,14 @@ pf_status upload_ghosts(pf_ctx* c) {
     for (int j = e.y0; j < e.y1; j++)
       for (int i = e.x0; i < e.x1; i++) g64[(size_t)i + (size_t)g.nx * j] = e.volts;
   std::vector<float> g32(g64.begin(), g64.end());
+  // open top: the electrode nodes of the first air plane are the Dirichlet nodes
+  std::vector<uint8_t> mask((size_t)g.nx * g.ny, 0);
+  for (auto& e : c->electrodes)
+    for (int j = e.y0; j < e.y1; j++)
+      for (int i = e.x0; i < e.x1; i++) mask[(size_t)i + (size_t)g.nx * j] = 1;
   PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.ghost64, g64.data(), g64.size() * 8, hipMemcpyHostToDevice, c->stream));
   PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.ghost32, g32.data(), g32.size() * 4, hipMemcpyHostToDevice, c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.emask, mask.data(), mask.size(), hipMemcpyHostToDevice, c->stream));
   PF_HIP(c, hipStreamSynchronize(c->stream));
   return PF_OK;
 }
@@ -860,7 +903,7 @@ pf_status ensure_basis(pf_ctx* c) {
                              c->stream));
     SolveResult r{};
     pf_status s = solve_poisson64<double>(c, kPredAux, nullptr, nullptr, 0.0, 0, 1, at<double>(c, c->lay.ghost_unit),
-                                          0.0, at<double>(c, c->lay.basis) + (size_t)e * c->dims.N, aux_tol(c), false,
+                                          0.0, at<double>(c, c->lay.basis) + (size_t)e * c->dims_p.N, aux_tol(c), false,
                                           &r);
     if (fatal(s)) return s;
     out = worst(out, s);
@@ -919,7 +962,7 @@ pf_status theta_accumulate(pf_ctx* c, const S* P, const S* V, double cdt, double
     PF_TRY(ensure_basis(c));
     for (int e = 0; e < ne; e++) {
       const pf_electrode& el = c->electrodes[e];
-      const double* phe = at<double>(c, c->lay.basis) + (size_t)e * d.N;
+      const double* phe = at<double>(c, c->lay.basis) + (size_t)e * c->dims_p.N;
       PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
         return launch_theta_dot<S>(d, cf, w, phe, el.x0, el.x1, el.y0, el.y1, P, V, cdt, part, c->stream);
       }));
@@ -985,7 +1028,7 @@ pf_status energy_t(pf_ctx* c, const S* P, double out[5]) {
   double* u = scratch<double>(c, kScrUE);
   if (c->cfg.terms & PF_TERM_ELEC) {
     PF_TRY(ensure_phi_bc(c));
-    PF_HIP(c, hipMemcpyAsync(phi, at<double>(c, c->lay.phi), d.N * 8, hipMemcpyDeviceToDevice, c->stream));
+    PF_HIP(c, hipMemcpyAsync(phi, at<double>(c, c->lay.phi), c->dims_p.N * 8, hipMemcpyDeviceToDevice, c->stream));
     SolveResult r{};
     pf_status s = solve_poisson64<S>(c, kPredAux, P, nullptr, 0.0, 1, 1, at<double>(c, c->lay.ghost64),
                                      c->cfg.phi_bottom, phi, c->cfg.tol_phi, true, &r);
@@ -1005,9 +1048,16 @@ pf_status energy_t(pf_ctx* c, const S* P, double out[5]) {
                             at<double>(c, c->lay.ghost64), u, part, c->stream);
   }));
   PF_HIP(c, reduce(c, part, c->nblocks, 4, 2, kRedSum, 0, 0, dev_result(c)));
-  PF_HIP(c, hipMemcpyAsync(c->host_res, dev_result(c), 4 * 8, hipMemcpyDeviceToHost, c->stream));
+  if (c->cfg.terms & PF_TERM_ELEC) {
+    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+      return launch_elec_quad<S>(c->dims_p, cf, P, phi, at<double>(c, c->lay.phi_bc), emask(c), part, c->stream);
+    }));
+    PF_HIP(c, reduce(c, part, c->nblocks_p, 1, 2, kRedSum, 0, 0, dev_result(c) + 4));
+  }
+  PF_HIP(c, hipMemcpyAsync(c->host_res, dev_result(c), 5 * 8, hipMemcpyDeviceToHost, c->stream));
   PF_TRY(sync(c));
   for (int t = 0; t < 4; t++) out[t] = c->host_res[t];
+  if (c->cfg.terms & PF_TERM_ELEC) out[2] += c->host_res[4];
   out[4] = out[0] + out[1] + out[2] + out[3];
   return st;
 }
@@ -1022,8 +1072,10 @@ namespace {
 // VGPRs for that; their FP64 ring takes 28.5 KB of LDS).
 TileMap poisson_tiles(const pf_config&, const Dims& d) { return make_tile_map(d, kBY, 1024); }
 TileMap fem_tiles(const pf_config&, const Dims& d) { return make_tile_map(d, kBY, 1024); }
-int partial_slots(const pf_config& c, const Dims& d) {
-  return std::max(node_blocks(d), std::max(poisson_tiles(c, d).nblocks, fem_tiles(c, d).nblocks));
+int partial_slots(const pf_config& c) {
+  const Dims d = film_dims(c), dp = potential_dims(c);
+  return std::max(std::max(node_blocks(d), node_blocks(dp)),
+                  std::max(poisson_tiles(c, dp).nblocks, fem_tiles(c, d).nblocks));
 }
 }  // namespace
 }  // namespace pf
@@ -1051,8 +1103,7 @@ pf_status pf_workspace_size(const pf_config* cfg, size_t* bytes) {
   if (!bytes) return PF_EINVAL;
   pf_status s = validate(cfg, nullptr);
   if (s != PF_OK) return s;
-  Dims d{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz, (int64_t)cfg->nx * cfg->ny};
-  *bytes = make_layout(*cfg, partial_slots(*cfg, d)).total;
+  *bytes = make_layout(*cfg, partial_slots(*cfg)).total;
   return PF_OK;
 }
 
@@ -1072,11 +1123,13 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->cfg = *cfg;
   c->electrodes.assign(cfg->electrodes, cfg->electrodes + cfg->n_electrodes);
   c->cfg.electrodes = c->electrodes.data();
-  c->dims = Dims{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz, (int64_t)cfg->nx * cfg->ny};
+  c->dims = film_dims(*cfg);
+  c->dims_p = potential_dims(*cfg);
   c->nblocks = node_blocks(c->dims);
-  c->tm_p = poisson_tiles(*cfg, c->dims);
+  c->nblocks_p = node_blocks(c->dims_p);
+  c->tm_p = poisson_tiles(*cfg, c->dims_p);
   c->tm_f = fem_tiles(*cfg, c->dims);
-  c->npartials = partial_slots(*cfg, c->dims);
+  c->npartials = partial_slots(*cfg);
   c->lay = make_layout(*cfg, c->npartials);
   if (bytes < c->lay.total) {
     fprintf(stderr, "pf_init: workspace of %zu bytes, %zu needed\n", bytes, c->lay.total);
@@ -1135,7 +1188,7 @@ void pf_destroy(pf_ctx* c) {
 
 pf_status pf_set_state(pf_ctx* c, const void* P, const void* phi0, const void* u0) {
   if (!c || !P) return fail(c, PF_EINVAL, "pf_set_state: null argument");
-  const int64_t N = c->dims.N;
+  const int64_t N = c->dims.N, Np = c->dims_p.N;
   const size_t es = state_bytes(c);
   c->cur = 0;
   c->step = 0;
@@ -1146,12 +1199,12 @@ pf_status pf_set_state(pf_ctx* c, const void* P, const void* phi0, const void* u
   double* phi = at<double>(c, c->lay.phi);
   double* u = at<double>(c, c->lay.u);
   PF_HIP(c, hipMemcpyAsync(Pc, P, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
-  if (phi0) PF_HIP(c, hipMemcpyAsync(phi, phi0, N * 8, hipMemcpyDeviceToDevice, c->stream));
-  else PF_HIP(c, launch_fill<double>(phi, N, 0.0, c->stream));
+  if (phi0) PF_HIP(c, hipMemcpyAsync(phi, phi0, Np * 8, hipMemcpyDeviceToDevice, c->stream));
+  else PF_HIP(c, launch_fill<double>(phi, Np, 0.0, c->stream));
   if (u0) PF_HIP(c, hipMemcpyAsync(u, u0, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
   else PF_HIP(c, launch_fill<double>(u, 3 * N, 0.0, c->stream));
   if (fp32(c)) {
-    PF_HIP(c, launch_convert<double, float>(phi, at<float>(c, c->lay.phi32), N, c->stream));
+    PF_HIP(c, launch_convert<double, float>(phi, at<float>(c, c->lay.phi32), Np, c->stream));
     PF_HIP(c, launch_convert<double, float>(u, at<float>(c, c->lay.u32), 3 * N, c->stream));
     PF_HIP(c, launch_fill<float>(static_cast<float*>(Vc), 3 * N, 0.0f, c->stream));
   } else {
@@ -1170,17 +1223,17 @@ pf_status pf_set_state(pf_ctx* c, const void* P, const void* phi0, const void* u
 
 pf_status pf_restore_state(pf_ctx* c, const void* P, const void* V, const void* phi, const void* u, int64_t step) {
   if (!c || !P || !V || !phi || !u) return fail(c, PF_EINVAL, "pf_restore_state: null argument");
-  const int64_t N = c->dims.N;
+  const int64_t N = c->dims.N, Np = c->dims_p.N;
   const size_t es = state_bytes(c);
   c->cur = 0;
   c->hist_valid = 0;
   c->hist_head = 0;
   PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.P[0], P, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
   PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.V[0], V, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
-  PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.phi), phi, N * 8, hipMemcpyDeviceToDevice, c->stream));
+  PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.phi), phi, Np * 8, hipMemcpyDeviceToDevice, c->stream));
   PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.u), u, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
   if (fp32(c)) {
-    PF_HIP(c, launch_convert<double, float>(at<double>(c, c->lay.phi), at<float>(c, c->lay.phi32), N, c->stream));
+    PF_HIP(c, launch_convert<double, float>(at<double>(c, c->lay.phi), at<float>(c, c->lay.phi32), Np, c->stream));
     PF_HIP(c, launch_convert<double, float>(at<double>(c, c->lay.u), at<float>(c, c->lay.u32), 3 * N, c->stream));
   }
   c->step = step;
@@ -1192,11 +1245,11 @@ pf_status pf_get_state(const pf_ctx* cc, void* P, void* V, void* phi, void* u, i
   pf_ctx* c = const_cast<pf_ctx*>(cc);
   if (!c) return PF_EINVAL;
   if (!c->have_state) return fail(c, PF_ESTATE, "pf_get_state: no state (call pf_set_state first)");
-  const int64_t N = c->dims.N;
+  const int64_t N = c->dims.N, Np = c->dims_p.N;
   const size_t es = state_bytes(c);
   if (P) PF_HIP(c, hipMemcpyAsync(P, c->ws + c->lay.P[c->cur], 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
   if (V) PF_HIP(c, hipMemcpyAsync(V, c->ws + c->lay.V[c->cur], 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
-  if (phi) PF_HIP(c, hipMemcpyAsync(phi, at<double>(c, c->lay.phi), N * 8, hipMemcpyDeviceToDevice, c->stream));
+  if (phi) PF_HIP(c, hipMemcpyAsync(phi, at<double>(c, c->lay.phi), Np * 8, hipMemcpyDeviceToDevice, c->stream));
   if (u) PF_HIP(c, hipMemcpyAsync(u, at<double>(c, c->lay.u), 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
   if (step) *step = c->step;
   return PF_OK;

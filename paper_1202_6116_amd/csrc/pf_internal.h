@@ -80,11 +80,16 @@ struct ExtrapRing {
   int m;
 };
 
-// Per-call description of the node grid.
+// Per-call description of a node grid: the film grid (nz = nzf) or the
+// potential grid (nz = nzp: the film plus, with the open top, the air planes
+// above it).  nzf, Nf and nzp are the same in both.
 struct Dims {
   int nx, ny, nz;
   int64_t N;        // nodes
   int64_t plane;    // nx * ny
+  int nzf;          // film planes
+  int64_t Nf;       // film nodes
+  int nzp;          // planes of the potential grid
 };
 
 // Material and model coefficients used inside kernels.
@@ -95,6 +100,9 @@ struct Coefs {
   T h, inv_h2, inv_2h, inv_h3;
   T eps_over_h2;        // eps_b / h^2
   T inv_diag_poisson;   // h^2 / (6 eps_b)
+  T eps_air_over_h2;    // open top: eps_air / h^2
+  T eps_iface_over_h2;  // open top: harmonic mean of eps_b and eps_air / h^2
+  int open;             // open top: air planes, zero normal field on top
   T C11, C12, C44, Q11, Q12, Q44;
   T phi_bottom;
   uint32_t terms;

@@ -338,6 +338,31 @@ __global__ void refine_update_kernel(double* x64, float* x32, const float* d, in
 // Poisson: A phi = -eps_b Lap_h phi (zero ghosts), b = -D_h P + ghost terms
 // ---------------------------------------------------------------------------
 
+// Coupling weights of plane k of the potential grid, divided by h^2: in-plane
+// faces (the plane's permittivity), the z-faces above and below (harmonic
+// means across the film/air interface; none above the open top) and the
+// Jacobi weight 1 / (4 xy + up + dn).  The metal top has eps_b everywhere.
+template <typename T>
+struct PlaneEps {
+  T xy, up, dn, w;
+};
+
+template <typename T>
+__device__ __forceinline__ PlaneEps<T> plane_eps(const Dims& d, const Coefs<T>& cf, int k) {
+  PlaneEps<T> e;
+  if (!cf.open) {
+    e.xy = e.up = e.dn = cf.eps_over_h2;
+    e.w = cf.inv_diag_poisson;
+    return e;
+  }
+  const T ef = cf.eps_over_h2, ea = cf.eps_air_over_h2, ei = cf.eps_iface_over_h2;
+  e.xy = k < d.nzf ? ef : ea;
+  e.dn = k < d.nzf ? ef : (k == d.nzf ? ei : ea);
+  e.up = k + 1 >= d.nzp ? (T)0 : (k + 1 < d.nzf ? ef : (k + 1 == d.nzf ? ei : ea));
+  e.w = (T)1 / (4 * e.xy + e.up + e.dn);
+  return e;
+}
+
 // b from Pp = P + cdt V (V may be null) and the ghost planes; r = b - A x;
 // p = r / diag; partial (b.b, r.z, r.r).  T: arithmetic and x; S: storage
 // of P and V; R: storage of r and p (FP32 for the inner solve of a
@@ -345,43 +370,74 @@ __global__ void refine_update_kernel(double* x64, float* x32, const float* d, in
 template <typename T, typename S, typename R>
 __global__ __launch_bounds__(kThreads) void poisson_setup_kernel(
     Dims d, Coefs<T> cf, const S* __restrict__ P, const S* __restrict__ V, T cdt, int with_P, int with_bc,
-    const T* __restrict__ ghost_top, T phi_bottom, const T* __restrict__ x, R* __restrict__ r, R* __restrict__ p,
-    R* __restrict__ dz, double* partials) {
+    const T* __restrict__ ghost_top, T phi_bottom, const uint8_t* __restrict__ emask, T* __restrict__ x,
+    R* __restrict__ r, R* __restrict__ p, R* __restrict__ dz, double* partials) {
   const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
   double v[3] = {0.0, 0.0, 0.0};
   if (i < d.nx && j < d.ny) {
-    const int64_t N = d.N, pl = d.plane;
-    const int64_t n = i + (int64_t)d.nx * j + pl * k;
-    const int64_t nxp = wrap(i + 1, d.nx) + (int64_t)d.nx * j + pl * k;
-    const int64_t nxm = wrap(i - 1, d.nx) + (int64_t)d.nx * j + pl * k;
-    const int64_t nyp = i + (int64_t)d.nx * wrap(j + 1, d.ny) + pl * k;
-    const int64_t nym = i + (int64_t)d.nx * wrap(j - 1, d.ny) + pl * k;
+    const int64_t Nf = d.Nf, pl = d.plane;
+    const int64_t col = i + (int64_t)d.nx * j;
+    const int64_t n = col + pl * k;
+    const int64_t cxp = wrap(i + 1, d.nx) + (int64_t)d.nx * j, cxm = wrap(i - 1, d.nx) + (int64_t)d.nx * j;
+    const int64_t cyp = i + (int64_t)d.nx * wrap(j + 1, d.ny), cym = i + (int64_t)d.nx * wrap(j - 1, d.ny);
+    const int64_t nxp = cxp + pl * k, nxm = cxm + pl * k, nyp = cyp + pl * k, nym = cym + pl * k;
     const bool up = k + 1 < d.nz, dn = k > 0;
-    auto pp = [&](int c, int64_t m) -> T { return (T)P[c * N + m] + (V ? cdt * (T)V[c * N + m] : (T)0); };
-    T b = 0;
-    if (with_P) {
-      const T dx = pp(0, nxp) - pp(0, nxm);
-      const T dy = pp(1, nyp) - pp(1, nym);
-      const T zp = up ? pp(2, n + pl) : (T)0;
-      const T zm = dn ? pp(2, n - pl) : (T)0;
-      b = -(dx + dy + (zp - zm)) * cf.inv_2h;
+    // electrode nodes of the open top (Dirichlet, first air plane)
+    auto is_el = [&](int kk, int64_t c) { return emask != nullptr && kk == d.nzf && emask[c] != 0; };
+    auto dval = [&](int64_t c) -> T { return with_bc ? ghost_top[c] : (T)0; };
+    if (is_el(k, col)) {
+      x[n] = dval(col);
+      r[n] = 0;
+      p[n] = 0;
+      if (dz) dz[n] = 0;
+    } else {
+      auto pp = [&](int c, int64_t m) -> T { return (T)P[c * Nf + m] + (V ? cdt * (T)V[c * Nf + m] : (T)0); };
+      T b = 0;
+      if (with_P) {
+        const T dx = k < d.nzf ? pp(0, nxp) - pp(0, nxm) : (T)0;
+        const T dy = k < d.nzf ? pp(1, nyp) - pp(1, nym) : (T)0;
+        const T zp = k + 1 < d.nzf ? pp(2, n + pl) : (T)0;
+        const T zm = (dn && k - 1 < d.nzf) ? pp(2, n - pl) : (T)0;
+        b = -(dx + dy + (zp - zm)) * cf.inv_2h;
+      }
+      const PlaneEps<T> e = plane_eps(d, cf, k);
+      if (with_bc) {
+        if (k == 0) b += e.dn * phi_bottom;
+        if (!cf.open && k == d.nz - 1) b += e.up * ghost_top[col];
+        if (cf.open) {
+          if (is_el(k, cxp)) b += e.xy * ghost_top[cxp];
+          if (is_el(k, cxm)) b += e.xy * ghost_top[cxm];
+          if (is_el(k, cyp)) b += e.xy * ghost_top[cyp];
+          if (is_el(k, cym)) b += e.xy * ghost_top[cym];
+          if (is_el(k + 1, col)) b += e.up * ghost_top[col];
+          if (is_el(k - 1, col)) b += e.dn * ghost_top[col];
+        }
+      }
+      T Ax;
+      if (!cf.open) {
+        T s = x[nxp] + x[nxm] + x[nyp] + x[nym];
+        if (up) s += x[n + pl];
+        if (dn) s += x[n - pl];
+        Ax = cf.eps_over_h2 * (6 * x[n] - s);
+      } else {
+        // electrode nodes enter through b; their x is not read here (this
+        // kernel writes it)
+        auto xu = [&](int kk, int64_t c, int64_t m) -> T { return is_el(kk, c) ? (T)0 : x[m]; };
+        const T sxy = xu(k, cxp, nxp) + xu(k, cxm, nxm) + xu(k, cyp, nyp) + xu(k, cym, nym);
+        const T xup = up ? xu(k + 1, col, n + pl) : (T)0;
+        const T xdn = dn ? xu(k - 1, col, n - pl) : (T)0;
+        const T xc = x[n];
+        Ax = e.xy * (4 * xc - sxy) + e.up * (xc - xup) + e.dn * (xc - xdn);
+      }
+      const T rr = b - Ax;
+      const T z = rr * e.w;
+      r[n] = (R)rr;
+      p[n] = (R)z;
+      if (dz) dz[n] = 0;
+      v[0] = (double)b * b;
+      v[1] = (double)rr * z;
+      v[2] = (double)rr * rr;
     }
-    if (with_bc) {
-      if (k == 0) b += cf.eps_over_h2 * phi_bottom;
-      if (k == d.nz - 1) b += cf.eps_over_h2 * ghost_top[i + (int64_t)d.nx * j];
-    }
-    T s = x[nxp] + x[nxm] + x[nyp] + x[nym];
-    if (up) s += x[n + pl];
-    if (dn) s += x[n - pl];
-    const T Ax = cf.eps_over_h2 * (6 * x[n] - s);
-    const T rr = b - Ax;
-    const T z = rr * cf.inv_diag_poisson;
-    r[n] = (R)rr;
-    p[n] = (R)z;
-    if (dz) dz[n] = 0;
-    v[0] = (double)b * b;
-    v[1] = (double)rr * z;
-    v[2] = (double)rr * rr;
   }
   block_partials<3, kThreads>(v, partials, node_block_id());
 }
@@ -397,7 +453,7 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
   if (sc->done) return;
   constexpr int TY = kBY;
   __shared__ T ring[3][1][TY + 2][kHX];
-  const T beta = (T)sc->beta, alpha = (T)sc->alpha, w = cf.inv_diag_poisson, c6 = cf.eps_over_h2;
+  const T beta = (T)sc->beta, alpha = (T)sc->alpha, c6 = cf.eps_over_h2;
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
@@ -407,7 +463,7 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
     raw[0] = r[m];
     raw[1] = p_old[m];
   };
-  auto comb = [&](int, const T* raw, T* out) { out[0] = raw[0] * w + beta * raw[1]; };
+  auto comb = [&](int kk, const T* raw, T* out) { out[0] = raw[0] * plane_eps(d, cf, kk).w + beta * raw[1]; };
   Stage<T, 2, Halo<TY>::NPT> st;
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
   stage_store<TY>(ring, st, tc.k0 - 1, comb);
@@ -432,9 +488,16 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
     if (valid) {
       const int sm = slot_of(k - 1), s0 = slot_of(k), sp = slot_of(k + 1);
       const T pc = ring[s0][0][ly + 1][lx + 1];
-      const T s = ring[s0][0][ly + 1][lx] + ring[s0][0][ly + 1][lx + 2] + ring[s0][0][ly][lx + 1] +
-                  ring[s0][0][ly + 2][lx + 1] + ring[sm][0][ly + 1][lx + 1] + ring[sp][0][ly + 1][lx + 1];
-      const T q = c6 * (6 * pc - s);
+      const T sxy = ring[s0][0][ly + 1][lx] + ring[s0][0][ly + 1][lx + 2] + ring[s0][0][ly][lx + 1] +
+                    ring[s0][0][ly + 2][lx + 1];
+      const T pdn = ring[sm][0][ly + 1][lx + 1], pup = ring[sp][0][ly + 1][lx + 1];
+      T q;
+      if (!cf.open) {
+        q = c6 * (6 * pc - (sxy + pdn + pup));
+      } else {
+        const PlaneEps<T> e = plane_eps(d, cf, k);
+        q = e.xy * (4 * pc - sxy) + e.up * (pc - pup) + e.dn * (pc - pdn);
+      }
       const int64_t n = col + d.plane * k;
       p_new[n] = pc;
       x[n] = cx + alpha * cpo;
@@ -452,11 +515,12 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void poisson_cg_b_kernel(Dims d, TileMap tm, Coefs<T> cf,
                                                                 const T* __restrict__ p, T* __restrict__ r,
+                                                                const uint8_t* __restrict__ emask,
                                                                 const CgScalars* sc, double* partials) {
   if (sc->done) return;
   constexpr int TY = kBY;
   __shared__ T ring[3][1][TY + 2][kHX];
-  const T alpha = (T)sc->alpha, w = cf.inv_diag_poisson, c6 = cf.eps_over_h2;
+  const T alpha = (T)sc->alpha, c6 = cf.eps_over_h2;
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
@@ -480,12 +544,17 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_b_kernel(Dims d, TileMap 
     if (valid) {
       const int sm = slot_of(k - 1), s0 = slot_of(k), sp = slot_of(k + 1);
       const T pc = ring[s0][0][ly + 1][lx + 1];
-      const T s = ring[s0][0][ly + 1][lx] + ring[s0][0][ly + 1][lx + 2] + ring[s0][0][ly][lx + 1] +
-                  ring[s0][0][ly + 2][lx + 1] + ring[sm][0][ly + 1][lx + 1] + ring[sp][0][ly + 1][lx + 1];
-      const T q = c6 * (6 * pc - s);
-      const T rn = cr - alpha * q;
+      const T sxy = ring[s0][0][ly + 1][lx] + ring[s0][0][ly + 1][lx + 2] + ring[s0][0][ly][lx + 1] +
+                    ring[s0][0][ly + 2][lx + 1];
+      const T pdn = ring[sm][0][ly + 1][lx + 1], pup = ring[sp][0][ly + 1][lx + 1];
+      const PlaneEps<T> e = plane_eps(d, cf, k);
+      T q;
+      if (!cf.open) q = c6 * (6 * pc - (sxy + pdn + pup));
+      else q = e.xy * (4 * pc - sxy) + e.up * (pc - pup) + e.dn * (pc - pdn);
+      T rn = cr - alpha * q;
+      if (emask != nullptr && k == d.nzf && emask[col] != 0) rn = 0;  // electrode rows stay zero
       r[col + d.plane * k] = rn;
-      a0 += (double)rn * (rn * w);
+      a0 += (double)rn * (rn * e.w);
       a1 += (double)rn * rn;
     }
     cr = nr;
@@ -938,7 +1007,7 @@ __global__ __launch_bounds__(kThreads) void force_kernel(
     for (int c = 0; c < 3; c++) F[c] -= cf.G * cf.inv_h2 * lap[c];
   }
   if (cf.terms & kElec) {
-    const T zp = (k + 1 < d.nz) ? phi[n + pl] : ghost_top[i + (int64_t)d.nx * j];
+    const T zp = (k + 1 < d.nzp) ? phi[n + pl] : ghost_top[i + (int64_t)d.nx * j];
     const T zm = (k > 0) ? phi[n - pl] : cf.phi_bottom;
     F[0] += (phi[nbr(d, i, j, k, 1, 0, 0)] - phi[nbr(d, i, j, k, -1, 0, 0)]) * cf.inv_2h;
     F[1] += (phi[nbr(d, i, j, k, 0, 1, 0)] - phi[nbr(d, i, j, k, 0, -1, 0)]) * cf.inv_2h;
@@ -1056,20 +1125,15 @@ __global__ __launch_bounds__(kThreads) void energy_kernel(Dims d, Coefs<double> 
       v[1] = 0.5 * cf.G * cf.h * s;
     }
     if (cf.terms & kElec) {
-      const bool up = k + 1 < d.nz, dn = k > 0;
+      // applied part -h^3 P . E_app; the polarisation part is a sum over the
+      // potential grid (elec_quad_kernel)
       const int64_t nxp = nbr(d, i, j, k, 1, 0, 0), nxm = nbr(d, i, j, k, -1, 0, 0);
       const int64_t nyp = nbr(d, i, j, k, 0, 1, 0), nym = nbr(d, i, j, k, 0, -1, 0);
-      const double rho = (Pc(0, nxp) - Pc(0, nxm) + Pc(1, nyp) - Pc(1, nym) + (up ? Pc(2, n + pl) : 0.0) -
-                          (dn ? Pc(2, n - pl) : 0.0)) * cf.inv_2h;
-      auto fp = [&](int64_t m) { return phi[m] - phi_bc[m]; };
-      const double f0 = fp(n);
-      const double sn = fp(nxp) + fp(nxm) + fp(nyp) + fp(nym) + (up ? fp(n + pl) : 0.0) + (dn ? fp(n - pl) : 0.0);
-      const double Af = cf.eps_over_h2 * (6 * f0 - sn);
-      const double zp = up ? phi_bc[n + pl] : ghost_top[i + (int64_t)d.nx * j];
-      const double zm = dn ? phi_bc[n - pl] : cf.phi_bottom;
+      const double zp = k + 1 < d.nzp ? phi_bc[n + pl] : ghost_top[i + (int64_t)d.nx * j];
+      const double zm = k > 0 ? phi_bc[n - pl] : cf.phi_bottom;
       const double E[3] = {-(phi_bc[nxp] - phi_bc[nxm]) * cf.inv_2h, -(phi_bc[nyp] - phi_bc[nym]) * cf.inv_2h,
                            -(zp - zm) * cf.inv_2h};
-      v[2] = h3 * (-rho * f0 - 0.5 * f0 * Af) - h3 * (p[0] * E[0] + p[1] * E[1] + p[2] * E[2]);
+      v[2] = -h3 * (p[0] * E[0] + p[1] * E[1] + p[2] * E[2]);
     }
     if (cf.terms & kElas) {
       // eps0^T C (M eps0) / 2 on every row
@@ -1116,6 +1180,46 @@ __global__ __launch_bounds__(kThreads) void energy_kernel(Dims d, Coefs<double> 
     }
   }
   block_partials<4, kThreads>(v, partials, node_block_id());
+}
+
+// Polarisation part of the electrostatic energy, (h^3/2) f^T A f at the
+// stationary point of -rho^T f - f^T A f / 2 (f = phi - phi_bc, the
+// potential of P alone): per node of the potential grid h^3 (-rho f - f (A
+// f) / 2), whose sum has an error second order in the solve error.
+template <typename S>
+__global__ __launch_bounds__(kThreads) void elec_quad_kernel(Dims d, Coefs<double> cf, const S* __restrict__ P,
+                                                             const double* __restrict__ phi,
+                                                             const double* __restrict__ phi_bc,
+                                                             const uint8_t* __restrict__ emask, double* partials) {
+  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
+  double v[1] = {0.0};
+  auto is_el = [&](int kk, int64_t c) { return emask != nullptr && kk == d.nzf && emask[c] != 0; };
+  if (i < d.nx && j < d.ny) {
+    const int64_t Nf = d.Nf, pl = d.plane;
+    const int64_t col = i + (int64_t)d.nx * j, n = col + pl * k;
+    if (!is_el(k, col)) {
+      const int64_t cxp = wrap(i + 1, d.nx) + (int64_t)d.nx * j, cxm = wrap(i - 1, d.nx) + (int64_t)d.nx * j;
+      const int64_t cyp = i + (int64_t)d.nx * wrap(j + 1, d.ny), cym = i + (int64_t)d.nx * wrap(j - 1, d.ny);
+      auto Pc = [&](int c, int64_t m) -> double { return (double)P[c * Nf + m]; };
+      double rho = 0.0;
+      if (k < d.nzf) rho += Pc(0, cxp + pl * k) - Pc(0, cxm + pl * k) + Pc(1, cyp + pl * k) - Pc(1, cym + pl * k);
+      if (k + 1 < d.nzf) rho += Pc(2, n + pl);
+      if (k > 0 && k - 1 < d.nzf) rho -= Pc(2, n - pl);
+      rho *= cf.inv_2h;
+      auto f = [&](int kk, int64_t c) -> double {
+        const int64_t m = c + pl * kk;
+        return is_el(kk, c) ? 0.0 : phi[m] - phi_bc[m];
+      };
+      const double f0 = f(k, col);
+      const double sxy = f(k, cxp) + f(k, cxm) + f(k, cyp) + f(k, cym);
+      const double fup = k + 1 < d.nz ? f(k + 1, col) : 0.0, fdn = k > 0 ? f(k - 1, col) : 0.0;
+      const PlaneEps<double> e = plane_eps(d, cf, k);
+      const double Af = e.xy * (4 * f0 - sxy) + e.up * (f0 - fup) + e.dn * (f0 - fdn);
+      const double h3 = cf.h * cf.h * cf.h;
+      v[0] = h3 * (-rho * f0 - 0.5 * f0 * Af);
+    }
+  }
+  block_partials<1, kThreads>(v, partials, node_block_id());
 }
 
 // ---------------------------------------------------------------------------
@@ -1165,7 +1269,7 @@ __global__ __launch_bounds__(kThreads) void hvp_kernel(Dims d, Coefs<double> cf,
     }
   }
   if (cf.terms & kElec) {
-    const double zp = (k + 1 < d.nz) ? psi[n + pl] : 0.0;
+    const double zp = (k + 1 < d.nzp) ? psi[n + pl] : 0.0;
     const double zm = (k > 0) ? psi[n - pl] : 0.0;
     acc[0] += (psi[nbr(d, i, j, k, 1, 0, 0)] - psi[nbr(d, i, j, k, -1, 0, 0)]) * cf.inv_2h;
     acc[1] += (psi[nbr(d, i, j, k, 0, 1, 0)] - psi[nbr(d, i, j, k, 0, -1, 0)]) * cf.inv_2h;
@@ -1254,7 +1358,7 @@ __global__ __launch_bounds__(kThreads) void theta_dot_kernel(Dims d, Coefs<doubl
     const int64_t n = i + (int64_t)d.nx * j + pl * k;
     if (phi_e) {
       const double ghost = (i >= x0 && i < x1 && j >= y0 && j < y1) ? 1.0 : 0.0;
-      const double zp = (k + 1 < d.nz) ? phi_e[n + pl] : ghost;
+      const double zp = (k + 1 < d.nzp) ? phi_e[n + pl] : ghost;
       const double zm = (k > 0) ? phi_e[n - pl] : 0.0;
       const double E0 = -(phi_e[nbr(d, i, j, k, 1, 0, 0)] - phi_e[nbr(d, i, j, k, -1, 0, 0)]) * cf.inv_2h;
       const double E1 = -(phi_e[nbr(d, i, j, k, 0, 1, 0)] - phi_e[nbr(d, i, j, k, 0, -1, 0)]) * cf.inv_2h;
@@ -1370,10 +1474,10 @@ hipError_t launch_refine_update(double* x64, float* x32, const float* d, int64_t
 
 template <typename T, typename S, typename R>
 hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
-                                int with_bc, const T* ghost_top, T phi_bottom, const T* x, R* r, R* p, R* dz,
-                                double* partials, hipStream_t s) {
+                                int with_bc, const T* ghost_top, T phi_bottom, const uint8_t* emask, T* x, R* r,
+                                R* p, R* dz, double* partials, hipStream_t s) {
   poisson_setup_kernel<T, S, R><<<node_grid(d), node_block(), 0, s>>>(d, cf, P, V, cdt, with_P, with_bc, ghost_top,
-                                                                      phi_bottom, x, r, p, dz, partials);
+                                                                      phi_bottom, emask, x, r, p, dz, partials);
   return hipGetLastError();
 }
 
@@ -1386,8 +1490,8 @@ hipError_t launch_poisson_cg_a(const Dims& d, const TileMap& tm, const Coefs<T>&
 
 template <typename T>
 hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* p, T* r,
-                               const CgScalars* sc, double* partials, hipStream_t s) {
-  poisson_cg_b_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, p, r, sc, partials);
+                               const uint8_t* emask, const CgScalars* sc, double* partials, hipStream_t s) {
+  poisson_cg_b_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, p, r, emask, sc, partials);
   return hipGetLastError();
 }
 
@@ -1431,6 +1535,13 @@ hipError_t launch_energy(const Dims& d, const Coefs<double>& cf, const FemTables
 }
 
 template <typename S>
+hipError_t launch_elec_quad(const Dims& dp, const Coefs<double>& cf, const S* P, const double* phi,
+                            const double* phi_bc, const uint8_t* emask, double* partials, hipStream_t s) {
+  elec_quad_kernel<S><<<node_grid(dp), node_block(), 0, s>>>(dp, cf, P, phi, phi_bc, emask, partials);
+  return hipGetLastError();
+}
+
+template <typename S>
 hipError_t launch_hvp(const Dims& d, const Coefs<double>& cf, const FemTables* tb, const S* P, const S* V,
                       double cdt, const double* w, const double* u, const double* psi, const double* du, double* Hw,
                       hipStream_t s) {
@@ -1454,6 +1565,8 @@ hipError_t launch_theta_dot(const Dims& d, const Coefs<double>& cf, const double
 }
 
 #define PF_INSTANTIATE_ADJ(S)                                                                                    \
+  template hipError_t launch_elec_quad<S>(const Dims&, const Coefs<double>&, const S*, const double*,            \
+                                          const double*, const uint8_t*, double*, hipStream_t);                  \
   template hipError_t launch_energy<S>(const Dims&, const Coefs<double>&, const FemTables*, const S*,            \
                                        const double*, const double*, const double*, const double*, double*,      \
                                        hipStream_t);                                                             \
@@ -1473,7 +1586,7 @@ PF_INSTANTIATE_ADJ(float)
   template hipError_t launch_poisson_cg_a<T>(const Dims&, const TileMap&, const Coefs<T>&, const T*, const T*,   \
                                              T*, T*, const CgScalars*, double*, hipStream_t);                    \
   template hipError_t launch_poisson_cg_b<T>(const Dims&, const TileMap&, const Coefs<T>&, const T*, T*,         \
-                                             const CgScalars*, double*, hipStream_t);                            \
+                                             const uint8_t*, const CgScalars*, double*, hipStream_t);            \
   template hipError_t launch_fem_cg_a<T>(const Dims&, const TileMap&, const FemTables*, const T*, const T*, T*,  \
                                          T*, const CgScalars*, double*, hipStream_t);                            \
   template hipError_t launch_fem_cg_b<T>(const Dims&, const TileMap&, const FemTables*, const T*, T*,            \
@@ -1486,7 +1599,7 @@ PF_INSTANTIATE(float)
 
 #define PF_INSTANTIATE_SETUP(T, S, R)                                                                            \
   template hipError_t launch_poisson_setup<T, S, R>(const Dims&, const Coefs<T>&, const S*, const S*, T, int,    \
-                                                    int, const T*, T, const T*, R*, R*, R*, double*,             \
+                                                    int, const T*, T, const uint8_t*, T*, R*, R*, R*, double*,   \
                                                     hipStream_t);                                                \
   template hipError_t launch_fem_setup<T, S, R>(const Dims&, const Coefs<T>&, const FemTables*, const S*,        \
                                                 const S*, T, const T*, T*, R*, R*, R*, R*, double*, hipStream_t);

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libpf.so")
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ENOCONV, PF_ENONFINITE, PF_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PF_INT_PC, PF_INT_EULER = 0, 1
 PF_FP64, PF_FP32_REFINE = 0, 1
+PF_TOP_METAL, PF_TOP_OPEN = 0, 1
 KERNEL_CLASSES = ["poisson_setup", "poisson_a", "poisson_b", "fem_setup", "fem_a", "fem_b", "force", "finish",
                   "reduce", "other"]
 
@@ -60,6 +61,7 @@ class pf_config(ctypes.Structure):
         ("terms", ctypes.c_uint32), ("nonlocal_every", ctypes.c_int32),
         ("extrap_order", ctypes.c_int32),
         ("noise_sigma", ctypes.c_double), ("noise_seed", ctypes.c_uint64),
+        ("top_bc", ctypes.c_int32), ("n_air", ctypes.c_int32), ("eps_air", ctypes.c_double),
     ]
 
 
@@ -147,6 +149,9 @@ def make_config(cfg: PFConfig):
     c.extrap_order = cfg.extrap_order
     c.noise_sigma = cfg.noise_sigma
     c.noise_seed = cfg.noise_seed
+    c.top_bc = {"metal": PF_TOP_METAL, "open": PF_TOP_OPEN}[cfg.top]
+    c.n_air = cfg.n_air
+    c.eps_air = cfg.eps_air
     return c, els
 
 
@@ -230,21 +235,23 @@ class Context:
         raise PFError(st, f"{what}: {status_str(st)}: {msg.decode() if msg else ''}")
 
     def _field(self, t: torch.Tensor, ncomp: int, dtype, name: str) -> torch.Tensor:
-        shape = (ncomp,) + self.cfg.shape if ncomp > 1 else self.cfg.shape
+        """ncomp = 0: a field of the potential grid (phi)."""
+        shape = (ncomp,) + self.cfg.shape if ncomp > 1 else (self.cfg.shape if ncomp == 1 else self.cfg.phi_shape)
         if t.device != self.device or t.dtype != dtype or tuple(t.shape) != shape or not t.is_contiguous():
             raise ValueError(f"{name}: expected a contiguous {dtype} tensor of shape {shape} on {self.device}, "
                              f"got {t.dtype} {tuple(t.shape)} on {t.device}")
         return t
 
     def new_field(self, ncomp: int, dtype=None) -> torch.Tensor:
-        shape = (ncomp,) + self.cfg.shape if ncomp > 1 else self.cfg.shape
+        """ncomp = 0: a field of the potential grid (phi)."""
+        shape = (ncomp,) + self.cfg.shape if ncomp > 1 else (self.cfg.shape if ncomp == 1 else self.cfg.phi_shape)
         return torch.zeros(shape, dtype=dtype or self.state_dtype, device=self.device)
 
     # --- entry points --------------------------------------------------------
     def set_state(self, P: torch.Tensor, phi0: Optional[torch.Tensor] = None, u0: Optional[torch.Tensor] = None):
         self._field(P, 3, self.state_dtype, "P")
         if phi0 is not None:
-            self._field(phi0, 1, torch.float64, "phi0")
+            self._field(phi0, 0, torch.float64, "phi0")
         if u0 is not None:
             self._field(u0, 3, torch.float64, "u0")
         return self._check(self.L.pf_set_state(self.ctx, _ptr(P), _ptr(phi0), _ptr(u0)), "pf_set_state", True)
@@ -252,14 +259,14 @@ class Context:
     def restore_state(self, P, V, phi, u, step: int):
         self._field(P, 3, self.state_dtype, "P")
         self._field(V, 3, self.state_dtype, "V")
-        self._field(phi, 1, torch.float64, "phi")
+        self._field(phi, 0, torch.float64, "phi")
         self._field(u, 3, torch.float64, "u")
         self._check(self.L.pf_restore_state(self.ctx, _ptr(P), _ptr(V), _ptr(phi), _ptr(u), step),
                     "pf_restore_state")
 
     def get_state(self):
         P, V = self.new_field(3), self.new_field(3)
-        phi, u = self.new_field(1, torch.float64), self.new_field(3, torch.float64)
+        phi, u = self.new_field(0, torch.float64), self.new_field(3, torch.float64)
         step = ctypes.c_int64()
         self._check(self.L.pf_get_state(self.ctx, _ptr(P), _ptr(V), _ptr(phi), _ptr(u), ctypes.byref(step)),
                     "pf_get_state")
@@ -275,7 +282,7 @@ class Context:
 
     def solve_phi(self, P: torch.Tensor, phi: Optional[torch.Tensor] = None):
         self._field(P, 3, self.state_dtype, "P")
-        phi = self.new_field(1, torch.float64) if phi is None else self._field(phi, 1, torch.float64, "phi")
+        phi = self.new_field(0, torch.float64) if phi is None else self._field(phi, 0, torch.float64, "phi")
         st = pf_solve_stats()
         s = self.L.pf_solve_phi(self.ctx, _ptr(P), _ptr(phi), ctypes.byref(st))
         self._check(s, "pf_solve_phi", True)
@@ -296,7 +303,7 @@ class Context:
     def force(self, P: torch.Tensor, phi: Optional[torch.Tensor], u: Optional[torch.Tensor]) -> torch.Tensor:
         self._field(P, 3, self.state_dtype, "P")
         if phi is not None:
-            self._field(phi, 1, torch.float64, "phi")
+            self._field(phi, 0, torch.float64, "phi")
         if u is not None:
             self._field(u, 3, torch.float64, "u")
         F = self.new_field(3)

@@ -141,7 +141,8 @@ class Workload:
 def workloads() -> dict:
     """The five problem sizes: a small film, the lateral-switching film that
     the throughput figure is quoted on, its mixed-precision big brother, the
-    adjoint case and the micron-scale film."""
+    adjoint case and the micron-scale film; and the lateral film with the
+    open-circuit top."""
     w = {}
     w["film_32x32x8"] = Workload(
         "film_32x32x8", PFConfig(nx=32, ny=32, nz=8, tol_phi=1e-10, tol_u=1e-10), "noise", 100, seed=1)
@@ -164,6 +165,13 @@ def workloads() -> dict:
         PFConfig(nx=1024, ny=1024, nz=96, electrodes=quarter_strips(1024, 1024), tol_phi=1e-9, tol_u=1e-9,
                  precision="fp32_refine"),
         "domains", 100, seed=5, checkpoint_every=20, region=None)
+    # the lateral film with the open-circuit top of the paper's second
+    # switching study: five air planes, film/air permittivities 100 / 1
+    w["lateral_open_256x256x64"] = Workload(
+        "lateral_open_256x256x64",
+        PFConfig(nx=256, ny=256, nz=64, electrodes=centred_strips(256, 256), tol_phi=1e-9, tol_u=1e-9,
+                 top="open", n_air=5, eps_b=100.0, eps_air=1.0),
+        "domains", 500, seed=6)
     return w
 
 

@@ -1,0 +1,162 @@
+"""GPU open-circuit top (air planes, layered dielectric, zero normal field on
+top, electrode nodes in the first air plane) against the FP64 oracle,
+through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1202_6116_amd.workloads import (
+    PFConfig, Electrode, TERM_ALL, TERM_ELEC, workloads, initial_polarisation, domain_polarisation,
+)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0").to(dtype)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def pf():
+    from paper_1202_6116_amd import pf as m
+    return m
+
+
+def open_cfg(**kw):
+    base = dict(nx=70, ny=13, nz=6, top="open", n_air=5, eps_b=20.0, eps_air=1.0, tol_phi=1e-13, tol_u=1e-13,
+                phi_bottom=0.1, electrodes=[Electrode(5, 20, 0, 13, 2.0), Electrode(40, 56, 2, 11, -1.5)])
+    base.update(kw)
+    return PFConfig(**base)
+
+
+@pytest.mark.parametrize("n_air", [1, 5])
+def test_open_poisson_matches_oracle(pf, oracle_mod, n_air):
+    cfg = open_cfg(n_air=n_air)
+    print(f"case: open poisson n_air={n_air}", flush=True)
+    P = domain_polarisation(cfg, 51, block=4)
+    ref, it, rr, st = oracle_mod.Oracle(cfg).solve_phi(P)
+    phi, stats = pf.Context(cfg).solve_phi(dev(P))
+    assert stats["status"] == 0 and stats["relres"] <= 1e-13
+    assert abs(stats["iters"] - it) <= 3
+    assert rel(host(phi), ref) < TOL
+    assert host(phi)[cfg.nz, 0, 5] == 2.0 and host(phi)[cfg.nz, 5, 45] == -1.5
+
+
+@pytest.mark.parametrize("integrator,ws", [("pc", 1), ("euler", 1), ("pc", 2)])
+def test_open_trajectory_matches_oracle(pf, oracle_mod, integrator, ws):
+    cfg = open_cfg(integrator=integrator, warm_start=ws)
+    print(f"case: open trajectory {integrator} ws={ws}", flush=True)
+    P0 = domain_polarisation(cfg, 52, block=4)
+    o = oracle_mod.Oracle(cfg)
+    P = P0.copy()
+    V, phi, u, _ = o.set_state(P)
+    o.step(P, V, phi, u, 10)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P0))
+    ctx.step(10)
+    Pg, Vg, phig, ug, _ = ctx.get_state()
+    assert rel(host(Pg), P) < TOL
+    assert rel(host(phig), phi) < TOL
+    assert rel(host(ug), u) < TOL
+
+
+@pytest.mark.parametrize("terms", [TERM_ELEC, TERM_ALL])
+def test_open_energy_matches_oracle(pf, oracle_mod, terms):
+    cfg = open_cfg(terms=terms, integrator="euler")
+    print(f"case: open energy terms={terms}", flush=True)
+    P = domain_polarisation(cfg, 53, block=4, std=0.1)
+    ref = oracle_mod.Oracle(cfg).energy(P, tol=1e-13)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P))
+    e = np.array(ctx.energy())
+    assert np.abs(e - ref).max() <= 1e-10 * np.abs(ref).max(), (e, ref)
+
+
+def test_open_full_plane_electrode_equals_metal(pf):
+    """A full-plane electrode at phi_top with eps_air = eps_b on one air
+    plane is the metal top."""
+    metal = PFConfig(nx=70, ny=13, nz=6, eps_b=3.0, phi_bottom=0.1, phi_top=0.4, tol_phi=1e-13, tol_u=1e-13)
+    opened = metal.replace(top="open", n_air=1, eps_air=3.0, phi_top=0.0, electrodes=[Electrode(0, 70, 0, 13, 0.4)])
+    P0 = dev(domain_polarisation(metal, 54, block=4))
+    out = []
+    for c in (metal, opened):
+        ctx = pf.Context(c)
+        ctx.set_state(P0)
+        ctx.step(5)
+        out.append(ctx.get_state())
+    assert rel(host(out[1][0]), host(out[0][0])) < 1e-12
+    assert rel(host(out[1][2])[:6], host(out[0][2])) < 1e-12
+
+
+def test_open_fp32_refined(pf, oracle_mod):
+    cfg = open_cfg(precision="fp32_refine", tol_phi=1e-9, tol_u=1e-9)
+    print("case: open fp32", flush=True)
+    P0 = domain_polarisation(cfg, 55, block=4)
+    o = oracle_mod.Oracle(cfg.replace(precision="fp64"))
+    P = P0.astype(np.float32).astype(np.float64)
+    V, phi, u, _ = o.set_state(P)
+    o.step(P, V, phi, u, 10)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P0, torch.float32))
+    ctx.step(10)
+    Pg, Vg, phig, ug, _ = ctx.get_state()
+    for name, a, b in (("P", Pg, P), ("phi", phig, phi), ("u", ug, u)):
+        assert rel(host(a), b) < 1e-4, name
+
+
+@pytest.mark.parametrize("integrator", ["pc", "euler"])
+def test_open_adjoint_matches_oracle(pf, oracle_mod, integrator):
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    cfg = PFConfig(nx=20, ny=9, nz=5, top="open", n_air=3, eps_b=8.0, eps_air=1.0, tol_phi=1e-13, tol_u=1e-13,
+                   dt=0.05, integrator=integrator, Q11=0.5, Q12=-0.15, Q44=0.2,
+                   electrodes=[Electrode(2, 6, 0, 9, 1.0), Electrode(12, 16, 0, 9, -1.0)])
+    print(f"case: open adjoint {integrator}", flush=True)
+    nsteps = 6
+    P0 = domain_polarisation(cfg, 56, block=3, std=0.2)
+    wgt = np.zeros((3,) + cfg.shape)
+    wgt[0, 2:, 2:6, 3:10] = 1.0 / 3 / 4 / 7
+    J_ref, dth_ref, dP_ref = oracle_mod.Oracle(cfg).gradient(P0, nsteps, wgt)
+    ctx = pf.Context(cfg)
+    P0t = dev(P0).requires_grad_(True)
+    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+    PN = tdgl_steps(P0t, volts, a1, ctx, nsteps, checkpoint_every=4)
+    J = (PN * dev(wgt)).sum()
+    J.backward()
+    assert abs(float(J.detach()) - J_ref) <= 1e-10 * abs(J_ref)
+    g = np.concatenate([volts.grad.cpu().numpy(), [a1.grad.item()]])
+    assert rel(g, dth_ref) < 1e-7, (g, dth_ref)
+    assert rel(host(P0t.grad), dP_ref) < 1e-7
+
+
+def test_open_lateral_256_full_size_properties(pf, oracle_mod):
+    """The open-top lateral film in the benchmark's launch configuration: the
+    GPU solution satisfies the oracle's residual test on the potential
+    grid, and the GPU force equals the oracle's force on the GPU fields."""
+    w = workloads()["lateral_open_256x256x64"]
+    cfg = w.cfg
+    print("case: lateral_open_256x256x64 solves + force", flush=True)
+    o = oracle_mod.Oracle(cfg)
+    P0 = initial_polarisation(w)
+    ctx = pf.Context(cfg)
+    Pd = dev(P0)
+    phi, st1 = ctx.solve_phi(Pd)
+    u, st2 = ctx.solve_u(Pd)
+    assert st1["status"] == 0 and st2["status"] == 0
+    phi_h, u_h = host(phi), host(u)
+    b = o.poisson_rhs(P0)
+    r = b - o.poisson_apply(phi_h)
+    assert np.linalg.norm(r) <= 1.05 * cfg.tol_phi * np.linalg.norm(b)
+    F = host(ctx.force(Pd, phi, u))
+    assert rel(F, o.force(P0, phi_h, u_h)) < 1e-12

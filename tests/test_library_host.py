@@ -36,12 +36,16 @@ def test_library_exports_every_declared_symbol():
     dict(electrodes=[Electrode(5, 5, 0, 4, 1.0)]),                                  # empty
     dict(C12=2.0), dict(terms=16), dict(integrator="leapfrog"), dict(warm_start=3),
     dict(extrap_order=9), dict(extrap_order=-1), dict(noise_sigma=-0.1), dict(noise_sigma=float("nan")),
+    dict(top="open", n_air=0), dict(top="open", n_air=17), dict(top="open", eps_air=0.0), dict(top_bc=5),
 ])
 def test_invalid_configurations_are_rejected(bad):
     cfg = PFConfig(nx=32, ny=8, nz=4)
-    if "integrator" in bad:
+    if "integrator" in bad or "top_bc" in bad:
         c, keep = pf.make_config(cfg)
-        c.integrator = 7
+        if "integrator" in bad:
+            c.integrator = 7
+        else:
+            c.top_bc = bad["top_bc"]
         n = ctypes.c_size_t()
         assert pf.lib().pf_workspace_size(ctypes.byref(c), ctypes.byref(n)) == pf.PF_EINVAL
         return
@@ -55,6 +59,9 @@ def test_workspace_size_scales_with_grid():
     b = pf.pf_workspace_size(PFConfig(nx=64, ny=32, nz=8))
     assert 1.8 < b / a < 2.2
     assert a % 256 == 0
+    # the open top adds the air planes to the potential-grid arrays only
+    c = pf.pf_workspace_size(PFConfig(nx=32, ny=32, nz=8, top="open", n_air=4))
+    assert a < c < 1.5 * a
 
 
 def test_status_strings():
