@@ -71,6 +71,12 @@ typedef struct {
                                      OR_TOP_OPEN: n_air air planes, zero normal field on top */
     int32_t n_air;                /* air planes of the potential grid (open top) */
     double eps_air;               /* permittivity of the air planes (open top) */
+    double misfit[3];             /* substrate strain imposed on the film: xx, yy and engineering
+                                     xy, grid frame (the clamp then holds an affine displacement) */
+    double rot[9];                /* crystal-to-grid rotation R, row-major: v_grid = R v_crystal */
+    /* derived by or_prepare from the crystal coefficients and R: */
+    double Cg[36];                /* stiffness in the grid frame, Voigt 6x6 */
+    double Qv[6][3][3];           /* eps0_v = P^T Qv[v] P (grid frame, engineering shear) */
 } or_params;
 
 typedef struct {
@@ -117,68 +123,141 @@ static double dot(const double *a, const double *b, int64_t n) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Crystal and grid frames                                                   */
+/* ------------------------------------------------------------------------ */
+/* The Landau coefficients, C and Q are given on the crystal axes; the grid
+ * axes are R times them (Sec. II distinguishes crystal directions from grid
+ * directions).  P is held on the grid axes: its crystal components are
+ * R^T P.  Voigt order (xx, yy, zz, xy, yz, zx).                              */
+
+static const int voigt_i[6] = {0, 1, 2, 0, 1, 2}, voigt_j[6] = {0, 1, 2, 1, 2, 0};
+
+/* Cubic fourth-order tensors: T_iiii = d11, T_iijj = d12 (i != j),
+ * T_ijij = T_ijji = d44 (i != j). */
+static double cubic_tensor(double d11, double d12, double d44, int i, int j, int k, int l) {
+    if (i == j && k == l) return i == k ? d11 : d12;
+    if (i != j && ((i == k && j == l) || (i == l && j == k))) return d44;
+    return 0.0;
+}
+
+/* T'_ijkl = R_ia R_jb R_kc R_ld T_abcd. */
+static double rotated(const double R[9], double d11, double d12, double d44, int i, int j, int k, int l) {
+    double s = 0;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++)
+            for (int c = 0; c < 3; c++)
+                for (int d = 0; d < 3; d++) {
+                    double t = cubic_tensor(d11, d12, d44, a, b, c, d);
+                    if (t != 0) s += R[3 * i + a] * R[3 * j + b] * R[3 * k + c] * R[3 * l + d] * t;
+                }
+    return s;
+}
+
+/* Fills the grid-frame stiffness (Voigt, tensor stress against engineering
+ * strain: C_vw = C'_{ij kl}) and the electrostriction forms: the tensor
+ * eigenstrain is eps0_ij = Q'_ijkl P_k P_l with the crystal Q_iiii = Q11,
+ * Q_iijj = Q12 and Q_ijij = Q_ijji = Q44/2 (so that eps0_ij = Q44 Pi Pj on
+ * the crystal axes, Eq. 15); the engineering shear doubles it. */
+void or_prepare(or_params *p) {
+    for (int v = 0; v < 6; v++)
+        for (int w = 0; w < 6; w++)
+            p->Cg[6 * v + w] = rotated(p->rot, p->C11, p->C12, p->C44, voigt_i[v], voigt_j[v], voigt_i[w], voigt_j[w]);
+    for (int v = 0; v < 6; v++) {
+        double scale = v < 3 ? 1.0 : 2.0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double qab = rotated(p->rot, p->Q11, p->Q12, 0.5 * p->Q44, voigt_i[v], voigt_j[v], a, b);
+                double qba = rotated(p->rot, p->Q11, p->Q12, 0.5 * p->Q44, voigt_i[v], voigt_j[v], b, a);
+                p->Qv[v][a][b] = scale * 0.5 * (qab + qba);
+            }
+    }
+}
+
+static void to_crystal(const or_params *p, const double P[3], double c[3]) {
+    for (int a = 0; a < 3; a++) c[a] = p->rot[a] * P[0] + p->rot[3 + a] * P[1] + p->rot[6 + a] * P[2];
+}
+
+static void to_grid(const or_params *p, const double c[3], double P[3]) {
+    for (int i = 0; i < 3; i++) P[i] = p->rot[3 * i] * c[0] + p->rot[3 * i + 1] * c[1] + p->rot[3 * i + 2] * c[2];
+}
+
+/* ------------------------------------------------------------------------ */
 /* Landau energy (Eq. 1) and its derivatives                                 */
 /* ------------------------------------------------------------------------ */
+/* Eq. 1 on the crystal components p = R^T P.                                */
 
-static double landau_energy_density(const or_params *p, double x, double y, double z) {
-    double x2 = x * x, y2 = y * y, z2 = z * z;
+static double landau_energy_density(const or_params *p, double X, double Y, double Z) {
+    double P[3] = {X, Y, Z}, c[3];
+    to_crystal(p, P, c);
+    double x2 = c[0] * c[0], y2 = c[1] * c[1], z2 = c[2] * c[2];
     return p->a1 * (x2 + y2 + z2) + p->a11 * (x2 * x2 + y2 * y2 + z2 * z2)
          + p->a12 * (x2 * y2 + y2 * z2 + z2 * x2);
 }
 
-/* dF_bulk/dP_x = 2 a1 Px + 4 a11 Px^3 + 2 a12 Px (Py^2 + Pz^2), cyclic. */
-static void landau_gradient(const or_params *p, double x, double y, double z, double g[3]) {
-    double x2 = x * x, y2 = y * y, z2 = z * z;
-    g[0] = 2 * p->a1 * x + 4 * p->a11 * x2 * x + 2 * p->a12 * x * (y2 + z2);
-    g[1] = 2 * p->a1 * y + 4 * p->a11 * y2 * y + 2 * p->a12 * y * (z2 + x2);
-    g[2] = 2 * p->a1 * z + 4 * p->a11 * z2 * z + 2 * p->a12 * z * (x2 + y2);
+/* Crystal frame: dF_bulk/dp_x = 2 a1 px + 4 a11 px^3 + 2 a12 px (py^2 + pz^2),
+ * cyclic; the grid-frame gradient is R times it. */
+static void landau_gradient(const or_params *p, double X, double Y, double Z, double g[3]) {
+    double P[3] = {X, Y, Z}, c[3], gc[3];
+    to_crystal(p, P, c);
+    double x = c[0], y = c[1], z = c[2], x2 = x * x, y2 = y * y, z2 = z * z;
+    gc[0] = 2 * p->a1 * x + 4 * p->a11 * x2 * x + 2 * p->a12 * x * (y2 + z2);
+    gc[1] = 2 * p->a1 * y + 4 * p->a11 * y2 * y + 2 * p->a12 * y * (z2 + x2);
+    gc[2] = 2 * p->a1 * z + 4 * p->a11 * z2 * z + 2 * p->a12 * z * (x2 + y2);
+    to_grid(p, gc, g);
 }
 
-/* Second derivatives of Eq. 1 (symmetric 3x3). */
-static void landau_hessian(const or_params *p, double x, double y, double z, double H[3][3]) {
-    double x2 = x * x, y2 = y * y, z2 = z * z;
-    H[0][0] = 2 * p->a1 + 12 * p->a11 * x2 + 2 * p->a12 * (y2 + z2);
-    H[1][1] = 2 * p->a1 + 12 * p->a11 * y2 + 2 * p->a12 * (z2 + x2);
-    H[2][2] = 2 * p->a1 + 12 * p->a11 * z2 + 2 * p->a12 * (x2 + y2);
-    H[0][1] = H[1][0] = 4 * p->a12 * x * y;
-    H[1][2] = H[2][1] = 4 * p->a12 * y * z;
-    H[0][2] = H[2][0] = 4 * p->a12 * x * z;
+/* Second derivatives of Eq. 1: R Hc R^T with the crystal-frame Hessian Hc. */
+static void landau_hessian(const or_params *p, double X, double Y, double Z, double H[3][3]) {
+    double P[3] = {X, Y, Z}, c[3], Hc[3][3];
+    to_crystal(p, P, c);
+    double x = c[0], y = c[1], z = c[2], x2 = x * x, y2 = y * y, z2 = z * z;
+    Hc[0][0] = 2 * p->a1 + 12 * p->a11 * x2 + 2 * p->a12 * (y2 + z2);
+    Hc[1][1] = 2 * p->a1 + 12 * p->a11 * y2 + 2 * p->a12 * (z2 + x2);
+    Hc[2][2] = 2 * p->a1 + 12 * p->a11 * z2 + 2 * p->a12 * (x2 + y2);
+    Hc[0][1] = Hc[1][0] = 4 * p->a12 * x * y;
+    Hc[1][2] = Hc[2][1] = 4 * p->a12 * y * z;
+    Hc[0][2] = Hc[2][0] = 4 * p->a12 * x * z;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double s = 0;
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++) s += p->rot[3 * i + a] * Hc[a][b] * p->rot[3 * j + b];
+            H[i][j] = s;
+        }
 }
 
 /* ------------------------------------------------------------------------ */
 /* Electrostriction (Eq. 15, first two lines)                                */
 /* ------------------------------------------------------------------------ */
 
-/* Voigt eigenstrain of one polarisation vector (engineering shear). */
+/* Voigt eigenstrain of one polarisation vector (grid frame, engineering
+ * shear), eps0_v = P^T Qv[v] P. */
 static void eigenstrain(const or_params *p, double x, double y, double z, double e[6]) {
-    double x2 = x * x, y2 = y * y, z2 = z * z;
-    e[0] = p->Q11 * x2 + p->Q12 * (y2 + z2);
-    e[1] = p->Q11 * y2 + p->Q12 * (z2 + x2);
-    e[2] = p->Q11 * z2 + p->Q12 * (x2 + y2);
-    e[3] = 2 * p->Q44 * x * y;
-    e[4] = 2 * p->Q44 * y * z;
-    e[5] = 2 * p->Q44 * z * x;
+    double P[3] = {x, y, z};
+    for (int v = 0; v < 6; v++) {
+        double s = 0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) s += p->Qv[v][a][b] * P[a] * P[b];
+        e[v] = s;
+    }
 }
 
-/* D[v][d] = d eps0_v / d P_d. */
+/* D[v][d] = d eps0_v / d P_d = 2 (Qv[v] P)_d. */
 static void eigenstrain_jacobian(const or_params *p, double x, double y, double z, double D[6][3]) {
-    double Q11 = p->Q11, Q12 = p->Q12, Q44 = p->Q44;
-    D[0][0] = 2 * Q11 * x; D[0][1] = 2 * Q12 * y; D[0][2] = 2 * Q12 * z;
-    D[1][0] = 2 * Q12 * x; D[1][1] = 2 * Q11 * y; D[1][2] = 2 * Q12 * z;
-    D[2][0] = 2 * Q12 * x; D[2][1] = 2 * Q12 * y; D[2][2] = 2 * Q11 * z;
-    D[3][0] = 2 * Q44 * y; D[3][1] = 2 * Q44 * x; D[3][2] = 0;
-    D[4][0] = 0;           D[4][1] = 2 * Q44 * z; D[4][2] = 2 * Q44 * y;
-    D[5][0] = 2 * Q44 * z; D[5][1] = 0;           D[5][2] = 2 * Q44 * x;
+    double P[3] = {x, y, z};
+    for (int v = 0; v < 6; v++)
+        for (int d = 0; d < 3; d++) D[v][d] = 2 * (p->Qv[v][d][0] * P[0] + p->Qv[v][d][1] * P[1] + p->Qv[v][d][2] * P[2]);
 }
 
 /* Second derivative contracted with a stress and a direction:
- * out[d] = sum_v s_v * sum_e d^2 eps0_v / dP_d dP_e * lam_e. */
+ * out[d] = sum_v s_v * sum_e d^2 eps0_v / dP_d dP_e * lam_e = sum_v s_v 2 (Qv[v] lam)_d. */
 static void eigenstrain_hessian_apply(const or_params *p, const double s[6], const double lam[3], double out[3]) {
-    double Q11 = p->Q11, Q12 = p->Q12, Q44 = p->Q44;
-    /* d^2 e0/dPx^2 = 2Q11, d^2 e1/dPx^2 = 2Q12, d^2 e2/dPx^2 = 2Q12, d^2 e3/dPx dPy = 2Q44, ... */
-    out[0] = 2 * (Q11 * s[0] + Q12 * (s[1] + s[2])) * lam[0] + 2 * Q44 * (s[3] * lam[1] + s[5] * lam[2]);
-    out[1] = 2 * (Q11 * s[1] + Q12 * (s[2] + s[0])) * lam[1] + 2 * Q44 * (s[3] * lam[0] + s[4] * lam[2]);
-    out[2] = 2 * (Q11 * s[2] + Q12 * (s[0] + s[1])) * lam[2] + 2 * Q44 * (s[4] * lam[1] + s[5] * lam[0]);
+    for (int d = 0; d < 3; d++) {
+        double a = 0;
+        for (int v = 0; v < 6; v++)
+            a += s[v] * 2 * (p->Qv[v][d][0] * lam[0] + p->Qv[v][d][1] * lam[1] + p->Qv[v][d][2] * lam[2]);
+        out[d] = a;
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -207,12 +286,11 @@ static void shape_natural_derivatives(const double q[3], double dN[8][3]) {
     }
 }
 
-/* Eq. 13 generalised to cubic symmetry (isotropic is C11 - C12 = 2 C44). */
+/* Eq. 13 generalised to cubic symmetry (isotropic is C11 - C12 = 2 C44),
+ * on the grid axes (or_prepare). */
 static void stiffness_matrix(const or_params *p, double C[6][6]) {
-    memset(C, 0, sizeof(double) * 36);
-    for (int r = 0; r < 3; r++)
-        for (int c = 0; c < 3; c++) C[r][c] = (r == c) ? p->C11 : p->C12;
-    C[3][3] = C[4][4] = C[5][5] = p->C44;
+    for (int r = 0; r < 6; r++)
+        for (int c = 0; c < 6; c++) C[r][c] = p->Cg[6 * r + c];
 }
 
 /* For one quadrature point q: Eq. 9-12.  Returns |J| and fills B (6x24) and N. */
@@ -332,14 +410,19 @@ static int64_t element_node(const or_params *p, int ci, int cj, int ck, int b) {
 
 static int element_exists(const or_params *p, int ck) { return ck >= 0 && ck <= p->nz - 2; }
 
-/* Nodal eigenstrain field (Voigt, e0[v*N + n]) of a polarisation field. */
+/* Nodal eigenstrain field (Voigt, e0[v*N + n]) of a polarisation field,
+ * relative to the substrate strain. */
 void or_nodal_eigenstrain(const or_params *p, const double *P, double *e0) {
     int64_t N = nnodes(p);
+    /* The substrate holds the film at the in-plane strain eps_s: with the
+     * affine displacement of that strain split off (the clamp then holds
+     * u = 0), the elastic strain is B u - (eps0 - eps_s).                   */
+    const double es[6] = {p->misfit[0], p->misfit[1], 0.0, p->misfit[2], 0.0, 0.0};
     #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++) {
         double e[6];
         eigenstrain(p, P[n], P[N + n], P[2 * N + n], e);
-        for (int v = 0; v < 6; v++) e0[v * N + n] = e[v];
+        for (int v = 0; v < 6; v++) e0[v * N + n] = e[v] - es[v];
     }
 }
 

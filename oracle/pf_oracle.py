@@ -57,6 +57,10 @@ class OrParams(ctypes.Structure):
         ("top_bc", ctypes.c_int32),
         ("n_air", ctypes.c_int32),
         ("eps_air", ctypes.c_double),
+        ("misfit", ctypes.c_double * 3),
+        ("rot", ctypes.c_double * 9),
+        ("Cg", ctypes.c_double * 36),
+        ("Qv", ctypes.c_double * 54),
     ]
 
 
@@ -118,6 +122,7 @@ def lib():
             "or_philox4x32_10": (None, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
                                         ctypes.POINTER(ctypes.c_uint32)]),
             "or_noise": (None, [P, ctypes.c_int64, d]),
+            "or_prepare": (None, [P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -175,6 +180,9 @@ class Oracle:
         p.top_bc = 1 if cfg.top == "open" else 0
         p.n_air = cfg.n_air
         p.eps_air = cfg.eps_air
+        p.misfit[:] = [float(x) for x in cfg.misfit]
+        p.rot[:] = [float(x) for x in cfg.rotation]
+        self.lib.or_prepare(ctypes.byref(p))
         self.p = p
         self.pp = ctypes.byref(p)
         self.N = cfg.nodes
@@ -195,6 +203,10 @@ class Oracle:
         return np.ascontiguousarray(a, dtype=np.float64)
 
     # --- element and FEM operator ---------------------------------------
+    def grid_stiffness(self):
+        """The 6x6 Voigt stiffness on the grid axes."""
+        return np.array(self.p.Cg[:]).reshape(6, 6)
+
     def element_stiffness(self):
         Ke = np.zeros((24, 24))
         self.lib.or_element_stiffness(self.pp, _ptr(Ke))

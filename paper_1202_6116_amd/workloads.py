@@ -82,6 +82,8 @@ class PFConfig:
     top: str = "metal"              # "metal": Dirichlet plane above the film; "open": air layers, Neumann top
     n_air: int = 5                  # open top: air planes of the potential grid above the film
     eps_air: float = 1.0            # open top: permittivity of the air planes
+    misfit: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # substrate strain: xx, yy, engineering xy
+    rotation: Tuple[float, ...] = (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0)  # crystal-to-grid R, row-major
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -204,6 +206,16 @@ def initial_polarisation(w: Workload) -> np.ndarray:
     if w.init == "noise":
         return noise_polarisation(w.cfg, w.seed)
     return domain_polarisation(w.cfg, w.seed)
+
+
+def axis_rotation(axis, angle: float) -> Tuple[float, ...]:
+    """Row-major rotation matrix by `angle` (radians) about the unit vector
+    along `axis` (Rodrigues' formula), as a PFConfig.rotation value."""
+    k = np.asarray(axis, dtype=float)
+    k = k / np.linalg.norm(k)
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    R = np.eye(3) + np.sin(angle) * K + (1 - np.cos(angle)) * (K @ K)
+    return tuple(float(x) for x in R.ravel())
 
 
 def random_field(shape: Tuple[int, ...], seed: int, scale: float = 1.0) -> np.ndarray:
