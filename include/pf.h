@@ -127,6 +127,14 @@ typedef struct {
   int32_t top_bc;               /* PF_TOP_METAL (ghost plane) or PF_TOP_OPEN (air) */
   int32_t n_air;                /* PF_TOP_OPEN: air planes, 1 .. 4 nz */
   double eps_air;               /* PF_TOP_OPEN: permittivity of the air (> 0) */
+  double misfit[3];             /* in-plane strain the substrate imposes on the film
+                                   (xx, yy, engineering xy; grid axes): the clamped
+                                   plane holds the affine displacement of that strain
+                                   and u is the displacement relative to it (Sec. III.B) */
+  double rotation[9];           /* crystal-to-grid rotation R, row-major (v_grid =
+                                   R v_crystal; all zeros: identity).  a1, a11, a12,
+                                   C and Q are crystal-axis coefficients; P, E, u and
+                                   the stresses live on the grid axes (Sec. II) */
 } pf_config;
 
 typedef struct {

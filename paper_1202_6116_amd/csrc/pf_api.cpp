@@ -41,13 +41,13 @@ template <typename T>
 hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* p, T* r,
                                const uint8_t* emask, const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T, typename S, typename R>
-hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const S* P, const S* V, T cdt,
-                            const T* W, T* x, R* r, R* p0, R* p1, R* dz, double* partials, hipStream_t s);
+hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, bool gen, const S* P, const S* V,
+                            T cdt, const T* W, T* x, R* r, R* p0, R* p1, R* dz, double* partials, hipStream_t s);
 template <typename T>
-hipError_t launch_fem_cg_a(const Dims& d, const TileMap& tm, const FemTables* tb, const T* r, const T* p_old,
-                           T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s);
+hipError_t launch_fem_cg_a(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const T* r,
+                           const T* p_old, T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T>
-hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb, const T* p, T* r,
+hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const T* p, T* r,
                            const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* P, const T* V, T cdt,
@@ -119,13 +119,6 @@ Row1D row1d(double h, int end) {
   return r;
 }
 
-// cubic elastic tensor C_{ijkl} (Voigt C11, C12, C44)
-double cijkl(const pf_config& c, int i, int j, int k, int l) {
-  if (i == j && k == l) return i == k ? c.C11 : c.C12;
-  if ((i == k && j == l) || (i == l && j == k)) return c.C44;
-  return 0.0;
-}
-
 int voigt(int a, int b) {
   if (a == b) return a;
   if ((a == 0 && b == 1) || (a == 1 && b == 0)) return 3;
@@ -133,8 +126,91 @@ int voigt(int a, int b) {
   return 5;
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Crystal frame: grid-frame stiffness and electrostriction
+// ---------------------------------------------------------------------------
+// C, Q and the Landau coefficients are given on the crystal axes; the
+// crystal-to-grid rotation R (all zeros: identity) maps them to the grid.
+
+Material make_material(const pf_config& c) {
+  Material m;
+  bool zero = true;
+  for (int t = 0; t < 9; t++) zero = zero && c.rotation[t] == 0.0;
+  for (int t = 0; t < 9; t++) m.R[t] = zero ? (t % 4 == 0 ? 1.0 : 0.0) : c.rotation[t];
+  m.rotated = false;
+  for (int t = 0; t < 9; t++) m.rotated = m.rotated || m.R[t] != (t % 4 == 0 ? 1.0 : 0.0);
+  // Bond's stress transformation in the Voigt order (xx, yy, zz, xy, yz, zx):
+  // sigma' = M sigma, and with engineering strain C' = M C M^T.
+  static const int vi[6] = {0, 1, 2, 0, 1, 2}, vj[6] = {0, 1, 2, 1, 2, 0};
+  const double* a = m.R;
+  double M[6][6];
+  for (int r = 0; r < 6; r++)
+    for (int q = 0; q < 6; q++) {
+      const int i = vi[r], j = vj[r], k = vi[q], l = vj[q];
+      M[r][q] = q < 3 ? a[3 * i + k] * a[3 * j + k] : a[3 * i + k] * a[3 * j + l] + a[3 * i + l] * a[3 * j + k];
+    }
+  double C0[6][6] = {};
+  for (int r = 0; r < 3; r++)
+    for (int q = 0; q < 3; q++) C0[r][q] = r == q ? c.C11 : c.C12;
+  C0[3][3] = C0[4][4] = C0[5][5] = c.C44;
+  for (int r = 0; r < 6; r++)
+    for (int q = 0; q < 6; q++) {
+      double sum = 0;
+      for (int s = 0; s < 6; s++)
+        for (int t = 0; t < 6; t++) sum += M[r][s] * C0[s][t] * M[q][t];
+      m.C[r][q] = m.rotated ? sum : C0[r][q];
+    }
+  // Eq. 15 as a quadratic form on the grid components: eps0(P) is the
+  // rotated crystal eigenstrain of p = R^T P; its coefficients follow from
+  // evaluations at e_a and e_a + e_b (polarisation identity).
+  auto eps_grid = [&](const double P[3], double e[6]) {
+    double p[3], ec[3][3], eg[3][3];
+    for (int k = 0; k < 3; k++) p[k] = a[k] * P[0] + a[3 + k] * P[1] + a[6 + k] * P[2];
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++)
+        ec[i][j] = i == j ? c.Q11 * p[i] * p[i] + c.Q12 * (p[(i + 1) % 3] * p[(i + 1) % 3] + p[(i + 2) % 3] * p[(i + 2) % 3])
+                          : c.Q44 * p[i] * p[j];
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        double sum = 0;
+        for (int k = 0; k < 3; k++)
+          for (int l = 0; l < 3; l++) sum += a[3 * i + k] * ec[k][l] * a[3 * j + l];
+        eg[i][j] = sum;
+      }
+    for (int v = 0; v < 6; v++) e[v] = (v < 3 ? 1.0 : 2.0) * eg[vi[v]][vj[v]];
+  };
+  double ea[3][6];
+  for (int q = 0; q < 3; q++) {
+    double P[3] = {0, 0, 0};
+    P[q] = 1;
+    eps_grid(P, ea[q]);
+    for (int v = 0; v < 6; v++) m.Qv[v][q] = ea[q][v];
+  }
+  static const int pa[3] = {0, 1, 2}, pb[3] = {1, 2, 0};  // pairs xy, yz, zx
+  for (int t = 0; t < 3; t++) {
+    double P[3] = {0, 0, 0}, e[6];
+    P[pa[t]] = P[pb[t]] = 1;
+    eps_grid(P, e);
+    for (int v = 0; v < 6; v++) m.Qv[v][3 + t] = 0.5 * (e[v] - ea[pa[t]][v] - ea[pb[t]][v]);
+  }
+  // cubic structure on the grid axes: no normal/shear or shear/shear coupling
+  m.cubic = true;
+  for (int r = 0; r < 6; r++)
+    for (int q = 0; q < 6; q++)
+      if ((r < 3) != (q < 3) || (r >= 3 && q >= 3 && r != q)) m.cubic = m.cubic && m.C[r][q] == 0.0;
+  return m;
+}
+
+namespace {
+
+// elastic tensor C_{ijkl} on the grid axes
+double cijkl(const Material& m, int i, int j, int k, int l) { return m.C[voigt(i, j)][voigt(k, l)]; }
+
 void build_tables(const pf_config& c, FemTables* t) {
   std::memset(t, 0, sizeof(*t));
+  const Material mat = make_material(c);
   const Row1D in = row1d(c.h, kEndInterior);
   const Row1D zrow[3] = {row1d(c.h, kEndLow), row1d(c.h, kEndInterior), row1d(c.h, kEndHigh)};
   auto factor = [](const Row1D& r, bool d_row, bool d_col, int o) {
@@ -158,7 +234,7 @@ void build_tables(const pf_config& c, FemTables* t) {
                 double sum = 0;
                 for (int j = 0; j < 3; j++)
                   for (int l = 0; l < 3; l++) {
-                    const double cf = cijkl(c, cc, j, e, l);
+                    const double cf = cijkl(mat, cc, j, e, l);
                     if (cf == 0.0) continue;
                     double p = cf;
                     for (int a = 0; a < 3; a++) p *= factor(*ax[a], a == j, a == l, off[a]);
@@ -188,8 +264,10 @@ void build_tables(const pf_config& c, FemTables* t) {
           t->Ms[zt][o] = ax[0]->m[off[0]] * ax[1]->m[off[1]] * ax[2]->m[off[2]];
         }
       }
-  t->inv_diag[0] = 1.0 / t->K[0][0][0][13];
-  t->inv_diag[1] = 1.0 / t->K[1][0][0][13];
+  for (int cc = 0; cc < 3; cc++) {
+    t->inv_diag[0][cc] = 1.0 / t->K[0][cc][cc][13];
+    t->inv_diag[1][cc] = 1.0 / t->K[1][cc][cc][13];
+  }
 }
 
 
@@ -303,6 +381,7 @@ constexpr int kMaxOuter = 30;
 struct pf_ctx {
   pf_config cfg;
   std::vector<pf_electrode> electrodes;
+  pf::Material mat;          // grid-frame stiffness and electrostriction
   pf::Dims dims;             // film grid
   pf::Dims dims_p;           // potential grid
   pf::Layout lay;
@@ -407,6 +486,23 @@ pf_status validate(const pf_config* c, std::string* why) {
   if (c->extrap_order < 0 || c->extrap_order > kMaxExtrap) return bad("extrap_order must be in 0..8");
   if (!(c->noise_sigma >= 0) || !std::isfinite(c->noise_sigma)) return bad("noise_sigma must be finite and >= 0");
   if (c->top_bc != PF_TOP_METAL && c->top_bc != PF_TOP_OPEN) return bad("unknown top_bc");
+  for (int t = 0; t < 3; t++)
+    if (!std::isfinite(c->misfit[t])) return bad("misfit not finite");
+  {
+    bool zero = true;
+    for (int t = 0; t < 9; t++) zero = zero && c->rotation[t] == 0.0;
+    if (!zero) {
+      const double* R = c->rotation;
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+          const double d = R[3 * i] * R[3 * j] + R[3 * i + 1] * R[3 * j + 1] + R[3 * i + 2] * R[3 * j + 2];
+          if (!(std::fabs(d - (i == j ? 1.0 : 0.0)) <= 1e-10)) return bad("rotation is not orthonormal");
+        }
+      const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                         R[2] * (R[3] * R[7] - R[4] * R[6]);
+      if (!(det > 0)) return bad("rotation must have determinant +1");
+    }
+  }
   if (c->top_bc == PF_TOP_OPEN) {
     if (c->n_air < 1 || c->n_air > 4 * c->nz) return bad("n_air must be in [1, 4 nz] with the open top");
     if (!(c->eps_air > 0) || !std::isfinite(c->eps_air)) return bad("eps_air must be > 0");
@@ -439,6 +535,16 @@ Coefs<T> make_coefs(const pf_ctx* c) {
   k.eps_air_over_h2 = (T)(ea / (g.h * g.h));
   k.eps_iface_over_h2 = (T)(ei / (g.h * g.h));
   k.open = open ? 1 : 0;
+  const Material& m = c->mat;
+  k.rotated = m.rotated ? 1 : 0;
+  for (int t = 0; t < 9; t++) k.R[t] = (T)m.R[t];
+  for (int r = 0; r < 6; r++)
+    for (int q = 0; q < 6; q++) {
+      k.Cg[6 * r + q] = (T)m.C[r][q];
+      k.Qv[r][q] = (T)m.Qv[r][q];
+    }
+  const double es[6] = {g.misfit[0], g.misfit[1], 0.0, g.misfit[2], 0.0, 0.0};
+  for (int v = 0; v < 6; v++) k.es[v] = (T)es[v];
   k.C11 = (T)g.C11;
   k.C12 = (T)g.C12;
   k.C44 = (T)g.C44;
@@ -599,12 +705,15 @@ std::function<hipError_t(int)> fem_iteration(pf_ctx* c, T* r, T* const pb[2], T*
     CgScalars* sc = dev_sc(c, 1);
     double* part = dev_partials(c, 1);
     hipError_t e = timed(c, PF_KC_FEM_A, 1, k, [&] {
-      return launch_fem_cg_a<T>(d, c->tm_f, tb, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
+      return launch_fem_cg_a<T>(d, c->tm_f, tb, !c->mat.cubic, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part,
+                                c->stream);
     });
     if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 1, 1, kRedAlpha, tol, 0, nullptr, 1, k);
     if (e == hipSuccess)
       e = timed(c, PF_KC_FEM_B, 1, k,
-                [&] { return launch_fem_cg_b<T>(d, c->tm_f, tb, pb[(k + 1) & 1], r, sc, part, c->stream); });
+                [&] {
+                  return launch_fem_cg_b<T>(d, c->tm_f, tb, !c->mat.cubic, pb[(k + 1) & 1], r, sc, part, c->stream);
+                });
     if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 2, 1, kRedBeta, tol, 0, nullptr, 1, k);
     return e;
   };
@@ -646,8 +755,8 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
   double* const pb[2] = {at<double>(c, c->lay.fp[0]), at<double>(c, c->lay.fp[1])};
   if (!warm) PF_HIP(c, launch_fill<double>(x, 3 * d.N, 0.0, c->stream));
   PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
-    return launch_fem_setup<double, S, double>(d, cf, tb, P, V, cdt, W, x, r, pb[0], pb[1], nullptr, part,
-                                               c->stream);
+    return launch_fem_setup<double, S, double>(d, cf, tb, !c->mat.cubic, P, V, cdt, W, x, r, pb[0], pb[1], nullptr,
+                                               part, c->stream);
   }));
   PF_HIP(c, reduce(c, part, c->nblocks, 3, 1, kRedSetup, tol, 0, nullptr));
   CgScalars h;
@@ -688,8 +797,8 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
   for (;;) {
     if (fem) {
       PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
-        return launch_fem_setup<double, float, float>(d, cf64, tb, P, V, cdt, nullptr, x64, r, pb[0], pb[1], dz,
-                                                      part, c->stream);
+        return launch_fem_setup<double, float, float>(d, cf64, tb, !c->mat.cubic, P, V, cdt, nullptr, x64, r, pb[0],
+                                                      pb[1], dz, part, c->stream);
       }));
     } else {
       PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
@@ -1123,6 +1232,7 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->cfg = *cfg;
   c->electrodes.assign(cfg->electrodes, cfg->electrodes + cfg->n_electrodes);
   c->cfg.electrodes = c->electrodes.data();
+  c->mat = make_material(*cfg);
   c->dims = film_dims(*cfg);
   c->dims_p = potential_dims(*cfg);
   c->nblocks = node_blocks(c->dims);

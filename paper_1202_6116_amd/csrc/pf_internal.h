@@ -36,8 +36,8 @@ struct FemTables {
   double Su[3][6][3][kTaps];
   // Consistent mass M x M x M, z in {kLow, kInterior, kHigh}.
   double Ms[3][kTaps];
-  // Inverse Jacobi diagonal of K for interior and top rows (all components).
-  double inv_diag[2];
+  // Inverse Jacobi diagonal of K for interior and top rows, per component.
+  double inv_diag[2][3];
 };
 
 // Scalars of one conjugate-gradient solve, resident in device memory.  The
@@ -80,6 +80,17 @@ struct ExtrapRing {
   int m;
 };
 
+// Material on the grid axes (host): rotation R (crystal to grid), the Voigt
+// stiffness C (engineering strain) and the electrostriction quadratic forms,
+// eps0_v = sum_q Qv[v][q] m_q with m = (x^2, y^2, z^2, 2xy, 2yz, 2zx).
+struct Material {
+  double R[9];
+  double C[6][6];
+  double Qv[6][6];
+  bool rotated;  // R is not the identity
+  bool cubic;    // C has the cubic zero pattern on the grid axes
+};
+
 // Per-call description of a node grid: the film grid (nz = nzf) or the
 // potential grid (nz = nzp: the film plus, with the open top, the air planes
 // above it).  nzf, Nf and nzp are the same in both.
@@ -103,6 +114,14 @@ struct Coefs {
   T eps_air_over_h2;    // open top: eps_air / h^2
   T eps_iface_over_h2;  // open top: harmonic mean of eps_b and eps_air / h^2
   int open;             // open top: air planes, zero normal field on top
+  // Rotated crystal frame (rotated != 0): R maps crystal axes to grid axes;
+  // Cg is the grid-frame Voigt stiffness and eps0_v = sum Qv[v][.] of the
+  // products (xx, yy, zz, 2xy, 2yz, 2zx) of the grid components of P.
+  int rotated;
+  T R[9];
+  T Cg[36];
+  T Qv[6][6];
+  T es[6];              // substrate strain (Voigt, engineering shear), subtracted from eps0
   T C11, C12, C44, Q11, Q12, Q44;
   T phi_bottom;
   uint32_t terms;

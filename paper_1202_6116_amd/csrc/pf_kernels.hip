@@ -573,7 +573,7 @@ namespace {
 // K u at a row of type zt (0 interior, 1 top) for a neighbour loader
 // ld(dx, dy, dz, out[3]).  Interior rows skip the structurally zero taps of
 // the coupling blocks (their 1D derivative factor vanishes at offset 0).
-template <typename T, typename Load>
+template <typename T, bool GEN, typename Load>
 __device__ __forceinline__ void fem_K_apply(const FemTables* __restrict__ tb, int zt, Load ld, T out[3]) {
   out[0] = out[1] = out[2] = 0;
   if (zt == 0) {
@@ -591,7 +591,7 @@ __device__ __forceinline__ void fem_K_apply(const FemTables* __restrict__ tb, in
           for (int c = 0; c < 3; c++)
 #pragma unroll
             for (int e = 0; e < 3; e++) {
-              if (c != e && (off[c] == 0 || off[e] == 0)) continue;
+              if (!GEN && c != e && (off[c] == 0 || off[e] == 0)) continue;
               out[c] += (T)tb->K[0][c][e][o] * u[e];
             }
         }
@@ -618,20 +618,44 @@ __device__ __forceinline__ int64_t nbr(const Dims& d, int i, int j, int k, int d
   return wrap(i + dx, d.nx) + (int64_t)d.nx * wrap(j + dy, d.ny) + d.plane * (k + dz);
 }
 
-template <typename T>
+// Nodal eigenstrain of P relative to the substrate strain (Eq. 15; Voigt,
+// engineering shear): the cubic form on crystal-aligned grids, else the
+// grid-frame quadratic forms Qv.
+template <bool ROT = true, typename T>
 __device__ __forceinline__ void eigenstrain(const Coefs<T>& cf, T x, T y, T z, T e[6]) {
+  if (ROT && cf.rotated) {
+    const T m[6] = {x * x, y * y, z * z, 2 * x * y, 2 * y * z, 2 * z * x};
+#pragma unroll
+    for (int v = 0; v < 6; v++) {
+      T a = 0;
+#pragma unroll
+      for (int q = 0; q < 6; q++) a += cf.Qv[v][q] * m[q];
+      e[v] = a - cf.es[v];
+    }
+    return;
+  }
   const T x2 = x * x, y2 = y * y, z2 = z * z;
-  e[0] = cf.Q11 * x2 + cf.Q12 * (y2 + z2);
-  e[1] = cf.Q11 * y2 + cf.Q12 * (z2 + x2);
-  e[2] = cf.Q11 * z2 + cf.Q12 * (x2 + y2);
-  e[3] = 2 * cf.Q44 * x * y;
-  e[4] = 2 * cf.Q44 * y * z;
-  e[5] = 2 * cf.Q44 * z * x;
+  e[0] = cf.Q11 * x2 + cf.Q12 * (y2 + z2) - cf.es[0];
+  e[1] = cf.Q11 * y2 + cf.Q12 * (z2 + x2) - cf.es[1];
+  e[2] = cf.Q11 * z2 + cf.Q12 * (x2 + y2) - cf.es[2];
+  e[3] = 2 * cf.Q44 * x * y - cf.es[3];
+  e[4] = 2 * cf.Q44 * y * z - cf.es[4];
+  e[5] = 2 * cf.Q44 * z * x - cf.es[5];
 }
 
-// sigma = C e for the cubic Voigt stiffness (engineering shear).
-template <typename T>
+// sigma = C e for the Voigt stiffness (engineering shear).
+template <bool ROT = true, typename T>
 __device__ __forceinline__ void cubic_stress(const Coefs<T>& cf, const T e[6], T s[6]) {
+  if (ROT && cf.rotated) {
+#pragma unroll
+    for (int v = 0; v < 6; v++) {
+      T a = 0;
+#pragma unroll
+      for (int w = 0; w < 6; w++) a += cf.Cg[6 * v + w] * e[w];
+      s[v] = a;
+    }
+    return;
+  }
   s[0] = cf.C11 * e[0] + cf.C12 * (e[1] + e[2]);
   s[1] = cf.C11 * e[1] + cf.C12 * (e[2] + e[0]);
   s[2] = cf.C11 * e[2] + cf.C12 * (e[0] + e[1]);
@@ -641,8 +665,20 @@ __device__ __forceinline__ void cubic_stress(const Coefs<T>& cf, const T e[6], T
 }
 
 // (d eps0/dP)(p) w: the eigenstrain linearised at p in direction w.
-template <typename T>
+template <bool ROT = true, typename T>
 __device__ __forceinline__ void eigenstrain_lin(const Coefs<T>& cf, T x, T y, T z, T wx, T wy, T wz, T e[6]) {
+  if (ROT && cf.rotated) {
+    const T m[6] = {2 * x * wx, 2 * y * wy, 2 * z * wz, 2 * (x * wy + y * wx), 2 * (y * wz + z * wy),
+                    2 * (z * wx + x * wz)};
+#pragma unroll
+    for (int v = 0; v < 6; v++) {
+      T a = 0;
+#pragma unroll
+      for (int q = 0; q < 6; q++) a += cf.Qv[v][q] * m[q];
+      e[v] = a;
+    }
+    return;
+  }
   e[0] = 2 * (cf.Q11 * x * wx + cf.Q12 * (y * wy + z * wz));
   e[1] = 2 * (cf.Q11 * y * wy + cf.Q12 * (z * wz + x * wx));
   e[2] = 2 * (cf.Q11 * z * wz + cf.Q12 * (x * wx + y * wy));
@@ -651,12 +687,84 @@ __device__ __forceinline__ void eigenstrain_lin(const Coefs<T>& cf, T x, T y, T 
   e[5] = 2 * cf.Q44 * (z * wx + x * wz);
 }
 
-// s . (d eps0/dP)(p): the elastic driving force of a nodal stress s.
-template <typename T>
+// s . (d eps0/dP)(p): the elastic driving force of a nodal stress s.  Also
+// s . (d2 eps0/dP2) w, which is the same contraction at p = w.
+template <bool ROT = true, typename T>
 __device__ __forceinline__ void stress_pull(const Coefs<T>& cf, const T p[3], const T s[6], T g[3]) {
+  if (ROT && cf.rotated) {
+    // sum_v s_v Qv[v] as a symmetric 3x3 matrix, times 2 p
+    T A[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 6; v++)
+#pragma unroll
+      for (int q = 0; q < 6; q++) A[q] += s[v] * cf.Qv[v][q];
+    g[0] = 2 * (A[0] * p[0] + A[3] * p[1] + A[5] * p[2]);
+    g[1] = 2 * (A[3] * p[0] + A[1] * p[1] + A[4] * p[2]);
+    g[2] = 2 * (A[5] * p[0] + A[4] * p[1] + A[2] * p[2]);
+    return;
+  }
   g[0] = 2 * p[0] * (cf.Q11 * s[0] + cf.Q12 * (s[1] + s[2])) + 2 * cf.Q44 * (p[1] * s[3] + p[2] * s[5]);
   g[1] = 2 * p[1] * (cf.Q11 * s[1] + cf.Q12 * (s[2] + s[0])) + 2 * cf.Q44 * (p[0] * s[3] + p[2] * s[4]);
   g[2] = 2 * p[2] * (cf.Q11 * s[2] + cf.Q12 * (s[0] + s[1])) + 2 * cf.Q44 * (p[1] * s[4] + p[0] * s[5]);
+}
+
+// Landau energy density, gradient and Hessian (Eq. 1) of the crystal
+// components p = R^T P; gradient and Hessian are returned on the grid axes.
+// ROT = false compiles the crystal-aligned forms only (the caller knows the
+// frame is not rotated); ROT = true decides at run time.
+template <bool ROT = true, typename T>
+__device__ __forceinline__ void to_crystal(const Coefs<T>& cf, const T P[3], T c[3]) {
+  if (!(ROT && cf.rotated)) {
+    c[0] = P[0], c[1] = P[1], c[2] = P[2];
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; a++) c[a] = cf.R[a] * P[0] + cf.R[3 + a] * P[1] + cf.R[6 + a] * P[2];
+}
+
+template <bool ROT = true, typename T>
+__device__ __forceinline__ void to_grid(const Coefs<T>& cf, const T c[3], T P[3]) {
+  if (!(ROT && cf.rotated)) {
+    P[0] = c[0], P[1] = c[1], P[2] = c[2];
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; a++) P[a] = cf.R[3 * a] * c[0] + cf.R[3 * a + 1] * c[1] + cf.R[3 * a + 2] * c[2];
+}
+
+template <bool ROT = true, typename T>
+__device__ __forceinline__ T landau_density(const Coefs<T>& cf, const T P[3]) {
+  T c[3];
+  to_crystal<ROT>(cf, P, c);
+  const T x2 = c[0] * c[0], y2 = c[1] * c[1], z2 = c[2] * c[2];
+  return cf.a1 * (x2 + y2 + z2) + cf.a11 * (x2 * x2 + y2 * y2 + z2 * z2) + cf.a12 * (x2 * y2 + y2 * z2 + z2 * x2);
+}
+
+template <bool ROT = true, typename T>
+__device__ __forceinline__ void landau_gradient(const Coefs<T>& cf, const T P[3], T g[3]) {
+  T c[3], gc[3];
+  to_crystal<ROT>(cf, P, c);
+  const T x2 = c[0] * c[0], y2 = c[1] * c[1], z2 = c[2] * c[2];
+  gc[0] = 2 * cf.a1 * c[0] + 4 * cf.a11 * x2 * c[0] + 2 * cf.a12 * c[0] * (y2 + z2);
+  gc[1] = 2 * cf.a1 * c[1] + 4 * cf.a11 * y2 * c[1] + 2 * cf.a12 * c[1] * (z2 + x2);
+  gc[2] = 2 * cf.a1 * c[2] + 4 * cf.a11 * z2 * c[2] + 2 * cf.a12 * c[2] * (x2 + y2);
+  to_grid<ROT>(cf, gc, g);
+}
+
+template <bool ROT = true, typename T>
+__device__ __forceinline__ void landau_hessian_apply(const Coefs<T>& cf, const T P[3], const T w[3], T out[3]) {
+  T c[3], wc[3], oc[3];
+  to_crystal<ROT>(cf, P, c);
+  to_crystal<ROT>(cf, w, wc);
+  const T x2 = c[0] * c[0], y2 = c[1] * c[1], z2 = c[2] * c[2];
+  const T H00 = 2 * cf.a1 + 12 * cf.a11 * x2 + 2 * cf.a12 * (y2 + z2);
+  const T H11 = 2 * cf.a1 + 12 * cf.a11 * y2 + 2 * cf.a12 * (z2 + x2);
+  const T H22 = 2 * cf.a1 + 12 * cf.a11 * z2 + 2 * cf.a12 * (x2 + y2);
+  const T H01 = 4 * cf.a12 * c[0] * c[1], H12 = 4 * cf.a12 * c[1] * c[2], H02 = 4 * cf.a12 * c[0] * c[2];
+  oc[0] = H00 * wc[0] + H01 * wc[1] + H02 * wc[2];
+  oc[1] = H01 * wc[0] + H11 * wc[1] + H12 * wc[2];
+  oc[2] = H02 * wc[0] + H12 * wc[1] + H22 * wc[2];
+  to_grid<ROT>(cf, oc, out);
 }
 
 }  // namespace
@@ -667,7 +775,7 @@ __device__ __forceinline__ void stress_pull(const Coefs<T>& cf, const T p[3], co
 // With W non-null the eigenstrain is replaced by its linearisation at Pp in
 // the direction W, deps0 = (d eps0/dP)(Pp) W (the right-hand side of the
 // adjoint FEM solve).
-template <typename T, typename S, typename R>
+template <typename T, typename S, typename R, bool GEN>
 __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
     Dims d, Coefs<T> cf, const FemTables* __restrict__ tb, const S* __restrict__ P, const S* __restrict__ V, T cdt,
     const T* __restrict__ W, T* __restrict__ x, R* __restrict__ r, R* __restrict__ p0, R* __restrict__ p1,
@@ -723,12 +831,11 @@ __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
         }
       };
       T Kx[3];
-      fem_K_apply<T>(tb, zt, ldx, Kx);
-      const T wdiag = (T)tb->inv_diag[zt];
+      fem_K_apply<T, GEN>(tb, zt, ldx, Kx);
 #pragma unroll
       for (int c = 0; c < 3; c++) {
         const T rr = f[c] - Kx[c];
-        const T z = rr * wdiag;
+        const T z = rr * (T)tb->inv_diag[zt][GEN ? c : 0];
         r[c * N + n] = (R)rr;
         p0[c * N + n] = (R)z;
         if (dz) dz[c * N + n] = 0;
@@ -745,7 +852,7 @@ __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
 // on the clamped plane), q = K p_new, x += alpha_prev p_old; partial p.q.
 // At most 128 VGPRs: four waves per SIMD, so four 256-thread blocks per CU
 // and the whole tile grid resident at once.
-template <typename T>
+template <typename T, bool GEN>
 __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
                                                             const T* __restrict__ r, const T* __restrict__ p_old,
                                                             T* __restrict__ p_new, T* __restrict__ x,
@@ -754,7 +861,9 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
   constexpr int TY = kBY;
   __shared__ T ring[3][3][TY + 2][kHX];
   const T beta = (T)sc->beta, alpha = (T)sc->alpha;
-  const T w_int = (T)tb->inv_diag[0], w_top = (T)tb->inv_diag[1];
+  // Jacobi weights per component (equal for a cubic stiffness on the grid axes)
+  const T w_int[3] = {(T)tb->inv_diag[0][0], (T)tb->inv_diag[0][GEN ? 1 : 0], (T)tb->inv_diag[0][GEN ? 2 : 0]};
+  const T w_top[3] = {(T)tb->inv_diag[1][0], (T)tb->inv_diag[1][GEN ? 1 : 0], (T)tb->inv_diag[1][GEN ? 2 : 0]};
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
@@ -770,9 +879,10 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
     }
   };
   auto comb = [&](int k, const T* raw, T* out) {
-    const T w = (k == d.nz - 1) ? w_top : w_int;
+    const bool top = k == d.nz - 1;
+    const T w0 = top ? w_top[0] : w_int[0];
 #pragma unroll
-    for (int c = 0; c < 3; c++) out[c] = raw[c] * w + beta * raw[3 + c];
+    for (int c = 0; c < 3; c++) out[c] = raw[c] * (GEN ? (top ? w_top[c] : w_int[c]) : w0) + beta * raw[3 + c];
   };
   // centre values (p_old, x) of a plane
   auto centre = [&](int k, T* cv) {
@@ -810,7 +920,7 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
         for (int c = 0; c < 3; c++) u[c] = ring[s][c][ly + 1 + dy][lx + 1 + dx];
       };
       T q[3];
-      fem_K_apply<T>(tb, zt, ld, q);
+      fem_K_apply<T, GEN>(tb, zt, ld, q);
       const int64_t n = col + d.plane * k;
       const int s0 = slot_of(k);
 #pragma unroll
@@ -830,7 +940,7 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
 }
 
 // Iteration kernel B: r -= alpha K p (operator recomputed); partial (r.z, r.r).
-template <typename T>
+template <typename T, bool GEN>
 __global__ __launch_bounds__(kThreads, 4) void fem_cg_b_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
                                                             const T* __restrict__ p, T* __restrict__ r,
                                                             const CgScalars* sc, double* partials) {
@@ -838,7 +948,8 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_b_kernel(Dims d, TileMap t
   constexpr int TY = kBY;
   __shared__ T ring[3][3][TY + 2][kHX];
   const T alpha = (T)sc->alpha;
-  const T w_int = (T)tb->inv_diag[0], w_top = (T)tb->inv_diag[1];
+  const T w_int[3] = {(T)tb->inv_diag[0][0], (T)tb->inv_diag[0][GEN ? 1 : 0], (T)tb->inv_diag[0][GEN ? 2 : 0]};
+  const T w_top[3] = {(T)tb->inv_diag[1][0], (T)tb->inv_diag[1][GEN ? 1 : 0], (T)tb->inv_diag[1][GEN ? 2 : 0]};
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
@@ -886,14 +997,14 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_b_kernel(Dims d, TileMap t
         for (int c = 0; c < 3; c++) u[c] = ring[s][c][ly + 1 + dy][lx + 1 + dx];
       };
       T q[3];
-      fem_K_apply<T>(tb, zt, ld, q);
-      const T w = zt ? w_top : w_int;
+      fem_K_apply<T, GEN>(tb, zt, ld, q);
       const int64_t n = col + d.plane * k;
+      const T w0 = zt ? w_top[0] : w_int[0];
 #pragma unroll
       for (int c = 0; c < 3; c++) {
         const T rn = cv[c] - alpha * q[c];
         r[c * N + n] = rn;
-        a0 += (double)rn * (rn * w);
+        a0 += (double)rn * (rn * (GEN ? (zt ? w_top[c] : w_int[c]) : w0));
         a1 += (double)rn * rn;
       }
     }
@@ -960,7 +1071,7 @@ __global__ void noise_kernel(NoiseSpec ns, int64_t N, double* __restrict__ xi) {
   }
 }
 
-template <typename T>
+template <typename T, bool ROT>
 __global__ __launch_bounds__(kThreads) void force_kernel(
     Dims d, Coefs<T> cf, const FemTables* __restrict__ tb, const T* __restrict__ P, const T* __restrict__ V, T cdt,
     const T* __restrict__ phi, const T* __restrict__ ghost_top, const T* __restrict__ u, int mode, NoiseSpec ns,
@@ -978,10 +1089,10 @@ __global__ __launch_bounds__(kThreads) void force_kernel(
   pp(n, p0);
   T F[3] = {0, 0, 0};
   if (cf.terms & kLandau) {
-    const T x2 = p0[0] * p0[0], y2 = p0[1] * p0[1], z2 = p0[2] * p0[2];
-    F[0] += 2 * cf.a1 * p0[0] + 4 * cf.a11 * x2 * p0[0] + 2 * cf.a12 * p0[0] * (y2 + z2);
-    F[1] += 2 * cf.a1 * p0[1] + 4 * cf.a11 * y2 * p0[1] + 2 * cf.a12 * p0[1] * (z2 + x2);
-    F[2] += 2 * cf.a1 * p0[2] + 4 * cf.a11 * z2 * p0[2] + 2 * cf.a12 * p0[2] * (x2 + y2);
+    T g[3];
+    landau_gradient<ROT>(cf, p0, g);
+#pragma unroll
+    for (int c = 0; c < 3; c++) F[c] += g[c];
   }
   if (cf.terms & kGrad) {
     T a[3], lap[3] = {0, 0, 0};
@@ -1026,7 +1137,7 @@ __global__ __launch_bounds__(kThreads) void force_kernel(
           const int64_t m = nbr(d, i, j, k, dx, dy, dz);
           T a[3], e[6];
           pp(m, a);
-          eigenstrain(cf, a[0], a[1], a[2], e);
+          eigenstrain<ROT>(cf, a[0], a[1], a[2], e);
           const T ms = (T)tb->Ms[zt][o];
           const T uu[3] = {u[m], u[N + m], u[2 * N + m]};
 #pragma unroll
@@ -1037,14 +1148,12 @@ __global__ __launch_bounds__(kThreads) void force_kernel(
             w[q] += acc;
           }
         }
-    T s[6];
-    cubic_stress(cf, w, s);
-    const T g0 = 2 * p0[0] * (cf.Q11 * s[0] + cf.Q12 * (s[1] + s[2])) + 2 * cf.Q44 * (p0[1] * s[3] + p0[2] * s[5]);
-    const T g1 = 2 * p0[1] * (cf.Q11 * s[1] + cf.Q12 * (s[2] + s[0])) + 2 * cf.Q44 * (p0[0] * s[3] + p0[2] * s[4]);
-    const T g2 = 2 * p0[2] * (cf.Q11 * s[2] + cf.Q12 * (s[0] + s[1])) + 2 * cf.Q44 * (p0[1] * s[4] + p0[0] * s[5]);
-    F[0] -= cf.inv_h3 * g0;
-    F[1] -= cf.inv_h3 * g1;
-    F[2] -= cf.inv_h3 * g2;
+    T s[6], g[3];
+    cubic_stress<ROT>(cf, w, s);
+    stress_pull<ROT>(cf, p0, s, g);
+    F[0] -= cf.inv_h3 * g[0];
+    F[1] -= cf.inv_h3 * g[1];
+    F[2] -= cf.inv_h3 * g[2];
   }
 #pragma unroll
   for (int c = 0; c < 3; c++) F[c] *= -cf.L;
@@ -1105,11 +1214,7 @@ __global__ __launch_bounds__(kThreads) void energy_kernel(Dims d, Coefs<double> 
     const double h3 = cf.h * cf.h * cf.h;
     auto Pc = [&](int c, int64_t m) -> double { return (double)P[c * N + m]; };
     const double p[3] = {Pc(0, n), Pc(1, n), Pc(2, n)};
-    if (cf.terms & kLandau) {
-      const double x2 = p[0] * p[0], y2 = p[1] * p[1], z2 = p[2] * p[2];
-      v[0] = h3 * (cf.a1 * (x2 + y2 + z2) + cf.a11 * (x2 * x2 + y2 * y2 + z2 * z2) +
-                   cf.a12 * (x2 * y2 + y2 * z2 + z2 * x2));
-    }
+    if (cf.terms & kLandau) v[0] = h3 * landau_density(cf, p);
     if (cf.terms & kGrad) {
       double s = 0.0;
       const int64_t ms[3] = {nbr(d, i, j, k, 1, 0, 0), nbr(d, i, j, k, 0, 1, 0), k + 1 < d.nz ? n + pl : -1};
@@ -1173,7 +1278,7 @@ __global__ __launch_bounds__(kThreads) void energy_kernel(Dims d, Coefs<double> 
           for (int c = 0; c < 3; c++) uu[c] = (k + dz == 0) ? 0.0 : u[c * N + m];
         };
         double Ku[3];
-        fem_K_apply<double>(tb, zt, ld, Ku);
+        fem_K_apply<double, true>(tb, zt, ld, Ku);
         for (int c = 0; c < 3; c++) el += 0.5 * u[c * N + n] * Ku[c] - u[c * N + n] * f[c];
       }
       v[3] = el;
@@ -1249,14 +1354,9 @@ __global__ __launch_bounds__(kThreads) void hvp_kernel(Dims d, Coefs<double> cf,
   X(n, x0);
   double acc[3] = {0, 0, 0};
   if (cf.terms & kLandau) {
-    const double x2 = x0[0] * x0[0], y2 = x0[1] * x0[1], z2 = x0[2] * x0[2];
-    const double H00 = 2 * cf.a1 + 12 * cf.a11 * x2 + 2 * cf.a12 * (y2 + z2);
-    const double H11 = 2 * cf.a1 + 12 * cf.a11 * y2 + 2 * cf.a12 * (z2 + x2);
-    const double H22 = 2 * cf.a1 + 12 * cf.a11 * z2 + 2 * cf.a12 * (x2 + y2);
-    const double H01 = 4 * cf.a12 * x0[0] * x0[1], H12 = 4 * cf.a12 * x0[1] * x0[2], H02 = 4 * cf.a12 * x0[0] * x0[2];
-    acc[0] += H00 * w0[0] + H01 * w0[1] + H02 * w0[2];
-    acc[1] += H01 * w0[0] + H11 * w0[1] + H12 * w0[2];
-    acc[2] += H02 * w0[0] + H12 * w0[1] + H22 * w0[2];
+    double hl[3];
+    landau_hessian_apply(cf, x0, w0, hl);
+    for (int c = 0; c < 3; c++) acc[c] += hl[c];
   }
   if (cf.terms & kGrad) {
     const int64_t ms[6] = {nbr(d, i, j, k, 1, 0, 0), nbr(d, i, j, k, -1, 0, 0), nbr(d, i, j, k, 0, 1, 0),
@@ -1303,10 +1403,7 @@ __global__ __launch_bounds__(kThreads) void hvp_kernel(Dims d, Coefs<double> cf,
     cubic_stress(cf, ws_, s);
     cubic_stress(cf, wd, ds);
     stress_pull(cf, x0, ds, g);
-    // s . d2eps0/dP2 w
-    hs[0] = 2 * (cf.Q11 * s[0] + cf.Q12 * (s[1] + s[2])) * w0[0] + 2 * cf.Q44 * (s[3] * w0[1] + s[5] * w0[2]);
-    hs[1] = 2 * (cf.Q11 * s[1] + cf.Q12 * (s[2] + s[0])) * w0[1] + 2 * cf.Q44 * (s[3] * w0[0] + s[4] * w0[2]);
-    hs[2] = 2 * (cf.Q11 * s[2] + cf.Q12 * (s[0] + s[1])) * w0[2] + 2 * cf.Q44 * (s[4] * w0[1] + s[5] * w0[0]);
+    stress_pull(cf, w0, s, hs);  // s . d2eps0/dP2 w (eps0 is quadratic in P)
     for (int c = 0; c < 3; c++) acc[c] -= cf.inv_h3 * (g[c] + hs[c]);
   }
   for (int c = 0; c < 3; c++) Hw[c * N + n] = -cf.L * acc[c];
@@ -1496,24 +1593,32 @@ hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>&
 }
 
 template <typename T, typename S, typename R>
-hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const S* P, const S* V, T cdt,
-                            const T* W, T* x, R* r, R* p0, R* p1, R* dz, double* partials, hipStream_t s) {
-  fem_setup_kernel<T, S, R><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, W, x, r, p0, p1, dz,
-                                                                  partials);
+hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, bool gen, const S* P, const S* V,
+                            T cdt, const T* W, T* x, R* r, R* p0, R* p1, R* dz, double* partials, hipStream_t s) {
+  if (gen)
+    fem_setup_kernel<T, S, R, true><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, W, x, r, p0, p1, dz,
+                                                                        partials);
+  else
+    fem_setup_kernel<T, S, R, false><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, W, x, r, p0, p1,
+                                                                         dz, partials);
+  return hipGetLastError();
+}
+
+// gen: the stiffness has no cubic structure on the grid axes (rotated
+// crystal), so no tap of the coupling blocks can be skipped.
+template <typename T>
+hipError_t launch_fem_cg_a(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const T* r,
+                           const T* p_old, T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s) {
+  if (gen) fem_cg_a_kernel<T, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, r, p_old, p_new, x, sc, partials);
+  else fem_cg_a_kernel<T, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, r, p_old, p_new, x, sc, partials);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fem_cg_a(const Dims& d, const TileMap& tm, const FemTables* tb, const T* r, const T* p_old,
-                           T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s) {
-  fem_cg_a_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, r, p_old, p_new, x, sc, partials);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb, const T* p, T* r,
+hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const T* p, T* r,
                            const CgScalars* sc, double* partials, hipStream_t s) {
-  fem_cg_b_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, p, r, sc, partials);
+  if (gen) fem_cg_b_kernel<T, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, p, r, sc, partials);
+  else fem_cg_b_kernel<T, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, p, r, sc, partials);
   return hipGetLastError();
 }
 
@@ -1521,8 +1626,12 @@ template <typename T>
 hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* P, const T* V, T cdt,
                         const T* phi, const T* ghost_top, const T* u, int mode, const NoiseSpec& ns, T* Pn,
                         T* Vn, T* Fout, hipStream_t s) {
-  force_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, phi, ghost_top, u, mode, ns, Pn, Vn,
-                                                        Fout);
+  if (cf.rotated)
+    force_kernel<T, true><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, phi, ghost_top, u, mode, ns,
+                                                              Pn, Vn, Fout);
+  else
+    force_kernel<T, false><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, phi, ghost_top, u, mode, ns,
+                                                               Pn, Vn, Fout);
   return hipGetLastError();
 }
 
@@ -1587,9 +1696,9 @@ PF_INSTANTIATE_ADJ(float)
                                              T*, T*, const CgScalars*, double*, hipStream_t);                    \
   template hipError_t launch_poisson_cg_b<T>(const Dims&, const TileMap&, const Coefs<T>&, const T*, T*,         \
                                              const uint8_t*, const CgScalars*, double*, hipStream_t);            \
-  template hipError_t launch_fem_cg_a<T>(const Dims&, const TileMap&, const FemTables*, const T*, const T*, T*,  \
-                                         T*, const CgScalars*, double*, hipStream_t);                            \
-  template hipError_t launch_fem_cg_b<T>(const Dims&, const TileMap&, const FemTables*, const T*, T*,            \
+  template hipError_t launch_fem_cg_a<T>(const Dims&, const TileMap&, const FemTables*, bool, const T*, const T*, \
+                                         T*, T*, const CgScalars*, double*, hipStream_t);                        \
+  template hipError_t launch_fem_cg_b<T>(const Dims&, const TileMap&, const FemTables*, bool, const T*, T*,      \
                                          const CgScalars*, double*, hipStream_t);                                \
   template hipError_t launch_force<T>(const Dims&, const Coefs<T>&, const FemTables*, const T*, const T*, T,     \
                                       const T*, const T*, const T*, int, const NoiseSpec&, T*, T*, T*, hipStream_t);
@@ -1601,7 +1710,7 @@ PF_INSTANTIATE(float)
   template hipError_t launch_poisson_setup<T, S, R>(const Dims&, const Coefs<T>&, const S*, const S*, T, int,    \
                                                     int, const T*, T, const uint8_t*, T*, R*, R*, R*, double*,   \
                                                     hipStream_t);                                                \
-  template hipError_t launch_fem_setup<T, S, R>(const Dims&, const Coefs<T>&, const FemTables*, const S*,        \
+  template hipError_t launch_fem_setup<T, S, R>(const Dims&, const Coefs<T>&, const FemTables*, bool, const S*,  \
                                                 const S*, T, const T*, T*, R*, R*, R*, R*, double*, hipStream_t);
 
 PF_INSTANTIATE_SETUP(double, double, double)

@@ -62,6 +62,7 @@ class pf_config(ctypes.Structure):
         ("extrap_order", ctypes.c_int32),
         ("noise_sigma", ctypes.c_double), ("noise_seed", ctypes.c_uint64),
         ("top_bc", ctypes.c_int32), ("n_air", ctypes.c_int32), ("eps_air", ctypes.c_double),
+        ("misfit", ctypes.c_double * 3), ("rotation", ctypes.c_double * 9),
     ]
 
 
@@ -152,6 +153,8 @@ def make_config(cfg: PFConfig):
     c.top_bc = {"metal": PF_TOP_METAL, "open": PF_TOP_OPEN}[cfg.top]
     c.n_air = cfg.n_air
     c.eps_air = cfg.eps_air
+    c.misfit[:] = [float(x) for x in cfg.misfit]
+    c.rotation[:] = [float(x) for x in cfg.rotation]
     return c, els
 
 

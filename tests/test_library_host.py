@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_1202_6116_amd import pf
-from paper_1202_6116_amd.workloads import PFConfig, Electrode, random_field
+from paper_1202_6116_amd.workloads import PFConfig, Electrode, random_field, axis_rotation
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -37,6 +37,8 @@ def test_library_exports_every_declared_symbol():
     dict(C12=2.0), dict(terms=16), dict(integrator="leapfrog"), dict(warm_start=3),
     dict(extrap_order=9), dict(extrap_order=-1), dict(noise_sigma=-0.1), dict(noise_sigma=float("nan")),
     dict(top="open", n_air=0), dict(top="open", n_air=17), dict(top="open", eps_air=0.0), dict(top_bc=5),
+    dict(rotation=(1, 0, 0, 0, 1, 0, 0, 0, 1.01)), dict(rotation=(1, 0, 0, 0, 1, 0, 0, 0, -1)),
+    dict(misfit=(0.0, float("inf"), 0.0)),
 ])
 def test_invalid_configurations_are_rejected(bad):
     cfg = PFConfig(nx=32, ny=8, nz=4)
@@ -85,9 +87,14 @@ def voigt_C(cfg):
     return C
 
 
-@pytest.mark.parametrize("h", [1.0, 0.6])
-def test_stiffness_table_matches_oracle_assembly(oracle_mod, h):
+@pytest.mark.parametrize("h,rotation", [(1.0, None), (0.6, None), (0.8, axis_rotation((1.0, 2.0, 3.0), 0.7)),
+                                        (1.0, (0, -1, 0, 1, 0, 0, 0, 0, 1))])
+def test_stiffness_table_matches_oracle_assembly(oracle_mod, h, rotation):
+    """The library's stiffness rows (grid-frame C by Bond's transformation)
+    against the oracle's assembly (C by fourth-order tensor rotation)."""
     cfg = PFConfig(nx=5, ny=5, nz=5, h=h, C11=1.7, C12=0.8, C44=0.5)
+    if rotation is not None:
+        cfg = cfg.replace(rotation=rotation)
     K = oracle_mod.Oracle(cfg).fem_assemble("nodewise")
     t = pf.pf_fem_tables(cfg)["K"]
     N = cfg.nodes
