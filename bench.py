@@ -113,6 +113,50 @@ def adjoint_leg(pf, torch, workloads, initial_polarisation, warm_start):
             "dJ_dV": [float(v) for v in volts.grad], "dJ_da1": float(a1.grad)}
 
 
+def micron_leg(pf, torch, workloads, initial_polarisation, warm_start, steps=5, adj_steps=3, warmup=1):
+    """The micron-scale film (1024x1024x96, FP32 sweeps with FP64 refinement):
+    forward throughput over `steps` steps, then a differentiable run of
+    `adj_steps` steps (one checkpoint segment) and its backward; peak device
+    memory of the whole leg.  J is the mean Pz of the film."""
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    w = workloads()["micron_1024x1024x96_fp32"]
+    cfg = w.cfg.replace(warm_start=warm_start)
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    ctx = pf.Context(cfg, "cuda:0")
+    P0 = torch.from_numpy(initial_polarisation(w)).to("cuda:0").to(ctx.state_dtype)
+    print(f"micron leg: workspace {ctx.ws.numel() / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    ctx.set_state(P0)
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.step(steps)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / steps
+    print(f"micron leg: forward {1e3 * fwd:.1f} ms/step", file=sys.stderr, flush=True)
+    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    PN = tdgl_steps(P0, volts, a1, ctx, adj_steps, adj_steps)
+    J = PN[2].double().mean()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(f"micron leg: differentiable forward {t1 - t0:.1f} s", file=sys.stderr, flush=True)
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(f"micron leg: adjoint {t2 - t1:.1f} s", file=sys.stderr, flush=True)
+    return {"workload": w.name, "cells": cfg.nodes, "steps": steps, "adjoint_steps": adj_steps,
+            "ms_per_step": round(1e3 * fwd, 2), "cell_steps_per_s": cfg.nodes / fwd,
+            "cg_iters_per_step": {"phi": st["iters_phi"] / max(1, st["solves_phi"]),
+                                  "u": st["iters_u"] / max(1, st["solves_u"])},
+            "differentiable_forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+            "adjoint_fwd_ratio": round((t2 - t1) / (t1 - t0), 3),
+            "peak_device_GiB": round(torch.cuda.max_memory_allocated() / 2**30, 2),
+            "dJ_dV": [float(v) for v in volts.grad], "dJ_da1": float(a1.grad)}
+
+
 def precision_leg(pf, torch, workloads, initial_polarisation, warm_start, steps=4, warmup=2):
     """The 512x512x128 lateral film for a few steps in FP32 sweeps with FP64
     refinement and in plain FP64 from the same start; returns both step times
@@ -164,6 +208,8 @@ def main():
                     help="time the steps without per-launch events (the roofline is then omitted)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32+refinement vs FP64 leg")
+    ap.add_argument("--micron", action="store_true",
+                    help="also run the 1024x1024x96 FP32 film: forward throughput, adjoint/forward ratio, peak memory")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 4 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -256,6 +302,11 @@ def main():
         out["adjoint"] = adjoint_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
     if not args.no_precision:
         out["precision"] = precision_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
+    if args.micron:
+        try:
+            out["micron"] = micron_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
+        except Exception as e:  # an optional leg: report, keep the main line
+            out["micron"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(w, it_phi, it_u)
