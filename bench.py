@@ -40,6 +40,14 @@ BYTES_PER_NODE_FP64 = {
 }
 
 
+# HBM bytes per working launch measured with rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (fetch counts scaled by 2.0, writes by 1.0, from a 1 GiB copy)
+# for the current kernels; summary and commands in
+# profiles/fem_cg_a_fp64_lateral_256x256x64.md.  Keyed by workload, precision
+# and kernel class; anything else reports null.
+MEASURED_TRAFFIC = {("lateral_256x256x64", "fp64", "fem_a"): 598.6e6}
+
+
 def nodes_per_launch(cls, cfg):
     if cls in ("fem_a", "fem_b"):
         return cfg.nodes - cfg.nx * cfg.ny
@@ -254,8 +262,13 @@ def main():
         kt = ctx.timing(False)
         return max(wall, e0.elapsed_time(e1) / 1e3), st, kt
 
+    def progress(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
+
     # throughput: K steps, no per-launch events
+    progress(f"{w.name}: warmup done, timing {args.steps} steps")
     secs, stats, _ = timed_steps(args.steps, False)
+    progress(f"{w.name}: {1e3 * secs / args.steps:.1f} ms/step")
     value = cfg.nodes * args.steps / secs
 
     it_phi = stats["iters_phi"] / max(1, stats["solves_phi"])
@@ -290,7 +303,8 @@ def main():
         tot_ms = sum(v[0] for v in kt.values())
         out["roofline"] = {
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": MEASURED_TRAFFIC.get((w.name, cfg.precision, dom)),
             "bytes_per_launch": nbytes, "avg_launch_us": round(avg_s * 1e6, 2),
             "step_alg_GBps": round(tot_bytes / (tot_ms / 1e3) / 1e9, 1),
             "timed_steps": ksteps, "ms_per_step_with_events": round(1e3 * ksecs / ksteps, 2),
@@ -299,15 +313,19 @@ def main():
     del ctx
     torch.cuda.empty_cache()
     if not args.no_adjoint:
+        progress("adjoint leg")
         out["adjoint"] = adjoint_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
     if not args.no_precision:
+        progress("precision leg")
         out["precision"] = precision_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
     if args.micron:
+        progress("micron leg")
         try:
             out["micron"] = micron_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
         except Exception as e:  # an optional leg: report, keep the main line
             out["micron"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
+        progress("oracle baseline")
         try:
             out["cpu_baseline"] = cpu_baseline(w, it_phi, it_u)
         except Exception as e:  # the oracle is test infrastructure; report, don't fail the bench
