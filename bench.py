@@ -210,6 +210,8 @@ def main():
     ap.add_argument("--extrap-order", type=int, default=None,
                     help="with --warm-start 2: number of earlier solutions the polynomial goes through "
                          "(0..8; default: the workload's)")
+    ap.add_argument("--precond", choices=("jacobi", "mg"), default=None,
+                    help="preconditioner of the FEM solves (default: the workload's, Jacobi)")
     ap.add_argument("--nonlocal-every", type=int, default=None,
                     help="refresh phi and u every k steps (default: the workload's, every step)")
     ap.add_argument("--no-kernel-timing", action="store_true",
@@ -238,6 +240,8 @@ def main():
         w.cfg = w.cfg.replace(extrap_order=args.extrap_order)
     if args.nonlocal_every is not None:
         w.cfg = w.cfg.replace(nonlocal_every=args.nonlocal_every)
+    if args.precond is not None:
+        w.cfg = w.cfg.replace(precond=args.precond)
     cfg = w.cfg
     dev = torch.device("cuda:0")
     ctx = pf.Context(cfg, "cuda:0")
@@ -283,7 +287,8 @@ def main():
                    "electrodes": len(cfg.electrodes), "init": w.init, "seed": w.seed,
                    "initial_guess": WARM_START_NAMES[int(cfg.warm_start)],
                    "extrap_order": cfg.extrap_order if cfg.warm_start == 2 else None,
-                   "nonlocal_every": max(1, cfg.nonlocal_every), "precision": cfg.precision},
+                   "nonlocal_every": max(1, cfg.nonlocal_every), "fem_precond": cfg.precond,
+                   "precision": cfg.precision},
         "cg_iters_per_step": {"phi": round(it_phi, 2), "u": round(it_u, 2)},
     }
     if not args.no_kernel_timing:

@@ -76,6 +76,8 @@ typedef enum {
 
 /* terms: which contributions enter the force (tests switch terms off) */
 enum { PF_TERM_LANDAU = 1, PF_TERM_GRAD = 2, PF_TERM_ELEC = 4, PF_TERM_ELAS = 8, PF_TERM_ALL = 15 };
+/* precond: preconditioner of the FEM conjugate gradients */
+enum { PF_PRECOND_JACOBI = 0, PF_PRECOND_MG = 1 };
 /* top_bc: electrostatic condition above the film */
 enum { PF_TOP_METAL = 0, PF_TOP_OPEN = 1 };
 /* integrator */
@@ -135,6 +137,14 @@ typedef struct {
                                    R v_crystal; all zeros: identity).  a1, a11, a12,
                                    C and Q are crystal-axis coefficients; P, E, u and
                                    the stresses live on the grid axes (Sec. II) */
+  int32_t precond;              /* FEM solves: PF_PRECOND_JACOBI (the paper's
+                                   Jacobi-preconditioned CG) or PF_PRECOND_MG (CG
+                                   preconditioned by one multigrid V-cycle: Galerkin
+                                   coarse operators of the trilinear prolongation,
+                                   one damped Jacobi sweep before and after, dense
+                                   coarsest solve; same solution, same stopping
+                                   test, far fewer iterations).  Grids too small to
+                                   coarsen fall back to Jacobi. */
 } pf_config;
 
 typedef struct {
@@ -262,6 +272,7 @@ enum {
   PF_KC_FINISH,            /* deferred solution update of a solve */
   PF_KC_REDUCE,            /* single-block reductions of the CG scalars */
   PF_KC_OTHER,             /* fills, copies, energy and adjoint sweeps */
+  PF_KC_MG,                /* multigrid V-cycle of the FEM preconditioner */
   PF_KC_COUNT
 };
 
@@ -283,6 +294,18 @@ pf_status pf_timing(pf_ctx *ctx, int enable, double *ms, int64_t *launches);
  * out in doubles; needs at least pf_fem_table_size() of them. */
 size_t pf_fem_table_size(void);
 pf_status pf_fem_tables(const pf_config *cfg, double *out, size_t count);
+
+/* Diagnostic (host only): the multigrid hierarchy of the FEM operator used
+ * with PF_PRECOND_MG.  *nlevels receives the number of levels; for the first
+ * max_levels of them dims[3l..3l+2] = (nx, ny, nz) and omega[l] = the Jacobi
+ * smoother's damping (either array may be NULL). */
+pf_status pf_mg_levels(const pf_config *cfg, int32_t *nlevels, int32_t *dims, double *omega, int32_t max_levels);
+
+/* Diagnostic (host only): the Galerkin operator P^T A P of level `level`
+ * (>= 1) as nz x 3 x 3 x 27 doubles, T[k][c][e][o]: row component c of plane
+ * k against component e of the neighbour at offset o (same numbering as the
+ * FEM tables).  `count` is the capacity of out in doubles. */
+pf_status pf_mg_table(const pf_config *cfg, int32_t level, double *out, size_t count);
 
 const char *pf_status_str(pf_status s);
 const char *pf_last_error(const pf_ctx *ctx);

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace pf {
 
 // Threads per block of the node kernels: 64 along x (one wavefront per
@@ -89,6 +91,38 @@ struct Material {
   double Qv[6][6];
   bool rotated;  // R is not the identity
   bool cubic;    // C has the cubic zero pattern on the grid axes
+};
+
+// Modes of the single-block reduce kernel.
+enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2, kRedOuter = 3, kRedSum = 4, kRedRho = 5 };
+
+// Multigrid hierarchy of the FEM operator (built on the host, pf_mg.cpp).
+enum { kMgResidual = 0, kMgSweep = 1 };  // level kernel: out = b - A x, or one damped Jacobi sweep
+constexpr int kMgMaxLevels = 12;
+constexpr int64_t kMgDenseMax = 512;  // coarsest level solved by a dense inverse up to this many unknowns
+
+// Linear interpolation in z from the coarse planes lo, hi (clamp plane 0
+// carries zero) to one fine plane.
+struct MgZ {
+  int lo, hi;
+  double wlo, whi;
+};
+
+struct MgLevel {
+  int nx, ny, nz;            // nodes per direction (plane 0 is the clamp)
+  bool cx, cy;               // halved in x / y from the finer level
+  double omega;              // damping of the Jacobi smoother
+  std::vector<double> dinv;  // inverse diagonal per plane and component (nz x 3)
+};
+
+struct MgHierarchy {
+  std::vector<MgLevel> levels;                // 0 = the FEM grid
+  std::vector<std::vector<double>> tables;    // level >= 1: nz x 3 x 3 x 27 stencils
+  std::vector<std::vector<MgZ>> zmaps;        // level >= 1: per plane of the finer level
+  std::vector<std::vector<int>> zfine;        // level >= 1: finer-level plane of each plane
+  int dense_n;                                // coarsest: unknowns of the dense inverse (0: none)
+  std::vector<double> dense_inv;              // dense_n x dense_n
+  int coarse_sweeps;                          // coarsest: Jacobi sweeps when there is no inverse
 };
 
 // Per-call description of a node grid: the film grid (nz = nzf) or the

@@ -177,14 +177,13 @@ __device__ __forceinline__ void stage_store(T (&ring)[3][NC][TY + 2][kHX], const
 //              the outer test still needs, max(tol2, tol ||b|| / (2 ||r||)),
 //              tol2 being the floor that FP32 arithmetic can reach
 //   kRedSum    plain sums written to out[0..NV-1]
-enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2, kRedOuter = 3, kRedSum = 4 };
 constexpr int kRedThreads = 1024;
 
 template <int NV>
 __global__ __launch_bounds__(kRedThreads) void cg_reduce_kernel(const double* __restrict__ partials, int nblocks,
                                                                 CgScalars* sc, int mode, double tol, int maxit,
                                                                 double tol2, double* out) {
-  if ((mode == kRedAlpha || mode == kRedBeta) && sc->done) return;
+  if ((mode == kRedAlpha || mode == kRedBeta || mode == kRedRho) && sc->done) return;
   __shared__ double red[NV][kRedThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double s[NV];
@@ -210,6 +209,11 @@ __global__ __launch_bounds__(kRedThreads) void cg_reduce_kernel(const double* __
   if (mode == kRedSum) {
 #pragma unroll
     for (int t = 0; t < NV; t++) out[t] = a[t];
+    return;
+  }
+  if (mode == kRedRho) {  // r.z of a preconditioner applied after the setup
+    if (!finite(a[0]) || !(a[0] > 0.0)) sc->done = kNonFinite;
+    else sc->rho = a[0];
     return;
   }
   if (mode == kRedOuter) {
@@ -852,11 +856,13 @@ __global__ __launch_bounds__(kThreads) void fem_setup_kernel(
 // on the clamped plane), q = K p_new, x += alpha_prev p_old; partial p.q.
 // At most 128 VGPRs: four waves per SIMD, so four 256-thread blocks per CU
 // and the whole tile grid resident at once.
+// unit_w: r holds the preconditioned residual z itself (multigrid), so the
+// Jacobi weights are not applied.
 template <typename T, bool GEN>
 __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
                                                             const T* __restrict__ r, const T* __restrict__ p_old,
                                                             T* __restrict__ p_new, T* __restrict__ x,
-                                                            const CgScalars* sc, double* partials) {
+                                                            const CgScalars* sc, double* partials, int unit_w) {
   if (sc->done) return;
   constexpr int TY = kBY;
   __shared__ T ring[3][3][TY + 2][kHX];
@@ -880,9 +886,10 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
   };
   auto comb = [&](int k, const T* raw, T* out) {
     const bool top = k == d.nz - 1;
-    const T w0 = top ? w_top[0] : w_int[0];
+    const T w0 = unit_w ? (T)1 : (top ? w_top[0] : w_int[0]);
 #pragma unroll
-    for (int c = 0; c < 3; c++) out[c] = raw[c] * (GEN ? (top ? w_top[c] : w_int[c]) : w0) + beta * raw[3 + c];
+    for (int c = 0; c < 3; c++)
+      out[c] = raw[c] * (GEN && !unit_w ? (top ? w_top[c] : w_int[c]) : w0) + beta * raw[3 + c];
   };
   // centre values (p_old, x) of a plane
   auto centre = [&](int k, T* cv) {
@@ -1014,6 +1021,260 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_b_kernel(Dims d, TileMap t
   }
   double v[2] = {a0, a1};
   block_partials<2, kThreads>(v, partials, tc.lid);
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid V-cycle of the FEM operator (preconditioner of the FEM CG)
+// ---------------------------------------------------------------------------
+// Level 0 is the FEM grid (operator from the FEM tables, tiled like the CG
+// kernels); coarser levels hold Galerkin operators as per-plane 27-point
+// block stencils.  Plane 0 of every level is the clamp: it is never written
+// (the buffers hold zero there).
+
+// Sum of v over the block, written by thread 0 to *dst.
+template <int NT>
+__device__ __forceinline__ void block_sum_to(double v, double* dst) {
+  __shared__ double red[NT / 64];
+  const int tid = tid_flat();
+  const int lane = tid & 63, wv = tid >> 6;
+  const double s = wave_sum(v);
+  if (lane == 0) red[wv] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; w++) t += red[w];
+    *dst = t;
+  }
+}
+
+// Fine level: out = b - K x (kMgResidual) or out = x + omega D^-1 (b - K x)
+// (kMgSweep); with partials, the tile's sum of b . out goes to
+// partials[lid * pstride + poff].
+template <typename T, bool GEN>
+__global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
+                                                           const double* __restrict__ dinv, int mode, double omega,
+                                                           const T* __restrict__ x, const T* __restrict__ b,
+                                                           T* __restrict__ out, const CgScalars* sc, double* partials,
+                                                           int pstride, int poff) {
+  if (sc->done) return;
+  constexpr int TY = kBY;
+  __shared__ T ring[3][3][TY + 2][kHX];
+  const TileCoord tc = tile_coord(d, tm);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
+  const int64_t N = d.N;
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  auto fetch = [&](int64_t m, int k, T* raw) {
+    if (k == 0) return;
+#pragma unroll
+    for (int c = 0; c < 3; c++) raw[c] = x[c * N + m];
+  };
+  auto comb = [&](int, const T* raw, T* o) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) o[c] = raw[c];
+  };
+  auto centre = [&](int k, T* cv) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) cv[c] = 0;
+    if (valid && k > 0 && k < tc.k1) {
+      const int64_t n = col + d.plane * k;
+#pragma unroll
+      for (int c = 0; c < 3; c++) cv[c] = b[c * N + n];
+    }
+  };
+  Stage<T, 3, Halo<TY>::NPT> st;
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store<TY>(ring, st, tc.k0 - 1, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store<TY>(ring, st, tc.k0, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  T cv[3];
+  centre(tc.k0, cv);
+  double acc = 0.0;
+  for (int k = tc.k0; k < tc.k1; k++) {
+    stage_store<TY>(ring, st, k + 1, comb);
+    if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
+    T nv[3];
+    centre(k + 1, nv);
+    __syncthreads();
+    if (valid && k > 0) {
+      const int zt = (k == d.nz - 1) ? 1 : 0;
+      auto ld = [&](int dx, int dy, int dz, T u[3]) {
+        const int s = slot_of(k + dz);
+#pragma unroll
+        for (int c = 0; c < 3; c++) u[c] = ring[s][c][ly + 1 + dy][lx + 1 + dx];
+      };
+      T q[3];
+      fem_K_apply<T, GEN>(tb, zt, ld, q);
+      const int64_t n = col + d.plane * k;
+      const int s0 = slot_of(k);
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        const T r = cv[c] - q[c];
+        const T o = mode == kMgResidual ? r : ring[s0][c][ly + 1][lx + 1] + (T)(omega * dinv[3 * k + c]) * r;
+        out[c * N + n] = o;
+        acc += (double)cv[c] * (double)o;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) cv[c] = nv[c];
+    __syncthreads();
+  }
+  if (partials) block_sum_to<kThreads>(acc, partials + (int64_t)tc.lid * pstride + poff);
+}
+
+// Coarse level (per-plane stencils tab[k][c][e][o]): out = b - A x or
+// out = x + omega D^-1 (b - A x).  One thread per node.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void mg_level_kernel(Dims d, const double* __restrict__ tab,
+                                                            const double* __restrict__ dinv, int mode, double omega,
+                                                            const T* __restrict__ x, const T* __restrict__ b,
+                                                            T* __restrict__ out, const CgScalars* sc) {
+  if (sc->done) return;
+  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
+  if (i >= d.nx || j >= d.ny || k == 0) return;
+  const int64_t N = d.N;
+  const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
+  const double* tk = tab + (size_t)k * 243;
+  double q[3] = {0.0, 0.0, 0.0};
+  for (int dz = -1; dz <= 1; dz++) {
+    const int kk = k + dz;
+    if (kk < 1 || kk >= d.nz) continue;
+#pragma unroll
+    for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+      for (int dx = -1; dx <= 1; dx++) {
+        const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+        const int64_t m = nbr(d, i, j, k, dx, dy, dz);
+        const double u[3] = {(double)x[m], (double)x[N + m], (double)x[2 * N + m]};
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+#pragma unroll
+          for (int e = 0; e < 3; e++) q[c] += tk[(c * 3 + e) * 27 + o] * u[e];
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    const double r = (double)b[c * N + n] - q[c];
+    out[c * N + n] = (T)(mode == kMgResidual ? r : (double)x[c * N + n] + omega * dinv[3 * k + c] * r);
+  }
+}
+
+// x = omega D^-1 b (the first sweep from zero); plane 0 gets zero.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void mg_scale_kernel(Dims d, const double* __restrict__ dinv, double omega,
+                                                            const T* __restrict__ b, T* __restrict__ x,
+                                                            const CgScalars* sc) {
+  if (sc->done) return;
+  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
+  if (i >= d.nx || j >= d.ny) return;
+  const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
+#pragma unroll
+  for (int c = 0; c < 3; c++) x[c * d.N + n] = (T)(omega * dinv[3 * k + c] * (double)b[c * d.N + n]);
+}
+
+// Parents of fine node i along a periodic axis: coarse node i/2 (even i) or
+// the two coarse neighbours with weight 1/2 (odd i); identity when the axis
+// is not coarsened.
+__device__ __forceinline__ int mg_parents(int i, int nc, int coarsened, int idx[2], double w[2]) {
+  if (!coarsened) {
+    idx[0] = i, w[0] = 1.0;
+    return 1;
+  }
+  if ((i & 1) == 0) {
+    idx[0] = i >> 1, w[0] = 1.0;
+    return 1;
+  }
+  idx[0] = (i - 1) >> 1, idx[1] = ((i + 1) >> 1) % nc, w[0] = w[1] = 0.5;
+  return 2;
+}
+
+// Restriction (the transpose of the prolongation): coarse b = P^T r.  One
+// thread per coarse node; fine planes zfine[K] - 1 .. zfine[K] + 1.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void mg_restrict_kernel(Dims df, Dims dc, int cx, int cy,
+                                                               const MgZ* __restrict__ zmap,
+                                                               const int* __restrict__ zfine, const T* __restrict__ rf,
+                                                               T* __restrict__ bc, const CgScalars* sc) {
+  if (sc->done) return;
+  const int I = blockIdx.x * kBX + threadIdx.x, J = blockIdx.y * kBY + threadIdx.y, K = blockIdx.z;
+  if (I >= dc.nx || J >= dc.ny || K == 0) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int kf0 = zfine[K];
+  for (int kf = kf0 - 1; kf <= kf0 + 1; kf++) {
+    if (kf < 1 || kf >= df.nz) continue;
+    const MgZ z = zmap[kf];
+    double wz = 0.0;
+    if (z.lo == K) wz += z.wlo;
+    if (z.hi == K && z.hi != z.lo) wz += z.whi;
+    if (wz == 0.0) continue;
+    for (int di = -1; di <= 1; di++) {
+      if (!cx && di != 0) continue;
+      const int fi = cx ? wrap(2 * I + di, df.nx) : I;
+      const double wx = di == 0 ? 1.0 : 0.5;
+      for (int dj = -1; dj <= 1; dj++) {
+        if (!cy && dj != 0) continue;
+        const int fj = cy ? wrap(2 * J + dj, df.ny) : J;
+        const double w = wz * wx * (dj == 0 ? 1.0 : 0.5);
+        const int64_t m = fi + (int64_t)df.nx * fj + df.plane * kf;
+#pragma unroll
+        for (int c = 0; c < 3; c++) acc[c] += w * (double)rf[c * df.N + m];
+      }
+    }
+  }
+  const int64_t nc = I + (int64_t)dc.nx * J + dc.plane * K;
+#pragma unroll
+  for (int c = 0; c < 3; c++) bc[c * dc.N + nc] = (T)acc[c];
+}
+
+// Prolongation and correction: xf += P xc.  One thread per fine node.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void mg_prolong_kernel(Dims df, Dims dc, int cx, int cy,
+                                                              const MgZ* __restrict__ zmap, const T* __restrict__ xc,
+                                                              T* __restrict__ xf, const CgScalars* sc) {
+  if (sc->done) return;
+  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
+  if (i >= df.nx || j >= df.ny || k == 0) return;
+  int xi[2], yi[2];
+  double xw[2], yw[2];
+  const int nxp = mg_parents(i, dc.nx, cx, xi, xw), nyp = mg_parents(j, dc.ny, cy, yi, yw);
+  const MgZ z = zmap[k];
+  const int zi[2] = {z.lo, z.hi};
+  const double zw[2] = {z.wlo, z.whi};
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < 2; a++) {
+    if (zw[a] == 0.0 || zi[a] == 0) continue;
+    for (int bq = 0; bq < nyp; bq++)
+      for (int q = 0; q < nxp; q++) {
+        const double w = zw[a] * yw[bq] * xw[q];
+        const int64_t m = xi[q] + (int64_t)dc.nx * yi[bq] + dc.plane * zi[a];
+#pragma unroll
+        for (int c = 0; c < 3; c++) acc[c] += w * (double)xc[c * dc.N + m];
+      }
+  }
+  const int64_t n = i + (int64_t)df.nx * j + df.plane * k;
+#pragma unroll
+  for (int c = 0; c < 3; c++) xf[c * df.N + n] = (T)((double)xf[c * df.N + n] + acc[c]);
+}
+
+// Coarsest level: x = M b over the unknowns (planes >= 1), M the dense
+// inverse (row-major, n x n).  One block per row.
+template <typename T>
+__global__ __launch_bounds__(256) void mg_dense_kernel(Dims d, int n, const double* __restrict__ M,
+                                                       const T* __restrict__ b, T* __restrict__ x,
+                                                       const CgScalars* sc) {
+  if (sc->done) return;
+  const int row = blockIdx.x;
+  const int64_t nu = d.N - d.plane;  // unknowns per component
+  auto vec = [&](int64_t u) { return (u / nu) * d.N + d.plane + u % nu; };
+  double s = 0.0;
+  for (int t = threadIdx.x; t < n; t += 256) s += M[(int64_t)row * n + t] * (double)b[vec(t)];
+  __shared__ double red[4];
+  const double w = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) x[vec(row)] = (T)(red[0] + red[1] + red[2] + red[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1608,9 +1869,13 @@ hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* 
 // crystal), so no tap of the coupling blocks can be skipped.
 template <typename T>
 hipError_t launch_fem_cg_a(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const T* r,
-                           const T* p_old, T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s) {
-  if (gen) fem_cg_a_kernel<T, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, r, p_old, p_new, x, sc, partials);
-  else fem_cg_a_kernel<T, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, r, p_old, p_new, x, sc, partials);
+                           const T* p_old, T* p_new, T* x, const CgScalars* sc, double* partials, int unit_w,
+                           hipStream_t s) {
+  if (gen)
+    fem_cg_a_kernel<T, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, r, p_old, p_new, x, sc, partials, unit_w);
+  else
+    fem_cg_a_kernel<T, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, r, p_old, p_new, x, sc, partials,
+                                                                 unit_w);
   return hipGetLastError();
 }
 
@@ -1619,6 +1884,54 @@ hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb
                            const CgScalars* sc, double* partials, hipStream_t s) {
   if (gen) fem_cg_b_kernel<T, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, p, r, sc, partials);
   else fem_cg_b_kernel<T, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, p, r, sc, partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const double* dinv, int mode,
+                          double omega, const T* x, const T* b, T* out, const CgScalars* sc, double* partials,
+                          int pstride, int poff, hipStream_t s) {
+  if (gen)
+    mg_fine_kernel<T, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, dinv, mode, omega, x, b, out, sc, partials,
+                                                              pstride, poff);
+  else
+    mg_fine_kernel<T, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, dinv, mode, omega, x, b, out, sc, partials,
+                                                               pstride, poff);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_level(const Dims& d, const double* tab, const double* dinv, int mode, double omega, const T* x,
+                           const T* b, T* out, const CgScalars* sc, hipStream_t s) {
+  mg_level_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, tab, dinv, mode, omega, x, b, out, sc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_scale(const Dims& d, const double* dinv, double omega, const T* b, T* x, const CgScalars* sc,
+                           hipStream_t s) {
+  mg_scale_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, dinv, omega, b, x, sc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int cx, int cy, const MgZ* zmap, const int* zfine,
+                              const T* rf, T* bc, const CgScalars* sc, hipStream_t s) {
+  mg_restrict_kernel<T><<<node_grid(dc), node_block(), 0, s>>>(df, dc, cx, cy, zmap, zfine, rf, bc, sc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_prolong(const Dims& df, const Dims& dc, int cx, int cy, const MgZ* zmap, const T* xc, T* xf,
+                             const CgScalars* sc, hipStream_t s) {
+  mg_prolong_kernel<T><<<node_grid(df), node_block(), 0, s>>>(df, dc, cx, cy, zmap, xc, xf, sc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_dense(const Dims& d, int n, const double* M, const T* b, T* x, const CgScalars* sc,
+                           hipStream_t s) {
+  mg_dense_kernel<T><<<n, 256, 0, s>>>(d, n, M, b, x, sc);
   return hipGetLastError();
 }
 
@@ -1697,7 +2010,7 @@ PF_INSTANTIATE_ADJ(float)
   template hipError_t launch_poisson_cg_b<T>(const Dims&, const TileMap&, const Coefs<T>&, const T*, T*,         \
                                              const uint8_t*, const CgScalars*, double*, hipStream_t);            \
   template hipError_t launch_fem_cg_a<T>(const Dims&, const TileMap&, const FemTables*, bool, const T*, const T*, \
-                                         T*, T*, const CgScalars*, double*, hipStream_t);                        \
+                                         T*, T*, const CgScalars*, double*, int, hipStream_t);                   \
   template hipError_t launch_fem_cg_b<T>(const Dims&, const TileMap&, const FemTables*, bool, const T*, T*,      \
                                          const CgScalars*, double*, hipStream_t);                                \
   template hipError_t launch_force<T>(const Dims&, const Coefs<T>&, const FemTables*, const T*, const T*, T,     \
@@ -1705,6 +2018,24 @@ PF_INSTANTIATE_ADJ(float)
 
 PF_INSTANTIATE(double)
 PF_INSTANTIATE(float)
+
+#define PF_INSTANTIATE_MG(T)                                                                                     \
+  template hipError_t launch_mg_fine<T>(const Dims&, const TileMap&, const FemTables*, bool, const double*, int,  \
+                                        double, const T*, const T*, T*, const CgScalars*, double*, int, int,       \
+                                        hipStream_t);                                                             \
+  template hipError_t launch_mg_level<T>(const Dims&, const double*, const double*, int, double, const T*,        \
+                                         const T*, T*, const CgScalars*, hipStream_t);                            \
+  template hipError_t launch_mg_scale<T>(const Dims&, const double*, double, const T*, T*, const CgScalars*,      \
+                                         hipStream_t);                                                            \
+  template hipError_t launch_mg_restrict<T>(const Dims&, const Dims&, int, int, const MgZ*, const int*, const T*, \
+                                            T*, const CgScalars*, hipStream_t);                                   \
+  template hipError_t launch_mg_prolong<T>(const Dims&, const Dims&, int, int, const MgZ*, const T*, T*,          \
+                                           const CgScalars*, hipStream_t);                                        \
+  template hipError_t launch_mg_dense<T>(const Dims&, int, const double*, const T*, T*, const CgScalars*,         \
+                                         hipStream_t);
+
+PF_INSTANTIATE_MG(double)
+PF_INSTANTIATE_MG(float)
 
 #define PF_INSTANTIATE_SETUP(T, S, R)                                                                            \
   template hipError_t launch_poisson_setup<T, S, R>(const Dims&, const Coefs<T>&, const S*, const S*, T, int,    \

@@ -1,0 +1,338 @@
+// Multigrid hierarchy of the FEM operator (host): grid levels, Galerkin
+// coarse operators A_{l+1} = P^T A_l P as per-plane 27-point block stencils,
+// Jacobi weights, smoother damping and the coarsest level's inverse.
+//
+// The film is periodic in x and y, clamped on plane 0 and free on top, so
+// every level operator is invariant under x/y translations and varies only
+// with the plane.  Prolongation P is trilinear: in x and y coarse node I sits
+// on fine node 2I (a level is halved while it is even and at least 8 wide);
+// in z the coarse planes are the even fine planes plus the top plane, so the
+// free surface stays on every level.  The coarse stencils are read off
+// A_{l+1} applied to unit vectors on small periodic probe domains, which is
+// exact because P, A_l and P^T all have a support of one coarse cell.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pf.h"
+#include "pf_internal.h"
+
+namespace pf {
+
+namespace {
+
+inline int tap_index(int dx, int dy, int dz) { return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1); }
+inline int wrap_host(int i, int n) { return ((i % n) + n) % n; }
+
+// A level operator on a periodic probe domain (wx x wy x nz, component-major).
+struct ProbeOp {
+  int wx, wy, nz;
+  const FemTables* fine;               // level 0 (FEM tables), or
+  const std::vector<double>* planes;   // level >= 1 (nz x 3 x 3 x 27)
+  int64_t plane() const { return (int64_t)wx * wy; }
+  int64_t n() const { return plane() * nz; }
+  double coef(int k, int c, int e, int o) const {
+    if (fine) return fine->K[k == nz - 1 ? 1 : 0][c][e][o];
+    return (*planes)[(((size_t)k * 3 + c) * 3 + e) * 27 + o];
+  }
+  // y = A x; plane 0 (clamp) rows and columns are zero.
+  void apply(const std::vector<double>& x, std::vector<double>& y) const {
+    const int64_t N = n();
+    y.assign(3 * N, 0.0);
+    for (int k = 1; k < nz; k++)
+      for (int j = 0; j < wy; j++)
+        for (int i = 0; i < wx; i++) {
+          const int64_t r = i + (int64_t)wx * (j + (int64_t)wy * k);
+          for (int dz = -1; dz <= 1; dz++) {
+            const int kk = k + dz;
+            if (kk < 1 || kk >= nz) continue;
+            for (int dy = -1; dy <= 1; dy++)
+              for (int dx = -1; dx <= 1; dx++) {
+                const int o = tap_index(dx, dy, dz);
+                const int64_t m = wrap_host(i + dx, wx) + (int64_t)wx * (wrap_host(j + dy, wy) + (int64_t)wy * kk);
+                for (int c = 0; c < 3; c++)
+                  for (int e = 0; e < 3; e++) y[c * N + r] += coef(k, c, e, o) * x[e * N + m];
+              }
+          }
+        }
+  }
+  double diag(int k, int c) const { return coef(k, c, c, 13); }
+};
+
+// Prolongation between a fine domain (fx, fy, fz) and a coarse one.
+struct ProbeTransfer {
+  int fx, fy, fz, cx_, cy_, cz;
+  bool cx, cy;
+  const std::vector<MgZ>* zmap;  // per fine plane
+  // fine (i, j, k) <- sum of weights times coarse values
+  template <typename F>
+  void for_parents(int i, int j, int k, F f) const {
+    int xi[2], yi[2];
+    double xw[2], yw[2];
+    int nxp, nyp;
+    if (cx) {
+      if (i % 2 == 0) {
+        xi[0] = i / 2, xw[0] = 1.0, nxp = 1;
+      } else {
+        xi[0] = (i - 1) / 2, xi[1] = wrap_host((i + 1) / 2, cx_), xw[0] = xw[1] = 0.5, nxp = 2;
+      }
+    } else {
+      xi[0] = i, xw[0] = 1.0, nxp = 1;
+    }
+    if (cy) {
+      if (j % 2 == 0) {
+        yi[0] = j / 2, yw[0] = 1.0, nyp = 1;
+      } else {
+        yi[0] = (j - 1) / 2, yi[1] = wrap_host((j + 1) / 2, cy_), yw[0] = yw[1] = 0.5, nyp = 2;
+      }
+    } else {
+      yi[0] = j, yw[0] = 1.0, nyp = 1;
+    }
+    const MgZ& z = (*zmap)[k];
+    const int zi[2] = {z.lo, z.hi};
+    const double zw[2] = {z.wlo, z.whi};
+    for (int a = 0; a < 2; a++) {
+      if (zw[a] == 0.0 || zi[a] == 0) continue;  // the clamp plane carries zero
+      for (int b = 0; b < nyp; b++)
+        for (int q = 0; q < nxp; q++) f(xi[q], yi[b], zi[a], zw[a] * yw[b] * xw[q]);
+    }
+  }
+  void prolong(const std::vector<double>& xc, std::vector<double>& xf) const {
+    const int64_t Nf = (int64_t)fx * fy * fz, Nc = (int64_t)cx_ * cy_ * cz;
+    xf.assign(3 * Nf, 0.0);
+    for (int k = 1; k < fz; k++)
+      for (int j = 0; j < fy; j++)
+        for (int i = 0; i < fx; i++) {
+          const int64_t r = i + (int64_t)fx * (j + (int64_t)fy * k);
+          for_parents(i, j, k, [&](int I, int J, int K, double w) {
+            const int64_t m = I + (int64_t)cx_ * (J + (int64_t)cy_ * K);
+            for (int c = 0; c < 3; c++) xf[c * Nf + r] += w * xc[c * Nc + m];
+          });
+        }
+  }
+  void restrict_(const std::vector<double>& yf, std::vector<double>& yc) const {
+    const int64_t Nf = (int64_t)fx * fy * fz, Nc = (int64_t)cx_ * cy_ * cz;
+    yc.assign(3 * Nc, 0.0);
+    for (int k = 1; k < fz; k++)
+      for (int j = 0; j < fy; j++)
+        for (int i = 0; i < fx; i++) {
+          const int64_t r = i + (int64_t)fx * (j + (int64_t)fy * k);
+          for_parents(i, j, k, [&](int I, int J, int K, double w) {
+            const int64_t m = I + (int64_t)cx_ * (J + (int64_t)cy_ * K);
+            for (int c = 0; c < 3; c++) yc[c * Nc + m] += w * yf[c * Nf + r];
+          });
+        }
+  }
+};
+
+// Coarse planes in z: the even fine planes and the top plane.
+std::vector<int> coarse_planes(int nz) {
+  std::vector<int> z;
+  for (int k = 0; k < nz; k += 2) z.push_back(k);
+  if (z.back() != nz - 1) z.push_back(nz - 1);
+  return z;
+}
+
+std::vector<MgZ> zmap_for(int nz, const std::vector<int>& zc) {
+  std::vector<MgZ> m(nz);
+  for (int k = 0; k < nz; k++) {
+    MgZ& e = m[k];
+    auto it = std::lower_bound(zc.begin(), zc.end(), k);
+    if (*it == k) {
+      e.lo = e.hi = (int)(it - zc.begin());
+      e.wlo = 1.0;
+      e.whi = 0.0;
+    } else {
+      const int b = (int)(it - zc.begin()), a = b - 1;
+      const double span = zc[b] - zc[a];
+      e.lo = a;
+      e.hi = b;
+      e.wlo = (zc[b] - k) / span;
+      e.whi = (k - zc[a]) / span;
+    }
+  }
+  return m;
+}
+
+// Largest eigenvalue of D^-1 A on an 8 x 8 periodic probe (power iteration).
+double jacobi_lambda_max(int nz, const FemTables* fine, const std::vector<double>* planes) {
+  ProbeOp op{8, 8, nz, fine, planes};
+  const int64_t N = op.n();
+  std::vector<double> x(3 * N), y;
+  uint32_t s = 12345u;
+  for (int64_t t = 0; t < 3 * N; t++) {
+    s = s * 1664525u + 1013904223u;
+    x[t] = (t % N) < op.plane() ? 0.0 : (double)(s >> 8) / (double)(1u << 24) - 0.5;
+  }
+  double lam = 0.0;
+  for (int it = 0; it < 60; it++) {
+    op.apply(x, y);
+    double nrm = 0.0;
+    for (int c = 0; c < 3; c++)
+      for (int64_t m = op.plane(); m < N; m++) {
+        const int k = (int)(m / op.plane());
+        y[c * N + m] /= op.diag(k, c);
+        nrm += y[c * N + m] * y[c * N + m];
+      }
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0)) break;
+    lam = nrm;
+    for (int64_t t = 0; t < 3 * N; t++) x[t] = y[t] / nrm;
+  }
+  return lam;
+}
+
+// In-place inverse of a symmetric positive definite matrix (Cholesky).
+bool spd_inverse(std::vector<double>& A, int n) {
+  std::vector<double> L(A.size(), 0.0);
+  for (int j = 0; j < n; j++) {
+    double d = A[(size_t)j * n + j];
+    for (int k = 0; k < j; k++) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(d > 0)) return false;
+    const double ljj = std::sqrt(d);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; i++) {
+      double s = A[(size_t)i * n + j];
+      for (int k = 0; k < j; k++) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = s / ljj;
+    }
+  }
+  // inverse = L^-T L^-1, column by column
+  std::vector<double> col(n);
+  for (int c = 0; c < n; c++) {
+    for (int i = 0; i < n; i++) {
+      double s = i == c ? 1.0 : 0.0;
+      for (int k = 0; k < i; k++) s -= L[(size_t)i * n + k] * col[k];
+      col[i] = s / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; i--) {
+      double s = col[i];
+      for (int k = i + 1; k < n; k++) s -= L[(size_t)k * n + i] * col[k];
+      col[i] = s / L[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; i++) A[(size_t)i * n + c] = col[i];
+  }
+  return true;
+}
+
+}  // namespace
+
+std::vector<MgLevel> mg_plan(const pf_config& cfg);
+MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb);
+
+// Grid levels: halve x and y while even and at least 8 wide, keep every
+// other plane and the top in z, until the coarsest level has at most
+// kMgDenseMax unknowns or nothing can be coarsened.
+std::vector<MgLevel> mg_plan(const pf_config& cfg) {
+  std::vector<MgLevel> lv;
+  MgLevel l0;
+  l0.nx = cfg.nx, l0.ny = cfg.ny, l0.nz = cfg.nz;
+  l0.cx = l0.cy = false;
+  l0.omega = 0.0;
+  lv.push_back(l0);
+  for (;;) {
+    const MgLevel f = lv.back();
+    if (3LL * f.nx * f.ny * (f.nz - 1) <= kMgDenseMax) break;
+    const bool cx = f.nx % 2 == 0 && f.nx >= 8, cy = f.ny % 2 == 0 && f.ny >= 8;
+    const int nzc = (int)coarse_planes(f.nz).size();
+    if (!cx && !cy && nzc == f.nz) break;
+    if ((int)lv.size() >= kMgMaxLevels) break;
+    MgLevel c;
+    c.nx = cx ? f.nx / 2 : f.nx;
+    c.ny = cy ? f.ny / 2 : f.ny;
+    c.nz = nzc;
+    c.cx = cx, c.cy = cy;
+    c.omega = 0.0;
+    lv.push_back(c);
+  }
+  return lv;
+}
+
+MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb) {
+  MgHierarchy h;
+  const std::vector<MgLevel> plan = mg_plan(cfg);
+  h.levels.push_back(plan[0]);
+  h.tables.emplace_back();
+  h.zmaps.emplace_back();
+  h.zfine.emplace_back();
+  for (size_t l = 1; l < plan.size(); l++) {
+    const MgLevel& f = h.levels.back();
+    const MgLevel& c = plan[l];
+    const bool cx = c.cx, cy = c.cy;
+    const std::vector<int> zc = coarse_planes(f.nz);
+    const std::vector<MgZ> zm = zmap_for(f.nz, zc);
+    // Galerkin operator by probing on periodic domains of 4 (coarsened) or
+    // 3 (kept) coarse nodes per direction.
+    const int wcx = cx ? 4 : 3, wcy = cy ? 4 : 3;
+    const int wfx = cx ? 8 : 3, wfy = cy ? 8 : 3;
+    const size_t lf = h.levels.size() - 1;
+    ProbeOp fine_op{wfx, wfy, f.nz, lf == 0 ? &tb : nullptr, lf == 0 ? nullptr : &h.tables[lf]};
+    ProbeTransfer tr{wfx, wfy, f.nz, wcx, wcy, c.nz, cx, cy, &zm};
+    std::vector<double> T((size_t)c.nz * 3 * 3 * 27, 0.0);
+    const int64_t Nc = (int64_t)wcx * wcy * c.nz;
+    std::vector<double> u(3 * Nc), v, w, y;
+    for (int K = 1; K < c.nz; K++)
+      for (int e = 0; e < 3; e++) {
+        std::fill(u.begin(), u.end(), 0.0);
+        u[e * Nc + (int64_t)wcx * wcy * K] = 1.0;
+        tr.prolong(u, v);
+        fine_op.apply(v, w);
+        tr.restrict_(w, y);
+        // column (e, K) at the origin: row (c, K') at (-dx, -dy) is the
+        // coefficient of offset (dx, dy, K - K')
+        for (int Kr = std::max(1, K - 1); Kr <= std::min(c.nz - 1, K + 1); Kr++)
+          for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+              const int64_t m = wrap_host(-dx, wcx) + (int64_t)wcx * (wrap_host(-dy, wcy) + (int64_t)wcy * Kr);
+              for (int cc = 0; cc < 3; cc++)
+                T[(((size_t)Kr * 3 + cc) * 3 + e) * 27 + tap_index(dx, dy, K - Kr)] = y[cc * Nc + m];
+            }
+      }
+    h.levels.push_back(c);
+    h.tables.push_back(std::move(T));
+    h.zmaps.push_back(zm);
+    h.zfine.push_back(zc);
+  }
+  // Jacobi weights and smoother damping per level
+  for (size_t l = 0; l < h.levels.size(); l++) {
+    MgLevel& L = h.levels[l];
+    L.dinv.assign((size_t)L.nz * 3, 0.0);
+    for (int k = 1; k < L.nz; k++)
+      for (int c = 0; c < 3; c++) {
+        const double d = l == 0 ? tb.K[k == L.nz - 1 ? 1 : 0][c][c][13] : h.tables[l][(((size_t)k * 3 + c) * 3 + c) * 27 + 13];
+        L.dinv[(size_t)k * 3 + c] = 1.0 / d;
+      }
+    const double lam = jacobi_lambda_max(L.nz, l == 0 ? &tb : nullptr, l == 0 ? nullptr : &h.tables[l]);
+    L.omega = 4.0 / (3.0 * 1.05 * lam);
+  }
+  // Coarsest level: dense inverse over its unknowns (planes >= 1), or damped
+  // Jacobi sweeps when it is too large for that.
+  const MgLevel& C = h.levels.back();
+  const int64_t n = 3LL * C.nx * C.ny * (C.nz - 1);
+  h.dense_n = 0;
+  h.coarse_sweeps = 0;
+  if (n <= kMgDenseMax) {
+    const size_t lc = h.levels.size() - 1;
+    ProbeOp op{C.nx, C.ny, C.nz, lc == 0 ? &tb : nullptr, lc == 0 ? nullptr : &h.tables[lc]};
+    const int64_t N = op.n(), pl = op.plane();
+    std::vector<double> A((size_t)n * n, 0.0), x(3 * N, 0.0), y;
+    auto idx = [&](int c, int64_t m) { return (int64_t)c * (N - pl) + (m - pl); };
+    for (int e = 0; e < 3; e++)
+      for (int64_t m = pl; m < N; m++) {
+        std::fill(x.begin(), x.end(), 0.0);
+        x[e * N + m] = 1.0;
+        op.apply(x, y);
+        for (int c = 0; c < 3; c++)
+          for (int64_t r = pl; r < N; r++) A[(size_t)idx(c, r) * n + idx(e, m)] = y[c * N + r];
+      }
+    if (spd_inverse(A, (int)n)) {
+      h.dense_n = (int)n;
+      h.dense_inv = std::move(A);
+    }
+  }
+  if (h.dense_n == 0) h.coarse_sweeps = 2 * std::max(C.nz, 8);
+  return h;
+}
+
+}  // namespace pf

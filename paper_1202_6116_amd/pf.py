@@ -22,14 +22,16 @@ PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ENOCONV, PF_ENONFINITE, PF_ESTATE = 0, 
 PF_INT_PC, PF_INT_EULER = 0, 1
 PF_FP64, PF_FP32_REFINE = 0, 1
 PF_TOP_METAL, PF_TOP_OPEN = 0, 1
+PF_PRECOND_JACOBI, PF_PRECOND_MG = 0, 1
 KERNEL_CLASSES = ["poisson_setup", "poisson_a", "poisson_b", "fem_setup", "fem_a", "fem_b", "force", "finish",
-                  "reduce", "other"]
+                  "reduce", "other", "mg"]
 
 # Every symbol declared in include/pf.h.
 EXPORTS = [
     "pf_workspace_size", "pf_init", "pf_set_state", "pf_restore_state", "pf_get_state", "pf_step",
     "pf_solve_phi", "pf_solve_u", "pf_force", "pf_noise", "pf_energy", "pf_set_params", "pf_adjoint_step",
-    "pf_adjoint_initial_rate", "pf_timing", "pf_fem_table_size", "pf_fem_tables", "pf_status_str", "pf_last_error",
+    "pf_adjoint_initial_rate", "pf_timing", "pf_fem_table_size", "pf_fem_tables", "pf_mg_levels", "pf_mg_table",
+    "pf_status_str", "pf_last_error",
     "pf_destroy",
 ]
 
@@ -63,6 +65,7 @@ class pf_config(ctypes.Structure):
         ("noise_sigma", ctypes.c_double), ("noise_seed", ctypes.c_uint64),
         ("top_bc", ctypes.c_int32), ("n_air", ctypes.c_int32), ("eps_air", ctypes.c_double),
         ("misfit", ctypes.c_double * 3), ("rotation", ctypes.c_double * 9),
+        ("precond", ctypes.c_int32),
     ]
 
 
@@ -117,6 +120,9 @@ def lib() -> ctypes.CDLL:
             "pf_timing": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)]),
             "pf_fem_table_size": (sz, []),
             "pf_fem_tables": (ctypes.c_int, [cfgp, dp, sz]),
+            "pf_mg_levels": (ctypes.c_int, [cfgp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp,
+                                            ctypes.c_int32]),
+            "pf_mg_table": (ctypes.c_int, [cfgp, ctypes.c_int32, dp, sz]),
             "pf_status_str": (ctypes.c_char_p, [ctypes.c_int]),
             "pf_last_error": (ctypes.c_char_p, [vp]),
             "pf_destroy": (None, [vp]),
@@ -155,6 +161,7 @@ def make_config(cfg: PFConfig):
     c.eps_air = cfg.eps_air
     c.misfit[:] = [float(x) for x in cfg.misfit]
     c.rotation[:] = [float(x) for x in cfg.rotation]
+    c.precond = {"jacobi": PF_PRECOND_JACOBI, "mg": PF_PRECOND_MG}[cfg.precond]
     return c, els
 
 
@@ -191,6 +198,31 @@ def pf_fem_tables(cfg: PFConfig):
         res[name] = out[o:o + cnt].reshape(shp)
         o += cnt
     return res
+
+
+def pf_mg_levels(cfg: PFConfig):
+    """The multigrid levels of the FEM operator: list of ((nx, ny, nz), omega)."""
+    import numpy as np
+    c, keep = make_config(cfg)
+    n = ctypes.c_int32()
+    dims = (ctypes.c_int32 * 48)()
+    om = np.zeros(16)
+    st = lib().pf_mg_levels(ctypes.byref(c), ctypes.byref(n), dims, om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 16)
+    if st != PF_OK:
+        raise PFError(st, f"pf_mg_levels: {status_str(st)}")
+    return [((dims[3 * l], dims[3 * l + 1], dims[3 * l + 2]), float(om[l])) for l in range(n.value)]
+
+
+def pf_mg_table(cfg: PFConfig, level: int):
+    """Galerkin stencils of a multigrid level >= 1, float64 (nz, 3, 3, 27)."""
+    import numpy as np
+    c, keep = make_config(cfg)
+    nz = pf_mg_levels(cfg)[level][0][2]
+    out = np.zeros(nz * 243)
+    st = lib().pf_mg_table(ctypes.byref(c), level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size)
+    if st != PF_OK:
+        raise PFError(st, f"pf_mg_table: {status_str(st)}")
+    return out.reshape(nz, 3, 3, 27)
 
 
 def _ptr(t: Optional[torch.Tensor]):

@@ -84,6 +84,7 @@ class PFConfig:
     eps_air: float = 1.0            # open top: permittivity of the air planes
     misfit: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # substrate strain: xx, yy, engineering xy
     rotation: Tuple[float, ...] = (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0)  # crystal-to-grid R, row-major
+    precond: str = "jacobi"         # FEM solves: "jacobi" (the paper's) or "mg" (multigrid V-cycle)
 
     @property
     def shape(self) -> Tuple[int, int, int]:

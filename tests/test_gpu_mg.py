@@ -1,0 +1,133 @@
+"""GPU FEM solves preconditioned by the multigrid V-cycle against the FP64
+oracle (Jacobi CG), through the C ABI: the solution is the same to the
+solver tolerance, with far fewer iterations."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1202_6116_amd.workloads import (
+    PFConfig, Electrode, workloads, initial_polarisation, domain_polarisation, axis_rotation,
+)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0").to(dtype)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def pf():
+    from paper_1202_6116_amd import pf as m
+    return m
+
+
+def mg_cfg(**kw):
+    base = dict(nx=64, ny=16, nz=8, tol_phi=1e-13, tol_u=1e-13, precond="mg", phi_bottom=0.1)
+    base.update(kw)
+    nx, ny = base["nx"], base["ny"]
+    base.setdefault("electrodes", [Electrode(nx // 12, nx // 3, 0, ny, 2.0),
+                                   Electrode(nx // 2, 7 * nx // 8, 1, ny - 2, -1.5)])
+    return PFConfig(**base)
+
+
+@pytest.mark.parametrize("shape", [(64, 16, 8), (70, 13, 6), (32, 32, 17)])
+def test_mg_fem_solve_matches_oracle(pf, oracle_mod, shape):
+    nx, ny, nz = shape
+    cfg = mg_cfg(nx=nx, ny=ny, nz=nz)
+    levels = pf.pf_mg_levels(cfg)
+    print(f"case: mg fem solve {shape} levels {[d for d, _ in levels]}", flush=True)
+    assert len(levels) >= 2
+    P = domain_polarisation(cfg, 71, block=4)
+    ref, it, rr, st = oracle_mod.Oracle(cfg).solve_u(P)
+    u, stats = pf.Context(cfg).solve_u(dev(P))
+    assert stats["status"] == 0 and stats["relres"] <= 1e-13
+    assert stats["iters"] < it / 3, (stats["iters"], it)
+    assert rel(host(u), ref) < TOL
+    assert np.all(host(u)[:, 0] == 0)
+
+
+@pytest.mark.parametrize("integrator,precision", [("pc", "fp64"), ("euler", "fp64"), ("pc", "fp32_refine")])
+def test_mg_trajectory_matches_oracle(pf, oracle_mod, integrator, precision):
+    cfg = mg_cfg(integrator=integrator, precision=precision, warm_start=2,
+                 tol_phi=1e-13 if precision == "fp64" else 1e-9, tol_u=1e-13 if precision == "fp64" else 1e-9)
+    print(f"case: mg trajectory {integrator} {precision}", flush=True)
+    P0 = domain_polarisation(cfg, 72, block=4)
+    o = oracle_mod.Oracle(cfg.replace(precision="fp64"))
+    P = P0.astype(np.float32).astype(np.float64) if precision != "fp64" else P0.copy()
+    V, phi, u, _ = o.set_state(P)
+    o.step(P, V, phi, u, 8)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P0, ctx.state_dtype))
+    ctx.step(8)
+    Pg, Vg, phig, ug, _ = ctx.get_state()
+    bar = TOL if precision == "fp64" else 1e-4
+    assert rel(host(Pg), P) < bar
+    assert rel(host(ug), u) < bar
+
+
+def test_mg_rotated_open_top(pf, oracle_mod):
+    cfg = mg_cfg(rotation=axis_rotation((1.0, 2.0, 3.0), 0.7), misfit=(0.004, -0.002, 0.003), top="open", n_air=3,
+                 eps_b=10.0, Q11=0.5, Q12=-0.15, Q44=0.2)
+    print("case: mg rotated open", flush=True)
+    P0 = domain_polarisation(cfg, 73, block=4)
+    o = oracle_mod.Oracle(cfg)
+    P = P0.copy()
+    V, phi, u, _ = o.set_state(P)
+    o.step(P, V, phi, u, 6)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P0))
+    ctx.step(6)
+    Pg, Vg, phig, ug, _ = ctx.get_state()
+    assert rel(host(Pg), P) < TOL
+    assert rel(host(ug), u) < TOL
+
+
+def test_mg_adjoint_matches_oracle(pf, oracle_mod):
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    cfg = PFConfig(nx=32, ny=16, nz=6, tol_phi=1e-13, tol_u=1e-13, dt=0.05, precond="mg",
+                   Q11=0.5, Q12=-0.15, Q44=0.2,
+                   electrodes=[Electrode(2, 8, 0, 16, 1.0), Electrode(18, 24, 0, 16, -1.0)])
+    print("case: mg adjoint", flush=True)
+    nsteps = 5
+    P0 = domain_polarisation(cfg, 74, block=3, std=0.2)
+    wgt = np.zeros((3,) + cfg.shape)
+    wgt[2, 2:, 2:6, 3:10] = 1.0 / 4 / 4 / 7
+    J_ref, dth_ref, dP_ref = oracle_mod.Oracle(cfg).gradient(P0, nsteps, wgt)
+    ctx = pf.Context(cfg)
+    P0t = dev(P0).requires_grad_(True)
+    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+    PN = tdgl_steps(P0t, volts, a1, ctx, nsteps, checkpoint_every=3)
+    J = (PN * dev(wgt)).sum()
+    J.backward()
+    assert abs(float(J.detach()) - J_ref) <= 1e-10 * abs(J_ref)
+    g = np.concatenate([volts.grad.cpu().numpy(), [a1.grad.item()]])
+    assert rel(g, dth_ref) < 1e-7, (g, dth_ref)
+    assert rel(host(P0t.grad), dP_ref) < 1e-7
+
+
+def test_mg_lateral_256_full_size(pf, oracle_mod):
+    """The 256x256x64 film with the multigrid preconditioner: the FEM
+    solution satisfies the oracle's residual test, in a few iterations."""
+    w = workloads()["lateral_256x256x64"]
+    cfg = w.cfg.replace(precond="mg")
+    print("case: mg lateral_256x256x64", flush=True)
+    o = oracle_mod.Oracle(cfg)
+    P0 = initial_polarisation(w)
+    u, st = pf.Context(cfg).solve_u(dev(P0))
+    assert st["status"] == 0 and st["iters"] < 40, st
+    f = o.fem_rhs(P0)
+    r = f - o.fem_apply(host(u))
+    assert np.linalg.norm(r) <= 1.05 * cfg.tol_u * np.linalg.norm(f)
