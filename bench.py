@@ -93,12 +93,12 @@ def cpu_baseline(w, iters_phi, iters_u):
     }
 
 
-def adjoint_leg(pf, torch, workloads, initial_polarisation, warm_start):
+def adjoint_leg(pf, torch, workloads, initial_polarisation, warm_start, precond):
     """Forward (50 steps, checkpoints every 10) and backward of the adjoint
     case; returns timings and the gradient."""
     from paper_1202_6116_amd.autograd import tdgl_steps
     w = workloads()["adjoint_128x128x32"]
-    cfg = w.cfg.replace(warm_start=warm_start)
+    cfg = w.cfg.replace(warm_start=warm_start, precond=precond)
     ctx = pf.Context(cfg, "cuda:0")
     P0 = torch.from_numpy(initial_polarisation(w)).to("cuda:0")
     x0, x1, y0, y1, z0, z1 = w.region
@@ -121,14 +121,14 @@ def adjoint_leg(pf, torch, workloads, initial_polarisation, warm_start):
             "dJ_dV": [float(v) for v in volts.grad], "dJ_da1": float(a1.grad)}
 
 
-def micron_leg(pf, torch, workloads, initial_polarisation, warm_start, steps=5, adj_steps=3, warmup=1):
+def micron_leg(pf, torch, workloads, initial_polarisation, warm_start, precond, steps=5, adj_steps=3, warmup=1):
     """The micron-scale film (1024x1024x96, FP32 sweeps with FP64 refinement):
     forward throughput over `steps` steps, then a differentiable run of
     `adj_steps` steps (one checkpoint segment) and its backward; peak device
     memory of the whole leg.  J is the mean Pz of the film."""
     from paper_1202_6116_amd.autograd import tdgl_steps
     w = workloads()["micron_1024x1024x96_fp32"]
-    cfg = w.cfg.replace(warm_start=warm_start)
+    cfg = w.cfg.replace(warm_start=warm_start, precond=precond)
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
     ctx = pf.Context(cfg, "cuda:0")
@@ -165,7 +165,7 @@ def micron_leg(pf, torch, workloads, initial_polarisation, warm_start, steps=5, 
             "dJ_dV": [float(v) for v in volts.grad], "dJ_da1": float(a1.grad)}
 
 
-def precision_leg(pf, torch, workloads, initial_polarisation, warm_start, steps=4, warmup=2):
+def precision_leg(pf, torch, workloads, initial_polarisation, warm_start, precond, steps=4, warmup=2):
     """The 512x512x128 lateral film for a few steps in FP32 sweeps with FP64
     refinement and in plain FP64 from the same start; returns both step times
     and the per-field relative difference after the steps."""
@@ -173,7 +173,7 @@ def precision_leg(pf, torch, workloads, initial_polarisation, warm_start, steps=
     res = {"workload": w.name, "steps": steps, "warmup": warmup}
     states = {}
     for prec in ("fp32_refine", "fp64"):
-        cfg = w.cfg.replace(precision=prec, warm_start=warm_start)
+        cfg = w.cfg.replace(precision=prec, warm_start=warm_start, precond=precond)
         ctx = pf.Context(cfg, "cuda:0")
         P0 = torch.from_numpy(initial_polarisation(w)).to("cuda:0").to(ctx.state_dtype)
         ctx.set_state(P0)
@@ -210,8 +210,8 @@ def main():
     ap.add_argument("--extrap-order", type=int, default=None,
                     help="with --warm-start 2: number of earlier solutions the polynomial goes through "
                          "(0..8; default: the workload's)")
-    ap.add_argument("--precond", choices=("jacobi", "mg"), default=None,
-                    help="preconditioner of the FEM solves (default: the workload's, Jacobi)")
+    ap.add_argument("--precond", choices=("jacobi", "mg"), default="mg",
+                    help="preconditioner of the FEM solves: mg (multigrid V-cycle, default) or jacobi (the paper's)")
     ap.add_argument("--nonlocal-every", type=int, default=None,
                     help="refresh phi and u every k steps (default: the workload's, every step)")
     ap.add_argument("--no-kernel-timing", action="store_true",
@@ -240,8 +240,7 @@ def main():
         w.cfg = w.cfg.replace(extrap_order=args.extrap_order)
     if args.nonlocal_every is not None:
         w.cfg = w.cfg.replace(nonlocal_every=args.nonlocal_every)
-    if args.precond is not None:
-        w.cfg = w.cfg.replace(precond=args.precond)
+    w.cfg = w.cfg.replace(precond=args.precond)
     cfg = w.cfg
     dev = torch.device("cuda:0")
     ctx = pf.Context(cfg, "cuda:0")
@@ -319,14 +318,14 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_adjoint:
         progress("adjoint leg")
-        out["adjoint"] = adjoint_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
+        out["adjoint"] = adjoint_leg(pf, torch, workloads, initial_polarisation, args.warm_start, args.precond)
     if not args.no_precision:
         progress("precision leg")
-        out["precision"] = precision_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
+        out["precision"] = precision_leg(pf, torch, workloads, initial_polarisation, args.warm_start, args.precond)
     if args.micron:
         progress("micron leg")
         try:
-            out["micron"] = micron_leg(pf, torch, workloads, initial_polarisation, args.warm_start)
+            out["micron"] = micron_leg(pf, torch, workloads, initial_polarisation, args.warm_start, args.precond)
         except Exception as e:  # an optional leg: report, keep the main line
             out["micron"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
