@@ -295,17 +295,21 @@ pf_status pf_timing(pf_ctx *ctx, int enable, double *ms, int64_t *launches);
 size_t pf_fem_table_size(void);
 pf_status pf_fem_tables(const pf_config *cfg, double *out, size_t count);
 
-/* Diagnostic (host only): the multigrid hierarchy of the FEM operator used
- * with PF_PRECOND_MG.  *nlevels receives the number of levels; for the first
- * max_levels of them dims[3l..3l+2] = (nx, ny, nz) and omega[l] = the Jacobi
- * smoother's damping (either array may be NULL). */
-pf_status pf_mg_levels(const pf_config *cfg, int32_t *nlevels, int32_t *dims, double *omega, int32_t max_levels);
+/* Diagnostic (host only): the multigrid hierarchy used with PF_PRECOND_MG,
+ * field 0 for the Poisson operator, 1 for the FEM operator.  *nlevels
+ * receives the number of levels; for the first max_levels of them
+ * dims[3l..3l+2] = (nx, ny, nz) and omega[l] = the Jacobi smoother's damping
+ * (either array may be NULL).  The Poisson levels count the ghost planes: the
+ * bottom one (plane 0) and, with the metal top, the top one, both fixed. */
+pf_status pf_mg_levels(const pf_config *cfg, int32_t field, int32_t *nlevels, int32_t *dims, double *omega,
+                       int32_t max_levels);
 
-/* Diagnostic (host only): the Galerkin operator P^T A P of level `level`
- * (>= 1) as nz x 3 x 3 x 27 doubles, T[k][c][e][o]: row component c of plane
- * k against component e of the neighbour at offset o (same numbering as the
- * FEM tables).  `count` is the capacity of out in doubles. */
-pf_status pf_mg_table(const pf_config *cfg, int32_t level, double *out, size_t count);
+/* Diagnostic (host only): the operator of level `level` as nz x nc x nc x 27
+ * doubles (nc = 1 for field 0, 3 for field 1), T[k][c][e][o]: row component
+ * c of plane k against component e of the neighbour at offset o (same
+ * numbering as the FEM tables); level 0 is the solver's operator, levels
+ * >= 1 the Galerkin products P^T A P.  `count` is the capacity of out. */
+pf_status pf_mg_table(const pf_config *cfg, int32_t field, int32_t level, double *out, size_t count);
 
 const char *pf_status_str(pf_status s);
 const char *pf_last_error(const pf_ctx *ctx);

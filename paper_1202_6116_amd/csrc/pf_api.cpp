@@ -21,26 +21,33 @@
 namespace pf {
 
 MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb);
+MgHierarchy build_mg_phi(const pf_config& cfg);
 std::vector<MgLevel> mg_plan(const pf_config& cfg);
+std::vector<MgLevel> mg_plan_phi(const pf_config& cfg);
 template <typename T>
 hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const double* dinv, int mode,
                           double omega, const T* x, const T* b, T* out, const CgScalars* sc, double* partials,
                           int pstride, int poff, hipStream_t s);
 template <typename T>
-hipError_t launch_mg_level(const Dims& d, const double* tab, const double* dinv, int mode, double omega, const T* x,
-                           const T* b, T* out, const CgScalars* sc, hipStream_t s);
+hipError_t launch_mg_level(const Dims& d, int nc, const double* tab, const double* dinv, int mode, double omega,
+                           const T* x, const T* b, T* out, const CgScalars* sc, int top_fixed, hipStream_t s);
 template <typename T>
-hipError_t launch_mg_scale(const Dims& d, const double* dinv, double omega, const T* b, T* x, const CgScalars* sc,
+hipError_t launch_mg_scale(const Dims& d, int nc, const double* dinv, double omega, const T* b, T* x,
+                           const CgScalars* sc, hipStream_t s);
+template <typename T>
+hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap,
+                              const int* zfine, const T* rf, T* bc, const CgScalars* sc, int zoff, int fnz,
+                              int ctop_fixed, hipStream_t s);
+template <typename T>
+hipError_t launch_mg_prolong(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap, const T* xc,
+                             T* xf, const CgScalars* sc, int zoff, int ftop_fixed, int ctop_fixed, hipStream_t s);
+template <typename T>
+hipError_t launch_mg_dense(const Dims& d, int nc, int n, const double* M, const T* b, T* x, const CgScalars* sc,
                            hipStream_t s);
 template <typename T>
-hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int cx, int cy, const MgZ* zmap, const int* zfine,
-                              const T* rf, T* bc, const CgScalars* sc, hipStream_t s);
-template <typename T>
-hipError_t launch_mg_prolong(const Dims& df, const Dims& dc, int cx, int cy, const MgZ* zmap, const T* xc, T* xf,
-                             const CgScalars* sc, hipStream_t s);
-template <typename T>
-hipError_t launch_mg_dense(const Dims& d, int n, const double* M, const T* b, T* x, const CgScalars* sc,
-                           hipStream_t s);
+hipError_t launch_mgp_fine(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const double* dinv, int mode,
+                           double omega, const T* x, const T* b, T* out, const uint8_t* emask, const CgScalars* sc,
+                           double* partials, int pstride, int poff, hipStream_t s);
 
 // kernel launchers (pf_kernels.hip)
 int node_blocks(const Dims& d);
@@ -58,7 +65,7 @@ hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, c
                                 R* p, R* dz, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_poisson_cg_a(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* r, const T* p_old,
-                               T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s);
+                               T* p_new, T* x, const CgScalars* sc, double* partials, int unit_w, hipStream_t s);
 template <typename T>
 hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* p, T* r,
                                const uint8_t* emask, const CgScalars* sc, double* partials, hipStream_t s);
@@ -313,6 +320,18 @@ Dims potential_dims(const pf_config& c) {
 }
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Workspace of the multigrid of one operator (PF_PRECOND_MG with at least two
+// levels): the solver-grid z, pre-smoothed iterate and residual; per coarser
+// level b, v, t, o; per level the inverse diagonal, per coarser level its
+// stencils and z maps; the dense inverse of the coarsest level.  Vectors hold
+// nc components of doubles.
+struct MgLayout {
+  size_t z = 0, v0 = 0, t0 = 0;
+  std::vector<size_t> b, v, t, o, dinv, tab, zmap, zfine;
+  size_t dense = 0, dense_n = 0;  // the dense inverse and its order
+  size_t first = 0, end = 0;   // the range of all multigrid vectors (cleared at init)
+};
+
 struct Layout {
   // byte offsets into the workspace
   size_t P[2], V[2];           // state (state precision), double-buffered
@@ -327,21 +346,15 @@ struct Layout {
                                // (extrap_order slots of Np (phi) then extrap_order of 3N (u))
   size_t scratch[8];           // max(3N, Np) doubles each: adjoint, energy, conversions
   size_t tables, scalars, result, partials;
-  // multigrid of the FEM operator (PF_PRECOND_MG with at least two levels):
-  // fine-level z, pre-smoothed iterate and residual (3N doubles each); per
-  // coarser level b, v, t, o (3 N_l doubles each); per level the inverse
-  // diagonal, per coarser level its stencils and z maps; the dense inverse
-  size_t mg_z, mg_v0, mg_t0;
-  std::vector<size_t> mg_b, mg_v, mg_t, mg_o, mg_dinv, mg_tab, mg_zmap, mg_zfine;
-  size_t mg_dense;
-  size_t mg_first, mg_end;     // the range of all multigrid vectors (cleared at init)
+  MgLayout mg[2];              // multigrid of the Poisson (0) and the FEM (1) operator
   size_t total;
 };
 
-// Multigrid levels used for this configuration (empty: Jacobi).
-std::vector<MgLevel> mg_levels_for(const pf_config& c) {
+// Multigrid levels of one operator (0: Poisson, 1: FEM) for this
+// configuration (empty: Jacobi).
+std::vector<MgLevel> mg_levels_for(const pf_config& c, int field) {
   if (c.precond != PF_PRECOND_MG) return {};
-  std::vector<MgLevel> lv = mg_plan(c);
+  std::vector<MgLevel> lv = field == 0 ? mg_plan_phi(c) : mg_plan(c);
   if (lv.size() < 2) lv.clear();
   return lv;
 }
@@ -383,31 +396,38 @@ Layout make_layout(const pf_config& c, int npartials) {
   L.du = take(3 * N * 4);
   L.hist = c.warm_start == 2 && c.extrap_order > 0 ? take((Np + 3 * N) * 8 * (size_t)c.extrap_order) : 0;
   for (int t = 0; t < 8; t++) L.scratch[t] = take(S * 8);
-  const std::vector<MgLevel> mg = mg_levels_for(c);
-  L.mg_z = L.mg_v0 = L.mg_t0 = L.mg_dense = L.mg_first = L.mg_end = 0;
-  if (!mg.empty()) {
-    L.mg_first = o;
-    L.mg_z = take(3 * N * 8);
-    L.mg_v0 = take(3 * N * 8);
-    L.mg_t0 = take(3 * N * 8);
+  for (int f = 0; f < 2; f++) {
+    const std::vector<MgLevel> mg = mg_levels_for(c, f);
+    if (mg.empty()) continue;
+    MgLayout& M = L.mg[f];
+    const size_t nc = f == 0 ? 1 : 3;
+    const size_t N0 = f == 0 ? Np : N;
+    const size_t top = f == 0 && c.top_bc == PF_TOP_METAL ? 1 : 0;
+    M.first = o;
+    M.z = take(nc * N0 * 8);
+    M.v0 = take(nc * N0 * 8);
+    M.t0 = take(nc * N0 * 8);
     for (size_t l = 0; l < mg.size(); l++) {
       const size_t Nl = (size_t)mg[l].nx * mg[l].ny * mg[l].nz;
       const bool c1 = l > 0;
-      L.mg_b.push_back(c1 ? take(3 * Nl * 8) : 0);
-      L.mg_v.push_back(c1 ? take(3 * Nl * 8) : 0);
-      L.mg_t.push_back(c1 ? take(3 * Nl * 8) : 0);
-      L.mg_o.push_back(c1 ? take(3 * Nl * 8) : 0);
+      M.b.push_back(c1 ? take(nc * Nl * 8) : 0);
+      M.v.push_back(c1 ? take(nc * Nl * 8) : 0);
+      M.t.push_back(c1 ? take(nc * Nl * 8) : 0);
+      M.o.push_back(c1 ? take(nc * Nl * 8) : 0);
     }
-    L.mg_end = o;
+    M.end = o;
     for (size_t l = 0; l < mg.size(); l++) {
-      L.mg_dinv.push_back(take((size_t)mg[l].nz * 3 * 8));
-      L.mg_tab.push_back(l > 0 ? take((size_t)mg[l].nz * 243 * 8) : 0);
-      L.mg_zmap.push_back(l > 0 ? take((size_t)mg[l - 1].nz * sizeof(MgZ)) : 0);
-      L.mg_zfine.push_back(l > 0 ? take((size_t)mg[l].nz * sizeof(int)) : 0);
+      M.dinv.push_back(take((size_t)mg[l].nz * nc * 8));
+      M.tab.push_back(l > 0 ? take((size_t)mg[l].nz * nc * nc * 27 * 8) : 0);
+      M.zmap.push_back(l > 0 ? take((size_t)mg[l - 1].nz * sizeof(MgZ)) : 0);
+      M.zfine.push_back(l > 0 ? take((size_t)mg[l].nz * sizeof(int)) : 0);
     }
     const MgLevel& C = mg.back();
-    const size_t n = 3 * (size_t)C.nx * C.ny * (C.nz - 1);
-    if ((int64_t)n <= kMgDenseMax) L.mg_dense = take(n * n * 8);
+    const size_t n = nc * (size_t)C.nx * C.ny * (C.nz - 1 - top);
+    if ((int64_t)n <= kMgDenseMax) {
+      M.dense = take(n * n * 8);
+      M.dense_n = n;
+    }
   }
   L.tables = take(sizeof(FemTables));
   L.scalars = take(sizeof(CgScalars) * kNumScalars);
@@ -446,8 +466,8 @@ struct pf_ctx {
   pf_config cfg;
   std::vector<pf_electrode> electrodes;
   pf::Material mat;          // grid-frame stiffness and electrostriction
-  pf::MgHierarchy mg;        // multigrid of the FEM operator (levels empty: Jacobi)
-  std::vector<pf::Dims> mg_dims;
+  pf::MgHierarchy mg[2];     // multigrid of the Poisson (0) and FEM (1) operator (no levels: Jacobi)
+  std::vector<pf::Dims> mg_dims[2];
   pf::Dims dims;             // film grid
   pf::Dims dims_p;           // potential grid
   pf::Layout lay;
@@ -744,6 +764,124 @@ pf_status cg_status(pf_ctx* c, const CgScalars& h, SolveResult* res, const char*
   return PF_OK;
 }
 
+bool mg_on(const pf_ctx* c, int f) { return !c->mg[f].levels.empty(); }
+
+// One multigrid V-cycle z0 = M r0 of the Poisson (f = 0) or the FEM (f = 1)
+// operator (pre-smoothing: one damped Jacobi sweep from zero; residual,
+// restriction, the coarser levels, prolongation; post-smoothing: one sweep),
+// symmetric, so CG may use it.  The Poisson cycle runs on the operator of all
+// potential-grid nodes and zeroes z0 on the electrode nodes of the open top,
+// a projection that keeps the preconditioner symmetric on the unknowns.  The
+// last sweep also writes the tiles' r0 . z0 to part[lid * pstride + poff].
+// k: the CG iteration (for the event timing), -1 in a setup.
+template <typename T>
+hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double* part, int pstride, int poff,
+                     int k) {
+  const MgHierarchy& h = c->mg[f];
+  const MgLayout& L = c->lay.mg[f];
+  const std::vector<Dims>& D = c->mg_dims[f];
+  const int nl = (int)h.levels.size();
+  const int nc = h.nc;
+  const int top = h.top_fixed ? 1 : 0;
+  const FemTables* tb = at<FemTables>(c, c->lay.tables);
+  const bool gen = !c->mat.cubic;
+  const Coefs<T> cf = make_coefs<T>(c);
+  hipStream_t st = c->stream;
+  auto V = [&](size_t off) { return at<T>(c, off); };
+  auto Dv = [&](int l) { return at<double>(c, L.dinv[l]); };
+  auto Zm = [&](int l) { return at<MgZ>(c, L.zmap[l]); };
+  auto Zf = [&](int l) { return at<int>(c, L.zfine[l]); };
+  auto run = [&](auto&& fn) { return timed(c, PF_KC_MG, f, k, fn); };
+  // the solver grid: the Poisson levels count a fixed bottom plane below it
+  const int zoff0 = f == 0 ? 1 : 0;
+  auto fine = [&](int mode, double omega, const T* x, T* out, double* pp) {
+    if (f == 0)
+      return launch_mgp_fine<T>(D[0], c->tm_p, cf, Dv(0), mode, omega, x, r0, out,
+                                mode == kMgSweep ? emask(c) : nullptr, sc, pp, pstride, poff, st);
+    return launch_mg_fine<T>(D[0], c->tm_f, tb, gen, Dv(0), mode, omega, x, r0, out, sc, pp, pstride, poff, st);
+  };
+  const Dims& d0 = D[0];
+  T* v0 = V(L.v0);
+  T* t0 = V(L.t0);
+  hipError_t e = run([&] { return launch_mg_scale<T>(d0, nc, Dv(0), h.levels[0].omega, r0, v0, sc, st); });
+  if (e == hipSuccess) e = run([&] { return fine(kMgResidual, 0.0, v0, t0, nullptr); });
+  if (e == hipSuccess)
+    e = run([&] {
+      return launch_mg_restrict<T>(d0, D[1], nc, h.levels[1].cx, h.levels[1].cy, Zm(1), Zf(1), t0, V(L.b[1]), sc,
+                                   zoff0, h.levels[0].nz, top, st);
+    });
+  for (int l = 1; l < nl - 1 && e == hipSuccess; l++) {
+    const Dims& d = D[l];
+    const double* tab = at<double>(c, L.tab[l]);
+    e = run([&] { return launch_mg_scale<T>(d, nc, Dv(l), h.levels[l].omega, V(L.b[l]), V(L.v[l]), sc, st); });
+    if (e == hipSuccess)
+      e = run([&] {
+        return launch_mg_level<T>(d, nc, tab, Dv(l), kMgResidual, 0.0, V(L.v[l]), V(L.b[l]), V(L.t[l]), sc, top,
+                                  st);
+      });
+    if (e == hipSuccess)
+      e = run([&] {
+        return launch_mg_restrict<T>(d, D[l + 1], nc, h.levels[l + 1].cx, h.levels[l + 1].cy, Zm(l + 1), Zf(l + 1),
+                                     V(L.t[l]), V(L.b[l + 1]), sc, 0, d.nz, top, st);
+      });
+  }
+  // coarsest level
+  const int lc = nl - 1;
+  if (e == hipSuccess) {
+    const Dims& d = D[lc];
+    if (h.dense_n > 0) {
+      e = run([&] {
+        return launch_mg_dense<T>(d, nc, h.dense_n, at<double>(c, L.dense), V(L.b[lc]), V(L.o[lc]), sc, st);
+      });
+    } else {
+      // damped Jacobi sweeps from zero, ping-pong between v and t, last into o
+      const double* tab = at<double>(c, L.tab[lc]);
+      const int ns = std::max(1, h.coarse_sweeps);
+      T* cur = V(ns == 1 ? L.o[lc] : L.v[lc]);
+      e = run([&] { return launch_mg_scale<T>(d, nc, Dv(lc), h.levels[lc].omega, V(L.b[lc]), cur, sc, st); });
+      for (int t = 1; t < ns && e == hipSuccess; t++) {
+        T* nxt = t == ns - 1 ? V(L.o[lc]) : (cur == V(L.v[lc]) ? V(L.t[lc]) : V(L.v[lc]));
+        e = run([&] {
+          return launch_mg_level<T>(d, nc, tab, Dv(lc), kMgSweep, h.levels[lc].omega, cur, V(L.b[lc]), nxt, sc, top,
+                                    st);
+        });
+        cur = nxt;
+      }
+    }
+  }
+  for (int l = nl - 2; l >= 1 && e == hipSuccess; l--) {
+    const Dims& d = D[l];
+    const double* tab = at<double>(c, L.tab[l]);
+    e = run([&] {
+      return launch_mg_prolong<T>(d, D[l + 1], nc, h.levels[l + 1].cx, h.levels[l + 1].cy, Zm(l + 1), V(L.o[l + 1]),
+                                  V(L.v[l]), sc, 0, top, top, st);
+    });
+    if (e == hipSuccess)
+      e = run([&] {
+        return launch_mg_level<T>(d, nc, tab, Dv(l), kMgSweep, h.levels[l].omega, V(L.v[l]), V(L.b[l]), V(L.o[l]),
+                                  sc, top, st);
+      });
+  }
+  if (e == hipSuccess)
+    e = run([&] {
+      return launch_mg_prolong<T>(d0, D[1], nc, h.levels[1].cx, h.levels[1].cy, Zm(1), V(L.o[1]), v0, sc, zoff0, 0,
+                                  top, st);
+    });
+  if (e == hipSuccess) e = run([&] { return fine(kMgSweep, h.levels[0].omega, v0, z0, part); });
+  return e;
+}
+
+// After a setup with the multigrid preconditioner: z = M r and rho = r.z.
+template <typename T>
+hipError_t mg_setup(pf_ctx* c, int f, const T* r) {
+  CgScalars* sc = dev_sc(c, f);
+  double* part = dev_partials(c, 3);
+  hipError_t e = mg_vcycle<T>(c, f, r, at<T>(c, c->lay.mg[f].z), sc, part, 1, 0, -1);
+  const int nb = f == 0 ? c->tm_p.nblocks : c->tm_f.nblocks;
+  if (e == hipSuccess) e = reduce(c, part, nb, 1, f, kRedRho, 0.0, 0.0, nullptr);
+  return e;
+}
+
 template <typename T>
 std::function<hipError_t(int)> poisson_iteration(pf_ctx* c, const Coefs<T>& cf, T* r, T* const pb[2], T* x,
                                                  double tol) {
@@ -752,122 +890,21 @@ std::function<hipError_t(int)> poisson_iteration(pf_ctx* c, const Coefs<T>& cf, 
     const uint8_t* em = emask(c);
     CgScalars* sc = dev_sc(c, 0);
     double* part = dev_partials(c, 0);
+    const bool mg = mg_on(c, 0);
+    T* z = mg ? at<T>(c, c->lay.mg[0].z) : nullptr;
     hipError_t e = timed(c, PF_KC_POISSON_A, 0, k, [&] {
-      return launch_poisson_cg_a<T>(d, c->tm_p, cf, r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, c->stream);
+      return launch_poisson_cg_a<T>(d, c->tm_p, cf, mg ? z : r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, mg ? 1 : 0,
+                                    c->stream);
     });
     if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 1, 0, kRedAlpha, tol, 0, nullptr, 0, k);
     if (e == hipSuccess)
       e = timed(c, PF_KC_POISSON_B, 0, k,
                 [&] { return launch_poisson_cg_b<T>(d, c->tm_p, cf, pb[(k + 1) & 1], r, em, sc, part, c->stream); });
+    // multigrid: z = M r replaces the Jacobi-weighted r.z of kernel B
+    if (e == hipSuccess && mg) e = mg_vcycle<T>(c, 0, r, z, sc, part, 2, 0, k);
     if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 2, 0, kRedBeta, tol, 0, nullptr, 0, k);
     return e;
   };
-}
-
-bool mg_on(const pf_ctx* c) { return !c->mg.levels.empty(); }
-
-// One multigrid V-cycle z0 = M r0 of the FEM operator (pre-smoothing: one
-// damped Jacobi sweep from zero; residual, restriction, the coarser levels,
-// prolongation; post-smoothing: one sweep), symmetric, so CG may use it.
-// The last sweep also writes the tiles' r0 . z0 to part[lid * pstride +
-// poff].  k: the CG iteration (for the event timing), -1 in a setup.
-template <typename T>
-hipError_t mg_vcycle(pf_ctx* c, const T* r0, T* z0, CgScalars* sc, double* part, int pstride, int poff, int k) {
-  const MgHierarchy& h = c->mg;
-  const Layout& L = c->lay;
-  const int nl = (int)h.levels.size();
-  const FemTables* tb = at<FemTables>(c, L.tables);
-  const bool gen = !c->mat.cubic;
-  hipStream_t st = c->stream;
-  auto V = [&](size_t off) { return at<T>(c, off); };
-  auto Dv = [&](int l) { return at<double>(c, L.mg_dinv[l]); };
-  auto Zm = [&](int l) { return at<MgZ>(c, L.mg_zmap[l]); };
-  auto Zf = [&](int l) { return at<int>(c, L.mg_zfine[l]); };
-  auto run = [&](auto&& f) { return timed(c, PF_KC_MG, 1, k, f); };
-  const Dims& d0 = c->mg_dims[0];
-  T* v0 = V(L.mg_v0);
-  T* t0 = V(L.mg_t0);
-  hipError_t e = run([&] { return launch_mg_scale<T>(d0, Dv(0), h.levels[0].omega, r0, v0, sc, st); });
-  if (e == hipSuccess)
-    e = run([&] {
-      return launch_mg_fine<T>(d0, c->tm_f, tb, gen, Dv(0), kMgResidual, 0.0, v0, r0, t0, sc, nullptr, 0, 0, st);
-    });
-  if (e == hipSuccess)
-    e = run([&] {
-      return launch_mg_restrict<T>(d0, c->mg_dims[1], h.levels[1].cx, h.levels[1].cy, Zm(1), Zf(1), t0,
-                                   V(L.mg_b[1]), sc, st);
-    });
-  for (int l = 1; l < nl - 1 && e == hipSuccess; l++) {
-    const Dims& d = c->mg_dims[l];
-    const double* tab = at<double>(c, L.mg_tab[l]);
-    e = run([&] { return launch_mg_scale<T>(d, Dv(l), h.levels[l].omega, V(L.mg_b[l]), V(L.mg_v[l]), sc, st); });
-    if (e == hipSuccess)
-      e = run([&] {
-        return launch_mg_level<T>(d, tab, Dv(l), kMgResidual, 0.0, V(L.mg_v[l]), V(L.mg_b[l]), V(L.mg_t[l]), sc, st);
-      });
-    if (e == hipSuccess)
-      e = run([&] {
-        return launch_mg_restrict<T>(d, c->mg_dims[l + 1], h.levels[l + 1].cx, h.levels[l + 1].cy, Zm(l + 1),
-                                     Zf(l + 1), V(L.mg_t[l]), V(L.mg_b[l + 1]), sc, st);
-      });
-  }
-  // coarsest level
-  const int lc = nl - 1;
-  if (e == hipSuccess) {
-    const Dims& d = c->mg_dims[lc];
-    if (h.dense_n > 0) {
-      e = run([&] {
-        return launch_mg_dense<T>(d, h.dense_n, at<double>(c, L.mg_dense), V(L.mg_b[lc]), V(L.mg_o[lc]), sc, st);
-      });
-    } else {
-      // damped Jacobi sweeps from zero, ping-pong between v and t, last into o
-      const double* tab = at<double>(c, L.mg_tab[lc]);
-      const int ns = std::max(1, h.coarse_sweeps);
-      T* cur = V(ns == 1 ? L.mg_o[lc] : L.mg_v[lc]);
-      e = run([&] { return launch_mg_scale<T>(d, Dv(lc), h.levels[lc].omega, V(L.mg_b[lc]), cur, sc, st); });
-      for (int t = 1; t < ns && e == hipSuccess; t++) {
-        T* nxt = t == ns - 1 ? V(L.mg_o[lc]) : (cur == V(L.mg_v[lc]) ? V(L.mg_t[lc]) : V(L.mg_v[lc]));
-        e = run([&] {
-          return launch_mg_level<T>(d, tab, Dv(lc), kMgSweep, h.levels[lc].omega, cur, V(L.mg_b[lc]), nxt, sc, st);
-        });
-        cur = nxt;
-      }
-    }
-  }
-  for (int l = nl - 2; l >= 1 && e == hipSuccess; l--) {
-    const Dims& d = c->mg_dims[l];
-    const double* tab = at<double>(c, L.mg_tab[l]);
-    e = run([&] {
-      return launch_mg_prolong<T>(d, c->mg_dims[l + 1], h.levels[l + 1].cx, h.levels[l + 1].cy, Zm(l + 1),
-                                  V(L.mg_o[l + 1]), V(L.mg_v[l]), sc, st);
-    });
-    if (e == hipSuccess)
-      e = run([&] {
-        return launch_mg_level<T>(d, tab, Dv(l), kMgSweep, h.levels[l].omega, V(L.mg_v[l]), V(L.mg_b[l]),
-                                  V(L.mg_o[l]), sc, st);
-      });
-  }
-  if (e == hipSuccess)
-    e = run([&] {
-      return launch_mg_prolong<T>(d0, c->mg_dims[1], h.levels[1].cx, h.levels[1].cy, Zm(1), V(L.mg_o[1]), v0, sc,
-                                  st);
-    });
-  if (e == hipSuccess)
-    e = run([&] {
-      return launch_mg_fine<T>(d0, c->tm_f, tb, gen, Dv(0), kMgSweep, h.levels[0].omega, v0, r0, z0, sc, part,
-                               pstride, poff, st);
-    });
-  return e;
-}
-
-// After a FEM setup with the multigrid preconditioner: z = M r and rho = r.z.
-template <typename T>
-hipError_t mg_setup(pf_ctx* c, const T* r) {
-  CgScalars* sc = dev_sc(c, 1);
-  double* part = dev_partials(c, 3);
-  hipError_t e = mg_vcycle<T>(c, r, at<T>(c, c->lay.mg_z), sc, part, 1, 0, -1);
-  if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 1, 1, kRedRho, 0.0, 0.0, nullptr);
-  return e;
 }
 
 template <typename T>
@@ -877,8 +914,8 @@ std::function<hipError_t(int)> fem_iteration(pf_ctx* c, T* r, T* const pb[2], T*
     const FemTables* tb = at<FemTables>(c, c->lay.tables);
     CgScalars* sc = dev_sc(c, 1);
     double* part = dev_partials(c, 1);
-    const bool mg = mg_on(c);
-    T* z = mg ? at<T>(c, c->lay.mg_z) : nullptr;
+    const bool mg = mg_on(c, 1);
+    T* z = mg ? at<T>(c, c->lay.mg[1].z) : nullptr;
     hipError_t e = timed(c, PF_KC_FEM_A, 1, k, [&] {
       return launch_fem_cg_a<T>(d, c->tm_f, tb, !c->mat.cubic, mg ? z : r, pb[k & 1], pb[(k + 1) & 1], x, sc, part,
                                 mg ? 1 : 0, c->stream);
@@ -890,7 +927,7 @@ std::function<hipError_t(int)> fem_iteration(pf_ctx* c, T* r, T* const pb[2], T*
                   return launch_fem_cg_b<T>(d, c->tm_f, tb, !c->mat.cubic, pb[(k + 1) & 1], r, sc, part, c->stream);
                 });
     // multigrid: z = M r replaces the Jacobi-weighted r.z of kernel B
-    if (e == hipSuccess && mg) e = mg_vcycle<T>(c, r, z, sc, part, 2, 0, k);
+    if (e == hipSuccess && mg) e = mg_vcycle<T>(c, 1, r, z, sc, part, 2, 0, k);
     if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 2, 1, kRedBeta, tol, 0, nullptr, 1, k);
     return e;
   };
@@ -913,6 +950,7 @@ pf_status solve_poisson64(pf_ctx* c, int pred, const S* P, const S* V, double cd
                                                    x, r, pb[0], nullptr, part, c->stream);
   }));
   PF_HIP(c, reduce(c, part, c->nblocks_p, 3, 0, kRedSetup, tol, 0, nullptr));
+  if (mg_on(c, 0)) PF_HIP(c, mg_setup<double>(c, 0, r));
   CgScalars h;
   PF_TRY(run_cg<double>(c, 0, c->pred[pred], x, pb, d.N, poisson_iteration<double>(c, cf, r, pb, x, tol), &h,
                         "Poisson solve"));
@@ -936,7 +974,7 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
                                                part, c->stream);
   }));
   PF_HIP(c, reduce(c, part, c->nblocks, 3, 1, kRedSetup, tol, 0, nullptr));
-  if (mg_on(c)) PF_HIP(c, mg_setup<double>(c, r));
+  if (mg_on(c, 1)) PF_HIP(c, mg_setup<double>(c, 1, r));
   CgScalars h;
   PF_TRY(run_cg<double>(c, 1, c->pred[pred], x, pb, 3 * d.N, fem_iteration<double>(c, r, pb, x, tol), &h,
                         "FEM solve"));
@@ -986,7 +1024,7 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
       }));
     }
     PF_HIP(c, reduce(c, part, setup_blocks, 3, which, kRedOuter, tol, kInnerTol, nullptr));
-    if (fem && mg_on(c)) PF_HIP(c, mg_setup<float>(c, r));
+    if (mg_on(c, which)) PF_HIP(c, mg_setup<float>(c, which, r));
     CgScalars h;
     PF_TRY(run_cg<float>(c, which, c->pred[pred], dz, pb, n, iteration, &h, what));
     res->iters += h.iter;
@@ -1142,36 +1180,46 @@ pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt
   return PF_OK;
 }
 
-// Builds the multigrid hierarchy of the FEM operator and uploads it; clears
-// the multigrid vectors (their clamp planes stay zero).  Synchronises.
-pf_status upload_mg(pf_ctx* c, const FemTables& tb) {
-  c->mg = build_mg(c->cfg, tb);
-  MgHierarchy& h = c->mg;
-  const Layout& L = c->lay;
-  if (h.levels.size() != L.mg_dinv.size())
-    return fail(c, PF_EINVAL, "multigrid plan changed between layout and init");
-  c->mg_dims.clear();
+// Builds the multigrid hierarchy of one operator (0: Poisson, 1: FEM) and
+// uploads it; clears the multigrid vectors (their fixed planes stay zero).
+// The Poisson solver grid stores no bottom ghost plane, so the inverse
+// diagonal of its level 0 is uploaded from its second plane on.
+// Synchronises.
+pf_status upload_mg(pf_ctx* c, int f, const FemTables& tb) {
+  c->mg[f] = f == 0 ? build_mg_phi(c->cfg) : build_mg(c->cfg, tb);
+  MgHierarchy& h = c->mg[f];
+  const MgLayout& L = c->lay.mg[f];
+  if (h.levels.size() != L.dinv.size()) return fail(c, PF_EINVAL, "multigrid plan changed between layout and init");
+  std::vector<Dims>& D = c->mg_dims[f];
+  D.clear();
   for (size_t l = 0; l < h.levels.size(); l++) {
     const MgLevel& m = h.levels[l];
     const int64_t plane = (int64_t)m.nx * m.ny;
-    c->mg_dims.push_back(l == 0 ? c->dims : Dims{m.nx, m.ny, m.nz, plane * m.nz, plane, m.nz, plane * m.nz, m.nz});
-    PF_HIP(c, hipMemcpyAsync(c->ws + L.mg_dinv[l], m.dinv.data(), m.dinv.size() * 8, hipMemcpyHostToDevice,
-                             c->stream));
+    D.push_back(l == 0 ? (f == 0 ? c->dims_p : c->dims)
+                       : Dims{m.nx, m.ny, m.nz, plane * m.nz, plane, m.nz, plane * m.nz, m.nz});
+    const size_t skip = l == 0 && f == 0 ? (size_t)h.nc : 0;
+    const size_t count = (size_t)D.back().nz * h.nc;
+    if (skip + count > m.dinv.size()) return fail(c, PF_EINVAL, "multigrid: level %zu does not match its grid", l);
+    PF_HIP(c, hipMemcpyAsync(c->ws + L.dinv[l], m.dinv.data() + skip, count * 8, hipMemcpyHostToDevice, c->stream));
     if (l > 0) {
-      PF_HIP(c, hipMemcpyAsync(c->ws + L.mg_tab[l], h.tables[l].data(), h.tables[l].size() * 8,
+      if (h.tables[l].size() != (size_t)m.nz * h.nc * h.nc * 27 || h.zmaps[l].size() != (size_t)h.levels[l - 1].nz ||
+          h.zfine[l].size() != (size_t)m.nz)
+        return fail(c, PF_EINVAL, "multigrid: level %zu tables do not match its grid", l);
+      PF_HIP(c, hipMemcpyAsync(c->ws + L.tab[l], h.tables[l].data(), h.tables[l].size() * 8, hipMemcpyHostToDevice,
+                               c->stream));
+      PF_HIP(c, hipMemcpyAsync(c->ws + L.zmap[l], h.zmaps[l].data(), h.zmaps[l].size() * sizeof(MgZ),
                                hipMemcpyHostToDevice, c->stream));
-      PF_HIP(c, hipMemcpyAsync(c->ws + L.mg_zmap[l], h.zmaps[l].data(), h.zmaps[l].size() * sizeof(MgZ),
-                               hipMemcpyHostToDevice, c->stream));
-      PF_HIP(c, hipMemcpyAsync(c->ws + L.mg_zfine[l], h.zfine[l].data(), h.zfine[l].size() * sizeof(int),
+      PF_HIP(c, hipMemcpyAsync(c->ws + L.zfine[l], h.zfine[l].data(), h.zfine[l].size() * sizeof(int),
                                hipMemcpyHostToDevice, c->stream));
     }
   }
   if (h.dense_n > 0) {
-    if (L.mg_dense == 0) return fail(c, PF_EINVAL, "multigrid: no room for the coarsest inverse");
-    PF_HIP(c, hipMemcpyAsync(c->ws + L.mg_dense, h.dense_inv.data(), h.dense_inv.size() * 8, hipMemcpyHostToDevice,
+    if (L.dense == 0 || (size_t)h.dense_n != L.dense_n)
+      return fail(c, PF_EINVAL, "multigrid: no room for the coarsest inverse");
+    PF_HIP(c, hipMemcpyAsync(c->ws + L.dense, h.dense_inv.data(), h.dense_inv.size() * 8, hipMemcpyHostToDevice,
                              c->stream));
   }
-  PF_HIP(c, launch_fill<double>(at<double>(c, L.mg_first), (int64_t)((L.mg_end - L.mg_first) / 8), 0.0, c->stream));
+  PF_HIP(c, launch_fill<double>(at<double>(c, L.first), (int64_t)((L.end - L.first) / 8), 0.0, c->stream));
   PF_HIP(c, hipStreamSynchronize(c->stream));
   return PF_OK;
 }
@@ -1402,6 +1450,17 @@ int partial_slots(const pf_config& c) {
 }  // namespace
 }  // namespace pf
 
+namespace pf {
+namespace {
+MgHierarchy diag_hierarchy(const pf_config* cfg, int32_t field) {
+  if (field == 0) return build_mg_phi(*cfg);
+  FemTables t;
+  build_tables(*cfg, &t);
+  return build_mg(*cfg, t);
+}
+}  // namespace
+}  // namespace pf
+
 using namespace pf;
 
 extern "C" {
@@ -1484,7 +1543,8 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   pf_status st = PF_OK;
   hipError_t e = hipMemcpyAsync(c->ws + c->lay.tables, &tb, sizeof(tb), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) st = fail(c, PF_EHIP, "table upload: %s", hipGetErrorString(e));
-  if (st == PF_OK && !c->lay.mg_dinv.empty()) st = upload_mg(c, tb);
+  for (int f = 0; f < 2 && st == PF_OK; f++)
+    if (!c->lay.mg[f].dinv.empty()) st = upload_mg(c, f, tb);
   if (st == PF_OK) st = upload_ghosts(c);
   if (st == PF_OK) {
     static_assert(sizeof(CgScalars) % 8 == 0, "scalars are cleared as doubles");
@@ -1728,11 +1788,10 @@ pf_status pf_timing(pf_ctx* c, int enable, double* ms, int64_t* launches) {
   return PF_OK;
 }
 
-pf_status pf_mg_levels(const pf_config* cfg, int32_t* nlevels, int32_t* dims, double* omega, int32_t max_levels) {
-  if (!nlevels || validate(cfg, nullptr) != PF_OK) return PF_EINVAL;
-  FemTables t;
-  build_tables(*cfg, &t);
-  const MgHierarchy h = build_mg(*cfg, t);
+pf_status pf_mg_levels(const pf_config* cfg, int32_t field, int32_t* nlevels, int32_t* dims, double* omega,
+                       int32_t max_levels) {
+  if (!nlevels || (field != 0 && field != 1) || validate(cfg, nullptr) != PF_OK) return PF_EINVAL;
+  const MgHierarchy h = diag_hierarchy(cfg, field);
   *nlevels = (int32_t)h.levels.size();
   for (int l = 0; l < (int)h.levels.size() && l < max_levels; l++) {
     if (dims) {
@@ -1745,12 +1804,10 @@ pf_status pf_mg_levels(const pf_config* cfg, int32_t* nlevels, int32_t* dims, do
   return PF_OK;
 }
 
-pf_status pf_mg_table(const pf_config* cfg, int32_t level, double* out, size_t count) {
-  if (!out || validate(cfg, nullptr) != PF_OK) return PF_EINVAL;
-  FemTables t;
-  build_tables(*cfg, &t);
-  const MgHierarchy h = build_mg(*cfg, t);
-  if (level < 1 || level >= (int32_t)h.levels.size()) return PF_EINVAL;
+pf_status pf_mg_table(const pf_config* cfg, int32_t field, int32_t level, double* out, size_t count) {
+  if (!out || (field != 0 && field != 1) || validate(cfg, nullptr) != PF_OK) return PF_EINVAL;
+  const MgHierarchy h = diag_hierarchy(cfg, field);
+  if (level < 0 || level >= (int32_t)h.levels.size()) return PF_EINVAL;
   const std::vector<double>& T = h.tables[level];
   if (count < T.size()) return PF_EINVAL;
   std::memcpy(out, T.data(), T.size() * 8);

@@ -449,11 +449,12 @@ __global__ __launch_bounds__(kThreads) void poisson_setup_kernel(
 // Iteration kernel A: p_new = z + beta p_old on the tile and its halo, q =
 // A p_new, x += alpha_prev p_old (the deferred update of the previous
 // iteration); partial p_new . q.
+// unit_w: r holds the preconditioned residual z itself (multigrid).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap tm, Coefs<T> cf,
                                                                 const T* __restrict__ r, const T* __restrict__ p_old,
                                                                 T* __restrict__ p_new, T* __restrict__ x,
-                                                                const CgScalars* sc, double* partials) {
+                                                                const CgScalars* sc, double* partials, int unit_w) {
   if (sc->done) return;
   constexpr int TY = kBY;
   __shared__ T ring[3][1][TY + 2][kHX];
@@ -467,7 +468,9 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
     raw[0] = r[m];
     raw[1] = p_old[m];
   };
-  auto comb = [&](int kk, const T* raw, T* out) { out[0] = raw[0] * plane_eps(d, cf, kk).w + beta * raw[1]; };
+  auto comb = [&](int kk, const T* raw, T* out) {
+    out[0] = raw[0] * (unit_w ? (T)1 : plane_eps(d, cf, kk).w) + beta * raw[1];
+  };
   Stage<T, 2, Halo<TY>::NPT> st;
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
   stage_store<TY>(ring, st, tc.k0 - 1, comb);
@@ -1124,45 +1127,52 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
   if (partials) block_sum_to<kThreads>(acc, partials + (int64_t)tc.lid * pstride + poff);
 }
 
-// Coarse level (per-plane stencils tab[k][c][e][o]): out = b - A x or
-// out = x + omega D^-1 (b - A x).  One thread per node.
-template <typename T>
+// Coarse level (per-plane stencils tab[k][c][e][o], NC components): out =
+// b - A x or out = x + omega D^-1 (b - A x).  Plane 0 and, with top_fixed,
+// the top plane hold no unknowns (never written, zero).  One thread per node.
+template <typename T, int NC>
 __global__ __launch_bounds__(kThreads) void mg_level_kernel(Dims d, const double* __restrict__ tab,
                                                             const double* __restrict__ dinv, int mode, double omega,
                                                             const T* __restrict__ x, const T* __restrict__ b,
-                                                            T* __restrict__ out, const CgScalars* sc) {
+                                                            T* __restrict__ out, const CgScalars* sc, int top_fixed) {
   if (sc->done) return;
   const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
-  if (i >= d.nx || j >= d.ny || k == 0) return;
+  const int ktop = d.nz - (top_fixed ? 1 : 0);
+  if (i >= d.nx || j >= d.ny || k == 0 || k >= ktop) return;
   const int64_t N = d.N;
   const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
-  const double* tk = tab + (size_t)k * 243;
-  double q[3] = {0.0, 0.0, 0.0};
+  const double* tk = tab + (size_t)k * NC * NC * 27;
+  double q[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) q[c] = 0.0;
   for (int dz = -1; dz <= 1; dz++) {
     const int kk = k + dz;
-    if (kk < 1 || kk >= d.nz) continue;
+    if (kk < 1 || kk >= ktop) continue;
 #pragma unroll
     for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
       for (int dx = -1; dx <= 1; dx++) {
         const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
         const int64_t m = nbr(d, i, j, k, dx, dy, dz);
-        const double u[3] = {(double)x[m], (double)x[N + m], (double)x[2 * N + m]};
+        double u[NC];
 #pragma unroll
-        for (int c = 0; c < 3; c++)
+        for (int e = 0; e < NC; e++) u[e] = (double)x[e * N + m];
 #pragma unroll
-          for (int e = 0; e < 3; e++) q[c] += tk[(c * 3 + e) * 27 + o] * u[e];
+        for (int c = 0; c < NC; c++)
+#pragma unroll
+          for (int e = 0; e < NC; e++) q[c] += tk[(c * NC + e) * 27 + o] * u[e];
       }
   }
 #pragma unroll
-  for (int c = 0; c < 3; c++) {
+  for (int c = 0; c < NC; c++) {
     const double r = (double)b[c * N + n] - q[c];
-    out[c * N + n] = (T)(mode == kMgResidual ? r : (double)x[c * N + n] + omega * dinv[3 * k + c] * r);
+    out[c * N + n] = (T)(mode == kMgResidual ? r : (double)x[c * N + n] + omega * dinv[NC * k + c] * r);
   }
 }
 
-// x = omega D^-1 b (the first sweep from zero); plane 0 gets zero.
-template <typename T>
+// x = omega D^-1 b (the first sweep from zero); fixed planes get zero (their
+// inverse diagonal is zero).
+template <typename T, int NC>
 __global__ __launch_bounds__(kThreads) void mg_scale_kernel(Dims d, const double* __restrict__ dinv, double omega,
                                                             const T* __restrict__ b, T* __restrict__ x,
                                                             const CgScalars* sc) {
@@ -1171,7 +1181,7 @@ __global__ __launch_bounds__(kThreads) void mg_scale_kernel(Dims d, const double
   if (i >= d.nx || j >= d.ny) return;
   const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
 #pragma unroll
-  for (int c = 0; c < 3; c++) x[c * d.N + n] = (T)(omega * dinv[3 * k + c] * (double)b[c * d.N + n]);
+  for (int c = 0; c < NC; c++) x[c * d.N + n] = (T)(omega * dinv[NC * k + c] * (double)b[c * d.N + n]);
 }
 
 // Parents of fine node i along a periodic axis: coarse node i/2 (even i) or
@@ -1191,19 +1201,25 @@ __device__ __forceinline__ int mg_parents(int i, int nc, int coarsened, int idx[
 }
 
 // Restriction (the transpose of the prolongation): coarse b = P^T r.  One
-// thread per coarse node; fine planes zfine[K] - 1 .. zfine[K] + 1.
-template <typename T>
+// thread per coarse node.  The z maps count the finer level's planes from its
+// plane 0; its stored plane is that index minus zoff (the Poisson grid
+// stores no ghost planes), and planes outside storage carry zero.
+template <typename T, int NC>
 __global__ __launch_bounds__(kThreads) void mg_restrict_kernel(Dims df, Dims dc, int cx, int cy,
                                                                const MgZ* __restrict__ zmap,
                                                                const int* __restrict__ zfine, const T* __restrict__ rf,
-                                                               T* __restrict__ bc, const CgScalars* sc) {
+                                                               T* __restrict__ bc, const CgScalars* sc, int zoff,
+                                                               int fnz, int ctop_fixed) {
   if (sc->done) return;
   const int I = blockIdx.x * kBX + threadIdx.x, J = blockIdx.y * kBY + threadIdx.y, K = blockIdx.z;
-  if (I >= dc.nx || J >= dc.ny || K == 0) return;
-  double acc[3] = {0.0, 0.0, 0.0};
+  if (I >= dc.nx || J >= dc.ny || K == 0 || (ctop_fixed && K == dc.nz - 1)) return;
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) acc[c] = 0.0;
   const int kf0 = zfine[K];
   for (int kf = kf0 - 1; kf <= kf0 + 1; kf++) {
-    if (kf < 1 || kf >= df.nz) continue;
+    const int ks = kf - zoff;
+    if (kf < 1 || kf >= fnz || ks < 0 || ks >= df.nz) continue;
     const MgZ z = zmap[kf];
     double wz = 0.0;
     if (z.lo == K) wz += z.wlo;
@@ -1217,56 +1233,61 @@ __global__ __launch_bounds__(kThreads) void mg_restrict_kernel(Dims df, Dims dc,
         if (!cy && dj != 0) continue;
         const int fj = cy ? wrap(2 * J + dj, df.ny) : J;
         const double w = wz * wx * (dj == 0 ? 1.0 : 0.5);
-        const int64_t m = fi + (int64_t)df.nx * fj + df.plane * kf;
+        const int64_t m = fi + (int64_t)df.nx * fj + df.plane * ks;
 #pragma unroll
-        for (int c = 0; c < 3; c++) acc[c] += w * (double)rf[c * df.N + m];
+        for (int c = 0; c < NC; c++) acc[c] += w * (double)rf[c * df.N + m];
       }
     }
   }
   const int64_t nc = I + (int64_t)dc.nx * J + dc.plane * K;
 #pragma unroll
-  for (int c = 0; c < 3; c++) bc[c * dc.N + nc] = (T)acc[c];
+  for (int c = 0; c < NC; c++) bc[c * dc.N + nc] = (T)acc[c];
 }
 
-// Prolongation and correction: xf += P xc.  One thread per fine node.
-template <typename T>
+// Prolongation and correction: xf += P xc.  One thread per stored fine node
+// (plane index + zoff in the z map); fixed planes are skipped.
+template <typename T, int NC>
 __global__ __launch_bounds__(kThreads) void mg_prolong_kernel(Dims df, Dims dc, int cx, int cy,
                                                               const MgZ* __restrict__ zmap, const T* __restrict__ xc,
-                                                              T* __restrict__ xf, const CgScalars* sc) {
+                                                              T* __restrict__ xf, const CgScalars* sc, int zoff,
+                                                              int ftop_fixed, int ctop_fixed) {
   if (sc->done) return;
   const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
-  if (i >= df.nx || j >= df.ny || k == 0) return;
+  const int kf = k + zoff;
+  if (i >= df.nx || j >= df.ny || kf == 0 || (ftop_fixed && k == df.nz - 1)) return;
   int xi[2], yi[2];
   double xw[2], yw[2];
   const int nxp = mg_parents(i, dc.nx, cx, xi, xw), nyp = mg_parents(j, dc.ny, cy, yi, yw);
-  const MgZ z = zmap[k];
+  const MgZ z = zmap[kf];
   const int zi[2] = {z.lo, z.hi};
   const double zw[2] = {z.wlo, z.whi};
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) acc[c] = 0.0;
   for (int a = 0; a < 2; a++) {
-    if (zw[a] == 0.0 || zi[a] == 0) continue;
+    if (zw[a] == 0.0 || zi[a] == 0 || (ctop_fixed && zi[a] == dc.nz - 1)) continue;
     for (int bq = 0; bq < nyp; bq++)
       for (int q = 0; q < nxp; q++) {
         const double w = zw[a] * yw[bq] * xw[q];
         const int64_t m = xi[q] + (int64_t)dc.nx * yi[bq] + dc.plane * zi[a];
 #pragma unroll
-        for (int c = 0; c < 3; c++) acc[c] += w * (double)xc[c * dc.N + m];
+        for (int c = 0; c < NC; c++) acc[c] += w * (double)xc[c * dc.N + m];
       }
   }
   const int64_t n = i + (int64_t)df.nx * j + df.plane * k;
 #pragma unroll
-  for (int c = 0; c < 3; c++) xf[c * df.N + n] = (T)((double)xf[c * df.N + n] + acc[c]);
+  for (int c = 0; c < NC; c++) xf[c * df.N + n] = (T)((double)xf[c * df.N + n] + acc[c]);
 }
 
-// Coarsest level: x = M b over the unknowns (planes >= 1), M the dense
-// inverse (row-major, n x n).  One block per row.
-template <typename T>
+// Coarsest level: x = M b over the unknowns (n / NC per component, planes 1
+// upwards), M the dense inverse (row-major, n x n).  One block per row.
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void mg_dense_kernel(Dims d, int n, const double* __restrict__ M,
                                                        const T* __restrict__ b, T* __restrict__ x,
                                                        const CgScalars* sc) {
   if (sc->done) return;
   const int row = blockIdx.x;
-  const int64_t nu = d.N - d.plane;  // unknowns per component
+  const int64_t nu = n / NC;  // unknowns per component
   auto vec = [&](int64_t u) { return (u / nu) * d.N + d.plane + u % nu; };
   double s = 0.0;
   for (int t = threadIdx.x; t < n; t += 256) s += M[(int64_t)row * n + t] * (double)b[vec(t)];
@@ -1275,6 +1296,68 @@ __global__ __launch_bounds__(256) void mg_dense_kernel(Dims d, int n, const doub
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
   __syncthreads();
   if (threadIdx.x == 0) x[vec(row)] = (T)(red[0] + red[1] + red[2] + red[3]);
+}
+
+// Poisson fine level (the potential grid, tiled like the CG kernels): out =
+// b - A x or out = x + omega D^-1 (b - A x) with the operator of every
+// stored plane counted (the electrode rows of the open top included); with
+// emask the output is zeroed on the electrode nodes (the preconditioner of
+// the reduced system), and with partials the tile's b . out goes to
+// partials[lid * pstride + poff].
+template <typename T>
+__global__ __launch_bounds__(kThreads) void mgp_fine_kernel(Dims d, TileMap tm, Coefs<T> cf,
+                                                            const double* __restrict__ dinv, int mode, double omega,
+                                                            const T* __restrict__ x, const T* __restrict__ b,
+                                                            T* __restrict__ out, const uint8_t* __restrict__ emask,
+                                                            const CgScalars* sc, double* partials, int pstride,
+                                                            int poff) {
+  if (sc->done) return;
+  constexpr int TY = kBY;
+  __shared__ T ring[3][1][TY + 2][kHX];
+  const T c6 = cf.eps_over_h2;
+  const TileCoord tc = tile_coord(d, tm);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  auto fetch = [&](int64_t m, int, T* raw) { raw[0] = x[m]; };
+  auto comb = [&](int, const T* raw, T* o) { o[0] = raw[0]; };
+  Stage<T, 1, Halo<TY>::NPT> st;
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store<TY>(ring, st, tc.k0 - 1, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store<TY>(ring, st, tc.k0, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  T cb = valid ? b[col + d.plane * tc.k0] : (T)0;
+  double acc = 0.0;
+  for (int k = tc.k0; k < tc.k1; k++) {
+    stage_store<TY>(ring, st, k + 1, comb);
+    if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
+    const T nb = (valid && k + 1 < tc.k1) ? b[col + d.plane * (k + 1)] : (T)0;
+    __syncthreads();
+    if (valid) {
+      const int sm = slot_of(k - 1), s0 = slot_of(k), sp = slot_of(k + 1);
+      const T pc = ring[s0][0][ly + 1][lx + 1];
+      const T sxy = ring[s0][0][ly + 1][lx] + ring[s0][0][ly + 1][lx + 2] + ring[s0][0][ly][lx + 1] +
+                    ring[s0][0][ly + 2][lx + 1];
+      const T pdn = ring[sm][0][ly + 1][lx + 1], pup = ring[sp][0][ly + 1][lx + 1];
+      T q;
+      if (!cf.open) {
+        q = c6 * (6 * pc - (sxy + pdn + pup));
+      } else {
+        const PlaneEps<T> e = plane_eps(d, cf, k);
+        q = e.xy * (4 * pc - sxy) + e.up * (pc - pup) + e.dn * (pc - pdn);
+      }
+      const T r = cb - q;
+      T o = mode == kMgResidual ? r : pc + (T)(omega * dinv[k]) * r;
+      if (emask != nullptr && k == d.nzf && emask[col] != 0) o = 0;
+      out[col + d.plane * k] = o;
+      acc += (double)cb * (double)o;
+    }
+    cb = nb;
+    __syncthreads();
+  }
+  if (partials) block_sum_to<kThreads>(acc, partials + (int64_t)tc.lid * pstride + poff);
 }
 
 // ---------------------------------------------------------------------------
@@ -1841,8 +1924,8 @@ hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, c
 
 template <typename T>
 hipError_t launch_poisson_cg_a(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* r, const T* p_old,
-                               T* p_new, T* x, const CgScalars* sc, double* partials, hipStream_t s) {
-  poisson_cg_a_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, r, p_old, p_new, x, sc, partials);
+                               T* p_new, T* x, const CgScalars* sc, double* partials, int unit_w, hipStream_t s) {
+  poisson_cg_a_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, r, p_old, p_new, x, sc, partials, unit_w);
   return hipGetLastError();
 }
 
@@ -1901,37 +1984,62 @@ hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb,
 }
 
 template <typename T>
-hipError_t launch_mg_level(const Dims& d, const double* tab, const double* dinv, int mode, double omega, const T* x,
-                           const T* b, T* out, const CgScalars* sc, hipStream_t s) {
-  mg_level_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, tab, dinv, mode, omega, x, b, out, sc);
+hipError_t launch_mg_level(const Dims& d, int nc, const double* tab, const double* dinv, int mode, double omega,
+                           const T* x, const T* b, T* out, const CgScalars* sc, int top_fixed, hipStream_t s) {
+  if (nc == 3)
+    mg_level_kernel<T, 3><<<node_grid(d), node_block(), 0, s>>>(d, tab, dinv, mode, omega, x, b, out, sc, top_fixed);
+  else
+    mg_level_kernel<T, 1><<<node_grid(d), node_block(), 0, s>>>(d, tab, dinv, mode, omega, x, b, out, sc, top_fixed);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_mg_scale(const Dims& d, const double* dinv, double omega, const T* b, T* x, const CgScalars* sc,
+hipError_t launch_mg_scale(const Dims& d, int nc, const double* dinv, double omega, const T* b, T* x,
+                           const CgScalars* sc, hipStream_t s) {
+  if (nc == 3) mg_scale_kernel<T, 3><<<node_grid(d), node_block(), 0, s>>>(d, dinv, omega, b, x, sc);
+  else mg_scale_kernel<T, 1><<<node_grid(d), node_block(), 0, s>>>(d, dinv, omega, b, x, sc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap,
+                              const int* zfine, const T* rf, T* bc, const CgScalars* sc, int zoff, int fnz,
+                              int ctop_fixed, hipStream_t s) {
+  if (nc == 3)
+    mg_restrict_kernel<T, 3><<<node_grid(dc), node_block(), 0, s>>>(df, dc, cx, cy, zmap, zfine, rf, bc, sc, zoff,
+                                                                     fnz, ctop_fixed);
+  else
+    mg_restrict_kernel<T, 1><<<node_grid(dc), node_block(), 0, s>>>(df, dc, cx, cy, zmap, zfine, rf, bc, sc, zoff,
+                                                                     fnz, ctop_fixed);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_prolong(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap, const T* xc,
+                             T* xf, const CgScalars* sc, int zoff, int ftop_fixed, int ctop_fixed, hipStream_t s) {
+  if (nc == 3)
+    mg_prolong_kernel<T, 3><<<node_grid(df), node_block(), 0, s>>>(df, dc, cx, cy, zmap, xc, xf, sc, zoff, ftop_fixed,
+                                                                    ctop_fixed);
+  else
+    mg_prolong_kernel<T, 1><<<node_grid(df), node_block(), 0, s>>>(df, dc, cx, cy, zmap, xc, xf, sc, zoff, ftop_fixed,
+                                                                    ctop_fixed);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mg_dense(const Dims& d, int nc, int n, const double* M, const T* b, T* x, const CgScalars* sc,
                            hipStream_t s) {
-  mg_scale_kernel<T><<<node_grid(d), node_block(), 0, s>>>(d, dinv, omega, b, x, sc);
+  if (nc == 3) mg_dense_kernel<T, 3><<<n, 256, 0, s>>>(d, n, M, b, x, sc);
+  else mg_dense_kernel<T, 1><<<n, 256, 0, s>>>(d, n, M, b, x, sc);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int cx, int cy, const MgZ* zmap, const int* zfine,
-                              const T* rf, T* bc, const CgScalars* sc, hipStream_t s) {
-  mg_restrict_kernel<T><<<node_grid(dc), node_block(), 0, s>>>(df, dc, cx, cy, zmap, zfine, rf, bc, sc);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_mg_prolong(const Dims& df, const Dims& dc, int cx, int cy, const MgZ* zmap, const T* xc, T* xf,
-                             const CgScalars* sc, hipStream_t s) {
-  mg_prolong_kernel<T><<<node_grid(df), node_block(), 0, s>>>(df, dc, cx, cy, zmap, xc, xf, sc);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_mg_dense(const Dims& d, int n, const double* M, const T* b, T* x, const CgScalars* sc,
-                           hipStream_t s) {
-  mg_dense_kernel<T><<<n, 256, 0, s>>>(d, n, M, b, x, sc);
+hipError_t launch_mgp_fine(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const double* dinv, int mode,
+                           double omega, const T* x, const T* b, T* out, const uint8_t* emask, const CgScalars* sc,
+                           double* partials, int pstride, int poff, hipStream_t s) {
+  mgp_fine_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, dinv, mode, omega, x, b, out, emask, sc, partials,
+                                                         pstride, poff);
   return hipGetLastError();
 }
 
@@ -2006,7 +2114,7 @@ PF_INSTANTIATE_ADJ(float)
   template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                                               \
   template hipError_t launch_cg_finish<T>(T*, const T*, int64_t, const CgScalars*, hipStream_t);                 \
   template hipError_t launch_poisson_cg_a<T>(const Dims&, const TileMap&, const Coefs<T>&, const T*, const T*,   \
-                                             T*, T*, const CgScalars*, double*, hipStream_t);                    \
+                                             T*, T*, const CgScalars*, double*, int, hipStream_t);               \
   template hipError_t launch_poisson_cg_b<T>(const Dims&, const TileMap&, const Coefs<T>&, const T*, T*,         \
                                              const uint8_t*, const CgScalars*, double*, hipStream_t);            \
   template hipError_t launch_fem_cg_a<T>(const Dims&, const TileMap&, const FemTables*, bool, const T*, const T*, \
@@ -2023,16 +2131,19 @@ PF_INSTANTIATE(float)
   template hipError_t launch_mg_fine<T>(const Dims&, const TileMap&, const FemTables*, bool, const double*, int,  \
                                         double, const T*, const T*, T*, const CgScalars*, double*, int, int,       \
                                         hipStream_t);                                                             \
-  template hipError_t launch_mg_level<T>(const Dims&, const double*, const double*, int, double, const T*,        \
-                                         const T*, T*, const CgScalars*, hipStream_t);                            \
-  template hipError_t launch_mg_scale<T>(const Dims&, const double*, double, const T*, T*, const CgScalars*,      \
+  template hipError_t launch_mg_level<T>(const Dims&, int, const double*, const double*, int, double, const T*,   \
+                                         const T*, T*, const CgScalars*, int, hipStream_t);                       \
+  template hipError_t launch_mg_scale<T>(const Dims&, int, const double*, double, const T*, T*, const CgScalars*, \
                                          hipStream_t);                                                            \
-  template hipError_t launch_mg_restrict<T>(const Dims&, const Dims&, int, int, const MgZ*, const int*, const T*, \
-                                            T*, const CgScalars*, hipStream_t);                                   \
-  template hipError_t launch_mg_prolong<T>(const Dims&, const Dims&, int, int, const MgZ*, const T*, T*,          \
-                                           const CgScalars*, hipStream_t);                                        \
-  template hipError_t launch_mg_dense<T>(const Dims&, int, const double*, const T*, T*, const CgScalars*,         \
-                                         hipStream_t);
+  template hipError_t launch_mg_restrict<T>(const Dims&, const Dims&, int, int, int, const MgZ*, const int*,      \
+                                            const T*, T*, const CgScalars*, int, int, int, hipStream_t);          \
+  template hipError_t launch_mg_prolong<T>(const Dims&, const Dims&, int, int, int, const MgZ*, const T*, T*,     \
+                                           const CgScalars*, int, int, int, hipStream_t);                         \
+  template hipError_t launch_mg_dense<T>(const Dims&, int, int, const double*, const T*, T*, const CgScalars*,    \
+                                         hipStream_t);                                                            \
+  template hipError_t launch_mgp_fine<T>(const Dims&, const TileMap&, const Coefs<T>&, const double*, int,        \
+                                         double, const T*, const T*, T*, const uint8_t*, const CgScalars*,        \
+                                         double*, int, int, hipStream_t);
 
 PF_INSTANTIATE_MG(double)
 PF_INSTANTIATE_MG(float)

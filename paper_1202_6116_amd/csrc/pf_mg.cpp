@@ -25,47 +25,53 @@ namespace {
 inline int tap_index(int dx, int dy, int dz) { return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1); }
 inline int wrap_host(int i, int n) { return ((i % n) + n) % n; }
 
-// A level operator on a periodic probe domain (wx x wy x nz, component-major).
+// A level operator on a periodic probe domain (wx x wy x nz, nc components,
+// component-major) from per-plane stencils T[k][c][e][o].  Plane 0, and the
+// top plane when it is fixed, hold no unknowns: their rows and columns are
+// zero.
 struct ProbeOp {
-  int wx, wy, nz;
-  const FemTables* fine;               // level 0 (FEM tables), or
-  const std::vector<double>* planes;   // level >= 1 (nz x 3 x 3 x 27)
+  int wx, wy, nz, nc;
+  bool top_fixed;
+  const std::vector<double>* planes;
   int64_t plane() const { return (int64_t)wx * wy; }
   int64_t n() const { return plane() * nz; }
+  bool active(int k) const { return k >= 1 && k < nz - (top_fixed ? 1 : 0); }
   double coef(int k, int c, int e, int o) const {
-    if (fine) return fine->K[k == nz - 1 ? 1 : 0][c][e][o];
-    return (*planes)[(((size_t)k * 3 + c) * 3 + e) * 27 + o];
+    return (*planes)[(((size_t)k * nc + c) * nc + e) * 27 + o];
   }
-  // y = A x; plane 0 (clamp) rows and columns are zero.
   void apply(const std::vector<double>& x, std::vector<double>& y) const {
     const int64_t N = n();
-    y.assign(3 * N, 0.0);
-    for (int k = 1; k < nz; k++)
+    y.assign((size_t)nc * N, 0.0);
+    for (int k = 0; k < nz; k++) {
+      if (!active(k)) continue;
       for (int j = 0; j < wy; j++)
         for (int i = 0; i < wx; i++) {
           const int64_t r = i + (int64_t)wx * (j + (int64_t)wy * k);
           for (int dz = -1; dz <= 1; dz++) {
             const int kk = k + dz;
-            if (kk < 1 || kk >= nz) continue;
+            if (kk < 0 || kk >= nz || !active(kk)) continue;
             for (int dy = -1; dy <= 1; dy++)
               for (int dx = -1; dx <= 1; dx++) {
                 const int o = tap_index(dx, dy, dz);
                 const int64_t m = wrap_host(i + dx, wx) + (int64_t)wx * (wrap_host(j + dy, wy) + (int64_t)wy * kk);
-                for (int c = 0; c < 3; c++)
-                  for (int e = 0; e < 3; e++) y[c * N + r] += coef(k, c, e, o) * x[e * N + m];
+                for (int c = 0; c < nc; c++)
+                  for (int e = 0; e < nc; e++) y[c * N + r] += coef(k, c, e, o) * x[e * N + m];
               }
           }
         }
+    }
   }
   double diag(int k, int c) const { return coef(k, c, c, 13); }
 };
 
-// Prolongation between a fine domain (fx, fy, fz) and a coarse one.
+// Prolongation between a fine domain (fx, fy, fz) and a coarse one; fixed
+// planes (0, and the tops when fixed) carry zero.
 struct ProbeTransfer {
-  int fx, fy, fz, cx_, cy_, cz;
-  bool cx, cy;
+  int fx, fy, fz, cx_, cy_, cz, nc;
+  bool cx, cy, top_fixed;
   const std::vector<MgZ>* zmap;  // per fine plane
-  // fine (i, j, k) <- sum of weights times coarse values
+  bool fine_active(int k) const { return k >= 1 && k < fz - (top_fixed ? 1 : 0); }
+  bool coarse_active(int k) const { return k >= 1 && k < cz - (top_fixed ? 1 : 0); }
   template <typename F>
   void for_parents(int i, int j, int k, F f) const {
     int xi[2], yi[2];
@@ -93,36 +99,40 @@ struct ProbeTransfer {
     const int zi[2] = {z.lo, z.hi};
     const double zw[2] = {z.wlo, z.whi};
     for (int a = 0; a < 2; a++) {
-      if (zw[a] == 0.0 || zi[a] == 0) continue;  // the clamp plane carries zero
+      if (zw[a] == 0.0 || !coarse_active(zi[a])) continue;
       for (int b = 0; b < nyp; b++)
         for (int q = 0; q < nxp; q++) f(xi[q], yi[b], zi[a], zw[a] * yw[b] * xw[q]);
     }
   }
   void prolong(const std::vector<double>& xc, std::vector<double>& xf) const {
     const int64_t Nf = (int64_t)fx * fy * fz, Nc = (int64_t)cx_ * cy_ * cz;
-    xf.assign(3 * Nf, 0.0);
-    for (int k = 1; k < fz; k++)
+    xf.assign((size_t)nc * Nf, 0.0);
+    for (int k = 0; k < fz; k++) {
+      if (!fine_active(k)) continue;
       for (int j = 0; j < fy; j++)
         for (int i = 0; i < fx; i++) {
           const int64_t r = i + (int64_t)fx * (j + (int64_t)fy * k);
           for_parents(i, j, k, [&](int I, int J, int K, double w) {
             const int64_t m = I + (int64_t)cx_ * (J + (int64_t)cy_ * K);
-            for (int c = 0; c < 3; c++) xf[c * Nf + r] += w * xc[c * Nc + m];
+            for (int c = 0; c < nc; c++) xf[c * Nf + r] += w * xc[c * Nc + m];
           });
         }
+    }
   }
   void restrict_(const std::vector<double>& yf, std::vector<double>& yc) const {
     const int64_t Nf = (int64_t)fx * fy * fz, Nc = (int64_t)cx_ * cy_ * cz;
-    yc.assign(3 * Nc, 0.0);
-    for (int k = 1; k < fz; k++)
+    yc.assign((size_t)nc * Nc, 0.0);
+    for (int k = 0; k < fz; k++) {
+      if (!fine_active(k)) continue;
       for (int j = 0; j < fy; j++)
         for (int i = 0; i < fx; i++) {
           const int64_t r = i + (int64_t)fx * (j + (int64_t)fy * k);
           for_parents(i, j, k, [&](int I, int J, int K, double w) {
             const int64_t m = I + (int64_t)cx_ * (J + (int64_t)cy_ * K);
-            for (int c = 0; c < 3; c++) yc[c * Nc + m] += w * yf[c * Nf + r];
+            for (int c = 0; c < nc; c++) yc[c * Nc + m] += w * yf[c * Nf + r];
           });
         }
+    }
   }
 };
 
@@ -156,29 +166,30 @@ std::vector<MgZ> zmap_for(int nz, const std::vector<int>& zc) {
 }
 
 // Largest eigenvalue of D^-1 A on an 8 x 8 periodic probe (power iteration).
-double jacobi_lambda_max(int nz, const FemTables* fine, const std::vector<double>* planes) {
-  ProbeOp op{8, 8, nz, fine, planes};
+double jacobi_lambda_max(int nz, int nc, bool top_fixed, const std::vector<double>* planes) {
+  ProbeOp op{8, 8, nz, nc, top_fixed, planes};
   const int64_t N = op.n();
-  std::vector<double> x(3 * N), y;
+  std::vector<double> x((size_t)nc * N), y;
   uint32_t s = 12345u;
-  for (int64_t t = 0; t < 3 * N; t++) {
+  for (int64_t t = 0; t < nc * N; t++) {
     s = s * 1664525u + 1013904223u;
-    x[t] = (t % N) < op.plane() ? 0.0 : (double)(s >> 8) / (double)(1u << 24) - 0.5;
+    x[t] = op.active((int)((t % N) / op.plane())) ? (double)(s >> 8) / (double)(1u << 24) - 0.5 : 0.0;
   }
   double lam = 0.0;
   for (int it = 0; it < 60; it++) {
     op.apply(x, y);
     double nrm = 0.0;
-    for (int c = 0; c < 3; c++)
-      for (int64_t m = op.plane(); m < N; m++) {
+    for (int c = 0; c < nc; c++)
+      for (int64_t m = 0; m < N; m++) {
         const int k = (int)(m / op.plane());
+        if (!op.active(k)) continue;
         y[c * N + m] /= op.diag(k, c);
         nrm += y[c * N + m] * y[c * N + m];
       }
     nrm = std::sqrt(nrm);
     if (!(nrm > 0)) break;
     lam = nrm;
-    for (int64_t t = 0; t < 3 * N; t++) x[t] = y[t] / nrm;
+    for (int64_t t = 0; t < nc * N; t++) x[t] = y[t] / nrm;
   }
   return lam;
 }
@@ -216,24 +227,23 @@ bool spd_inverse(std::vector<double>& A, int n) {
   return true;
 }
 
-}  // namespace
-
-std::vector<MgLevel> mg_plan(const pf_config& cfg);
-MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb);
+int64_t unknowns(const MgLevel& l, int nc, bool top_fixed) {
+  return (int64_t)nc * l.nx * l.ny * (l.nz - 1 - (top_fixed ? 1 : 0));
+}
 
 // Grid levels: halve x and y while even and at least 8 wide, keep every
 // other plane and the top in z, until the coarsest level has at most
 // kMgDenseMax unknowns or nothing can be coarsened.
-std::vector<MgLevel> mg_plan(const pf_config& cfg) {
+std::vector<MgLevel> plan_levels(int nx, int ny, int nz, int nc, bool top_fixed) {
   std::vector<MgLevel> lv;
   MgLevel l0;
-  l0.nx = cfg.nx, l0.ny = cfg.ny, l0.nz = cfg.nz;
+  l0.nx = nx, l0.ny = ny, l0.nz = nz;
   l0.cx = l0.cy = false;
   l0.omega = 0.0;
   lv.push_back(l0);
   for (;;) {
     const MgLevel f = lv.back();
-    if (3LL * f.nx * f.ny * (f.nz - 1) <= kMgDenseMax) break;
+    if (unknowns(f, nc, top_fixed) <= kMgDenseMax) break;
     const bool cx = f.nx % 2 == 0 && f.nx >= 8, cy = f.ny % 2 == 0 && f.ny >= 8;
     const int nzc = (int)coarse_planes(f.nz).size();
     if (!cx && !cy && nzc == f.nz) break;
@@ -249,13 +259,17 @@ std::vector<MgLevel> mg_plan(const pf_config& cfg) {
   return lv;
 }
 
-MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb) {
+// The hierarchy for a level-0 operator given as per-plane stencils.
+MgHierarchy build_generic(int nx, int ny, int nz, int nc, bool top_fixed, std::vector<double> level0) {
   MgHierarchy h;
-  const std::vector<MgLevel> plan = mg_plan(cfg);
+  h.nc = nc;
+  h.top_fixed = top_fixed;
+  const std::vector<MgLevel> plan = plan_levels(nx, ny, nz, nc, top_fixed);
   h.levels.push_back(plan[0]);
-  h.tables.emplace_back();
+  h.tables.push_back(std::move(level0));
   h.zmaps.emplace_back();
   h.zfine.emplace_back();
+  const size_t blk = (size_t)nc * nc * 27;
   for (size_t l = 1; l < plan.size(); l++) {
     const MgLevel& f = h.levels.back();
     const MgLevel& c = plan[l];
@@ -267,13 +281,13 @@ MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb) {
     const int wcx = cx ? 4 : 3, wcy = cy ? 4 : 3;
     const int wfx = cx ? 8 : 3, wfy = cy ? 8 : 3;
     const size_t lf = h.levels.size() - 1;
-    ProbeOp fine_op{wfx, wfy, f.nz, lf == 0 ? &tb : nullptr, lf == 0 ? nullptr : &h.tables[lf]};
-    ProbeTransfer tr{wfx, wfy, f.nz, wcx, wcy, c.nz, cx, cy, &zm};
-    std::vector<double> T((size_t)c.nz * 3 * 3 * 27, 0.0);
+    ProbeOp fine_op{wfx, wfy, f.nz, nc, top_fixed, &h.tables[lf]};
+    ProbeTransfer tr{wfx, wfy, f.nz, wcx, wcy, c.nz, nc, cx, cy, top_fixed, &zm};
+    std::vector<double> T((size_t)c.nz * blk, 0.0);
     const int64_t Nc = (int64_t)wcx * wcy * c.nz;
-    std::vector<double> u(3 * Nc), v, w, y;
-    for (int K = 1; K < c.nz; K++)
-      for (int e = 0; e < 3; e++) {
+    std::vector<double> u((size_t)nc * Nc), v, w, y;
+    for (int K = 1; K < c.nz - (top_fixed ? 1 : 0); K++)
+      for (int e = 0; e < nc; e++) {
         std::fill(u.begin(), u.end(), 0.0);
         u[e * Nc + (int64_t)wcx * wcy * K] = 1.0;
         tr.prolong(u, v);
@@ -285,8 +299,8 @@ MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb) {
           for (int dy = -1; dy <= 1; dy++)
             for (int dx = -1; dx <= 1; dx++) {
               const int64_t m = wrap_host(-dx, wcx) + (int64_t)wcx * (wrap_host(-dy, wcy) + (int64_t)wcy * Kr);
-              for (int cc = 0; cc < 3; cc++)
-                T[(((size_t)Kr * 3 + cc) * 3 + e) * 27 + tap_index(dx, dy, K - Kr)] = y[cc * Nc + m];
+              for (int cc = 0; cc < nc; cc++)
+                T[(((size_t)Kr * nc + cc) * nc + e) * 27 + tap_index(dx, dy, K - Kr)] = y[cc * Nc + m];
             }
       }
     h.levels.push_back(c);
@@ -297,34 +311,33 @@ MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb) {
   // Jacobi weights and smoother damping per level
   for (size_t l = 0; l < h.levels.size(); l++) {
     MgLevel& L = h.levels[l];
-    L.dinv.assign((size_t)L.nz * 3, 0.0);
-    for (int k = 1; k < L.nz; k++)
-      for (int c = 0; c < 3; c++) {
-        const double d = l == 0 ? tb.K[k == L.nz - 1 ? 1 : 0][c][c][13] : h.tables[l][(((size_t)k * 3 + c) * 3 + c) * 27 + 13];
-        L.dinv[(size_t)k * 3 + c] = 1.0 / d;
-      }
-    const double lam = jacobi_lambda_max(L.nz, l == 0 ? &tb : nullptr, l == 0 ? nullptr : &h.tables[l]);
+    ProbeOp op{8, 8, L.nz, nc, top_fixed, &h.tables[l]};
+    L.dinv.assign((size_t)L.nz * nc, 0.0);
+    for (int k = 0; k < L.nz; k++)
+      if (op.active(k))
+        for (int c = 0; c < nc; c++) L.dinv[(size_t)k * nc + c] = 1.0 / op.diag(k, c);
+    const double lam = jacobi_lambda_max(L.nz, nc, top_fixed, &h.tables[l]);
     L.omega = 4.0 / (3.0 * 1.05 * lam);
   }
-  // Coarsest level: dense inverse over its unknowns (planes >= 1), or damped
-  // Jacobi sweeps when it is too large for that.
+  // Coarsest level: dense inverse over its unknowns, or damped Jacobi sweeps
+  // when it is too large for that.
   const MgLevel& C = h.levels.back();
-  const int64_t n = 3LL * C.nx * C.ny * (C.nz - 1);
+  const int64_t n = unknowns(C, nc, top_fixed);
   h.dense_n = 0;
   h.coarse_sweeps = 0;
   if (n <= kMgDenseMax) {
-    const size_t lc = h.levels.size() - 1;
-    ProbeOp op{C.nx, C.ny, C.nz, lc == 0 ? &tb : nullptr, lc == 0 ? nullptr : &h.tables[lc]};
+    ProbeOp op{C.nx, C.ny, C.nz, nc, top_fixed, &h.tables.back()};
     const int64_t N = op.n(), pl = op.plane();
-    std::vector<double> A((size_t)n * n, 0.0), x(3 * N, 0.0), y;
-    auto idx = [&](int c, int64_t m) { return (int64_t)c * (N - pl) + (m - pl); };
-    for (int e = 0; e < 3; e++)
-      for (int64_t m = pl; m < N; m++) {
+    const int64_t nu = n / nc;  // unknowns per component: planes 1 .. active top
+    std::vector<double> A((size_t)n * n, 0.0), x((size_t)nc * N, 0.0), y;
+    auto idx = [&](int c, int64_t m) { return (int64_t)c * nu + (m - pl); };
+    for (int e = 0; e < nc; e++)
+      for (int64_t m = pl; m < pl + nu; m++) {
         std::fill(x.begin(), x.end(), 0.0);
         x[e * N + m] = 1.0;
         op.apply(x, y);
-        for (int c = 0; c < 3; c++)
-          for (int64_t r = pl; r < N; r++) A[(size_t)idx(c, r) * n + idx(e, m)] = y[c * N + r];
+        for (int c = 0; c < nc; c++)
+          for (int64_t r = pl; r < pl + nu; r++) A[(size_t)idx(c, r) * n + idx(e, m)] = y[c * N + r];
       }
     if (spd_inverse(A, (int)n)) {
       h.dense_n = (int)n;
@@ -333,6 +346,64 @@ MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb) {
   }
   if (h.dense_n == 0) h.coarse_sweeps = 2 * std::max(C.nz, 8);
   return h;
+}
+
+// Poisson: the potential grid extended by the bottom ghost plane (plane 0,
+// fixed) and, with the metal top, the top ghost plane (fixed); stored plane
+// k is extended plane k + 1.
+int phi_ext_planes(const pf_config& c) {
+  const bool open = c.top_bc == PF_TOP_OPEN;
+  const int nzp = c.nz + (open ? c.n_air : 0);
+  return nzp + 1 + (open ? 0 : 1);
+}
+
+}  // namespace
+
+std::vector<MgLevel> mg_plan(const pf_config& cfg);
+std::vector<MgLevel> mg_plan_phi(const pf_config& cfg);
+MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb);
+MgHierarchy build_mg_phi(const pf_config& cfg);
+
+std::vector<MgLevel> mg_plan(const pf_config& cfg) { return plan_levels(cfg.nx, cfg.ny, cfg.nz, 3, false); }
+
+std::vector<MgLevel> mg_plan_phi(const pf_config& cfg) {
+  return plan_levels(cfg.nx, cfg.ny, phi_ext_planes(cfg), 1, cfg.top_bc != PF_TOP_OPEN);
+}
+
+// FEM: level 0 is the assembled stiffness (interior rows, the top row; plane
+// 0 clamped).
+MgHierarchy build_mg(const pf_config& cfg, const FemTables& tb) {
+  std::vector<double> T0((size_t)cfg.nz * 243, 0.0);
+  for (int k = 1; k < cfg.nz; k++)
+    for (int c = 0; c < 3; c++)
+      for (int e = 0; e < 3; e++)
+        for (int o = 0; o < 27; o++)
+          T0[(((size_t)k * 3 + c) * 3 + e) * 27 + o] = tb.K[k == cfg.nz - 1 ? 1 : 0][c][e][o];
+  return build_generic(cfg.nx, cfg.ny, cfg.nz, 3, false, std::move(T0));
+}
+
+// Poisson: level 0 is the 7-point operator -div(eps grad) / h^2 of the
+// potential grid on the extended planes, with the electrode nodes of the
+// open top counted as unknowns (the preconditioner's output is zeroed there).
+MgHierarchy build_mg_phi(const pf_config& cfg) {
+  const bool open = cfg.top_bc == PF_TOP_OPEN;
+  const int nze = phi_ext_planes(cfg);
+  const int nzf = cfg.nz, nzp = nze - 1 - (open ? 0 : 1);
+  const double ih2 = 1.0 / (cfg.h * cfg.h);
+  const double ef = cfg.eps_b * ih2, ea = (open ? cfg.eps_air : cfg.eps_b) * ih2;
+  const double ei = (open && cfg.eps_air != cfg.eps_b) ? 2 * cfg.eps_b * cfg.eps_air / (cfg.eps_b + cfg.eps_air) * ih2 : ef;
+  std::vector<double> T0((size_t)nze * 27, 0.0);
+  for (int k = 0; k < nzp; k++) {  // stored plane k, extended k + 1
+    const double xy = k < nzf ? ef : ea;
+    const double dn = k < nzf ? ef : (k == nzf ? ei : ea);
+    const double up = (k + 1 >= nzp) ? (open ? 0.0 : xy) : (k + 1 < nzf ? ef : (k + 1 == nzf ? ei : ea));
+    double* t = &T0[(size_t)(k + 1) * 27];
+    t[tap_index(0, 0, 0)] = 4 * xy + up + dn;
+    t[tap_index(1, 0, 0)] = t[tap_index(-1, 0, 0)] = t[tap_index(0, 1, 0)] = t[tap_index(0, -1, 0)] = -xy;
+    t[tap_index(0, 0, 1)] = -up;
+    t[tap_index(0, 0, -1)] = -dn;
+  }
+  return build_generic(cfg.nx, cfg.ny, nze, 1, !open, std::move(T0));
 }
 
 }  // namespace pf

@@ -120,9 +120,9 @@ def lib() -> ctypes.CDLL:
             "pf_timing": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)]),
             "pf_fem_table_size": (sz, []),
             "pf_fem_tables": (ctypes.c_int, [cfgp, dp, sz]),
-            "pf_mg_levels": (ctypes.c_int, [cfgp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp,
-                                            ctypes.c_int32]),
-            "pf_mg_table": (ctypes.c_int, [cfgp, ctypes.c_int32, dp, sz]),
+            "pf_mg_levels": (ctypes.c_int, [cfgp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32), dp, ctypes.c_int32]),
+            "pf_mg_table": (ctypes.c_int, [cfgp, ctypes.c_int32, ctypes.c_int32, dp, sz]),
             "pf_status_str": (ctypes.c_char_p, [ctypes.c_int]),
             "pf_last_error": (ctypes.c_char_p, [vp]),
             "pf_destroy": (None, [vp]),
@@ -200,29 +200,34 @@ def pf_fem_tables(cfg: PFConfig):
     return res
 
 
-def pf_mg_levels(cfg: PFConfig):
-    """The multigrid levels of the FEM operator: list of ((nx, ny, nz), omega)."""
+def pf_mg_levels(cfg: PFConfig, field: str = "u"):
+    """The multigrid levels of the FEM ("u") or Poisson ("phi") operator:
+    list of ((nx, ny, nz), omega)."""
     import numpy as np
     c, keep = make_config(cfg)
     n = ctypes.c_int32()
     dims = (ctypes.c_int32 * 48)()
     om = np.zeros(16)
-    st = lib().pf_mg_levels(ctypes.byref(c), ctypes.byref(n), dims, om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 16)
+    st = lib().pf_mg_levels(ctypes.byref(c), 1 if field == "u" else 0, ctypes.byref(n), dims,
+                            om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 16)
     if st != PF_OK:
         raise PFError(st, f"pf_mg_levels: {status_str(st)}")
     return [((dims[3 * l], dims[3 * l + 1], dims[3 * l + 2]), float(om[l])) for l in range(n.value)]
 
 
-def pf_mg_table(cfg: PFConfig, level: int):
-    """Galerkin stencils of a multigrid level >= 1, float64 (nz, 3, 3, 27)."""
+def pf_mg_table(cfg: PFConfig, level: int, field: str = "u"):
+    """Stencils of a multigrid level (0: the operator, >= 1: Galerkin), float64
+    (nz, nc, nc, 27) with nc = 3 for "u" and 1 for "phi"."""
     import numpy as np
     c, keep = make_config(cfg)
-    nz = pf_mg_levels(cfg)[level][0][2]
-    out = np.zeros(nz * 243)
-    st = lib().pf_mg_table(ctypes.byref(c), level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size)
+    nz = pf_mg_levels(cfg, field)[level][0][2]
+    nc = 3 if field == "u" else 1
+    out = np.zeros(nz * nc * nc * 27)
+    st = lib().pf_mg_table(ctypes.byref(c), 1 if field == "u" else 0, level,
+                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size)
     if st != PF_OK:
         raise PFError(st, f"pf_mg_table: {status_str(st)}")
-    return out.reshape(nz, 3, 3, 27)
+    return out.reshape(nz, nc, nc, 27)
 
 
 def _ptr(t: Optional[torch.Tensor]):

@@ -1,6 +1,6 @@
-"""GPU FEM solves preconditioned by the multigrid V-cycle against the FP64
-oracle (Jacobi CG), through the C ABI: the solution is the same to the
-solver tolerance, with far fewer iterations."""
+"""GPU Poisson and FEM solves preconditioned by the multigrid V-cycle
+against the FP64 oracle (Jacobi CG), through the C ABI: the solution is the
+same to the solver tolerance, with far fewer iterations."""
 import numpy as np
 import pytest
 import torch
@@ -56,6 +56,34 @@ def test_mg_fem_solve_matches_oracle(pf, oracle_mod, shape):
     assert stats["iters"] < it / 3, (stats["iters"], it)
     assert rel(host(u), ref) < TOL
     assert np.all(host(u)[:, 0] == 0)
+
+
+@pytest.mark.parametrize("shape,top", [((64, 16, 8), "metal"), ((70, 13, 6), "metal"), ((32, 32, 17), "metal"),
+                                       ((64, 16, 8), "open"), ((70, 13, 6), "open")])
+def test_mg_poisson_solve_matches_oracle(pf, oracle_mod, shape, top):
+    nx, ny, nz = shape
+    cfg = mg_cfg(nx=nx, ny=ny, nz=nz, top=top, n_air=4, eps_b=20.0, eps_air=1.0)
+    levels = pf.pf_mg_levels(cfg, field="phi")
+    print(f"case: mg poisson solve {shape} {top} levels {[d for d, _ in levels]}", flush=True)
+    assert len(levels) >= 2
+    P = domain_polarisation(cfg, 75, block=4)
+    ref, it, rr, st = oracle_mod.Oracle(cfg).solve_phi(P)
+    phi, stats = pf.Context(cfg).solve_phi(dev(P))
+    assert stats["status"] == 0 and stats["relres"] <= 1e-13
+    assert stats["iters"] < it / 3, (stats["iters"], it)
+    assert rel(host(phi), ref) < TOL
+
+
+@pytest.mark.parametrize("top", ["metal", "open"])
+def test_mg_energy_matches_oracle(pf, oracle_mod, top):
+    cfg = mg_cfg(top=top, n_air=3, eps_b=20.0)
+    print(f"case: mg energy {top}", flush=True)
+    P = domain_polarisation(cfg, 76, block=4, std=0.1)
+    ref = oracle_mod.Oracle(cfg).energy(P, tol=1e-13)
+    ctx = pf.Context(cfg)
+    ctx.set_state(dev(P))
+    e = np.array(ctx.energy())
+    assert np.abs(e - ref).max() <= 1e-10 * np.abs(ref).max(), (e, ref)
 
 
 @pytest.mark.parametrize("integrator,precision", [("pc", "fp64"), ("euler", "fp64"), ("pc", "fp32_refine")])
@@ -118,15 +146,22 @@ def test_mg_adjoint_matches_oracle(pf, oracle_mod):
     assert rel(host(P0t.grad), dP_ref) < 1e-7
 
 
-def test_mg_lateral_256_full_size(pf, oracle_mod):
-    """The 256x256x64 film with the multigrid preconditioner: the FEM
-    solution satisfies the oracle's residual test, in a few iterations."""
-    w = workloads()["lateral_256x256x64"]
+@pytest.mark.parametrize("name", ["lateral_256x256x64", "lateral_open_256x256x64"])
+def test_mg_lateral_256_full_size(pf, oracle_mod, name):
+    """The 256x256x64 film with the multigrid preconditioner: the Poisson and
+    FEM solutions satisfy the oracle's residual tests, in a few iterations."""
+    w = workloads()[name]
     cfg = w.cfg.replace(precond="mg")
-    print("case: mg lateral_256x256x64", flush=True)
+    print(f"case: mg {name}", flush=True)
     o = oracle_mod.Oracle(cfg)
     P0 = initial_polarisation(w)
-    u, st = pf.Context(cfg).solve_u(dev(P0))
+    ctx = pf.Context(cfg)
+    phi, sp_ = ctx.solve_phi(dev(P0))
+    assert sp_["status"] == 0 and sp_["iters"] < 60, sp_
+    b = o.poisson_rhs(P0)
+    r = b - o.poisson_apply(host(phi))
+    assert np.linalg.norm(r) <= 1.05 * cfg.tol_phi * np.linalg.norm(b)
+    u, st = ctx.solve_u(dev(P0))
     assert st["status"] == 0 and st["iters"] < 40, st
     f = o.fem_rhs(P0)
     r = f - o.fem_apply(host(u))

@@ -109,5 +109,75 @@ def test_level1_galerkin_stencils(shape, rotation):
 
 def test_hierarchy_of_the_benchmark_film():
     cfg = PFConfig(nx=256, ny=256, nz=64)
+    assert [d for d, _ in pf.pf_mg_levels(cfg, "phi")] == [(256, 256, 66), (128, 128, 34), (64, 64, 18), (32, 32, 10),
+                                                           (16, 16, 6), (8, 8, 4)]
     dims = [d for d, _ in pf.pf_mg_levels(cfg)]
     assert dims == [(256, 256, 64), (128, 128, 33), (64, 64, 17), (32, 32, 9), (16, 16, 5), (8, 8, 3)]
+
+
+def oracle_poisson_matrix(oracle_mod, cfg):
+    o = oracle_mod.Oracle(cfg)
+    M = cfg.nx * cfg.ny * cfg.phi_planes
+    A = np.zeros((M, M))
+    for t in range(M):
+        e = np.zeros(M)
+        e[t] = 1
+        A[:, t] = o.poisson_apply(e.reshape(cfg.phi_shape)).ravel()
+    return A
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(top="open", n_air=3, eps_b=7.0, eps_air=1.5), dict(h=0.8, eps_b=2.0)])
+def test_poisson_levels_match_oracle_and_galerkin(oracle_mod, kw):
+    """Level 0 of the Poisson hierarchy is the oracle's operator (stored plane
+    k is extended plane k + 1; the ghost planes are fixed), and level 1 is
+    P^T A P on the extended grid."""
+    cfg = PFConfig(nx=16, ny=12, nz=7, **kw)
+    A = oracle_poisson_matrix(oracle_mod, cfg)
+    levels = pf.pf_mg_levels(cfg, "phi")
+    open_top = cfg.top == "open"
+    nze = cfg.phi_planes + 1 + (0 if open_top else 1)
+    assert levels[0][0] == (16, 12, nze)
+    T0 = pf.pf_mg_table(cfg, 0, "phi")[:, 0, 0, :]
+    nx, ny, K = cfg.nx, cfg.ny, cfg.phi_planes
+    for k in range(K):
+        for (j, i) in ((0, 0), (5, 7), (11, 15)):
+            n = i + nx * (j + ny * k)
+            s = np.zeros(27)
+            for o in range(27):
+                dx, dy, dz = tap(o)
+                if not 0 <= k + dz < K:
+                    continue
+                s[o] = A[n, (i + dx) % nx + nx * ((j + dy) % ny + ny * (k + dz))]
+            ref = T0[k + 1].copy()
+            if k == 0:  # the coupling to the bottom ghost plane is not a matrix entry
+                ref[[o for o in range(27) if tap(o)[2] == -1]] = 0
+            if k == K - 1:
+                ref[[o for o in range(27) if tap(o)[2] == 1]] = 0
+            np.testing.assert_allclose(s, ref, rtol=0, atol=1e-13)
+    assert np.abs(T0[0]).max() == 0 and (open_top or np.abs(T0[-1]).max() == 0)
+    # level 1 by scipy on the extended grid
+    (cx, cy, cz), _ = levels[1]
+    Pz = prolongation(nze, cz, False)
+    top_fixed = not open_top
+    fine_rows = list(range(1, nze - (1 if top_fixed else 0)))        # extended planes of the unknowns
+    coarse_cols = list(range(1, cz - (1 if top_fixed else 0)))
+    Pz = Pz[np.ix_(fine_rows, coarse_cols)]
+    P = np.kron(Pz, np.kron(prolongation(ny, cy, True), prolongation(nx, cx, True)))
+    Ac = P.T @ A @ P
+    T1 = pf.pf_mg_table(cfg, 1, "phi")[:, 0, 0, :]
+    nzu = len(coarse_cols)
+    for kc in range(nzu):
+        for (J, I) in ((0, 0), (3, 5)):
+            r = I + cx * (J + cy * kc)
+            s = np.zeros(27)
+            for o in range(27):
+                dx, dy, dz = tap(o)
+                if not 0 <= kc + dz < nzu:
+                    continue
+                s[o] = Ac[r, (I + dx) % cx + cx * ((J + dy) % cy + cy * (kc + dz))]
+            ref = T1[kc + 1].copy()
+            if kc == 0:
+                ref[[o for o in range(27) if tap(o)[2] == -1]] = 0
+            if kc == nzu - 1:
+                ref[[o for o in range(27) if tap(o)[2] == 1]] = 0
+            np.testing.assert_allclose(s, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
