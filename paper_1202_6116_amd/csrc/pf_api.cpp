@@ -80,9 +80,9 @@ template <typename T>
 hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const T* p, T* r,
                            const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T>
-hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* P, const T* V, T cdt,
-                        const T* phi, const T* ghost_top, const T* u, int mode, const NoiseSpec& ns, T* Pn,
-                        T* Vn, T* Fout, hipStream_t s);
+hipError_t launch_force(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const FemTables* tb, const T* P,
+                        const T* V, T cdt, const T* phi, const T* ghost_top, const T* u, int mode,
+                        const NoiseSpec& ns, T* Pn, T* Vn, T* Fout, hipStream_t s);
 hipError_t launch_noise(const NoiseSpec& ns, int64_t N, double* xi, hipStream_t s);
 template <typename S>
 hipError_t launch_elec_quad(const Dims& dp, const Coefs<double>& cf, const S* P, const double* phi,
@@ -293,6 +293,12 @@ void build_tables(const pf_config& c, FemTables* t) {
           t->Ms[zt][o] = ax[0]->m[off[0]] * ax[1]->m[off[1]] * ax[2]->m[off[2]];
         }
       }
+  for (int zt = 0; zt < 3; zt++)
+    for (int o = 0; o < 3; o++) {
+      t->m1[zt][o] = zrow[zt].m[o];
+      t->g1[zt][o] = zrow[zt].g[o];
+      t->gt1[zt][o] = zrow[zt].gt[o];
+    }
   for (int cc = 0; cc < 3; cc++) {
     t->inv_diag[0][cc] = 1.0 / t->K[0][cc][cc][13];
     t->inv_diag[1][cc] = 1.0 / t->K[1][cc][cc][13];
@@ -1163,7 +1169,7 @@ pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt
     const float* phi = phi_override ? static_cast<const float*>(phi_override) : at<float>(c, c->lay.phi32);
     const float* u = u_override ? static_cast<const float*>(u_override) : at<float>(c, c->lay.u32);
     PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
-      return launch_force<float>(c->dims, cf, tb, static_cast<const float*>(P), static_cast<const float*>(V),
+      return launch_force<float>(c->dims, c->tm_f, cf, tb, static_cast<const float*>(P), static_cast<const float*>(V),
                                  (float)cdt, phi, at<float>(c, c->lay.ghost32), u, mode, ns, static_cast<float*>(Pn),
                                  static_cast<float*>(Vn), static_cast<float*>(F), c->stream);
     }));
@@ -1172,7 +1178,7 @@ pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt
     const double* phi = phi_override ? static_cast<const double*>(phi_override) : at<double>(c, c->lay.phi);
     const double* u = u_override ? static_cast<const double*>(u_override) : at<double>(c, c->lay.u);
     PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
-      return launch_force<double>(c->dims, cf, tb, static_cast<const double*>(P), static_cast<const double*>(V), cdt,
+      return launch_force<double>(c->dims, c->tm_f, cf, tb, static_cast<const double*>(P), static_cast<const double*>(V), cdt,
                                   phi, at<double>(c, c->lay.ghost64), u, mode, ns, static_cast<double*>(Pn),
                                   static_cast<double*>(Vn), static_cast<double*>(F), c->stream);
     }));

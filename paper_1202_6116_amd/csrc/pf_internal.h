@@ -40,6 +40,10 @@ struct FemTables {
   double Ms[3][kTaps];
   // Inverse Jacobi diagonal of K for interior and top rows, per component.
   double inv_diag[2][3];
+  // The 1D element integrals the 3D stencils above are products of (row
+  // kind z in {kLow, kInterior, kHigh}, tap dz + 1): mass int N_n N_m,
+  // int N_n N_m' (g) and int N_n' N_m (gt).  The x and y axes use kInterior.
+  double m1[3][3], g1[3][3], gt1[3][3];
 };
 
 // Scalars of one conjugate-gradient solve, resident in device memory.  The

@@ -1415,119 +1415,235 @@ __global__ void noise_kernel(NoiseSpec ns, int64_t N, double* __restrict__ xi) {
   }
 }
 
-template <typename T, bool ROT>
-__global__ __launch_bounds__(kThreads) void force_kernel(
-    Dims d, Coefs<T> cf, const FemTables* __restrict__ tb, const T* __restrict__ P, const T* __restrict__ V, T cdt,
-    const T* __restrict__ phi, const T* __restrict__ ghost_top, const T* __restrict__ u, int mode, NoiseSpec ns,
-    T* __restrict__ Pn, T* __restrict__ Vn, T* __restrict__ Fout) {
-  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
-  if (i >= d.nx || j >= d.ny) return;
+// The force is a tile kernel.  Its elastic term needs, at every node, the
+// consistent-mass weighted strains w_v = int N_n (eps_v(u) - eps0_v(Pp)) over
+// the 27 neighbours.  Those 3D stencils are products of 1D element
+// integrals (mass m and int N_n N_m' = g; end rows in z), so they are applied
+// in two passes.  Each source plane s is staged in LDS as (eps0(Pp), u) on
+// the tile and its halo; every node of the tile reduces it in x and y, and
+// pushes the result into the z-sums of the planes s - 1, s, s + 1 of its own
+// column, held in registers; plane s - 1 is then complete.  With Voigt order
+// (xx, yy, zz, xy, yz, xz) and in-plane rows m, g:
+//   M_v = -(m x m) e_v + (g x m) u_x [xx] + (m x g) u_y [yy]
+//         + (m x g) u_x + (g x m) u_y [xy] + (m x g) u_z [yz] + (g x m) u_z [xz]
+//   Z_zz = (m x m) u_z, Z_yz = (m x m) u_y, Z_xz = (m x m) u_x
+//   w_v(t) = sum_dz mz_t(dz) M_v(t + dz) + gz_t(dz) Z_v(t + dz)
+// Pp is staged in a two-plane ring for the Laplacian.
+constexpr int kEU = 9;  // staged per halo point: e_0..e_5, u_x, u_y, u_z
+
+// At most 168 VGPRs: the 47.5 KB of LDS (FP64) allow three blocks per CU,
+// so three waves per SIMD.  NOISE compiles the thermal-noise term.
+template <typename T, bool ROT, bool NOISE>
+__global__ __launch_bounds__(kThreads, 3) void force_kernel(
+    Dims d, TileMap tm, Coefs<T> cf, const FemTables* __restrict__ tb, const T* __restrict__ P,
+    const T* __restrict__ V, T cdt, const T* __restrict__ phi, const T* __restrict__ ghost_top,
+    const T* __restrict__ u, int mode, NoiseSpec ns, T* __restrict__ Pn, T* __restrict__ Vn, T* __restrict__ Fout) {
+  constexpr int TY = kBY;
+  using H = Halo<TY>;
+  __shared__ T eu[kEU][TY + 2][kHX];
+  __shared__ T pc[2][3][TY + 2][kHX];
+  const TileCoord tc = tile_coord(d, tm);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
   const int64_t N = d.N, pl = d.plane;
-  const int64_t n = i + (int64_t)d.nx * j + pl * k;
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
   const bool hasV = V != nullptr;
-  auto pp = [&](int64_t m, T out[3]) {
+  const bool elas = (cf.terms & kElas) != 0;
+  // raw values of the next source plane: P, V, u of this thread's halo points
+  Stage<T, 9, H::NPT> st;
+  auto fetch = [&](int64_t m, int, T* raw) {
 #pragma unroll
-    for (int c = 0; c < 3; c++) out[c] = P[c * N + m] + (hasV ? cdt * V[c * N + m] : (T)0);
+    for (int c = 0; c < 3; c++) {
+      raw[c] = P[c * N + m];
+      raw[3 + c] = hasV ? V[c * N + m] : (T)0;
+      raw[6 + c] = elas ? u[c * N + m] : (T)0;
+    }
   };
-  T p0[3];
-  pp(n, p0);
-  T F[3] = {0, 0, 0};
-  if (cf.terms & kLandau) {
-    T g[3];
-    landau_gradient<ROT>(cf, p0, g);
+  // stage the fetched plane s: Pp into the ring slot s & 1, (e, u) into eu
+  auto stage = [&](int s) {
 #pragma unroll
-    for (int c = 0; c < 3; c++) F[c] += g[c];
-  }
-  if (cf.terms & kGrad) {
-    T a[3], lap[3] = {0, 0, 0};
-    const int64_t ms[4] = {nbr(d, i, j, k, 1, 0, 0), nbr(d, i, j, k, -1, 0, 0), nbr(d, i, j, k, 0, 1, 0),
-                           nbr(d, i, j, k, 0, -1, 0)};
+    for (int q = 0; q < H::NPT; q++) {
+      const int t = tid_flat() + q * kThreads;
+      if (t >= H::HP) continue;
+      const int hx = t % kHX, hy = t / kHX;
+      const T* raw = st.v[q];
+      T pp[3];
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-      pp(ms[t], a);
+      for (int c = 0; c < 3; c++) pp[c] = raw[c] + cdt * raw[3 + c];
 #pragma unroll
-      for (int c = 0; c < 3; c++) lap[c] += a[c] - p0[c];
-    }
-    if (k + 1 < d.nz) {
-      pp(n + pl, a);
+      for (int c = 0; c < 3; c++) pc[s & 1][c][hy][hx] = pp[c];
+      if (elas) {
+        // points outside the grid were fetched as zeros: their e must be zero too
+        const int gi = tc.i0 + hx - 1, gj = tc.j0 + hy - 1;
+        const bool live = s >= 0 && s < d.nz && gi >= -1 && gi <= d.nx && gj >= -1 && gj <= d.ny;
+        T e[6] = {0, 0, 0, 0, 0, 0};
+        if (live) eigenstrain<ROT>(cf, pp[0], pp[1], pp[2], e);
 #pragma unroll
-      for (int c = 0; c < 3; c++) lap[c] += a[c] - p0[c];
-    }
-    if (k > 0) {
-      pp(n - pl, a);
+        for (int v = 0; v < 6; v++) eu[v][hy][hx] = e[v];
 #pragma unroll
-      for (int c = 0; c < 3; c++) lap[c] += a[c] - p0[c];
-    }
-#pragma unroll
-    for (int c = 0; c < 3; c++) F[c] -= cf.G * cf.inv_h2 * lap[c];
-  }
-  if (cf.terms & kElec) {
-    const T zp = (k + 1 < d.nzp) ? phi[n + pl] : ghost_top[i + (int64_t)d.nx * j];
-    const T zm = (k > 0) ? phi[n - pl] : cf.phi_bottom;
-    F[0] += (phi[nbr(d, i, j, k, 1, 0, 0)] - phi[nbr(d, i, j, k, -1, 0, 0)]) * cf.inv_2h;
-    F[1] += (phi[nbr(d, i, j, k, 0, 1, 0)] - phi[nbr(d, i, j, k, 0, -1, 0)]) * cf.inv_2h;
-    F[2] += (zp - zm) * cf.inv_2h;
-  }
-  if (cf.terms & kElas) {
-    const int zt = (k == 0) ? kLow : ((k == d.nz - 1) ? kHigh : kInterior);
-    const int dzmin = (k == 0) ? 0 : -1, dzmax = (k == d.nz - 1) ? 0 : 1;
-    T w[6] = {0, 0, 0, 0, 0, 0};
-    for (int dz = dzmin; dz <= dzmax; dz++)
-#pragma unroll
-      for (int dy = -1; dy <= 1; dy++)
-#pragma unroll
-        for (int dx = -1; dx <= 1; dx++) {
-          const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-          const int64_t m = nbr(d, i, j, k, dx, dy, dz);
-          T a[3], e[6];
-          pp(m, a);
-          eigenstrain<ROT>(cf, a[0], a[1], a[2], e);
-          const T ms = (T)tb->Ms[zt][o];
-          const T uu[3] = {u[m], u[N + m], u[2 * N + m]};
-#pragma unroll
-          for (int q = 0; q < 6; q++) {
-            T acc = -ms * e[q];
-#pragma unroll
-            for (int c = 0; c < 3; c++) acc += (T)tb->Su[zt][q][c][o] * uu[c];
-            w[q] += acc;
-          }
-        }
-    T s[6], g[3];
-    cubic_stress<ROT>(cf, w, s);
-    stress_pull<ROT>(cf, p0, s, g);
-    F[0] -= cf.inv_h3 * g[0];
-    F[1] -= cf.inv_h3 * g[1];
-    F[2] -= cf.inv_h3 * g[2];
-  }
-#pragma unroll
-  for (int c = 0; c < 3; c++) F[c] *= -cf.L;
-  if (ns.amp != 0.0 && (mode == kPcStep || mode == kEulerStep)) {
-    double xi[3];
-    noise_variates(ns, n, xi);
-#pragma unroll
-    for (int c = 0; c < 3; c++) F[c] += (T)(ns.amp * xi[c]);
-  }
-  switch (mode) {
-    case kForceOut:
-#pragma unroll
-      for (int c = 0; c < 3; c++) Fout[c * N + n] = F[c];
-      break;
-    case kPcInit:
-#pragma unroll
-      for (int c = 0; c < 3; c++) Vn[c * N + n] = F[c];
-      break;
-    case kPcStep:
-#pragma unroll
-      for (int c = 0; c < 3; c++) {
-        const T vn = (T)0.5 * (V[c * N + n] + F[c]);
-        Vn[c * N + n] = vn;
-        Pn[c * N + n] = P[c * N + n] + cf.dt * vn;
+        for (int c = 0; c < 3; c++) eu[6 + c][hy][hx] = raw[6 + c];
       }
-      break;
-    default:  // kEulerStep
+    }
+  };
+  const T mI[3] = {(T)tb->m1[kInterior][0], (T)tb->m1[kInterior][1], (T)tb->m1[kInterior][2]};
+  const T gI[3] = {(T)tb->g1[kInterior][0], (T)tb->g1[kInterior][1], (T)tb->g1[kInterior][2]};
+  // in-plane pass of the staged plane at this node: M (6) and Z (zz, yz, xz)
+  auto xy_pass = [&](T M[6], T Z[3]) {
 #pragma unroll
-      for (int c = 0; c < 3; c++) Pn[c * N + n] = P[c * N + n] + cf.dt * F[c];
-      break;
+    for (int v = 0; v < 6; v++) M[v] = 0;
+    Z[0] = Z[1] = Z[2] = 0;
+    // rows one at a time: unrolled, the 81 LDS loads of a node would all be
+    // issued at once and hold ~160 registers
+#pragma unroll 1
+    for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+      for (int dx = -1; dx <= 1; dx++) {
+        const int hx = lx + 1 + dx, hy = ly + 1 + dy;
+        const T mm = mI[dx + 1] * mI[dy + 1], gm = gI[dx + 1] * mI[dy + 1], mg = mI[dx + 1] * gI[dy + 1];
+#pragma unroll
+        for (int v = 0; v < 6; v++) M[v] -= mm * eu[v][hy][hx];
+        const T ux = eu[6][hy][hx], uy = eu[7][hy][hx], uz = eu[8][hy][hx];
+        M[0] += gm * ux;
+        M[1] += mg * uy;
+        M[3] += mg * ux + gm * uy;
+        M[4] += mg * uz;
+        M[5] += gm * uz;
+        Z[0] += mm * uz;
+        Z[1] += mm * uy;
+        Z[2] += mm * ux;
+      }
+  };
+  auto zkind = [&](int t) { return t == 0 ? kLow : (t == d.nz - 1 ? kHigh : kInterior); };
+  // w (target t) += (or =) the contribution of a source plane at z offset dz
+  auto contrib = [&](int t, int dz, const T M[6], const T Z[3], T w[6], bool add) {
+    const int zk = zkind(t);
+    const T mz = (T)tb->m1[zk][dz + 1], gz = (T)tb->g1[zk][dz + 1];
+    T c[6];
+#pragma unroll
+    for (int v = 0; v < 6; v++) c[v] = mz * M[v];
+    c[2] += gz * Z[0];
+    c[4] += gz * Z[1];
+    c[5] += gz * Z[2];
+#pragma unroll
+    for (int v = 0; v < 6; v++) w[v] = add ? w[v] + c[v] : c[v];
+  };
+  T w0[6] = {0, 0, 0, 0, 0, 0}, w1[6] = {0, 0, 0, 0, 0, 0};  // z-sums of planes k and k + 1
+  T pdn[3] = {0, 0, 0};                                        // Pp of the plane below, own column
+  const int k0 = tc.k0;
+  // prologue: sources k0 - 1 (if any) and k0
+  if (k0 > 0) {
+    stage_fetch<TY>(st, d, tc.i0, tc.j0, k0 - 1, fetch);
+    stage(k0 - 1);
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < 3; c++) pdn[c] = pc[(k0 - 1) & 1][c][ly + 1][lx + 1];
+      if (elas) {
+        T M[6], Z[3];
+        xy_pass(M, Z);
+        contrib(k0, -1, M, Z, w0, false);
+      }
+    }
+    __syncthreads();
+  }
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, k0, fetch);
+  stage(k0);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, k0 + 1, fetch);
+  __syncthreads();
+  if (valid && elas) {
+    T M[6], Z[3];
+    xy_pass(M, Z);
+    contrib(k0, 0, M, Z, w0, true);
+    contrib(k0 + 1, -1, M, Z, w1, false);
+  }
+  __syncthreads();
+  for (int k = k0; k < tc.k1; k++) {
+    // source k + 1 (zeros above the grid) completes plane k
+    stage(k + 1);
+    if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
+    __syncthreads();
+    if (valid) {
+      const int64_t n = col + pl * k;
+      const int s0 = k & 1, s1 = (k + 1) & 1;
+      T p0[3];
+#pragma unroll
+      for (int c = 0; c < 3; c++) p0[c] = pc[s0][c][ly + 1][lx + 1];
+      T F[3] = {0, 0, 0};
+      if (elas) {
+        T M[6], Z[3];
+        xy_pass(M, Z);
+        if (k + 1 < d.nz) contrib(k, 1, M, Z, w0, true);
+        T sg[6], g[3];
+        cubic_stress<ROT>(cf, w0, sg);
+        stress_pull<ROT>(cf, p0, sg, g);
+#pragma unroll
+        for (int c = 0; c < 3; c++) F[c] -= cf.inv_h3 * g[c];
+        // slide: plane k + 1 becomes the one being completed
+#pragma unroll
+        for (int v = 0; v < 6; v++) w0[v] = w1[v];
+        if (k + 1 < d.nz) {
+          contrib(k + 1, 0, M, Z, w0, true);
+          contrib(k + 2, -1, M, Z, w1, false);
+        }
+      }
+      if (cf.terms & kLandau) {
+        T g[3];
+        landau_gradient<ROT>(cf, p0, g);
+#pragma unroll
+        for (int c = 0; c < 3; c++) F[c] += g[c];
+      }
+      if (cf.terms & kGrad) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          T lap = pc[s0][c][ly + 1][lx] + pc[s0][c][ly + 1][lx + 2] + pc[s0][c][ly][lx + 1] +
+                  pc[s0][c][ly + 2][lx + 1] - 4 * p0[c];
+          if (k + 1 < d.nz) lap += pc[s1][c][ly + 1][lx + 1] - p0[c];
+          if (k > 0) lap += pdn[c] - p0[c];
+          F[c] -= cf.G * cf.inv_h2 * lap;
+        }
+      }
+      if (cf.terms & kElec) {
+        const T zp = (k + 1 < d.nzp) ? phi[n + pl] : ghost_top[col];
+        const T zm = (k > 0) ? phi[n - pl] : cf.phi_bottom;
+        F[0] += (phi[nbr(d, i, j, k, 1, 0, 0)] - phi[nbr(d, i, j, k, -1, 0, 0)]) * cf.inv_2h;
+        F[1] += (phi[nbr(d, i, j, k, 0, 1, 0)] - phi[nbr(d, i, j, k, 0, -1, 0)]) * cf.inv_2h;
+        F[2] += (zp - zm) * cf.inv_2h;
+      }
+#pragma unroll
+      for (int c = 0; c < 3; c++) F[c] *= -cf.L;
+      if (NOISE && (mode == kPcStep || mode == kEulerStep)) {
+        double xi[3];
+        noise_variates(ns, n, xi);
+#pragma unroll
+        for (int c = 0; c < 3; c++) F[c] += (T)(ns.amp * xi[c]);
+      }
+      switch (mode) {
+        case kForceOut:
+#pragma unroll
+          for (int c = 0; c < 3; c++) Fout[c * N + n] = F[c];
+          break;
+        case kPcInit:
+#pragma unroll
+          for (int c = 0; c < 3; c++) Vn[c * N + n] = F[c];
+          break;
+        case kPcStep:
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            const T vn = (T)0.5 * (V[c * N + n] + F[c]);
+            Vn[c * N + n] = vn;
+            Pn[c * N + n] = P[c * N + n] + cf.dt * vn;
+          }
+          break;
+        default:  // kEulerStep
+#pragma unroll
+          for (int c = 0; c < 3; c++) Pn[c * N + n] = P[c * N + n] + cf.dt * F[c];
+          break;
+      }
+#pragma unroll
+      for (int c = 0; c < 3; c++) pdn[c] = p0[c];
+    }
+    __syncthreads();
   }
 }
 
@@ -2044,15 +2160,21 @@ hipError_t launch_mgp_fine(const Dims& d, const TileMap& tm, const Coefs<T>& cf,
 }
 
 template <typename T>
-hipError_t launch_force(const Dims& d, const Coefs<T>& cf, const FemTables* tb, const T* P, const T* V, T cdt,
-                        const T* phi, const T* ghost_top, const T* u, int mode, const NoiseSpec& ns, T* Pn,
-                        T* Vn, T* Fout, hipStream_t s) {
-  if (cf.rotated)
-    force_kernel<T, true><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, phi, ghost_top, u, mode, ns,
-                                                              Pn, Vn, Fout);
-  else
-    force_kernel<T, false><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, phi, ghost_top, u, mode, ns,
-                                                               Pn, Vn, Fout);
+hipError_t launch_force(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const FemTables* tb, const T* P,
+                        const T* V, T cdt, const T* phi, const T* ghost_top, const T* u, int mode,
+                        const NoiseSpec& ns, T* Pn, T* Vn, T* Fout, hipStream_t s) {
+  const bool noise = ns.amp != 0.0;
+#define PF_FORCE(ROT, NOISE)                                                                                  \
+  force_kernel<T, ROT, NOISE><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, tb, P, V, cdt, phi, ghost_top, u, \
+                                                                  mode, ns, Pn, Vn, Fout)
+  if (cf.rotated) {
+    if (noise) PF_FORCE(true, true);
+    else PF_FORCE(true, false);
+  } else {
+    if (noise) PF_FORCE(false, true);
+    else PF_FORCE(false, false);
+  }
+#undef PF_FORCE
   return hipGetLastError();
 }
 
@@ -2121,8 +2243,9 @@ PF_INSTANTIATE_ADJ(float)
                                          T*, T*, const CgScalars*, double*, int, hipStream_t);                   \
   template hipError_t launch_fem_cg_b<T>(const Dims&, const TileMap&, const FemTables*, bool, const T*, T*,      \
                                          const CgScalars*, double*, hipStream_t);                                \
-  template hipError_t launch_force<T>(const Dims&, const Coefs<T>&, const FemTables*, const T*, const T*, T,     \
-                                      const T*, const T*, const T*, int, const NoiseSpec&, T*, T*, T*, hipStream_t);
+  template hipError_t launch_force<T>(const Dims&, const TileMap&, const Coefs<T>&, const FemTables*, const T*,  \
+                                      const T*, T, const T*, const T*, const T*, int, const NoiseSpec&, T*, T*, T*, \
+                                      hipStream_t);
 
 PF_INSTANTIATE(double)
 PF_INSTANTIATE(float)
