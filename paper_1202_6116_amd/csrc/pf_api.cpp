@@ -70,8 +70,9 @@ template <typename T>
 hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* p, T* r,
                                const uint8_t* emask, const CgScalars* sc, double* partials, hipStream_t s);
 template <typename T, typename S, typename R>
-hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, bool gen, const S* P, const S* V,
-                            T cdt, const T* W, T* x, R* r, R* p0, R* p1, R* dz, double* partials, hipStream_t s);
+hipError_t launch_fem_setup(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const FemTables* tb, bool gen,
+                            const S* P, const S* V, T cdt, const T* W, T* x, R* r, R* p0, R* p1, R* dz,
+                            double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_fem_cg_a(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const T* r,
                            const T* p_old, T* p_new, T* x, const CgScalars* sc, double* partials, int unit_w,
@@ -976,10 +977,10 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
   double* const pb[2] = {at<double>(c, c->lay.fp[0]), at<double>(c, c->lay.fp[1])};
   if (!warm) PF_HIP(c, launch_fill<double>(x, 3 * d.N, 0.0, c->stream));
   PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
-    return launch_fem_setup<double, S, double>(d, cf, tb, !c->mat.cubic, P, V, cdt, W, x, r, pb[0], pb[1], nullptr,
+    return launch_fem_setup<double, S, double>(d, c->tm_f, cf, tb, !c->mat.cubic, P, V, cdt, W, x, r, pb[0], pb[1], nullptr,
                                                part, c->stream);
   }));
-  PF_HIP(c, reduce(c, part, c->nblocks, 3, 1, kRedSetup, tol, 0, nullptr));
+  PF_HIP(c, reduce(c, part, c->tm_f.nblocks, 3, 1, kRedSetup, tol, 0, nullptr));
   if (mg_on(c, 1)) PF_HIP(c, mg_setup<double>(c, 1, r));
   CgScalars h;
   PF_TRY(run_cg<double>(c, 1, c->pred[pred], x, pb, 3 * d.N, fem_iteration<double>(c, r, pb, x, tol), &h,
@@ -999,7 +1000,7 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
   const Dims& d = fem ? c->dims : c->dims_p;
   const int which = fem ? 1 : 0;
   const int64_t n = fem ? 3 * d.N : d.N;
-  const int setup_blocks = fem ? c->nblocks : c->nblocks_p;
+  const int setup_blocks = fem ? c->tm_f.nblocks : c->nblocks_p;
   const Coefs<double> cf64 = make_coefs<double>(c);
   const Coefs<float> cf32 = make_coefs<float>(c);
   const FemTables* tb = at<FemTables>(c, c->lay.tables);
@@ -1019,7 +1020,7 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
   for (;;) {
     if (fem) {
       PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
-        return launch_fem_setup<double, float, float>(d, cf64, tb, !c->mat.cubic, P, V, cdt, nullptr, x64, r, pb[0],
+        return launch_fem_setup<double, float, float>(d, c->tm_f, cf64, tb, !c->mat.cubic, P, V, cdt, nullptr, x64, r, pb[0],
                                                       pb[1], dz, part, c->stream);
       }));
     } else {

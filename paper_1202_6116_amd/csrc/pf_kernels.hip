@@ -778,81 +778,183 @@ __device__ __forceinline__ void landau_hessian_apply(const Coefs<T>& cf, const T
 
 // f = body force of the eigenstrain of Pp = P + cdt V (Eq. 15); r = f - K x;
 // p = r / diag.  The clamped plane k = 0 has x = r = p = 0 (both direction
-// buffers).  Partial (f.f, r.z, r.r).
+// buffers).  Partial (f.f, r.z, r.r) per tile.
 // With W non-null the eigenstrain is replaced by its linearisation at Pp in
 // the direction W, deps0 = (d eps0/dP)(Pp) W (the right-hand side of the
 // adjoint FEM solve).
+// A tile kernel like the force: the body-force stencils are products of 1D
+// element integrals (rows m, gt = int N_n' N_m), so with the nodal
+// eigenstress sigma = C eps0 staged per plane in LDS, each node forms
+//   A_c = (gt x m) sigma_cx + (m x gt) sigma_cy,   B_c = (m x m) sigma_cz
+// in x and y and sums f_c(t) = sum_dz mz_t(dz) A_c + gtz_t(dz) B_c over its
+// column in registers; x is staged in the usual three-plane ring for K x.
 template <typename T, typename S, typename R, bool GEN>
-__global__ __launch_bounds__(kThreads) void fem_setup_kernel(
-    Dims d, Coefs<T> cf, const FemTables* __restrict__ tb, const S* __restrict__ P, const S* __restrict__ V, T cdt,
-    const T* __restrict__ W, T* __restrict__ x, R* __restrict__ r, R* __restrict__ p0, R* __restrict__ p1,
-    R* __restrict__ dz, double* partials) {
-  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
-  double v[3] = {0.0, 0.0, 0.0};
-  if (i < d.nx && j < d.ny) {
-    const int64_t N = d.N;
-    const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
-    if (k == 0) {
+__global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
+    Dims d, TileMap tm, Coefs<T> cf, const FemTables* __restrict__ tb, const S* __restrict__ P,
+    const S* __restrict__ V, T cdt, const T* __restrict__ W, T* __restrict__ x, R* __restrict__ r,
+    R* __restrict__ p0, R* __restrict__ p1, R* __restrict__ dz, double* partials) {
+  constexpr int TY = kBY;
+  using H = Halo<TY>;
+  __shared__ T sgm[6][TY + 2][kHX];
+  __shared__ T ring[3][3][TY + 2][kHX];
+  const TileCoord tc = tile_coord(d, tm);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
+  const int64_t N = d.N, pl = d.plane;
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  const bool hasV = V != nullptr, hasW = W != nullptr;
+  Stage<T, 9, H::NPT> sp;  // P, V, W of the next source plane
+  Stage<T, 3, H::NPT> sx;  // x of the next plane
+  auto fetch_p = [&](int64_t m, int, T* raw) {
 #pragma unroll
-      for (int c = 0; c < 3; c++) {
-        x[c * N + n] = 0;
-        r[c * N + n] = 0;
-        p0[c * N + n] = 0;
-        p1[c * N + n] = 0;
-        if (dz) dz[c * N + n] = 0;
+    for (int c = 0; c < 3; c++) {
+      raw[c] = (T)P[c * N + m];
+      raw[3 + c] = hasV ? (T)V[c * N + m] : (T)0;
+      raw[6 + c] = hasW ? W[c * N + m] : (T)0;
+    }
+  };
+  auto fetch_x = [&](int64_t m, int k, T* raw) {
+    if (k == 0) return;  // the clamp
+#pragma unroll
+    for (int c = 0; c < 3; c++) raw[c] = x[c * N + m];
+  };
+  auto comb_x = [&](int, const T* raw, T* o) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) o[c] = raw[c];
+  };
+  auto fetch = [&](int k) {
+    stage_fetch<TY>(sp, d, tc.i0, tc.j0, k, fetch_p);
+    stage_fetch<TY>(sx, d, tc.i0, tc.j0, k, fetch_x);
+  };
+  // stage plane s: eigenstress into sgm, x into the ring
+  auto stage = [&](int s) {
+#pragma unroll
+    for (int q = 0; q < H::NPT; q++) {
+      const int t = tid_flat() + q * kThreads;
+      if (t >= H::HP) continue;
+      const int hx = t % kHX, hy = t / kHX;
+      const int gi = tc.i0 + hx - 1, gj = tc.j0 + hy - 1;
+      const bool live = s >= 0 && s < d.nz && gi >= -1 && gi <= d.nx && gj >= -1 && gj <= d.ny;
+      T sg[6] = {0, 0, 0, 0, 0, 0};
+      if (live) {
+        const T* raw = sp.v[q];
+        const T px = raw[0] + cdt * raw[3], py = raw[1] + cdt * raw[4], pz = raw[2] + cdt * raw[5];
+        T e[6];
+        if (hasW) eigenstrain_lin(cf, px, py, pz, raw[6], raw[7], raw[8], e);
+        else eigenstrain(cf, px, py, pz, e);
+        cubic_stress(cf, e, sg);
       }
-    } else {
-      const int zt = (k == d.nz - 1) ? 1 : 0;
-      const int dzmax = zt ? 0 : 1;
-      T f[3] = {0, 0, 0};
-      for (int dz = -1; dz <= dzmax; dz++)
 #pragma unroll
-        for (int dy = -1; dy <= 1; dy++)
+      for (int v = 0; v < 6; v++) sgm[v][hy][hx] = sg[v];
+    }
+    stage_store<TY>(ring, sx, s, comb_x);
+  };
+  const T mI[3] = {(T)tb->m1[kInterior][0], (T)tb->m1[kInterior][1], (T)tb->m1[kInterior][2]};
+  const T tI[3] = {(T)tb->gt1[kInterior][0], (T)tb->gt1[kInterior][1], (T)tb->gt1[kInterior][2]};
+  auto xy_pass = [&](T A[3], T B[3]) {
 #pragma unroll
-          for (int dx = -1; dx <= 1; dx++) {
-            const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-            const int64_t m = nbr(d, i, j, k, dx, dy, dz);
-            T px = (T)P[m], py = (T)P[N + m], pz = (T)P[2 * N + m];
-            if (V) {
-              px += cdt * (T)V[m];
-              py += cdt * (T)V[N + m];
-              pz += cdt * (T)V[2 * N + m];
-            }
-            T e[6], s[6];
-            if (W) eigenstrain_lin(cf, px, py, pz, W[m], W[N + m], W[2 * N + m], e);
-            else eigenstrain(cf, px, py, pz, e);
-            cubic_stress(cf, e, s);
+    for (int c = 0; c < 3; c++) A[c] = B[c] = 0;
+#pragma unroll 1
+    for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
-            for (int c = 0; c < 3; c++)
+      for (int dx = -1; dx <= 1; dx++) {
+        const int hx = lx + 1 + dx, hy = ly + 1 + dy;
+        const T mm = mI[dx + 1] * mI[dy + 1], gm = tI[dx + 1] * mI[dy + 1], mg = mI[dx + 1] * tI[dy + 1];
+        const T s0 = sgm[0][hy][hx], s1 = sgm[1][hy][hx], s2 = sgm[2][hy][hx];
+        const T s3 = sgm[3][hy][hx], s4 = sgm[4][hy][hx], s5 = sgm[5][hy][hx];
+        A[0] += gm * s0 + mg * s3;
+        A[1] += gm * s3 + mg * s1;
+        A[2] += gm * s5 + mg * s4;
+        B[0] += mm * s5;
+        B[1] += mm * s4;
+        B[2] += mm * s2;
+      }
+  };
+  auto zkind = [&](int t) { return t == 0 ? kLow : (t == d.nz - 1 ? kHigh : kInterior); };
+  auto contrib = [&](int t, int dzo, const T A[3], const T B[3], T f[3], bool add) {
+    const int zk = zkind(t);
+    const T mz = (T)tb->m1[zk][dzo + 1], gz = (T)tb->gt1[zk][dzo + 1];
 #pragma unroll
-              for (int q = 0; q < 6; q++) f[c] += (T)tb->Bf[zt][c][q][o] * s[q];
-          }
-      auto ldx = [&](int dx, int dy, int dz, T u[3]) {
-        const int64_t m = nbr(d, i, j, k, dx, dy, dz);
-        if (k + dz == 0) {
-          u[0] = u[1] = u[2] = 0;  // clamped column
-        } else {
-          u[0] = x[m];
-          u[1] = x[N + m];
-          u[2] = x[2 * N + m];
+    for (int c = 0; c < 3; c++) f[c] = (add ? f[c] : (T)0) + mz * A[c] + gz * B[c];
+  };
+  T f0[3] = {0, 0, 0}, f1[3] = {0, 0, 0};  // z-sums of the body force of planes k and k + 1
+  const int k0 = tc.k0;
+  if (k0 > 0) {
+    fetch(k0 - 1);
+    stage(k0 - 1);
+    __syncthreads();
+    if (valid) {
+      T A[3], B[3];
+      xy_pass(A, B);
+      contrib(k0, -1, A, B, f0, false);
+    }
+    __syncthreads();
+  }
+  fetch(k0);
+  stage(k0);
+  fetch(k0 + 1);
+  __syncthreads();
+  if (valid) {
+    T A[3], B[3];
+    xy_pass(A, B);
+    contrib(k0, 0, A, B, f0, true);
+    contrib(k0 + 1, -1, A, B, f1, false);
+  }
+  __syncthreads();
+  const T w_int[3] = {(T)tb->inv_diag[0][0], (T)tb->inv_diag[0][GEN ? 1 : 0], (T)tb->inv_diag[0][GEN ? 2 : 0]};
+  const T w_top[3] = {(T)tb->inv_diag[1][0], (T)tb->inv_diag[1][GEN ? 1 : 0], (T)tb->inv_diag[1][GEN ? 2 : 0]};
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int k = k0; k < tc.k1; k++) {
+    stage(k + 1);
+    if (k + 2 <= tc.k1) fetch(k + 2);
+    __syncthreads();
+    if (valid) {
+      T A[3], B[3];
+      xy_pass(A, B);
+      if (k + 1 < d.nz) contrib(k, 1, A, B, f0, true);
+      const int64_t n = col + pl * k;
+      if (k == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          x[c * N + n] = 0;
+          r[c * N + n] = 0;
+          p0[c * N + n] = 0;
+          p1[c * N + n] = 0;
+          if (dz) dz[c * N + n] = 0;
         }
-      };
-      T Kx[3];
-      fem_K_apply<T, GEN>(tb, zt, ldx, Kx);
+      } else {
+        const int zt = (k == d.nz - 1) ? 1 : 0;
+        auto ld = [&](int ox, int oy, int oz, T u[3]) {
+          const int sl = slot_of(k + oz);
 #pragma unroll
-      for (int c = 0; c < 3; c++) {
-        const T rr = f[c] - Kx[c];
-        const T z = rr * (T)tb->inv_diag[zt][GEN ? c : 0];
-        r[c * N + n] = (R)rr;
-        p0[c * N + n] = (R)z;
-        if (dz) dz[c * N + n] = 0;
-        v[0] += (double)f[c] * f[c];
-        v[1] += (double)rr * z;
-        v[2] += (double)rr * rr;
+          for (int c = 0; c < 3; c++) u[c] = ring[sl][c][ly + 1 + oy][lx + 1 + ox];
+        };
+        T Kx[3];
+        fem_K_apply<T, GEN>(tb, zt, ld, Kx);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          const T rr = f0[c] - Kx[c];
+          const T z = rr * (zt ? w_top[c] : w_int[c]);
+          r[c * N + n] = (R)rr;
+          p0[c * N + n] = (R)z;
+          if (dz) dz[c * N + n] = 0;
+          v[0] += (double)f0[c] * f0[c];
+          v[1] += (double)rr * z;
+          v[2] += (double)rr * rr;
+        }
+      }
+      // slide: plane k + 1 becomes the one being completed
+#pragma unroll
+      for (int c = 0; c < 3; c++) f0[c] = f1[c];
+      if (k + 1 < d.nz) {
+        contrib(k + 1, 0, A, B, f0, true);
+        contrib(k + 2, -1, A, B, f1, false);
       }
     }
+    __syncthreads();
   }
-  block_partials<3, kThreads>(v, partials, node_block_id());
+  block_partials<3, kThreads>(v, partials, tc.lid);
 }
 
 // Iteration kernel A: p_new = z + beta p_old on the tile and its halo (zero
@@ -2053,14 +2155,15 @@ hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>&
 }
 
 template <typename T, typename S, typename R>
-hipError_t launch_fem_setup(const Dims& d, const Coefs<T>& cf, const FemTables* tb, bool gen, const S* P, const S* V,
-                            T cdt, const T* W, T* x, R* r, R* p0, R* p1, R* dz, double* partials, hipStream_t s) {
+hipError_t launch_fem_setup(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const FemTables* tb, bool gen,
+                            const S* P, const S* V, T cdt, const T* W, T* x, R* r, R* p0, R* p1, R* dz,
+                            double* partials, hipStream_t s) {
   if (gen)
-    fem_setup_kernel<T, S, R, true><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, W, x, r, p0, p1, dz,
-                                                                        partials);
+    fem_setup_kernel<T, S, R, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, tb, P, V, cdt, W, x, r, p0, p1, dz,
+                                                                       partials);
   else
-    fem_setup_kernel<T, S, R, false><<<node_grid(d), node_block(), 0, s>>>(d, cf, tb, P, V, cdt, W, x, r, p0, p1,
-                                                                         dz, partials);
+    fem_setup_kernel<T, S, R, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, tb, P, V, cdt, W, x, r, p0, p1,
+                                                                        dz, partials);
   return hipGetLastError();
 }
 
@@ -2275,8 +2378,9 @@ PF_INSTANTIATE_MG(float)
   template hipError_t launch_poisson_setup<T, S, R>(const Dims&, const Coefs<T>&, const S*, const S*, T, int,    \
                                                     int, const T*, T, const uint8_t*, T*, R*, R*, R*, double*,   \
                                                     hipStream_t);                                                \
-  template hipError_t launch_fem_setup<T, S, R>(const Dims&, const Coefs<T>&, const FemTables*, bool, const S*,  \
-                                                const S*, T, const T*, T*, R*, R*, R*, R*, double*, hipStream_t);
+  template hipError_t launch_fem_setup<T, S, R>(const Dims&, const TileMap&, const Coefs<T>&, const FemTables*,   \
+                                                bool, const S*, const S*, T, const T*, T*, R*, R*, R*, R*, double*, \
+                                                hipStream_t);
 
 PF_INSTANTIATE_SETUP(double, double, double)
 PF_INSTANTIATE_SETUP(double, float, float)
