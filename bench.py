@@ -33,10 +33,15 @@ HBM_PEAK_GBS = 8000.0
 #   fem_a          r, p_old, x (72) read; p_new, x (48) written   (rows k >= 1)
 #   fem_b          p, r (48) read; r (24) written                 (rows k >= 1)
 #   force          P, V (48) + phi (8) + u (24) read; P, V (48) written
+#   mg_u0          FEM multigrid on the solver grid (residual or last sweep):
+#                  x, b (48) read; out (24) written                 (rows k >= 1)
+#   mg_phi0        the same for the Poisson operator: x, b (16) read; out (8)
 #   finish         x, p read, x written (Poisson 24, FEM 72 per node)
+# The Poisson classes run over the potential grid (the film plus, with the
+# open top, the air planes), the others over the film.
 BYTES_PER_NODE_FP64 = {
     "poisson_setup": 72, "poisson_a": 40, "poisson_b": 24, "fem_setup": 120, "fem_a": 120, "fem_b": 72,
-    "force": 128,
+    "force": 128, "mg_u0": 72, "mg_phi0": 24,
 }
 
 
@@ -49,8 +54,10 @@ MEASURED_TRAFFIC = {("lateral_256x256x64", "fp64", "fem_a"): 598.6e6}
 
 
 def nodes_per_launch(cls, cfg):
-    if cls in ("fem_a", "fem_b"):
+    if cls in ("fem_a", "fem_b", "mg_u0"):
         return cfg.nodes - cfg.nx * cfg.ny
+    if cls.startswith("poisson") or cls == "mg_phi0":
+        return cfg.nx * cfg.ny * cfg.phi_planes
     return cfg.nodes
 
 

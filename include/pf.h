@@ -272,7 +272,9 @@ enum {
   PF_KC_FINISH,            /* deferred solution update of a solve */
   PF_KC_REDUCE,            /* single-block reductions of the CG scalars */
   PF_KC_OTHER,             /* fills, copies, energy and adjoint sweeps */
-  PF_KC_MG,                /* multigrid V-cycle of the FEM preconditioner */
+  PF_KC_MG,                /* multigrid V-cycles: coarse levels, transfers, first sweeps */
+  PF_KC_MG_U0,             /* FEM multigrid: residual and last sweep on the solver grid */
+  PF_KC_MG_PHI0,           /* Poisson multigrid: residual and last sweep on the solver grid */
   PF_KC_COUNT
 };
 

@@ -811,7 +811,8 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   T* v0 = V(L.v0);
   T* t0 = V(L.t0);
   hipError_t e = run([&] { return launch_mg_scale<T>(d0, nc, Dv(0), h.levels[0].omega, r0, v0, sc, st); });
-  if (e == hipSuccess) e = run([&] { return fine(kMgResidual, 0.0, v0, t0, nullptr); });
+  auto run0 = [&](auto&& fn) { return timed(c, f == 0 ? PF_KC_MG_PHI0 : PF_KC_MG_U0, f, k, fn); };
+  if (e == hipSuccess) e = run0([&] { return fine(kMgResidual, 0.0, v0, t0, nullptr); });
   if (e == hipSuccess)
     e = run([&] {
       return launch_mg_restrict<T>(d0, D[1], nc, h.levels[1].cx, h.levels[1].cy, Zm(1), Zf(1), t0, V(L.b[1]), sc,
@@ -874,7 +875,7 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
       return launch_mg_prolong<T>(d0, D[1], nc, h.levels[1].cx, h.levels[1].cy, Zm(1), V(L.o[1]), v0, sc, zoff0, 0,
                                   top, st);
     });
-  if (e == hipSuccess) e = run([&] { return fine(kMgSweep, h.levels[0].omega, v0, z0, part); });
+  if (e == hipSuccess) e = run0([&] { return fine(kMgSweep, h.levels[0].omega, v0, z0, part); });
   return e;
 }
 

@@ -24,7 +24,7 @@ PF_FP64, PF_FP32_REFINE = 0, 1
 PF_TOP_METAL, PF_TOP_OPEN = 0, 1
 PF_PRECOND_JACOBI, PF_PRECOND_MG = 0, 1
 KERNEL_CLASSES = ["poisson_setup", "poisson_a", "poisson_b", "fem_setup", "fem_a", "fem_b", "force", "finish",
-                  "reduce", "other", "mg"]
+                  "reduce", "other", "mg", "mg_u0", "mg_phi0"]
 
 # Every symbol declared in include/pf.h.
 EXPORTS = [
