@@ -40,7 +40,8 @@ hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int nc, int cx, in
                               int ctop_fixed, hipStream_t s);
 template <typename T>
 hipError_t launch_mg_prolong(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap, const T* xc,
-                             T* xf, const CgScalars* sc, int zoff, int ftop_fixed, int ctop_fixed, hipStream_t s);
+                             T* xf, const CgScalars* sc, int zoff, int ftop_fixed, int ctop_fixed, const T* bf,
+                             const double* dinv, double omega, hipStream_t s);
 template <typename T>
 hipError_t launch_mg_dense(const Dims& d, int nc, int n, const double* M, const T* b, T* x, const CgScalars* sc,
                            hipStream_t s);
@@ -776,7 +777,9 @@ bool mg_on(const pf_ctx* c, int f) { return !c->mg[f].levels.empty(); }
 // One multigrid V-cycle z0 = M r0 of the Poisson (f = 0) or the FEM (f = 1)
 // operator (pre-smoothing: one damped Jacobi sweep from zero; residual,
 // restriction, the coarser levels, prolongation; post-smoothing: one sweep),
-// symmetric, so CG may use it.  The Poisson cycle runs on the operator of all
+// symmetric, so CG may use it.  On the solver grid the first sweep is never
+// stored: the residual kernel applies A to omega D^-1 b on the fly
+// (kMgFirst) and the prolongation forms omega D^-1 b + P e.  The Poisson cycle runs on the operator of all
 // potential-grid nodes and zeroes z0 on the electrode nodes of the open top,
 // a projection that keeps the preconditioner symmetric on the unknowns.  The
 // last sweep also writes the tiles' r0 . z0 to part[lid * pstride + poff].
@@ -808,11 +811,11 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
     return launch_mg_fine<T>(D[0], c->tm_f, tb, gen, Dv(0), mode, omega, x, r0, out, sc, pp, pstride, poff, st);
   };
   const Dims& d0 = D[0];
+  const double om0 = h.levels[0].omega;
   T* v0 = V(L.v0);
   T* t0 = V(L.t0);
-  hipError_t e = run([&] { return launch_mg_scale<T>(d0, nc, Dv(0), h.levels[0].omega, r0, v0, sc, st); });
   auto run0 = [&](auto&& fn) { return timed(c, f == 0 ? PF_KC_MG_PHI0 : PF_KC_MG_U0, f, k, fn); };
-  if (e == hipSuccess) e = run0([&] { return fine(kMgResidual, 0.0, v0, t0, nullptr); });
+  hipError_t e = run0([&] { return fine(kMgFirst, om0, nullptr, t0, nullptr); });
   if (e == hipSuccess)
     e = run([&] {
       return launch_mg_restrict<T>(d0, D[1], nc, h.levels[1].cx, h.levels[1].cy, Zm(1), Zf(1), t0, V(L.b[1]), sc,
@@ -862,7 +865,7 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
     const double* tab = at<double>(c, L.tab[l]);
     e = run([&] {
       return launch_mg_prolong<T>(d, D[l + 1], nc, h.levels[l + 1].cx, h.levels[l + 1].cy, Zm(l + 1), V(L.o[l + 1]),
-                                  V(L.v[l]), sc, 0, top, top, st);
+                                  V(L.v[l]), sc, 0, top, top, nullptr, nullptr, 0.0, st);
     });
     if (e == hipSuccess)
       e = run([&] {
@@ -873,9 +876,9 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   if (e == hipSuccess)
     e = run([&] {
       return launch_mg_prolong<T>(d0, D[1], nc, h.levels[1].cx, h.levels[1].cy, Zm(1), V(L.o[1]), v0, sc, zoff0, 0,
-                                  top, st);
+                                  top, r0, Dv(0), om0, st);
     });
-  if (e == hipSuccess) e = run0([&] { return fine(kMgSweep, h.levels[0].omega, v0, z0, part); });
+  if (e == hipSuccess) e = run0([&] { return fine(kMgSweep, om0, v0, z0, part); });
   return e;
 }
 

@@ -101,7 +101,11 @@ struct Material {
 enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2, kRedOuter = 3, kRedSum = 4, kRedRho = 5 };
 
 // Multigrid hierarchy of the FEM operator (built on the host, pf_mg.cpp).
-enum { kMgResidual = 0, kMgSweep = 1 };  // level kernel: out = b - A x, or one damped Jacobi sweep
+// Level kernels: out = b - A x (kMgResidual), one damped Jacobi sweep
+// out = x + omega D^-1 (b - A x) (kMgSweep), or (solver-grid kernels only)
+// the residual of the first sweep from zero, out = b - A (omega D^-1 b), with
+// x not read (kMgFirst).
+enum { kMgResidual = 0, kMgSweep = 1, kMgFirst = 2 };
 constexpr int kMgMaxLevels = 12;
 constexpr int64_t kMgDenseMax = 512;  // coarsest level solved by a dense inverse up to this many unknowns
 

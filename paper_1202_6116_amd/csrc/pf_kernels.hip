@@ -1152,10 +1152,11 @@ __device__ __forceinline__ void block_sum_to(double v, double* dst) {
   }
 }
 
-// Fine level: out = b - K x (kMgResidual) or out = x + omega D^-1 (b - K x)
-// (kMgSweep); with partials, the tile's sum of b . out goes to
-// partials[lid * pstride + poff].
-template <typename T, bool GEN>
+// Fine level: out = b - K x (kMgResidual), out = x + omega D^-1 (b - K x)
+// (kMgSweep) or out = b - K (omega D^-1 b) (kMgFirst); with partials, the
+// tile's sum of b . out goes to partials[lid * pstride + poff].  D^-1 of the
+// fine level is the Jacobi weight of the FEM tables (interior or top row).
+template <typename T, bool GEN, bool FIRST>
 __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
                                                            const double* __restrict__ dinv, int mode, double omega,
                                                            const T* __restrict__ x, const T* __restrict__ b,
@@ -1172,8 +1173,15 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
   const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
   auto fetch = [&](int64_t m, int k, T* raw) {
     if (k == 0) return;
+    if (FIRST) {
+      // omega D^-1 b: the Jacobi weight of the row kind (interior or top), per component
+      const int zt = k == d.nz - 1 ? 1 : 0;
 #pragma unroll
-    for (int c = 0; c < 3; c++) raw[c] = x[c * N + m];
+      for (int c = 0; c < 3; c++) raw[c] = (T)(omega * tb->inv_diag[zt][c]) * b[c * N + m];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; c++) raw[c] = x[c * N + m];
+    }
   };
   auto comb = [&](int, const T* raw, T* o) {
 #pragma unroll
@@ -1217,7 +1225,7 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
 #pragma unroll
       for (int c = 0; c < 3; c++) {
         const T r = cv[c] - q[c];
-        const T o = mode == kMgResidual ? r : ring[s0][c][ly + 1][lx + 1] + (T)(omega * dinv[3 * k + c]) * r;
+        const T o = mode != kMgSweep ? r : ring[s0][c][ly + 1][lx + 1] + (T)(omega * dinv[3 * k + c]) * r;
         out[c * N + n] = o;
         acc += (double)cv[c] * (double)o;
       }
@@ -1346,13 +1354,17 @@ __global__ __launch_bounds__(kThreads) void mg_restrict_kernel(Dims df, Dims dc,
   for (int c = 0; c < NC; c++) bc[c * dc.N + nc] = (T)acc[c];
 }
 
-// Prolongation and correction: xf += P xc.  One thread per stored fine node
+// Prolongation and correction: xf += P xc, or, with bf, xf = omega D^-1 bf
+// + P xc (the first sweep from zero, which the kMgFirst residual kernels
+// never stored, plus the correction).  One thread per stored fine node
 // (plane index + zoff in the z map); fixed planes are skipped.
 template <typename T, int NC>
 __global__ __launch_bounds__(kThreads) void mg_prolong_kernel(Dims df, Dims dc, int cx, int cy,
                                                               const MgZ* __restrict__ zmap, const T* __restrict__ xc,
                                                               T* __restrict__ xf, const CgScalars* sc, int zoff,
-                                                              int ftop_fixed, int ctop_fixed) {
+                                                              int ftop_fixed, int ctop_fixed,
+                                                              const T* __restrict__ bf,
+                                                              const double* __restrict__ dinv, double omega) {
   if (sc->done) return;
   const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
   const int kf = k + zoff;
@@ -1378,7 +1390,10 @@ __global__ __launch_bounds__(kThreads) void mg_prolong_kernel(Dims df, Dims dc, 
   }
   const int64_t n = i + (int64_t)df.nx * j + df.plane * k;
 #pragma unroll
-  for (int c = 0; c < NC; c++) xf[c * df.N + n] = (T)((double)xf[c * df.N + n] + acc[c]);
+  for (int c = 0; c < NC; c++) {
+    const double base = bf ? omega * dinv[NC * k + c] * (double)bf[c * df.N + n] : (double)xf[c * df.N + n];
+    xf[c * df.N + n] = (T)(base + acc[c]);
+  }
 }
 
 // Coarsest level: x = M b over the unknowns (n / NC per component, planes 1
@@ -1400,13 +1415,13 @@ __global__ __launch_bounds__(256) void mg_dense_kernel(Dims d, int n, const doub
   if (threadIdx.x == 0) x[vec(row)] = (T)(red[0] + red[1] + red[2] + red[3]);
 }
 
-// Poisson fine level (the potential grid, tiled like the CG kernels): out =
-// b - A x or out = x + omega D^-1 (b - A x) with the operator of every
-// stored plane counted (the electrode rows of the open top included); with
+// Poisson fine level (the potential grid, tiled like the CG kernels), the
+// modes of the FEM fine level, with the operator of every stored plane
+// counted (the electrode rows of the open top included); with
 // emask the output is zeroed on the electrode nodes (the preconditioner of
 // the reduced system), and with partials the tile's b . out goes to
 // partials[lid * pstride + poff].
-template <typename T>
+template <typename T, bool FIRST>
 __global__ __launch_bounds__(kThreads) void mgp_fine_kernel(Dims d, TileMap tm, Coefs<T> cf,
                                                             const double* __restrict__ dinv, int mode, double omega,
                                                             const T* __restrict__ x, const T* __restrict__ b,
@@ -1422,7 +1437,7 @@ __global__ __launch_bounds__(kThreads) void mgp_fine_kernel(Dims d, TileMap tm, 
   const int i = tc.i0 + lx, j = tc.j0 + ly;
   const bool valid = i < d.nx && j < d.ny;
   const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
-  auto fetch = [&](int64_t m, int, T* raw) { raw[0] = x[m]; };
+  auto fetch = [&](int64_t m, int k, T* raw) { raw[0] = FIRST ? (T)(omega * dinv[k]) * b[m] : x[m]; };
   auto comb = [&](int, const T* raw, T* o) { o[0] = raw[0]; };
   Stage<T, 1, Halo<TY>::NPT> st;
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
@@ -1451,7 +1466,7 @@ __global__ __launch_bounds__(kThreads) void mgp_fine_kernel(Dims d, TileMap tm, 
         q = e.xy * (4 * pc - sxy) + e.up * (pc - pup) + e.dn * (pc - pdn);
       }
       const T r = cb - q;
-      T o = mode == kMgResidual ? r : pc + (T)(omega * dinv[k]) * r;
+      T o = mode != kMgSweep ? r : pc + (T)(omega * dinv[k]) * r;
       if (emask != nullptr && k == d.nzf && emask[col] != 0) o = 0;
       out[col + d.plane * k] = o;
       acc += (double)cb * (double)o;
@@ -2193,12 +2208,18 @@ template <typename T>
 hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const double* dinv, int mode,
                           double omega, const T* x, const T* b, T* out, const CgScalars* sc, double* partials,
                           int pstride, int poff, hipStream_t s) {
-  if (gen)
-    mg_fine_kernel<T, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, dinv, mode, omega, x, b, out, sc, partials,
-                                                              pstride, poff);
-  else
-    mg_fine_kernel<T, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, dinv, mode, omega, x, b, out, sc, partials,
-                                                               pstride, poff);
+#define PF_MG_FINE(GEN, FIRST)                                                                              \
+  mg_fine_kernel<T, GEN, FIRST><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, dinv, mode, omega, x, b, out, sc, \
+                                                                    partials, pstride, poff)
+  const bool first = mode == kMgFirst;
+  if (gen) {
+    if (first) PF_MG_FINE(true, true);
+    else PF_MG_FINE(true, false);
+  } else {
+    if (first) PF_MG_FINE(false, true);
+    else PF_MG_FINE(false, false);
+  }
+#undef PF_MG_FINE
   return hipGetLastError();
 }
 
@@ -2235,13 +2256,14 @@ hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int nc, int cx, in
 
 template <typename T>
 hipError_t launch_mg_prolong(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap, const T* xc,
-                             T* xf, const CgScalars* sc, int zoff, int ftop_fixed, int ctop_fixed, hipStream_t s) {
+                             T* xf, const CgScalars* sc, int zoff, int ftop_fixed, int ctop_fixed, const T* bf,
+                             const double* dinv, double omega, hipStream_t s) {
   if (nc == 3)
     mg_prolong_kernel<T, 3><<<node_grid(df), node_block(), 0, s>>>(df, dc, cx, cy, zmap, xc, xf, sc, zoff, ftop_fixed,
-                                                                    ctop_fixed);
+                                                                    ctop_fixed, bf, dinv, omega);
   else
     mg_prolong_kernel<T, 1><<<node_grid(df), node_block(), 0, s>>>(df, dc, cx, cy, zmap, xc, xf, sc, zoff, ftop_fixed,
-                                                                    ctop_fixed);
+                                                                    ctop_fixed, bf, dinv, omega);
   return hipGetLastError();
 }
 
@@ -2257,8 +2279,12 @@ template <typename T>
 hipError_t launch_mgp_fine(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const double* dinv, int mode,
                            double omega, const T* x, const T* b, T* out, const uint8_t* emask, const CgScalars* sc,
                            double* partials, int pstride, int poff, hipStream_t s) {
-  mgp_fine_kernel<T><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, dinv, mode, omega, x, b, out, emask, sc, partials,
-                                                         pstride, poff);
+  if (mode == kMgFirst)
+    mgp_fine_kernel<T, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, dinv, mode, omega, x, b, out, emask, sc,
+                                                               partials, pstride, poff);
+  else
+    mgp_fine_kernel<T, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, dinv, mode, omega, x, b, out, emask, sc,
+                                                                partials, pstride, poff);
   return hipGetLastError();
 }
 
@@ -2364,7 +2390,8 @@ PF_INSTANTIATE(float)
   template hipError_t launch_mg_restrict<T>(const Dims&, const Dims&, int, int, int, const MgZ*, const int*,      \
                                             const T*, T*, const CgScalars*, int, int, int, hipStream_t);          \
   template hipError_t launch_mg_prolong<T>(const Dims&, const Dims&, int, int, int, const MgZ*, const T*, T*,     \
-                                           const CgScalars*, int, int, int, hipStream_t);                         \
+                                           const CgScalars*, int, int, int, const T*, const double*, double,      \
+                                           hipStream_t);                                                          \
   template hipError_t launch_mg_dense<T>(const Dims&, int, int, const double*, const T*, T*, const CgScalars*,    \
                                          hipStream_t);                                                            \
   template hipError_t launch_mgp_fine<T>(const Dims&, const TileMap&, const Coefs<T>&, const double*, int,        \
