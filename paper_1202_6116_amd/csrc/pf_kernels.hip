@@ -32,6 +32,17 @@ __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >=
 
 __device__ __forceinline__ int tid_flat() { return threadIdx.x + threadIdx.y * blockDim.x; }
 
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -1396,6 +1407,145 @@ __global__ __launch_bounds__(kThreads) void mg_prolong_kernel(Dims df, Dims dc, 
   }
 }
 
+// The transfers between a level and the next when both x and y are halved
+// (the common case; the kernels above handle the others).
+//
+// Restriction by coarse columns: thread (I, J) owns KC coarse planes of one
+// z-chunk and visits each contributing fine plane once, summing its 3 x 3
+// in-plane footprint (weights 1/2, 1, 1/2 per axis) and pushing it into the
+// planes the z map sends it to.  Large planes take KC = 4 (fewer re-reads of
+// the fine planes shared by neighbouring coarse planes), small ones KC = 1
+// (more threads).
+template <typename T, int NC, int KC>
+__global__ __launch_bounds__(kThreads) void mg_restrict2_kernel(Dims df, Dims dc, const MgZ* __restrict__ zmap,
+                                                                const int* __restrict__ zfine,
+                                                                const T* __restrict__ rf, T* __restrict__ bc,
+                                                                const CgScalars* sc, int zoff, int fnz,
+                                                                int ctop_fixed) {
+  if (sc->done) return;
+  const int I = blockIdx.x * kBX + threadIdx.x, J = blockIdx.y * kBY + threadIdx.y;
+  if (I >= dc.nx || J >= dc.ny) return;
+  const int K0 = blockIdx.z * KC;
+  const int Ktop = dc.nz - (ctop_fixed ? 1 : 0);  // coarse planes [1, Ktop) hold unknowns
+  const int Ka = max(K0, 1), Kb = min(K0 + KC, Ktop);
+  if (Ka >= Kb) return;
+  double acc[KC][NC];
+#pragma unroll
+  for (int q = 0; q < KC; q++)
+#pragma unroll
+    for (int c = 0; c < NC; c++) acc[q][c] = 0.0;
+  int fx[3], fy[3];
+#pragma unroll
+  for (int t = 0; t < 3; t++) {
+    fx[t] = wrap(2 * I + t - 1, df.nx);
+    fy[t] = wrap(2 * J + t - 1, df.ny);
+  }
+  const double w1[3] = {0.5, 1.0, 0.5};
+  const int kf0 = max(zfine[Ka] - 1, 1), kf1 = min(zfine[Kb - 1] + 1, fnz - 1);
+  for (int kf = kf0; kf <= kf1; kf++) {
+    const int ks = kf - zoff;
+    if (ks < 0 || ks >= df.nz) continue;
+    const MgZ z = zmap[kf];
+    double s[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) s[c] = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        const double w = w1[a] * w1[b];
+        const int64_t m = fx[a] + (int64_t)df.nx * fy[b] + df.plane * ks;
+#pragma unroll
+        for (int c = 0; c < NC; c++) s[c] += w * (double)rf[c * df.N + m];
+      }
+#pragma unroll
+    for (int q = 0; q < KC; q++) {
+      const int K = K0 + q;
+      double wz = 0.0;
+      if (z.lo == K) wz += z.wlo;
+      if (z.hi == K && z.hi != z.lo) wz += z.whi;
+#pragma unroll
+      for (int c = 0; c < NC; c++) acc[q][c] += wz * s[c];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KC; q++) {
+    const int K = K0 + q;
+    if (K < Ka || K >= Kb) continue;
+    const int64_t n = I + (int64_t)dc.nx * J + dc.plane * K;
+#pragma unroll
+    for (int c = 0; c < NC; c++) bc[c * dc.N + n] = (T)acc[q][c];
+  }
+}
+
+// Prolongation by coarse footprints: thread (I, J) of fine plane k forms the
+// z-interpolated coarse values at (I, J), (I+1, J), (I, J+1), (I+1, J+1) once
+// and writes the four fine nodes (2I, 2J) .. (2I+1, 2J+1); the modes of
+// mg_prolong_kernel.
+template <typename T, int NC>
+__global__ __launch_bounds__(kThreads) void mg_prolong2_kernel(Dims df, Dims dc, const MgZ* __restrict__ zmap,
+                                                               const T* __restrict__ xc, T* __restrict__ xf,
+                                                               const CgScalars* sc, int zoff, int ftop_fixed,
+                                                               int ctop_fixed, const T* __restrict__ bf,
+                                                               const double* __restrict__ dinv, double omega) {
+  if (sc->done) return;
+  const int I = blockIdx.x * kBX + threadIdx.x, J = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
+  const int kf = k + zoff;
+  if (I >= dc.nx || J >= dc.ny || kf == 0 || (ftop_fixed && k == df.nz - 1)) return;
+  const MgZ z = zmap[kf];
+  const int zi[2] = {z.lo, z.hi};
+  const double zw[2] = {z.wlo, z.whi};
+  const int I1 = I + 1 == dc.nx ? 0 : I + 1, J1 = J + 1 == dc.ny ? 0 : J + 1;
+  double e[2][2][NC];
+#pragma unroll
+  for (int b = 0; b < 2; b++)
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int c = 0; c < NC; c++) e[b][a][c] = 0.0;
+  for (int t = 0; t < 2; t++) {
+    if (zw[t] == 0.0 || zi[t] == 0 || (ctop_fixed && zi[t] == dc.nz - 1)) continue;
+    const int64_t base = dc.plane * zi[t];
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int a = 0; a < 2; a++) {
+        const int64_t m = (a ? I1 : I) + (int64_t)dc.nx * (b ? J1 : J) + base;
+#pragma unroll
+        for (int c = 0; c < NC; c++) e[b][a][c] += zw[t] * (double)xc[c * dc.N + m];
+      }
+  }
+  // the fine pair (2I, 2I + 1) of a row is one 2-vector (fine nx is even)
+  using T2 = typename Vec2<T>::type;
+#pragma unroll
+  for (int b = 0; b < 2; b++) {
+    const int64_t n = 2 * I + (int64_t)df.nx * (2 * J + b) + df.plane * k;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      // bilinear weights of the fine nodes (2I, 2J + b) and (2I + 1, 2J + b)
+      const double v0 = b ? 0.5 * (e[0][0][c] + e[1][0][c]) : e[0][0][c];
+      const double v1 = b ? 0.25 * (e[0][0][c] + e[0][1][c] + e[1][0][c] + e[1][1][c])
+                          : 0.5 * (e[0][0][c] + e[0][1][c]);
+      T2* dst = reinterpret_cast<T2*>(xf + c * df.N + n);
+      double b0, b1;
+      if (bf) {
+        const T2 bv = *reinterpret_cast<const T2*>(bf + c * df.N + n);
+        const double wgt = omega * dinv[NC * k + c];
+        b0 = wgt * (double)bv.x;
+        b1 = wgt * (double)bv.y;
+      } else {
+        const T2 xv = *dst;
+        b0 = (double)xv.x;
+        b1 = (double)xv.y;
+      }
+      T2 o;
+      o.x = (T)(b0 + v0);
+      o.y = (T)(b1 + v1);
+      *dst = o;
+    }
+  }
+}
+
 // Coarsest level: x = M b over the unknowns (n / NC per component, planes 1
 // upwards), M the dense inverse (row-major, n x n).  One block per row.
 template <typename T, int NC>
@@ -2245,6 +2395,22 @@ template <typename T>
 hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap,
                               const int* zfine, const T* rf, T* bc, const CgScalars* sc, int zoff, int fnz,
                               int ctop_fixed, hipStream_t s) {
+  if (cx && cy && df.nx == 2 * dc.nx && df.ny == 2 * dc.ny) {
+    const bool wide = dc.plane >= 16384;
+    const int kc = wide ? 4 : 1;
+    const dim3 g((dc.nx + kBX - 1) / kBX, (dc.ny + kBY - 1) / kBY, (dc.nz + kc - 1) / kc);
+#define PF_RESTRICT2(NC, KC) \
+  mg_restrict2_kernel<T, NC, KC><<<g, node_block(), 0, s>>>(df, dc, zmap, zfine, rf, bc, sc, zoff, fnz, ctop_fixed)
+    if (nc == 3) {
+      if (wide) PF_RESTRICT2(3, 4);
+      else PF_RESTRICT2(3, 1);
+    } else {
+      if (wide) PF_RESTRICT2(1, 4);
+      else PF_RESTRICT2(1, 1);
+    }
+#undef PF_RESTRICT2
+    return hipGetLastError();
+  }
   if (nc == 3)
     mg_restrict_kernel<T, 3><<<node_grid(dc), node_block(), 0, s>>>(df, dc, cx, cy, zmap, zfine, rf, bc, sc, zoff,
                                                                      fnz, ctop_fixed);
@@ -2258,6 +2424,16 @@ template <typename T>
 hipError_t launch_mg_prolong(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap, const T* xc,
                              T* xf, const CgScalars* sc, int zoff, int ftop_fixed, int ctop_fixed, const T* bf,
                              const double* dinv, double omega, hipStream_t s) {
+  if (cx && cy && df.nx == 2 * dc.nx && df.ny == 2 * dc.ny && dc.plane >= 16384) {
+    const dim3 g((dc.nx + kBX - 1) / kBX, (dc.ny + kBY - 1) / kBY, df.nz);
+    if (nc == 3)
+      mg_prolong2_kernel<T, 3><<<g, node_block(), 0, s>>>(df, dc, zmap, xc, xf, sc, zoff, ftop_fixed, ctop_fixed, bf,
+                                                          dinv, omega);
+    else
+      mg_prolong2_kernel<T, 1><<<g, node_block(), 0, s>>>(df, dc, zmap, xc, xf, sc, zoff, ftop_fixed, ctop_fixed, bf,
+                                                          dinv, omega);
+    return hipGetLastError();
+  }
   if (nc == 3)
     mg_prolong_kernel<T, 3><<<node_grid(df), node_block(), 0, s>>>(df, dc, cx, cy, zmap, xc, xf, sc, zoff, ftop_fixed,
                                                                     ctop_fixed, bf, dinv, omega);
