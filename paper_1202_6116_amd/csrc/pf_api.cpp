@@ -336,6 +336,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct MgLayout {
   size_t z = 0, v0 = 0, t0 = 0;
   std::vector<size_t> b, v, t, o, dinv, tab, zmap, zfine;
+  std::vector<size_t> tabw;    // coarser levels: the stencils times omega D^-1 (the first sweep folded in)
   size_t dense = 0, dense_n = 0;  // the dense inverse and its order
   size_t first = 0, end = 0;   // the range of all multigrid vectors (cleared at init)
 };
@@ -427,6 +428,7 @@ Layout make_layout(const pf_config& c, int npartials) {
     for (size_t l = 0; l < mg.size(); l++) {
       M.dinv.push_back(take((size_t)mg[l].nz * nc * 8));
       M.tab.push_back(l > 0 ? take((size_t)mg[l].nz * nc * nc * 27 * 8) : 0);
+      M.tabw.push_back(l > 0 ? take((size_t)mg[l].nz * nc * nc * 27 * 8) : 0);
       M.zmap.push_back(l > 0 ? take((size_t)mg[l - 1].nz * sizeof(MgZ)) : 0);
       M.zfine.push_back(l > 0 ? take((size_t)mg[l].nz * sizeof(int)) : 0);
     }
@@ -777,9 +779,11 @@ bool mg_on(const pf_ctx* c, int f) { return !c->mg[f].levels.empty(); }
 // One multigrid V-cycle z0 = M r0 of the Poisson (f = 0) or the FEM (f = 1)
 // operator (pre-smoothing: one damped Jacobi sweep from zero; residual,
 // restriction, the coarser levels, prolongation; post-smoothing: one sweep),
-// symmetric, so CG may use it.  On the solver grid the first sweep is never
-// stored: the residual kernel applies A to omega D^-1 b on the fly
-// (kMgFirst) and the prolongation forms omega D^-1 b + P e.  The Poisson cycle runs on the operator of all
+// symmetric, so CG may use it.  The first sweep is never stored: on the
+// solver grid the residual kernel applies A to omega D^-1 b on the fly
+// (kMgFirst), on the coarser levels it runs with the stencils of
+// A omega D^-1 (folded on the host), and the prolongation forms
+// omega D^-1 b + P e.  The Poisson cycle runs on the operator of all
 // potential-grid nodes and zeroes z0 on the electrode nodes of the open top,
 // a projection that keeps the preconditioner symmetric on the unknowns.  The
 // last sweep also writes the tiles' r0 . z0 to part[lid * pstride + poff].
@@ -823,13 +827,11 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
     });
   for (int l = 1; l < nl - 1 && e == hipSuccess; l++) {
     const Dims& d = D[l];
-    const double* tab = at<double>(c, L.tab[l]);
-    e = run([&] { return launch_mg_scale<T>(d, nc, Dv(l), h.levels[l].omega, V(L.b[l]), V(L.v[l]), sc, st); });
-    if (e == hipSuccess)
-      e = run([&] {
-        return launch_mg_level<T>(d, nc, tab, Dv(l), kMgResidual, 0.0, V(L.v[l]), V(L.b[l]), V(L.t[l]), sc, top,
-                                  st);
-      });
+    // residual of the first sweep: b - (A omega D^-1) b with the folded stencils
+    const double* tabw = at<double>(c, L.tabw[l]);
+    e = run([&] {
+      return launch_mg_level<T>(d, nc, tabw, Dv(l), kMgResidual, 0.0, V(L.b[l]), V(L.b[l]), V(L.t[l]), sc, top, st);
+    });
     if (e == hipSuccess)
       e = run([&] {
         return launch_mg_restrict<T>(d, D[l + 1], nc, h.levels[l + 1].cx, h.levels[l + 1].cy, Zm(l + 1), Zf(l + 1),
@@ -865,7 +867,7 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
     const double* tab = at<double>(c, L.tab[l]);
     e = run([&] {
       return launch_mg_prolong<T>(d, D[l + 1], nc, h.levels[l + 1].cx, h.levels[l + 1].cy, Zm(l + 1), V(L.o[l + 1]),
-                                  V(L.v[l]), sc, 0, top, top, nullptr, nullptr, 0.0, st);
+                                  V(L.v[l]), sc, 0, top, top, V(L.b[l]), Dv(l), h.levels[l].omega, st);
     });
     if (e == hipSuccess)
       e = run([&] {
@@ -1199,6 +1201,7 @@ pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt
 pf_status upload_mg(pf_ctx* c, int f, const FemTables& tb) {
   c->mg[f] = f == 0 ? build_mg_phi(c->cfg) : build_mg(c->cfg, tb);
   MgHierarchy& h = c->mg[f];
+  h.tables_w.clear();
   const MgLayout& L = c->lay.mg[f];
   if (h.levels.size() != L.dinv.size()) return fail(c, PF_EINVAL, "multigrid plan changed between layout and init");
   std::vector<Dims>& D = c->mg_dims[f];
@@ -1218,6 +1221,21 @@ pf_status upload_mg(pf_ctx* c, int f, const FemTables& tb) {
         return fail(c, PF_EINVAL, "multigrid: level %zu tables do not match its grid", l);
       PF_HIP(c, hipMemcpyAsync(c->ws + L.tab[l], h.tables[l].data(), h.tables[l].size() * 8, hipMemcpyHostToDevice,
                                c->stream));
+      // A omega D^-1: column (plane k + dz, component e) scaled by omega / diag
+      std::vector<double> tw(h.tables[l].size(), 0.0);
+      const int nc = h.nc;
+      for (int k = 0; k < m.nz; k++)
+        for (int cc = 0; cc < nc; cc++)
+          for (int e = 0; e < nc; e++)
+            for (int o = 0; o < 27; o++) {
+              const int kk = k + o / 9 - 1;
+              if (kk < 0 || kk >= m.nz) continue;
+              const size_t at_ = (((size_t)k * nc + cc) * nc + e) * 27 + o;
+              tw[at_] = h.tables[l][at_] * m.omega * m.dinv[(size_t)kk * nc + e];
+            }
+      h.tables_w.push_back(std::move(tw));
+      PF_HIP(c, hipMemcpyAsync(c->ws + L.tabw[l], h.tables_w.back().data(), h.tables_w.back().size() * 8,
+                               hipMemcpyHostToDevice, c->stream));
       PF_HIP(c, hipMemcpyAsync(c->ws + L.zmap[l], h.zmaps[l].data(), h.zmaps[l].size() * sizeof(MgZ),
                                hipMemcpyHostToDevice, c->stream));
       PF_HIP(c, hipMemcpyAsync(c->ws + L.zfine[l], h.zfine[l].data(), h.zfine[l].size() * sizeof(int),

@@ -128,6 +128,7 @@ struct MgHierarchy {
   bool top_fixed;                             // the top plane of every level is fixed (metal top)
   std::vector<MgLevel> levels;                // 0 = the solver's grid
   std::vector<std::vector<double>> tables;    // nz x nc x nc x 27 stencils (level 0: the operator itself)
+  std::vector<std::vector<double>> tables_w;  // level >= 1 (from index 0 up): stencils times omega D^-1
   std::vector<std::vector<MgZ>> zmaps;        // level >= 1: per plane of the finer level
   std::vector<std::vector<int>> zfine;        // level >= 1: finer-level plane of each plane
   int dense_n;                                // coarsest: unknowns of the dense inverse (0: none)
