@@ -12,8 +12,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
 #include <functional>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pf_internal.h"
@@ -368,7 +372,10 @@ std::vector<MgLevel> mg_levels_for(const pf_config& c, int field) {
   return lv;
 }
 
-constexpr int kNumScalars = 4;
+// Scalar slots: 0 Poisson CG, 1 FEM CG, 2 sums (energy, adjoint); partial
+// slots likewise, plus 3 and 4 for the multigrid setups of the FEM and the
+// Poisson solve (which may run at the same time).
+constexpr int kNumScalars = 5;
 constexpr int kPartialsPerBlock = 4;
 constexpr int kResultSlots = 128;
 
@@ -483,13 +490,28 @@ struct pf_ctx {
   pf::Layout lay;
   char* ws;
   size_t ws_bytes;
-  hipStream_t stream;
+  hipStream_t stream;        // the caller's stream
+  // The FEM solve of a step runs on a worker thread with a stream of its
+  // own, concurrently with the Poisson solve (forked from and joined back
+  // into the caller's stream by events).
+  int device;
+  hipStream_t stream2;
+  hipEvent_t ev_fork, ev_join;
+  struct Worker {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::function<void()> job;
+    bool busy = false, quit = false;
+  };
+  std::unique_ptr<Worker> worker;
+  std::mutex err_mu;
   int nblocks;              // node-kernel blocks (film grid)
   int nblocks_p;            // node-kernel blocks (potential grid)
   pf::TileMap tm_p;         // tiles of the Poisson iteration kernels (64 x 4)
   pf::TileMap tm_f;         // tiles of the FEM iteration kernels (64 x 4)
   int npartials;            // partial slots per solver (max of both block counts)
-  pf::CgScalars* host_sc;   // pinned read-back buffer
+  pf::CgScalars* host_sc;   // pinned read-back buffers, one per scalar slot
   double* host_res;         // pinned read-back of reduction results
   std::string err;
   bool have_state;
@@ -515,6 +537,11 @@ struct pf_ctx {
 namespace pf {
 namespace {
 
+// The stream the calling host thread enqueues on: the caller's stream, or
+// the context's second stream on its worker thread.
+thread_local hipStream_t tl_stream = nullptr;
+inline hipStream_t strm(const pf_ctx* c) { return tl_stream ? tl_stream : c->stream; }
+
 template <typename T>
 T* at(pf_ctx* c, size_t off) {
   return reinterpret_cast<T*>(c->ws + off);
@@ -532,9 +559,44 @@ pf_status fail(pf_ctx* c, pf_status s, const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
+    std::lock_guard<std::mutex> g(c->err_mu);
     c->err = buf;
   }
   return s;
+}
+
+// The worker thread: runs one posted job at a time on the context's second
+// stream (its device made current first).
+void worker_main(pf_ctx* c) {
+  (void)hipSetDevice(c->device);
+  tl_stream = c->stream2;
+  pf_ctx::Worker& w = *c->worker;
+  std::unique_lock<std::mutex> lk(w.mu);
+  for (;;) {
+    w.cv.wait(lk, [&] { return w.quit || static_cast<bool>(w.job); });
+    if (w.quit) return;
+    std::function<void()> job = std::move(w.job);
+    w.job = nullptr;
+    lk.unlock();
+    job();
+    lk.lock();
+    w.busy = false;
+    w.cv.notify_all();
+  }
+}
+
+void worker_post(pf_ctx* c, std::function<void()> job) {
+  pf_ctx::Worker& w = *c->worker;
+  std::lock_guard<std::mutex> g(w.mu);
+  w.job = std::move(job);
+  w.busy = true;
+  w.cv.notify_all();
+}
+
+void worker_wait(pf_ctx* c) {
+  pf_ctx::Worker& w = *c->worker;
+  std::unique_lock<std::mutex> lk(w.mu);
+  w.cv.wait(lk, [&] { return !w.busy; });
 }
 
 #define PF_HIP(ctx, ...)                                                                         \
@@ -677,11 +739,11 @@ hipError_t timed(pf_ctx* c, int cls, int solver, int k, F&& launch) {
     if (err != hipSuccess) return err;
     c->events.push_back(e);
   }
-  hipError_t err = hipEventRecord(c->events[2 * slot], c->stream);
+  hipError_t err = hipEventRecord(c->events[2 * slot], strm(c));
   if (err != hipSuccess) return err;
   err = launch();
   if (err != hipSuccess) return err;
-  err = hipEventRecord(c->events[2 * slot + 1], c->stream);
+  err = hipEventRecord(c->events[2 * slot + 1], strm(c));
   if (err != hipSuccess) return err;
   c->pending.push_back({cls, slot, solver, k});
   return hipSuccess;
@@ -703,15 +765,15 @@ void collect_timing(pf_ctx* c, int solver, int iters) {
 }
 
 pf_status read_scalars(pf_ctx* c, int which, CgScalars* out) {
-  PF_HIP(c, hipMemcpyAsync(c->host_sc, dev_sc(c, which), sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
-  PF_HIP(c, hipStreamSynchronize(c->stream));
-  *out = *c->host_sc;
+  PF_HIP(c, hipMemcpyAsync(c->host_sc + which, dev_sc(c, which), sizeof(CgScalars), hipMemcpyDeviceToHost, strm(c)));
+  PF_HIP(c, hipStreamSynchronize(strm(c)));
+  *out = c->host_sc[which];
   if (c->timing) collect_timing(c, which, out->iter);
   return PF_OK;
 }
 
 pf_status sync(pf_ctx* c) {
-  PF_HIP(c, hipStreamSynchronize(c->stream));
+  PF_HIP(c, hipStreamSynchronize(strm(c)));
   if (c->timing) collect_timing(c, -1, 0);
   return PF_OK;
 }
@@ -720,7 +782,7 @@ hipError_t reduce(pf_ctx* c, const double* part, int nb, int nv, int which, int 
                   double* out, int solver = -1, int k = -1) {
   const int maxit = c->cfg.maxit;
   return timed(c, PF_KC_REDUCE, solver, k, [&] {
-    return launch_cg_reduce(part, nb, nv, dev_sc(c, which), mode, tol, maxit, c->stream, tol2, out);
+    return launch_cg_reduce(part, nb, nv, dev_sc(c, which), mode, tol, maxit, strm(c), tol2, out);
   });
 }
 
@@ -758,7 +820,7 @@ pf_status run_cg(pf_ctx* c, int which, int predicted, T* x, T* const pbuf[2], in
   }
   if (h.done != kNonFinite)
     PF_HIP(c, timed(c, PF_KC_FINISH, -1, -1,
-                    [&] { return launch_cg_finish<T>(x, pbuf[h.iter & 1], n, dev_sc(c, which), c->stream); }));
+                    [&] { return launch_cg_finish<T>(x, pbuf[h.iter & 1], n, dev_sc(c, which), strm(c)); }));
   *hout = h;
   if (h.done == kNonFinite) return fail(c, PF_ENONFINITE, "%s: non-finite value in the CG reductions", what);
   return PF_OK;
@@ -800,7 +862,7 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   const FemTables* tb = at<FemTables>(c, c->lay.tables);
   const bool gen = !c->mat.cubic;
   const Coefs<T> cf = make_coefs<T>(c);
-  hipStream_t st = c->stream;
+  hipStream_t st = strm(c);
   auto V = [&](size_t off) { return at<T>(c, off); };
   auto Dv = [&](int l) { return at<double>(c, L.dinv[l]); };
   auto Zm = [&](int l) { return at<MgZ>(c, L.zmap[l]); };
@@ -888,7 +950,7 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
 template <typename T>
 hipError_t mg_setup(pf_ctx* c, int f, const T* r) {
   CgScalars* sc = dev_sc(c, f);
-  double* part = dev_partials(c, 3);
+  double* part = dev_partials(c, f == 0 ? 4 : 3);
   hipError_t e = mg_vcycle<T>(c, f, r, at<T>(c, c->lay.mg[f].z), sc, part, 1, 0, -1);
   const int nb = f == 0 ? c->tm_p.nblocks : c->tm_f.nblocks;
   if (e == hipSuccess) e = reduce(c, part, nb, 1, f, kRedRho, 0.0, 0.0, nullptr);
@@ -907,12 +969,12 @@ std::function<hipError_t(int)> poisson_iteration(pf_ctx* c, const Coefs<T>& cf, 
     T* z = mg ? at<T>(c, c->lay.mg[0].z) : nullptr;
     hipError_t e = timed(c, PF_KC_POISSON_A, 0, k, [&] {
       return launch_poisson_cg_a<T>(d, c->tm_p, cf, mg ? z : r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, mg ? 1 : 0,
-                                    c->stream);
+                                    strm(c));
     });
     if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 1, 0, kRedAlpha, tol, 0, nullptr, 0, k);
     if (e == hipSuccess)
       e = timed(c, PF_KC_POISSON_B, 0, k,
-                [&] { return launch_poisson_cg_b<T>(d, c->tm_p, cf, pb[(k + 1) & 1], r, em, sc, part, c->stream); });
+                [&] { return launch_poisson_cg_b<T>(d, c->tm_p, cf, pb[(k + 1) & 1], r, em, sc, part, strm(c)); });
     // multigrid: z = M r replaces the Jacobi-weighted r.z of kernel B
     if (e == hipSuccess && mg) e = mg_vcycle<T>(c, 0, r, z, sc, part, 2, 0, k);
     if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 2, 0, kRedBeta, tol, 0, nullptr, 0, k);
@@ -931,13 +993,13 @@ std::function<hipError_t(int)> fem_iteration(pf_ctx* c, T* r, T* const pb[2], T*
     T* z = mg ? at<T>(c, c->lay.mg[1].z) : nullptr;
     hipError_t e = timed(c, PF_KC_FEM_A, 1, k, [&] {
       return launch_fem_cg_a<T>(d, c->tm_f, tb, !c->mat.cubic, mg ? z : r, pb[k & 1], pb[(k + 1) & 1], x, sc, part,
-                                mg ? 1 : 0, c->stream);
+                                mg ? 1 : 0, strm(c));
     });
     if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 1, 1, kRedAlpha, tol, 0, nullptr, 1, k);
     if (e == hipSuccess)
       e = timed(c, PF_KC_FEM_B, 1, k,
                 [&] {
-                  return launch_fem_cg_b<T>(d, c->tm_f, tb, !c->mat.cubic, pb[(k + 1) & 1], r, sc, part, c->stream);
+                  return launch_fem_cg_b<T>(d, c->tm_f, tb, !c->mat.cubic, pb[(k + 1) & 1], r, sc, part, strm(c));
                 });
     // multigrid: z = M r replaces the Jacobi-weighted r.z of kernel B
     if (e == hipSuccess && mg) e = mg_vcycle<T>(c, 1, r, z, sc, part, 2, 0, k);
@@ -957,10 +1019,10 @@ pf_status solve_poisson64(pf_ctx* c, int pred, const S* P, const S* V, double cd
   double* part = dev_partials(c, 0);
   double* r = at<double>(c, c->lay.pr);
   double* const pb[2] = {at<double>(c, c->lay.pp[0]), at<double>(c, c->lay.pp[1])};
-  if (!warm) PF_HIP(c, launch_fill<double>(x, d.N, 0.0, c->stream));
+  if (!warm) PF_HIP(c, launch_fill<double>(x, d.N, 0.0, strm(c)));
   PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
     return launch_poisson_setup<double, S, double>(d, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, emask(c),
-                                                   x, r, pb[0], nullptr, part, c->stream);
+                                                   x, r, pb[0], nullptr, part, strm(c));
   }));
   PF_HIP(c, reduce(c, part, c->nblocks_p, 3, 0, kRedSetup, tol, 0, nullptr));
   if (mg_on(c, 0)) PF_HIP(c, mg_setup<double>(c, 0, r));
@@ -981,10 +1043,10 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
   double* part = dev_partials(c, 1);
   double* r = at<double>(c, c->lay.fr);
   double* const pb[2] = {at<double>(c, c->lay.fp[0]), at<double>(c, c->lay.fp[1])};
-  if (!warm) PF_HIP(c, launch_fill<double>(x, 3 * d.N, 0.0, c->stream));
+  if (!warm) PF_HIP(c, launch_fill<double>(x, 3 * d.N, 0.0, strm(c)));
   PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
     return launch_fem_setup<double, S, double>(d, c->tm_f, cf, tb, !c->mat.cubic, P, V, cdt, W, x, r, pb[0], pb[1], nullptr,
-                                               part, c->stream);
+                                               part, strm(c));
   }));
   PF_HIP(c, reduce(c, part, c->tm_f.nblocks, 3, 1, kRedSetup, tol, 0, nullptr));
   if (mg_on(c, 1)) PF_HIP(c, mg_setup<double>(c, 1, r));
@@ -1017,7 +1079,7 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
   float* dz = at<float>(c, fem ? c->lay.du : c->lay.dphi);
   const char* what = fem ? "FEM solve (refined)" : "Poisson solve (refined)";
   const int pred = fem ? kPredUIn : kPredPhiIn;
-  if (!warm) PF_HIP(c, launch_fill<double>(x64, n, 0.0, c->stream));
+  if (!warm) PF_HIP(c, launch_fill<double>(x64, n, 0.0, strm(c)));
   res->iters = 0;
   res->outer = 0;
   res->relres = 0;
@@ -1027,13 +1089,13 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
     if (fem) {
       PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
         return launch_fem_setup<double, float, float>(d, c->tm_f, cf64, tb, !c->mat.cubic, P, V, cdt, nullptr, x64, r, pb[0],
-                                                      pb[1], dz, part, c->stream);
+                                                      pb[1], dz, part, strm(c));
       }));
     } else {
       PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
         return launch_poisson_setup<double, float, float>(d, cf64, P, V, cdt, 1, 1, at<double>(c, c->lay.ghost64),
                                                           c->cfg.phi_bottom, emask(c), x64, r, pb[0], dz, part,
-                                                          c->stream);
+                                                          strm(c));
       }));
     }
     PF_HIP(c, reduce(c, part, setup_blocks, 3, which, kRedOuter, tol, kInnerTol, nullptr));
@@ -1043,12 +1105,12 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
     res->iters += h.iter;
     res->relres = h.outer_b2 > 0 ? std::sqrt(h.outer_r2 / h.outer_b2) : 0.0;
     if (h.outer_done) {
-      if (h.zero_rhs) PF_HIP(c, launch_fill<double>(x64, n, 0.0, c->stream));
-      PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_convert<double, float>(x64, x32, n, c->stream); }));
+      if (h.zero_rhs) PF_HIP(c, launch_fill<double>(x64, n, 0.0, strm(c)));
+      PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_convert<double, float>(x64, x32, n, strm(c)); }));
       return PF_OK;
     }
     if (h.iter > 0) c->pred[pred] = h.iter;
-    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_refine_update(x64, x32, dz, n, c->stream); }));
+    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_refine_update(x64, x32, dz, n, strm(c)); }));
     res->outer++;
     if (res->outer >= kMaxOuter) {
       return fail(c, PF_ENOCONV, "%s: %d refinement sweeps, relres %.3e", what, res->outer, res->relres);
@@ -1107,45 +1169,71 @@ pf_status extrapolate_state(pf_ctx* c) {
   if (cap == 0) return PF_OK;  // the previous solution is the guess
   if (c->cfg.terms & PF_TERM_ELEC)
     PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-      return launch_extrapolate(at<double>(c, c->lay.phi), ring[0], Np, c->stream);
+      return launch_extrapolate(at<double>(c, c->lay.phi), ring[0], Np, strm(c));
     }));
   if (c->cfg.terms & PF_TERM_ELAS)
     PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-      return launch_extrapolate(at<double>(c, c->lay.u), ring[1], 3 * N, c->stream);
+      return launch_extrapolate(at<double>(c, c->lay.u), ring[1], 3 * N, strm(c));
     }));
   c->hist_head = (c->hist_head + 1) % cap;
   if (c->hist_valid < cap) c->hist_valid++;
   return PF_OK;
 }
 
-// Solves phi and u of the state at Pp = P + cdt V (state precision).
+// Solves phi and u of the state at Pp = P + cdt V (state precision).  With
+// both fields and no per-launch timing the FEM solve runs on the worker's
+// stream concurrently with the Poisson solve on the caller's: the two touch
+// disjoint buffers and scalar slots, so the results do not depend on how
+// their kernels interleave.
 pf_status solve_nonlocal(pf_ctx* c, const void* P, const void* V, double cdt, bool warm, pf_step_stats* st) {
-  pf_status out = PF_OK;
   double* phi = at<double>(c, c->lay.phi);
   double* u = at<double>(c, c->lay.u);
-  if (c->cfg.terms & PF_TERM_ELEC) {
-    SolveResult r{};
-    pf_status s;
+  auto poisson = [&](SolveResult* r) -> pf_status {
     if (fp32(c))
-      s = solve_refined(c, false, static_cast<const float*>(P), static_cast<const float*>(V), cdt, phi,
-                        at<float>(c, c->lay.phi32), c->cfg.tol_phi, warm, &r);
-    else
-      s = solve_poisson64<double>(c, kPredPhi, static_cast<const double*>(P), static_cast<const double*>(V), cdt, 1,
-                                  1, at<double>(c, c->lay.ghost64), c->cfg.phi_bottom, phi, c->cfg.tol_phi, warm,
-                                  &r);
+      return solve_refined(c, false, static_cast<const float*>(P), static_cast<const float*>(V), cdt, phi,
+                           at<float>(c, c->lay.phi32), c->cfg.tol_phi, warm, r);
+    return solve_poisson64<double>(c, kPredPhi, static_cast<const double*>(P), static_cast<const double*>(V), cdt, 1,
+                                   1, at<double>(c, c->lay.ghost64), c->cfg.phi_bottom, phi, c->cfg.tol_phi, warm, r);
+  };
+  auto fem = [&](SolveResult* r) -> pf_status {
+    if (fp32(c))
+      return solve_refined(c, true, static_cast<const float*>(P), static_cast<const float*>(V), cdt, u,
+                           at<float>(c, c->lay.u32), c->cfg.tol_u, warm, r);
+    return solve_fem64<double>(c, kPredU, static_cast<const double*>(P), static_cast<const double*>(V), cdt, nullptr,
+                               u, c->cfg.tol_u, warm, r);
+  };
+  const bool elec = c->cfg.terms & PF_TERM_ELEC, elas = c->cfg.terms & PF_TERM_ELAS;
+  if (elec && elas && c->worker && !c->timing) {
+    PF_HIP(c, hipEventRecord(c->ev_fork, strm(c)));
+    SolveResult rf{};
+    pf_status sf = PF_OK;
+    worker_post(c, [&] {
+      const hipError_t e = hipStreamWaitEvent(c->stream2, c->ev_fork, 0);
+      sf = e == hipSuccess ? fem(&rf) : fail(c, PF_EHIP, "fork: %s", hipGetErrorString(e));
+      const hipError_t e2 = hipEventRecord(c->ev_join, c->stream2);
+      if (e2 != hipSuccess && !fatal(sf)) sf = fail(c, PF_EHIP, "join: %s", hipGetErrorString(e2));
+    });
+    SolveResult rp{};
+    const pf_status sp = poisson(&rp);
+    worker_wait(c);
+    PF_HIP(c, hipStreamWaitEvent(strm(c), c->ev_join, 0));
+    if (fatal(sp)) return sp;
+    if (fatal(sf)) return sf;
+    stats_add(st, 0, rp);
+    stats_add(st, 1, rf);
+    return worst(sp, sf);
+  }
+  pf_status out = PF_OK;
+  if (elec) {
+    SolveResult r{};
+    const pf_status s = poisson(&r);
     if (fatal(s)) return s;
     stats_add(st, 0, r);
     out = worst(out, s);
   }
-  if (c->cfg.terms & PF_TERM_ELAS) {
+  if (elas) {
     SolveResult r{};
-    pf_status s;
-    if (fp32(c))
-      s = solve_refined(c, true, static_cast<const float*>(P), static_cast<const float*>(V), cdt, u,
-                        at<float>(c, c->lay.u32), c->cfg.tol_u, warm, &r);
-    else
-      s = solve_fem64<double>(c, kPredU, static_cast<const double*>(P), static_cast<const double*>(V), cdt, nullptr,
-                              u, c->cfg.tol_u, warm, &r);
+    const pf_status s = fem(&r);
     if (fatal(s)) return s;
     stats_add(st, 1, r);
     out = worst(out, s);
@@ -1178,7 +1266,7 @@ pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt
     PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
       return launch_force<float>(c->dims, c->tm_f, cf, tb, static_cast<const float*>(P), static_cast<const float*>(V),
                                  (float)cdt, phi, at<float>(c, c->lay.ghost32), u, mode, ns, static_cast<float*>(Pn),
-                                 static_cast<float*>(Vn), static_cast<float*>(F), c->stream);
+                                 static_cast<float*>(Vn), static_cast<float*>(F), strm(c));
     }));
   } else {
     const Coefs<double> cf = make_coefs<double>(c);
@@ -1187,7 +1275,7 @@ pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt
     PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
       return launch_force<double>(c->dims, c->tm_f, cf, tb, static_cast<const double*>(P), static_cast<const double*>(V), cdt,
                                   phi, at<double>(c, c->lay.ghost64), u, mode, ns, static_cast<double*>(Pn),
-                                  static_cast<double*>(Vn), static_cast<double*>(F), c->stream);
+                                  static_cast<double*>(Vn), static_cast<double*>(F), strm(c));
     }));
   }
   return PF_OK;
@@ -1214,13 +1302,13 @@ pf_status upload_mg(pf_ctx* c, int f, const FemTables& tb) {
     const size_t skip = l == 0 && f == 0 ? (size_t)h.nc : 0;
     const size_t count = (size_t)D.back().nz * h.nc;
     if (skip + count > m.dinv.size()) return fail(c, PF_EINVAL, "multigrid: level %zu does not match its grid", l);
-    PF_HIP(c, hipMemcpyAsync(c->ws + L.dinv[l], m.dinv.data() + skip, count * 8, hipMemcpyHostToDevice, c->stream));
+    PF_HIP(c, hipMemcpyAsync(c->ws + L.dinv[l], m.dinv.data() + skip, count * 8, hipMemcpyHostToDevice, strm(c)));
     if (l > 0) {
       if (h.tables[l].size() != (size_t)m.nz * h.nc * h.nc * 27 || h.zmaps[l].size() != (size_t)h.levels[l - 1].nz ||
           h.zfine[l].size() != (size_t)m.nz)
         return fail(c, PF_EINVAL, "multigrid: level %zu tables do not match its grid", l);
       PF_HIP(c, hipMemcpyAsync(c->ws + L.tab[l], h.tables[l].data(), h.tables[l].size() * 8, hipMemcpyHostToDevice,
-                               c->stream));
+                               strm(c)));
       // A omega D^-1: column (plane k + dz, component e) scaled by omega / diag
       std::vector<double> tw(h.tables[l].size(), 0.0);
       const int nc = h.nc;
@@ -1235,21 +1323,21 @@ pf_status upload_mg(pf_ctx* c, int f, const FemTables& tb) {
             }
       h.tables_w.push_back(std::move(tw));
       PF_HIP(c, hipMemcpyAsync(c->ws + L.tabw[l], h.tables_w.back().data(), h.tables_w.back().size() * 8,
-                               hipMemcpyHostToDevice, c->stream));
+                               hipMemcpyHostToDevice, strm(c)));
       PF_HIP(c, hipMemcpyAsync(c->ws + L.zmap[l], h.zmaps[l].data(), h.zmaps[l].size() * sizeof(MgZ),
-                               hipMemcpyHostToDevice, c->stream));
+                               hipMemcpyHostToDevice, strm(c)));
       PF_HIP(c, hipMemcpyAsync(c->ws + L.zfine[l], h.zfine[l].data(), h.zfine[l].size() * sizeof(int),
-                               hipMemcpyHostToDevice, c->stream));
+                               hipMemcpyHostToDevice, strm(c)));
     }
   }
   if (h.dense_n > 0) {
     if (L.dense == 0 || (size_t)h.dense_n != L.dense_n)
       return fail(c, PF_EINVAL, "multigrid: no room for the coarsest inverse");
     PF_HIP(c, hipMemcpyAsync(c->ws + L.dense, h.dense_inv.data(), h.dense_inv.size() * 8, hipMemcpyHostToDevice,
-                             c->stream));
+                             strm(c)));
   }
-  PF_HIP(c, launch_fill<double>(at<double>(c, L.first), (int64_t)((L.end - L.first) / 8), 0.0, c->stream));
-  PF_HIP(c, hipStreamSynchronize(c->stream));
+  PF_HIP(c, launch_fill<double>(at<double>(c, L.first), (int64_t)((L.end - L.first) / 8), 0.0, strm(c)));
+  PF_HIP(c, hipStreamSynchronize(strm(c)));
   return PF_OK;
 }
 
@@ -1266,10 +1354,10 @@ pf_status upload_ghosts(pf_ctx* c) {
   for (auto& e : c->electrodes)
     for (int j = e.y0; j < e.y1; j++)
       for (int i = e.x0; i < e.x1; i++) mask[(size_t)i + (size_t)g.nx * j] = 1;
-  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.ghost64, g64.data(), g64.size() * 8, hipMemcpyHostToDevice, c->stream));
-  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.ghost32, g32.data(), g32.size() * 4, hipMemcpyHostToDevice, c->stream));
-  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.emask, mask.data(), mask.size(), hipMemcpyHostToDevice, c->stream));
-  PF_HIP(c, hipStreamSynchronize(c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.ghost64, g64.data(), g64.size() * 8, hipMemcpyHostToDevice, strm(c)));
+  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.ghost32, g32.data(), g32.size() * 4, hipMemcpyHostToDevice, strm(c)));
+  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.emask, mask.data(), mask.size(), hipMemcpyHostToDevice, strm(c)));
+  PF_HIP(c, hipStreamSynchronize(strm(c)));
   return PF_OK;
 }
 
@@ -1299,7 +1387,7 @@ pf_status ensure_basis(pf_ctx* c) {
     for (int j = el.y0; j < el.y1; j++)
       for (int i = el.x0; i < el.x1; i++) unit[(size_t)i + (size_t)g.nx * j] = 1.0;
     PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.ghost_unit, unit.data(), unit.size() * 8, hipMemcpyHostToDevice,
-                             c->stream));
+                             strm(c)));
     SolveResult r{};
     pf_status s = solve_poisson64<double>(c, kPredAux, nullptr, nullptr, 0.0, 0, 1, at<double>(c, c->lay.ghost_unit),
                                           0.0, at<double>(c, c->lay.basis) + (size_t)e * c->dims_p.N, aux_tol(c), false,
@@ -1343,7 +1431,7 @@ pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt) {
     out = worst(out, s);
   }
   PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-    return launch_hvp<S>(d, cf, tb, P, V, cdt, w, ulin, psi, du, scratch<double>(c, kScrHw), c->stream);
+    return launch_hvp<S>(d, cf, tb, P, V, cdt, w, ulin, psi, du, scratch<double>(c, kScrHw), strm(c));
   }));
   c->adj_warm = true;
   return out;
@@ -1363,18 +1451,18 @@ pf_status theta_accumulate(pf_ctx* c, const S* P, const S* V, double cdt, double
       const pf_electrode& el = c->electrodes[e];
       const double* phe = at<double>(c, c->lay.basis) + (size_t)e * c->dims_p.N;
       PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-        return launch_theta_dot<S>(d, cf, w, phe, el.x0, el.x1, el.y0, el.y1, P, V, cdt, part, c->stream);
+        return launch_theta_dot<S>(d, cf, w, phe, el.x0, el.x1, el.y0, el.y1, P, V, cdt, part, strm(c));
       }));
       PF_HIP(c, reduce(c, part, c->nblocks, 1, 2, kRedSum, 0, 0, dev_result(c) + e));
     }
   }
   if (c->cfg.terms & PF_TERM_LANDAU) {
     PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-      return launch_theta_dot<S>(d, cf, w, nullptr, 0, 0, 0, 0, P, V, cdt, part, c->stream);
+      return launch_theta_dot<S>(d, cf, w, nullptr, 0, 0, 0, 0, P, V, cdt, part, strm(c));
     }));
     PF_HIP(c, reduce(c, part, c->nblocks, 1, 2, kRedSum, 0, 0, dev_result(c) + ne));
   }
-  PF_HIP(c, hipMemcpyAsync(c->host_res, dev_result(c), (ne + 1) * 8, hipMemcpyDeviceToHost, c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->host_res, dev_result(c), (ne + 1) * 8, hipMemcpyDeviceToHost, strm(c)));
   PF_TRY(sync(c));
   for (int e = 0; e < ne; e++)
     if ((c->cfg.terms & PF_TERM_ELEC)) dtheta[e] += scale * c->host_res[e];
@@ -1391,11 +1479,11 @@ pf_status adjoint_step_t(pf_ctx* c, const S* Pn, const S* Vn, S* lamP, S* lamV, 
   double* Hw = scratch<double>(c, kScrHw);
   const S* V = pc ? Vn : nullptr;
   const double cdt = pc ? dt : 0.0;
-  PF_HIP(c, launch_adjoint_axpy<S>(pc ? kAdjPrepPc : kAdjPrepEuler, dt, lamP, lamV, w, Hw, n3, c->stream));
+  PF_HIP(c, launch_adjoint_axpy<S>(pc ? kAdjPrepPc : kAdjPrepEuler, dt, lamP, lamV, w, Hw, n3, strm(c)));
   pf_status s = hvp<S>(c, Pn, V, cdt);
   if (fatal(s)) return s;
   PF_TRY(theta_accumulate<S>(c, Pn, V, cdt, pc ? 1.0 : dt, dtheta));
-  PF_HIP(c, launch_adjoint_axpy<S>(pc ? kAdjUpdPc : kAdjUpdEuler, dt, lamP, lamV, w, Hw, n3, c->stream));
+  PF_HIP(c, launch_adjoint_axpy<S>(pc ? kAdjUpdPc : kAdjUpdEuler, dt, lamP, lamV, w, Hw, n3, strm(c)));
   PF_TRY(sync(c));
   return s;
 }
@@ -1405,11 +1493,11 @@ pf_status adjoint_initial_t(pf_ctx* c, const S* P0, S* lamP, S* lamV, double* dt
   const int64_t n3 = 3 * c->dims.N;
   double* w = scratch<double>(c, kScrW);
   double* Hw = scratch<double>(c, kScrHw);
-  PF_HIP(c, launch_adjoint_axpy<S>(kAdjPrepInit, 0.0, lamP, lamV, w, Hw, n3, c->stream));
+  PF_HIP(c, launch_adjoint_axpy<S>(kAdjPrepInit, 0.0, lamP, lamV, w, Hw, n3, strm(c)));
   pf_status s = hvp<S>(c, P0, nullptr, 0.0);
   if (fatal(s)) return s;
   PF_TRY(theta_accumulate<S>(c, P0, nullptr, 0.0, 1.0, dtheta));
-  PF_HIP(c, launch_adjoint_axpy<S>(kAdjUpdInit, 0.0, lamP, lamV, w, Hw, n3, c->stream));
+  PF_HIP(c, launch_adjoint_axpy<S>(kAdjUpdInit, 0.0, lamP, lamV, w, Hw, n3, strm(c)));
   PF_TRY(sync(c));
   return s;
 }
@@ -1427,7 +1515,7 @@ pf_status energy_t(pf_ctx* c, const S* P, double out[5]) {
   double* u = scratch<double>(c, kScrUE);
   if (c->cfg.terms & PF_TERM_ELEC) {
     PF_TRY(ensure_phi_bc(c));
-    PF_HIP(c, hipMemcpyAsync(phi, at<double>(c, c->lay.phi), c->dims_p.N * 8, hipMemcpyDeviceToDevice, c->stream));
+    PF_HIP(c, hipMemcpyAsync(phi, at<double>(c, c->lay.phi), c->dims_p.N * 8, hipMemcpyDeviceToDevice, strm(c)));
     SolveResult r{};
     pf_status s = solve_poisson64<S>(c, kPredAux, P, nullptr, 0.0, 1, 1, at<double>(c, c->lay.ghost64),
                                      c->cfg.phi_bottom, phi, c->cfg.tol_phi, true, &r);
@@ -1435,7 +1523,7 @@ pf_status energy_t(pf_ctx* c, const S* P, double out[5]) {
     st = worst(st, s);
   }
   if (c->cfg.terms & PF_TERM_ELAS) {
-    PF_HIP(c, hipMemcpyAsync(u, at<double>(c, c->lay.u), 3 * d.N * 8, hipMemcpyDeviceToDevice, c->stream));
+    PF_HIP(c, hipMemcpyAsync(u, at<double>(c, c->lay.u), 3 * d.N * 8, hipMemcpyDeviceToDevice, strm(c)));
     SolveResult r{};
     pf_status s = solve_fem64<S>(c, kPredAux, P, nullptr, 0.0, nullptr, u, c->cfg.tol_u, true, &r);
     if (fatal(s)) return s;
@@ -1444,16 +1532,16 @@ pf_status energy_t(pf_ctx* c, const S* P, double out[5]) {
   double* part = dev_partials(c, 2);
   PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
     return launch_energy<S>(d, cf, at<FemTables>(c, c->lay.tables), P, phi, at<double>(c, c->lay.phi_bc),
-                            at<double>(c, c->lay.ghost64), u, part, c->stream);
+                            at<double>(c, c->lay.ghost64), u, part, strm(c));
   }));
   PF_HIP(c, reduce(c, part, c->nblocks, 4, 2, kRedSum, 0, 0, dev_result(c)));
   if (c->cfg.terms & PF_TERM_ELEC) {
     PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-      return launch_elec_quad<S>(c->dims_p, cf, P, phi, at<double>(c, c->lay.phi_bc), emask(c), part, c->stream);
+      return launch_elec_quad<S>(c->dims_p, cf, P, phi, at<double>(c, c->lay.phi_bc), emask(c), part, strm(c));
     }));
     PF_HIP(c, reduce(c, part, c->nblocks_p, 1, 2, kRedSum, 0, 0, dev_result(c) + 4));
   }
-  PF_HIP(c, hipMemcpyAsync(c->host_res, dev_result(c), 5 * 8, hipMemcpyDeviceToHost, c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->host_res, dev_result(c), 5 * 8, hipMemcpyDeviceToHost, strm(c)));
   PF_TRY(sync(c));
   for (int t = 0; t < 4; t++) out[t] = c->host_res[t];
   if (c->cfg.terms & PF_TERM_ELEC) out[2] += c->host_res[4];
@@ -1561,16 +1649,28 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   std::memset(c->kc_n, 0, sizeof(c->kc_n));
   c->host_sc = nullptr;
   c->host_res = nullptr;
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_sc), sizeof(CgScalars), hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_sc), sizeof(CgScalars) * kNumScalars, hipHostMallocDefault) !=
+          hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->host_res), kResultSlots * 8, hipHostMallocDefault) != hipSuccess) {
     fprintf(stderr, "pf_init: pinned host allocation failed\n");
     pf_destroy(c);
     return PF_EHIP;
   }
+  // the second stream (default priority) and the worker thread that uses it
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    fprintf(stderr, "pf_init: stream or event creation failed\n");
+    pf_destroy(c);
+    return PF_EHIP;
+  }
+  c->worker.reset(new pf_ctx::Worker());
+  c->worker->th = std::thread(worker_main, c);
   FemTables tb;
   build_tables(c->cfg, &tb);
   pf_status st = PF_OK;
-  hipError_t e = hipMemcpyAsync(c->ws + c->lay.tables, &tb, sizeof(tb), hipMemcpyHostToDevice, c->stream);
+  hipError_t e = hipMemcpyAsync(c->ws + c->lay.tables, &tb, sizeof(tb), hipMemcpyHostToDevice, strm(c));
   if (e != hipSuccess) st = fail(c, PF_EHIP, "table upload: %s", hipGetErrorString(e));
   for (int f = 0; f < 2 && st == PF_OK; f++)
     if (!c->lay.mg[f].dinv.empty()) st = upload_mg(c, f, tb);
@@ -1578,8 +1678,8 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   if (st == PF_OK) {
     static_assert(sizeof(CgScalars) % 8 == 0, "scalars are cleared as doubles");
     e = launch_fill<double>(reinterpret_cast<double*>(c->ws + c->lay.scalars),
-                            (int64_t)(sizeof(CgScalars) * kNumScalars / 8), 0.0, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+                            (int64_t)(sizeof(CgScalars) * kNumScalars / 8), 0.0, strm(c));
+    if (e == hipSuccess) e = hipStreamSynchronize(strm(c));
     if (e != hipSuccess) st = fail(c, PF_EHIP, "init: %s", hipGetErrorString(e));
   }
   if (st != PF_OK) {
@@ -1593,6 +1693,18 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
 
 void pf_destroy(pf_ctx* c) {
   if (!c) return;
+  if (c->worker) {
+    {
+      std::lock_guard<std::mutex> g(c->worker->mu);
+      c->worker->quit = true;
+      c->worker->cv.notify_all();
+    }
+    c->worker->th.join();
+    c->worker.reset();
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->stream2) (void)hipStreamDestroy(c->stream2);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
   if (c->host_res) (void)hipHostFree(c->host_res);
@@ -1611,17 +1723,17 @@ pf_status pf_set_state(pf_ctx* c, const void* P, const void* phi0, const void* u
   void* Vc = c->ws + c->lay.V[0];
   double* phi = at<double>(c, c->lay.phi);
   double* u = at<double>(c, c->lay.u);
-  PF_HIP(c, hipMemcpyAsync(Pc, P, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
-  if (phi0) PF_HIP(c, hipMemcpyAsync(phi, phi0, Np * 8, hipMemcpyDeviceToDevice, c->stream));
-  else PF_HIP(c, launch_fill<double>(phi, Np, 0.0, c->stream));
-  if (u0) PF_HIP(c, hipMemcpyAsync(u, u0, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
-  else PF_HIP(c, launch_fill<double>(u, 3 * N, 0.0, c->stream));
+  PF_HIP(c, hipMemcpyAsync(Pc, P, 3 * N * es, hipMemcpyDeviceToDevice, strm(c)));
+  if (phi0) PF_HIP(c, hipMemcpyAsync(phi, phi0, Np * 8, hipMemcpyDeviceToDevice, strm(c)));
+  else PF_HIP(c, launch_fill<double>(phi, Np, 0.0, strm(c)));
+  if (u0) PF_HIP(c, hipMemcpyAsync(u, u0, 3 * N * 8, hipMemcpyDeviceToDevice, strm(c)));
+  else PF_HIP(c, launch_fill<double>(u, 3 * N, 0.0, strm(c)));
   if (fp32(c)) {
-    PF_HIP(c, launch_convert<double, float>(phi, at<float>(c, c->lay.phi32), Np, c->stream));
-    PF_HIP(c, launch_convert<double, float>(u, at<float>(c, c->lay.u32), 3 * N, c->stream));
-    PF_HIP(c, launch_fill<float>(static_cast<float*>(Vc), 3 * N, 0.0f, c->stream));
+    PF_HIP(c, launch_convert<double, float>(phi, at<float>(c, c->lay.phi32), Np, strm(c)));
+    PF_HIP(c, launch_convert<double, float>(u, at<float>(c, c->lay.u32), 3 * N, strm(c)));
+    PF_HIP(c, launch_fill<float>(static_cast<float*>(Vc), 3 * N, 0.0f, strm(c)));
   } else {
-    PF_HIP(c, launch_fill<double>(static_cast<double*>(Vc), 3 * N, 0.0, c->stream));
+    PF_HIP(c, launch_fill<double>(static_cast<double*>(Vc), 3 * N, 0.0, strm(c)));
   }
   pf_status s = PF_OK;
   if (c->cfg.integrator == PF_INT_PC) {
@@ -1641,13 +1753,13 @@ pf_status pf_restore_state(pf_ctx* c, const void* P, const void* V, const void* 
   c->cur = 0;
   c->hist_valid = 0;
   c->hist_head = 0;
-  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.P[0], P, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
-  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.V[0], V, 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
-  PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.phi), phi, Np * 8, hipMemcpyDeviceToDevice, c->stream));
-  PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.u), u, 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.P[0], P, 3 * N * es, hipMemcpyDeviceToDevice, strm(c)));
+  PF_HIP(c, hipMemcpyAsync(c->ws + c->lay.V[0], V, 3 * N * es, hipMemcpyDeviceToDevice, strm(c)));
+  PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.phi), phi, Np * 8, hipMemcpyDeviceToDevice, strm(c)));
+  PF_HIP(c, hipMemcpyAsync(at<double>(c, c->lay.u), u, 3 * N * 8, hipMemcpyDeviceToDevice, strm(c)));
   if (fp32(c)) {
-    PF_HIP(c, launch_convert<double, float>(at<double>(c, c->lay.phi), at<float>(c, c->lay.phi32), Np, c->stream));
-    PF_HIP(c, launch_convert<double, float>(at<double>(c, c->lay.u), at<float>(c, c->lay.u32), 3 * N, c->stream));
+    PF_HIP(c, launch_convert<double, float>(at<double>(c, c->lay.phi), at<float>(c, c->lay.phi32), Np, strm(c)));
+    PF_HIP(c, launch_convert<double, float>(at<double>(c, c->lay.u), at<float>(c, c->lay.u32), 3 * N, strm(c)));
   }
   c->step = step;
   c->have_state = true;
@@ -1660,10 +1772,10 @@ pf_status pf_get_state(const pf_ctx* cc, void* P, void* V, void* phi, void* u, i
   if (!c->have_state) return fail(c, PF_ESTATE, "pf_get_state: no state (call pf_set_state first)");
   const int64_t N = c->dims.N, Np = c->dims_p.N;
   const size_t es = state_bytes(c);
-  if (P) PF_HIP(c, hipMemcpyAsync(P, c->ws + c->lay.P[c->cur], 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
-  if (V) PF_HIP(c, hipMemcpyAsync(V, c->ws + c->lay.V[c->cur], 3 * N * es, hipMemcpyDeviceToDevice, c->stream));
-  if (phi) PF_HIP(c, hipMemcpyAsync(phi, at<double>(c, c->lay.phi), Np * 8, hipMemcpyDeviceToDevice, c->stream));
-  if (u) PF_HIP(c, hipMemcpyAsync(u, at<double>(c, c->lay.u), 3 * N * 8, hipMemcpyDeviceToDevice, c->stream));
+  if (P) PF_HIP(c, hipMemcpyAsync(P, c->ws + c->lay.P[c->cur], 3 * N * es, hipMemcpyDeviceToDevice, strm(c)));
+  if (V) PF_HIP(c, hipMemcpyAsync(V, c->ws + c->lay.V[c->cur], 3 * N * es, hipMemcpyDeviceToDevice, strm(c)));
+  if (phi) PF_HIP(c, hipMemcpyAsync(phi, at<double>(c, c->lay.phi), Np * 8, hipMemcpyDeviceToDevice, strm(c)));
+  if (u) PF_HIP(c, hipMemcpyAsync(u, at<double>(c, c->lay.u), 3 * N * 8, hipMemcpyDeviceToDevice, strm(c)));
   if (step) *step = c->step;
   return PF_OK;
 }
@@ -1738,7 +1850,7 @@ pf_status pf_solve_u(pf_ctx* c, const void* P, void* u, pf_solve_stats* st) {
 
 pf_status pf_noise(pf_ctx* c, int64_t step, double* xi) {
   if (!c || !xi) return fail(c, PF_EINVAL, "pf_noise: null argument");
-  PF_HIP(c, launch_noise(noise_spec(c, step, true), c->dims.N, xi, c->stream));
+  PF_HIP(c, launch_noise(noise_spec(c, step, true), c->dims.N, xi, strm(c)));
   return PF_OK;
 }
 
@@ -1750,8 +1862,8 @@ pf_status pf_force(pf_ctx* c, const void* P, const void* phi, const void* u, voi
   if (fp32(c)) {
     float* phi32 = scratch<float>(c, kScrTmp);
     float* u32 = phi32 + N;
-    if (phi) PF_HIP(c, launch_convert<double, float>(static_cast<const double*>(phi), phi32, N, c->stream));
-    if (u) PF_HIP(c, launch_convert<double, float>(static_cast<const double*>(u), u32, 3 * N, c->stream));
+    if (phi) PF_HIP(c, launch_convert<double, float>(static_cast<const double*>(phi), phi32, N, strm(c)));
+    if (u) PF_HIP(c, launch_convert<double, float>(static_cast<const double*>(u), u32, 3 * N, strm(c)));
     return launch_state_force(c, P, nullptr, 0.0, kForceOut, nullptr, nullptr, F, phi32, u32);
   }
   return launch_state_force(c, P, nullptr, 0.0, kForceOut, nullptr, nullptr, F, phi, u);
