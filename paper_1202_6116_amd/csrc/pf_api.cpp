@@ -1413,22 +1413,49 @@ pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt) {
   double* ulin = scratch<double>(c, kScrULin);
   double* du = scratch<double>(c, kScrDu);
   double* psi = scratch<double>(c, kScrPsi);
-  pf_status out = PF_OK;
-  if (c->cfg.terms & PF_TERM_ELAS) {
+  // the displacement at the linearisation point and the adjoint displacement
+  auto fem = [&]() -> pf_status {
     SolveResult r{};
     pf_status s = solve_fem64<S>(c, kPredAdjU, P, V, cdt, nullptr, ulin, c->cfg.tol_u, c->adj_warm, &r);
     if (fatal(s)) return s;
-    out = worst(out, s);
-    s = solve_fem64<S>(c, kPredAdjDu, P, V, cdt, w, du, c->cfg.tol_u, c->adj_warm, &r);
-    if (fatal(s)) return s;
-    out = worst(out, s);
-  }
-  if (c->cfg.terms & PF_TERM_ELEC) {
+    const pf_status s2 = solve_fem64<S>(c, kPredAdjDu, P, V, cdt, w, du, c->cfg.tol_u, c->adj_warm, &r);
+    return fatal(s2) ? s2 : worst(s, s2);
+  };
+  // the adjoint potential
+  auto poisson = [&]() -> pf_status {
     SolveResult r{};
-    pf_status s = solve_poisson64<double>(c, kPredAdjPsi, w, nullptr, 0.0, 1, 0, at<double>(c, c->lay.ghost64), 0.0,
-                                          psi, c->cfg.tol_phi, c->adj_warm, &r);
-    if (fatal(s)) return s;
-    out = worst(out, s);
+    return solve_poisson64<double>(c, kPredAdjPsi, w, nullptr, 0.0, 1, 0, at<double>(c, c->lay.ghost64), 0.0, psi,
+                                   c->cfg.tol_phi, c->adj_warm, &r);
+  };
+  const bool elec = c->cfg.terms & PF_TERM_ELEC, elas = c->cfg.terms & PF_TERM_ELAS;
+  pf_status out = PF_OK;
+  if (elec && elas && c->worker && !c->timing) {
+    // concurrent, as the forward solves
+    PF_HIP(c, hipEventRecord(c->ev_fork, strm(c)));
+    pf_status sf = PF_OK;
+    worker_post(c, [&] {
+      const hipError_t e = hipStreamWaitEvent(c->stream2, c->ev_fork, 0);
+      sf = e == hipSuccess ? fem() : fail(c, PF_EHIP, "fork: %s", hipGetErrorString(e));
+      const hipError_t e2 = hipEventRecord(c->ev_join, c->stream2);
+      if (e2 != hipSuccess && !fatal(sf)) sf = fail(c, PF_EHIP, "join: %s", hipGetErrorString(e2));
+    });
+    const pf_status sp = poisson();
+    worker_wait(c);
+    PF_HIP(c, hipStreamWaitEvent(strm(c), c->ev_join, 0));
+    if (fatal(sp)) return sp;
+    if (fatal(sf)) return sf;
+    out = worst(sp, sf);
+  } else {
+    if (elas) {
+      const pf_status s = fem();
+      if (fatal(s)) return s;
+      out = worst(out, s);
+    }
+    if (elec) {
+      const pf_status s = poisson();
+      if (fatal(s)) return s;
+      out = worst(out, s);
+    }
   }
   PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
     return launch_hvp<S>(d, cf, tb, P, V, cdt, w, ulin, psi, du, scratch<double>(c, kScrHw), strm(c));
