@@ -33,24 +33,30 @@ HBM_PEAK_GBS = 8000.0
 #   fem_a          r, p_old, x (72) read; p_new, x (48) written   (rows k >= 1)
 #   fem_b          p, r (48) read; r (24) written                 (rows k >= 1)
 #   force          P, V (48) + phi (8) + u (24) read; P, V (48) written
-#   mg_u0          FEM multigrid on the solver grid (residual or last sweep):
-#                  x, b (48) read; out (24) written                 (rows k >= 1)
-#   mg_phi0        the same for the Poisson operator: x, b (16) read; out (8)
+#   mg_u0          FEM multigrid on the solver grid, one residual of the first
+#                  sweep (b (24) read, out (24) written) and one last sweep
+#                  (x, b (48) read, out (24) written) per V-cycle: 60 on
+#                  average                                        (rows k >= 1)
+#   mg_phi0        the same for the Poisson operator: (16 + 24) / 2 = 20
 #   finish         x, p read, x written (Poisson 24, FEM 72 per node)
 # The Poisson classes run over the potential grid (the film plus, with the
 # open top, the air planes), the others over the film.
 BYTES_PER_NODE_FP64 = {
     "poisson_setup": 72, "poisson_a": 40, "poisson_b": 24, "fem_setup": 120, "fem_a": 120, "fem_b": 72,
-    "force": 128, "mg_u0": 72, "mg_phi0": 24,
+    "force": 128, "mg_u0": 60, "mg_phi0": 20,
 }
 
 
 # HBM bytes per working launch measured with rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (fetch counts scaled by 2.0, writes by 1.0, from a 1 GiB copy)
-# for the current kernels; summary and commands in
-# profiles/fem_cg_a_fp64_lateral_256x256x64.md.  Keyed by workload, precision
+# for the current kernels (mg_u0: the mean of its two variants, which run
+# equally often); summary and commands in
+# profiles/mg_fine_fp64_lateral_256x256x64.md.  Keyed by workload, precision
 # and kernel class; anything else reports null.
-MEASURED_TRAFFIC = {("lateral_256x256x64", "fp64", "fem_a"): 598.6e6}
+MEASURED_TRAFFIC = {
+    ("lateral_256x256x64", "fp64", "mg_u0"): 259.7e6,
+    ("lateral_256x256x64", "fp64", "fem_a"): 593.8e6,
+}
 
 
 def nodes_per_launch(cls, cfg):
