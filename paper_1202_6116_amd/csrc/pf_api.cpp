@@ -299,6 +299,41 @@ void build_tables(const pf_config& c, FemTables* t) {
           t->Ms[zt][o] = ax[0]->m[off[0]] * ax[1]->m[off[1]] * ax[2]->m[off[2]];
         }
       }
+  // compact form for a stiffness cubic on the grid axes, checked entry by entry
+  {
+    double kmax = 0.0;
+    for (int kt = 0; kt < 2; kt++)
+      for (int cc = 0; cc < 3; cc++)
+        for (int e = 0; e < 3; e++)
+          for (int o = 0; o < kTaps; o++) kmax = std::max(kmax, std::fabs(t->K[kt][cc][e][o]));
+    const double tol = 1e-12 * kmax;
+    bool seen_i[8] = {}, seen_t[24] = {};
+    bool ok = true;
+    for (int kt = 0; kt < 2 && ok; kt++)
+      for (int cc = 0; cc < 3 && ok; cc++)
+        for (int e = 0; e < 3 && ok; e++)
+          for (int o = 0; o < kTaps && ok; o++) {
+            const int off[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
+            int sg = 1;
+            const int cl = kc_class(kt, cc, e, off, &sg);
+            const double v = t->K[kt][cc][e][o];
+            if (cl < 0) {
+              ok = std::fabs(v) <= tol;
+              continue;
+            }
+            double* slot = kt == 0 ? &t->kc_int[cl] : &t->kc_top[cl];
+            bool* seen = kt == 0 ? &seen_i[cl] : &seen_t[cl];
+            if (!*seen) {
+              *slot = sg * v;
+              *seen = true;
+            } else {
+              ok = std::fabs(v - sg * *slot) <= tol;
+            }
+          }
+    for (int q = 0; q < 8; q++) ok = ok && seen_i[q];
+    for (int q = 0; q < 24; q++) ok = ok && seen_t[q];
+    t->compact = ok ? 1 : 0;
+  }
   for (int zt = 0; zt < 3; zt++)
     for (int o = 0; o < 3; o++) {
       t->m1[zt][o] = zrow[zt].m[o];
@@ -483,6 +518,7 @@ struct pf_ctx {
   pf_config cfg;
   std::vector<pf_electrode> electrodes;
   pf::Material mat;          // grid-frame stiffness and electrostriction
+  bool gen;                  // FEM kernels take the general stencil (the stiffness is not cubic on the grid axes)
   pf::MgHierarchy mg[2];     // multigrid of the Poisson (0) and FEM (1) operator (no levels: Jacobi)
   std::vector<pf::Dims> mg_dims[2];
   pf::Dims dims;             // film grid
@@ -860,7 +896,7 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   const int nc = h.nc;
   const int top = h.top_fixed ? 1 : 0;
   const FemTables* tb = at<FemTables>(c, c->lay.tables);
-  const bool gen = !c->mat.cubic;
+  const bool gen = c->gen;
   const Coefs<T> cf = make_coefs<T>(c);
   hipStream_t st = strm(c);
   auto V = [&](size_t off) { return at<T>(c, off); };
@@ -992,14 +1028,14 @@ std::function<hipError_t(int)> fem_iteration(pf_ctx* c, T* r, T* const pb[2], T*
     const bool mg = mg_on(c, 1);
     T* z = mg ? at<T>(c, c->lay.mg[1].z) : nullptr;
     hipError_t e = timed(c, PF_KC_FEM_A, 1, k, [&] {
-      return launch_fem_cg_a<T>(d, c->tm_f, tb, !c->mat.cubic, mg ? z : r, pb[k & 1], pb[(k + 1) & 1], x, sc, part,
+      return launch_fem_cg_a<T>(d, c->tm_f, tb, c->gen, mg ? z : r, pb[k & 1], pb[(k + 1) & 1], x, sc, part,
                                 mg ? 1 : 0, strm(c));
     });
     if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 1, 1, kRedAlpha, tol, 0, nullptr, 1, k);
     if (e == hipSuccess)
       e = timed(c, PF_KC_FEM_B, 1, k,
                 [&] {
-                  return launch_fem_cg_b<T>(d, c->tm_f, tb, !c->mat.cubic, pb[(k + 1) & 1], r, sc, part, strm(c));
+                  return launch_fem_cg_b<T>(d, c->tm_f, tb, c->gen, pb[(k + 1) & 1], r, sc, part, strm(c));
                 });
     // multigrid: z = M r replaces the Jacobi-weighted r.z of kernel B
     if (e == hipSuccess && mg) e = mg_vcycle<T>(c, 1, r, z, sc, part, 2, 0, k);
@@ -1045,7 +1081,7 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
   double* const pb[2] = {at<double>(c, c->lay.fp[0]), at<double>(c, c->lay.fp[1])};
   if (!warm) PF_HIP(c, launch_fill<double>(x, 3 * d.N, 0.0, strm(c)));
   PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
-    return launch_fem_setup<double, S, double>(d, c->tm_f, cf, tb, !c->mat.cubic, P, V, cdt, W, x, r, pb[0], pb[1], nullptr,
+    return launch_fem_setup<double, S, double>(d, c->tm_f, cf, tb, c->gen, P, V, cdt, W, x, r, pb[0], pb[1], nullptr,
                                                part, strm(c));
   }));
   PF_HIP(c, reduce(c, part, c->tm_f.nblocks, 3, 1, kRedSetup, tol, 0, nullptr));
@@ -1088,7 +1124,7 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
   for (;;) {
     if (fem) {
       PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
-        return launch_fem_setup<double, float, float>(d, c->tm_f, cf64, tb, !c->mat.cubic, P, V, cdt, nullptr, x64, r, pb[0],
+        return launch_fem_setup<double, float, float>(d, c->tm_f, cf64, tb, c->gen, P, V, cdt, nullptr, x64, r, pb[0],
                                                       pb[1], dz, part, strm(c));
       }));
     } else {
@@ -1696,6 +1732,7 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->worker->th = std::thread(worker_main, c);
   FemTables tb;
   build_tables(c->cfg, &tb);
+  c->gen = !c->mat.cubic || !tb.compact;
   pf_status st = PF_OK;
   hipError_t e = hipMemcpyAsync(c->ws + c->lay.tables, &tb, sizeof(tb), hipMemcpyHostToDevice, strm(c));
   if (e != hipSuccess) st = fail(c, PF_EHIP, "table upload: %s", hipGetErrorString(e));

@@ -44,7 +44,47 @@ struct FemTables {
   // kind z in {kLow, kInterior, kHigh}, tap dz + 1): mass int N_n N_m,
   // int N_n N_m' (g) and int N_n' N_m (gt).  The x and y axes use kInterior.
   double m1[3][3], g1[3][3], gt1[3][3];
+  // With a stiffness cubic on the grid axes, K takes few distinct values:
+  // K[zt][c][e](o) = sign * kc[class] (kc_class below); compact = 1 when
+  // every coefficient of K was checked to have that form.
+  double kc_int[8], kc_top[24];
+  int32_t compact;
 };
+
+__host__ __device__ __forceinline__ int kc_abs(int v) { return v < 0 ? -v : v; }
+__host__ __device__ __forceinline__ int kc_sgn(int v) { return v < 0 ? -1 : 1; }
+
+// Class of the stiffness coefficient K[zt][c][e] at offset off for a
+// stiffness cubic on the grid axes (-1: structurally zero), and its sign.
+// Interior rows (zt 0) depend on which offsets are non-zero (the element
+// integrals are even in the offset, their derivative rows odd); top rows
+// (zt 1) also on whether the neighbour is in the plane below.
+__host__ __device__ __forceinline__ int kc_class(int zt, int c, int e, const int off[3], int* sign) {
+  *sign = 1;
+  if (zt == 0) {
+    if (c == e) return kc_abs(off[c]) * 3 + kc_abs(off[(c + 1) % 3]) + kc_abs(off[(c + 2) % 3]);
+    if (off[c] == 0 || off[e] == 0) return -1;
+    *sign = kc_sgn(off[c]) * kc_sgn(off[e]);
+    return 6 + kc_abs(off[3 - c - e]);
+  }
+  if (off[2] > 0) return -1;  // no element above the top plane
+  const int zi = off[2] == 0 ? 1 : 0;
+  if (c < 2 && e < 2) {
+    if (c == e) return kc_abs(off[c]) * 4 + kc_abs(off[1 - c]) * 2 + zi;
+    if (off[c] == 0 || off[e] == 0) return -1;
+    *sign = kc_sgn(off[c]) * kc_sgn(off[e]);
+    return 14 + zi;
+  }
+  if (c == 2 && e == 2) return 8 + zi * 3 + kc_abs(off[0]) + kc_abs(off[1]);
+  if (e == 2) {  // in-plane row, z column
+    if (off[c] == 0) return -1;
+    *sign = kc_sgn(off[c]);
+    return 16 + kc_abs(off[1 - c]) * 2 + zi;
+  }
+  if (off[e] == 0) return -1;  // z row, in-plane column
+  *sign = kc_sgn(off[e]);
+  return 20 + kc_abs(off[1 - e]) * 2 + zi;
+}
 
 // Scalars of one conjugate-gradient solve, resident in device memory.  The
 // last block of each reduction kernel updates them; every kernel of a solve

@@ -589,11 +589,61 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_b_kernel(Dims d, TileMap 
 namespace {
 
 // K u at a row of type zt (0 interior, 1 top) for a neighbour loader
-// ld(dx, dy, dz, out[3]).  Interior rows skip the structurally zero taps of
-// the coupling blocks (their 1D derivative factor vanishes at offset 0).
+// ld(dx, dy, dz, out[3]).  GEN: the general stencil of the tables.  Else the
+// stiffness is cubic on the grid axes and each coefficient is one of 8
+// (interior) or 24 (top) values, indexed at compile time by kc_class: they
+// fit the scalar registers (the 153 and 243 table values do not, and
+// spilled coefficients cost v_readlane instructions per row of nodes), and
+// the structurally zero taps are skipped.
 template <typename T, bool GEN, typename Load>
 __device__ __forceinline__ void fem_K_apply(const FemTables* __restrict__ tb, int zt, Load ld, T out[3]) {
   out[0] = out[1] = out[2] = 0;
+  if (!GEN) {
+    if (zt == 0) {
+#pragma unroll
+      for (int dz = -1; dz <= 1; dz++)
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+          for (int dx = -1; dx <= 1; dx++) {
+            const int off[3] = {dx, dy, dz};
+            T u[3];
+            ld(dx, dy, dz, u);
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+#pragma unroll
+              for (int e = 0; e < 3; e++) {
+                int sg = 1;
+                const int cl = kc_class(0, c, e, off, &sg);
+                if (cl < 0) continue;
+                const T k = (T)tb->kc_int[cl];
+                out[c] += (sg > 0 ? k : -k) * u[e];
+              }
+          }
+    } else {
+#pragma unroll
+      for (int dz = -1; dz <= 0; dz++)
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+          for (int dx = -1; dx <= 1; dx++) {
+            const int off[3] = {dx, dy, dz};
+            T u[3];
+            ld(dx, dy, dz, u);
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+#pragma unroll
+              for (int e = 0; e < 3; e++) {
+                int sg = 1;
+                const int cl = kc_class(1, c, e, off, &sg);
+                if (cl < 0) continue;
+                const T k = (T)tb->kc_top[cl];
+                out[c] += (sg > 0 ? k : -k) * u[e];
+              }
+          }
+    }
+    return;
+  }
   if (zt == 0) {
 #pragma unroll
     for (int dz = -1; dz <= 1; dz++)
@@ -602,16 +652,12 @@ __device__ __forceinline__ void fem_K_apply(const FemTables* __restrict__ tb, in
 #pragma unroll
         for (int dx = -1; dx <= 1; dx++) {
           const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-          const int off[3] = {dx, dy, dz};
           T u[3];
           ld(dx, dy, dz, u);
 #pragma unroll
           for (int c = 0; c < 3; c++)
 #pragma unroll
-            for (int e = 0; e < 3; e++) {
-              if (!GEN && c != e && (off[c] == 0 || off[e] == 0)) continue;
-              out[c] += (T)tb->K[0][c][e][o] * u[e];
-            }
+            for (int e = 0; e < 3; e++) out[c] += (T)tb->K[0][c][e][o] * u[e];
         }
   } else {
 #pragma unroll
