@@ -845,7 +845,10 @@ __device__ __forceinline__ void landau_hessian_apply(const Coefs<T>& cf, const T
 //   A_c = (gt x m) sigma_cx + (m x gt) sigma_cy,   B_c = (m x m) sigma_cz
 // in x and y and sums f_c(t) = sum_dz mz_t(dz) A_c + gtz_t(dz) B_c over its
 // column in registers; x is staged in the usual three-plane ring for K x.
-template <typename T, typename S, typename R, bool GEN>
+// ROT compiles the rotated-frame eigenstrain and stress (run-time check);
+// without it the crystal-aligned forms only, which keeps the 78 coefficients
+// of the rotated forms out of the scalar registers.
+template <typename T, typename S, typename R, bool GEN, bool ROT>
 __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
     Dims d, TileMap tm, Coefs<T> cf, const FemTables* __restrict__ tb, const S* __restrict__ P,
     const S* __restrict__ V, T cdt, const T* __restrict__ W, T* __restrict__ x, R* __restrict__ r,
@@ -898,9 +901,9 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
         const T* raw = sp.v[q];
         const T px = raw[0] + cdt * raw[3], py = raw[1] + cdt * raw[4], pz = raw[2] + cdt * raw[5];
         T e[6];
-        if (hasW) eigenstrain_lin(cf, px, py, pz, raw[6], raw[7], raw[8], e);
-        else eigenstrain(cf, px, py, pz, e);
-        cubic_stress(cf, e, sg);
+        if (hasW) eigenstrain_lin<ROT>(cf, px, py, pz, raw[6], raw[7], raw[8], e);
+        else eigenstrain<ROT>(cf, px, py, pz, e);
+        cubic_stress<ROT>(cf, e, sg);
       }
 #pragma unroll
       for (int v = 0; v < 6; v++) sgm[v][hy][hx] = sg[v];
@@ -1309,21 +1312,31 @@ __global__ __launch_bounds__(kThreads) void mg_level_kernel(Dims d, const double
   const int64_t N = d.N;
   const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
   const double* tk = tab + (size_t)k * NC * NC * 27;
+  // neighbour indices in 32 bits (coarse levels are small), per-component
+  // base pointers uniform across the block
+  const int pl = (int)d.plane;
+  const int xi[3] = {wrap(i - 1, d.nx), i, wrap(i + 1, d.nx)};
+  const int yo[3] = {wrap(j - 1, d.ny) * d.nx, j * d.nx, wrap(j + 1, d.ny) * d.nx};
+  const T* xb[NC];
+#pragma unroll
+  for (int e = 0; e < NC; e++) xb[e] = x + e * N;
   double q[NC];
 #pragma unroll
   for (int c = 0; c < NC; c++) q[c] = 0.0;
+#pragma unroll
   for (int dz = -1; dz <= 1; dz++) {
     const int kk = k + dz;
     if (kk < 1 || kk >= ktop) continue;
+    const int zo = kk * pl;
 #pragma unroll
     for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
       for (int dx = -1; dx <= 1; dx++) {
         const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-        const int64_t m = nbr(d, i, j, k, dx, dy, dz);
+        const int m = xi[dx + 1] + yo[dy + 1] + zo;
         double u[NC];
 #pragma unroll
-        for (int e = 0; e < NC; e++) u[e] = (double)x[e * N + m];
+        for (int e = 0; e < NC; e++) u[e] = (double)xb[e][m];
 #pragma unroll
         for (int c = 0; c < NC; c++)
 #pragma unroll
@@ -2369,12 +2382,17 @@ template <typename T, typename S, typename R>
 hipError_t launch_fem_setup(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const FemTables* tb, bool gen,
                             const S* P, const S* V, T cdt, const T* W, T* x, R* r, R* p0, R* p1, R* dz,
                             double* partials, hipStream_t s) {
-  if (gen)
-    fem_setup_kernel<T, S, R, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, tb, P, V, cdt, W, x, r, p0, p1, dz,
-                                                                       partials);
-  else
-    fem_setup_kernel<T, S, R, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, tb, P, V, cdt, W, x, r, p0, p1,
-                                                                        dz, partials);
+#define PF_FEM_SETUP(GEN, ROT)                                                                               \
+  fem_setup_kernel<T, S, R, GEN, ROT><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, tb, P, V, cdt, W, x, r, p0, p1, \
+                                                                          dz, partials)
+  if (gen) {
+    if (cf.rotated) PF_FEM_SETUP(true, true);
+    else PF_FEM_SETUP(true, false);
+  } else {
+    if (cf.rotated) PF_FEM_SETUP(false, true);
+    else PF_FEM_SETUP(false, false);
+  }
+#undef PF_FEM_SETUP
   return hipGetLastError();
 }
 
