@@ -53,7 +53,10 @@ BYTES_PER_NODE_FP64 = {
 # equally often); summary and commands in
 # profiles/mg_fine_fp64_lateral_256x256x64.md.  Keyed by workload, precision
 # and kernel class; anything else reports null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("lateral_256x256x64", "fp64", "mg_u0"): 260.7e6,
+    ("lateral_256x256x64", "fp64", "fem_a"): 604.6e6,
+}
 
 
 def nodes_per_launch(cls, cfg):
