@@ -166,3 +166,25 @@ def test_mg_lateral_256_full_size(pf, oracle_mod, name):
     f = o.fem_rhs(P0)
     r = f - o.fem_apply(host(u))
     assert np.linalg.norm(r) <= 1.05 * cfg.tol_u * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("precond,precision", [("mg", "fp64"), ("jacobi", "fp64"), ("mg", "fp32_refine")])
+def test_concurrent_solves_match_sequential_bitwise(pf, precond, precision):
+    """The Poisson and FEM solves of a step run on two streams; per-launch
+    timing runs them one after the other.  They touch disjoint buffers, so
+    both orders give the same bits."""
+    cfg = mg_cfg(precond=precond, precision=precision, warm_start=2,
+                 tol_phi=1e-12 if precision == "fp64" else 1e-9, tol_u=1e-12 if precision == "fp64" else 1e-9)
+    print(f"case: concurrent vs sequential {precond} {precision}", flush=True)
+    P0 = domain_polarisation(cfg, 77, block=4)
+    out = []
+    for sequential in (False, True):
+        ctx = pf.Context(cfg)
+        ctx.timing(sequential)
+        ctx.set_state(dev(P0, ctx.state_dtype))
+        ctx.step(5)
+        Pg, Vg, phig, ug, _ = ctx.get_state()
+        out.append([t.clone() for t in (Pg, Vg, phig, ug)])
+        ctx.timing(False)
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
