@@ -852,7 +852,10 @@ pf_status run_cg(pf_ctx* c, int which, int predicted, T* x, T* const pbuf[2], in
     PF_TRY(read_scalars(c, which, &h));
     if (h.done != kRunning) break;
     if (k >= maxit) return fail(c, PF_EHIP, "%s: solver state did not advance", what);
-    batch = std::max(4, predicted / 8);
+    // one more iteration usually suffices after the predicted count: small
+    // follow-up batches waste no iterations (each is ~35 launches with the
+    // multigrid cycle) for one more read-back
+    batch = std::max(1, predicted / 8);
   }
   if (h.done != kNonFinite)
     PF_HIP(c, timed(c, PF_KC_FINISH, -1, -1,
