@@ -48,7 +48,13 @@
  * Streams.  Every call enqueues on the stream given to pf_init and returns
  *   without waiting, except calls that return host values (pf_step and the
  *   solves, which read back iteration counts; pf_energy), which synchronise
- *   that stream.
+ *   that stream.  Each context also owns one more stream (default priority)
+ *   and one host worker thread, created by pf_init and released by
+ *   pf_destroy: when a step (or an adjoint step) solves both fields, the FEM
+ *   solve runs there, forked from and joined back into the caller's stream
+ *   by events, concurrently with the Poisson solve; results are bitwise
+ *   those of the sequential order.  With per-launch timing on (pf_timing)
+ *   the solves run one after the other on the caller's stream.
  *
  * Errors.  Every call returns a pf_status; nothing is thrown across the ABI.
  *   pf_last_error() describes the last failure of a context.  A context is

@@ -1186,11 +1186,14 @@ void stats_add(pf_step_stats* st, int which, const SolveResult& r) {
 // available: the order grows by one per refresh up to extrap_order).  The
 // weights of the polynomial through m + 1 equally spaced values, evaluated
 // one step past the newest, are (-1)^t C(m+1, t+1), t = 0..m.
-pf_status extrapolate_state(pf_ctx* c) {
+// extrapolate_plan does the host side (ring descriptors of phi and u, ring
+// head advanced; false: order 0, nothing to launch); extrapolate_field
+// launches one field's kernel on the calling thread's stream, so each solve
+// extrapolates its own field on its own stream.
+bool extrapolate_plan(pf_ctx* c, ExtrapRing ring[2]) {
   const int cap = c->cfg.extrap_order;
   const int m = std::min(c->hist_valid, cap);
   const int64_t N = c->dims.N, Np = c->dims_p.N;
-  ExtrapRing ring[2];
   for (int f = 0; f < 2; f++) {
     ExtrapRing& r = ring[f];
     const int64_t len = f == 0 ? Np : 3 * N;
@@ -1205,17 +1208,16 @@ pf_status extrapolate_state(pf_ctx* c) {
     for (int t = m; t < kMaxExtrap; t++) r.h[t] = nullptr;
     r.dest = cap > 0 ? base + (int64_t)c->hist_head * len : nullptr;
   }
-  if (cap == 0) return PF_OK;  // the previous solution is the guess
-  if (c->cfg.terms & PF_TERM_ELEC)
-    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-      return launch_extrapolate(at<double>(c, c->lay.phi), ring[0], Np, strm(c));
-    }));
-  if (c->cfg.terms & PF_TERM_ELAS)
-    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-      return launch_extrapolate(at<double>(c, c->lay.u), ring[1], 3 * N, strm(c));
-    }));
+  if (cap == 0) return false;  // the previous solution is the guess
   c->hist_head = (c->hist_head + 1) % cap;
   if (c->hist_valid < cap) c->hist_valid++;
+  return true;
+}
+
+pf_status extrapolate_field(pf_ctx* c, int f, const ExtrapRing& ring) {
+  const int64_t n = f == 0 ? c->dims_p.N : 3 * c->dims.N;
+  double* x = at<double>(c, f == 0 ? c->lay.phi : c->lay.u);
+  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_extrapolate(x, ring, n, strm(c)); }));
   return PF_OK;
 }
 
@@ -1224,10 +1226,13 @@ pf_status extrapolate_state(pf_ctx* c) {
 // stream concurrently with the Poisson solve on the caller's: the two touch
 // disjoint buffers and scalar slots, so the results do not depend on how
 // their kernels interleave.
-pf_status solve_nonlocal(pf_ctx* c, const void* P, const void* V, double cdt, bool warm, pf_step_stats* st) {
+// ring (non-null): first replace each field by its extrapolation.
+pf_status solve_nonlocal(pf_ctx* c, const void* P, const void* V, double cdt, bool warm, pf_step_stats* st,
+                         const ExtrapRing* ring = nullptr) {
   double* phi = at<double>(c, c->lay.phi);
   double* u = at<double>(c, c->lay.u);
   auto poisson = [&](SolveResult* r) -> pf_status {
+    if (ring) PF_TRY(extrapolate_field(c, 0, ring[0]));
     if (fp32(c))
       return solve_refined(c, false, static_cast<const float*>(P), static_cast<const float*>(V), cdt, phi,
                            at<float>(c, c->lay.phi32), c->cfg.tol_phi, warm, r);
@@ -1235,6 +1240,7 @@ pf_status solve_nonlocal(pf_ctx* c, const void* P, const void* V, double cdt, bo
                                    1, at<double>(c, c->lay.ghost64), c->cfg.phi_bottom, phi, c->cfg.tol_phi, warm, r);
   };
   auto fem = [&](SolveResult* r) -> pf_status {
+    if (ring) PF_TRY(extrapolate_field(c, 1, ring[1]));
     if (fp32(c))
       return solve_refined(c, true, static_cast<const float*>(P), static_cast<const float*>(V), cdt, u,
                            at<float>(c, c->lay.u32), c->cfg.tol_u, warm, r);
@@ -1861,8 +1867,10 @@ pf_status pf_step(pf_ctx* c, int32_t nsteps, pf_step_stats* st) {
     void* Pn = c->ws + c->lay.P[c->cur ^ 1];
     void* Vn = c->ws + c->lay.V[c->cur ^ 1];
     if (c->step % every == 0) {
-      if (c->cfg.warm_start == 2) PF_TRY(extrapolate_state(c));
-      pf_status r = solve_nonlocal(c, P, pc ? V : nullptr, pc ? c->cfg.dt : 0.0, c->cfg.warm_start != 0, st);
+      ExtrapRing ring[2];
+      const bool ex = c->cfg.warm_start == 2 && extrapolate_plan(c, ring);
+      pf_status r = solve_nonlocal(c, P, pc ? V : nullptr, pc ? c->cfg.dt : 0.0, c->cfg.warm_start != 0, st,
+                                   ex ? ring : nullptr);
       if (fatal(r)) return r;
       out = worst(out, r);
     }

@@ -155,3 +155,59 @@ def test_stress_tables_match_oracle(oracle_mod):
                     m = (k + dz, (j + dy) % cfg.ny, (i + dx) % cfg.nx)
                     w += tb["Su"][zt, :, :, oo] @ u[(slice(None),) + m] - tb["Ms"][zt, oo] * e0[(slice(None),) + m]
                 np.testing.assert_allclose(C @ w, s[:, k, j, i], rtol=0, atol=1e-12)
+
+
+def _cubic_class(zt, c, e, off):
+    """The coefficient classes of a stiffness cubic on the grid axes, written
+    out independently of the library: interior rows depend on which offsets
+    are non-zero (even element integrals, odd derivative rows); top rows on
+    that and on whether the neighbour lies in the plane below.  Returns
+    (key, sign); key None for a structural zero."""
+    a = [abs(v) for v in off]
+    sg = [(-1 if v < 0 else 1) for v in off]
+    if zt == 0:
+        if c == e:
+            others = sorted(a[q] for q in range(3) if q != c)
+            return ("d", a[c], tuple(others)), 1
+        if off[c] == 0 or off[e] == 0:
+            return None, 1
+        return ("o", a[3 - c - e]), sg[c] * sg[e]
+    if off[2] > 0:
+        return None, 1
+    below = off[2] < 0
+    if c < 2 and e < 2:
+        if c == e:
+            return ("td", a[c], a[1 - c], below), 1
+        if off[c] == 0 or off[e] == 0:
+            return None, 1
+        return ("to", below), sg[c] * sg[e]
+    if c == 2 and e == 2:
+        return ("tz", below, a[0] + a[1]), 1
+    if e == 2:
+        return (("tcz", a[1 - c], below), sg[c]) if off[c] != 0 else (None, 1)
+    return (("tzc", a[1 - e], below), sg[e]) if off[e] != 0 else (None, 1)
+
+
+@pytest.mark.parametrize("C", [(1.7, 0.8, 0.5), (2.3, 1.1, 0.9), (1.0, 0.3, 0.35)])
+def test_cubic_stiffness_has_the_compact_form(C):
+    """With a stiffness cubic on the grid axes the FEM kernels take each of
+    the 27-point coefficients from a handful of values (8 interior, 24
+    top-row classes); every table entry of a class must be the same value up
+    to its sign, and the structural zeros zero."""
+    cfg = PFConfig(nx=8, ny=8, nz=6, C11=C[0], C12=C[1], C44=C[2])
+    K = pf.pf_fem_tables(cfg)["K"]
+    kmax = np.abs(K).max()
+    for zt in range(2):
+        seen = {}
+        for c in range(3):
+            for e in range(3):
+                for o in range(27):
+                    off = (o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1)
+                    key, sgn = _cubic_class(zt, c, e, off)
+                    v = K[zt, c, e, o]
+                    if key is None:
+                        assert abs(v) <= 1e-12 * kmax, (zt, c, e, off, v)
+                        continue
+                    ref = seen.setdefault(key, sgn * v)
+                    assert abs(v - sgn * ref) <= 1e-12 * kmax, (zt, c, e, off, v, ref)
+        assert len(seen) == (8 if zt == 0 else 24)
