@@ -35,15 +35,17 @@ HBM_PEAK_GBS = 8000.0
 #   force          P, V (48) + phi (8) + u (24) read; P, V (48) written
 #   mg_u0          FEM multigrid on the solver grid, one residual of the first
 #                  sweep (b (24) read, out (24) written) and one last sweep
-#                  (x, b (48) read, out (24) written) per V-cycle: 60 on
+#                  that forms x from b and the next level's correction
+#                  (b (24) + correction (3: level 1 has about 1/8 of the
+#                  nodes) read, out (24) written) per V-cycle: 49.5 on
 #                  average                                        (rows k >= 1)
-#   mg_phi0        the same for the Poisson operator: (16 + 24) / 2 = 20
+#   mg_phi0        the same for the Poisson operator: (16 + 17) / 2 = 16.5
 #   finish         x, p read, x written (Poisson 24, FEM 72 per node)
 # The Poisson classes run over the potential grid (the film plus, with the
 # open top, the air planes), the others over the film.
 BYTES_PER_NODE_FP64 = {
     "poisson_setup": 72, "poisson_a": 40, "poisson_b": 24, "fem_setup": 120, "fem_a": 120, "fem_b": 72,
-    "force": 128, "mg_u0": 60, "mg_phi0": 20,
+    "force": 128, "mg_u0": 49.5, "mg_phi0": 16.5,
 }
 
 
@@ -54,7 +56,6 @@ BYTES_PER_NODE_FP64 = {
 # profiles/mg_fine_fp64_lateral_256x256x64.md.  Keyed by workload, precision
 # and kernel class; anything else reports null.
 MEASURED_TRAFFIC = {
-    ("lateral_256x256x64", "fp64", "mg_u0"): 260.7e6,
     ("lateral_256x256x64", "fp64", "fem_a"): 604.6e6,
 }
 

@@ -30,8 +30,8 @@ std::vector<MgLevel> mg_plan(const pf_config& cfg);
 std::vector<MgLevel> mg_plan_phi(const pf_config& cfg);
 template <typename T>
 hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const double* dinv, int mode,
-                          double omega, const T* x, const T* b, T* out, const CgScalars* sc, double* partials,
-                          int pstride, int poff, hipStream_t s);
+                          double omega, const T* x, const T* b, T* out, const MgCoarse<T>& mc, const CgScalars* sc,
+                          double* partials, int pstride, int poff, hipStream_t s);
 template <typename T>
 hipError_t launch_mg_level(const Dims& d, int nc, const double* tab, const double* dinv, int mode, double omega,
                            const T* x, const T* b, T* out, const CgScalars* sc, int top_fixed, hipStream_t s);
@@ -51,8 +51,9 @@ hipError_t launch_mg_dense(const Dims& d, int nc, int n, const double* M, const 
                            hipStream_t s);
 template <typename T>
 hipError_t launch_mgp_fine(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const double* dinv, int mode,
-                           double omega, const T* x, const T* b, T* out, const uint8_t* emask, const CgScalars* sc,
-                           double* partials, int pstride, int poff, hipStream_t s);
+                           double omega, const T* x, const T* b, T* out, const MgCoarse<T>& mc,
+                           const uint8_t* emask, const CgScalars* sc, double* partials, int pstride, int poff,
+                           hipStream_t s);
 
 // kernel launchers (pf_kernels.hip)
 int node_blocks(const Dims& d);
@@ -880,7 +881,8 @@ bool mg_on(const pf_ctx* c, int f) { return !c->mg[f].levels.empty(); }
 // One multigrid V-cycle z0 = M r0 of the Poisson (f = 0) or the FEM (f = 1)
 // operator (pre-smoothing: one damped Jacobi sweep from zero; residual,
 // restriction, the coarser levels, prolongation; post-smoothing: one sweep),
-// symmetric, so CG may use it.  The first sweep is never stored: on the
+// symmetric, so CG may use it.  When level 1 halves x and y, the last
+// prolongation happens inside the post-smoothing kernel (kMgCorrect).  The first sweep is never stored: on the
 // solver grid the residual kernel applies A to omega D^-1 b on the fly
 // (kMgFirst), on the coarser levels it runs with the stencils of
 // A omega D^-1 (folded on the host), and the prolongation forms
@@ -909,12 +911,23 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   auto run = [&](auto&& fn) { return timed(c, PF_KC_MG, f, k, fn); };
   // the solver grid: the Poisson levels count a fixed bottom plane below it
   const int zoff0 = f == 0 ? 1 : 0;
+  // the correction of level 1 as the kMgCorrect kernels read it
+  MgCoarse<T> mc{};
+  mc.e = V(L.o[1]);
+  mc.zmap = Zm(1);
+  mc.N = D[1].N;
+  mc.plane = D[1].plane;
+  mc.nx = D[1].nx, mc.ny = D[1].ny, mc.nz = D[1].nz;
+  mc.zoff = zoff0;
+  mc.top_fixed = top;
   auto fine = [&](int mode, double omega, const T* x, T* out, double* pp) {
     if (f == 0)
-      return launch_mgp_fine<T>(D[0], c->tm_p, cf, Dv(0), mode, omega, x, r0, out,
-                                mode == kMgSweep ? emask(c) : nullptr, sc, pp, pstride, poff, st);
-    return launch_mg_fine<T>(D[0], c->tm_f, tb, gen, Dv(0), mode, omega, x, r0, out, sc, pp, pstride, poff, st);
+      return launch_mgp_fine<T>(D[0], c->tm_p, cf, Dv(0), mode, omega, x, r0, out, mc,
+                                mode != kMgFirst ? emask(c) : nullptr, sc, pp, pstride, poff, st);
+    return launch_mg_fine<T>(D[0], c->tm_f, tb, gen, Dv(0), mode, omega, x, r0, out, mc, sc, pp, pstride, poff, st);
   };
+  // level 1 halves x and y: the last prolongation is fused into the sweep
+  const bool fused = h.levels[1].cx && h.levels[1].cy && D[0].nx == 2 * D[1].nx && D[0].ny == 2 * D[1].ny;
   const Dims& d0 = D[0];
   const double om0 = h.levels[0].omega;
   T* v0 = V(L.v0);
@@ -976,6 +989,10 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
                                   sc, top, st);
       });
   }
+  if (fused) {
+    if (e == hipSuccess) e = run0([&] { return fine(kMgCorrect, om0, nullptr, z0, part); });
+    return e;
+  }
   if (e == hipSuccess)
     e = run([&] {
       return launch_mg_prolong<T>(d0, D[1], nc, h.levels[1].cx, h.levels[1].cy, Zm(1), V(L.o[1]), v0, sc, zoff0, 0,
@@ -1015,8 +1032,10 @@ std::function<hipError_t(int)> poisson_iteration(pf_ctx* c, const Coefs<T>& cf, 
       e = timed(c, PF_KC_POISSON_B, 0, k,
                 [&] { return launch_poisson_cg_b<T>(d, c->tm_p, cf, pb[(k + 1) & 1], r, em, sc, part, strm(c)); });
     // multigrid: z = M r replaces the Jacobi-weighted r.z of kernel B
+    // (with multigrid the convergence test comes first, so the last iteration runs no V-cycle)
+    if (e == hipSuccess && mg) e = reduce(c, part, c->tm_p.nblocks, 2, 0, kRedCheck, tol, 0, nullptr, 0, k);
     if (e == hipSuccess && mg) e = mg_vcycle<T>(c, 0, r, z, sc, part, 2, 0, k);
-    if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 2, 0, kRedBeta, tol, 0, nullptr, 0, k);
+    if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 2, 0, mg ? kRedConj : kRedBeta, tol, 0, nullptr, 0, k);
     return e;
   };
 }
@@ -1041,8 +1060,10 @@ std::function<hipError_t(int)> fem_iteration(pf_ctx* c, T* r, T* const pb[2], T*
                   return launch_fem_cg_b<T>(d, c->tm_f, tb, c->gen, pb[(k + 1) & 1], r, sc, part, strm(c));
                 });
     // multigrid: z = M r replaces the Jacobi-weighted r.z of kernel B
+    // (with multigrid the convergence test comes first, so the last iteration runs no V-cycle)
+    if (e == hipSuccess && mg) e = reduce(c, part, c->tm_f.nblocks, 2, 1, kRedCheck, tol, 0, nullptr, 1, k);
     if (e == hipSuccess && mg) e = mg_vcycle<T>(c, 1, r, z, sc, part, 2, 0, k);
-    if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 2, 1, kRedBeta, tol, 0, nullptr, 1, k);
+    if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 2, 1, mg ? kRedConj : kRedBeta, tol, 0, nullptr, 1, k);
     return e;
   };
 }

@@ -138,14 +138,16 @@ struct Material {
 };
 
 // Modes of the single-block reduce kernel.
-enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2, kRedOuter = 3, kRedSum = 4, kRedRho = 5 };
+enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2, kRedOuter = 3, kRedSum = 4, kRedRho = 5, kRedCheck = 6, kRedConj = 7 };
 
 // Multigrid hierarchy of the FEM operator (built on the host, pf_mg.cpp).
 // Level kernels: out = b - A x (kMgResidual), one damped Jacobi sweep
 // out = x + omega D^-1 (b - A x) (kMgSweep), or (solver-grid kernels only)
 // the residual of the first sweep from zero, out = b - A (omega D^-1 b), with
-// x not read (kMgFirst).
-enum { kMgResidual = 0, kMgSweep = 1, kMgFirst = 2 };
+// x not read (kMgFirst), or the sweep of kMgSweep from x = omega D^-1 b + P e,
+// x formed on the fly from b and the correction e of the next level, when
+// that level halves x and y (kMgCorrect: the prolongation is never stored).
+enum { kMgResidual = 0, kMgSweep = 1, kMgFirst = 2, kMgCorrect = 3 };
 constexpr int kMgMaxLevels = 12;
 constexpr int64_t kMgDenseMax = 512;  // coarsest level solved by a dense inverse up to this many unknowns
 
@@ -154,6 +156,19 @@ constexpr int64_t kMgDenseMax = 512;  // coarsest level solved by a dense invers
 struct MgZ {
   int lo, hi;
   double wlo, whi;
+};
+
+// The correction e of the next coarser level, read by the kMgCorrect
+// solver-grid kernels: NC components of N values each; zmap gives the coarse
+// z parents of the fine plane with extended index k + zoff (k the stored
+// plane); the plane 0 and, with top_fixed, the top plane carry zero.
+template <typename T>
+struct MgCoarse {
+  const T* e;
+  const MgZ* zmap;
+  int64_t N, plane;
+  int nx, ny, nz;
+  int zoff, top_fixed;
 };
 
 struct MgLevel {

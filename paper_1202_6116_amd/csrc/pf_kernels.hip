@@ -188,13 +188,19 @@ __device__ __forceinline__ void stage_store(T (&ring)[3][NC][TY + 2][kHX], const
 //              the outer test still needs, max(tol2, tol ||b|| / (2 ||r||)),
 //              tol2 being the floor that FP32 arithmetic can reach
 //   kRedSum    plain sums written to out[0..NV-1]
+//   kRedCheck  r.r (second value) after the residual update: iteration
+//              count and convergence, decided before the preconditioner
+//              runs (so the last iteration applies none)
+//   kRedConj   r.z (first value) of the preconditioned residual -> beta
 constexpr int kRedThreads = 1024;
 
 template <int NV>
 __global__ __launch_bounds__(kRedThreads) void cg_reduce_kernel(const double* __restrict__ partials, int nblocks,
                                                                 CgScalars* sc, int mode, double tol, int maxit,
                                                                 double tol2, double* out) {
-  if ((mode == kRedAlpha || mode == kRedBeta || mode == kRedRho) && sc->done) return;
+  if ((mode == kRedAlpha || mode == kRedBeta || mode == kRedRho || mode == kRedCheck || mode == kRedConj) &&
+      sc->done)
+    return;
   __shared__ double red[NV][kRedThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double s[NV];
@@ -279,6 +285,22 @@ __global__ __launch_bounds__(kRedThreads) void cg_reduce_kernel(const double* __
   } else if (mode == kRedAlpha) {
     if (!finite(a[0]) || !(a[0] > 0.0)) sc->done = kNonFinite;
     else sc->alpha = sc->rho / a[0];
+  } else if (mode == kRedCheck) {
+    const double rr = a[NV > 1 ? 1 : 0];
+    const int it = sc->iter + 1;
+    sc->iter = it;
+    sc->rnorm2 = rr;
+    if (!finite(rr)) sc->done = kNonFinite;
+    else if (converged(rr, sc->bnorm2, sc->tol)) sc->done = kConverged;
+    else if (it >= sc->maxit) sc->done = kMaxIt;
+  } else if (mode == kRedConj) {
+    const double rz = a[0];
+    if (!finite(rz) || !(rz > 0.0)) {
+      sc->done = kNonFinite;
+    } else {
+      sc->beta = rz / sc->rho;
+      sc->rho = rz;
+    }
   } else {
     const double rz = a[0], rr = a[NV > 1 ? 1 : 0];
     const int it = sc->iter + 1;
@@ -1212,19 +1234,115 @@ __device__ __forceinline__ void block_sum_to(double v, double* dst) {
   }
 }
 
+// The coarse correction at the nodes of a tile and its halo (kMgCorrect).
+// With x and y halved, a fine node i has the coarse parents i >> 1 and
+// (i + 1) >> 1 along each axis (one parent when i is even).  For each fine
+// plane the footprint of the tile, CX x CY coarse columns starting at
+// (i0 / 2 - 1, j0 / 2 - 1), is z-interpolated into an LDS table; halo point
+// (hx, hy) then has its parents in table columns (hx + 1) >> 1, (hx >> 1) + 1
+// and rows (hy + 1) >> 1, (hy >> 1) + 1 (i0 and j0 even).
+template <int TY>
+struct CoarseTile {
+  static constexpr int CX = kBX / 2 + 2, CY = TY / 2 + 2, NP = CX * CY;
+};
+static_assert(CoarseTile<kBY>::NP <= kThreads, "one coarse column per thread");
+
+template <typename T, int NC>
+struct CoarseRegs {
+  int64_t col;  // the coarse column this thread stages, -1 if none
+  double w[2];  // z weights of the two parents of the plane being staged
+  T v[2][NC];
+};
+
+__device__ __forceinline__ int pmod(int a, int n) { return ((a % n) + n) % n; }
+
+template <int TY, typename T, int NC>
+__device__ __forceinline__ void coarse_init(CoarseRegs<T, NC>& cr, const MgCoarse<T>& mc, int i0, int j0) {
+  using C = CoarseTile<TY>;
+  const int t = tid_flat();
+  cr.col = -1;
+  if (t < C::NP)
+    cr.col = pmod(i0 / 2 - 1 + t % C::CX, mc.nx) + (int64_t)mc.nx * pmod(j0 / 2 - 1 + t / C::CX, mc.ny);
+}
+
+// Loads the coarse parents of stored fine plane k (weights zero outside the
+// fine planes [0, fnz) and for fixed coarse planes).
+template <typename T, int NC>
+__device__ __forceinline__ void coarse_fetch(CoarseRegs<T, NC>& cr, const MgCoarse<T>& mc, int k, int fnz) {
+#pragma unroll
+  for (int t = 0; t < 2; t++) {
+    cr.w[t] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; c++) cr.v[t][c] = 0;
+  }
+  if (cr.col < 0 || k < 0 || k >= fnz) return;
+  const MgZ z = mc.zmap[k + mc.zoff];
+  const int zi[2] = {z.lo, z.hi};
+  const double zw[2] = {z.wlo, z.whi};
+#pragma unroll
+  for (int t = 0; t < 2; t++) {
+    if (zw[t] == 0.0 || zi[t] == 0 || (mc.top_fixed && zi[t] == mc.nz - 1)) continue;
+    cr.w[t] = zw[t];
+#pragma unroll
+    for (int c = 0; c < NC; c++) cr.v[t][c] = mc.e[c * mc.N + cr.col + mc.plane * zi[t]];
+  }
+}
+
+template <int TY, typename T, int NC>
+__device__ __forceinline__ void coarse_store(double (&E)[2][NC][CoarseTile<TY>::CY][CoarseTile<TY>::CX],
+                                             const CoarseRegs<T, NC>& cr, int k) {
+  using C = CoarseTile<TY>;
+  if (cr.col < 0) return;
+  const int t = tid_flat();
+#pragma unroll
+  for (int c = 0; c < NC; c++)
+    E[k & 1][c][t / C::CX][t % C::CX] = cr.w[0] * (double)cr.v[0][c] + cr.w[1] * (double)cr.v[1][c];
+}
+
+template <int TY, int NC>
+__device__ __forceinline__ double coarse_interp(const double (&E)[2][NC][CoarseTile<TY>::CY][CoarseTile<TY>::CX],
+                                                int k, int c, int hx, int hy) {
+  const int a0 = (hx + 1) >> 1, a1 = (hx >> 1) + 1, b0 = (hy + 1) >> 1, b1 = (hy >> 1) + 1;
+  const double(&e)[CoarseTile<TY>::CY][CoarseTile<TY>::CX] = E[k & 1][c];
+  return 0.5 * (0.5 * (e[b0][a0] + e[b0][a1]) + 0.5 * (e[b1][a0] + e[b1][a1]));
+}
+
+// stage_store with the halo coordinates passed to comb(k, raw, out, hx, hy).
+template <int TY, typename T, int NC, int RAW, int NPT, typename Comb>
+__device__ __forceinline__ void stage_store_xy(T (&ring)[3][NC][TY + 2][kHX], const Stage<T, RAW, NPT>& st, int k,
+                                               Comb comb) {
+  using H = Halo<TY>;
+  const int s = slot_of(k);
+#pragma unroll
+  for (int q = 0; q < NPT; q++) {
+    const int t = tid_flat() + q * kThreads;
+    if (t < H::HP) {
+      const int hx = t % kHX, hy = t / kHX;
+      T out[NC];
+      comb(k, st.v[q], out, hx, hy);
+#pragma unroll
+      for (int c = 0; c < NC; c++) ring[s][c][hy][hx] = out[c];
+    }
+  }
+}
+
 // Fine level: out = b - K x (kMgResidual), out = x + omega D^-1 (b - K x)
-// (kMgSweep) or out = b - K (omega D^-1 b) (kMgFirst); with partials, the
-// tile's sum of b . out goes to partials[lid * pstride + poff].  D^-1 of the
-// fine level is the Jacobi weight of the FEM tables (interior or top row).
-template <typename T, bool GEN, bool FIRST>
+// (kMgSweep), out = b - K (omega D^-1 b) (kMgFirst), or the sweep from
+// x = omega D^-1 b + P e (kMgCorrect, e from mc); with partials, the tile's
+// sum of b . out goes to partials[lid * pstride + poff].  D^-1 of the fine
+// level is the Jacobi weight of the FEM tables (interior or top row).
+template <typename T, bool GEN, int MODE>
 __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
-                                                           const double* __restrict__ dinv, int mode, double omega,
+                                                           const double* __restrict__ dinv, double omega,
                                                            const T* __restrict__ x, const T* __restrict__ b,
-                                                           T* __restrict__ out, const CgScalars* sc, double* partials,
-                                                           int pstride, int poff) {
+                                                           T* __restrict__ out, MgCoarse<T> mc, const CgScalars* sc,
+                                                           double* partials, int pstride, int poff) {
   if (sc->done) return;
   constexpr int TY = kBY;
+  constexpr bool FIRST = MODE == kMgFirst, CORR = MODE == kMgCorrect;
+  using C = CoarseTile<TY>;
   __shared__ T ring[3][3][TY + 2][kHX];
+  __shared__ double E[2][CORR ? 3 : 1][CORR ? C::CY : 1][CORR ? C::CX : 1];
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
@@ -1240,12 +1358,27 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
       for (int c = 0; c < 3; c++) raw[c] = (T)(omega * tb->inv_diag[zt][c]) * b[c * N + m];
     } else {
 #pragma unroll
-      for (int c = 0; c < 3; c++) raw[c] = x[c * N + m];
+      for (int c = 0; c < 3; c++) raw[c] = (CORR ? b : x)[c * N + m];
     }
   };
   auto comb = [&](int, const T* raw, T* o) {
 #pragma unroll
     for (int c = 0; c < 3; c++) o[c] = raw[c];
+  };
+  // kMgCorrect: x = omega D^-1 b + P e on the planes with unknowns (1 .. nz-1)
+  auto comb_corr = [&](int k, const T* raw, T* o, int hx, int hy) {
+    const bool live = k > 0 && k < d.nz;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      if constexpr (CORR)
+        o[c] = live ? (T)(omega * dinv[3 * k + c] * (double)raw[c] + coarse_interp<TY, 3>(E, k, c, hx, hy)) : (T)0;
+      else
+        o[c] = raw[c];
+    }
+  };
+  auto put = [&](const auto& stg, int k) {
+    if constexpr (CORR) stage_store_xy<TY>(ring, stg, k, comb_corr);
+    else stage_store<TY>(ring, stg, k, comb);
   };
   auto centre = [&](int k, T* cv) {
 #pragma unroll
@@ -1256,18 +1389,38 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
       for (int c = 0; c < 3; c++) cv[c] = b[c * N + n];
     }
   };
+  CoarseRegs<T, CORR ? 3 : 1> cr;
+  if constexpr (CORR) {
+    // the coarse tables of planes k0 - 1 and k0 precede their ring slots;
+    // the one of k0 + 1 is written once nothing reads its buffer (k0 - 1)
+    coarse_init<TY>(cr, mc, tc.i0, tc.j0);
+    coarse_fetch(cr, mc, tc.k0 - 1, d.nz);
+    coarse_store<TY>(E, cr, tc.k0 - 1);
+    coarse_fetch(cr, mc, tc.k0, d.nz);
+    coarse_store<TY>(E, cr, tc.k0);
+    coarse_fetch(cr, mc, tc.k0 + 1, d.nz);
+    __syncthreads();
+  }
   Stage<T, 3, Halo<TY>::NPT> st;
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
-  stage_store<TY>(ring, st, tc.k0 - 1, comb);
+  put(st, tc.k0 - 1);
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
-  stage_store<TY>(ring, st, tc.k0, comb);
+  put(st, tc.k0);
+  if constexpr (CORR) {
+    __syncthreads();
+    coarse_store<TY>(E, cr, tc.k0 + 1);
+    __syncthreads();
+  }
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
   T cv[3];
   centre(tc.k0, cv);
   double acc = 0.0;
   for (int k = tc.k0; k < tc.k1; k++) {
-    stage_store<TY>(ring, st, k + 1, comb);
-    if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
+    put(st, k + 1);
+    if (k + 2 <= tc.k1) {
+      stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
+      if constexpr (CORR) coarse_fetch(cr, mc, k + 2, d.nz);
+    }
     T nv[3];
     centre(k + 1, nv);
     __syncthreads();
@@ -1285,11 +1438,15 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
 #pragma unroll
       for (int c = 0; c < 3; c++) {
         const T r = cv[c] - q[c];
-        const T o = mode != kMgSweep ? r : ring[s0][c][ly + 1][lx + 1] + (T)(omega * dinv[3 * k + c]) * r;
+        const T o = (MODE == kMgSweep || CORR) ? ring[s0][c][ly + 1][lx + 1] + (T)(omega * dinv[3 * k + c]) * r : r;
         out[c * N + n] = o;
         acc += (double)cv[c] * (double)o;
       }
     }
+    // the table of plane k + 2 reuses the buffer of plane k, last read
+    // before the barrier above
+    if constexpr (CORR)
+      if (k + 2 <= tc.k1) coarse_store<TY>(E, cr, k + 2);
 #pragma unroll
     for (int c = 0; c < 3; c++) cv[c] = nv[c];
     __syncthreads();
@@ -1630,35 +1787,68 @@ __global__ __launch_bounds__(256) void mg_dense_kernel(Dims d, int n, const doub
 // emask the output is zeroed on the electrode nodes (the preconditioner of
 // the reduced system), and with partials the tile's b . out goes to
 // partials[lid * pstride + poff].
-template <typename T, bool FIRST>
+template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void mgp_fine_kernel(Dims d, TileMap tm, Coefs<T> cf,
-                                                            const double* __restrict__ dinv, int mode, double omega,
+                                                            const double* __restrict__ dinv, double omega,
                                                             const T* __restrict__ x, const T* __restrict__ b,
-                                                            T* __restrict__ out, const uint8_t* __restrict__ emask,
-                                                            const CgScalars* sc, double* partials, int pstride,
-                                                            int poff) {
+                                                            T* __restrict__ out, MgCoarse<T> mc,
+                                                            const uint8_t* __restrict__ emask, const CgScalars* sc,
+                                                            double* partials, int pstride, int poff) {
   if (sc->done) return;
   constexpr int TY = kBY;
+  constexpr bool FIRST = MODE == kMgFirst, CORR = MODE == kMgCorrect;
+  using C = CoarseTile<TY>;
   __shared__ T ring[3][1][TY + 2][kHX];
+  __shared__ double E[2][1][CORR ? C::CY : 1][CORR ? C::CX : 1];
   const T c6 = cf.eps_over_h2;
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
   const bool valid = i < d.nx && j < d.ny;
   const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
-  auto fetch = [&](int64_t m, int k, T* raw) { raw[0] = FIRST ? (T)(omega * dinv[k]) * b[m] : x[m]; };
+  auto fetch = [&](int64_t m, int k, T* raw) { raw[0] = FIRST ? (T)(omega * dinv[k]) * b[m] : (CORR ? b : x)[m]; };
   auto comb = [&](int, const T* raw, T* o) { o[0] = raw[0]; };
+  // kMgCorrect: x = omega D^-1 b + P e on the stored planes
+  auto comb_corr = [&](int k, const T* raw, T* o, int hx, int hy) {
+    if constexpr (CORR)
+      o[0] = k >= 0 && k < d.nz ? (T)(omega * dinv[k] * (double)raw[0] + coarse_interp<TY, 1>(E, k, 0, hx, hy))
+                                : (T)0;
+    else
+      o[0] = raw[0];
+  };
+  auto put = [&](const auto& stg, int k) {
+    if constexpr (CORR) stage_store_xy<TY>(ring, stg, k, comb_corr);
+    else stage_store<TY>(ring, stg, k, comb);
+  };
+  CoarseRegs<T, 1> cr;
+  if constexpr (CORR) {
+    coarse_init<TY>(cr, mc, tc.i0, tc.j0);
+    coarse_fetch(cr, mc, tc.k0 - 1, d.nz);
+    coarse_store<TY>(E, cr, tc.k0 - 1);
+    coarse_fetch(cr, mc, tc.k0, d.nz);
+    coarse_store<TY>(E, cr, tc.k0);
+    coarse_fetch(cr, mc, tc.k0 + 1, d.nz);
+    __syncthreads();
+  }
   Stage<T, 1, Halo<TY>::NPT> st;
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
-  stage_store<TY>(ring, st, tc.k0 - 1, comb);
+  put(st, tc.k0 - 1);
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
-  stage_store<TY>(ring, st, tc.k0, comb);
+  put(st, tc.k0);
+  if constexpr (CORR) {
+    __syncthreads();
+    coarse_store<TY>(E, cr, tc.k0 + 1);
+    __syncthreads();
+  }
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
   T cb = valid ? b[col + d.plane * tc.k0] : (T)0;
   double acc = 0.0;
   for (int k = tc.k0; k < tc.k1; k++) {
-    stage_store<TY>(ring, st, k + 1, comb);
-    if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
+    put(st, k + 1);
+    if (k + 2 <= tc.k1) {
+      stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
+      if constexpr (CORR) coarse_fetch(cr, mc, k + 2, d.nz);
+    }
     const T nb = (valid && k + 1 < tc.k1) ? b[col + d.plane * (k + 1)] : (T)0;
     __syncthreads();
     if (valid) {
@@ -1675,11 +1865,15 @@ __global__ __launch_bounds__(kThreads) void mgp_fine_kernel(Dims d, TileMap tm, 
         q = e.xy * (4 * pc - sxy) + e.up * (pc - pup) + e.dn * (pc - pdn);
       }
       const T r = cb - q;
-      T o = mode != kMgSweep ? r : pc + (T)(omega * dinv[k]) * r;
+      T o = (MODE == kMgSweep || CORR) ? pc + (T)(omega * dinv[k]) * r : r;
       if (emask != nullptr && k == d.nzf && emask[col] != 0) o = 0;
       out[col + d.plane * k] = o;
       acc += (double)cb * (double)o;
     }
+    // the table of plane k + 2 reuses the buffer of plane k, last read
+    // before the barrier above
+    if constexpr (CORR)
+      if (k + 2 <= tc.k1) coarse_store<TY>(E, cr, k + 2);
     cb = nb;
     __syncthreads();
   }
@@ -2420,19 +2614,25 @@ hipError_t launch_fem_cg_b(const Dims& d, const TileMap& tm, const FemTables* tb
 
 template <typename T>
 hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const double* dinv, int mode,
-                          double omega, const T* x, const T* b, T* out, const CgScalars* sc, double* partials,
-                          int pstride, int poff, hipStream_t s) {
-#define PF_MG_FINE(GEN, FIRST)                                                                              \
-  mg_fine_kernel<T, GEN, FIRST><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, dinv, mode, omega, x, b, out, sc, \
-                                                                    partials, pstride, poff)
-  const bool first = mode == kMgFirst;
-  if (gen) {
-    if (first) PF_MG_FINE(true, true);
-    else PF_MG_FINE(true, false);
-  } else {
-    if (first) PF_MG_FINE(false, true);
-    else PF_MG_FINE(false, false);
+                          double omega, const T* x, const T* b, T* out, const MgCoarse<T>& mc, const CgScalars* sc,
+                          double* partials, int pstride, int poff, hipStream_t s) {
+  if (mode == kMgCorrect && (tm.ty % 2 != 0 || d.nx != 2 * mc.nx || d.ny != 2 * mc.ny)) return hipErrorInvalidValue;
+#define PF_MG_FINE(GEN, MODE)                                                                                  \
+  mg_fine_kernel<T, GEN, MODE><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, dinv, omega, x, b, out, mc, sc, \
+                                                                   partials, pstride, poff)
+#define PF_MG_FINE_MODES(GEN)                  \
+  switch (mode) {                              \
+    case kMgSweep: PF_MG_FINE(GEN, kMgSweep); break;     \
+    case kMgFirst: PF_MG_FINE(GEN, kMgFirst); break;     \
+    case kMgCorrect: PF_MG_FINE(GEN, kMgCorrect); break; \
+    default: return hipErrorInvalidValue;      \
   }
+  if (gen) {
+    PF_MG_FINE_MODES(true)
+  } else {
+    PF_MG_FINE_MODES(false)
+  }
+#undef PF_MG_FINE_MODES
 #undef PF_MG_FINE
   return hipGetLastError();
 }
@@ -2517,14 +2717,20 @@ hipError_t launch_mg_dense(const Dims& d, int nc, int n, const double* M, const 
 
 template <typename T>
 hipError_t launch_mgp_fine(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const double* dinv, int mode,
-                           double omega, const T* x, const T* b, T* out, const uint8_t* emask, const CgScalars* sc,
-                           double* partials, int pstride, int poff, hipStream_t s) {
-  if (mode == kMgFirst)
-    mgp_fine_kernel<T, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, dinv, mode, omega, x, b, out, emask, sc,
-                                                               partials, pstride, poff);
-  else
-    mgp_fine_kernel<T, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, dinv, mode, omega, x, b, out, emask, sc,
-                                                                partials, pstride, poff);
+                           double omega, const T* x, const T* b, T* out, const MgCoarse<T>& mc,
+                           const uint8_t* emask, const CgScalars* sc, double* partials, int pstride, int poff,
+                           hipStream_t s) {
+  if (mode == kMgCorrect && (tm.ty % 2 != 0 || d.nx != 2 * mc.nx || d.ny != 2 * mc.ny)) return hipErrorInvalidValue;
+#define PF_MGP_FINE(MODE)                                                                                          \
+  mgp_fine_kernel<T, MODE><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, dinv, omega, x, b, out, mc, emask, sc, \
+                                                               partials, pstride, poff)
+  switch (mode) {
+    case kMgSweep: PF_MGP_FINE(kMgSweep); break;
+    case kMgFirst: PF_MGP_FINE(kMgFirst); break;
+    case kMgCorrect: PF_MGP_FINE(kMgCorrect); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PF_MGP_FINE
   return hipGetLastError();
 }
 
@@ -2621,8 +2827,8 @@ PF_INSTANTIATE(float)
 
 #define PF_INSTANTIATE_MG(T)                                                                                     \
   template hipError_t launch_mg_fine<T>(const Dims&, const TileMap&, const FemTables*, bool, const double*, int,  \
-                                        double, const T*, const T*, T*, const CgScalars*, double*, int, int,       \
-                                        hipStream_t);                                                             \
+                                        double, const T*, const T*, T*, const MgCoarse<T>&, const CgScalars*,     \
+                                        double*, int, int, hipStream_t);                                          \
   template hipError_t launch_mg_level<T>(const Dims&, int, const double*, const double*, int, double, const T*,   \
                                          const T*, T*, const CgScalars*, int, hipStream_t);                       \
   template hipError_t launch_mg_scale<T>(const Dims&, int, const double*, double, const T*, T*, const CgScalars*, \
@@ -2635,8 +2841,8 @@ PF_INSTANTIATE(float)
   template hipError_t launch_mg_dense<T>(const Dims&, int, int, const double*, const T*, T*, const CgScalars*,    \
                                          hipStream_t);                                                            \
   template hipError_t launch_mgp_fine<T>(const Dims&, const TileMap&, const Coefs<T>&, const double*, int,        \
-                                         double, const T*, const T*, T*, const uint8_t*, const CgScalars*,        \
-                                         double*, int, int, hipStream_t);
+                                         double, const T*, const T*, T*, const MgCoarse<T>&, const uint8_t*,      \
+                                         const CgScalars*, double*, int, int, hipStream_t);
 
 PF_INSTANTIATE_MG(double)
 PF_INSTANTIATE_MG(float)
