@@ -1457,7 +1457,11 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
 // Coarse level (per-plane stencils tab[k][c][e][o], NC components): out =
 // b - A x or out = x + omega D^-1 (b - A x).  Plane 0 and, with top_fixed,
 // the top plane hold no unknowns (never written, zero).  One thread per node.
-template <typename T, int NC>
+// With STAGE the block first copies its plane's stencil into LDS (one load
+// per thread): the scalar loads of the NC x NC x 27 coefficients, more than
+// the scalar registers hold, would otherwise form a chain of round trips
+// that dominates the launch on the small levels.
+template <typename T, int NC, bool STAGE>
 __global__ __launch_bounds__(kThreads) void mg_level_kernel(Dims d, const double* __restrict__ tab,
                                                             const double* __restrict__ dinv, int mode, double omega,
                                                             const T* __restrict__ x, const T* __restrict__ b,
@@ -1465,10 +1469,18 @@ __global__ __launch_bounds__(kThreads) void mg_level_kernel(Dims d, const double
   if (sc->done) return;
   const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
   const int ktop = d.nz - (top_fixed ? 1 : 0);
-  if (i >= d.nx || j >= d.ny || k == 0 || k >= ktop) return;
+  if (k == 0 || k >= ktop) return;  // uniform over the block
+  constexpr int NT = NC * NC * 27;
+  __shared__ double ctab[STAGE ? NT : 1];
+  const double* tk = tab + (size_t)k * NT;
+  if constexpr (STAGE) {
+    for (int t = tid_flat(); t < NT; t += kThreads) ctab[t] = tk[t];
+    __syncthreads();
+    tk = ctab;
+  }
+  if (i >= d.nx || j >= d.ny) return;
   const int64_t N = d.N;
   const int64_t n = i + (int64_t)d.nx * j + d.plane * k;
-  const double* tk = tab + (size_t)k * NC * NC * 27;
   // neighbour indices in 32 bits (coarse levels are small), per-component
   // base pointers uniform across the block
   const int pl = (int)d.plane;
@@ -2637,13 +2649,17 @@ hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb,
   return hipGetLastError();
 }
 
+// The three-component stencils are staged in LDS (the Poisson stencil fits
+// the scalar registers).
 template <typename T>
 hipError_t launch_mg_level(const Dims& d, int nc, const double* tab, const double* dinv, int mode, double omega,
                            const T* x, const T* b, T* out, const CgScalars* sc, int top_fixed, hipStream_t s) {
   if (nc == 3)
-    mg_level_kernel<T, 3><<<node_grid(d), node_block(), 0, s>>>(d, tab, dinv, mode, omega, x, b, out, sc, top_fixed);
+    mg_level_kernel<T, 3, true><<<node_grid(d), node_block(), 0, s>>>(d, tab, dinv, mode, omega, x, b, out, sc,
+                                                                     top_fixed);
   else
-    mg_level_kernel<T, 1><<<node_grid(d), node_block(), 0, s>>>(d, tab, dinv, mode, omega, x, b, out, sc, top_fixed);
+    mg_level_kernel<T, 1, false><<<node_grid(d), node_block(), 0, s>>>(d, tab, dinv, mode, omega, x, b, out, sc,
+                                                                      top_fixed);
   return hipGetLastError();
 }
 
