@@ -1326,23 +1326,23 @@ __device__ __forceinline__ void stage_store_xy(T (&ring)[3][NC][TY + 2][kHX], co
   }
 }
 
-// Fine level: out = b - K x (kMgResidual), out = x + omega D^-1 (b - K x)
-// (kMgSweep), out = b - K (omega D^-1 b) (kMgFirst), or the sweep from
-// x = omega D^-1 b + P e (kMgCorrect, e from mc); with partials, the tile's
-// sum of b . out goes to partials[lid * pstride + poff].  D^-1 of the fine
-// level is the Jacobi weight of the FEM tables (interior or top row).
-template <typename T, bool GEN, int MODE>
-__global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
-                                                           const double* __restrict__ dinv, double omega,
-                                                           const T* __restrict__ x, const T* __restrict__ b,
-                                                           T* __restrict__ out, MgCoarse<T> mc, const CgScalars* sc,
-                                                           double* partials, int pstride, int poff) {
+// Fine level, kMgCorrect: out = x + omega D^-1 (b - K x) from
+// x = omega D^-1 b + P e (e from mc), x formed while its planes are staged;
+// with partials, the tile's sum of b . out goes to partials[lid * pstride +
+// poff].  D^-1 of the fine level is the Jacobi weight of the FEM tables
+// (interior or top row).  The stiffness is applied in pull form (each node
+// reads its 27 neighbours from a three-plane LDS ring): the push form of
+// mg_fine_kernel needs more registers than this kernel can spare.
+template <typename T, bool GEN>
+__global__ __launch_bounds__(kThreads, 4) void mg_correct_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
+                                                              const double* __restrict__ dinv, double omega,
+                                                              const T* __restrict__ b, T* __restrict__ out,
+                                                              MgCoarse<T> mc, const CgScalars* sc, double* partials,
+                                                              int pstride, int poff) {
   if (sc->done) return;
   constexpr int TY = kBY;
-  constexpr bool FIRST = MODE == kMgFirst, CORR = MODE == kMgCorrect;
-  using C = CoarseTile<TY>;
   __shared__ T ring[3][3][TY + 2][kHX];
-  __shared__ double E[2][CORR ? 3 : 1][CORR ? C::CY : 1][CORR ? C::CX : 1];
+  __shared__ double E[2][3][CoarseTile<TY>::CY][CoarseTile<TY>::CX];
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
@@ -1351,35 +1351,17 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
   const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
   auto fetch = [&](int64_t m, int k, T* raw) {
     if (k == 0) return;
-    if (FIRST) {
-      // omega D^-1 b: the Jacobi weight of the row kind (interior or top), per component
-      const int zt = k == d.nz - 1 ? 1 : 0;
 #pragma unroll
-      for (int c = 0; c < 3; c++) raw[c] = (T)(omega * tb->inv_diag[zt][c]) * b[c * N + m];
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; c++) raw[c] = (CORR ? b : x)[c * N + m];
-    }
+    for (int c = 0; c < 3; c++) raw[c] = b[c * N + m];
   };
-  auto comb = [&](int, const T* raw, T* o) {
-#pragma unroll
-    for (int c = 0; c < 3; c++) o[c] = raw[c];
-  };
-  // kMgCorrect: x = omega D^-1 b + P e on the planes with unknowns (1 .. nz-1)
-  auto comb_corr = [&](int k, const T* raw, T* o, int hx, int hy) {
+  // x = omega D^-1 b + P e on the planes with unknowns (1 .. nz-1)
+  auto comb = [&](int k, const T* raw, T* o, int hx, int hy) {
     const bool live = k > 0 && k < d.nz;
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      if constexpr (CORR)
-        o[c] = live ? (T)(omega * dinv[3 * k + c] * (double)raw[c] + coarse_interp<TY, 3>(E, k, c, hx, hy)) : (T)0;
-      else
-        o[c] = raw[c];
-    }
+    for (int c = 0; c < 3; c++)
+      o[c] = live ? (T)(omega * dinv[3 * k + c] * (double)raw[c] + coarse_interp<TY, 3>(E, k, c, hx, hy)) : (T)0;
   };
-  auto put = [&](const auto& stg, int k) {
-    if constexpr (CORR) stage_store_xy<TY>(ring, stg, k, comb_corr);
-    else stage_store<TY>(ring, stg, k, comb);
-  };
+  auto put = [&](const auto& stg, int k) { stage_store_xy<TY>(ring, stg, k, comb); };
   auto centre = [&](int k, T* cv) {
 #pragma unroll
     for (int c = 0; c < 3; c++) cv[c] = 0;
@@ -1389,28 +1371,24 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
       for (int c = 0; c < 3; c++) cv[c] = b[c * N + n];
     }
   };
-  CoarseRegs<T, CORR ? 3 : 1> cr;
-  if constexpr (CORR) {
-    // the coarse tables of planes k0 - 1 and k0 precede their ring slots;
-    // the one of k0 + 1 is written once nothing reads its buffer (k0 - 1)
-    coarse_init<TY>(cr, mc, tc.i0, tc.j0);
-    coarse_fetch(cr, mc, tc.k0 - 1, d.nz);
-    coarse_store<TY>(E, cr, tc.k0 - 1);
-    coarse_fetch(cr, mc, tc.k0, d.nz);
-    coarse_store<TY>(E, cr, tc.k0);
-    coarse_fetch(cr, mc, tc.k0 + 1, d.nz);
-    __syncthreads();
-  }
+  // the coarse tables of planes k0 - 1 and k0 precede their ring slots; the
+  // one of k0 + 1 is written once nothing reads its buffer (that of k0 - 1)
+  CoarseRegs<T, 3> cr;
+  coarse_init<TY>(cr, mc, tc.i0, tc.j0);
+  coarse_fetch(cr, mc, tc.k0 - 1, d.nz);
+  coarse_store<TY>(E, cr, tc.k0 - 1);
+  coarse_fetch(cr, mc, tc.k0, d.nz);
+  coarse_store<TY>(E, cr, tc.k0);
+  coarse_fetch(cr, mc, tc.k0 + 1, d.nz);
+  __syncthreads();
   Stage<T, 3, Halo<TY>::NPT> st;
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
   put(st, tc.k0 - 1);
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
   put(st, tc.k0);
-  if constexpr (CORR) {
-    __syncthreads();
-    coarse_store<TY>(E, cr, tc.k0 + 1);
-    __syncthreads();
-  }
+  __syncthreads();
+  coarse_store<TY>(E, cr, tc.k0 + 1);
+  __syncthreads();
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
   T cv[3];
   centre(tc.k0, cv);
@@ -1419,7 +1397,7 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
     put(st, k + 1);
     if (k + 2 <= tc.k1) {
       stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
-      if constexpr (CORR) coarse_fetch(cr, mc, k + 2, d.nz);
+      coarse_fetch(cr, mc, k + 2, d.nz);
     }
     T nv[3];
     centre(k + 1, nv);
@@ -1438,20 +1416,163 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
 #pragma unroll
       for (int c = 0; c < 3; c++) {
         const T r = cv[c] - q[c];
-        const T o = (MODE == kMgSweep || CORR) ? ring[s0][c][ly + 1][lx + 1] + (T)(omega * dinv[3 * k + c]) * r : r;
+        const T o = ring[s0][c][ly + 1][lx + 1] + (T)(omega * dinv[3 * k + c]) * r;
         out[c * N + n] = o;
         acc += (double)cv[c] * (double)o;
       }
     }
     // the table of plane k + 2 reuses the buffer of plane k, last read
     // before the barrier above
-    if constexpr (CORR)
-      if (k + 2 <= tc.k1) coarse_store<TY>(E, cr, k + 2);
+    if (k + 2 <= tc.k1) coarse_store<TY>(E, cr, k + 2);
 #pragma unroll
     for (int c = 0; c < 3; c++) cv[c] = nv[c];
     __syncthreads();
   }
   if (partials) block_sum_to<kThreads>(acc, partials + (int64_t)tc.lid * pstride + poff);
+}
+
+// Stiffness apply in z-push form: the node values u(dx, dy) of source plane
+// s (ld(dx, dy, u)) add their part of K u to the outputs of planes s - 1
+// (acc[0], which sees plane s at dz = +1), s (acc[1], dz = 0) and s + 1
+// (acc[2], dz = -1), each with the row kind of its own plane: Z0 and ZP are
+// those of planes s and s + 1 (0 interior, 1 top, -1 no plane).  Plane s - 1
+// is an interior row (a top row has no plane above it).  Each source value
+// is read once per plane instead of once per output plane.
+template <typename T, bool GEN, int Z0, int ZP, typename Load>
+__device__ __forceinline__ void fem_K_push(const FemTables* __restrict__ tb, Load ld, T (&acc)[3][3]) {
+#pragma unroll
+  for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+    for (int dx = -1; dx <= 1; dx++) {
+      T u[3];
+      ld(dx, dy, u);
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        const int zt = q == 0 ? 0 : (q == 1 ? Z0 : ZP);
+        const int dz = 1 - q;
+        if (zt < 0 || (zt == 1 && dz > 0)) continue;
+        const int off[3] = {dx, dy, dz};
+        const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+#pragma unroll
+          for (int e = 0; e < 3; e++) {
+            if (GEN) {
+              acc[q][c] += (T)tb->K[zt][c][e][o] * u[e];
+            } else {
+              int sg = 1;
+              const int cl = kc_class(zt, c, e, off, &sg);
+              if (cl < 0) continue;
+              const T k = (T)(zt ? tb->kc_top[cl] : tb->kc_int[cl]);
+              acc[q][c] += (sg > 0 ? k : -k) * u[e];
+            }
+          }
+      }
+    }
+}
+
+// Fine level: out = b - K (omega D^-1 b) (kMgFirst) or out = x + omega D^-1
+// (b - K x) (kMgSweep); with partials, the tile's sum of b . out goes to
+// partials[lid * pstride + poff].  D^-1 of the fine level is the Jacobi
+// weight of the FEM tables (interior or top row).  The z-march visits
+// the source planes s = k0 - 1 .. k1 once each; plane s is staged in a
+// three-slot LDS ring, pushed into the register accumulators of planes
+// s - 1, s, s + 1 (fem_K_push), and plane s - 1 is then complete.  With
+// three slots one barrier per plane suffices: the slot written while plane
+// s is pushed last held plane s - 2.
+template <typename T, bool GEN, int MODE>
+__global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
+                                                           const double* __restrict__ dinv, double omega,
+                                                           const T* __restrict__ x, const T* __restrict__ b,
+                                                           T* __restrict__ out, const CgScalars* sc, double* partials,
+                                                           int pstride, int poff) {
+  if (sc->done) return;
+  constexpr int TY = kBY;
+  constexpr bool FIRST = MODE == kMgFirst;
+  constexpr bool UPDATE = MODE == kMgSweep;  // out = x + omega D^-1 r
+  __shared__ T ring[3][3][TY + 2][kHX];
+  const TileCoord tc = tile_coord(d, tm);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
+  const int64_t N = d.N;
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  auto fetch = [&](int64_t m, int k, T* raw) {
+    if (k == 0) return;
+    if (FIRST) {
+      const int zt = k == d.nz - 1 ? 1 : 0;
+#pragma unroll
+      for (int c = 0; c < 3; c++) raw[c] = (T)(omega * tb->inv_diag[zt][c]) * b[c * N + m];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; c++) raw[c] = x[c * N + m];
+    }
+  };
+  auto comb = [&](int, const T* raw, T* o) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) o[c] = raw[c];
+  };
+  auto centre = [&](int k, T* cv) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) cv[c] = 0;
+    if (valid && k > 0 && k < tc.k1) {
+      const int64_t n = col + d.plane * k;
+#pragma unroll
+      for (int c = 0; c < 3; c++) cv[c] = b[c * N + n];
+    }
+  };
+  Stage<T, 3, Halo<TY>::NPT> st;
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store<TY>(ring, st, tc.k0 - 1, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  T acc[3][3];
+  T cvT[3], cvS[3], xT[3], xS[3];  // b and x at the centre of planes s - 1 (T) and s (S)
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    acc[0][c] = acc[1][c] = acc[2][c] = 0;
+    cvT[c] = xT[c] = xS[c] = 0;
+  }
+  double dot = 0.0;
+  for (int s = tc.k0 - 1; s <= tc.k1; s++) {
+    if (s + 1 <= tc.k1) stage_store<TY>(ring, st, s + 1, comb);
+    if (s + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, s + 2, fetch);
+    centre(s, cvS);  // used once plane s is complete, an iteration later
+    __syncthreads();
+    const int sl = slot_of(s);
+    auto ld = [&](int dx, int dy, T u[3]) {
+#pragma unroll
+      for (int c = 0; c < 3; c++) u[c] = ring[sl][c][ly + 1 + dy][lx + 1 + dx];
+    };
+    if (s > 0 && s < d.nz) {
+      if (UPDATE) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) xS[c] = ring[sl][c][ly + 1][lx + 1];
+      }
+      if (s < d.nz - 2) fem_K_push<T, GEN, 0, 0>(tb, ld, acc);
+      else if (s == d.nz - 2) fem_K_push<T, GEN, 0, 1>(tb, ld, acc);
+      else fem_K_push<T, GEN, 1, -1>(tb, ld, acc);
+    }
+    const int t = s - 1;  // complete: its last source plane was s
+    if (valid && t >= 1 && t >= tc.k0 && t < tc.k1) {
+      const int64_t n = col + d.plane * t;
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        const T r = cvT[c] - acc[0][c];
+        const T o = UPDATE ? xT[c] + (T)(omega * dinv[3 * t + c]) * r : r;
+        out[c * N + n] = o;
+        dot += (double)cvT[c] * (double)o;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      acc[0][c] = acc[1][c];
+      acc[1][c] = acc[2][c];
+      acc[2][c] = 0;
+      cvT[c] = cvS[c];
+      xT[c] = xS[c];
+    }
+  }
+  if (partials) block_sum_to<kThreads>(dot, partials + (int64_t)tc.lid * pstride + poff);
 }
 
 // Coarse level (per-plane stencils tab[k][c][e][o], NC components): out =
@@ -2630,14 +2751,17 @@ hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb,
                           double* partials, int pstride, int poff, hipStream_t s) {
   if (mode == kMgCorrect && (tm.ty % 2 != 0 || d.nx != 2 * mc.nx || d.ny != 2 * mc.ny)) return hipErrorInvalidValue;
 #define PF_MG_FINE(GEN, MODE)                                                                                  \
-  mg_fine_kernel<T, GEN, MODE><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, dinv, omega, x, b, out, mc, sc, \
-                                                                   partials, pstride, poff)
-#define PF_MG_FINE_MODES(GEN)                  \
-  switch (mode) {                              \
-    case kMgSweep: PF_MG_FINE(GEN, kMgSweep); break;     \
-    case kMgFirst: PF_MG_FINE(GEN, kMgFirst); break;     \
-    case kMgCorrect: PF_MG_FINE(GEN, kMgCorrect); break; \
-    default: return hipErrorInvalidValue;      \
+  mg_fine_kernel<T, GEN, MODE><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, dinv, omega, x, b, out, sc, partials, \
+                                                                   pstride, poff)
+#define PF_MG_CORRECT(GEN)                                                                                    \
+  mg_correct_kernel<T, GEN><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, dinv, omega, b, out, mc, sc, partials, \
+                                                                pstride, poff)
+#define PF_MG_FINE_MODES(GEN)                              \
+  switch (mode) {                                          \
+    case kMgSweep: PF_MG_FINE(GEN, kMgSweep); break;       \
+    case kMgFirst: PF_MG_FINE(GEN, kMgFirst); break;       \
+    case kMgCorrect: PF_MG_CORRECT(GEN); break;            \
+    default: return hipErrorInvalidValue;                  \
   }
   if (gen) {
     PF_MG_FINE_MODES(true)
@@ -2645,6 +2769,7 @@ hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb,
     PF_MG_FINE_MODES(false)
   }
 #undef PF_MG_FINE_MODES
+#undef PF_MG_CORRECT
 #undef PF_MG_FINE
   return hipGetLastError();
 }
