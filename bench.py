@@ -169,7 +169,7 @@ def micron_leg(pf, torch, workloads, initial_polarisation, warm_start, precond, 
             "dJ_dV": [float(v) for v in volts.grad], "dJ_da1": float(a1.grad)}
 
 
-def precision_leg(pf, torch, workloads, initial_polarisation, warm_start, precond, steps=4, warmup=2):
+def precision_leg(pf, torch, workloads, initial_polarisation, warm_start, precond, steps=10, warmup=10):
     """The 512x512x128 lateral film for a few steps in FP32 sweeps with FP64
     refinement and in plain FP64 from the same start; returns both step times
     and the per-field relative difference after the steps."""

@@ -78,7 +78,10 @@ hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>&
 template <typename T, typename S, typename R>
 hipError_t launch_fem_setup(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const FemTables* tb, bool gen,
                             const S* P, const S* V, T cdt, const T* W, T* x, R* r, R* p0, R* p1, R* dz,
-                            double* partials, hipStream_t s);
+                            T* fout, double* partials, hipStream_t s);
+template <typename T, typename R>
+hipError_t launch_fem_resid(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const T* f, T* x, R* r,
+                            R* p0, R* p1, R* dz, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_fem_cg_a(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const T* r,
                            const T* p_old, T* p_new, T* x, const CgScalars* sc, double* partials, int unit_w,
@@ -391,6 +394,7 @@ struct Layout {
   size_t phi_bc, basis;        // boundary potential and electrode basis (FP64)
   size_t pr, pp[2], fr, fp[2]; // CG vectors, sized for FP64 (FP32 solves use half)
   size_t dphi, du;             // refinement corrections (FP32)
+  size_t fbody;                // FP32_REFINE: the FEM body force of the first sweep (FP64)
   size_t hist;                 // ring of earlier solutions for extrapolated warm starts
                                // (extrap_order slots of Np (phi) then extrap_order of 3N (u))
   size_t scratch[8];           // max(3N, Np) doubles each: adjoint, energy, conversions
@@ -446,6 +450,7 @@ Layout make_layout(const pf_config& c, int npartials) {
   for (int b = 0; b < 2; b++) L.fp[b] = take(3 * N * 8);
   L.dphi = take(Np * 4);
   L.du = take(3 * N * 4);
+  L.fbody = c.precision == PF_FP32_REFINE ? take(3 * N * 8) : 0;
   L.hist = c.warm_start == 2 && c.extrap_order > 0 ? take((Np + 3 * N) * 8 * (size_t)c.extrap_order) : 0;
   for (int t = 0; t < 8; t++) L.scratch[t] = take(S * 8);
   for (int f = 0; f < 2; f++) {
@@ -1106,7 +1111,7 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
   if (!warm) PF_HIP(c, launch_fill<double>(x, 3 * d.N, 0.0, strm(c)));
   PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
     return launch_fem_setup<double, S, double>(d, c->tm_f, cf, tb, c->gen, P, V, cdt, W, x, r, pb[0], pb[1], nullptr,
-                                               part, strm(c));
+                                               nullptr, part, strm(c));
   }));
   PF_HIP(c, reduce(c, part, c->tm_f.nblocks, 3, 1, kRedSetup, tol, 0, nullptr));
   if (mg_on(c, 1)) PF_HIP(c, mg_setup<double>(c, 1, r));
@@ -1122,7 +1127,9 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
 // the correction equation in FP32 (FP64 dot products) to the accuracy the
 // outer test still needs (no tighter than kInnerTol), adds the correction to
 // x64 and refreshes the FP32 working copy x32.  One sweep usually suffices,
-// so the Krylov space is rarely thrown away by a restart.
+// so the Krylov space is rarely thrown away by a restart.  The FEM setup of
+// the first sweep stores the body force (FP64); later sweeps form b - K x64
+// from it without evaluating the eigenstress again.
 pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, double cdt, double* x64, float* x32,
                         double tol, bool warm, SolveResult* res) {
   const Dims& d = fem ? c->dims : c->dims_p;
@@ -1145,11 +1152,17 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
   res->relres = 0;
   auto iteration = fem ? fem_iteration<float>(c, r, pb, dz, kInnerTol)
                        : poisson_iteration<float>(c, cf32, r, pb, dz, kInnerTol);
+  double* fbody = at<double>(c, c->lay.fbody);
   for (;;) {
-    if (fem) {
+    if (fem && res->outer == 0) {
       PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
         return launch_fem_setup<double, float, float>(d, c->tm_f, cf64, tb, c->gen, P, V, cdt, nullptr, x64, r, pb[0],
-                                                      pb[1], dz, part, strm(c));
+                                                      pb[1], dz, fbody, part, strm(c));
+      }));
+    } else if (fem) {
+      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
+        return launch_fem_resid<double, float>(d, c->tm_f, tb, c->gen, fbody, x64, r, pb[0], pb[1], dz, part,
+                                               strm(c));
       }));
     } else {
       PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {

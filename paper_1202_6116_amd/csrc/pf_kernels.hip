@@ -874,7 +874,7 @@ template <typename T, typename S, typename R, bool GEN, bool ROT>
 __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
     Dims d, TileMap tm, Coefs<T> cf, const FemTables* __restrict__ tb, const S* __restrict__ P,
     const S* __restrict__ V, T cdt, const T* __restrict__ W, T* __restrict__ x, R* __restrict__ r,
-    R* __restrict__ p0, R* __restrict__ p1, R* __restrict__ dz, double* partials) {
+    R* __restrict__ p0, R* __restrict__ p1, R* __restrict__ dz, T* __restrict__ fout, double* partials) {
   constexpr int TY = kBY;
   using H = Halo<TY>;
   __shared__ T sgm[6][TY + 2][kHX];
@@ -1004,6 +1004,7 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
           p0[c * N + n] = 0;
           p1[c * N + n] = 0;
           if (dz) dz[c * N + n] = 0;
+          if (fout) fout[c * N + n] = 0;
         }
       } else {
         const int zt = (k == d.nz - 1) ? 1 : 0;
@@ -1021,6 +1022,7 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
           r[c * N + n] = (R)rr;
           p0[c * N + n] = (R)z;
           if (dz) dz[c * N + n] = 0;
+          if (fout) fout[c * N + n] = f0[c];
           v[0] += (double)f0[c] * f0[c];
           v[1] += (double)rr * z;
           v[2] += (double)rr * rr;
@@ -1032,6 +1034,94 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
       if (k + 1 < d.nz) {
         contrib(k + 1, 0, A, B, f0, true);
         contrib(k + 2, -1, A, B, f1, false);
+      }
+    }
+    __syncthreads();
+  }
+  block_partials<3, kThreads>(v, partials, tc.lid);
+}
+
+// Residual of a later refinement sweep, r = f - K x, from the body force f
+// that the first sweep's setup stored (fem_setup_kernel with fout), so the
+// eigenstress is not formed again.  Outputs as fem_setup_kernel: r, the
+// Jacobi-weighted p0, zeros in dz (and in x, r, p0, p1 on the clamped plane),
+// and the partials (f.f, r.z, r.r) per tile.  x is staged in the three-plane
+// LDS ring; K x is the same apply as in fem_setup_kernel, so the residual is
+// bitwise the one the full setup would form.
+template <typename T, typename R, bool GEN>
+__global__ __launch_bounds__(kThreads, 4) void fem_resid_kernel(Dims d, TileMap tm, const FemTables* __restrict__ tb,
+                                                             const T* __restrict__ f, T* __restrict__ x,
+                                                             R* __restrict__ r, R* __restrict__ p0,
+                                                             R* __restrict__ p1, R* __restrict__ dz,
+                                                             double* partials) {
+  constexpr int TY = kBY;
+  using H = Halo<TY>;
+  __shared__ T ring[3][3][TY + 2][kHX];
+  const TileCoord tc = tile_coord(d, tm);
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
+  const int64_t N = d.N, pl = d.plane;
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  Stage<T, 3, H::NPT> sx;
+  auto fetch_x = [&](int64_t m, int k, T* raw) {
+    if (k == 0) return;  // the clamp
+#pragma unroll
+    for (int c = 0; c < 3; c++) raw[c] = x[c * N + m];
+  };
+  auto comb_x = [&](int, const T* raw, T* o) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) o[c] = raw[c];
+  };
+  const int k0 = tc.k0;
+  if (k0 > 0) {
+    stage_fetch<TY>(sx, d, tc.i0, tc.j0, k0 - 1, fetch_x);
+    stage_store<TY>(ring, sx, k0 - 1, comb_x);
+  }
+  stage_fetch<TY>(sx, d, tc.i0, tc.j0, k0, fetch_x);
+  stage_store<TY>(ring, sx, k0, comb_x);
+  stage_fetch<TY>(sx, d, tc.i0, tc.j0, k0 + 1, fetch_x);
+  const T w_int[3] = {(T)tb->inv_diag[0][0], (T)tb->inv_diag[0][GEN ? 1 : 0], (T)tb->inv_diag[0][GEN ? 2 : 0]};
+  const T w_top[3] = {(T)tb->inv_diag[1][0], (T)tb->inv_diag[1][GEN ? 1 : 0], (T)tb->inv_diag[1][GEN ? 2 : 0]};
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int k = k0; k < tc.k1; k++) {
+    // the slot of plane k + 1 last held plane k - 2, read before the barrier
+    // that ended the previous plane
+    stage_store<TY>(ring, sx, k + 1, comb_x);
+    if (k + 2 <= tc.k1) stage_fetch<TY>(sx, d, tc.i0, tc.j0, k + 2, fetch_x);
+    __syncthreads();
+    if (valid) {
+      const int64_t n = col + pl * k;
+      if (k == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          x[c * N + n] = 0;
+          r[c * N + n] = 0;
+          p0[c * N + n] = 0;
+          p1[c * N + n] = 0;
+          dz[c * N + n] = 0;
+        }
+      } else {
+        const int zt = (k == d.nz - 1) ? 1 : 0;
+        auto ld = [&](int ox, int oy, int oz, T u[3]) {
+          const int sl = slot_of(k + oz);
+#pragma unroll
+          for (int c = 0; c < 3; c++) u[c] = ring[sl][c][ly + 1 + oy][lx + 1 + ox];
+        };
+        T Kx[3];
+        fem_K_apply<T, GEN>(tb, zt, ld, Kx);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          const T fc = f[c * N + n];
+          const T rr = fc - Kx[c];
+          const T z = rr * (zt ? w_top[c] : w_int[c]);
+          r[c * N + n] = (R)rr;
+          p0[c * N + n] = (R)z;
+          dz[c * N + n] = 0;
+          v[0] += (double)fc * fc;
+          v[1] += (double)rr * z;
+          v[2] += (double)rr * rr;
+        }
       }
     }
     __syncthreads();
@@ -2708,10 +2798,10 @@ hipError_t launch_poisson_cg_b(const Dims& d, const TileMap& tm, const Coefs<T>&
 template <typename T, typename S, typename R>
 hipError_t launch_fem_setup(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const FemTables* tb, bool gen,
                             const S* P, const S* V, T cdt, const T* W, T* x, R* r, R* p0, R* p1, R* dz,
-                            double* partials, hipStream_t s) {
+                            T* fout, double* partials, hipStream_t s) {
 #define PF_FEM_SETUP(GEN, ROT)                                                                               \
   fem_setup_kernel<T, S, R, GEN, ROT><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, tb, P, V, cdt, W, x, r, p0, p1, \
-                                                                          dz, partials)
+                                                                          dz, fout, partials)
   if (gen) {
     if (cf.rotated) PF_FEM_SETUP(true, true);
     else PF_FEM_SETUP(true, false);
@@ -2720,6 +2810,16 @@ hipError_t launch_fem_setup(const Dims& d, const TileMap& tm, const Coefs<T>& cf
     else PF_FEM_SETUP(false, false);
   }
 #undef PF_FEM_SETUP
+  return hipGetLastError();
+}
+
+template <typename T, typename R>
+hipError_t launch_fem_resid(const Dims& d, const TileMap& tm, const FemTables* tb, bool gen, const T* f, T* x, R* r,
+                            R* p0, R* p1, R* dz, double* partials, hipStream_t s) {
+  if (gen)
+    fem_resid_kernel<T, R, true><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, f, x, r, p0, p1, dz, partials);
+  else
+    fem_resid_kernel<T, R, false><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tb, f, x, r, p0, p1, dz, partials);
   return hipGetLastError();
 }
 
@@ -2993,13 +3093,16 @@ PF_INSTANTIATE_MG(float)
                                                     int, const T*, T, const uint8_t*, T*, R*, R*, R*, double*,   \
                                                     hipStream_t);                                                \
   template hipError_t launch_fem_setup<T, S, R>(const Dims&, const TileMap&, const Coefs<T>&, const FemTables*,   \
-                                                bool, const S*, const S*, T, const T*, T*, R*, R*, R*, R*, double*, \
-                                                hipStream_t);
+                                                bool, const S*, const S*, T, const T*, T*, R*, R*, R*, R*, T*,    \
+                                                double*, hipStream_t);
 
 PF_INSTANTIATE_SETUP(double, double, double)
 PF_INSTANTIATE_SETUP(double, float, float)
 PF_INSTANTIATE_SETUP(double, float, double)
 
+template hipError_t launch_fem_resid<double, float>(const Dims&, const TileMap&, const FemTables*, bool,
+                                                    const double*, double*, float*, float*, float*, float*, double*,
+                                                    hipStream_t);
 template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
 template hipError_t launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
 
