@@ -146,6 +146,32 @@ def test_adjoint_gradient_matches_oracle(pf, oracle_mod, integrator):
     assert rel(host(P0t.grad), dP_ref) < 1e-7
 
 
+def test_fp32_adjoint_gradient_matches_oracle(pf, oracle_mod):
+    """The adjoint of an FP32 + refinement context (FP32 state and adjoint
+    vectors, FP64 solves) against the FP64 oracle's adjoint gradient: the
+    state is rounded to FP32 every step, so the bar is 1e-6 relative
+    (measured: 2e-8 for J and the parameters, 1e-7 for dJ/dP0)."""
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    cfg = adjoint_cfg(precision="fp32_refine", tol_phi=1e-11, tol_u=1e-11)
+    print("case: adjoint fp32_refine", flush=True)
+    nsteps = 6
+    P0 = domain_polarisation(cfg, 32, block=3, std=0.2).astype(np.float32).astype(np.float64)
+    wgt = np.zeros((3,) + cfg.shape)
+    wgt[2, 2:, 2:6, 3:10] = 1.0 / 3 / 4 / 7
+    J_ref, dth_ref, dP_ref = oracle_mod.Oracle(cfg.replace(precision="fp64")).gradient(P0, nsteps, wgt)
+    ctx = pf.Context(cfg)
+    P0t = dev(P0, torch.float32).requires_grad_(True)
+    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+    PN = tdgl_steps(P0t, volts, a1, ctx, nsteps, checkpoint_every=4)
+    J = (PN.double() * dev(wgt)).sum()
+    J.backward()
+    g = np.concatenate([volts.grad.cpu().numpy(), [a1.grad.item()]])
+    errs = (abs(float(J.detach()) - J_ref) / abs(J_ref), rel(g, dth_ref), rel(host(P0t.grad), dP_ref))
+    print("fp32 adjoint: J, dtheta, dJ/dP0 relative errors", errs, flush=True)
+    assert errs[0] < 1e-6 and errs[1] < 1e-6 and errs[2] < 1e-6
+
+
 def test_adjoint_full_size_vs_central_differences(pf):
     """The 128x128x32 adjoint case: dJ/dV_1, dJ/dV_2, dJ/da1 of the mean Pz
     over the 32x32x8 box after 50 steps (checkpoint every 10) against
