@@ -123,6 +123,22 @@ __device__ __forceinline__ TileCoord tile_coord(const Dims& d, const TileMap& tm
 
 __device__ __forceinline__ int slot_of(int k) { return (k + 3) % 3; }
 
+// Jacobi weights of the FEM rows (interior and top plane, per component)
+// held in scalars: a run-time choice between two arrays would put the arrays
+// in scratch memory.  Without GEN the components share one weight.
+template <typename T, bool GEN>
+struct JacobiW {
+  T i0, i1, i2, t0, t1, t2;
+  __device__ __forceinline__ explicit JacobiW(const FemTables* __restrict__ tb)
+      : i0((T)tb->inv_diag[0][0]), i1((T)tb->inv_diag[0][GEN ? 1 : 0]), i2((T)tb->inv_diag[0][GEN ? 2 : 0]),
+        t0((T)tb->inv_diag[1][0]), t1((T)tb->inv_diag[1][GEN ? 1 : 0]), t2((T)tb->inv_diag[1][GEN ? 2 : 0]) {}
+  __device__ __forceinline__ T operator()(bool top, int c) const {
+    const T wi = c == 0 ? i0 : (c == 1 ? i1 : i2);
+    const T wt = c == 0 ? t0 : (c == 1 ? t1 : t2);
+    return top ? wt : wi;
+  }
+};
+
 // Software-pipelined staging of tile planes.  Each thread owns NPT of the
 // halo-plane points.  stage_fetch issues the global loads of a plane into
 // registers (raw values, RAW per point); stage_store combines them into the
@@ -984,8 +1000,7 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
     contrib(k0 + 1, -1, A, B, f1, false);
   }
   __syncthreads();
-  const T w_int[3] = {(T)tb->inv_diag[0][0], (T)tb->inv_diag[0][GEN ? 1 : 0], (T)tb->inv_diag[0][GEN ? 2 : 0]};
-  const T w_top[3] = {(T)tb->inv_diag[1][0], (T)tb->inv_diag[1][GEN ? 1 : 0], (T)tb->inv_diag[1][GEN ? 2 : 0]};
+  const JacobiW<T, GEN> jw(tb);
   double v[3] = {0.0, 0.0, 0.0};
   for (int k = k0; k < tc.k1; k++) {
     stage(k + 1);
@@ -1018,7 +1033,7 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
 #pragma unroll
         for (int c = 0; c < 3; c++) {
           const T rr = f0[c] - Kx[c];
-          const T z = rr * (zt ? w_top[c] : w_int[c]);
+          const T z = rr * jw(zt, c);
           r[c * N + n] = (R)rr;
           p0[c * N + n] = (R)z;
           if (dz) dz[c * N + n] = 0;
@@ -1081,8 +1096,7 @@ __global__ __launch_bounds__(kThreads, 4) void fem_resid_kernel(Dims d, TileMap 
   stage_fetch<TY>(sx, d, tc.i0, tc.j0, k0, fetch_x);
   stage_store<TY>(ring, sx, k0, comb_x);
   stage_fetch<TY>(sx, d, tc.i0, tc.j0, k0 + 1, fetch_x);
-  const T w_int[3] = {(T)tb->inv_diag[0][0], (T)tb->inv_diag[0][GEN ? 1 : 0], (T)tb->inv_diag[0][GEN ? 2 : 0]};
-  const T w_top[3] = {(T)tb->inv_diag[1][0], (T)tb->inv_diag[1][GEN ? 1 : 0], (T)tb->inv_diag[1][GEN ? 2 : 0]};
+  const JacobiW<T, GEN> jw(tb);
   double v[3] = {0.0, 0.0, 0.0};
   for (int k = k0; k < tc.k1; k++) {
     // the slot of plane k + 1 last held plane k - 2, read before the barrier
@@ -1114,7 +1128,7 @@ __global__ __launch_bounds__(kThreads, 4) void fem_resid_kernel(Dims d, TileMap 
         for (int c = 0; c < 3; c++) {
           const T fc = f[c * N + n];
           const T rr = fc - Kx[c];
-          const T z = rr * (zt ? w_top[c] : w_int[c]);
+          const T z = rr * jw(zt, c);
           r[c * N + n] = (R)rr;
           p0[c * N + n] = (R)z;
           dz[c * N + n] = 0;
@@ -1145,8 +1159,7 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
   __shared__ T ring[3][3][TY + 2][kHX];
   const T beta = (T)sc->beta, alpha = (T)sc->alpha;
   // Jacobi weights per component (equal for a cubic stiffness on the grid axes)
-  const T w_int[3] = {(T)tb->inv_diag[0][0], (T)tb->inv_diag[0][GEN ? 1 : 0], (T)tb->inv_diag[0][GEN ? 2 : 0]};
-  const T w_top[3] = {(T)tb->inv_diag[1][0], (T)tb->inv_diag[1][GEN ? 1 : 0], (T)tb->inv_diag[1][GEN ? 2 : 0]};
+  const JacobiW<T, GEN> jw(tb);
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
@@ -1163,10 +1176,8 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
   };
   auto comb = [&](int k, const T* raw, T* out) {
     const bool top = k == d.nz - 1;
-    const T w0 = unit_w ? (T)1 : (top ? w_top[0] : w_int[0]);
 #pragma unroll
-    for (int c = 0; c < 3; c++)
-      out[c] = raw[c] * (GEN && !unit_w ? (top ? w_top[c] : w_int[c]) : w0) + beta * raw[3 + c];
+    for (int c = 0; c < 3; c++) out[c] = raw[c] * (unit_w ? (T)1 : jw(top, c)) + beta * raw[3 + c];
   };
   // centre values (p_old, x) of a plane
   auto centre = [&](int k, T* cv) {
@@ -1232,8 +1243,7 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_b_kernel(Dims d, TileMap t
   constexpr int TY = kBY;
   __shared__ T ring[3][3][TY + 2][kHX];
   const T alpha = (T)sc->alpha;
-  const T w_int[3] = {(T)tb->inv_diag[0][0], (T)tb->inv_diag[0][GEN ? 1 : 0], (T)tb->inv_diag[0][GEN ? 2 : 0]};
-  const T w_top[3] = {(T)tb->inv_diag[1][0], (T)tb->inv_diag[1][GEN ? 1 : 0], (T)tb->inv_diag[1][GEN ? 2 : 0]};
+  const JacobiW<T, GEN> jw(tb);
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
@@ -1283,12 +1293,11 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_b_kernel(Dims d, TileMap t
       T q[3];
       fem_K_apply<T, GEN>(tb, zt, ld, q);
       const int64_t n = col + d.plane * k;
-      const T w0 = zt ? w_top[0] : w_int[0];
 #pragma unroll
       for (int c = 0; c < 3; c++) {
         const T rn = cv[c] - alpha * q[c];
         r[c * N + n] = rn;
-        a0 += (double)rn * (rn * (GEN ? (zt ? w_top[c] : w_int[c]) : w0));
+        a0 += (double)rn * (rn * jw(zt, c));
         a1 += (double)rn * rn;
       }
     }
@@ -1359,22 +1368,18 @@ __device__ __forceinline__ void coarse_init(CoarseRegs<T, NC>& cr, const MgCoars
 // fine planes [0, fnz) and for fixed coarse planes).
 template <typename T, int NC>
 __device__ __forceinline__ void coarse_fetch(CoarseRegs<T, NC>& cr, const MgCoarse<T>& mc, int k, int fnz) {
-#pragma unroll
-  for (int t = 0; t < 2; t++) {
-    cr.w[t] = 0.0;
-#pragma unroll
-    for (int c = 0; c < NC; c++) cr.v[t][c] = 0;
-  }
-  if (cr.col < 0 || k < 0 || k >= fnz) return;
-  const MgZ z = mc.zmap[k + mc.zoff];
+  // the plane's parents and weights are uniform over the block (scalar
+  // registers); only the loads depend on the thread's column
+  const bool inside = k >= 0 && k < fnz;
+  const MgZ z = mc.zmap[inside ? k + mc.zoff : mc.zoff];
   const int zi[2] = {z.lo, z.hi};
   const double zw[2] = {z.wlo, z.whi};
 #pragma unroll
   for (int t = 0; t < 2; t++) {
-    if (zw[t] == 0.0 || zi[t] == 0 || (mc.top_fixed && zi[t] == mc.nz - 1)) continue;
-    cr.w[t] = zw[t];
+    const bool live = inside && zw[t] != 0.0 && zi[t] != 0 && !(mc.top_fixed && zi[t] == mc.nz - 1);
+    cr.w[t] = live ? zw[t] : 0.0;
 #pragma unroll
-    for (int c = 0; c < NC; c++) cr.v[t][c] = mc.e[c * mc.N + cr.col + mc.plane * zi[t]];
+    for (int c = 0; c < NC; c++) cr.v[t][c] = live && cr.col >= 0 ? mc.e[c * mc.N + cr.col + mc.plane * zi[t]] : (T)0;
   }
 }
 
