@@ -1592,20 +1592,19 @@ __global__ __launch_bounds__(kThreads, 4) void mg_fine_kernel(Dims d, TileMap tm
   const bool valid = i < d.nx && j < d.ny;
   const int64_t N = d.N;
   const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  // plain loads: arithmetic on a loaded value would wait for the load here
+  // and undo the prefetch; the first sweep's omega D^-1 is applied when the
+  // plane is staged
   auto fetch = [&](int64_t m, int k, T* raw) {
     if (k == 0) return;
-    if (FIRST) {
-      const int zt = k == d.nz - 1 ? 1 : 0;
+    const T* src = FIRST ? b : x;
 #pragma unroll
-      for (int c = 0; c < 3; c++) raw[c] = (T)(omega * tb->inv_diag[zt][c]) * b[c * N + m];
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; c++) raw[c] = x[c * N + m];
-    }
+    for (int c = 0; c < 3; c++) raw[c] = src[c * N + m];
   };
-  auto comb = [&](int, const T* raw, T* o) {
+  auto comb = [&](int k, const T* raw, T* o) {
+    const int zt = k == d.nz - 1 ? 1 : 0;
 #pragma unroll
-    for (int c = 0; c < 3; c++) o[c] = raw[c];
+    for (int c = 0; c < 3; c++) o[c] = FIRST ? (T)(omega * tb->inv_diag[zt][c]) * raw[c] : raw[c];
   };
   auto centre = [&](int k, T* cv) {
 #pragma unroll
@@ -2034,8 +2033,12 @@ __global__ __launch_bounds__(kThreads) void mgp_fine_kernel(Dims d, TileMap tm, 
   const int i = tc.i0 + lx, j = tc.j0 + ly;
   const bool valid = i < d.nx && j < d.ny;
   const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
-  auto fetch = [&](int64_t m, int k, T* raw) { raw[0] = FIRST ? (T)(omega * dinv[k]) * b[m] : (CORR ? b : x)[m]; };
-  auto comb = [&](int, const T* raw, T* o) { o[0] = raw[0]; };
+  // plain loads (see mg_fine_kernel); the first sweep's omega D^-1 is applied
+  // when the plane is staged (raw is zero outside the stored planes)
+  auto fetch = [&](int64_t m, int, T* raw) { raw[0] = ((FIRST || CORR) ? b : x)[m]; };
+  auto comb = [&](int k, const T* raw, T* o) {
+    o[0] = FIRST && k >= 0 && k < d.nz ? (T)(omega * dinv[k]) * raw[0] : raw[0];
+  };
   // kMgCorrect: x = omega D^-1 b + P e on the stored planes
   auto comb_corr = [&](int k, const T* raw, T* o, int hx, int hy) {
     if constexpr (CORR)
