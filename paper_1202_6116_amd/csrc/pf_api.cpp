@@ -1172,10 +1172,21 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
       }));
     }
     PF_HIP(c, reduce(c, part, setup_blocks, 3, which, kRedOuter, tol, kInnerTol, nullptr));
-    if (mg_on(c, which)) PF_HIP(c, mg_setup<float>(c, which, r));
     CgScalars h;
-    PF_TRY(run_cg<float>(c, which, c->pred[pred], dz, pb, n, iteration, &h, what));
-    res->iters += h.iter;
+    bool inner = true;
+    if (res->outer > 0) {
+      // a later sweep mostly finds the outer test met: read it back before
+      // launching the inner solve, whose batch would otherwise only return
+      // at entry
+      PF_TRY(read_scalars(c, which, &h));
+      if (h.done == kNonFinite) return fail(c, PF_ENONFINITE, "%s: non-finite value in the CG reductions", what);
+      inner = !h.outer_done;
+    }
+    if (inner) {
+      if (mg_on(c, which)) PF_HIP(c, mg_setup<float>(c, which, r));
+      PF_TRY(run_cg<float>(c, which, c->pred[pred], dz, pb, n, iteration, &h, what));
+      res->iters += h.iter;
+    }
     res->relres = h.outer_b2 > 0 ? std::sqrt(h.outer_r2 / h.outer_b2) : 0.0;
     if (h.outer_done) {
       if (h.zero_rhs) PF_HIP(c, launch_fill<double>(x64, n, 0.0, strm(c)));
