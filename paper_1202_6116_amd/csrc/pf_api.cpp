@@ -1153,6 +1153,7 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
   auto iteration = fem ? fem_iteration<float>(c, r, pb, dz, kInnerTol)
                        : poisson_iteration<float>(c, cf32, r, pb, dz, kInnerTol);
   double* fbody = at<double>(c, c->lay.fbody);
+  bool synced = false;  // x32 == (float) x64, as the last refinement update left it
   for (;;) {
     if (fem && res->outer == 0) {
       PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
@@ -1189,12 +1190,17 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
     }
     res->relres = h.outer_b2 > 0 ? std::sqrt(h.outer_r2 / h.outer_b2) : 0.0;
     if (h.outer_done) {
-      if (h.zero_rhs) PF_HIP(c, launch_fill<double>(x64, n, 0.0, strm(c)));
-      PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_convert<double, float>(x64, x32, n, strm(c)); }));
+      if (h.zero_rhs) {
+        PF_HIP(c, launch_fill<double>(x64, n, 0.0, strm(c)));
+        synced = false;
+      }
+      if (!synced)
+        PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_convert<double, float>(x64, x32, n, strm(c)); }));
       return PF_OK;
     }
     if (h.iter > 0) c->pred[pred] = h.iter;
     PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_refine_update(x64, x32, dz, n, strm(c)); }));
+    synced = true;
     res->outer++;
     if (res->outer >= kMaxOuter) {
       return fail(c, PF_ENOCONV, "%s: %d refinement sweeps, relres %.3e", what, res->outer, res->relres);
