@@ -252,7 +252,8 @@ pf_status pf_set_params(pf_ctx *ctx, const double *volts, double a1);
 
 /* One reverse step of the discrete adjoint of pf_step (needs
  * nonlocal_every <= 1; the linearised solves run in FP64 in both
- * precisions, warm-started from the previous adjoint step's solutions).  In: the state
+ * precisions, warm-started from the previous adjoint step's solutions, with
+ * warm_start 2 extrapolated from the last extrap_order + 1 of them).  In: the state
  * (P_n, V_n) before forward step n (device, 3N each, state precision; V_n is
  * ignored for Euler) and the adjoints (lamP, lamV) of the state after it;
  * out: lamP, lamV overwritten by the adjoints of the state before it, and

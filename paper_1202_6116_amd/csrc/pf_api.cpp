@@ -397,6 +397,8 @@ struct Layout {
   size_t fbody;                // FP32_REFINE: the FEM body force of the first sweep (FP64)
   size_t hist;                 // ring of earlier solutions for extrapolated warm starts
                                // (extrap_order slots of Np (phi) then extrap_order of 3N (u))
+  size_t adj_hist;             // the same for the adjoint solutions: psi (Np), the displacement
+                               // at the linearisation point (3N), the adjoint displacement (3N)
   size_t scratch[8];           // max(3N, Np) doubles each: adjoint, energy, conversions
   size_t tables, scalars, result, partials;
   MgLayout mg[2];              // multigrid of the Poisson (0) and the FEM (1) operator
@@ -452,6 +454,7 @@ Layout make_layout(const pf_config& c, int npartials) {
   L.du = take(3 * N * 4);
   L.fbody = c.precision == PF_FP32_REFINE ? take(3 * N * 8) : 0;
   L.hist = c.warm_start == 2 && c.extrap_order > 0 ? take((Np + 3 * N) * 8 * (size_t)c.extrap_order) : 0;
+  L.adj_hist = c.warm_start == 2 && c.extrap_order > 0 ? take((Np + 6 * N) * 8 * (size_t)c.extrap_order) : 0;
   for (int t = 0; t < 8; t++) L.scratch[t] = take(S * 8);
   for (int f = 0; f < 2; f++) {
     const std::vector<MgLevel> mg = mg_levels_for(c, f);
@@ -562,6 +565,7 @@ struct pf_ctx {
   bool adj_warm;            // adjoint scratch holds earlier adjoint solutions
   int hist_valid;           // solutions held for extrapolated warm starts (0..extrap_order)
   int hist_head;            // ring slot that the next stored solution goes to
+  int adj_valid, adj_head;  // the same for the adjoint solutions
   int64_t step;
   int cur;                  // which P/V buffer is current
   int pred[pf::kPredCount];
@@ -1241,28 +1245,43 @@ void stats_add(pf_step_stats* st, int which, const SolveResult& r) {
 // head advanced; false: order 0, nothing to launch); extrapolate_field
 // launches one field's kernel on the calling thread's stream, so each solve
 // extrapolates its own field on its own stream.
-bool extrapolate_plan(pf_ctx* c, ExtrapRing ring[2]) {
+// ring_plan: the descriptors of nf fields of lengths len[] whose rings lie
+// one after the other at byte offset off; valid and head are the ring's
+// fill and next slot.
+bool ring_plan(pf_ctx* c, size_t off, int nf, const int64_t* len, int& valid, int& head, ExtrapRing* ring) {
   const int cap = c->cfg.extrap_order;
-  const int m = std::min(c->hist_valid, cap);
-  const int64_t N = c->dims.N, Np = c->dims_p.N;
-  for (int f = 0; f < 2; f++) {
+  const int m = std::min(valid, cap);
+  int64_t first = 0;
+  for (int f = 0; f < nf; f++) {
     ExtrapRing& r = ring[f];
-    const int64_t len = f == 0 ? Np : 3 * N;
-    double* base = cap > 0 ? at<double>(c, c->lay.hist) + (f == 0 ? 0 : (int64_t)cap * Np) : nullptr;
+    double* base = cap > 0 ? at<double>(c, off) + first : nullptr;
+    first += (int64_t)cap * len[f];
     r.m = m;
     for (int t = 0; t <= m; t++) {
       double b = 1;
       for (int q = 1; q <= t + 1; q++) b = b * (m + 2 - q) / q;
       r.c[t] = (t & 1) ? -b : b;
     }
-    for (int t = 0; t < m; t++) r.h[t] = base + (int64_t)((c->hist_head - 1 - t + 2 * cap) % cap) * len;
+    for (int t = 0; t < m; t++) r.h[t] = base + (int64_t)((head - 1 - t + 2 * cap) % cap) * len[f];
     for (int t = m; t < kMaxExtrap; t++) r.h[t] = nullptr;
-    r.dest = cap > 0 ? base + (int64_t)c->hist_head * len : nullptr;
+    r.dest = cap > 0 ? base + (int64_t)head * len[f] : nullptr;
   }
   if (cap == 0) return false;  // the previous solution is the guess
-  c->hist_head = (c->hist_head + 1) % cap;
-  if (c->hist_valid < cap) c->hist_valid++;
+  head = (head + 1) % cap;
+  if (valid < cap) valid++;
   return true;
+}
+
+bool extrapolate_plan(pf_ctx* c, ExtrapRing ring[2]) {
+  const int64_t len[2] = {c->dims_p.N, 3 * c->dims.N};
+  return ring_plan(c, c->lay.hist, 2, len, c->hist_valid, c->hist_head, ring);
+}
+
+// Replaces x (n values, the previous solution) by its extrapolation and
+// stores the previous solution in the ring, on the calling thread's stream.
+pf_status extrapolate_into(pf_ctx* c, double* x, int64_t n, const ExtrapRing& ring) {
+  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_extrapolate(x, ring, n, strm(c)); }));
+  return PF_OK;
 }
 
 pf_status extrapolate_field(pf_ctx* c, int f, const ExtrapRing& ring) {
@@ -1509,9 +1528,19 @@ pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt) {
   double* ulin = scratch<double>(c, kScrULin);
   double* du = scratch<double>(c, kScrDu);
   double* psi = scratch<double>(c, kScrPsi);
+  // warm_start 2: the adjoint solutions of the previous adjoint steps are
+  // extrapolated like the forward ones (rings of psi, ulin, du)
+  ExtrapRing ring[3];
+  const int64_t len[3] = {c->dims_p.N, 3 * d.N, 3 * d.N};
+  const bool ex = c->adj_warm && c->cfg.warm_start == 2 &&
+                  ring_plan(c, c->lay.adj_hist, 3, len, c->adj_valid, c->adj_head, ring);
   // the displacement at the linearisation point and the adjoint displacement
   auto fem = [&]() -> pf_status {
     SolveResult r{};
+    if (ex) {
+      PF_TRY(extrapolate_into(c, ulin, len[1], ring[1]));
+      PF_TRY(extrapolate_into(c, du, len[2], ring[2]));
+    }
     pf_status s = solve_fem64<S>(c, kPredAdjU, P, V, cdt, nullptr, ulin, c->cfg.tol_u, c->adj_warm, &r);
     if (fatal(s)) return s;
     const pf_status s2 = solve_fem64<S>(c, kPredAdjDu, P, V, cdt, w, du, c->cfg.tol_u, c->adj_warm, &r);
@@ -1520,6 +1549,7 @@ pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt) {
   // the adjoint potential
   auto poisson = [&]() -> pf_status {
     SolveResult r{};
+    if (ex) PF_TRY(extrapolate_into(c, psi, len[0], ring[0]));
     return solve_poisson64<double>(c, kPredAdjPsi, w, nullptr, 0.0, 1, 0, at<double>(c, c->lay.ghost64), 0.0, psi,
                                    c->cfg.tol_phi, c->adj_warm, &r);
   };
@@ -1764,6 +1794,8 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->have_state = c->phi_bc_valid = c->basis_valid = c->adj_warm = false;
   c->hist_valid = 0;
   c->hist_head = 0;
+  c->adj_valid = 0;
+  c->adj_head = 0;
   c->step = 0;
   c->cur = 0;
   for (int t = 0; t < kPredCount; t++) c->pred[t] = 16;
