@@ -262,6 +262,14 @@ pf_status pf_set_params(pf_ctx *ctx, const double *volts, double a1);
  * one adjoint Poisson and one adjoint FEM solve.  Synchronises. */
 pf_status pf_adjoint_step(pf_ctx *ctx, const void *P_n, const void *V_n, void *lamP, void *lamV, double *dtheta);
 
+/* pf_adjoint_step with the displacement at the linearisation point given:
+ * u_n (device, 3N doubles) is what forward step n solved for (the u that
+ * pf_get_state returns after that step), so only the adjoint Poisson and
+ * FEM systems are solved.  u_n = NULL: the same as pf_adjoint_step.
+ * Synchronises. */
+pf_status pf_adjoint_step_u(pf_ctx *ctx, const void *P_n, const void *V_n, const void *u_n, void *lamP, void *lamV,
+                            double *dtheta);
+
 /* Folds the initial rate V0 = F(P0) of the predictor-corrector into the
  * adjoints: lamP += (dF/dP)(P0) lamV, dtheta += lamV . dF/dtheta(P0),
  * lamV = 0.  No-op for Euler.  Synchronises. */

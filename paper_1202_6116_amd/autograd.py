@@ -6,7 +6,8 @@ Backward: for each checkpoint segment, newest first, the segment is
 recomputed from its checkpoint (bitwise identical: the library's reductions
 are deterministic and the checkpoint carries the solver warm starts), and
 the discrete adjoint of every step is applied in reverse with
-pf_adjoint_step; finally pf_adjoint_initial_rate folds in the initial rate
+pf_adjoint_step_u, given the displacement that the recomputed step solved
+for; finally pf_adjoint_initial_rate folds in the initial rate
 V0 = F(P0) of the predictor-corrector.  Gradients are returned for P0, the
 voltages and a1.
 """
@@ -62,10 +63,13 @@ class PFSteps(torch.autograd.Function):
             states = []
             for _ in range(start, stop):
                 Pn, Vn = pf.get_state()[:2]
-                states.append((Pn, Vn))
                 pf.step(1)
-            for Pn, Vn in reversed(states):
-                pf.adjoint_step(Pn, Vn, lamP, lamV, dtheta)
+                # the displacement step n solved for: the adjoint step's
+                # linearisation point needs no second solve
+                un = pf.get_state()[3]
+                states.append((Pn, Vn, un))
+            for Pn, Vn, un in reversed(states):
+                pf.adjoint_step(Pn, Vn, lamP, lamV, dtheta, un)
         pf.adjoint_initial_rate(P0, lamP, lamV, dtheta)
         vdev, vdt, adev, adt = fctx.theta_dev
         g_volts = torch.tensor(dtheta[:fctx.n_volts], dtype=vdt, device=vdev)

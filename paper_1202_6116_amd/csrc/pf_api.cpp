@@ -1520,7 +1520,7 @@ pf_status ensure_basis(pf_ctx* c) {
 
 // Hw = (dF/dP)(X) w, X = P + cdt V (storage S), w in scratch kScrW.
 template <typename S>
-pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt) {
+pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt, const double* ulin_in = nullptr) {
   const Dims& d = c->dims;
   const Coefs<double> cf = make_coefs<double>(c);
   const FemTables* tb = at<FemTables>(c, c->lay.tables);
@@ -1535,14 +1535,18 @@ pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt) {
   const bool ex = c->adj_warm && c->cfg.warm_start == 2 &&
                   ring_plan(c, c->lay.adj_hist, 3, len, c->adj_valid, c->adj_head, ring);
   // the displacement at the linearisation point and the adjoint displacement
+  // (given: the forward step's own solution, no solve)
   auto fem = [&]() -> pf_status {
     SolveResult r{};
     if (ex) {
-      PF_TRY(extrapolate_into(c, ulin, len[1], ring[1]));
+      if (!ulin_in) PF_TRY(extrapolate_into(c, ulin, len[1], ring[1]));
       PF_TRY(extrapolate_into(c, du, len[2], ring[2]));
     }
-    pf_status s = solve_fem64<S>(c, kPredAdjU, P, V, cdt, nullptr, ulin, c->cfg.tol_u, c->adj_warm, &r);
-    if (fatal(s)) return s;
+    pf_status s = PF_OK;
+    if (!ulin_in) {
+      s = solve_fem64<S>(c, kPredAdjU, P, V, cdt, nullptr, ulin, c->cfg.tol_u, c->adj_warm, &r);
+      if (fatal(s)) return s;
+    }
     const pf_status s2 = solve_fem64<S>(c, kPredAdjDu, P, V, cdt, w, du, c->cfg.tol_u, c->adj_warm, &r);
     return fatal(s2) ? s2 : worst(s, s2);
   };
@@ -1584,7 +1588,8 @@ pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt) {
     }
   }
   PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
-    return launch_hvp<S>(d, cf, tb, P, V, cdt, w, ulin, psi, du, scratch<double>(c, kScrHw), strm(c));
+    return launch_hvp<S>(d, cf, tb, P, V, cdt, w, ulin_in ? ulin_in : ulin, psi, du, scratch<double>(c, kScrHw),
+                         strm(c));
   }));
   c->adj_warm = true;
   return out;
@@ -1624,7 +1629,8 @@ pf_status theta_accumulate(pf_ctx* c, const S* P, const S* V, double cdt, double
 }
 
 template <typename S>
-pf_status adjoint_step_t(pf_ctx* c, const S* Pn, const S* Vn, S* lamP, S* lamV, double* dtheta) {
+pf_status adjoint_step_t(pf_ctx* c, const S* Pn, const S* Vn, S* lamP, S* lamV, double* dtheta,
+                         const double* un = nullptr) {
   const bool pc = c->cfg.integrator == PF_INT_PC;
   const int64_t n3 = 3 * c->dims.N;
   const double dt = c->cfg.dt;
@@ -1633,7 +1639,7 @@ pf_status adjoint_step_t(pf_ctx* c, const S* Pn, const S* Vn, S* lamP, S* lamV, 
   const S* V = pc ? Vn : nullptr;
   const double cdt = pc ? dt : 0.0;
   PF_HIP(c, launch_adjoint_axpy<S>(pc ? kAdjPrepPc : kAdjPrepEuler, dt, lamP, lamV, w, Hw, n3, strm(c)));
-  pf_status s = hvp<S>(c, Pn, V, cdt);
+  pf_status s = hvp<S>(c, Pn, V, cdt, un);
   if (fatal(s)) return s;
   PF_TRY(theta_accumulate<S>(c, Pn, V, cdt, pc ? 1.0 : dt, dtheta));
   PF_HIP(c, launch_adjoint_axpy<S>(pc ? kAdjUpdPc : kAdjUpdEuler, dt, lamP, lamV, w, Hw, n3, strm(c)));
@@ -2052,16 +2058,22 @@ pf_status pf_set_params(pf_ctx* c, const double* volts, double a1) {
   return PF_OK;
 }
 
-pf_status pf_adjoint_step(pf_ctx* c, const void* P_n, const void* V_n, void* lamP, void* lamV, double* dtheta) {
+pf_status pf_adjoint_step_u(pf_ctx* c, const void* P_n, const void* V_n, const void* u_n, void* lamP, void* lamV,
+                            double* dtheta) {
   if (!c || !P_n || !lamP || !lamV || !dtheta) return fail(c, PF_EINVAL, "pf_adjoint_step: null argument");
   if (c->cfg.integrator == PF_INT_PC && !V_n) return fail(c, PF_EINVAL, "pf_adjoint_step: V_n needed");
   if (c->cfg.nonlocal_every > 1)
     return fail(c, PF_EINVAL, "pf_adjoint_step: the adjoint needs phi and u refreshed every step");
+  const double* un = static_cast<const double*>(u_n);
   if (fp32(c))
     return adjoint_step_t<float>(c, static_cast<const float*>(P_n), static_cast<const float*>(V_n),
-                                 static_cast<float*>(lamP), static_cast<float*>(lamV), dtheta);
+                                 static_cast<float*>(lamP), static_cast<float*>(lamV), dtheta, un);
   return adjoint_step_t<double>(c, static_cast<const double*>(P_n), static_cast<const double*>(V_n),
-                                static_cast<double*>(lamP), static_cast<double*>(lamV), dtheta);
+                                static_cast<double*>(lamP), static_cast<double*>(lamV), dtheta, un);
+}
+
+pf_status pf_adjoint_step(pf_ctx* c, const void* P_n, const void* V_n, void* lamP, void* lamV, double* dtheta) {
+  return pf_adjoint_step_u(c, P_n, V_n, nullptr, lamP, lamV, dtheta);
 }
 
 pf_status pf_adjoint_initial_rate(pf_ctx* c, const void* P0, void* lamP, void* lamV, double* dtheta) {

@@ -30,6 +30,7 @@ KERNEL_CLASSES = ["poisson_setup", "poisson_a", "poisson_b", "fem_setup", "fem_a
 EXPORTS = [
     "pf_workspace_size", "pf_init", "pf_set_state", "pf_restore_state", "pf_get_state", "pf_step",
     "pf_solve_phi", "pf_solve_u", "pf_force", "pf_noise", "pf_energy", "pf_set_params", "pf_adjoint_step",
+    "pf_adjoint_step_u",
     "pf_adjoint_initial_rate", "pf_timing", "pf_fem_table_size", "pf_fem_tables", "pf_mg_levels", "pf_mg_table",
     "pf_status_str", "pf_last_error",
     "pf_destroy",
@@ -116,6 +117,7 @@ def lib() -> ctypes.CDLL:
             "pf_energy": (ctypes.c_int, [vp, dp]),
             "pf_set_params": (ctypes.c_int, [vp, dp, ctypes.c_double]),
             "pf_adjoint_step": (ctypes.c_int, [vp, vp, vp, vp, vp, dp]),
+            "pf_adjoint_step_u": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, dp]),
             "pf_adjoint_initial_rate": (ctypes.c_int, [vp, vp, vp, vp, dp]),
             "pf_timing": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)]),
             "pf_fem_table_size": (sz, []),
@@ -381,14 +383,18 @@ class Context:
         a = float(self.cfg.a1 if a1 is None else a1)
         self._check(self.L.pf_set_params(self.ctx, arr, a), "pf_set_params")
 
-    def adjoint_step(self, Pn, Vn, lamP, lamV, dtheta):
+    def adjoint_step(self, Pn, Vn, lamP, lamV, dtheta, un=None):
+        """One reverse step; un (FP64 3N, optional): the u that forward step n
+        solved for, which spares the re-solve at the linearisation point."""
         self._field(Pn, 3, self.state_dtype, "P_n")
         self._field(lamP, 3, self.state_dtype, "lamP")
         self._field(lamV, 3, self.state_dtype, "lamV")
         if Vn is not None:
             self._field(Vn, 3, self.state_dtype, "V_n")
+        if un is not None:
+            self._field(un, 3, torch.float64, "u_n")
         arr = (ctypes.c_double * len(dtheta))(*dtheta)
-        s = self.L.pf_adjoint_step(self.ctx, _ptr(Pn), _ptr(Vn), _ptr(lamP), _ptr(lamV), arr)
+        s = self.L.pf_adjoint_step_u(self.ctx, _ptr(Pn), _ptr(Vn), _ptr(un), _ptr(lamP), _ptr(lamV), arr)
         self._check(s, "pf_adjoint_step", True)
         for t in range(len(dtheta)):
             dtheta[t] = arr[t]

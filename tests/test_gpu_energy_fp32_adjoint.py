@@ -172,6 +172,35 @@ def test_fp32_adjoint_gradient_matches_oracle(pf, oracle_mod):
     assert errs[0] < 1e-6 and errs[1] < 1e-6 and errs[2] < 1e-6
 
 
+def test_adjoint_step_with_forward_displacement(pf):
+    """pf_adjoint_step_u, given the displacement each forward step solved
+    for, agrees with pf_adjoint_step, which solves for it again (both to
+    tolerance 1e-13)."""
+    cfg = adjoint_cfg()
+    print("case: adjoint step with the forward displacement", flush=True)
+    P0 = dev(domain_polarisation(cfg, 33, block=3, std=0.2))
+    ctx = pf.Context(cfg)
+    ctx.set_state(P0)
+    states = []
+    for _ in range(4):
+        Pn, Vn = [t.clone() for t in ctx.get_state()[:2]]
+        ctx.step(1)
+        states.append((Pn, Vn, ctx.get_state()[3].clone()))
+    rng = np.random.default_rng(5)
+    lam0 = dev(rng.normal(size=(3,) + cfg.shape))
+    out = []
+    for use_u in (False, True):
+        c2 = pf.Context(cfg)
+        c2.set_state(P0)
+        lamP, lamV = lam0.clone(), torch.zeros_like(lam0)
+        dth = [0.0, 0.0, 0.0]
+        for Pn, Vn, un in reversed(states):
+            c2.adjoint_step(Pn, Vn, lamP, lamV, dth, un if use_u else None)
+        out.append((host(lamP), host(lamV), np.array(dth)))
+    for a, b in zip(*out):
+        assert rel(a, b) < 1e-9
+
+
 def test_adjoint_full_size_vs_central_differences(pf):
     """The 128x128x32 adjoint case: dJ/dV_1, dJ/dV_2, dJ/da1 of the mean Pz
     over the 32x32x8 box after 50 steps (checkpoint every 10) against
