@@ -4,10 +4,11 @@ Forward: n library steps from P0 with the electrode voltages and Landau a1
 given as tensors, keeping the full state (P, V, phi, u) every k steps.
 Backward: for each checkpoint segment, newest first, the segment is
 recomputed from its checkpoint (bitwise identical: the library's reductions
-are deterministic and the checkpoint carries the solver warm starts), and
-the discrete adjoint of every step is applied in reverse with
-pf_adjoint_step_u, given the displacement that the recomputed step solved
-for; finally pf_adjoint_initial_rate folds in the initial rate
+are deterministic and the checkpoint carries the solver warm starts; the
+newest segment's states are kept from the forward instead), and the
+discrete adjoint of every step is applied in reverse with
+pf_adjoint_step_u, given the displacement that the step solved for;
+finally pf_adjoint_initial_rate folds in the initial rate
 V0 = F(P0) of the predictor-corrector.  Gradients are returned for P0, the
 voltages and a1.
 """
@@ -28,6 +29,10 @@ class PFSteps(torch.autograd.Function):
         P0c = P0.detach().contiguous()
         pf.set_state(P0c)
         checkpoints = []
+        # the states of the last segment are kept as the forward makes them
+        # (the backward starts there, so that segment needs no recomputation)
+        last_start = ((nsteps - 1) // k) * k if nsteps > 0 else 0
+        last = []
         for s in range(nsteps):
             if s % k == 0:
                 cp = pf.get_state()
@@ -36,8 +41,14 @@ class PFSteps(torch.autograd.Function):
                 # identical to its recomputation (solver warm-start history
                 # starts afresh at every checkpoint)
                 pf.restore_state(*cp)
-            pf.step(1)
+            if s >= last_start:
+                Pn, Vn = pf.get_state()[:2]
+                pf.step(1)
+                last.append((Pn, Vn, pf.get_state()[3]))
+            else:
+                pf.step(1)
         PN = pf.get_state()[0]
+        fctx.last = last
         fctx.pf = pf
         fctx.nsteps = nsteps
         fctx.k = k
@@ -55,21 +66,26 @@ class PFSteps(torch.autograd.Function):
         lamV = torch.zeros_like(lamP)
         dtheta = [0.0] * (fctx.n_volts + 1)
         nsteps, k = fctx.nsteps, fctx.k
-        for seg in reversed(range(len(fctx.checkpoints))):
-            P, V, phi, u, step = fctx.checkpoints[seg]
-            start = seg * k
-            stop = min(nsteps, start + k)
-            pf.restore_state(P, V, phi, u, step)
-            states = []
-            for _ in range(start, stop):
-                Pn, Vn = pf.get_state()[:2]
-                pf.step(1)
-                # the displacement step n solved for: the adjoint step's
-                # linearisation point needs no second solve
-                un = pf.get_state()[3]
-                states.append((Pn, Vn, un))
+        nseg = len(fctx.checkpoints)
+        for seg in reversed(range(nseg)):
+            if seg == nseg - 1:
+                states = fctx.last
+            else:
+                P, V, phi, u, step = fctx.checkpoints[seg]
+                start = seg * k
+                stop = min(nsteps, start + k)
+                pf.restore_state(P, V, phi, u, step)
+                states = []
+                for _ in range(start, stop):
+                    Pn, Vn = pf.get_state()[:2]
+                    pf.step(1)
+                    # the displacement step n solved for: the adjoint step's
+                    # linearisation point needs no second solve
+                    un = pf.get_state()[3]
+                    states.append((Pn, Vn, un))
             for Pn, Vn, un in reversed(states):
                 pf.adjoint_step(Pn, Vn, lamP, lamV, dtheta, un)
+        fctx.last = None
         pf.adjoint_initial_rate(P0, lamP, lamV, dtheta)
         vdev, vdt, adev, adt = fctx.theta_dev
         g_volts = torch.tensor(dtheta[:fctx.n_volts], dtype=vdt, device=vdev)
