@@ -902,15 +902,21 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
   const int64_t N = d.N, pl = d.plane;
   const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
   const bool hasV = V != nullptr, hasW = W != nullptr;
-  Stage<T, 9, H::NPT> sp;  // P, V, W of the next source plane
+  // the prefetch keeps P and V in the state precision: converting a loaded
+  // value would wait for the load; they are converted when staged
+  Stage<S, 6, H::NPT> sp;  // P, V of the next source plane
+  Stage<T, 3, H::NPT> sw;  // W of the next source plane (with hasW)
   Stage<T, 3, H::NPT> sx;  // x of the next plane
-  auto fetch_p = [&](int64_t m, int, T* raw) {
+  auto fetch_p = [&](int64_t m, int, S* raw) {
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      raw[c] = (T)P[c * N + m];
-      raw[3 + c] = hasV ? (T)V[c * N + m] : (T)0;
-      raw[6 + c] = hasW ? W[c * N + m] : (T)0;
+      raw[c] = P[c * N + m];
+      raw[3 + c] = hasV ? V[c * N + m] : (S)0;
     }
+  };
+  auto fetch_w = [&](int64_t m, int, T* raw) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) raw[c] = W[c * N + m];
   };
   auto fetch_x = [&](int64_t m, int k, T* raw) {
     if (k == 0) return;  // the clamp
@@ -923,6 +929,7 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
   };
   auto fetch = [&](int k) {
     stage_fetch<TY>(sp, d, tc.i0, tc.j0, k, fetch_p);
+    if (hasW) stage_fetch<TY>(sw, d, tc.i0, tc.j0, k, fetch_w);
     stage_fetch<TY>(sx, d, tc.i0, tc.j0, k, fetch_x);
   };
   // stage plane s: eigenstress into sgm, x into the ring
@@ -936,10 +943,10 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
       const bool live = s >= 0 && s < d.nz && gi >= -1 && gi <= d.nx && gj >= -1 && gj <= d.ny;
       T sg[6] = {0, 0, 0, 0, 0, 0};
       if (live) {
-        const T* raw = sp.v[q];
-        const T px = raw[0] + cdt * raw[3], py = raw[1] + cdt * raw[4], pz = raw[2] + cdt * raw[5];
+        const S* raw = sp.v[q];
+        const T px = (T)raw[0] + cdt * (T)raw[3], py = (T)raw[1] + cdt * (T)raw[4], pz = (T)raw[2] + cdt * (T)raw[5];
         T e[6];
-        if (hasW) eigenstrain_lin<ROT>(cf, px, py, pz, raw[6], raw[7], raw[8], e);
+        if (hasW) eigenstrain_lin<ROT>(cf, px, py, pz, sw.v[q][0], sw.v[q][1], sw.v[q][2], e);
         else eigenstrain<ROT>(cf, px, py, pz, e);
         cubic_stress<ROT>(cf, e, sg);
       }
