@@ -397,8 +397,9 @@ struct Layout {
   size_t fbody;                // FP32_REFINE: the FEM body force of the first sweep (FP64)
   size_t hist;                 // ring of earlier solutions for extrapolated warm starts
                                // (extrap_order slots of Np (phi) then extrap_order of 3N (u))
-  size_t adj_hist;             // the same for the adjoint solutions: psi (Np), the displacement
-                               // at the linearisation point (3N), the adjoint displacement (3N)
+  size_t adj_hist;             // the same for the adjoint solutions: psi (Np) and the adjoint
+                               // displacement (3N), then the displacement at the
+                               // linearisation point (3N, a ring of its own)
   size_t scratch[8];           // max(3N, Np) doubles each: adjoint, energy, conversions
   size_t tables, scalars, result, partials;
   MgLayout mg[2];              // multigrid of the Poisson (0) and the FEM (1) operator
@@ -565,7 +566,8 @@ struct pf_ctx {
   bool adj_warm;            // adjoint scratch holds earlier adjoint solutions
   int hist_valid;           // solutions held for extrapolated warm starts (0..extrap_order)
   int hist_head;            // ring slot that the next stored solution goes to
-  int adj_valid, adj_head;  // the same for the adjoint solutions
+  int adj_valid, adj_head;  // the same for the adjoint solutions psi and du
+  int lin_valid, lin_head;  // and for the displacement at the linearisation point
   int64_t step;
   int cur;                  // which P/V buffer is current
   int pred[pf::kPredCount];
@@ -1529,19 +1531,27 @@ pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt, const double* ulin_
   double* du = scratch<double>(c, kScrDu);
   double* psi = scratch<double>(c, kScrPsi);
   // warm_start 2: the adjoint solutions of the previous adjoint steps are
-  // extrapolated like the forward ones (rings of psi, ulin, du)
-  ExtrapRing ring[3];
-  const int64_t len[3] = {c->dims_p.N, 3 * d.N, 3 * d.N};
-  const bool ex = c->adj_warm && c->cfg.warm_start == 2 &&
-                  ring_plan(c, c->lay.adj_hist, 3, len, c->adj_valid, c->adj_head, ring);
+  // extrapolated like the forward ones (rings of psi and du; ulin has a ring
+  // of its own, which restarts after steps that were given ulin)
+  ExtrapRing ring[2], lring[1];
+  const int64_t len[2] = {c->dims_p.N, 3 * d.N};
+  const int64_t llen[1] = {3 * d.N};
+  const bool xw = c->adj_warm && c->cfg.warm_start == 2;
+  const bool ex = xw && ring_plan(c, c->lay.adj_hist, 2, len, c->adj_valid, c->adj_head, ring);
+  const size_t loff = c->lay.adj_hist + (size_t)c->cfg.extrap_order * (size_t)(len[0] + len[1]) * 8;
+  const bool lex = xw && !ulin_in && ring_plan(c, loff, 1, llen, c->lin_valid, c->lin_head, lring);
+  if (ulin_in) {
+    // the scratch keeps the latest displacement, a valid warm start should a
+    // later step have to solve for it
+    c->lin_valid = 0;
+    PF_HIP(c, hipMemcpyAsync(ulin, ulin_in, (size_t)llen[0] * sizeof(double), hipMemcpyDeviceToDevice, strm(c)));
+  }
   // the displacement at the linearisation point and the adjoint displacement
   // (given: the forward step's own solution, no solve)
   auto fem = [&]() -> pf_status {
     SolveResult r{};
-    if (ex) {
-      if (!ulin_in) PF_TRY(extrapolate_into(c, ulin, len[1], ring[1]));
-      PF_TRY(extrapolate_into(c, du, len[2], ring[2]));
-    }
+    if (lex) PF_TRY(extrapolate_into(c, ulin, llen[0], lring[0]));
+    if (ex) PF_TRY(extrapolate_into(c, du, len[1], ring[1]));
     pf_status s = PF_OK;
     if (!ulin_in) {
       s = solve_fem64<S>(c, kPredAdjU, P, V, cdt, nullptr, ulin, c->cfg.tol_u, c->adj_warm, &r);
@@ -1802,6 +1812,8 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->hist_head = 0;
   c->adj_valid = 0;
   c->adj_head = 0;
+  c->lin_valid = 0;
+  c->lin_head = 0;
   c->step = 0;
   c->cur = 0;
   for (int t = 0; t < kPredCount; t++) c->pred[t] = 16;

@@ -182,23 +182,27 @@ def test_adjoint_step_with_forward_displacement(pf):
     ctx = pf.Context(cfg)
     ctx.set_state(P0)
     states = []
-    for _ in range(4):
+    for _ in range(6):
         Pn, Vn = [t.clone() for t in ctx.get_state()[:2]]
         ctx.step(1)
         states.append((Pn, Vn, ctx.get_state()[3].clone()))
     rng = np.random.default_rng(5)
     lam0 = dev(rng.normal(size=(3,) + cfg.shape))
     out = []
-    for use_u in (False, True):
+    # never given, always given, and given on every other step (the solves in
+    # between restart the displacement's extrapolation from the given ones)
+    for mode in ("none", "all", "mixed"):
         c2 = pf.Context(cfg)
         c2.set_state(P0)
         lamP, lamV = lam0.clone(), torch.zeros_like(lam0)
         dth = [0.0, 0.0, 0.0]
-        for Pn, Vn, un in reversed(states):
-            c2.adjoint_step(Pn, Vn, lamP, lamV, dth, un if use_u else None)
+        for t, (Pn, Vn, un) in enumerate(reversed(states)):
+            give = mode == "all" or (mode == "mixed" and t % 2 == 0)
+            c2.adjoint_step(Pn, Vn, lamP, lamV, dth, un if give else None)
         out.append((host(lamP), host(lamV), np.array(dth)))
-    for a, b in zip(*out):
-        assert rel(a, b) < 1e-9
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert rel(b, a) < 1e-9
 
 
 def test_adjoint_full_size_vs_central_differences(pf):
