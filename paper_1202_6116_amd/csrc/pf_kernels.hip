@@ -1741,7 +1741,7 @@ __global__ __launch_bounds__(kThreads) void mg_level_kernel(Dims d, const double
   }
 }
 
-// Levels with at least this many nodes use mg_level_tile_kernel.
+// FP64 levels with at least this many nodes use mg_level_tile_kernel.
 constexpr int64_t kMgTileMinNodes = 1 << 19;
 
 // mg_level_kernel with the neighbourhood staged: the block's kBX x kBY
@@ -2970,9 +2970,11 @@ hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb,
 template <typename T>
 hipError_t launch_mg_level(const Dims& d, int nc, const double* tab, const double* dinv, int mode, double omega,
                            const T* x, const T* b, T* out, const CgScalars* sc, int top_fixed, hipStream_t s) {
-  // large levels stage the neighbourhood in LDS; on small ones the extra
-  // barrier and staging cost more than the loads they save
-  const bool tile = d.N >= kMgTileMinNodes;
+  // large FP64 levels stage the neighbourhood in LDS; on small ones the
+  // extra barrier and staging cost more than the loads they save, and with
+  // FP32 vectors the node kernel's loads are cheap enough that the LDS
+  // reads of the staged form do not pay
+  const bool tile = sizeof(T) == 8 && d.N >= kMgTileMinNodes;
   if (nc == 3) {
     if (tile)
       mg_level_tile_kernel<T, 3><<<node_grid(d), node_block(), 0, s>>>(d, tab, dinv, mode, omega, x, b, out, sc,
