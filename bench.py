@@ -52,12 +52,12 @@ BYTES_PER_NODE_FP64 = {
 # HBM bytes per working launch measured with rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (fetch counts scaled by 2.0, writes by 1.0, from a 1 GiB copy)
 # for the current kernels (mg_u0: the mean of its two kernels, the first
-# sweep's residual (245.9 MB) and the correction with the last sweep
-# (231.9 MB), which run equally often); summary and commands in
+# sweep's residual (244.5 MB) and the correction with the last sweep
+# (232.8 MB), which run equally often); summary and commands in
 # profiles/mg_u0_fp64_lateral_256x256x64.md.  Keyed by workload, precision
 # and kernel class; anything else reports null.
 MEASURED_TRAFFIC = {
-    ("lateral_256x256x64", "fp64", "mg_u0"): 238.9e6,
+    ("lateral_256x256x64", "fp64", "mg_u0"): 238.6e6,
     ("lateral_256x256x64", "fp64", "fem_a"): 606.1e6,
 }
 
