@@ -174,12 +174,18 @@ def micron_leg(pf, torch, workloads, initial_polarisation, warm_start, precond, 
 def precision_leg(pf, torch, workloads, initial_polarisation, warm_start, precond, steps=10, warmup=10):
     """The 512x512x128 lateral film for a few steps in FP32 sweeps with FP64
     refinement and in plain FP64 from the same start; returns both step times
-    and the per-field relative difference after the steps."""
+    and the per-field relative difference after the steps, and the same for
+    plain FP64 with looser solver tolerances (the FP64 path at the final-P
+    accuracy that FP32 + refinement reaches)."""
     w = workloads()["lateral_512x512x128_fp32"]
     res = {"workload": w.name, "steps": steps, "warmup": warmup}
     states = {}
-    for prec in ("fp32_refine", "fp64"):
+    runs = [("fp32_refine", "fp32_refine", None), ("fp64", "fp64", None),
+            ("fp64_tol_1e-07", "fp64", 1e-7), ("fp64_tol_1e-06", "fp64", 1e-6)]
+    for name, prec, tol in runs:
         cfg = w.cfg.replace(precision=prec, warm_start=warm_start, precond=precond)
+        if tol is not None:
+            cfg = cfg.replace(tol_phi=tol, tol_u=tol)
         ctx = pf.Context(cfg, "cuda:0")
         P0 = torch.from_numpy(initial_polarisation(w)).to("cuda:0").to(ctx.state_dtype)
         ctx.set_state(P0)
@@ -189,17 +195,21 @@ def precision_leg(pf, torch, workloads, initial_polarisation, warm_start, precon
         st = ctx.step(steps)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        res[prec] = {"ms_per_step": round(1e3 * dt, 2), "cell_steps_per_s": cfg.nodes / dt,
+        res[name] = {"ms_per_step": round(1e3 * dt, 2), "cell_steps_per_s": cfg.nodes / dt,
                      "cg_iters_per_step": {"phi": st["iters_phi"] / max(1, st["solves_phi"]),
                                            "u": st["iters_u"] / max(1, st["solves_u"])}}
         P, V, phi, u, _ = ctx.get_state()
-        states[prec] = [t.double() for t in (P, V, phi, u)]
+        states[name] = [t.double() for t in (P, V, phi, u)]
         del ctx
         torch.cuda.empty_cache()
     res["speedup_fp32_refine_vs_fp64"] = round(res["fp64"]["ms_per_step"] / res["fp32_refine"]["ms_per_step"], 3)
-    res["rel_diff_vs_fp64"] = {
-        name: float((a - b).abs().max() / b.abs().max())
-        for name, a, b in zip(("P", "V", "phi", "u"), states["fp32_refine"], states["fp64"])}
+    def rel_diff(run):
+        return {field: float((a - b).abs().max() / b.abs().max())
+                for field, a, b in zip(("P", "V", "phi", "u"), states[run], states["fp64"])}
+
+    res["rel_diff_vs_fp64"] = rel_diff("fp32_refine")
+    for name, _, tol in runs[2:]:
+        res[name]["rel_diff_vs_fp64"] = rel_diff(name)
     return res
 
 
