@@ -123,12 +123,14 @@ def adjoint_cfg(**kw):
     return PFConfig(**base)
 
 
-@pytest.mark.parametrize("integrator", ["pc", "euler"])
-def test_adjoint_gradient_matches_oracle(pf, oracle_mod, integrator):
+@pytest.mark.parametrize("integrator,ws", [("pc", 1), ("euler", 1), ("pc", 2)])
+def test_adjoint_gradient_matches_oracle(pf, oracle_mod, integrator, ws):
+    """warm_start 2 also extrapolates the adjoint solves' initial guesses
+    (eight steps fill the rings of order 4)."""
     from paper_1202_6116_amd.autograd import tdgl_steps
-    cfg = adjoint_cfg(integrator=integrator)
-    print(f"case: adjoint {integrator}", flush=True)
-    nsteps = 6
+    cfg = adjoint_cfg(integrator=integrator, warm_start=ws)
+    print(f"case: adjoint {integrator} warm start {ws}", flush=True)
+    nsteps = 6 if ws == 1 else 8
     P0 = domain_polarisation(cfg, 31, block=3, std=0.2)
     wgt = np.zeros((3,) + cfg.shape)
     wgt[2, 2:, 2:6, 3:10] = 1.0 / 3 / 4 / 7

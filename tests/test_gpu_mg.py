@@ -122,13 +122,14 @@ def test_mg_rotated_open_top(pf, oracle_mod):
     assert rel(host(ug), u) < TOL
 
 
-def test_mg_adjoint_matches_oracle(pf, oracle_mod):
+@pytest.mark.parametrize("ws", [1, 2])
+def test_mg_adjoint_matches_oracle(pf, oracle_mod, ws):
     from paper_1202_6116_amd.autograd import tdgl_steps
     cfg = PFConfig(nx=32, ny=16, nz=6, tol_phi=1e-13, tol_u=1e-13, dt=0.05, precond="mg",
-                   Q11=0.5, Q12=-0.15, Q44=0.2,
+                   Q11=0.5, Q12=-0.15, Q44=0.2, warm_start=ws,
                    electrodes=[Electrode(2, 8, 0, 16, 1.0), Electrode(18, 24, 0, 16, -1.0)])
-    print("case: mg adjoint", flush=True)
-    nsteps = 5
+    print(f"case: mg adjoint, warm start {ws}", flush=True)
+    nsteps = 5 if ws == 1 else 8
     P0 = domain_polarisation(cfg, 74, block=3, std=0.2)
     wgt = np.zeros((3,) + cfg.shape)
     wgt[2, 2:, 2:6, 3:10] = 1.0 / 4 / 4 / 7
