@@ -63,7 +63,8 @@ template <typename T, typename U> hipError_t launch_convert(const T* a, U* b, in
 template <typename T> hipError_t launch_cg_finish(T* x, const T* p, int64_t n, const CgScalars* sc, hipStream_t s);
 hipError_t launch_cg_reduce(const double* partials, int nblocks, int nv, CgScalars* sc, int mode, double tol,
                             int maxit, hipStream_t s, double tol2, double* out);
-hipError_t launch_refine_update(double* x64, float* x32, const float* d, int64_t n, hipStream_t s);
+hipError_t launch_refine_update(double* x64, float* x32, const float* d, const float* p, const CgScalars* sc,
+                                int64_t n, hipStream_t s);
 hipError_t launch_extrapolate(double* x, const ExtrapRing& ring, int64_t n, hipStream_t s);
 template <typename T, typename S, typename R>
 hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
@@ -852,8 +853,11 @@ struct SolveResult {
 };
 
 template <typename T>
+// defer (non-null): the deferred last update x += alpha p is left to the
+// caller, who receives p.
 pf_status run_cg(pf_ctx* c, int which, int predicted, T* x, T* const pbuf[2], int64_t n,
-                 const std::function<hipError_t(int)>& iteration, CgScalars* hout, const char* what) {
+                 const std::function<hipError_t(int)>& iteration, CgScalars* hout, const char* what,
+                 const T** defer = nullptr) {
   CgScalars h;
   int k = 0;
   int batch = std::max(2, predicted);
@@ -869,9 +873,12 @@ pf_status run_cg(pf_ctx* c, int which, int predicted, T* x, T* const pbuf[2], in
     // multigrid cycle) for one more read-back
     batch = std::max(1, predicted / 8);
   }
-  if (h.done != kNonFinite)
-    PF_HIP(c, timed(c, PF_KC_FINISH, -1, -1,
-                    [&] { return launch_cg_finish<T>(x, pbuf[h.iter & 1], n, dev_sc(c, which), strm(c)); }));
+  if (h.done != kNonFinite) {
+    if (defer) *defer = pbuf[h.iter & 1];
+    else
+      PF_HIP(c, timed(c, PF_KC_FINISH, -1, -1,
+                      [&] { return launch_cg_finish<T>(x, pbuf[h.iter & 1], n, dev_sc(c, which), strm(c)); }));
+  }
   *hout = h;
   if (h.done == kNonFinite) return fail(c, PF_ENONFINITE, "%s: non-finite value in the CG reductions", what);
   return PF_OK;
@@ -1180,6 +1187,7 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
     }
     PF_HIP(c, reduce(c, part, setup_blocks, 3, which, kRedOuter, tol, kInnerTol, nullptr));
     CgScalars h;
+    const float* pfin = nullptr;  // the inner solve's deferred last update (applied by the refinement update)
     bool inner = true;
     if (res->outer > 0) {
       // a later sweep mostly finds the outer test met: read it back before
@@ -1191,7 +1199,7 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
     }
     if (inner) {
       if (mg_on(c, which)) PF_HIP(c, mg_setup<float>(c, which, r));
-      PF_TRY(run_cg<float>(c, which, c->pred[pred], dz, pb, n, iteration, &h, what));
+      PF_TRY(run_cg<float>(c, which, c->pred[pred], dz, pb, n, iteration, &h, what, &pfin));
       res->iters += h.iter;
     }
     res->relres = h.outer_b2 > 0 ? std::sqrt(h.outer_r2 / h.outer_b2) : 0.0;
@@ -1205,7 +1213,9 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
       return PF_OK;
     }
     if (h.iter > 0) c->pred[pred] = h.iter;
-    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_refine_update(x64, x32, dz, n, strm(c)); }));
+    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+      return launch_refine_update(x64, x32, dz, pfin, pfin ? dev_sc(c, which) : nullptr, n, strm(c));
+    }));
     synced = true;
     res->outer++;
     if (res->outer >= kMaxOuter) {

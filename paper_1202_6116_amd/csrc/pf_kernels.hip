@@ -377,11 +377,18 @@ __global__ void extrapolate_kernel(double* x, ExtrapRing ring, int64_t n) {
 }
 
 // Iterative refinement: x64 += d, x32 = x64 (rounded working copy).
-__global__ void refine_update_kernel(double* x64, float* x32, const float* d, int64_t n) {
+// x64 += d, x32 = (float) x64.  With p, the inner solve's deferred last
+// update is applied first, d + alpha p, as cg_finish_kernel would have
+// (zero when the inner right-hand side was zero).
+__global__ void refine_update_kernel(double* x64, float* x32, const float* d, const float* p, const CgScalars* sc,
+                                     int64_t n) {
+  const float alpha = p ? (float)sc->alpha : 0.f;
+  const bool zero = p && sc->zero_rhs != 0;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; t < n; t += stride) {
-    const double v = x64[t] + (double)d[t];
+    const float dz = p ? (zero ? 0.f : d[t] + alpha * p[t]) : d[t];
+    const double v = x64[t] + (double)dz;
     x64[t] = v;
     x32[t] = (float)v;
   }
@@ -2858,8 +2865,9 @@ hipError_t launch_noise(const NoiseSpec& ns, int64_t N, double* xi, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_refine_update(double* x64, float* x32, const float* d, int64_t n, hipStream_t s) {
-  refine_update_kernel<<<flat_blocks(n), 256, 0, s>>>(x64, x32, d, n);
+hipError_t launch_refine_update(double* x64, float* x32, const float* d, const float* p, const CgScalars* sc,
+                                int64_t n, hipStream_t s) {
+  refine_update_kernel<<<flat_blocks(n), 256, 0, s>>>(x64, x32, d, p, sc, n);
   return hipGetLastError();
 }
 
