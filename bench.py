@@ -101,7 +101,7 @@ def cpu_baseline(w, side=64):
 
 def adjoint_leg(pf, torch, workloads, initial_polarisation, warm_start, precond):
     """Forward (50 steps, checkpoints every 10) and backward of the adjoint
-    case; returns timings and the gradient."""
+    case, after one untimed pass of both; returns timings and the gradient."""
     from paper_1202_6116_amd.autograd import tdgl_steps
     w = workloads()["adjoint_128x128x32"]
     cfg = w.cfg.replace(warm_start=warm_start, precond=precond)
@@ -110,17 +110,18 @@ def adjoint_leg(pf, torch, workloads, initial_polarisation, warm_start, precond)
     x0, x1, y0, y1, z0, z1 = w.region
     wgt = torch.zeros((3,) + cfg.shape, dtype=torch.float64, device="cuda:0")
     wgt[2, z0:z1, y0:y1, x0:x1] = 1.0 / ((x1 - x0) * (y1 - y0) * (z1 - z0))
-    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
-    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    PN = tdgl_steps(P0, volts, a1, ctx, w.steps, w.checkpoint_every)
-    J = (PN * wgt).sum()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    J.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    for rep in range(2):  # the first pass is an untimed warm-up; both do the same work
+        volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+        a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        PN = tdgl_steps(P0, volts, a1, ctx, w.steps, w.checkpoint_every)
+        J = (PN * wgt).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
     return {"workload": w.name, "steps": w.steps, "checkpoint_every": w.checkpoint_every,
             "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
             "adjoint_fwd_ratio": round((t2 - t1) / (t1 - t0), 3),

@@ -272,7 +272,9 @@ pf_status pf_adjoint_step_u(pf_ctx *ctx, const void *P_n, const void *V_n, const
 
 /* Folds the initial rate V0 = F(P0) of the predictor-corrector into the
  * adjoints: lamP += (dF/dP)(P0) lamV, dtheta += lamV . dF/dtheta(P0),
- * lamV = 0.  No-op for Euler.  Synchronises. */
+ * lamV = 0 (no-op for Euler).  Ends the reverse sweep in both cases: the
+ * next adjoint step starts its solves from zero instead of from this sweep's
+ * adjoint solutions.  Synchronises. */
 pf_status pf_adjoint_initial_rate(pf_ctx *ctx, const void *P0, void *lamP, void *lamV, double *dtheta);
 
 /* Kernel classes for pf_timing. */

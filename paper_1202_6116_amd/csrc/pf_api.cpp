@@ -2100,12 +2100,21 @@ pf_status pf_adjoint_step(pf_ctx* c, const void* P_n, const void* V_n, void* lam
 
 pf_status pf_adjoint_initial_rate(pf_ctx* c, const void* P0, void* lamP, void* lamV, double* dtheta) {
   if (!c || !P0 || !lamP || !lamV || !dtheta) return fail(c, PF_EINVAL, "pf_adjoint_initial_rate: null argument");
-  if (c->cfg.integrator != PF_INT_PC) return PF_OK;
-  if (fp32(c))
-    return adjoint_initial_t<float>(c, static_cast<const float*>(P0), static_cast<float*>(lamP),
-                                    static_cast<float*>(lamV), dtheta);
-  return adjoint_initial_t<double>(c, static_cast<const double*>(P0), static_cast<double*>(lamP),
-                                   static_cast<double*>(lamV), dtheta);
+  pf_status s = PF_OK;
+  if (c->cfg.integrator == PF_INT_PC) {
+    if (fp32(c))
+      s = adjoint_initial_t<float>(c, static_cast<const float*>(P0), static_cast<float*>(lamP),
+                                   static_cast<float*>(lamV), dtheta);
+    else
+      s = adjoint_initial_t<double>(c, static_cast<const double*>(P0), static_cast<double*>(lamP),
+                                    static_cast<double*>(lamV), dtheta);
+  }
+  // The reverse sweep ends here: the next adjoint step starts its solves from
+  // zero, so a sweep does not depend on the solutions of an earlier one.
+  c->adj_warm = false;
+  c->adj_valid = c->adj_head = 0;
+  c->lin_valid = c->lin_head = 0;
+  return s;
 }
 
 pf_status pf_timing(pf_ctx* c, int enable, double* ms, int64_t* launches) {

@@ -148,6 +148,30 @@ def test_adjoint_gradient_matches_oracle(pf, oracle_mod, integrator, ws):
     assert rel(host(P0t.grad), dP_ref) < 1e-7
 
 
+@pytest.mark.parametrize("integrator", ["pc", "euler"])
+def test_repeated_backward_is_bitwise_reproducible(pf, integrator):
+    """The adjoint warm starts carry within one reverse sweep only: a second
+    forward and backward on the same context gives the same gradient bit for
+    bit."""
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    cfg = adjoint_cfg(integrator=integrator, warm_start=2, tol_phi=1e-10, tol_u=1e-10)
+    print(f"case: repeated backward {integrator}", flush=True)
+    P0 = domain_polarisation(cfg, 33, block=3, std=0.2)
+    wgt = dev(np.full((3,) + cfg.shape, 1.0 / (3 * cfg.nx * cfg.ny * cfg.nz)))
+    ctx = pf.Context(cfg)
+    grads = []
+    for _ in range(2):
+        P0t = dev(P0).requires_grad_(True)
+        volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+        a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+        PN = tdgl_steps(P0t, volts, a1, ctx, 8, checkpoint_every=3)
+        ((PN * PN) * wgt).sum().backward()
+        grads.append((host(volts.grad), float(a1.grad), host(P0t.grad)))
+    assert np.array_equal(grads[0][0], grads[1][0])
+    assert grads[0][1] == grads[1][1]
+    assert np.array_equal(grads[0][2], grads[1][2])
+
+
 def test_fp32_adjoint_gradient_matches_oracle(pf, oracle_mod):
     """The adjoint of an FP32 + refinement context (FP32 state and adjoint
     vectors, FP64 solves) against the FP64 oracle's adjoint gradient: the
