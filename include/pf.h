@@ -247,7 +247,8 @@ pf_status pf_noise(pf_ctx *ctx, int64_t step, double *xi);
 pf_status pf_energy(pf_ctx *ctx, double out[5]);
 
 /* Changes electrode voltages (n_electrodes host doubles, NULL: keep) and
- * the Landau coefficient a1 (used by the differentiable layer). */
+ * the Landau coefficient a1 (used by the differentiable layer).  A
+ * non-finite value returns PF_EINVAL and changes nothing. */
 pf_status pf_set_params(pf_ctx *ctx, const double *volts, double a1);
 
 /* One reverse step of the discrete adjoint of pf_step (needs

@@ -2065,13 +2065,15 @@ pf_status pf_energy(pf_ctx* c, double out[5]) {
 
 pf_status pf_set_params(pf_ctx* c, const double* volts, double a1) {
   if (!c) return PF_EINVAL;
+  // validate everything before changing anything: a rejected call leaves the
+  // parameters as they were
   if (!std::isfinite(a1)) return fail(c, PF_EINVAL, "pf_set_params: a1 not finite");
+  if (volts)
+    for (int e = 0; e < c->cfg.n_electrodes; e++)
+      if (!std::isfinite(volts[e])) return fail(c, PF_EINVAL, "pf_set_params: voltage not finite");
   c->cfg.a1 = a1;
   if (volts) {
-    for (int e = 0; e < c->cfg.n_electrodes; e++) {
-      if (!std::isfinite(volts[e])) return fail(c, PF_EINVAL, "pf_set_params: voltage not finite");
-      c->electrodes[e].volts = volts[e];
-    }
+    for (int e = 0; e < c->cfg.n_electrodes; e++) c->electrodes[e].volts = volts[e];
     c->phi_bc_valid = false;
     c->hist_valid = 0;
     c->hist_head = 0;

@@ -211,3 +211,46 @@ def test_cubic_stiffness_has_the_compact_form(C):
                     ref = seen.setdefault(key, sgn * v)
                     assert abs(v - sgn * ref) <= 1e-12 * kmax, (zt, c, e, off, v, ref)
         assert len(seen) == (8 if zt == 0 else 24)
+
+
+def test_null_context_is_rejected_without_touching_the_device():
+    """Every entry point that takes a context returns PF_EINVAL for a null
+    one before any HIP call, and the status strings cover every code."""
+    L = pf.lib()
+    z = None
+    calls = {
+        "pf_set_state": (z, z, z, z),
+        "pf_restore_state": (z, z, z, z, z, 0),
+        "pf_get_state": (z, z, z, z, z, z),
+        "pf_step": (z, 1, z),
+        "pf_solve_phi": (z, z, z, z),
+        "pf_solve_u": (z, z, z, z),
+        "pf_force": (z, z, z, z, z),
+        "pf_noise": (z, 0, z),
+        "pf_energy": (z, z),
+        "pf_set_params": (z, z, 0.0),
+        "pf_adjoint_step": (z, z, z, z, z, z),
+        "pf_adjoint_step_u": (z, z, z, z, z, z, z),
+        "pf_adjoint_initial_rate": (z, z, z, z, z),
+        "pf_timing": (z, 0, z, z),
+    }
+    for name, args in calls.items():
+        assert getattr(L, name)(*args) == pf.PF_EINVAL, name
+    L.pf_destroy(None)
+    assert pf.status_str(pf.PF_OK) == "ok"
+    texts = {pf.status_str(s) for s in (pf.PF_EINVAL, pf.PF_ENOMEM, pf.PF_EHIP, pf.PF_ENOCONV,
+                                        pf.PF_ENONFINITE, pf.PF_ESTATE)}
+    assert len(texts) == 6 and "ok" not in texts
+
+
+def test_table_queries_reject_bad_arguments():
+    cfg = PFConfig(nx=32, ny=32, nz=8)
+    c, keep = pf.make_config(cfg)
+    L = pf.lib()
+    n = ctypes.c_int32()
+    assert L.pf_mg_levels(ctypes.byref(c), 2, ctypes.byref(n), None, None, 0) == pf.PF_EINVAL
+    assert L.pf_mg_levels(ctypes.byref(c), 1, ctypes.byref(n), None, None, 0) == pf.PF_OK and n.value >= 2
+    out = (ctypes.c_double * 4)()
+    assert L.pf_mg_table(ctypes.byref(c), 1, n.value, out, 4) == pf.PF_EINVAL   # level out of range
+    assert L.pf_mg_table(ctypes.byref(c), 1, 0, out, 1) == pf.PF_EINVAL         # buffer too small
+    assert L.pf_fem_tables(ctypes.byref(c), out, 1) == pf.PF_EINVAL
