@@ -241,8 +241,7 @@ def main():
                     help="after the run, copy a 1 GiB device buffer 4 times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; the path's sharding across GPUs is described in the "
-              "design notes, not implemented", file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus 1); the step is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -254,3 +254,17 @@ def test_table_queries_reject_bad_arguments():
     assert L.pf_mg_table(ctypes.byref(c), 1, n.value, out, 4) == pf.PF_EINVAL   # level out of range
     assert L.pf_mg_table(ctypes.byref(c), 1, 0, out, 1) == pf.PF_EINVAL         # buffer too small
     assert L.pf_fem_tables(ctypes.byref(c), out, 1) == pf.PF_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with status 2 and
+    says so, before touching any device."""
+    import subprocess
+    import sys
+    from pathlib import Path
+    root = Path(__file__).resolve().parents[1]
+    r = subprocess.run([sys.executable, str(root / "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
