@@ -97,8 +97,8 @@ static inline int64_t nphi(const or_params *p) { return (int64_t)p->nx * p->ny *
 
 static inline int64_t node(const or_params *p, int i, int j, int k) {
     int nx = p->nx, ny = p->ny;
-    i = ((i % nx) + nx) % nx;    /* periodic x */
-    j = ((j % ny) + ny) % ny;    /* periodic y */
+    if (i < 0 || i >= nx) i = ((i % nx) + nx) % nx;    /* periodic x */
+    if (j < 0 || j >= ny) j = ((j % ny) + ny) % ny;    /* periodic y */
     return (int64_t)i + (int64_t)nx * ((int64_t)j + (int64_t)ny * k);
 }
 
@@ -857,6 +857,7 @@ static int pcg(const or_params *p, apply_fn A, const void *actx, const double *d
     }
     if (!warm) memset(x, 0, sizeof(double) * (size_t)n);
     A(p, actx, x, q);
+    #pragma omp parallel for schedule(static)
     for (int64_t t = 0; t < n; t++) { r[t] = b[t] - q[t]; z[t] = r[t] / diag[t]; d[t] = z[t]; }
     double rz = dot(r, z, n);
     double rnorm = sqrt(dot(r, r, n));
@@ -864,10 +865,12 @@ static int pcg(const or_params *p, apply_fn A, const void *actx, const double *d
     while (rnorm > tol * bnorm && k < p->maxit) {
         A(p, actx, d, q);
         double alpha = rz / dot(d, q, n);
+        #pragma omp parallel for schedule(static)
         for (int64_t t = 0; t < n; t++) { x[t] += alpha * d[t]; r[t] -= alpha * q[t]; z[t] = r[t] / diag[t]; }
         double rz_new = dot(r, z, n);
         double beta = rz_new / rz;
         rz = rz_new;
+        #pragma omp parallel for schedule(static)
         for (int64_t t = 0; t < n; t++) d[t] = z[t] + beta * d[t];
         rnorm = sqrt(dot(r, r, n));
         k++;

@@ -163,6 +163,12 @@ def workloads() -> dict:
         PFConfig(nx=128, ny=128, nz=32, electrodes=[Electrode(16, 32, 0, 128, 2.0), Electrode(96, 112, 0, 128, -2.0)],
                  tol_phi=1e-12, tol_u=1e-12),
         "domains", 50, seed=4, checkpoint_every=10, region=(48, 80, 48, 80, 24, 32))
+    # the micron-scale film in plain FP64 (the precision the paper's PETSc
+    # solves run in): the largest film that fits one GPU in FP64
+    w["micron_1024x1024x96"] = Workload(
+        "micron_1024x1024x96",
+        PFConfig(nx=1024, ny=1024, nz=96, electrodes=quarter_strips(1024, 1024), tol_phi=1e-9, tol_u=1e-9),
+        "domains", 100, seed=5, checkpoint_every=20, region=None)
     w["micron_1024x1024x96_fp32"] = Workload(
         "micron_1024x1024x96_fp32",
         PFConfig(nx=1024, ny=1024, nz=96, electrodes=quarter_strips(1024, 1024), tol_phi=1e-9, tol_u=1e-9,
