@@ -296,12 +296,27 @@ enum {
   PF_KC_COUNT
 };
 
-/* Per-kernel-class timing with HIP events recorded around every launch on
- * the context's stream (launches that return at entry after a solve has
- * converged are not counted).  Returns the accumulated milliseconds and
- * launch counts since the last call (arrays of PF_KC_COUNT, may be NULL),
- * resets them, and turns timing on (enable = 1) or off (0). */
-pf_status pf_timing(pf_ctx *ctx, int enable, double *ms, int64_t *launches);
+/* Modes of pf_timing. */
+enum {
+  PF_TIMING_OFF = 0,
+  PF_TIMING_EVENTS = 1, /* HIP events around every launch, byte and launch counts;
+                           the two solves of a step run one after the other */
+  PF_TIMING_BYTES = 2   /* launch and byte counts only (no events); the solves
+                           stay concurrent */
+};
+
+/* Per-kernel-class accounting of launches on the context's streams.
+ * Returns what was accumulated since the last call (arrays of PF_KC_COUNT,
+ * each may be NULL): milliseconds between the events around each launch
+ * (PF_TIMING_EVENTS only), launch counts, and algorithmic bytes: the HBM
+ * traffic each launch must move at least, its compulsory reads and writes
+ * with every stencil neighbour counted once (e.g. a FEM CG direction
+ * update + operator launch: r or z, the old direction and x read, the new
+ * direction and x written, 5 x 3 values per node above the clamped plane).
+ * Launches that return at entry after a solve has converged are not
+ * counted.  Resets the accumulators and sets the mode (PF_TIMING_*; other
+ * values: PF_EINVAL).  Synchronises. */
+pf_status pf_timing(pf_ctx *ctx, int mode, double *ms, int64_t *launches, double *bytes);
 
 /* Diagnostic (host only, no GPU needed): the constant 27-point operator
  * tables the kernels use for cfg, as doubles in this order:

@@ -42,9 +42,9 @@ class PFSteps(torch.autograd.Function):
                 # starts afresh at every checkpoint)
                 pf.restore_state(*cp)
             if s >= last_start:
-                Pn, Vn = pf.get_state()[:2]
+                Pn, Vn = pf.get_fields("P", "V")
                 pf.step(1)
-                last.append((Pn, Vn, pf.get_state()[3]))
+                last.append((Pn, Vn, pf.get_fields("u")[0]))
             else:
                 pf.step(1)
         PN = pf.get_state()[0]
@@ -66,26 +66,36 @@ class PFSteps(torch.autograd.Function):
         lamV = torch.zeros_like(lamP)
         dtheta = [0.0] * (fctx.n_volts + 1)
         nsteps, k = fctx.nsteps, fctx.k
+        if fctx.checkpoints is None:
+            raise RuntimeError("PFSteps: the backward frees its checkpoints and runs once per forward")
         nseg = len(fctx.checkpoints)
+        # At most one segment's states are held at a time: the newest
+        # segment's (kept from the forward) are dropped before the next
+        # segment is recomputed, and each checkpoint once its segment is.
         for seg in reversed(range(nseg)):
             if seg == nseg - 1:
-                states = fctx.last
+                states, fctx.last = fctx.last, None
             else:
                 P, V, phi, u, step = fctx.checkpoints[seg]
                 start = seg * k
                 stop = min(nsteps, start + k)
                 pf.restore_state(P, V, phi, u, step)
+                del P, V, phi, u
                 states = []
                 for _ in range(start, stop):
-                    Pn, Vn = pf.get_state()[:2]
+                    st = pf.get_fields("P", "V")
                     pf.step(1)
                     # the displacement step n solved for: the adjoint step's
                     # linearisation point needs no second solve
-                    un = pf.get_state()[3]
-                    states.append((Pn, Vn, un))
-            for Pn, Vn, un in reversed(states):
+                    states.append(st + pf.get_fields("u"))
+                    del st
+            fctx.checkpoints[seg] = None
+            while states:
+                Pn, Vn, un = states.pop()
                 pf.adjoint_step(Pn, Vn, lamP, lamV, dtheta, un)
-        fctx.last = None
+                del Pn, Vn, un
+            del states
+        fctx.checkpoints = None
         pf.adjoint_initial_rate(P0, lamP, lamV, dtheta)
         vdev, vdt, adev, adt = fctx.theta_dev
         g_volts = torch.tensor(dtheta[:fctx.n_volts], dtype=vdt, device=vdev)

@@ -41,7 +41,7 @@ hipError_t launch_mg_scale(const Dims& d, int nc, const double* dinv, double ome
 template <typename T>
 hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap,
                               const int* zfine, const T* rf, T* bc, const CgScalars* sc, int zoff, int fnz,
-                              int ctop_fixed, hipStream_t s);
+                              int ftop_fixed, int ctop_fixed, hipStream_t s);
 template <typename T>
 hipError_t launch_mg_prolong(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap, const T* xc,
                              T* xf, const CgScalars* sc, int zoff, int ftop_fixed, int ctop_fixed, const T* bf,
@@ -572,15 +572,22 @@ struct pf_ctx {
   int64_t step;
   int cur;                  // which P/V buffer is current
   int pred[pf::kPredCount];
-  // per-kernel-class event timing
-  bool timing;
+  // per-kernel-class accounting: PF_TIMING_EVENTS records events around
+  // every launch (solves sequential), PF_TIMING_BYTES only counts launches
+  // and their algorithmic bytes (solves stay concurrent)
+  int timing;
   std::vector<hipEvent_t> events;
   struct TimedLaunch {
     int cls, slot, solver, k;
+    double bytes;
   };
-  std::vector<TimedLaunch> pending;
+  // launches awaiting their solve's iteration count: [0] the caller's
+  // thread, [1] the worker's
+  std::vector<TimedLaunch> pending[2];
+  std::mutex kc_mu;
   double kc_ms[PF_KC_COUNT];
   int64_t kc_n[PF_KC_COUNT];
+  double kc_bytes[PF_KC_COUNT];
 };
 
 namespace pf {
@@ -778,10 +785,17 @@ const uint8_t* emask(pf_ctx* c) { return c->cfg.top_bc == PF_TOP_OPEN ? at<uint8
 // Event timing of launches
 // ---------------------------------------------------------------------------
 
+// bytes: the launch's algorithmic HBM traffic (compulsory reads and writes,
+// stencil neighbours counted once), accumulated per class.
 template <typename F>
-hipError_t timed(pf_ctx* c, int cls, int solver, int k, F&& launch) {
-  if (!c->timing) return launch();
-  const int slot = (int)c->pending.size();
+hipError_t timed(pf_ctx* c, int cls, int solver, int k, double bytes, F&& launch) {
+  if (c->timing == PF_TIMING_OFF) return launch();
+  if (c->timing == PF_TIMING_BYTES) {
+    hipError_t err = launch();
+    if (err == hipSuccess) c->pending[tl_stream ? 1 : 0].push_back({cls, -1, solver, k, bytes});
+    return err;
+  }
+  const int slot = (int)c->pending[0].size();
   while ((int)c->events.size() < 2 * (slot + 1)) {
     hipEvent_t e;
     hipError_t err = hipEventCreate(&e);
@@ -794,43 +808,45 @@ hipError_t timed(pf_ctx* c, int cls, int solver, int k, F&& launch) {
   if (err != hipSuccess) return err;
   err = hipEventRecord(c->events[2 * slot + 1], strm(c));
   if (err != hipSuccess) return err;
-  c->pending.push_back({cls, slot, solver, k});
+  c->pending[0].push_back({cls, slot, solver, k, bytes});
   return hipSuccess;
 }
 
 // After a stream synchronisation: accumulates the pending launches.  CG
 // iterations at or beyond `iters` of `solver` returned at entry and are
 // dropped.
-void collect_timing(pf_ctx* c, int solver, int iters) {
-  for (const auto& t : c->pending) {
+void collect_timing(pf_ctx* c, int solver, int iters, int list) {
+  std::lock_guard<std::mutex> g(c->kc_mu);
+  for (const auto& t : c->pending[list]) {
     if (t.solver >= 0 && t.solver == solver && t.k >= iters) continue;
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c->events[2 * t.slot], c->events[2 * t.slot + 1]) == hipSuccess) {
-      c->kc_ms[t.cls] += ms;
-      c->kc_n[t.cls] += 1;
-    }
+    if (t.slot >= 0 && hipEventElapsedTime(&ms, c->events[2 * t.slot], c->events[2 * t.slot + 1]) != hipSuccess)
+      continue;
+    c->kc_ms[t.cls] += ms;
+    c->kc_n[t.cls] += 1;
+    c->kc_bytes[t.cls] += t.bytes;
   }
-  c->pending.clear();
+  c->pending[list].clear();
 }
 
 pf_status read_scalars(pf_ctx* c, int which, CgScalars* out) {
   PF_HIP(c, hipMemcpyAsync(c->host_sc + which, dev_sc(c, which), sizeof(CgScalars), hipMemcpyDeviceToHost, strm(c)));
   PF_HIP(c, hipStreamSynchronize(strm(c)));
   *out = c->host_sc[which];
-  if (c->timing) collect_timing(c, which, out->iter);
+  if (c->timing) collect_timing(c, which, out->iter, tl_stream ? 1 : 0);
   return PF_OK;
 }
 
 pf_status sync(pf_ctx* c) {
   PF_HIP(c, hipStreamSynchronize(strm(c)));
-  if (c->timing) collect_timing(c, -1, 0);
+  if (c->timing) collect_timing(c, -1, 0, tl_stream ? 1 : 0);
   return PF_OK;
 }
 
 hipError_t reduce(pf_ctx* c, const double* part, int nb, int nv, int which, int mode, double tol, double tol2,
                   double* out, int solver = -1, int k = -1) {
   const int maxit = c->cfg.maxit;
-  return timed(c, PF_KC_REDUCE, solver, k, [&] {
+  return timed(c, PF_KC_REDUCE, solver, k, (double)nb * nv * 8 + sizeof(CgScalars), [&] {
     return launch_cg_reduce(part, nb, nv, dev_sc(c, which), mode, tol, maxit, strm(c), tol2, out);
   });
 }
@@ -876,7 +892,7 @@ pf_status run_cg(pf_ctx* c, int which, int predicted, T* x, T* const pbuf[2], in
   if (h.done != kNonFinite) {
     if (defer) *defer = pbuf[h.iter & 1];
     else
-      PF_HIP(c, timed(c, PF_KC_FINISH, -1, -1,
+      PF_HIP(c, timed(c, PF_KC_FINISH, -1, -1, 3.0 * n * sizeof(T),
                       [&] { return launch_cg_finish<T>(x, pbuf[h.iter & 1], n, dev_sc(c, which), strm(c)); }));
   }
   *hout = h;
@@ -926,7 +942,9 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   auto Dv = [&](int l) { return at<double>(c, L.dinv[l]); };
   auto Zm = [&](int l) { return at<MgZ>(c, L.zmap[l]); };
   auto Zf = [&](int l) { return at<int>(c, L.zfine[l]); };
-  auto run = [&](auto&& fn) { return timed(c, PF_KC_MG, f, k, fn); };
+  auto run = [&](double bytes, auto&& fn) { return timed(c, PF_KC_MG, f, k, bytes, fn); };
+  // algorithmic bytes: nc values of T per node of level l, times `reps`
+  auto lb = [&](int l, double reps) { return reps * nc * (double)D[l].N * sizeof(T); };
   // the solver grid: the Poisson levels count a fixed bottom plane below it
   const int zoff0 = f == 0 ? 1 : 0;
   // the correction of level 1 as the kMgCorrect kernels read it
@@ -950,24 +968,30 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   const double om0 = h.levels[0].omega;
   T* v0 = V(L.v0);
   T* t0 = V(L.t0);
-  auto run0 = [&](auto&& fn) { return timed(c, f == 0 ? PF_KC_MG_PHI0 : PF_KC_MG_U0, f, k, fn); };
-  hipError_t e = run0([&] { return fine(kMgFirst, om0, nullptr, t0, nullptr); });
+  auto run0 = [&](double bytes, auto&& fn) { return timed(c, f == 0 ? PF_KC_MG_PHI0 : PF_KC_MG_U0, f, k, bytes, fn); };
+  // the solver grid's unknowns: the FEM's clamped plane is not one
+  const double n0 = f == 0 ? (double)c->dims_p.N : (double)(c->dims.N - c->dims.plane);
+  const double v0b = nc * n0 * sizeof(T);
+  // first sweep's residual: b read, t written
+  hipError_t e = run0(2 * v0b, [&] { return fine(kMgFirst, om0, nullptr, t0, nullptr); });
   if (e == hipSuccess)
-    e = run([&] {
+    e = run(lb(0, 1) + lb(1, 1), [&] {
+      // the solver grid stores no fixed planes (the Poisson ghost planes
+      // lie outside its storage)
       return launch_mg_restrict<T>(d0, D[1], nc, h.levels[1].cx, h.levels[1].cy, Zm(1), Zf(1), t0, V(L.b[1]), sc,
-                                   zoff0, h.levels[0].nz, top, st);
+                                   zoff0, h.levels[0].nz, 0, top, st);
     });
   for (int l = 1; l < nl - 1 && e == hipSuccess; l++) {
     const Dims& d = D[l];
     // residual of the first sweep: b - (A omega D^-1) b with the folded stencils
     const double* tabw = at<double>(c, L.tabw[l]);
-    e = run([&] {
+    e = run(lb(l, 2), [&] {
       return launch_mg_level<T>(d, nc, tabw, Dv(l), kMgResidual, 0.0, V(L.b[l]), V(L.b[l]), V(L.t[l]), sc, top, st);
     });
     if (e == hipSuccess)
-      e = run([&] {
+      e = run(lb(l, 1) + lb(l + 1, 1), [&] {
         return launch_mg_restrict<T>(d, D[l + 1], nc, h.levels[l + 1].cx, h.levels[l + 1].cy, Zm(l + 1), Zf(l + 1),
-                                     V(L.t[l]), V(L.b[l + 1]), sc, 0, d.nz, top, st);
+                                     V(L.t[l]), V(L.b[l + 1]), sc, 0, d.nz, top, top, st);
       });
   }
   // coarsest level
@@ -975,7 +999,7 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   if (e == hipSuccess) {
     const Dims& d = D[lc];
     if (h.dense_n > 0) {
-      e = run([&] {
+      e = run(8.0 * h.dense_n * h.dense_n + lb(lc, 2), [&] {
         return launch_mg_dense<T>(d, nc, h.dense_n, at<double>(c, L.dense), V(L.b[lc]), V(L.o[lc]), sc, st);
       });
     } else {
@@ -983,10 +1007,10 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
       const double* tab = at<double>(c, L.tab[lc]);
       const int ns = std::max(1, h.coarse_sweeps);
       T* cur = V(ns == 1 ? L.o[lc] : L.v[lc]);
-      e = run([&] { return launch_mg_scale<T>(d, nc, Dv(lc), h.levels[lc].omega, V(L.b[lc]), cur, sc, st); });
+      e = run(lb(lc, 2), [&] { return launch_mg_scale<T>(d, nc, Dv(lc), h.levels[lc].omega, V(L.b[lc]), cur, sc, st); });
       for (int t = 1; t < ns && e == hipSuccess; t++) {
         T* nxt = t == ns - 1 ? V(L.o[lc]) : (cur == V(L.v[lc]) ? V(L.t[lc]) : V(L.v[lc]));
-        e = run([&] {
+        e = run(lb(lc, 3), [&] {
           return launch_mg_level<T>(d, nc, tab, Dv(lc), kMgSweep, h.levels[lc].omega, cur, V(L.b[lc]), nxt, sc, top,
                                     st);
         });
@@ -997,26 +1021,27 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   for (int l = nl - 2; l >= 1 && e == hipSuccess; l--) {
     const Dims& d = D[l];
     const double* tab = at<double>(c, L.tab[l]);
-    e = run([&] {
+    e = run(lb(l, 2) + lb(l + 1, 1), [&] {
       return launch_mg_prolong<T>(d, D[l + 1], nc, h.levels[l + 1].cx, h.levels[l + 1].cy, Zm(l + 1), V(L.o[l + 1]),
                                   V(L.v[l]), sc, 0, top, top, V(L.b[l]), Dv(l), h.levels[l].omega, st);
     });
     if (e == hipSuccess)
-      e = run([&] {
+      e = run(lb(l, 3), [&] {
         return launch_mg_level<T>(d, nc, tab, Dv(l), kMgSweep, h.levels[l].omega, V(L.v[l]), V(L.b[l]), V(L.o[l]),
                                   sc, top, st);
       });
   }
   if (fused) {
-    if (e == hipSuccess) e = run0([&] { return fine(kMgCorrect, om0, nullptr, z0, part); });
+    // b and the level-1 correction read, z written
+    if (e == hipSuccess) e = run0(2 * v0b + lb(1, 1), [&] { return fine(kMgCorrect, om0, nullptr, z0, part); });
     return e;
   }
   if (e == hipSuccess)
-    e = run([&] {
+    e = run(lb(0, 2) + lb(1, 1), [&] {
       return launch_mg_prolong<T>(d0, D[1], nc, h.levels[1].cx, h.levels[1].cy, Zm(1), V(L.o[1]), v0, sc, zoff0, 0,
                                   top, r0, Dv(0), om0, st);
     });
-  if (e == hipSuccess) e = run0([&] { return fine(kMgSweep, om0, v0, z0, part); });
+  if (e == hipSuccess) e = run0(3 * v0b, [&] { return fine(kMgSweep, om0, v0, z0, part); });
   return e;
 }
 
@@ -1041,13 +1066,15 @@ std::function<hipError_t(int)> poisson_iteration(pf_ctx* c, const Coefs<T>& cf, 
     double* part = dev_partials(c, 0);
     const bool mg = mg_on(c, 0);
     T* z = mg ? at<T>(c, c->lay.mg[0].z) : nullptr;
-    hipError_t e = timed(c, PF_KC_POISSON_A, 0, k, [&] {
+    const double vb = (double)d.N * sizeof(T);
+    // A: r or z, p_old, x read; p_new, x written.  B: p, r read; r written.
+    hipError_t e = timed(c, PF_KC_POISSON_A, 0, k, 5 * vb, [&] {
       return launch_poisson_cg_a<T>(d, c->tm_p, cf, mg ? z : r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, mg ? 1 : 0,
                                     strm(c));
     });
     if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 1, 0, kRedAlpha, tol, 0, nullptr, 0, k);
     if (e == hipSuccess)
-      e = timed(c, PF_KC_POISSON_B, 0, k,
+      e = timed(c, PF_KC_POISSON_B, 0, k, 3 * vb,
                 [&] { return launch_poisson_cg_b<T>(d, c->tm_p, cf, pb[(k + 1) & 1], r, em, sc, part, strm(c)); });
     // multigrid: z = M r replaces the Jacobi-weighted r.z of kernel B
     // (with multigrid the convergence test comes first, so the last iteration runs no V-cycle)
@@ -1067,13 +1094,15 @@ std::function<hipError_t(int)> fem_iteration(pf_ctx* c, T* r, T* const pb[2], T*
     double* part = dev_partials(c, 1);
     const bool mg = mg_on(c, 1);
     T* z = mg ? at<T>(c, c->lay.mg[1].z) : nullptr;
-    hipError_t e = timed(c, PF_KC_FEM_A, 1, k, [&] {
+    // the clamped plane holds no unknowns
+    const double vb = 3.0 * (d.N - d.plane) * sizeof(T);
+    hipError_t e = timed(c, PF_KC_FEM_A, 1, k, 5 * vb, [&] {
       return launch_fem_cg_a<T>(d, c->tm_f, tb, c->gen, mg ? z : r, pb[k & 1], pb[(k + 1) & 1], x, sc, part,
                                 mg ? 1 : 0, strm(c));
     });
     if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 1, 1, kRedAlpha, tol, 0, nullptr, 1, k);
     if (e == hipSuccess)
-      e = timed(c, PF_KC_FEM_B, 1, k,
+      e = timed(c, PF_KC_FEM_B, 1, k, 3 * vb,
                 [&] {
                   return launch_fem_cg_b<T>(d, c->tm_f, tb, c->gen, pb[(k + 1) & 1], r, sc, part, strm(c));
                 });
@@ -1098,7 +1127,9 @@ pf_status solve_poisson64(pf_ctx* c, int pred, const S* P, const S* V, double cd
   double* r = at<double>(c, c->lay.pr);
   double* const pb[2] = {at<double>(c, c->lay.pp[0]), at<double>(c, c->lay.pp[1])};
   if (!warm) PF_HIP(c, launch_fill<double>(x, d.N, 0.0, strm(c)));
-  PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
+  // P (and V) read when with_P; x read; r, p written
+  const double sb = (with_P ? 3.0 * c->dims.N * sizeof(S) * (V ? 2 : 1) : 0.0) + 3.0 * d.N * 8;
+  PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, sb, [&] {
     return launch_poisson_setup<double, S, double>(d, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, emask(c),
                                                    x, r, pb[0], nullptr, part, strm(c));
   }));
@@ -1122,7 +1153,10 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
   double* r = at<double>(c, c->lay.fr);
   double* const pb[2] = {at<double>(c, c->lay.fp[0]), at<double>(c, c->lay.fp[1])};
   if (!warm) PF_HIP(c, launch_fill<double>(x, 3 * d.N, 0.0, strm(c)));
-  PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
+  // P (and V), or W, read; x read; r, p written
+  const double n3 = 3.0 * d.N;
+  const double sb = (W ? n3 * 8 : n3 * sizeof(S) * (V ? 2 : 1)) + 3 * n3 * 8;
+  PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, sb, [&] {
     return launch_fem_setup<double, S, double>(d, c->tm_f, cf, tb, c->gen, P, V, cdt, W, x, r, pb[0], pb[1], nullptr,
                                                nullptr, part, strm(c));
   }));
@@ -1168,18 +1202,23 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
   double* fbody = at<double>(c, c->lay.fbody);
   bool synced = false;  // x32 == (float) x64, as the last refinement update left it
   for (;;) {
+    // per unknown: the first FEM sweep reads P, V (FP32) and x64 and writes
+    // r, p, d (FP32) and the FP64 body force; later sweeps read the body
+    // force and x64 instead of P, V; the Poisson setup reads P, V of the
+    // film and x64 and writes r, p, d
+    const double n3 = 3.0 * c->dims.N;
     if (fem && res->outer == 0) {
-      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
+      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, n3 * (4 + 4 + 8 + 3 * 4 + 8), [&] {
         return launch_fem_setup<double, float, float>(d, c->tm_f, cf64, tb, c->gen, P, V, cdt, nullptr, x64, r, pb[0],
                                                       pb[1], dz, fbody, part, strm(c));
       }));
     } else if (fem) {
-      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, [&] {
+      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, n3 * (8 + 8 + 3 * 4), [&] {
         return launch_fem_resid<double, float>(d, c->tm_f, tb, c->gen, fbody, x64, r, pb[0], pb[1], dz, part,
                                                strm(c));
       }));
     } else {
-      PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, [&] {
+      PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, n3 * (4 + 4) + (double)d.N * (8 + 3 * 4), [&] {
         return launch_poisson_setup<double, float, float>(d, cf64, P, V, cdt, 1, 1, at<double>(c, c->lay.ghost64),
                                                           c->cfg.phi_bottom, emask(c), x64, r, pb[0], dz, part,
                                                           strm(c));
@@ -1209,11 +1248,13 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
         synced = false;
       }
       if (!synced)
-        PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_convert<double, float>(x64, x32, n, strm(c)); }));
+        PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, 12.0 * n,
+                        [&] { return launch_convert<double, float>(x64, x32, n, strm(c)); }));
       return PF_OK;
     }
     if (h.iter > 0) c->pred[pred] = h.iter;
-    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+    // x64 read and written, x32 written, d (and the last direction) read
+    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, (double)n * (16 + 4 + 4 + (pfin ? 4 : 0)), [&] {
       return launch_refine_update(x64, x32, dz, pfin, pfin ? dev_sc(c, which) : nullptr, n, strm(c));
     }));
     synced = true;
@@ -1292,14 +1333,18 @@ bool extrapolate_plan(pf_ctx* c, ExtrapRing ring[2]) {
 // Replaces x (n values, the previous solution) by its extrapolation and
 // stores the previous solution in the ring, on the calling thread's stream.
 pf_status extrapolate_into(pf_ctx* c, double* x, int64_t n, const ExtrapRing& ring) {
-  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_extrapolate(x, ring, n, strm(c)); }));
+  // x and m history slots read; x and the ring slot written
+  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, 8.0 * n * (ring.m + 3),
+                  [&] { return launch_extrapolate(x, ring, n, strm(c)); }));
   return PF_OK;
 }
 
 pf_status extrapolate_field(pf_ctx* c, int f, const ExtrapRing& ring) {
   const int64_t n = f == 0 ? c->dims_p.N : 3 * c->dims.N;
   double* x = at<double>(c, f == 0 ? c->lay.phi : c->lay.u);
-  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] { return launch_extrapolate(x, ring, n, strm(c)); }));
+  // x and m history slots read; x and the ring slot written
+  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, 8.0 * n * (ring.m + 3),
+                  [&] { return launch_extrapolate(x, ring, n, strm(c)); }));
   return PF_OK;
 }
 
@@ -1330,7 +1375,7 @@ pf_status solve_nonlocal(pf_ctx* c, const void* P, const void* V, double cdt, bo
                                u, c->cfg.tol_u, warm, r);
   };
   const bool elec = c->cfg.terms & PF_TERM_ELEC, elas = c->cfg.terms & PF_TERM_ELAS;
-  if (elec && elas && c->worker && !c->timing) {
+  if (elec && elas && c->worker && c->timing != PF_TIMING_EVENTS) {
     PF_HIP(c, hipEventRecord(c->ev_fork, strm(c)));
     SolveResult rf{};
     pf_status sf = PF_OK;
@@ -1386,11 +1431,16 @@ pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt
                              void* F, const void* phi_override = nullptr, const void* u_override = nullptr) {
   const FemTables* tb = at<FemTables>(c, c->lay.tables);
   const NoiseSpec ns = noise_spec(c, c->step, mode == kPcStep || mode == kEulerStep);
+  // P (and V), phi, u read; the new P and V (predictor-corrector step) or
+  // one of V, P, F written
+  const size_t es = fp32(c) ? 4 : 8;
+  const double n3 = 3.0 * c->dims.N;
+  const double fb = es * (n3 * (V ? 2 : 1) + (double)c->dims_p.N + n3 + n3 * (mode == kPcStep ? 2 : 1));
   if (fp32(c)) {
     const Coefs<float> cf = make_coefs<float>(c);
     const float* phi = phi_override ? static_cast<const float*>(phi_override) : at<float>(c, c->lay.phi32);
     const float* u = u_override ? static_cast<const float*>(u_override) : at<float>(c, c->lay.u32);
-    PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
+    PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, fb, [&] {
       return launch_force<float>(c->dims, c->tm_f, cf, tb, static_cast<const float*>(P), static_cast<const float*>(V),
                                  (float)cdt, phi, at<float>(c, c->lay.ghost32), u, mode, ns, static_cast<float*>(Pn),
                                  static_cast<float*>(Vn), static_cast<float*>(F), strm(c));
@@ -1399,7 +1449,7 @@ pf_status launch_state_force(pf_ctx* c, const void* P, const void* V, double cdt
     const Coefs<double> cf = make_coefs<double>(c);
     const double* phi = phi_override ? static_cast<const double*>(phi_override) : at<double>(c, c->lay.phi);
     const double* u = u_override ? static_cast<const double*>(u_override) : at<double>(c, c->lay.u);
-    PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, [&] {
+    PF_HIP(c, timed(c, PF_KC_FORCE, -1, -1, fb, [&] {
       return launch_force<double>(c->dims, c->tm_f, cf, tb, static_cast<const double*>(P), static_cast<const double*>(V), cdt,
                                   phi, at<double>(c, c->lay.ghost64), u, mode, ns, static_cast<double*>(Pn),
                                   static_cast<double*>(Vn), static_cast<double*>(F), strm(c));
@@ -1579,7 +1629,7 @@ pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt, const double* ulin_
   };
   const bool elec = c->cfg.terms & PF_TERM_ELEC, elas = c->cfg.terms & PF_TERM_ELAS;
   pf_status out = PF_OK;
-  if (elec && elas && c->worker && !c->timing) {
+  if (elec && elas && c->worker && c->timing != PF_TIMING_EVENTS) {
     // concurrent, as the forward solves
     PF_HIP(c, hipEventRecord(c->ev_fork, strm(c)));
     pf_status sf = PF_OK;
@@ -1607,7 +1657,9 @@ pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt, const double* ulin_
       out = worst(out, s);
     }
   }
-  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+  // P (and V), w, the linearisation point's u, psi and du read; H w written
+  const double hb = 3.0 * d.N * (sizeof(S) * (V ? 2 : 1) + 4 * 8) + 8.0 * c->dims_p.N;
+  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, hb, [&] {
     return launch_hvp<S>(d, cf, tb, P, V, cdt, w, ulin_in ? ulin_in : ulin, psi, du, scratch<double>(c, kScrHw),
                          strm(c));
   }));
@@ -1628,14 +1680,14 @@ pf_status theta_accumulate(pf_ctx* c, const S* P, const S* V, double cdt, double
     for (int e = 0; e < ne; e++) {
       const pf_electrode& el = c->electrodes[e];
       const double* phe = at<double>(c, c->lay.basis) + (size_t)e * c->dims_p.N;
-      PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+      PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, 3.0 * d.N * 8 + 8.0 * c->dims_p.N, [&] {
         return launch_theta_dot<S>(d, cf, w, phe, el.x0, el.x1, el.y0, el.y1, P, V, cdt, part, strm(c));
       }));
       PF_HIP(c, reduce(c, part, c->nblocks, 1, 2, kRedSum, 0, 0, dev_result(c) + e));
     }
   }
   if (c->cfg.terms & PF_TERM_LANDAU) {
-    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, 3.0 * d.N * (8 + sizeof(S) * (V ? 2 : 1)), [&] {
       return launch_theta_dot<S>(d, cf, w, nullptr, 0, 0, 0, 0, P, V, cdt, part, strm(c));
     }));
     PF_HIP(c, reduce(c, part, c->nblocks, 1, 2, kRedSum, 0, 0, dev_result(c) + ne));
@@ -1709,13 +1761,13 @@ pf_status energy_t(pf_ctx* c, const S* P, double out[5]) {
     st = worst(st, s);
   }
   double* part = dev_partials(c, 2);
-  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+  PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, 3.0 * d.N * (sizeof(S) + 8) + 16.0 * c->dims_p.N, [&] {
     return launch_energy<S>(d, cf, at<FemTables>(c, c->lay.tables), P, phi, at<double>(c, c->lay.phi_bc),
                             at<double>(c, c->lay.ghost64), u, part, strm(c));
   }));
   PF_HIP(c, reduce(c, part, c->nblocks, 4, 2, kRedSum, 0, 0, dev_result(c)));
   if (c->cfg.terms & PF_TERM_ELEC) {
-    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, [&] {
+    PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, 3.0 * d.N * sizeof(S) + 16.0 * c->dims_p.N, [&] {
       return launch_elec_quad<S>(c->dims_p, cf, P, phi, at<double>(c, c->lay.phi_bc), emask(c), part, strm(c));
     }));
     PF_HIP(c, reduce(c, part, c->nblocks_p, 1, 2, kRedSum, 0, 0, dev_result(c) + 4));
@@ -1827,9 +1879,10 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->step = 0;
   c->cur = 0;
   for (int t = 0; t < kPredCount; t++) c->pred[t] = 16;
-  c->timing = false;
+  c->timing = PF_TIMING_OFF;
   std::memset(c->kc_ms, 0, sizeof(c->kc_ms));
   std::memset(c->kc_n, 0, sizeof(c->kc_n));
+  std::memset(c->kc_bytes, 0, sizeof(c->kc_bytes));
   c->host_sc = nullptr;
   c->host_res = nullptr;
   if (hipHostMalloc(reinterpret_cast<void**>(&c->host_sc), sizeof(CgScalars) * kNumScalars, hipHostMallocDefault) !=
@@ -2046,9 +2099,11 @@ pf_status pf_force(pf_ctx* c, const void* P, const void* phi, const void* u, voi
   if ((c->cfg.terms & PF_TERM_ELAS) && !u) return fail(c, PF_EINVAL, "pf_force: u needed");
   const int64_t N = c->dims.N;
   if (fp32(c)) {
+    // rounded copies in two scratch slots (free outside pf_energy): phi
+    // spans the potential grid, air planes of the open top included
     float* phi32 = scratch<float>(c, kScrTmp);
-    float* u32 = phi32 + N;
-    if (phi) PF_HIP(c, launch_convert<double, float>(static_cast<const double*>(phi), phi32, N, strm(c)));
+    float* u32 = scratch<float>(c, kScrUE);
+    if (phi) PF_HIP(c, launch_convert<double, float>(static_cast<const double*>(phi), phi32, c->dims_p.N, strm(c)));
     if (u) PF_HIP(c, launch_convert<double, float>(static_cast<const double*>(u), u32, 3 * N, strm(c)));
     return launch_state_force(c, P, nullptr, 0.0, kForceOut, nullptr, nullptr, F, phi32, u32);
   }
@@ -2119,16 +2174,26 @@ pf_status pf_adjoint_initial_rate(pf_ctx* c, const void* P0, void* lamP, void* l
   return s;
 }
 
-pf_status pf_timing(pf_ctx* c, int enable, double* ms, int64_t* launches) {
+pf_status pf_timing(pf_ctx* c, int mode, double* ms, int64_t* launches, double* bytes) {
   if (!c) return PF_EINVAL;
+  if (mode != PF_TIMING_OFF && mode != PF_TIMING_EVENTS && mode != PF_TIMING_BYTES)
+    return fail(c, PF_EINVAL, "pf_timing: unknown mode %d", mode);
   PF_TRY(sync(c));
+  // every solve has read back its iteration count by now: what is still
+  // pending (the worker's last launches) counts in full
+  if (c->timing) {
+    collect_timing(c, -1, 0, 0);
+    collect_timing(c, -1, 0, 1);
+  }
   for (int t = 0; t < PF_KC_COUNT; t++) {
     if (ms) ms[t] = c->kc_ms[t];
     if (launches) launches[t] = c->kc_n[t];
+    if (bytes) bytes[t] = c->kc_bytes[t];
     c->kc_ms[t] = 0;
     c->kc_n[t] = 0;
+    c->kc_bytes[t] = 0;
   }
-  c->timing = enable != 0;
+  c->timing = mode;
   return PF_OK;
 }
 

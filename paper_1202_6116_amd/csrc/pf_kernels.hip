@@ -1857,13 +1857,16 @@ __device__ __forceinline__ int mg_parents(int i, int nc, int coarsened, int idx[
 // Restriction (the transpose of the prolongation): coarse b = P^T r.  One
 // thread per coarse node.  The z maps count the finer level's planes from its
 // plane 0; its stored plane is that index minus zoff (the Poisson grid
-// stores no ghost planes), and planes outside storage carry zero.
+// stores no ghost planes), and planes outside storage carry zero.  Fixed
+// planes of the finer level (its plane 0 and, with ftop_fixed, its top
+// plane) hold no unknowns and are never read: no kernel writes them, so
+// they may hold anything (other precisions' data included).
 template <typename T, int NC>
 __global__ __launch_bounds__(kThreads) void mg_restrict_kernel(Dims df, Dims dc, int cx, int cy,
                                                                const MgZ* __restrict__ zmap,
                                                                const int* __restrict__ zfine, const T* __restrict__ rf,
                                                                T* __restrict__ bc, const CgScalars* sc, int zoff,
-                                                               int fnz, int ctop_fixed) {
+                                                               int fnz, int ftop_fixed, int ctop_fixed) {
   if (sc->done) return;
   const int I = blockIdx.x * kBX + threadIdx.x, J = blockIdx.y * kBY + threadIdx.y, K = blockIdx.z;
   if (I >= dc.nx || J >= dc.ny || K == 0 || (ctop_fixed && K == dc.nz - 1)) return;
@@ -1873,7 +1876,7 @@ __global__ __launch_bounds__(kThreads) void mg_restrict_kernel(Dims df, Dims dc,
   const int kf0 = zfine[K];
   for (int kf = kf0 - 1; kf <= kf0 + 1; kf++) {
     const int ks = kf - zoff;
-    if (kf < 1 || kf >= fnz || ks < 0 || ks >= df.nz) continue;
+    if (kf < 1 || kf >= fnz - (ftop_fixed ? 1 : 0) || ks < 0 || ks >= df.nz) continue;
     const MgZ z = zmap[kf];
     double wz = 0.0;
     if (z.lo == K) wz += z.wlo;
@@ -1954,7 +1957,7 @@ __global__ __launch_bounds__(kThreads) void mg_restrict2_kernel(Dims df, Dims dc
                                                                 const int* __restrict__ zfine,
                                                                 const T* __restrict__ rf, T* __restrict__ bc,
                                                                 const CgScalars* sc, int zoff, int fnz,
-                                                                int ctop_fixed) {
+                                                                int ftop_fixed, int ctop_fixed) {
   if (sc->done) return;
   const int I = blockIdx.x * kBX + threadIdx.x, J = blockIdx.y * kBY + threadIdx.y;
   if (I >= dc.nx || J >= dc.ny) return;
@@ -1974,7 +1977,8 @@ __global__ __launch_bounds__(kThreads) void mg_restrict2_kernel(Dims df, Dims dc
     fy[t] = wrap(2 * J + t - 1, df.ny);
   }
   const double w1[3] = {0.5, 1.0, 0.5};
-  const int kf0 = max(zfine[Ka] - 1, 1), kf1 = min(zfine[Kb - 1] + 1, fnz - 1);
+  // the finer level's fixed planes are not read (see mg_restrict_kernel)
+  const int kf0 = max(zfine[Ka] - 1, 1), kf1 = min(zfine[Kb - 1] + 1, fnz - 1 - (ftop_fixed ? 1 : 0));
   for (int kf = kf0; kf <= kf1; kf++) {
     const int ks = kf - zoff;
     if (ks < 0 || ks >= df.nz) continue;
@@ -3012,13 +3016,14 @@ hipError_t launch_mg_scale(const Dims& d, int nc, const double* dinv, double ome
 template <typename T>
 hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int nc, int cx, int cy, const MgZ* zmap,
                               const int* zfine, const T* rf, T* bc, const CgScalars* sc, int zoff, int fnz,
-                              int ctop_fixed, hipStream_t s) {
+                              int ftop_fixed, int ctop_fixed, hipStream_t s) {
   if (cx && cy && df.nx == 2 * dc.nx && df.ny == 2 * dc.ny) {
     const bool wide = dc.plane >= 16384;
     const int kc = wide ? 4 : 1;
     const dim3 g((dc.nx + kBX - 1) / kBX, (dc.ny + kBY - 1) / kBY, (dc.nz + kc - 1) / kc);
 #define PF_RESTRICT2(NC, KC) \
-  mg_restrict2_kernel<T, NC, KC><<<g, node_block(), 0, s>>>(df, dc, zmap, zfine, rf, bc, sc, zoff, fnz, ctop_fixed)
+  mg_restrict2_kernel<T, NC, KC><<<g, node_block(), 0, s>>>(df, dc, zmap, zfine, rf, bc, sc, zoff, fnz, ftop_fixed, \
+                                                            ctop_fixed)
     if (nc == 3) {
       if (wide) PF_RESTRICT2(3, 4);
       else PF_RESTRICT2(3, 1);
@@ -3031,10 +3036,10 @@ hipError_t launch_mg_restrict(const Dims& df, const Dims& dc, int nc, int cx, in
   }
   if (nc == 3)
     mg_restrict_kernel<T, 3><<<node_grid(dc), node_block(), 0, s>>>(df, dc, cx, cy, zmap, zfine, rf, bc, sc, zoff,
-                                                                     fnz, ctop_fixed);
+                                                                     fnz, ftop_fixed, ctop_fixed);
   else
     mg_restrict_kernel<T, 1><<<node_grid(dc), node_block(), 0, s>>>(df, dc, cx, cy, zmap, zfine, rf, bc, sc, zoff,
-                                                                     fnz, ctop_fixed);
+                                                                     fnz, ftop_fixed, ctop_fixed);
   return hipGetLastError();
 }
 
@@ -3188,7 +3193,7 @@ PF_INSTANTIATE(float)
   template hipError_t launch_mg_scale<T>(const Dims&, int, const double*, double, const T*, T*, const CgScalars*, \
                                          hipStream_t);                                                            \
   template hipError_t launch_mg_restrict<T>(const Dims&, const Dims&, int, int, int, const MgZ*, const int*,      \
-                                            const T*, T*, const CgScalars*, int, int, int, hipStream_t);          \
+                                            const T*, T*, const CgScalars*, int, int, int, int, hipStream_t);     \
   template hipError_t launch_mg_prolong<T>(const Dims&, const Dims&, int, int, int, const MgZ*, const T*, T*,     \
                                            const CgScalars*, int, int, int, const T*, const double*, double,      \
                                            hipStream_t);                                                          \

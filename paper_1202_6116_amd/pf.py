@@ -23,6 +23,7 @@ PF_INT_PC, PF_INT_EULER = 0, 1
 PF_FP64, PF_FP32_REFINE = 0, 1
 PF_TOP_METAL, PF_TOP_OPEN = 0, 1
 PF_PRECOND_JACOBI, PF_PRECOND_MG = 0, 1
+PF_TIMING_OFF, PF_TIMING_EVENTS, PF_TIMING_BYTES = 0, 1, 2
 KERNEL_CLASSES = ["poisson_setup", "poisson_a", "poisson_b", "fem_setup", "fem_a", "fem_b", "force", "finish",
                   "reduce", "other", "mg", "mg_u0", "mg_phi0"]
 
@@ -119,7 +120,7 @@ def lib() -> ctypes.CDLL:
             "pf_adjoint_step": (ctypes.c_int, [vp, vp, vp, vp, vp, dp]),
             "pf_adjoint_step_u": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, dp]),
             "pf_adjoint_initial_rate": (ctypes.c_int, [vp, vp, vp, vp, dp]),
-            "pf_timing": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)]),
+            "pf_timing": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64), dp]),
             "pf_fem_table_size": (sz, []),
             "pf_fem_tables": (ctypes.c_int, [cfgp, dp, sz]),
             "pf_mg_levels": (ctypes.c_int, [cfgp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -314,6 +315,24 @@ class Context:
                     "pf_get_state")
         return P, V, phi, u, step.value
 
+    def get_fields(self, *names):
+        """Copies of the named state fields ("P", "V", "phi", "u"), in the
+        order given (pf_get_state with the other pointers NULL)."""
+        made = {}
+        for nm in names:
+            if nm in ("P", "V"):
+                made[nm] = self.new_field(3)
+            elif nm == "phi":
+                made[nm] = self.new_field(0, torch.float64)
+            elif nm == "u":
+                made[nm] = self.new_field(3, torch.float64)
+            else:
+                raise ValueError(f"get_fields: unknown field {nm!r}")
+        step = ctypes.c_int64()
+        self._check(self.L.pf_get_state(self.ctx, _ptr(made.get("P")), _ptr(made.get("V")), _ptr(made.get("phi")),
+                                        _ptr(made.get("u")), ctypes.byref(step)), "pf_get_state")
+        return tuple(made[nm] for nm in names)
+
     def step(self, nsteps: int = 1) -> dict:
         st = pf_step_stats()
         s = self.L.pf_step(self.ctx, nsteps, ctypes.byref(st))
@@ -359,14 +378,18 @@ class Context:
         self._check(self.L.pf_noise(self.ctx, int(step), _ptr(xi)), "pf_noise")
         return xi
 
-    def timing(self, enable: bool):
-        """Returns {class: (ms, launches)} accumulated since the last call and
-        switches per-launch event timing on or off."""
+    def timing(self, mode):
+        """Returns {class: (ms, launches, algorithmic bytes)} accumulated since
+        the last call and sets the accounting mode: False / PF_TIMING_OFF,
+        True / PF_TIMING_EVENTS (per-launch events, solves sequential) or
+        PF_TIMING_BYTES (launch and byte counts only)."""
+        mode = {False: PF_TIMING_OFF, True: PF_TIMING_EVENTS}.get(mode, mode)
         n = len(KERNEL_CLASSES)
         ms = (ctypes.c_double * n)()
         cnt = (ctypes.c_int64 * n)()
-        self._check(self.L.pf_timing(self.ctx, 1 if enable else 0, ms, cnt), "pf_timing")
-        return {k: (ms[t], cnt[t]) for t, k in enumerate(KERNEL_CLASSES)}
+        nb = (ctypes.c_double * n)()
+        self._check(self.L.pf_timing(self.ctx, int(mode), ms, cnt, nb), "pf_timing")
+        return {k: (ms[t], cnt[t], nb[t]) for t, k in enumerate(KERNEL_CLASSES)}
 
     def energy(self):
         out = (ctypes.c_double * 5)()

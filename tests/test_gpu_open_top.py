@@ -160,3 +160,23 @@ def test_open_lateral_256_full_size_properties(pf, oracle_mod):
     assert np.linalg.norm(r) <= 1.05 * cfg.tol_phi * np.linalg.norm(b)
     F = host(ctx.force(Pd, phi, u))
     assert rel(F, o.force(P0, phi_h, u_h)) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_open_force_matches_oracle(pf, oracle_mod, precision):
+    """pf_force with the open top: the top film plane's field reaches into
+    the first air plane of phi.  FP32 + refinement rounds P, phi and u to
+    float and evaluates in float (bar 1e-6 relative to the largest force
+    component); FP64 at 1e-12."""
+    cfg = open_cfg(precision=precision)
+    print(f"case: open force {precision}", flush=True)
+    P = domain_polarisation(cfg, 53, block=4, std=0.1)
+    if precision != "fp64":
+        P = P.astype(np.float32).astype(np.float64)
+    o = oracle_mod.Oracle(cfg)
+    phi = o.solve_phi(P)[0]
+    u = o.solve_u(P)[0]
+    ref = o.force(P, phi, u)
+    ctx = pf.Context(cfg)
+    F = host(ctx.force(dev(P, ctx.state_dtype), dev(phi), dev(u)))
+    assert rel(F, ref) < (1e-12 if precision == "fp64" else 1e-6)

@@ -232,7 +232,7 @@ def test_null_context_is_rejected_without_touching_the_device():
         "pf_adjoint_step": (z, z, z, z, z, z),
         "pf_adjoint_step_u": (z, z, z, z, z, z, z),
         "pf_adjoint_initial_rate": (z, z, z, z, z),
-        "pf_timing": (z, 0, z, z),
+        "pf_timing": (z, 0, z, z, z),
     }
     for name, args in calls.items():
         assert getattr(L, name)(*args) == pf.PF_EINVAL, name
