@@ -182,6 +182,25 @@ pf_status pf_workspace_size(const pf_config *cfg, size_t *bytes);
  * min(tol_phi, 1e-12).  *out is set on success. */
 pf_status pf_init(const pf_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream, pf_ctx **out);
 
+/* pf_init for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * context's workspace is the library's static device array of 64 MiB
+ * (one per GPU, held from the first use on that GPU until the process
+ * ends; enough for a 64 x 64 x 16 film in FP64 with the multigrid), not
+ * caller memory.  Binds to the current device and to hip_stream (NULL: the
+ * null stream).  The call allocates no device memory and no pinned host
+ * memory and creates no stream, event or thread; the context's two solves
+ * of a step therefore run one after the other on hip_stream (results are
+ * bitwise those of a pf_init context).  Rejects a configuration whose
+ * pf_workspace_size exceeds 64 MiB with PF_EINVAL (message on stderr).  One
+ * context per GPU at a time: while one made by this call lives, a second on
+ * the same device returns PF_ESTATE; pf_destroy (which waits for the
+ * stream) frees the array for the next.  The array keeps the last
+ * context's contents: initialisation clears what must start at zero, as
+ * pf_init does for the caller's uninitialised workspace.  Calls that
+ * overlap on one context race (contexts are not thread-safe). */
+pf_status pf_init_static(const pf_config *cfg, void *hip_stream, pf_ctx **out);
+
 /* Loads the polarisation P (device, 3N) as the current state, with optional
  * initial guesses phi0 (Np doubles) and u0 (3N doubles) for the first solves
  * (NULL: zero).  For the predictor-corrector it solves phi and u at P and

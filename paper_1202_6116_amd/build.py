@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpf.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["pf_kernels.hip", "pf_api.cpp", "pf_mg.cpp"]
+SOURCES = ["pf_kernels.hip", "pf_api.cpp", "pf_mg.cpp", "pf_static.hip"]
 
 # Packed FP32 instructions stay off (the compiler would otherwise form them
 # from float code).

@@ -537,6 +537,7 @@ struct pf_ctx {
   pf::Layout lay;
   char* ws;
   size_t ws_bytes;
+  int static_device;         // pf_init_static: the device whose static workspace this is (-1: caller's workspace)
   hipStream_t stream;        // the caller's stream
   // The FEM solve of a step runs on a worker thread with a stream of its
   // own, concurrently with the Poisson solve (forked from and joined back
@@ -1836,19 +1837,17 @@ pf_status pf_workspace_size(const pf_config* cfg, size_t* bytes) {
   return PF_OK;
 }
 
-pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf_ctx** out) {
-  if (!out) return PF_EINVAL;
-  *out = nullptr;
-  std::string why;
-  if (validate(cfg, &why) != PF_OK) {
-    fprintf(stderr, "pf_init: %s\n", why.c_str());
-    return PF_EINVAL;
-  }
-  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
-    fprintf(stderr, "pf_init: workspace must be non-null and 256-byte aligned\n");
-    return PF_EINVAL;
-  }
+namespace {
+
+// pf_init and pf_init_static.  static_device >= 0: the workspace is that
+// device's static array (claimed by the caller); the context then takes no
+// pinned host memory, second stream or worker thread (its solves run one
+// after the other on the caller's stream), so making it allocates no
+// device memory.
+pf_status init_ctx(const char* who, const pf_config* cfg, void* ws, size_t bytes, void* stream, int static_device,
+                   pf_ctx** out) {
   pf_ctx* c = new pf_ctx();
+  c->static_device = static_device;
   c->cfg = *cfg;
   c->electrodes.assign(cfg->electrodes, cfg->electrodes + cfg->n_electrodes);
   c->cfg.electrodes = c->electrodes.data();
@@ -1862,7 +1861,7 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   c->npartials = partial_slots(*cfg);
   c->lay = make_layout(*cfg, c->npartials);
   if (bytes < c->lay.total) {
-    fprintf(stderr, "pf_init: workspace of %zu bytes, %zu needed\n", bytes, c->lay.total);
+    fprintf(stderr, "%s: workspace of %zu bytes, %zu needed\n", who, bytes, c->lay.total);
     delete c;
     return PF_ENOMEM;
   }
@@ -1885,24 +1884,31 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
   std::memset(c->kc_bytes, 0, sizeof(c->kc_bytes));
   c->host_sc = nullptr;
   c->host_res = nullptr;
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_sc), sizeof(CgScalars) * kNumScalars, hipHostMallocDefault) !=
-          hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->host_res), kResultSlots * 8, hipHostMallocDefault) != hipSuccess) {
-    fprintf(stderr, "pf_init: pinned host allocation failed\n");
-    pf_destroy(c);
-    return PF_EHIP;
+  if (static_device >= 0) {
+    // read-backs into ordinary host memory, solves on the caller's stream
+    c->device = static_device;
+    c->host_sc = new CgScalars[kNumScalars];
+    c->host_res = new double[kResultSlots];
+  } else {
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->host_sc), sizeof(CgScalars) * kNumScalars,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->host_res), kResultSlots * 8, hipHostMallocDefault) != hipSuccess) {
+      fprintf(stderr, "%s: pinned host allocation failed\n", who);
+      pf_destroy(c);
+      return PF_EHIP;
+    }
+    // the second stream (default priority) and the worker thread that uses it
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      fprintf(stderr, "%s: stream or event creation failed\n", who);
+      pf_destroy(c);
+      return PF_EHIP;
+    }
+    c->worker.reset(new pf_ctx::Worker());
+    c->worker->th = std::thread(worker_main, c);
   }
-  // the second stream (default priority) and the worker thread that uses it
-  if (hipGetDevice(&c->device) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-    fprintf(stderr, "pf_init: stream or event creation failed\n");
-    pf_destroy(c);
-    return PF_EHIP;
-  }
-  c->worker.reset(new pf_ctx::Worker());
-  c->worker->th = std::thread(worker_main, c);
   FemTables tb;
   build_tables(c->cfg, &tb);
   c->gen = !c->mat.cubic || !tb.compact;
@@ -1920,12 +1926,64 @@ pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf
     if (e != hipSuccess) st = fail(c, PF_EHIP, "init: %s", hipGetErrorString(e));
   }
   if (st != PF_OK) {
-    fprintf(stderr, "pf_init: %s\n", c->err.c_str());
+    fprintf(stderr, "%s: %s\n", who, c->err.c_str());
     pf_destroy(c);
     return st;
   }
   *out = c;
   return PF_OK;
+}
+
+}  // namespace
+
+pf_status pf_init(const pf_config* cfg, void* ws, size_t bytes, void* stream, pf_ctx** out) {
+  if (!out) return PF_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (validate(cfg, &why) != PF_OK) {
+    fprintf(stderr, "pf_init: %s\n", why.c_str());
+    return PF_EINVAL;
+  }
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) {
+    fprintf(stderr, "pf_init: workspace must be non-null and 256-byte aligned\n");
+    return PF_EINVAL;
+  }
+  return init_ctx("pf_init", cfg, ws, bytes, stream, -1, out);
+}
+
+pf_status pf_init_static(const pf_config* cfg, void* stream, pf_ctx** out) {
+  if (!out) return PF_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (validate(cfg, &why) != PF_OK) {
+    fprintf(stderr, "pf_init_static: %s\n", why.c_str());
+    return PF_EINVAL;
+  }
+  size_t need = 0;
+  if (pf_workspace_size(cfg, &need) != PF_OK) return PF_EINVAL;
+  if (need > kStaticWorkspaceBytes) {
+    fprintf(stderr, "pf_init_static: the configuration needs a workspace of %zu bytes; the static workspace holds "
+            "%zu (use pf_init with a workspace of the caller's)\n", need, kStaticWorkspaceBytes);
+    return PF_EINVAL;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    fprintf(stderr, "pf_init_static: no current device\n");
+    return PF_EHIP;
+  }
+  void* ws = nullptr;
+  const hipError_t e = static_workspace_acquire(dev, &ws);
+  if (e == hipErrorAlreadyAcquired) {
+    fprintf(stderr, "pf_init_static: another context uses the static workspace of device %d\n", dev);
+    return PF_ESTATE;
+  }
+  if (e != hipSuccess) {
+    fprintf(stderr, "pf_init_static: static workspace of device %d: %s\n", dev, hipGetErrorString(e));
+    return PF_EHIP;
+  }
+  const pf_status st = init_ctx("pf_init_static", cfg, ws, kStaticWorkspaceBytes, stream, dev, out);
+  if (st != PF_OK) static_workspace_release(dev);
+  return st;
 }
 
 void pf_destroy(pf_ctx* c) {
@@ -1943,8 +2001,18 @@ void pf_destroy(pf_ctx* c) {
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->stream2) (void)hipStreamDestroy(c->stream2);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
-  if (c->host_sc) (void)hipHostFree(c->host_sc);
-  if (c->host_res) (void)hipHostFree(c->host_res);
+  if (c->static_device >= 0) {
+    // the static workspace is free for the device's next context once the
+    // work queued on it has finished
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    delete[] c->host_sc;
+    delete[] c->host_res;
+    static_workspace_release(c->static_device);
+  } else {
+    if (c->host_sc) (void)hipHostFree(c->host_sc);
+    if (c->host_res) (void)hipHostFree(c->host_res);
+  }
   delete c;
 }
 

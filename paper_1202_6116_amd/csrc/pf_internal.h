@@ -148,6 +148,11 @@ enum { kRedSetup = 0, kRedAlpha = 1, kRedBeta = 2, kRedOuter = 3, kRedSum = 4, k
 // x formed on the fly from b and the correction e of the next level, when
 // that level halves x and y (kMgCorrect: the prolongation is never stored).
 enum { kMgResidual = 0, kMgSweep = 1, kMgFirst = 2, kMgCorrect = 3 };
+// Size of the static device workspace of pf_init_static (per GPU).
+constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
+hipError_t static_workspace_acquire(int device, void** ptr);
+void static_workspace_release(int device);
+
 constexpr int kMgMaxLevels = 12;
 constexpr int64_t kMgDenseMax = 512;  // coarsest level solved by a dense inverse up to this many unknowns
 

@@ -29,7 +29,7 @@ KERNEL_CLASSES = ["poisson_setup", "poisson_a", "poisson_b", "fem_setup", "fem_a
 
 # Every symbol declared in include/pf.h.
 EXPORTS = [
-    "pf_workspace_size", "pf_init", "pf_set_state", "pf_restore_state", "pf_get_state", "pf_step",
+    "pf_workspace_size", "pf_init", "pf_init_static", "pf_set_state", "pf_restore_state", "pf_get_state", "pf_step",
     "pf_solve_phi", "pf_solve_u", "pf_force", "pf_noise", "pf_energy", "pf_set_params", "pf_adjoint_step",
     "pf_adjoint_step_u",
     "pf_adjoint_initial_rate", "pf_timing", "pf_fem_table_size", "pf_fem_tables", "pf_mg_levels", "pf_mg_table",
@@ -107,6 +107,7 @@ def lib() -> ctypes.CDLL:
         sig = {
             "pf_workspace_size": (ctypes.c_int, [cfgp, ctypes.POINTER(sz)]),
             "pf_init": (ctypes.c_int, [cfgp, vp, sz, vp, ctypes.POINTER(vp)]),
+            "pf_init_static": (ctypes.c_int, [cfgp, vp, ctypes.POINTER(vp)]),
             "pf_set_state": (ctypes.c_int, [vp, vp, vp, vp]),
             "pf_restore_state": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_int64]),
             "pf_get_state": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]),
@@ -239,34 +240,47 @@ def _ptr(t: Optional[torch.Tensor]):
 
 class Context:
     """One library context bound to a configuration, a torch-owned device
-    workspace and the current torch stream of `device`."""
+    workspace (or, with static_workspace, the library's static one: see
+    pf_init_static) and the current torch stream of `device`."""
 
-    def __init__(self, cfg: PFConfig, device: str = "cuda:0"):
+    def __init__(self, cfg: PFConfig, device: str = "cuda:0", static_workspace: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("the phase-field library needs a GPU (torch.cuda is not available)")
         self.cfg = cfg
         self.device = torch.device(device)
         self.L = lib()
         self._cfg_struct, self._els = make_config(cfg)
-        nbytes = pf_workspace_size(cfg)
-        # over-allocate by 256 B and align the base
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.ws.data_ptr()
-        self._ws_ptr = (base + 255) // 256 * 256
         self.stream = torch.cuda.current_stream(self.device)
         self.ctx = ctypes.c_void_p()
-        st = self.L.pf_init(ctypes.byref(self._cfg_struct), ctypes.c_void_p(self._ws_ptr), nbytes,
-                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx))
-        if st != PF_OK:
-            raise PFError(st, f"pf_init: {status_str(st)}")
+        if static_workspace:
+            self.ws = None
+            with torch.cuda.device(self.device):
+                st = self.L.pf_init_static(ctypes.byref(self._cfg_struct), ctypes.c_void_p(self.stream.cuda_stream),
+                                           ctypes.byref(self.ctx))
+            if st != PF_OK:
+                raise PFError(st, f"pf_init_static: {status_str(st)}")
+        else:
+            nbytes = pf_workspace_size(cfg)
+            # over-allocate by 256 B and align the base
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            st = self.L.pf_init(ctypes.byref(self._cfg_struct), ctypes.c_void_p(self._ws_ptr), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx))
+            if st != PF_OK:
+                raise PFError(st, f"pf_init: {status_str(st)}")
         self.state_dtype = torch.float64 if cfg.precision == "fp64" else torch.float32
         self.N = cfg.nodes
 
+    def close(self):
+        """Releases the context (pf_destroy); also done when it is collected."""
+        if getattr(self, "ctx", None) and self.ctx.value:
+            self.L.pf_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
     def __del__(self):
         try:
-            if getattr(self, "ctx", None) and self.ctx.value:
-                self.L.pf_destroy(self.ctx)
-                self.ctx = ctypes.c_void_p()
+            self.close()
         except Exception:
             pass
 

@@ -236,6 +236,8 @@ def test_null_context_is_rejected_without_touching_the_device():
     }
     for name, args in calls.items():
         assert getattr(L, name)(*args) == pf.PF_EINVAL, name
+    c, keep = pf.make_config(PFConfig(nx=16, ny=16, nz=4))
+    assert L.pf_init_static(ctypes.byref(c), z, z) == pf.PF_EINVAL  # no out pointer
     L.pf_destroy(None)
     assert pf.status_str(pf.PF_OK) == "ok"
     texts = {pf.status_str(s) for s in (pf.PF_EINVAL, pf.PF_ENOMEM, pf.PF_EHIP, pf.PF_ENOCONV,
@@ -268,3 +270,16 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_static_init_rejects_films_beyond_its_workspace():
+    """pf_init_static checks the workspace the configuration needs against
+    its 64 MiB static array before it touches the device."""
+    L = pf.lib()
+    for cfg, fits in ((PFConfig(nx=64, ny=64, nz=16, precond="mg", warm_start=2), True),
+                      (PFConfig(nx=128, ny=128, nz=32, precond="mg"), False)):
+        assert (pf.pf_workspace_size(cfg) <= 64 << 20) == fits
+    c, keep = pf.make_config(PFConfig(nx=128, ny=128, nz=32, precond="mg"))
+    out = ctypes.c_void_p()
+    assert L.pf_init_static(ctypes.byref(c), None, ctypes.byref(out)) == pf.PF_EINVAL
+    assert out.value is None
