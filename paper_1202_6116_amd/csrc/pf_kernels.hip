@@ -1748,8 +1748,10 @@ __global__ __launch_bounds__(kThreads) void mg_level_kernel(Dims d, const double
   }
 }
 
-// FP64 levels with at least this many nodes use mg_level_tile_kernel.
+// Levels with at least kMgMarchMinNodes nodes use mg_level_zm_kernel, FP64
+// levels with at least kMgTileMinNodes mg_level_tile_kernel.
 constexpr int64_t kMgTileMinNodes = 1 << 19;
+constexpr int64_t kMgMarchMinNodes = 1 << 22;
 
 // mg_level_kernel with the neighbourhood staged: the block's kBX x kBY
 // columns of plane k and their one-node halo on planes k - 1, k and k + 1
@@ -1821,6 +1823,110 @@ __global__ __launch_bounds__(kThreads) void mg_level_tile_kernel(Dims d, const d
   for (int c = 0; c < NC; c++) {
     const double r = (double)b[c * N + n] - q[c];
     out[c * N + n] = (T)(mode == kMgResidual ? r : (double)x[c * N + n] + omega * dinv[NC * k + c] * r);
+  }
+}
+
+// mg_level_kernel by 64 x 4 tiles marching up a z-chunk: each plane of x is
+// fetched from memory once (with its one-node halo) into a three-plane LDS
+// ring, software-pipelined like the solver-grid kernels (the loads of plane
+// k + 2 are in flight while plane k is computed), and each plane's stencil
+// is staged in a double-buffered LDS table (one coefficient per thread).
+// Fixed planes are staged as zero and never written; the arithmetic and the
+// order of summation are those of mg_level_kernel.
+template <typename T, int NC>
+__global__ __launch_bounds__(kThreads) void mg_level_zm_kernel(Dims d, TileMap tm, const double* __restrict__ tab,
+                                                               const double* __restrict__ dinv, int mode,
+                                                               double omega, const T* __restrict__ x,
+                                                               const T* __restrict__ b, T* __restrict__ out,
+                                                               const CgScalars* sc, int top_fixed) {
+  if (sc->done) return;
+  constexpr int TY = kBY;
+  constexpr int NT = NC * NC * 27;
+  static_assert(NT <= kThreads, "one stencil coefficient per thread");
+  __shared__ T ring[3][NC][TY + 2][kHX];
+  __shared__ double ctab[2][NT];
+  const TileCoord tc = tile_coord(d, tm);
+  const int ktop = d.nz - (top_fixed ? 1 : 0);
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = tid_flat();
+  const int i = tc.i0 + lx, j = tc.j0 + ly;
+  const bool valid = i < d.nx && j < d.ny;
+  const int64_t N = d.N;
+  const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
+  auto live = [&](int k) { return k >= 1 && k < ktop; };
+  auto fetch = [&](int64_t m, int k, T* raw) {
+    if (!live(k)) return;
+#pragma unroll
+    for (int e = 0; e < NC; e++) raw[e] = x[e * N + m];
+  };
+  auto comb = [&](int, const T* raw, T* o) {
+#pragma unroll
+    for (int e = 0; e < NC; e++) o[e] = raw[e];
+  };
+  auto coef = [&](int k) { return (tid < NT && live(k)) ? tab[(size_t)k * NT + tid] : 0.0; };
+  auto centre = [&](int k, T* bv) {
+#pragma unroll
+    for (int c = 0; c < NC; c++) bv[c] = 0;
+    if (valid && live(k)) {
+      const int64_t n = col + d.plane * k;
+#pragma unroll
+      for (int c = 0; c < NC; c++) bv[c] = b[c * N + n];
+    }
+  };
+  Stage<T, NC, Halo<TY>::NPT> st;
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 - 1, fetch);
+  stage_store<TY>(ring, st, tc.k0 - 1, comb);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
+  stage_store<TY>(ring, st, tc.k0, comb);
+  if (tid < NT) ctab[tc.k0 & 1][tid] = coef(tc.k0);
+  stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
+  double cn = coef(tc.k0 + 1);
+  T bv[NC];
+  centre(tc.k0, bv);
+  for (int k = tc.k0; k < tc.k1; k++) {
+    stage_store<TY>(ring, st, k + 1, comb);
+    if (tid < NT) ctab[(k + 1) & 1][tid] = cn;
+    if (k + 2 <= tc.k1) {
+      stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
+      cn = coef(k + 2);
+    }
+    T bn[NC];
+    centre(k + 1, bn);
+    __syncthreads();
+    if (valid && live(k)) {
+      const double* tk = ctab[k & 1];
+      double q[NC];
+#pragma unroll
+      for (int c = 0; c < NC; c++) q[c] = 0.0;
+#pragma unroll
+      for (int dz = -1; dz <= 1; dz++) {
+        if (!live(k + dz)) continue;
+        const int s = slot_of(k + dz);
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+          for (int dx = -1; dx <= 1; dx++) {
+            const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+            double u[NC];
+#pragma unroll
+            for (int e = 0; e < NC; e++) u[e] = (double)ring[s][e][ly + 1 + dy][lx + 1 + dx];
+#pragma unroll
+            for (int c = 0; c < NC; c++)
+#pragma unroll
+              for (int e = 0; e < NC; e++) q[c] += tk[(c * NC + e) * 27 + o] * u[e];
+          }
+      }
+      const int64_t n = col + d.plane * k;
+      const int sk = slot_of(k);
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        const double r = (double)bv[c] - q[c];
+        out[c * N + n] =
+            (T)(mode == kMgResidual ? r : (double)ring[sk][c][ly + 1][lx + 1] + omega * dinv[NC * k + c] * r);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) bv[c] = bn[c];
+    __syncthreads();
   }
 }
 
@@ -2982,10 +3088,19 @@ hipError_t launch_mg_fine(const Dims& d, const TileMap& tm, const FemTables* tb,
 template <typename T>
 hipError_t launch_mg_level(const Dims& d, int nc, const double* tab, const double* dinv, int mode, double omega,
                            const T* x, const T* b, T* out, const CgScalars* sc, int top_fixed, hipStream_t s) {
-  // large FP64 levels stage the neighbourhood in LDS; on small ones the
-  // extra barrier and staging cost more than the loads they save, and with
-  // FP32 vectors the node kernel's loads are cheap enough that the LDS
-  // reads of the staged form do not pay
+  // the largest levels march z with each plane staged once; mid-size FP64
+  // levels stage a tile's neighbourhood per plane (more blocks in flight);
+  // on small ones the node kernel's parallelism wins
+  if (d.N >= kMgMarchMinNodes) {
+    const TileMap tm = make_tile_map(d, kBY, 4096);
+    if (nc == 3)
+      mg_level_zm_kernel<T, 3><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tab, dinv, mode, omega, x, b, out, sc,
+                                                                  top_fixed);
+    else
+      mg_level_zm_kernel<T, 1><<<tm.nblocks, node_block(), 0, s>>>(d, tm, tab, dinv, mode, omega, x, b, out, sc,
+                                                                  top_fixed);
+    return hipGetLastError();
+  }
   const bool tile = sizeof(T) == 8 && d.N >= kMgTileMinNodes;
   if (nc == 3) {
     if (tile)

@@ -143,8 +143,12 @@ def test_mg_adjoint_matches_oracle(pf, oracle_mod, ws):
     J.backward()
     assert abs(float(J.detach()) - J_ref) <= 1e-10 * abs(J_ref)
     g = np.concatenate([volts.grad.cpu().numpy(), [a1.grad.item()]])
-    assert rel(g, dth_ref) < 1e-7, (g, dth_ref)
-    assert rel(host(P0t.grad), dP_ref) < 1e-7
+    errs = (rel(g, dth_ref), rel(host(P0t.grad), dP_ref))
+    print("adjoint relative errors (dtheta, dJ/dP0):", errs, flush=True)
+    # both sides solve to a relative residual of 1e-13, so each gradient
+    # carries an error of order kappa * 1e-13 (kappa <= 1e3 on these films);
+    # measured: 1e-15 .. 1e-14
+    assert errs[0] < 1e-10 and errs[1] < 1e-10, (g, dth_ref)
 
 
 @pytest.mark.parametrize("name", ["lateral_256x256x64", "lateral_open_256x256x64"])
