@@ -1751,7 +1751,7 @@ __global__ __launch_bounds__(kThreads) void mg_level_kernel(Dims d, const double
 // Levels with at least kMgMarchMinNodes nodes use mg_level_zm_kernel, FP64
 // levels with at least kMgTileMinNodes mg_level_tile_kernel.
 constexpr int64_t kMgTileMinNodes = 1 << 19;
-constexpr int64_t kMgMarchMinNodes = 1 << 22;
+constexpr int64_t kMgMarchMinNodes = 1 << 19;
 
 // mg_level_kernel with the neighbourhood staged: the block's kBX x kBY
 // columns of plane k and their one-node halo on planes k - 1, k and k + 1
@@ -1829,8 +1829,10 @@ __global__ __launch_bounds__(kThreads) void mg_level_tile_kernel(Dims d, const d
 // mg_level_kernel by 64 x 4 tiles marching up a z-chunk: each plane of x is
 // fetched from memory once (with its one-node halo) into a three-plane LDS
 // ring, software-pipelined like the solver-grid kernels (the loads of plane
-// k + 2 are in flight while plane k is computed), and each plane's stencil
-// is staged in a double-buffered LDS table (one coefficient per thread).
+// k + 2 are in flight while plane k is computed).  The plane's stencil is
+// uniform over the block and read with scalar loads, so the LDS serves only
+// the neighbour values (a table staged in LDS made the kernel LDS-bound: 27
+// taps x NC^2 coefficient reads per node against 27 NC neighbour reads).
 // Fixed planes are staged as zero and never written; the arithmetic and the
 // order of summation are those of mg_level_kernel.
 template <typename T, int NC>
@@ -1842,12 +1844,10 @@ __global__ __launch_bounds__(kThreads) void mg_level_zm_kernel(Dims d, TileMap t
   if (sc->done) return;
   constexpr int TY = kBY;
   constexpr int NT = NC * NC * 27;
-  static_assert(NT <= kThreads, "one stencil coefficient per thread");
   __shared__ T ring[3][NC][TY + 2][kHX];
-  __shared__ double ctab[2][NT];
   const TileCoord tc = tile_coord(d, tm);
   const int ktop = d.nz - (top_fixed ? 1 : 0);
-  const int lx = threadIdx.x, ly = threadIdx.y, tid = tid_flat();
+  const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
   const bool valid = i < d.nx && j < d.ny;
   const int64_t N = d.N;
@@ -1862,7 +1862,6 @@ __global__ __launch_bounds__(kThreads) void mg_level_zm_kernel(Dims d, TileMap t
 #pragma unroll
     for (int e = 0; e < NC; e++) o[e] = raw[e];
   };
-  auto coef = [&](int k) { return (tid < NT && live(k)) ? tab[(size_t)k * NT + tid] : 0.0; };
   auto centre = [&](int k, T* bv) {
 #pragma unroll
     for (int c = 0; c < NC; c++) bv[c] = 0;
@@ -1877,23 +1876,17 @@ __global__ __launch_bounds__(kThreads) void mg_level_zm_kernel(Dims d, TileMap t
   stage_store<TY>(ring, st, tc.k0 - 1, comb);
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0, fetch);
   stage_store<TY>(ring, st, tc.k0, comb);
-  if (tid < NT) ctab[tc.k0 & 1][tid] = coef(tc.k0);
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
-  double cn = coef(tc.k0 + 1);
   T bv[NC];
   centre(tc.k0, bv);
   for (int k = tc.k0; k < tc.k1; k++) {
     stage_store<TY>(ring, st, k + 1, comb);
-    if (tid < NT) ctab[(k + 1) & 1][tid] = cn;
-    if (k + 2 <= tc.k1) {
-      stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
-      cn = coef(k + 2);
-    }
+    if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
     T bn[NC];
     centre(k + 1, bn);
     __syncthreads();
     if (valid && live(k)) {
-      const double* tk = ctab[k & 1];
+      const double* tk = tab + (size_t)k * NT;
       double q[NC];
 #pragma unroll
       for (int c = 0; c < NC; c++) q[c] = 0.0;
