@@ -39,6 +39,11 @@
  * Precision.  PF_FP64: every array is double.  PF_FP32_REFINE: P, V and
  *   forces are float, phi and u are double (the refined masters); the sweeps
  *   run in float, dot products and the outer residuals in double.
+ *   PF_FP32_SOLVES: the solves of PF_FP32_REFINE (float CG and multigrid
+ *   sweeps on the correction, double dot products, outer residuals and
+ *   masters), everything else as PF_FP64 (double state, force and update),
+ *   so the state keeps double precision while the solves move half the
+ *   bytes.
  *
  * Memory.  The caller owns all device memory: the state arrays it passes in
  *   and one workspace of pf_workspace_size() bytes (256-byte aligned).  The
@@ -89,7 +94,7 @@ enum { PF_TOP_METAL = 0, PF_TOP_OPEN = 1 };
 /* integrator */
 enum { PF_INT_PC = 0, PF_INT_EULER = 1 };
 /* precision */
-enum { PF_FP64 = 0, PF_FP32_REFINE = 1 };
+enum { PF_FP64 = 0, PF_FP32_REFINE = 1, PF_FP32_SOLVES = 2 };
 
 /* An electrode: the half-open node rectangle [x0, x1) x [y0, y1) of the top
  * ghost plane held at `volts` (Sec. III.C).  Electrodes must not overlap. */
@@ -112,7 +117,7 @@ typedef struct {
   double C11, C12, C44;         /* cubic elastic stiffness (Eq. 13 generalised) */
   double Q11, Q12, Q44;         /* electrostriction, Eq. 15 */
   int32_t integrator;           /* PF_INT_PC (default) or PF_INT_EULER */
-  int32_t precision;            /* PF_FP64 or PF_FP32_REFINE */
+  int32_t precision;            /* PF_FP64, PF_FP32_REFINE or PF_FP32_SOLVES */
   double tol_phi, tol_u;        /* CG stop: ||b - A x||_2 <= tol ||b||_2 */
   int32_t maxit;                /* CG iteration cap per solve (> 0) */
   int32_t warm_start;           /* 0: solves start from zero; 1: from the previous

@@ -454,7 +454,7 @@ Layout make_layout(const pf_config& c, int npartials) {
   for (int b = 0; b < 2; b++) L.fp[b] = take(3 * N * 8);
   L.dphi = take(Np * 4);
   L.du = take(3 * N * 4);
-  L.fbody = c.precision == PF_FP32_REFINE ? take(3 * N * 8) : 0;
+  L.fbody = c.precision != PF_FP64 ? take(3 * N * 8) : 0;
   L.hist = c.warm_start == 2 && c.extrap_order > 0 ? take((Np + 3 * N) * 8 * (size_t)c.extrap_order) : 0;
   L.adj_hist = c.warm_start == 2 && c.extrap_order > 0 ? take((Np + 6 * N) * 8 * (size_t)c.extrap_order) : 0;
   for (int t = 0; t < 8; t++) L.scratch[t] = take(S * 8);
@@ -694,7 +694,8 @@ pf_status validate(const pf_config* c, std::string* why) {
     }
   }
   if (c->integrator != PF_INT_PC && c->integrator != PF_INT_EULER) return bad("unknown integrator");
-  if (c->precision != PF_FP64 && c->precision != PF_FP32_REFINE) return bad("unknown precision");
+  if (c->precision != PF_FP64 && c->precision != PF_FP32_REFINE && c->precision != PF_FP32_SOLVES)
+    return bad("unknown precision");
   if (!(c->tol_phi > 0) || !(c->tol_u > 0)) return bad("tolerances must be > 0");
   if (c->maxit <= 0) return bad("maxit must be > 0");
   if (c->warm_start < 0 || c->warm_start > 2) return bad("warm_start must be 0, 1 or 2");
@@ -772,7 +773,10 @@ Coefs<T> make_coefs(const pf_ctx* c) {
   return k;
 }
 
+// fp32: the state (P, V) and the force are float; refined: the solves run
+// in float with double refinement (PF_FP32_REFINE and PF_FP32_SOLVES)
 bool fp32(const pf_ctx* c) { return c->cfg.precision == PF_FP32_REFINE; }
+bool refined(const pf_ctx* c) { return c->cfg.precision != PF_FP64; }
 size_t state_bytes(const pf_ctx* c) { return fp32(c) ? 4 : 8; }
 
 CgScalars* dev_sc(pf_ctx* c, int which) { return at<CgScalars>(c, c->lay.scalars) + which; }
@@ -1178,7 +1182,9 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
 // so the Krylov space is rarely thrown away by a restart.  The FEM setup of
 // the first sweep stores the body force (FP64); later sweeps form b - K x64
 // from it without evaluating the eigenstress again.
-pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, double cdt, double* x64, float* x32,
+// S: the state's type (float for PF_FP32_REFINE, double for PF_FP32_SOLVES).
+template <typename S>
+pf_status solve_refined(pf_ctx* c, bool fem, const S* P, const S* V, double cdt, double* x64, float* x32,
                         double tol, bool warm, SolveResult* res) {
   const Dims& d = fem ? c->dims : c->dims_p;
   const int which = fem ? 1 : 0;
@@ -1203,15 +1209,16 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
   double* fbody = at<double>(c, c->lay.fbody);
   bool synced = false;  // x32 == (float) x64, as the last refinement update left it
   for (;;) {
-    // per unknown: the first FEM sweep reads P, V (FP32) and x64 and writes
-    // r, p, d (FP32) and the FP64 body force; later sweeps read the body
-    // force and x64 instead of P, V; the Poisson setup reads P, V of the
-    // film and x64 and writes r, p, d
+    // per unknown: the first FEM sweep reads P, V and x64 and writes r, p,
+    // d (FP32) and the FP64 body force; later sweeps read the body force
+    // and x64 instead of P, V; the Poisson setup reads P, V of the film and
+    // x64 and writes r, p, d
     const double n3 = 3.0 * c->dims.N;
+    const double sv = 2.0 * sizeof(S);
     if (fem && res->outer == 0) {
-      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, n3 * (4 + 4 + 8 + 3 * 4 + 8), [&] {
-        return launch_fem_setup<double, float, float>(d, c->tm_f, cf64, tb, c->gen, P, V, cdt, nullptr, x64, r, pb[0],
-                                                      pb[1], dz, fbody, part, strm(c));
+      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, n3 * (sv + 8 + 3 * 4 + 8), [&] {
+        return launch_fem_setup<double, S, float>(d, c->tm_f, cf64, tb, c->gen, P, V, cdt, nullptr, x64, r, pb[0],
+                                                  pb[1], dz, fbody, part, strm(c));
       }));
     } else if (fem) {
       PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, n3 * (8 + 8 + 3 * 4), [&] {
@@ -1219,8 +1226,8 @@ pf_status solve_refined(pf_ctx* c, bool fem, const float* P, const float* V, dou
                                                strm(c));
       }));
     } else {
-      PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, n3 * (4 + 4) + (double)d.N * (8 + 3 * 4), [&] {
-        return launch_poisson_setup<double, float, float>(d, cf64, P, V, cdt, 1, 1, at<double>(c, c->lay.ghost64),
+      PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, n3 * sv + (double)d.N * (8 + 3 * 4), [&] {
+        return launch_poisson_setup<double, S, float>(d, cf64, P, V, cdt, 1, 1, at<double>(c, c->lay.ghost64),
                                                           c->cfg.phi_bottom, emask(c), x64, r, pb[0], dz, part,
                                                           strm(c));
       }));
@@ -1362,16 +1369,22 @@ pf_status solve_nonlocal(pf_ctx* c, const void* P, const void* V, double cdt, bo
   auto poisson = [&](SolveResult* r) -> pf_status {
     if (ring) PF_TRY(extrapolate_field(c, 0, ring[0]));
     if (fp32(c))
-      return solve_refined(c, false, static_cast<const float*>(P), static_cast<const float*>(V), cdt, phi,
-                           at<float>(c, c->lay.phi32), c->cfg.tol_phi, warm, r);
+      return solve_refined<float>(c, false, static_cast<const float*>(P), static_cast<const float*>(V), cdt, phi,
+                                  at<float>(c, c->lay.phi32), c->cfg.tol_phi, warm, r);
+    if (refined(c))
+      return solve_refined<double>(c, false, static_cast<const double*>(P), static_cast<const double*>(V), cdt, phi,
+                                   at<float>(c, c->lay.phi32), c->cfg.tol_phi, warm, r);
     return solve_poisson64<double>(c, kPredPhi, static_cast<const double*>(P), static_cast<const double*>(V), cdt, 1,
                                    1, at<double>(c, c->lay.ghost64), c->cfg.phi_bottom, phi, c->cfg.tol_phi, warm, r);
   };
   auto fem = [&](SolveResult* r) -> pf_status {
     if (ring) PF_TRY(extrapolate_field(c, 1, ring[1]));
     if (fp32(c))
-      return solve_refined(c, true, static_cast<const float*>(P), static_cast<const float*>(V), cdt, u,
-                           at<float>(c, c->lay.u32), c->cfg.tol_u, warm, r);
+      return solve_refined<float>(c, true, static_cast<const float*>(P), static_cast<const float*>(V), cdt, u,
+                                  at<float>(c, c->lay.u32), c->cfg.tol_u, warm, r);
+    if (refined(c))
+      return solve_refined<double>(c, true, static_cast<const double*>(P), static_cast<const double*>(V), cdt, u,
+                                   at<float>(c, c->lay.u32), c->cfg.tol_u, warm, r);
     return solve_fem64<double>(c, kPredU, static_cast<const double*>(P), static_cast<const double*>(V), cdt, nullptr,
                                u, c->cfg.tol_u, warm, r);
   };
@@ -2121,8 +2134,11 @@ pf_status pf_solve_phi(pf_ctx* c, const void* P, void* phi, pf_solve_stats* st) 
   SolveResult r{};
   pf_status s;
   if (fp32(c))
-    s = solve_refined(c, false, static_cast<const float*>(P), nullptr, 0.0, static_cast<double*>(phi),
-                      scratch<float>(c, kScrTmp), c->cfg.tol_phi, c->cfg.warm_start != 0, &r);
+    s = solve_refined<float>(c, false, static_cast<const float*>(P), nullptr, 0.0, static_cast<double*>(phi),
+                             scratch<float>(c, kScrTmp), c->cfg.tol_phi, c->cfg.warm_start != 0, &r);
+  else if (refined(c))
+    s = solve_refined<double>(c, false, static_cast<const double*>(P), nullptr, 0.0, static_cast<double*>(phi),
+                              scratch<float>(c, kScrTmp), c->cfg.tol_phi, c->cfg.warm_start != 0, &r);
   else
     s = solve_poisson64<double>(c, kPredAux, static_cast<const double*>(P), nullptr, 0.0, 1, 1,
                                 at<double>(c, c->lay.ghost64), c->cfg.phi_bottom, static_cast<double*>(phi),
@@ -2141,8 +2157,11 @@ pf_status pf_solve_u(pf_ctx* c, const void* P, void* u, pf_solve_stats* st) {
   SolveResult r{};
   pf_status s;
   if (fp32(c))
-    s = solve_refined(c, true, static_cast<const float*>(P), nullptr, 0.0, static_cast<double*>(u),
-                      scratch<float>(c, kScrTmp), c->cfg.tol_u, c->cfg.warm_start != 0, &r);
+    s = solve_refined<float>(c, true, static_cast<const float*>(P), nullptr, 0.0, static_cast<double*>(u),
+                             scratch<float>(c, kScrTmp), c->cfg.tol_u, c->cfg.warm_start != 0, &r);
+  else if (refined(c))
+    s = solve_refined<double>(c, true, static_cast<const double*>(P), nullptr, 0.0, static_cast<double*>(u),
+                              scratch<float>(c, kScrTmp), c->cfg.tol_u, c->cfg.warm_start != 0, &r);
   else
     s = solve_fem64<double>(c, kPredAux, static_cast<const double*>(P), nullptr, 0.0, nullptr,
                             static_cast<double*>(u), c->cfg.tol_u, c->cfg.warm_start != 0, &r);

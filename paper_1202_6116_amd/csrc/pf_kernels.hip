@@ -3325,6 +3325,7 @@ PF_INSTANTIATE_MG(float)
 PF_INSTANTIATE_SETUP(double, double, double)
 PF_INSTANTIATE_SETUP(double, float, float)
 PF_INSTANTIATE_SETUP(double, float, double)
+PF_INSTANTIATE_SETUP(double, double, float)
 
 template hipError_t launch_fem_resid<double, float>(const Dims&, const TileMap&, const FemTables*, bool,
                                                     const double*, double*, float*, float*, float*, float*, double*,

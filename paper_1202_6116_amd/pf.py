@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libpf.so")
 
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ENOCONV, PF_ENONFINITE, PF_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PF_INT_PC, PF_INT_EULER = 0, 1
-PF_FP64, PF_FP32_REFINE = 0, 1
+PF_FP64, PF_FP32_REFINE, PF_FP32_SOLVES = 0, 1, 2
+PRECISIONS = {"fp64": PF_FP64, "fp32_refine": PF_FP32_REFINE, "fp32_solves": PF_FP32_SOLVES}
 PF_TOP_METAL, PF_TOP_OPEN = 0, 1
 PF_PRECOND_JACOBI, PF_PRECOND_MG = 0, 1
 PF_TIMING_OFF, PF_TIMING_EVENTS, PF_TIMING_BYTES = 0, 1, 2
@@ -152,7 +153,7 @@ def make_config(cfg: PFConfig):
     c.n_electrodes = len(cfg.electrodes)
     c.electrodes = ctypes.cast(els, ctypes.POINTER(pf_electrode))
     c.integrator = PF_INT_PC if cfg.integrator == "pc" else PF_INT_EULER
-    c.precision = PF_FP64 if cfg.precision == "fp64" else PF_FP32_REFINE
+    c.precision = PRECISIONS[cfg.precision]
     c.maxit = cfg.maxit
     c.warm_start = int(cfg.warm_start)
     c.terms = cfg.terms
@@ -269,7 +270,7 @@ class Context:
                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx))
             if st != PF_OK:
                 raise PFError(st, f"pf_init: {status_str(st)}")
-        self.state_dtype = torch.float64 if cfg.precision == "fp64" else torch.float32
+        self.state_dtype = torch.float32 if cfg.precision == "fp32_refine" else torch.float64
         self.N = cfg.nodes
 
     def close(self):

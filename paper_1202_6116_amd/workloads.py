@@ -69,7 +69,7 @@ class PFConfig:
     Q12: float = -0.015
     Q44: float = 0.02
     integrator: str = "pc"          # "pc" (Eq. 19) or "euler"
-    precision: str = "fp64"         # "fp64" or "fp32_refine"
+    precision: str = "fp64"         # "fp64", "fp32_refine" or "fp32_solves" (FP64 state, FP32 refined solves)
     tol_phi: float = 1e-10
     tol_u: float = 1e-10
     maxit: int = 5000
