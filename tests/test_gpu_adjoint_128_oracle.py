@@ -1,0 +1,69 @@
+"""The 128x128x32 adjoint case at full size against the FP64 oracle's own
+discrete adjoint over a prefix of the trajectory (written by
+tests/golden/make_adjoint_128_oracle.py, which calls only the oracle): J,
+dJ/dV_e, dJ/da1 and dJ/dP0 on sampled columns.  The GPU runs the same case
+through the differentiable layer with checkpoints (two segments, one
+recomputed).  Bar: 1e-8 relative.  The forward solves run to 1e-12 and the
+adjoint solves to 1e-13 on the oracle's side (to the preset's 1e-12 on the
+GPU's, with other preconditioners and warm starts), so two correct runs
+differ by about kappa * 1e-12 with kappa up to ~1e4 for the FEM operator of
+this film."""
+import glob
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1202_6116_amd.workloads import initial_polarisation, workloads
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+BAR = 1e-8
+
+
+def prefixes():
+    return sorted(int(re.search(r"steps(\d+)\.npz$", f).group(1))
+                  for f in glob.glob(os.path.join(GOLDEN, "adjoint_128x128x32_oracle_steps*.npz")))
+
+
+@pytest.fixture(scope="module")
+def pf():
+    from paper_1202_6116_amd import pf as m
+    return m
+
+
+@pytest.mark.skipif(not prefixes(), reason="the oracle's adjoint of the 128x128x32 case is not in tests/golden")
+@pytest.mark.parametrize("precond", ["mg", "jacobi"])
+def test_adjoint_128_matches_cpu_adjoint(pf, precond):
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    nsteps = prefixes()[-1]
+    ref = np.load(os.path.join(GOLDEN, f"adjoint_128x128x32_oracle_steps{nsteps}.npz"))
+    assert json.loads(str(ref["meta"]))["workload"] == "adjoint_128x128x32"
+    w = workloads()["adjoint_128x128x32"]
+    cfg = w.cfg.replace(precond=precond, warm_start=2)
+    print(f"case: adjoint 128x128x32, {nsteps} steps, {precond}, vs the oracle's adjoint", flush=True)
+    ctx = pf.Context(cfg)
+    P0 = torch.from_numpy(initial_polarisation(w)).to("cuda:0").requires_grad_(True)
+    x0, x1, y0, y1, z0, z1 = w.region
+    wgt = torch.zeros((3,) + cfg.shape, dtype=torch.float64, device="cuda:0")
+    wgt[2, z0:z1, y0:y1, x0:x1] = 1.0 / ((x1 - x0) * (y1 - y0) * (z1 - z0))
+    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+    PN = tdgl_steps(P0, volts, a1, ctx, nsteps, max(1, nsteps // 2))
+    J = (PN * wgt).sum()
+    J.backward()
+    xs = torch.as_tensor(ref["xs"], device="cuda:0")
+    ys = torch.as_tensor(ref["ys"], device="cuda:0")
+    dP = P0.grad.index_select(-2, ys).index_select(-1, xs).cpu().numpy()
+    g = np.concatenate([volts.grad.cpu().numpy(), [a1.grad.item()]])
+    errs = {"J": abs(float(J.detach()) - float(ref["J"])) / abs(float(ref["J"])),
+            "dtheta": float(np.abs(g - ref["dtheta"]).max() / np.abs(ref["dtheta"]).max()),
+            "dJ/dP0": float(np.abs(dP - ref["dP0"]).max() / float(ref["dP0_scale"]))}
+    print("relative errors vs the oracle's adjoint:", errs, flush=True)
+    for k, v in errs.items():
+        assert v < BAR, (k, v)

@@ -283,3 +283,18 @@ def test_static_init_rejects_films_beyond_its_workspace():
     out = ctypes.c_void_p()
     assert L.pf_init_static(ctypes.byref(c), None, ctypes.byref(out)) == pf.PF_EINVAL
     assert out.value is None
+
+
+def test_precision_modes_and_their_workspaces():
+    """The three precision modes validate; an unknown one does not.  The
+    FP32-solves mode keeps the FP64 state and adds the FP64 body force of the
+    refinement sweeps, so its workspace is the FP64 one plus 3N doubles."""
+    L = pf.lib()
+    base = PFConfig(nx=32, ny=16, nz=6, precond="mg", warm_start=2)
+    sizes = {p: pf.pf_workspace_size(base.replace(precision=p)) for p in ("fp64", "fp32_refine", "fp32_solves")}
+    assert sizes["fp32_solves"] >= sizes["fp64"] + 3 * base.nodes * 8
+    assert sizes["fp32_refine"] < sizes["fp32_solves"]
+    c, keep = pf.make_config(base)
+    c.precision = 3
+    n = ctypes.c_size_t()
+    assert L.pf_workspace_size(ctypes.byref(c), ctypes.byref(n)) == pf.PF_EINVAL
