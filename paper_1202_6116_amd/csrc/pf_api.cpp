@@ -538,6 +538,15 @@ struct pf_ctx {
   char* ws;
   size_t ws_bytes;
   int static_device;         // pf_init_static: the device whose static workspace this is (-1: caller's workspace)
+  // The coarse part of each V-cycle (restriction from the solver grid down
+  // to the coarsest level and back up to level 1) has fixed arguments for a
+  // field (0 Poisson, 1 FEM) and vector type ([1]: float): it is captured
+  // once into a graph of kernel nodes and replayed.  graphs: off for static
+  // contexts, with per-launch events, or after a failed capture.
+  bool graphs;
+  hipStream_t capture_stream[2];
+  hipGraphExec_t mg_graph[2][2];
+  double mg_graph_bytes[2][2];
   hipStream_t stream;        // the caller's stream
   // The FEM solve of a step runs on a worker thread with a stream of its
   // own, concurrently with the Poisson solve (forked from and joined back
@@ -947,7 +956,17 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   auto Dv = [&](int l) { return at<double>(c, L.dinv[l]); };
   auto Zm = [&](int l) { return at<MgZ>(c, L.zmap[l]); };
   auto Zf = [&](int l) { return at<int>(c, L.zfine[l]); };
-  auto run = [&](double bytes, auto&& fn) { return timed(c, PF_KC_MG, f, k, bytes, fn); };
+  // while the coarse part is captured into a graph, launches are recorded
+  // (not run) and their bytes summed for the graph's accounting
+  bool capturing = false;
+  double cap_bytes = 0.0;
+  auto run = [&](double bytes, auto&& fn) -> hipError_t {
+    if (capturing) {
+      cap_bytes += bytes;
+      return fn();
+    }
+    return timed(c, PF_KC_MG, f, k, bytes, fn);
+  };
   // algorithmic bytes: nc values of T per node of level l, times `reps`
   auto lb = [&](int l, double reps) { return reps * nc * (double)D[l].N * sizeof(T); };
   // the solver grid: the Poisson levels count a fixed bottom plane below it
@@ -979,8 +998,10 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   const double v0b = nc * n0 * sizeof(T);
   // first sweep's residual: b read, t written
   hipError_t e = run0(2 * v0b, [&] { return fine(kMgFirst, om0, nullptr, t0, nullptr); });
-  if (e == hipSuccess)
-    e = run(lb(0, 1) + lb(1, 1), [&] {
+  // the coarse part: restriction to level 1, the coarser levels, and the
+  // prolongations and sweeps back up to level 1
+  auto coarse_part = [&]() -> hipError_t {
+  hipError_t e = run(lb(0, 1) + lb(1, 1), [&] {
       // the solver grid stores no fixed planes (the Poisson ghost planes
       // lie outside its storage)
       return launch_mg_restrict<T>(d0, D[1], nc, h.levels[1].cx, h.levels[1].cy, Zm(1), Zf(1), t0, V(L.b[1]), sc,
@@ -1035,6 +1056,44 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
         return launch_mg_level<T>(d, nc, tab, Dv(l), kMgSweep, h.levels[l].omega, V(L.v[l]), V(L.b[l]), V(L.o[l]),
                                   sc, top, st);
       });
+  }
+  return e;
+  };
+  if (e == hipSuccess) {
+    const int ti = sizeof(T) == 4 ? 1 : 0;
+    if (c->graphs && c->timing != PF_TIMING_EVENTS && !c->mg_graph[f][ti]) {
+      // capture on the field's own stream (the caller's may be the null
+      // stream, which cannot capture); nothing runs while capturing
+      const hipStream_t keep = st;
+      st = c->capture_stream[f];
+      capturing = true;
+      cap_bytes = 0.0;
+      hipGraph_t g = nullptr;
+      hipError_t ce = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      if (ce == hipSuccess) {
+        const hipError_t le = coarse_part();
+        ce = hipStreamEndCapture(st, &g);
+        if (ce == hipSuccess) ce = le;
+      }
+      hipGraphExec_t ex = nullptr;
+      if (ce == hipSuccess && g) ce = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      st = keep;
+      capturing = false;
+      if (ce == hipSuccess && ex) {
+        c->mg_graph[f][ti] = ex;
+        c->mg_graph_bytes[f][ti] = cap_bytes;
+      } else {
+        c->graphs = false;  // launch kernel by kernel from now on
+        (void)hipGetLastError();
+      }
+    }
+    if (c->graphs && c->timing != PF_TIMING_EVENTS && c->mg_graph[f][ti]) {
+      hipGraphExec_t ex = c->mg_graph[f][ti];
+      e = timed(c, PF_KC_MG, f, k, c->mg_graph_bytes[f][ti], [&] { return hipGraphLaunch(ex, st); });
+    } else {
+      e = coarse_part();
+    }
   }
   if (fused) {
     // b and the level-1 correction read, z written
@@ -1914,11 +1973,14 @@ pf_status init_ctx(const char* who, const pf_config* cfg, void* ws, size_t bytes
     if (hipGetDevice(&c->device) != hipSuccess ||
         hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->capture_stream[0], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->capture_stream[1], hipStreamNonBlocking) != hipSuccess) {
       fprintf(stderr, "%s: stream or event creation failed\n", who);
       pf_destroy(c);
       return PF_EHIP;
     }
+    c->graphs = true;
     c->worker.reset(new pf_ctx::Worker());
     c->worker->th = std::thread(worker_main, c);
   }
@@ -2013,6 +2075,17 @@ void pf_destroy(pf_ctx* c) {
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->stream2) (void)hipStreamDestroy(c->stream2);
+  if (c->mg_graph[0][0] || c->mg_graph[0][1] || c->mg_graph[1][0] || c->mg_graph[1][1]) {
+    // no replay may still be queued when its graph goes
+    if (c->stream2) (void)hipStreamSynchronize(c->stream2);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+  }
+  for (int f = 0; f < 2; f++) {
+    for (int t = 0; t < 2; t++)
+      if (c->mg_graph[f][t]) (void)hipGraphExecDestroy(c->mg_graph[f][t]);
+    if (c->capture_stream[f]) (void)hipStreamDestroy(c->capture_stream[f]);
+  }
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->static_device >= 0) {
     // the static workspace is free for the device's next context once the
