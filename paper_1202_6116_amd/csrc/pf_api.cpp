@@ -541,8 +541,9 @@ struct pf_ctx {
   // The coarse part of each V-cycle (restriction from the solver grid down
   // to the coarsest level and back up to level 1) has fixed arguments for a
   // field (0 Poisson, 1 FEM) and vector type ([1]: float): it is captured
-  // once into a graph of kernel nodes and replayed.  graphs: off for static
-  // contexts, with per-launch events, or after a failed capture.
+  // once into a graph of kernel nodes and replayed (with per-launch events,
+  // one pair around each replay).  graphs: off for static contexts and
+  // after a failed capture.
   bool graphs;
   hipStream_t capture_stream[2];
   hipGraphExec_t mg_graph[2][2];
@@ -1061,7 +1062,7 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
   };
   if (e == hipSuccess) {
     const int ti = sizeof(T) == 4 ? 1 : 0;
-    if (c->graphs && c->timing != PF_TIMING_EVENTS && !c->mg_graph[f][ti]) {
+    if (c->graphs && !c->mg_graph[f][ti]) {
       // capture on the field's own stream (the caller's may be the null
       // stream, which cannot capture); nothing runs while capturing
       const hipStream_t keep = st;
@@ -1088,7 +1089,7 @@ hipError_t mg_vcycle(pf_ctx* c, int f, const T* r0, T* z0, CgScalars* sc, double
         (void)hipGetLastError();
       }
     }
-    if (c->graphs && c->timing != PF_TIMING_EVENTS && c->mg_graph[f][ti]) {
+    if (c->graphs && c->mg_graph[f][ti]) {
       hipGraphExec_t ex = c->mg_graph[f][ti];
       e = timed(c, PF_KC_MG, f, k, c->mg_graph_bytes[f][ti], [&] { return hipGraphLaunch(ex, st); });
     } else {

@@ -177,10 +177,10 @@ def test_mg_lateral_256_full_size(pf, oracle_mod, name):
 def test_concurrent_solves_match_sequential_bitwise(pf, precond, precision):
     """The Poisson and FEM solves of a step run on two streams; per-launch
     timing runs them one after the other.  They touch disjoint buffers, so
-    both orders give the same bits.  Without per-launch events the coarse
-    part of every V-cycle is a graph captured once and replayed (every
-    iteration of every solve, with eager launches and synchronisations in
-    between); with them it runs kernel by kernel: the same bits again."""
+    both orders give the same bits.  (The coarse part of every V-cycle is
+    a graph captured once and replayed in all three modes; the static
+    contexts of test_zz_no_alloc launch it kernel by kernel and give the
+    bits of these.)"""
     cfg = mg_cfg(precond=precond, precision=precision, warm_start=2,
                  tol_phi=1e-12 if precision == "fp64" else 1e-9, tol_u=1e-12 if precision == "fp64" else 1e-9)
     print(f"case: concurrent vs sequential {precond} {precision}", flush=True)

@@ -30,8 +30,9 @@ def test_static_workspace_context_matches_caller_workspace(pf):
     """Two static contexts in a row, the second on a smaller film (the
     array keeps the first one's contents), and an FP32 one: each gives the
     bits of a context on a torch-owned workspace (its solves run one after
-    the other, which does not change the results), and making one takes no
-    torch memory."""
+    the other, and its V-cycles launch their coarse part kernel by kernel
+    where the other replays a captured graph: neither changes the results),
+    and making one takes no torch memory."""
     cases = [
         PFConfig(nx=64, ny=48, nz=10, precond="mg", warm_start=2, tol_phi=1e-11, tol_u=1e-11,
                  electrodes=[Electrode(6, 18, 0, 48, 2.0), Electrode(38, 50, 0, 48, -2.0)]),
