@@ -67,9 +67,9 @@ hipError_t launch_refine_update(double* x64, float* x32, const float* d, const f
                                 int64_t n, hipStream_t s);
 hipError_t launch_extrapolate(double* x, const ExtrapRing& ring, int64_t n, hipStream_t s);
 template <typename T, typename S, typename R>
-hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
-                                int with_bc, const T* ghost_top, T phi_bottom, const uint8_t* emask, T* x, R* r,
-                                R* p, R* dz, double* partials, hipStream_t s);
+hipError_t launch_poisson_setup(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const S* P, const S* V, T cdt,
+                                int with_P, int with_bc, const T* ghost_top, T phi_bottom, const uint8_t* emask,
+                                T* x, R* r, R* p, R* dz, double* partials, hipStream_t s);
 template <typename T>
 hipError_t launch_poisson_cg_a(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const T* r, const T* p_old,
                                T* p_new, T* x, const CgScalars* sc, double* partials, int unit_w, hipStream_t s);
@@ -1195,10 +1195,10 @@ pf_status solve_poisson64(pf_ctx* c, int pred, const S* P, const S* V, double cd
   // P (and V) read when with_P; x read; r, p written
   const double sb = (with_P ? 3.0 * c->dims.N * sizeof(S) * (V ? 2 : 1) : 0.0) + 3.0 * d.N * 8;
   PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, sb, [&] {
-    return launch_poisson_setup<double, S, double>(d, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, emask(c),
+    return launch_poisson_setup<double, S, double>(d, c->tm_p, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, emask(c),
                                                    x, r, pb[0], nullptr, part, strm(c));
   }));
-  PF_HIP(c, reduce(c, part, c->nblocks_p, 3, 0, kRedSetup, tol, 0, nullptr));
+  PF_HIP(c, reduce(c, part, c->tm_p.nblocks, 3, 0, kRedSetup, tol, 0, nullptr));
   if (mg_on(c, 0)) PF_HIP(c, mg_setup<double>(c, 0, r));
   CgScalars h;
   PF_TRY(run_cg<double>(c, 0, c->pred[pred], x, pb, d.N, poisson_iteration<double>(c, cf, r, pb, x, tol), &h,
@@ -1249,7 +1249,7 @@ pf_status solve_refined(pf_ctx* c, bool fem, const S* P, const S* V, double cdt,
   const Dims& d = fem ? c->dims : c->dims_p;
   const int which = fem ? 1 : 0;
   const int64_t n = fem ? 3 * d.N : d.N;
-  const int setup_blocks = fem ? c->tm_f.nblocks : c->nblocks_p;
+  const int setup_blocks = fem ? c->tm_f.nblocks : c->tm_p.nblocks;
   const Coefs<double> cf64 = make_coefs<double>(c);
   const Coefs<float> cf32 = make_coefs<float>(c);
   const FemTables* tb = at<FemTables>(c, c->lay.tables);
@@ -1287,7 +1287,7 @@ pf_status solve_refined(pf_ctx* c, bool fem, const S* P, const S* V, double cdt,
       }));
     } else {
       PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, n3 * sv + (double)d.N * (8 + 3 * 4), [&] {
-        return launch_poisson_setup<double, S, float>(d, cf64, P, V, cdt, 1, 1, at<double>(c, c->lay.ghost64),
+        return launch_poisson_setup<double, S, float>(d, c->tm_p, cf64, P, V, cdt, 1, 1, at<double>(c, c->lay.ghost64),
                                                           c->cfg.phi_bottom, emask(c), x64, r, pb[0], dz, part,
                                                           strm(c));
       }));

@@ -112,6 +112,7 @@ enum CgDone { kRunning = 0, kConverged = 1, kMaxIt = 2, kNonFinite = 3 };
 // cut into nkz chunks of kz planes; one block per (column, chunk).
 struct TileMap {
   int ty, ntx, nty, kz, nkz, nblocks;
+  int gy;  // tile rows per group of the block order (see tile_coord)
 };
 
 // Polynomial extrapolation of a solution to the next step from the current

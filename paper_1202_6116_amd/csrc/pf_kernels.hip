@@ -107,12 +107,22 @@ struct TileCoord {
   int i0, j0, k0, k1, lid;
 };
 
+// Within a z-chunk, tiles go in groups of gy tile rows: the rows of a group
+// fastest, then x, then the groups, so that the blocks that share a y halo
+// row start one after the other (x neighbours gy apart) and read it while it
+// is still in the XCD's L2; the last group may hold fewer rows.
 __device__ __forceinline__ TileCoord tile_coord(const Dims& d, const TileMap& tm) {
   const int lid = logical_block(tm.nblocks);
   TileCoord t;
-  const int tx = lid % tm.ntx;
-  const int ty = (lid / tm.ntx) % tm.nty;
-  const int kc = lid / (tm.ntx * tm.nty);
+  const int cols = tm.ntx * tm.nty;
+  const int kc = lid / cols;
+  const int c = lid - kc * cols;
+  const int gsz = tm.gy * tm.ntx;
+  const int g = c / gsz;
+  const int r = c - g * gsz;
+  const int rows = min(tm.gy, tm.nty - g * tm.gy);
+  const int tx = r / rows;
+  const int ty = g * tm.gy + (r - tx * rows);
   t.i0 = tx * kBX;
   t.j0 = ty * tm.ty;
   t.k0 = kc * tm.kz;
@@ -426,80 +436,96 @@ __device__ __forceinline__ PlaneEps<T> plane_eps(const Dims& d, const Coefs<T>& 
 // b from Pp = P + cdt V (V may be null) and the ghost planes; r = b - A x;
 // p = r / diag; partial (b.b, r.z, r.r).  T: arithmetic and x; S: storage
 // of P and V; R: storage of r and p (FP32 for the inner solve of a
-// refinement sweep, which also clears its correction dz).
+// refinement sweep, which also clears its correction dz).  Each block
+// marches a 64 x 4 tile up its z-chunk: the values of its own column at the
+// planes below and above (x and Pp_z) are carried in registers, so every
+// plane is read once; the in-plane neighbours come from the plane in hand.
 template <typename T, typename S, typename R>
 __global__ __launch_bounds__(kThreads) void poisson_setup_kernel(
-    Dims d, Coefs<T> cf, const S* __restrict__ P, const S* __restrict__ V, T cdt, int with_P, int with_bc,
-    const T* __restrict__ ghost_top, T phi_bottom, const uint8_t* __restrict__ emask, T* __restrict__ x,
-    R* __restrict__ r, R* __restrict__ p, R* __restrict__ dz, double* partials) {
-  const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y, k = blockIdx.z;
+    Dims d, TileMap tm, Coefs<T> cf, const S* __restrict__ P, const S* __restrict__ V, T cdt, int with_P,
+    int with_bc, const T* __restrict__ ghost_top, T phi_bottom, const uint8_t* __restrict__ emask,
+    T* __restrict__ x, R* __restrict__ r, R* __restrict__ p, R* __restrict__ dz, double* partials) {
+  const TileCoord tc = tile_coord(d, tm);
+  const int i = tc.i0 + threadIdx.x, j = tc.j0 + threadIdx.y;
   double v[3] = {0.0, 0.0, 0.0};
   if (i < d.nx && j < d.ny) {
     const int64_t Nf = d.Nf, pl = d.plane;
     const int64_t col = i + (int64_t)d.nx * j;
-    const int64_t n = col + pl * k;
     const int64_t cxp = wrap(i + 1, d.nx) + (int64_t)d.nx * j, cxm = wrap(i - 1, d.nx) + (int64_t)d.nx * j;
     const int64_t cyp = i + (int64_t)d.nx * wrap(j + 1, d.ny), cym = i + (int64_t)d.nx * wrap(j - 1, d.ny);
-    const int64_t nxp = cxp + pl * k, nxm = cxm + pl * k, nyp = cyp + pl * k, nym = cym + pl * k;
-    const bool up = k + 1 < d.nz, dn = k > 0;
     // electrode nodes of the open top (Dirichlet, first air plane)
     auto is_el = [&](int kk, int64_t c) { return emask != nullptr && kk == d.nzf && emask[c] != 0; };
     auto dval = [&](int64_t c) -> T { return with_bc ? ghost_top[c] : (T)0; };
-    if (is_el(k, col)) {
-      x[n] = dval(col);
-      r[n] = 0;
-      p[n] = 0;
-      if (dz) dz[n] = 0;
-    } else {
-      auto pp = [&](int c, int64_t m) -> T { return (T)P[c * Nf + m] + (V ? cdt * (T)V[c * Nf + m] : (T)0); };
-      T b = 0;
-      if (with_P) {
-        const T dx = k < d.nzf ? pp(0, nxp) - pp(0, nxm) : (T)0;
-        const T dy = k < d.nzf ? pp(1, nyp) - pp(1, nym) : (T)0;
-        const T zp = k + 1 < d.nzf ? pp(2, n + pl) : (T)0;
-        const T zm = (dn && k - 1 < d.nzf) ? pp(2, n - pl) : (T)0;
-        b = -(dx + dy + (zp - zm)) * cf.inv_2h;
-      }
-      const PlaneEps<T> e = plane_eps(d, cf, k);
-      if (with_bc) {
-        if (k == 0) b += e.dn * phi_bottom;
-        if (!cf.open && k == d.nz - 1) b += e.up * ghost_top[col];
-        if (cf.open) {
-          if (is_el(k, cxp)) b += e.xy * ghost_top[cxp];
-          if (is_el(k, cxm)) b += e.xy * ghost_top[cxm];
-          if (is_el(k, cyp)) b += e.xy * ghost_top[cyp];
-          if (is_el(k, cym)) b += e.xy * ghost_top[cym];
-          if (is_el(k + 1, col)) b += e.up * ghost_top[col];
-          if (is_el(k - 1, col)) b += e.dn * ghost_top[col];
-        }
-      }
-      T Ax;
-      if (!cf.open) {
-        T s = x[nxp] + x[nxm] + x[nyp] + x[nym];
-        if (up) s += x[n + pl];
-        if (dn) s += x[n - pl];
-        Ax = cf.eps_over_h2 * (6 * x[n] - s);
+    auto pp = [&](int c, int64_t m) -> T { return (T)P[c * Nf + m] + (V ? cdt * (T)V[c * Nf + m] : (T)0); };
+    // own column: Pp_z of the film planes and x of planes k - 1, k, k + 1
+    // (x is not read at electrode nodes: this kernel writes it there)
+    auto pz = [&](int kk) -> T { return with_P && kk >= 0 && kk < d.nzf ? pp(2, col + pl * kk) : (T)0; };
+    auto xcol = [&](int kk) -> T {
+      return kk >= 0 && kk < d.nz && !is_el(kk, col) ? x[col + pl * kk] : (T)0;
+    };
+    const int k0 = tc.k0;
+    T pz_m = pz(k0 - 1), pz_c = pz(k0);
+    T x_m = xcol(k0 - 1), x_c = xcol(k0);
+    for (int k = k0; k < tc.k1; k++) {
+      const int64_t n = col + pl * k;
+      const bool up = k + 1 < d.nz, dn = k > 0;
+      const T pz_p = pz(k + 1);
+      const T x_p = xcol(k + 1);
+      if (is_el(k, col)) {
+        x[n] = dval(col);
+        r[n] = 0;
+        p[n] = 0;
+        if (dz) dz[n] = 0;
       } else {
-        // electrode nodes enter through b; their x is not read here (this
-        // kernel writes it)
-        auto xu = [&](int kk, int64_t c, int64_t m) -> T { return is_el(kk, c) ? (T)0 : x[m]; };
-        const T sxy = xu(k, cxp, nxp) + xu(k, cxm, nxm) + xu(k, cyp, nyp) + xu(k, cym, nym);
-        const T xup = up ? xu(k + 1, col, n + pl) : (T)0;
-        const T xdn = dn ? xu(k - 1, col, n - pl) : (T)0;
-        const T xc = x[n];
-        Ax = e.xy * (4 * xc - sxy) + e.up * (xc - xup) + e.dn * (xc - xdn);
+        const int64_t nxp = cxp + pl * k, nxm = cxm + pl * k, nyp = cyp + pl * k, nym = cym + pl * k;
+        T b = 0;
+        if (with_P) {
+          const T dx = k < d.nzf ? pp(0, nxp) - pp(0, nxm) : (T)0;
+          const T dy = k < d.nzf ? pp(1, nyp) - pp(1, nym) : (T)0;
+          b = -(dx + dy + (pz_p - pz_m)) * cf.inv_2h;
+        }
+        const PlaneEps<T> e = plane_eps(d, cf, k);
+        if (with_bc) {
+          if (k == 0) b += e.dn * phi_bottom;
+          if (!cf.open && k == d.nz - 1) b += e.up * ghost_top[col];
+          if (cf.open) {
+            if (is_el(k, cxp)) b += e.xy * ghost_top[cxp];
+            if (is_el(k, cxm)) b += e.xy * ghost_top[cxm];
+            if (is_el(k, cyp)) b += e.xy * ghost_top[cyp];
+            if (is_el(k, cym)) b += e.xy * ghost_top[cym];
+            if (is_el(k + 1, col)) b += e.up * ghost_top[col];
+            if (is_el(k - 1, col)) b += e.dn * ghost_top[col];
+          }
+        }
+        T Ax;
+        if (!cf.open) {
+          T s = x[nxp] + x[nxm] + x[nyp] + x[nym];
+          if (up) s += x_p;
+          if (dn) s += x_m;
+          Ax = cf.eps_over_h2 * (6 * x_c - s);
+        } else {
+          auto xu = [&](int kk, int64_t c, int64_t m) -> T { return is_el(kk, c) ? (T)0 : x[m]; };
+          const T sxy = xu(k, cxp, nxp) + xu(k, cxm, nxm) + xu(k, cyp, nyp) + xu(k, cym, nym);
+          const T xup = up ? x_p : (T)0;
+          const T xdn = dn ? x_m : (T)0;
+          Ax = e.xy * (4 * x_c - sxy) + e.up * (x_c - xup) + e.dn * (x_c - xdn);
+        }
+        const T rr = b - Ax;
+        const T z = rr * e.w;
+        r[n] = (R)rr;
+        p[n] = (R)z;
+        if (dz) dz[n] = 0;
+        v[0] += (double)b * b;
+        v[1] += (double)rr * z;
+        v[2] += (double)rr * rr;
       }
-      const T rr = b - Ax;
-      const T z = rr * e.w;
-      r[n] = (R)rr;
-      p[n] = (R)z;
-      if (dz) dz[n] = 0;
-      v[0] = (double)b * b;
-      v[1] = (double)rr * z;
-      v[2] = (double)rr * rr;
+      pz_m = pz_c;
+      pz_c = pz_p;
+      x_m = x_c;
+      x_c = x_p;
     }
   }
-  block_partials<3, kThreads>(v, partials, node_block_id());
+  block_partials<3, kThreads>(v, partials, tc.lid);
 }
 
 // Iteration kernel A: p_new = z + beta p_old on the tile and its halo, q =
@@ -2475,6 +2501,12 @@ __global__ __launch_bounds__(kThreads, 3) void force_kernel(
   T w0[6] = {0, 0, 0, 0, 0, 0}, w1[6] = {0, 0, 0, 0, 0, 0};  // z-sums of planes k and k + 1
   T pdn[3] = {0, 0, 0};                                        // Pp of the plane below, own column
   const int k0 = tc.k0;
+  // phi of the own column at plane k - 1 (the bottom boundary value below
+  // the grid), carried up the march from the plane's in-plane loads in a
+  // per-thread LDS slot (no register is free across the elastic term)
+  const bool elec = (cf.terms & kElec) != 0;
+  __shared__ T phm[TY][kBX];
+  if (valid && elec) phm[ly][lx] = k0 > 0 ? phi[col + pl * (k0 - 1)] : cf.phi_bottom;
   // prologue: sources k0 - 1 (if any) and k0
   if (k0 > 0) {
     stage_fetch<TY>(st, d, tc.i0, tc.j0, k0 - 1, fetch);
@@ -2547,12 +2579,12 @@ __global__ __launch_bounds__(kThreads, 3) void force_kernel(
           F[c] -= cf.G * cf.inv_h2 * lap;
         }
       }
-      if (cf.terms & kElec) {
+      if (elec) {
         const T zp = (k + 1 < d.nzp) ? phi[n + pl] : ghost_top[col];
-        const T zm = (k > 0) ? phi[n - pl] : cf.phi_bottom;
         F[0] += (phi[nbr(d, i, j, k, 1, 0, 0)] - phi[nbr(d, i, j, k, -1, 0, 0)]) * cf.inv_2h;
         F[1] += (phi[nbr(d, i, j, k, 0, 1, 0)] - phi[nbr(d, i, j, k, 0, -1, 0)]) * cf.inv_2h;
-        F[2] += (zp - zm) * cf.inv_2h;
+        F[2] += (zp - phm[ly][lx]) * cf.inv_2h;
+        phm[ly][lx] = phi[n];
       }
 #pragma unroll
       for (int c = 0; c < 3; c++) F[c] *= -cf.L;
@@ -2914,6 +2946,12 @@ TileMap make_tile_map(const Dims& d, int ty, int target) {
   t.kz = (int)kz;
   t.nkz = (d.nz + t.kz - 1) / t.kz;
   t.nblocks = (int)(cols * t.nkz);
+  int gy = 4;
+  if (const char* env = getenv("PF_TILE_GY")) {
+    const long v = strtol(env, nullptr, 10);
+    if (v >= 1 && v <= 64) gy = (int)v;
+  }
+  t.gy = gy < t.nty ? gy : t.nty;
   return t;
 }
 
@@ -2975,11 +3013,11 @@ hipError_t launch_refine_update(double* x64, float* x32, const float* d, const f
 }
 
 template <typename T, typename S, typename R>
-hipError_t launch_poisson_setup(const Dims& d, const Coefs<T>& cf, const S* P, const S* V, T cdt, int with_P,
-                                int with_bc, const T* ghost_top, T phi_bottom, const uint8_t* emask, T* x, R* r,
-                                R* p, R* dz, double* partials, hipStream_t s) {
-  poisson_setup_kernel<T, S, R><<<node_grid(d), node_block(), 0, s>>>(d, cf, P, V, cdt, with_P, with_bc, ghost_top,
-                                                                      phi_bottom, emask, x, r, p, dz, partials);
+hipError_t launch_poisson_setup(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const S* P, const S* V, T cdt,
+                                int with_P, int with_bc, const T* ghost_top, T phi_bottom, const uint8_t* emask,
+                                T* x, R* r, R* p, R* dz, double* partials, hipStream_t s) {
+  poisson_setup_kernel<T, S, R><<<tm.nblocks, node_block(), 0, s>>>(d, tm, cf, P, V, cdt, with_P, with_bc, ghost_top,
+                                                                    phi_bottom, emask, x, r, p, dz, partials);
   return hipGetLastError();
 }
 
@@ -3315,9 +3353,9 @@ PF_INSTANTIATE_MG(double)
 PF_INSTANTIATE_MG(float)
 
 #define PF_INSTANTIATE_SETUP(T, S, R)                                                                            \
-  template hipError_t launch_poisson_setup<T, S, R>(const Dims&, const Coefs<T>&, const S*, const S*, T, int,    \
-                                                    int, const T*, T, const uint8_t*, T*, R*, R*, R*, double*,   \
-                                                    hipStream_t);                                                \
+  template hipError_t launch_poisson_setup<T, S, R>(const Dims&, const TileMap&, const Coefs<T>&, const S*,      \
+                                                    const S*, T, int, int, const T*, T, const uint8_t*, T*, R*,  \
+                                                    R*, R*, double*, hipStream_t);                               \
   template hipError_t launch_fem_setup<T, S, R>(const Dims&, const TileMap&, const Coefs<T>&, const FemTables*,   \
                                                 bool, const S*, const S*, T, const T*, T*, R*, R*, R*, R*, T*,    \
                                                 double*, hipStream_t);
