@@ -1862,8 +1862,16 @@ namespace {
 // Tile grids of 64 x 4-node tiles sized to what stays resident at once, four
 // 256-thread blocks per CU (the FEM iteration kernels are capped at 128
 // VGPRs for that; their FP64 ring takes 28.5 KB of LDS).
-TileMap poisson_tiles(const pf_config&, const Dims& d) { return make_tile_map(d, kBY, 1024); }
-TileMap fem_tiles(const pf_config&, const Dims& d) { return make_tile_map(d, kBY, 1024); }
+// Tiles of the solver-grid kernels: z-chunks short enough for about 4096
+// blocks (16 per CU: the small kernels keep 8 resident) while a chunk keeps
+// at least 16 planes (its two halo planes cost at most 1/8 more reads);
+// otherwise chunks for about 1024 blocks.
+TileMap solver_tiles(const Dims& d) {
+  const TileMap t = make_tile_map(d, kBY, 4096);
+  return t.kz >= 16 ? t : make_tile_map(d, kBY, 1024);
+}
+TileMap poisson_tiles(const pf_config&, const Dims& d) { return solver_tiles(d); }
+TileMap fem_tiles(const pf_config&, const Dims& d) { return solver_tiles(d); }
 int partial_slots(const pf_config& c) {
   const Dims d = film_dims(c), dp = potential_dims(c);
   return std::max(std::max(node_blocks(d), node_blocks(dp)),
