@@ -2,8 +2,8 @@
 discrete adjoint over a prefix of the trajectory (written by
 tests/golden/make_adjoint_128_oracle.py, which calls only the oracle): J,
 dJ/dV_e, dJ/da1 and dJ/dP0 on sampled columns.  The GPU runs the same case
-through the differentiable layer with checkpoints (two segments, one
-recomputed).  The forward solves run to 1e-12 and the adjoint solves to
+through the differentiable layer with checkpoints (two segments of half the
+prefix each, the first recomputed).  The forward solves run to 1e-12 and the adjoint solves to
 1e-13 on the oracle's side (to the preset's 1e-12 on the GPU's, with other
 preconditioners and warm starts), so two correct runs may differ by up to
 kappa * 1e-12, ~1e-8 with kappa ~1e4 for the FEM operator of this film; the
@@ -42,10 +42,10 @@ def pf():
 
 
 @pytest.mark.skipif(not prefixes(), reason="the oracle's adjoint of the 128x128x32 case is not in tests/golden")
+@pytest.mark.parametrize("nsteps", prefixes())
 @pytest.mark.parametrize("precond", ["mg", "jacobi"])
-def test_adjoint_128_matches_cpu_adjoint(pf, precond):
+def test_adjoint_128_matches_cpu_adjoint(pf, precond, nsteps):
     from paper_1202_6116_amd.autograd import tdgl_steps
-    nsteps = prefixes()[-1]
     ref = np.load(os.path.join(GOLDEN, f"adjoint_128x128x32_oracle_steps{nsteps}.npz"))
     assert json.loads(str(ref["meta"]))["workload"] == "adjoint_128x128x32"
     w = workloads()["adjoint_128x128x32"]
