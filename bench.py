@@ -242,6 +242,42 @@ def micron_adjoint_leg(pf, torch, w):
     return out
 
 
+def ablation_leg(pf, torch, w, steps=20, warmup=5):
+    """The paper's two solver-time ablations on one film, each from the same
+    start, `steps` steps timed after `warmup`: the initial guess of the solves
+    (zero, the previous step's solution as the paper does, the extrapolation
+    of earlier solutions), and the non-local fields refreshed every step or
+    every 5 steps with the paper's guess; with the paper's solver (Jacobi
+    PCG) and with the multigrid one."""
+    from paper_1202_6116_amd.workloads import initial_polarisation
+    runs = {}
+    for precond in ("jacobi", "mg"):
+        for name, kw in (("zero_guess", dict(warm_start=0)), ("previous_solution", dict(warm_start=1)),
+                         ("extrapolated", dict(warm_start=2)),
+                         ("previous_solution_nonlocal_every_5", dict(warm_start=1, nonlocal_every=5))):
+            cfg = w.cfg.replace(precond=precond, **kw)
+            ctx = pf.Context(cfg, "cuda:0")
+            ctx.set_state(torch.from_numpy(initial_polarisation(w)).to(device="cuda:0", dtype=ctx.state_dtype))
+            ctx.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ctx.step(steps)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            runs[f"{precond}/{name}"] = {"ms_per_step": round(1e3 * secs / steps, 3), "cg_iters_per_solve": iters(st),
+                                        "solves_per_step": round((st["solves_phi"] + st["solves_u"]) / steps, 2)}
+            del ctx
+    out = {"workload": w.name, "steps": steps, "warmup": warmup, "runs": runs}
+    for precond in ("jacobi", "mg"):
+        r = {k.split("/", 1)[1]: v["ms_per_step"] for k, v in runs.items() if k.startswith(precond + "/")}
+        out[f"{precond}_previous_vs_zero_guess_speedup"] = round(r["zero_guess"] / r["previous_solution"], 2)
+        out[f"{precond}_extrapolated_vs_previous_speedup"] = round(r["previous_solution"] / r["extrapolated"], 2)
+        out[f"{precond}_nonlocal_every_5_speedup"] = round(
+            r["previous_solution"] / r["previous_solution_nonlocal_every_5"], 2)
+    torch.cuda.empty_cache()
+    return out
+
+
 def precision_leg(pf, torch, w, steps=10, warmup=5,
                   runs=(("fp64", 1e-9), ("fp64", 1e-7), ("fp64", 1e-6), ("fp64", 1e-5),
                         ("fp32_refine", 1e-9), ("fp32_refine", 1e-7), ("fp32_refine", 1e-6),
@@ -308,6 +344,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 128x128x32 adjoint leg")
     ap.add_argument("--no-micron-adjoint", action="store_true", help="skip the 100-step micron adjoint leg")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32+refinement vs FP64 leg")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the initial-guess and non-local-every-5 ablations on the 256x256x64 film")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 4 times (reference for HBM counters)")
@@ -361,6 +399,9 @@ def main():
             del c
             torch.cuda.empty_cache()
             legs["jacobi"] = {"config": config_of(jw), **r}
+        if not args.no_ablation:
+            progress("leg ablations")
+            legs["ablations"] = ablation_leg(pf, torch, prepared("lateral_256x256x64"))
         if not args.no_precision:
             progress("leg precision")
             legs["precision"] = precision_leg(pf, torch, prepared("micron_1024x1024x96"))
