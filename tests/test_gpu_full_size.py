@@ -1,6 +1,7 @@
-"""The FP32 + FP64-refinement films at their full sizes (512x512x128 and the
-micron-scale 1024x1024x96), in the launch configuration that bench.py times
-(multigrid-preconditioned CG), against the FP64 oracle.
+"""The films at their full sizes, in the launch configuration that bench.py
+times (multigrid-preconditioned CG), against the FP64 oracle: the FP64
+micron-scale film (1024x1024x96, the headline) and the FP32 +
+FP64-refinement films (512x512x128 and the micron film).
 
 The Poisson solution is checked on the whole grid with the oracle's own
 residual test.  The oracle's FEM right-hand side takes minutes at these
@@ -62,12 +63,17 @@ def pf():
     return m
 
 
-@pytest.mark.parametrize("name", ["lateral_512x512x128_fp32", "micron_1024x1024x96_fp32"])
-def test_fp32_full_size_solves_and_force(pf, oracle_mod, name):
+# force bars: FP32 force arithmetic, or FP64 with another order of the sums
+FORCE_BAR = {"fp32_refine": 1e-6, "fp64": 1e-10}
+
+
+@pytest.mark.parametrize("name", ["micron_1024x1024x96", "lateral_512x512x128_fp32", "micron_1024x1024x96_fp32"])
+def test_full_size_solves_and_force(pf, oracle_mod, name):
     w = workloads()[name]
     cfg = w.cfg.replace(precond="mg")
-    print(f"case: {name} full size, FP32 + refinement, multigrid", flush=True)
-    P32 = initial_polarisation(w).astype(np.float32)
+    fp32 = cfg.precision != "fp64"
+    print(f"case: {name} full size, {cfg.precision}, multigrid", flush=True)
+    P32 = initial_polarisation(w).astype(np.float32 if fp32 else np.float64)
     ctx = pf.Context(cfg)
     Pd = dev(P32)
     phi, sp = ctx.solve_phi(Pd)
@@ -103,10 +109,11 @@ def test_fp32_full_size_solves_and_force(pf, oracle_mod, name):
         f = inner(ow.fem_rhs(Pw))
         res = f - inner(ow.fem_apply(uw))
         wrel = float(np.linalg.norm(res) / np.linalg.norm(f))
-        # force from the same P, phi and u, evaluated in FP32 on the GPU
+        # force from the same P, phi and u, evaluated on the GPU in the
+        # film's precision
         Fo = inner(ow.force(Pw, phiw, uw))
         ferr = float(np.abs(inner(cut(F, x0, y0)) - Fo).max() / np.abs(Fo).max())
         print(f"  window ({x0}, {y0}) volts {None if e is None else e.volts}: FEM relres {wrel:.2e}, "
               f"force rel err {ferr:.2e}", flush=True)
         assert wrel <= 10 * cfg.tol_u
-        assert ferr < 1e-6
+        assert ferr < FORCE_BAR[cfg.precision]

@@ -6,7 +6,7 @@ import numpy as np
 
 from paper_1202_6116_amd.workloads import Electrode, PFConfig, domain_polarisation, random_field
 
-import test_gpu_full_size_fp32 as fs
+import test_gpu_full_size as fs
 
 
 def test_windowed_oracle_equals_whole_film(oracle_mod):
