@@ -317,7 +317,14 @@ MgHierarchy build_generic(int nx, int ny, int nz, int nc, bool top_fixed, std::v
       if (op.active(k))
         for (int c = 0; c < nc; c++) L.dinv[(size_t)k * nc + c] = 1.0 / op.diag(k, c);
     const double lam = jacobi_lambda_max(L.nz, nc, top_fixed, &h.tables[l]);
-    L.omega = 4.0 / (3.0 * 1.05 * lam);
+    // damping of the Jacobi smoother: 4 / (3 lambda_max(D^-1 A)) is the
+    // classic choice for smoothing alone; as the preconditioner of CG the
+    // cycle converges fastest at about 1.3 times it (the solver-grid films:
+    // 11% fewer iterations; at 1.5 times, where omega lambda_max nears 2 and
+    // the cycle nears indefiniteness, it is slower than at 1), with the
+    // estimate of lambda_max taken 5% high.  omega lambda_max stays at 1.65,
+    // below 2, so the symmetric cycle stays positive definite.
+    L.omega = 1.3 * 4.0 / (3.0 * 1.05 * lam);
   }
   // Coarsest level: dense inverse over its unknowns, or damped Jacobi sweeps
   // when it is too large for that.
