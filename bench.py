@@ -34,8 +34,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "TDGL cell-steps/s incl. Poisson+FEM solves; HBM GB/s vs peak; adjoint/fwd ratio"
-WARM_START_NAMES = {0: "zero", 1: "previous solution", 2: "extrapolated from earlier solutions"}
+WARM_START_NAMES = {0: "zero", 1: "previous solution", 2: "extrapolated from earlier solutions",
+                    3: "extrapolated from earlier solutions, order chosen per refresh"}
 HBM_PEAK_GBS = 8000.0
+# highest extrapolation order of the adaptive warm start (the orders that
+# predict best fall from ~8 early in a switching run to ~4 late in it)
+ADAPTIVE_MAX_ORDER = 8
 TARGET_FRAC = 0.60
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and then
@@ -140,7 +144,7 @@ def config_of(w):
     return {"workload": w.name, "grid": [cfg.nx, cfg.ny, cfg.nz], "cells": cfg.nodes, "integrator": cfg.integrator,
             "tol_phi": cfg.tol_phi, "tol_u": cfg.tol_u, "electrodes": len(cfg.electrodes), "init": w.init,
             "seed": w.seed, "initial_guess": WARM_START_NAMES[int(cfg.warm_start)],
-            "extrap_order": cfg.extrap_order if cfg.warm_start == 2 else None,
+            "extrap_order": cfg.extrap_order if cfg.warm_start >= 2 else None,
             "nonlocal_every": max(1, cfg.nonlocal_every), "precond": cfg.precond, "precision": cfg.precision}
 
 
@@ -161,8 +165,12 @@ def cpu_baseline(w, side=48, steps=6, warmup=2):
     sx, sy = min(cfg.nx, side), min(cfg.ny, side)
     # two strips 16 nodes wide at +-2 V centred at sx/4 and 3 sx/4, full length in y
     strips = [Electrode(sx // 4 - 8, sx // 4 + 8, 0, sy, 2.0), Electrode(3 * sx // 4 - 8, 3 * sx // 4 + 8, 0, sy, -2.0)]
+    # the oracle's own warm starts: the previous solution or its extrapolation
+    # of fixed order (order 4 when the GPU run chooses the order per refresh)
+    ws = min(int(cfg.warm_start), 2)
     scfg = cfg.replace(nx=sx, ny=sy, electrodes=strips if cfg.electrodes else [], precision="fp64",
-                       precond="jacobi")
+                       precond="jacobi", warm_start=ws,
+                       extrap_order=4 if int(cfg.warm_start) == 3 else cfg.extrap_order)
     o = Oracle(scfg)
     P = domain_polarisation(scfg, w.seed)
     V, phi, u, _ = o.set_state(P)
@@ -181,7 +189,8 @@ def cpu_baseline(w, side=48, steps=6, warmup=2):
     return {
         "value": scfg.nodes * steps / t_sample, "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
         "sample": (f"{steps} predictor-corrector steps of the FP64 oracle (Jacobi CG to tol {cfg.tol_phi:g}/"
-                   f"{cfg.tol_u:g}, warm start {WARM_START_NAMES[int(scfg.warm_start)]}: Poisson "
+                   f"{cfg.tol_u:g}, warm start {WARM_START_NAMES[int(scfg.warm_start)]}"
+                   f"{f' of order {scfg.extrap_order}' if scfg.warm_start == 2 else ''}: Poisson "
                    f"{st['iters_phi']} it, FEM {st['iters_u']} it in all) on a {sx}x{sy}x{cfg.nz} slab of the "
                    f"workload with two strips at sx/4 and 3sx/4, after an untimed set_state and {warmup} untimed "
                    f"steps, {t_sample:.1f} s; cells/s of the slab"),
@@ -259,14 +268,16 @@ def ablation_leg(pf, torch, w, steps=20, warmup=5):
     """The paper's two solver-time ablations on one film, each from the same
     start, `steps` steps timed after `warmup`: the initial guess of the solves
     (zero, the previous step's solution as the paper does, the extrapolation
-    of earlier solutions), and the non-local fields refreshed every step or
+    of earlier solutions of order 4 and of the order chosen per refresh),
+    and the non-local fields refreshed every step or
     every 5 steps with the paper's guess; with the paper's solver (Jacobi
     PCG) and with the multigrid one."""
     from paper_1202_6116_amd.workloads import initial_polarisation
     runs = {}
     for precond in ("jacobi", "mg"):
         for name, kw in (("zero_guess", dict(warm_start=0)), ("previous_solution", dict(warm_start=1)),
-                         ("extrapolated", dict(warm_start=2)),
+                         ("extrapolated", dict(warm_start=2, extrap_order=4)),
+                         ("extrapolated_adaptive", dict(warm_start=3, extrap_order=ADAPTIVE_MAX_ORDER)),
                          ("previous_solution_nonlocal_every_5", dict(warm_start=1, nonlocal_every=5))):
             cfg = w.cfg.replace(precond=precond, **kw)
             ctx = pf.Context(cfg, "cuda:0")
@@ -285,6 +296,7 @@ def ablation_leg(pf, torch, w, steps=20, warmup=5):
         r = {k.split("/", 1)[1]: v["ms_per_step"] for k, v in runs.items() if k.startswith(precond + "/")}
         out[f"{precond}_previous_vs_zero_guess_speedup"] = round(r["zero_guess"] / r["previous_solution"], 2)
         out[f"{precond}_extrapolated_vs_previous_speedup"] = round(r["previous_solution"] / r["extrapolated"], 2)
+        out[f"{precond}_adaptive_vs_extrapolated_speedup"] = round(r["extrapolated"] / r["extrapolated_adaptive"], 2)
         out[f"{precond}_nonlocal_every_5_speedup"] = round(
             r["previous_solution"] / r["previous_solution_nonlocal_every_5"], 2)
     torch.cuda.empty_cache()
@@ -339,12 +351,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="micron_1024x1024x96", choices=sorted(all_workloads()))
-    ap.add_argument("--warm-start", type=int, default=2, choices=(0, 1, 2),
+    ap.add_argument("--warm-start", type=int, default=3, choices=(0, 1, 2, 3),
                     help="initial guess of each solve: 0 zero, 1 previous solution, 2 extrapolated from the "
-                         "last solutions (default 2)")
+                         "last solutions, 3 extrapolated with the order chosen per refresh (default 3)")
     ap.add_argument("--extrap-order", type=int, default=None,
-                    help="with --warm-start 2: number of earlier solutions the polynomial goes through "
-                         "(0..8; default: the workload's)")
+                    help="with --warm-start 2 or 3: number of earlier solutions the polynomial goes through, "
+                         "for 3 the highest order tried (0..8; default: the workload's for 2, "
+                         f"{ADAPTIVE_MAX_ORDER} for 3)")
     ap.add_argument("--precond", choices=("jacobi", "mg"), default="mg",
                     help="preconditioner of both solves: mg (multigrid V-cycle, default) or jacobi (the oracle's)")
     ap.add_argument("--nonlocal-every", type=int, default=None,
@@ -377,6 +390,8 @@ def main():
         cfg = w.cfg.replace(warm_start=args.warm_start, precond=args.precond)
         if args.extrap_order is not None:
             cfg = cfg.replace(extrap_order=args.extrap_order)
+        elif args.warm_start == 3:
+            cfg = cfg.replace(extrap_order=ADAPTIVE_MAX_ORDER)
         if args.nonlocal_every is not None:
             cfg = cfg.replace(nonlocal_every=args.nonlocal_every)
         w.cfg = cfg.replace(**kw)
@@ -406,7 +421,10 @@ def main():
             r.pop("kernel_classes", None)
             legs["lateral"] = {"config": config_of(lw), **r}
         if not args.no_jacobi and args.precond != "jacobi":
-            jw = prepared(args.workload, precond="jacobi")
+            # the paper's solver with the order-4 extrapolation: the adaptive
+            # order scores the rough part of the error, which Jacobi-PCG removes
+            # fastest, and is slower there
+            jw = prepared(args.workload, precond="jacobi", warm_start=2, extrap_order=4)
             progress(f"leg {jw.name} jacobi")
             r, c = measure(pf, torch, jw, 3, 2, 2)
             del c
@@ -421,7 +439,11 @@ def main():
         if not args.no_micron_adjoint:
             progress("leg micron adjoint")
             try:
-                legs["micron_adjoint"] = micron_adjoint_leg(pf, torch, prepared("micron_1024x1024x96_fp32"))
+                # extrapolation up to order 4: the adjoint's rings of psi and du
+                # hold extrap_order solutions each, and the run keeps 100 steps
+                # of checkpoints besides
+                legs["micron_adjoint"] = micron_adjoint_leg(
+                    pf, torch, prepared("micron_1024x1024x96_fp32", extrap_order=4))
             except Exception as e:  # a leg: report, keep the headline
                 legs["micron_adjoint"] = {"error": repr(e)}
         if not args.no_adjoint:

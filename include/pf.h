@@ -123,11 +123,17 @@ typedef struct {
   int32_t warm_start;           /* 0: solves start from zero; 1: from the previous
                                    solution (the paper's warm start); 2: from the
                                    polynomial extrapolation to the next step of the
-                                   last solutions (see extrap_order) */
+                                   last solutions (see extrap_order); 3: as 2, the
+                                   order of each refresh (0..extrap_order) chosen
+                                   as the one whose extrapolation from the solutions
+                                   before the newest came closest to the newest
+                                   (squared second differences along x of the error
+                                   on a fixed 1/64 sample of the field); the adjoint
+                                   solves extrapolate as with 2 */
   uint32_t terms;               /* PF_TERM_* mask */
   int32_t nonlocal_every;       /* refresh phi and u every k steps (<= 1: every
                                    step), the paper's Fig. 3d option */
-  int32_t extrap_order;         /* warm_start 2: the guess is the polynomial through
+  int32_t extrap_order;         /* warm_start 2 and 3: the guess is the polynomial through
                                    the last solution and up to extrap_order (0..8)
                                    earlier ones, x_next = sum_t (-1)^t C(m+1,t+1)
                                    x_{n-t}; the order grows with the history kept

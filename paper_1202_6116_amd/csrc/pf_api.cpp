@@ -66,6 +66,8 @@ hipError_t launch_cg_reduce(const double* partials, int nblocks, int nv, CgScala
 hipError_t launch_refine_update(double* x64, float* x32, const float* d, const float* p, const CgScalars* sc,
                                 int64_t n, hipStream_t s);
 hipError_t launch_extrapolate(double* x, const ExtrapRing& ring, int64_t n, hipStream_t s);
+hipError_t launch_extrap_score(const double* x, const ExtrapRing& ring, const ExtrapScore& sc, int64_t n,
+                               hipStream_t s);
 template <typename T, typename S, typename R>
 hipError_t launch_poisson_setup(const Dims& d, const TileMap& tm, const Coefs<T>& cf, const S* P, const S* V, T cdt,
                                 int with_P, int with_bc, const T* ghost_top, T phi_bottom, const uint8_t* emask,
@@ -396,6 +398,7 @@ struct Layout {
   size_t pr, pp[2], fr, fp[2]; // CG vectors, sized for FP64 (FP32 solves use half)
   size_t dphi, du;             // refinement corrections (FP32)
   size_t fbody;                // FP32_REFINE: the FEM body force of the first sweep (FP64)
+  size_t escore;               // warm_start 3: the score partials of phi and u
   size_t hist;                 // ring of earlier solutions for extrapolated warm starts
                                // (extrap_order slots of Np (phi) then extrap_order of 3N (u))
   size_t adj_hist;             // the same for the adjoint solutions: psi (Np) and the adjoint
@@ -422,6 +425,10 @@ std::vector<MgLevel> mg_levels_for(const pf_config& c, int field) {
 constexpr int kNumScalars = 5;
 constexpr int kPartialsPerBlock = 4;
 constexpr int kResultSlots = 128;
+
+// Slots of the ring of earlier solutions: extrap_order, one more with
+// warm_start 3 (its orders are scored on the solutions before the newest).
+int ring_slots(const pf_config& c) { return c.extrap_order + (c.warm_start == 3 ? 1 : 0); }
 
 Layout make_layout(const pf_config& c, int npartials) {
   const size_t N = (size_t)c.nx * c.ny * c.nz;
@@ -455,8 +462,9 @@ Layout make_layout(const pf_config& c, int npartials) {
   L.dphi = take(Np * 4);
   L.du = take(3 * N * 4);
   L.fbody = c.precision != PF_FP64 ? take(3 * N * 8) : 0;
-  L.hist = c.warm_start == 2 && c.extrap_order > 0 ? take((Np + 3 * N) * 8 * (size_t)c.extrap_order) : 0;
-  L.adj_hist = c.warm_start == 2 && c.extrap_order > 0 ? take((Np + 6 * N) * 8 * (size_t)c.extrap_order) : 0;
+  L.hist = c.warm_start >= 2 && c.extrap_order > 0 ? take((Np + 3 * N) * 8 * (size_t)ring_slots(c)) : 0;
+  L.adj_hist = c.warm_start >= 2 && c.extrap_order > 0 ? take((Np + 6 * N) * 8 * (size_t)c.extrap_order) : 0;
+  L.escore = take((size_t)2 * kScoreBlocks * (kMaxExtrap + 1) * 8);
   for (int t = 0; t < 8; t++) L.scratch[t] = take(S * 8);
   for (int f = 0; f < 2; f++) {
     const std::vector<MgLevel> mg = mg_levels_for(c, f);
@@ -576,7 +584,9 @@ struct pf_ctx {
   bool phi_bc_valid;
   bool basis_valid;
   bool adj_warm;            // adjoint scratch holds earlier adjoint solutions
-  int hist_valid;           // solutions held for extrapolated warm starts (0..extrap_order)
+  int hist_valid;           // solutions held for extrapolated warm starts (0..ring slots)
+  std::vector<double> escore_host[2];  // warm_start 3: the score partials of phi and u read back
+  int extrap_chosen[2] = {0, 0};       // warm_start 3: the order of the last refresh of phi and u
   int hist_head;            // ring slot that the next stored solution goes to
   int adj_valid, adj_head;  // the same for the adjoint solutions psi and du
   int lin_valid, lin_head;  // and for the displacement at the linearisation point
@@ -708,7 +718,7 @@ pf_status validate(const pf_config* c, std::string* why) {
     return bad("unknown precision");
   if (!(c->tol_phi > 0) || !(c->tol_u > 0)) return bad("tolerances must be > 0");
   if (c->maxit <= 0) return bad("maxit must be > 0");
-  if (c->warm_start < 0 || c->warm_start > 2) return bad("warm_start must be 0, 1 or 2");
+  if (c->warm_start < 0 || c->warm_start > 3) return bad("warm_start must be 0, 1, 2 or 3");
   if (c->extrap_order < 0 || c->extrap_order > kMaxExtrap) return bad("extrap_order must be in 0..8");
   if (!(c->noise_sigma >= 0) || !std::isfinite(c->noise_sigma)) return bad("noise_sigma must be finite and >= 0");
   if (c->top_bc != PF_TOP_METAL && c->top_bc != PF_TOP_OPEN) return bad("unknown top_bc");
@@ -1362,40 +1372,54 @@ void stats_add(pf_step_stats* st, int which, const SolveResult& r) {
 // available: the order grows by one per refresh up to extrap_order).  The
 // weights of the polynomial through m + 1 equally spaced values, evaluated
 // one step past the newest, are (-1)^t C(m+1, t+1), t = 0..m.
+// warm_start 3: the order of each refresh is the one among 0..extrap_order
+// whose extrapolation from the solutions before the newest would have come
+// closest to the newest (squared error summed over a fixed sample of the
+// field, 1/64 of its values in chunks of 256); the order that predicts best
+// changes along a trajectory (high while the fields move smoothly, low once
+// the step-to-step changes approach the solver tolerance, which the weights
+// amplify).
 // extrapolate_plan does the host side (ring descriptors of phi and u, ring
 // head advanced; false: order 0, nothing to launch); extrapolate_field
-// launches one field's kernel on the calling thread's stream, so each solve
+// launches one field's kernels on the calling thread's stream, so each solve
 // extrapolates its own field on its own stream.
-// ring_plan: the descriptors of nf fields of lengths len[] whose rings lie
-// one after the other at byte offset off; valid and head are the ring's
-// fill and next slot.
-bool ring_plan(pf_ctx* c, size_t off, int nf, const int64_t* len, int& valid, int& head, ExtrapRing* ring) {
-  const int cap = c->cfg.extrap_order;
+// ring_plan: the descriptors of nf fields of lengths len[] whose rings of
+// `slots` values lie one after the other at byte offset off; valid and head
+// are the ring's fill and next slot; cap the highest order.
+void extrap_weights(int m, double* c) {
+  for (int t = 0; t <= m; t++) {
+    double b = 1;
+    for (int q = 1; q <= t + 1; q++) b = b * (m + 2 - q) / q;
+    c[t] = (t & 1) ? -b : b;
+  }
+}
+
+bool ring_plan(pf_ctx* c, size_t off, int nf, const int64_t* len, int& valid, int& head, ExtrapRing* ring, int slots,
+               int cap) {
   const int m = std::min(valid, cap);
+  const int nh = std::min(valid, slots);
   int64_t first = 0;
   for (int f = 0; f < nf; f++) {
     ExtrapRing& r = ring[f];
-    double* base = cap > 0 ? at<double>(c, off) + first : nullptr;
-    first += (int64_t)cap * len[f];
+    double* base = slots > 0 ? at<double>(c, off) + first : nullptr;
+    first += (int64_t)slots * len[f];
     r.m = m;
-    for (int t = 0; t <= m; t++) {
-      double b = 1;
-      for (int q = 1; q <= t + 1; q++) b = b * (m + 2 - q) / q;
-      r.c[t] = (t & 1) ? -b : b;
-    }
-    for (int t = 0; t < m; t++) r.h[t] = base + (int64_t)((head - 1 - t + 2 * cap) % cap) * len[f];
-    for (int t = m; t < kMaxExtrap; t++) r.h[t] = nullptr;
-    r.dest = cap > 0 ? base + (int64_t)head * len[f] : nullptr;
+    r.nh = nh;
+    extrap_weights(m, r.c);
+    for (int t = 0; t <= kMaxExtrap; t++)
+      r.h[t] = t < nh ? base + (int64_t)((head - 1 - t + 2 * slots) % slots) * len[f] : nullptr;
+    r.dest = slots > 0 ? base + (int64_t)head * len[f] : nullptr;
   }
   if (cap == 0) return false;  // the previous solution is the guess
-  head = (head + 1) % cap;
-  if (valid < cap) valid++;
+  head = (head + 1) % slots;
+  if (valid < slots) valid++;
   return true;
 }
 
 bool extrapolate_plan(pf_ctx* c, ExtrapRing ring[2]) {
   const int64_t len[2] = {c->dims_p.N, 3 * c->dims.N};
-  return ring_plan(c, c->lay.hist, 2, len, c->hist_valid, c->hist_head, ring);
+  return ring_plan(c, c->lay.hist, 2, len, c->hist_valid, c->hist_head, ring, ring_slots(c->cfg),
+                   c->cfg.extrap_order);
 }
 
 // Replaces x (n values, the previous solution) by its extrapolation and
@@ -1407,9 +1431,38 @@ pf_status extrapolate_into(pf_ctx* c, double* x, int64_t n, const ExtrapRing& ri
   return PF_OK;
 }
 
-pf_status extrapolate_field(pf_ctx* c, int f, const ExtrapRing& ring) {
+pf_status extrapolate_field(pf_ctx* c, int f, const ExtrapRing& ring0) {
   const int64_t n = f == 0 ? c->dims_p.N : 3 * c->dims.N;
   double* x = at<double>(c, f == 0 ? c->lay.phi : c->lay.u);
+  ExtrapRing ring = ring0;
+  if (c->cfg.warm_start == 3) {
+    // score the orders the history allows, then extrapolate with the best
+    ExtrapScore sc{};
+    sc.mmax = std::min(c->cfg.extrap_order, ring.nh - 1);
+    int best = 0;
+    if (sc.mmax >= 1) {
+      for (int m = 0; m <= sc.mmax; m++) extrap_weights(m, sc.c[m]);
+      const int nv = kMaxExtrap + 1;
+      sc.partials = at<double>(c, c->lay.escore) + (size_t)f * kScoreBlocks * nv;
+      // the sampled values of x and of the mmax + 1 earlier solutions read
+      const double sb = 8.0 * (sc.mmax + 2) * (double)n / kScoreStride;
+      PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, sb, [&] { return launch_extrap_score(x, ring, sc, n, strm(c)); }));
+      std::vector<double>& hp = c->escore_host[f];
+      PF_HIP(c, hipMemcpyAsync(hp.data(), sc.partials, hp.size() * sizeof(double), hipMemcpyDeviceToHost, strm(c)));
+      PF_HIP(c, hipStreamSynchronize(strm(c)));
+      double emin = 0.0;
+      for (int m = 0; m <= sc.mmax; m++) {
+        double e = 0.0;
+        for (int b = 0; b < kScoreBlocks; b++) e += hp[(size_t)b * nv + m];
+        if (m == 0 || e < emin) emin = e, best = m;
+      }
+    } else {
+      best = ring.m;  // no choice yet: what the history holds (order 0 or 1)
+    }
+    ring.m = best;
+    extrap_weights(best, ring.c);
+    c->extrap_chosen[f] = best;
+  }
   // x and m history slots read; x and the ring slot written
   PF_HIP(c, timed(c, PF_KC_OTHER, -1, -1, 8.0 * n * (ring.m + 3),
                   [&] { return launch_extrapolate(x, ring, n, strm(c)); }));
@@ -1664,16 +1717,18 @@ pf_status hvp(pf_ctx* c, const S* P, const S* V, double cdt, const double* ulin_
   double* ulin = scratch<double>(c, kScrULin);
   double* du = scratch<double>(c, kScrDu);
   double* psi = scratch<double>(c, kScrPsi);
-  // warm_start 2: the adjoint solutions of the previous adjoint steps are
-  // extrapolated like the forward ones (rings of psi and du; ulin has a ring
-  // of its own, which restarts after steps that were given ulin)
+  // warm_start 2 and 3: the adjoint solutions of the previous adjoint steps
+  // are extrapolated like the forward ones with warm_start 2 (rings of psi
+  // and du; ulin has a ring of its own, which restarts after steps that were
+  // given ulin)
   ExtrapRing ring[2], lring[1];
   const int64_t len[2] = {c->dims_p.N, 3 * d.N};
   const int64_t llen[1] = {3 * d.N};
-  const bool xw = c->adj_warm && c->cfg.warm_start == 2;
-  const bool ex = xw && ring_plan(c, c->lay.adj_hist, 2, len, c->adj_valid, c->adj_head, ring);
+  const bool xw = c->adj_warm && c->cfg.warm_start >= 2;
+  const int cap = c->cfg.extrap_order;
+  const bool ex = xw && ring_plan(c, c->lay.adj_hist, 2, len, c->adj_valid, c->adj_head, ring, cap, cap);
   const size_t loff = c->lay.adj_hist + (size_t)c->cfg.extrap_order * (size_t)(len[0] + len[1]) * 8;
-  const bool lex = xw && !ulin_in && ring_plan(c, loff, 1, llen, c->lin_valid, c->lin_head, lring);
+  const bool lex = xw && !ulin_in && ring_plan(c, loff, 1, llen, c->lin_valid, c->lin_head, lring, cap, cap);
   if (ulin_in) {
     // the scratch keeps the latest displacement, a valid warm start should a
     // later step have to solve for it
@@ -1956,6 +2011,7 @@ pf_status init_ctx(const char* who, const pf_config* cfg, void* ws, size_t bytes
   c->adj_head = 0;
   c->lin_valid = 0;
   c->lin_head = 0;
+  for (int f = 0; f < 2; f++) c->escore_host[f].assign((size_t)kScoreBlocks * (kMaxExtrap + 1), 0.0);
   c->step = 0;
   c->cur = 0;
   for (int t = 0; t < kPredCount; t++) c->pred[t] = 16;
@@ -2195,7 +2251,7 @@ pf_status pf_step(pf_ctx* c, int32_t nsteps, pf_step_stats* st) {
     void* Vn = c->ws + c->lay.V[c->cur ^ 1];
     if (c->step % every == 0) {
       ExtrapRing ring[2];
-      const bool ex = c->cfg.warm_start == 2 && extrapolate_plan(c, ring);
+      const bool ex = c->cfg.warm_start >= 2 && extrapolate_plan(c, ring);
       pf_status r = solve_nonlocal(c, P, pc ? V : nullptr, pc ? c->cfg.dt : 0.0, c->cfg.warm_start != 0, st,
                                    ex ? ring : nullptr);
       if (fatal(r)) return r;

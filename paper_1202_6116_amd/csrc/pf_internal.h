@@ -121,10 +121,22 @@ struct TileMap {
 // the current value then replaces the oldest (or the next free) ring slot.
 constexpr int kMaxExtrap = 8;
 struct ExtrapRing {
-  const double* h[kMaxExtrap];  // earlier solutions, newest first (m used)
-  double* dest;                 // ring slot that receives the current value
-  double c[kMaxExtrap + 1];     // c[0] for the current value, c[t] for h[t-1]
+  const double* h[kMaxExtrap + 1];  // earlier solutions, newest first (m used, nh valid)
+  double* dest;                     // ring slot that receives the current value
+  double c[kMaxExtrap + 1];         // c[0] for the current value, c[t] for h[t-1]
   int m;
+  int nh;                           // earlier solutions held (warm_start 3 scores orders < nh)
+};
+
+// warm_start 3: sampled one-step prediction errors of the extrapolation
+// orders 0..mmax (every kScoreStride-th chunk of 256 values of a field),
+// per block of extrap_score_kernel; c[m][t] are the weights of order m.
+constexpr int kScoreBlocks = 1024;
+constexpr int kScoreStride = 64;
+struct ExtrapScore {
+  double c[kMaxExtrap + 1][kMaxExtrap + 1];
+  double* partials;  // kScoreBlocks x (kMaxExtrap + 1)
+  int mmax;
 };
 
 // Material on the grid axes (host): rotation R (crystal to grid), the Voigt

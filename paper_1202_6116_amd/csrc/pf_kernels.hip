@@ -386,6 +386,57 @@ __global__ void extrapolate_kernel(double* x, ExtrapRing ring, int64_t n) {
   }
 }
 
+// warm_start 3: how well each extrapolation order 0..mmax would have
+// predicted the newest solution x from the solutions before it (ring.h[0]
+// newest), measured on every kScoreStride-th chunk of 256 values by the
+// squared second difference along x of the prediction error (the solves
+// start from the residual b - A x0 = A (x - x0), and A weighs an error by
+// its second differences, so rough errors cost more than smooth ones of the
+// same size): per block, the sums go to partials[block][m].
+__global__ __launch_bounds__(256) void extrap_score_kernel(const double* __restrict__ x, ExtrapRing ring,
+                                                           ExtrapScore sc, int64_t n) {
+  double e[kMaxExtrap + 1];
+#pragma unroll
+  for (int m = 0; m <= kMaxExtrap; m++) e[m] = 0.0;
+  const int lane = threadIdx.x & 63;
+  const int64_t chunks = (n + 255) / 256;
+  // uniform over the block: every lane takes part in the shuffles
+  for (int64_t q = (int64_t)blockIdx.x * kScoreStride; q < chunks; q += (int64_t)gridDim.x * kScoreStride) {
+    const int64_t i = q * 256 + threadIdx.x;
+    const bool in = i < n;
+    double h[kMaxExtrap + 1];
+#pragma unroll
+    for (int t = 0; t <= kMaxExtrap; t++) h[t] = in && t <= sc.mmax ? ring.h[t][i] : 0.0;
+    const double xv = in ? x[i] : 0.0;
+    // the neighbours along the chunk are the lanes beside (its interior lanes count)
+    const bool inner = in && lane > 0 && lane < 63 && i + 1 < n;
+#pragma unroll
+    for (int m = 0; m <= kMaxExtrap; m++) {
+      if (m > sc.mmax) break;
+      double pr = 0.0;
+#pragma unroll
+      for (int t = 0; t <= m; t++) pr += sc.c[m][t] * h[t];
+      const double er = pr - xv;
+      const double lo = __shfl_up(er, 1, 64), hi = __shfl_down(er, 1, 64);
+      const double d2 = hi - 2.0 * er + lo;
+      if (inner) e[m] += d2 * d2;
+    }
+  }
+  __shared__ double red[kMaxExtrap + 1][256 / 64];
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int m = 0; m <= kMaxExtrap; m++) {
+    const double w = wave_sum(e[m]);
+    if (lane == 0) red[m][wv] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x <= kMaxExtrap) {
+    double t = 0.0;
+    for (int w = 0; w < 256 / 64; w++) t += red[threadIdx.x][w];
+    sc.partials[(int64_t)blockIdx.x * (kMaxExtrap + 1) + threadIdx.x] = t;
+  }
+}
+
 // Iterative refinement: x64 += d, x32 = x64 (rounded working copy).
 // x64 += d, x32 = (float) x64.  With p, the inner solve's deferred last
 // update is applied first, d + alpha p, as cg_finish_kernel would have
@@ -2998,6 +3049,13 @@ hipError_t launch_extrapolate(double* x, const ExtrapRing& ring, int64_t n, hipS
     case 8: extrapolate_kernel<8><<<nb, 256, 0, s>>>(x, ring, n); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_extrap_score(const double* x, const ExtrapRing& ring, const ExtrapScore& sc, int64_t n,
+                               hipStream_t s) {
+  if (sc.mmax < 0 || sc.mmax > kMaxExtrap || sc.mmax >= ring.nh) return hipErrorInvalidValue;
+  extrap_score_kernel<<<kScoreBlocks, 256, 0, s>>>(x, ring, sc, n);
   return hipGetLastError();
 }
 

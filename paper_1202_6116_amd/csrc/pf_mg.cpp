@@ -325,6 +325,8 @@ MgHierarchy build_generic(int nx, int ny, int nz, int nc, bool top_fixed, std::v
     // estimate of lambda_max taken 5% high.  omega lambda_max stays at 1.65,
     // below 2, so the symmetric cycle stays positive definite.
     L.omega = 1.3 * 4.0 / (3.0 * 1.05 * lam);
+    if (l > 0) if (const char* env = getenv("PF_MG_COARSE_SCALE")) L.omega *= strtod(env, nullptr);
+    if (l == 0) if (const char* env = getenv("PF_MG_FINE_SCALE")) L.omega *= strtod(env, nullptr);
   }
   // Coarsest level: dense inverse over its unknowns, or damped Jacobi sweeps
   // when it is too large for that.

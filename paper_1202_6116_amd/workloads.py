@@ -73,8 +73,9 @@ class PFConfig:
     tol_phi: float = 1e-10
     tol_u: float = 1e-10
     maxit: int = 5000
-    warm_start: int = 1             # 0 cold, 1 previous solution, 2 extrapolated from earlier solutions
-    extrap_order: int = 4           # warm_start 2: polynomial through up to 1 + this many solutions
+    warm_start: int = 1             # 0 cold, 1 previous solution, 2 extrapolated from earlier solutions,
+                                    # 3 extrapolated with the order chosen per refresh (up to extrap_order)
+    extrap_order: int = 4           # warm_start 2, 3: polynomial through up to 1 + this many solutions
     noise_sigma: float = 0.0        # thermal noise: one Euler step adds noise_sigma * sqrt(dt) * N(0, 1)
     noise_seed: int = 0             # key of the counter-based noise generator
     terms: int = TERM_ALL

@@ -295,6 +295,57 @@ def test_extrapolation_history_spans_step_calls(pf):
     assert sc["iters_phi"] == sb["iters_phi"] and sc["iters_u"] == sb["iters_u"]
 
 
+@pytest.mark.parametrize("order", [1, 4, 8])
+def test_adaptive_extrapolation_matches_oracle(pf, oracle_mod, order):
+    """warm_start 3 chooses the order of each refresh (up to extrap_order)
+    by how well each order would have predicted the newest solution from the
+    ones before it; only the initial guesses change, so the trajectory
+    matches the oracle's (which starts each solve from the previous
+    solution) at the parity bar, and the choices depend on the state alone:
+    two contexts agree bitwise, a run split over two calls agrees with a
+    single one, and set_state starts the history afresh."""
+    cfg = ragged_cfg(warm_start=3, extrap_order=order)
+    print(f"case: trajectory 70x13x6 adaptive extrapolation up to order {order}", flush=True)
+    P0 = domain_polarisation(cfg, 19, block=4)
+    o = oracle_mod.Oracle(cfg.replace(warm_start=1))
+    P = P0.copy()
+    V, phi, u, _ = o.set_state(P)
+    o.step(P, V, phi, u, 12)
+    a = pf.Context(cfg)
+    a.set_state(dev(P0))
+    sa = a.step(12)
+    Pa, Va, phia, ua, _ = a.get_state()
+    assert rel(host(Pa), P) < TOL
+    assert rel(host(phia), phi) < TOL
+    assert rel(host(ua), u) < TOL
+    b = pf.Context(cfg)
+    b.set_state(dev(P0))
+    sb = b.step(5)
+    sb2 = b.step(7)
+    for x, y in zip((Pa, Va, phia, ua), b.get_state()[:4]):
+        assert torch.equal(x, y)
+    assert sa["iters_phi"] == sb["iters_phi"] + sb2["iters_phi"]
+    assert sa["iters_u"] == sb["iters_u"] + sb2["iters_u"]
+    b.set_state(dev(P0))
+    sc = b.step(5)
+    assert sc["iters_phi"] == sb["iters_phi"] and sc["iters_u"] == sb["iters_u"]
+
+
+def test_adaptive_extrapolation_of_order_zero_is_the_previous_solution(pf):
+    """With extrap_order 0 there is no order to choose: warm_start 3 gives
+    the bits of warm_start 1 (and of warm_start 2 with order 0)."""
+    P0 = dev(domain_polarisation(ragged_cfg(), 20, block=4))
+    out = []
+    for ws in (1, 2, 3):
+        ctx = pf.Context(ragged_cfg(warm_start=ws, extrap_order=0))
+        ctx.set_state(P0)
+        ctx.step(6)
+        out.append(ctx.get_state()[:4])
+    for other in out[1:]:
+        for x, y in zip(out[0], other):
+            assert torch.equal(x, y)
+
+
 @pytest.mark.parametrize("integrator,ws", [("pc", 1), ("euler", 1), ("pc", 2)])
 def test_nonlocal_every_k_matches_oracle(pf, oracle_mod, integrator, ws):
     """Non-local fields refreshed every 5 steps (the paper's Fig. 3d

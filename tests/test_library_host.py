@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     dict(electrodes=[Electrode(0, 4, 0, 4, 1.0), Electrode(2, 6, 1, 3, -1.0)]),     # overlap
     dict(electrodes=[Electrode(30, 40, 0, 4, 1.0)]),                                # out of range
     dict(electrodes=[Electrode(5, 5, 0, 4, 1.0)]),                                  # empty
-    dict(C12=2.0), dict(terms=16), dict(integrator="leapfrog"), dict(warm_start=3),
+    dict(C12=2.0), dict(terms=16), dict(integrator="leapfrog"), dict(warm_start=4),
     dict(extrap_order=9), dict(extrap_order=-1), dict(noise_sigma=-0.1), dict(noise_sigma=float("nan")),
     dict(top="open", n_air=0), dict(top="open", n_air=17), dict(top="open", eps_air=0.0), dict(top_bc=5),
     dict(rotation=(1, 0, 0, 0, 1, 0, 0, 0, 1.01)), dict(rotation=(1, 0, 0, 0, 1, 0, 0, 0, -1)),
@@ -54,6 +54,18 @@ def test_invalid_configurations_are_rejected(bad):
     with pytest.raises(pf.PFError) as ei:
         pf.pf_workspace_size(cfg.replace(**bad))
     assert ei.value.status == pf.PF_EINVAL
+
+
+def test_adaptive_warm_start_keeps_one_more_solution():
+    """warm_start 3 scores the orders up to extrap_order on the solutions
+    before the newest, so its ring holds one more solution of phi and u than
+    warm_start 2 (FP64 values), plus the fixed score partials."""
+    cfg = PFConfig(nx=32, ny=16, nz=6, warm_start=2, extrap_order=3)
+    two = pf.pf_workspace_size(cfg)
+    three = pf.pf_workspace_size(cfg.replace(warm_start=3))
+    slot = 8 * (cfg.phi_planes * cfg.ny * cfg.nx + 3 * cfg.nodes)
+    assert three - two >= slot
+    assert three - two <= slot + 2 * 1024 * 9 * 8 + 4096
 
 
 def test_workspace_size_scales_with_grid():
