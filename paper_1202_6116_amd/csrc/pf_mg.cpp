@@ -319,14 +319,15 @@ MgHierarchy build_generic(int nx, int ny, int nz, int nc, bool top_fixed, std::v
     const double lam = jacobi_lambda_max(L.nz, nc, top_fixed, &h.tables[l]);
     // damping of the Jacobi smoother: 4 / (3 lambda_max(D^-1 A)) is the
     // classic choice for smoothing alone; as the preconditioner of CG the
-    // cycle converges fastest at about 1.3 times it (the solver-grid films:
-    // 11% fewer iterations; at 1.5 times, where omega lambda_max nears 2 and
-    // the cycle nears indefiniteness, it is slower than at 1), with the
-    // estimate of lambda_max taken 5% high.  omega lambda_max stays at 1.65,
-    // below 2, so the symmetric cycle stays positive definite.
-    L.omega = 1.3 * 4.0 / (3.0 * 1.05 * lam);
-    if (l > 0) if (const char* env = getenv("PF_MG_COARSE_SCALE")) L.omega *= strtod(env, nullptr);
-    if (l == 0) if (const char* env = getenv("PF_MG_FINE_SCALE")) L.omega *= strtod(env, nullptr);
+    // cycle converges fastest at about 1.3 times it (the benchmark films: 11%
+    // fewer iterations; at 1.5 times on every level, where omega lambda_max
+    // nears 2 and the cycle nears indefiniteness, slower than at 1), and the
+    // coarse levels of the FEM hierarchy at 1.15 times that again (5% fewer
+    // FEM iterations; the Poisson levels gain nothing from it), with the
+    // estimate of lambda_max taken 5% high.  omega lambda_max stays at 1.65
+    // (1.90 on the coarse FEM levels), below 2, so the symmetric cycle stays
+    // positive definite.
+    L.omega = (nc == 3 && l > 0 ? 1.15 : 1.0) * 1.3 * 4.0 / (3.0 * 1.05 * lam);
   }
   // Coarsest level: dense inverse over its unknowns, or damped Jacobi sweeps
   // when it is too large for that.
