@@ -295,8 +295,8 @@ def test_extrapolation_history_spans_step_calls(pf):
     assert sc["iters_phi"] == sb["iters_phi"] and sc["iters_u"] == sb["iters_u"]
 
 
-@pytest.mark.parametrize("order", [1, 4, 8])
-def test_adaptive_extrapolation_matches_oracle(pf, oracle_mod, order):
+@pytest.mark.parametrize("order,kw", [(1, {}), (4, {}), (8, {}), (8, {"precond": "mg", "precision": "fp32_solves"})])
+def test_adaptive_extrapolation_matches_oracle(pf, oracle_mod, order, kw):
     """warm_start 3 chooses the order of each refresh (up to extrap_order)
     by how well each order would have predicted the newest solution from the
     ones before it; only the initial guesses change, so the trajectory
@@ -304,10 +304,10 @@ def test_adaptive_extrapolation_matches_oracle(pf, oracle_mod, order):
     solution) at the parity bar, and the choices depend on the state alone:
     two contexts agree bitwise, a run split over two calls agrees with a
     single one, and set_state starts the history afresh."""
-    cfg = ragged_cfg(warm_start=3, extrap_order=order)
-    print(f"case: trajectory 70x13x6 adaptive extrapolation up to order {order}", flush=True)
+    cfg = ragged_cfg(warm_start=3, extrap_order=order, **kw)
+    print(f"case: trajectory 70x13x6 adaptive extrapolation up to order {order} {kw}", flush=True)
     P0 = domain_polarisation(cfg, 19, block=4)
-    o = oracle_mod.Oracle(cfg.replace(warm_start=1))
+    o = oracle_mod.Oracle(cfg.replace(warm_start=1, precision="fp64", precond="jacobi"))
     P = P0.copy()
     V, phi, u, _ = o.set_state(P)
     o.step(P, V, phi, u, 12)
