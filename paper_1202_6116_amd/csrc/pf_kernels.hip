@@ -412,14 +412,15 @@ __global__ __launch_bounds__(256) void extrap_score_kernel(const double* __restr
     const bool inner = in && lane > 0 && lane < 63 && i + 1 < n;
 #pragma unroll
     for (int m = 0; m <= kMaxExtrap; m++) {
-      if (m > sc.mmax) break;
-      double pr = 0.0;
+      if (m <= sc.mmax) {  // uniform over the block
+        double pr = 0.0;
 #pragma unroll
-      for (int t = 0; t <= m; t++) pr += sc.c[m][t] * h[t];
-      const double er = pr - xv;
-      const double lo = __shfl_up(er, 1, 64), hi = __shfl_down(er, 1, 64);
-      const double d2 = hi - 2.0 * er + lo;
-      if (inner) e[m] += d2 * d2;
+        for (int t = 0; t <= m; t++) pr += sc.c[m][t] * h[t];
+        const double er = pr - xv;
+        const double lo = __shfl_up(er, 1, 64), hi = __shfl_down(er, 1, 64);
+        const double d2 = hi - 2.0 * er + lo;
+        if (inner) e[m] += d2 * d2;
+      }
     }
   }
   __shared__ double red[kMaxExtrap + 1][256 / 64];
