@@ -2656,16 +2656,19 @@ __global__ __launch_bounds__(kThreads, 3) void force_kernel(
           for (int c = 0; c < 3; c++) Vn[c * N + n] = F[c];
           break;
         case kPcStep:
+          // P + dt V' = Pp + dt (V' - V) with Pp = P + dt V the staged
+          // predictor (cdt = dt here): P is not read again
 #pragma unroll
           for (int c = 0; c < 3; c++) {
-            const T vn = (T)0.5 * (V[c * N + n] + F[c]);
+            const T v = V[c * N + n];
+            const T vn = (T)0.5 * (v + F[c]);
             Vn[c * N + n] = vn;
-            Pn[c * N + n] = P[c * N + n] + cf.dt * vn;
+            Pn[c * N + n] = p0[c] + cf.dt * (vn - v);
           }
           break;
-        default:  // kEulerStep
+        default:  // kEulerStep: Pp = P (cdt = 0, no V)
 #pragma unroll
-          for (int c = 0; c < 3; c++) Pn[c * N + n] = P[c * N + n] + cf.dt * F[c];
+          for (int c = 0; c < 3; c++) Pn[c * N + n] = p0[c] + cf.dt * F[c];
           break;
       }
 #pragma unroll
