@@ -9,12 +9,14 @@
  *   - the Landau bulk force (Eq. 1),
  *   - the gradient (domain-wall) force, a 7-point Laplacian (Eq. 2-3),
  *   - the electrostatic field E = -grad phi with eps Lap phi = div P (Eq. 4-5,
- *     17-18), solved by Jacobi-preconditioned conjugate gradients,
+ *     17-18), solved by preconditioned conjugate gradients,
  *   - the elastic force of the electrostrictive eigenstrain (Eq. 6, 15),
  *     with the displacement from a trilinear-hex FEM solve K u = f (Eq. 8-16),
- *     also by Jacobi-preconditioned conjugate gradients,
+ *     also by preconditioned conjugate gradients,
  *   - the predictor-corrector of Eq. 19 (rate carried as state) or forward
  *     Euler.
+ * Both solves take the same preconditioner (pf_config.precond): Jacobi, or
+ * one geometric multigrid V-cycle per CG iteration.
  *
  * Conventions.
  *   Grid: nodes (i, j, k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz, spacing h,
@@ -87,7 +89,7 @@ typedef enum {
 
 /* terms: which contributions enter the force (tests switch terms off) */
 enum { PF_TERM_LANDAU = 1, PF_TERM_GRAD = 2, PF_TERM_ELEC = 4, PF_TERM_ELAS = 8, PF_TERM_ALL = 15 };
-/* precond: preconditioner of the FEM conjugate gradients */
+/* precond: preconditioner of both conjugate-gradient solves (Poisson and FEM) */
 enum { PF_PRECOND_JACOBI = 0, PF_PRECOND_MG = 1 };
 /* top_bc: electrostatic condition above the film */
 enum { PF_TOP_METAL = 0, PF_TOP_OPEN = 1 };
@@ -154,7 +156,8 @@ typedef struct {
                                    R v_crystal; all zeros: identity).  a1, a11, a12,
                                    C and Q are crystal-axis coefficients; P, E, u and
                                    the stresses live on the grid axes (Sec. II) */
-  int32_t precond;              /* FEM solves: PF_PRECOND_JACOBI (the paper's
+  int32_t precond;              /* Poisson and FEM solves alike:
+                                   PF_PRECOND_JACOBI (the paper's
                                    Jacobi-preconditioned CG) or PF_PRECOND_MG (CG
                                    preconditioned by one multigrid V-cycle: Galerkin
                                    coarse operators of the trilinear prolongation,
@@ -224,7 +227,10 @@ pf_status pf_set_state(pf_ctx *ctx, const void *P, const void *phi0, const void 
 pf_status pf_restore_state(pf_ctx *ctx, const void *P, const void *V, const void *phi, const void *u, int64_t step);
 
 /* Copies the current state into caller arrays (any may be NULL): P and V
- * (3N, state precision), phi (Np doubles), u (3N doubles).  Asynchronous. */
+ * (3N, state precision), phi (Np doubles), u (3N doubles), and the step
+ * counter into *step (host; may be NULL).  The counter is an addition to the
+ * four state arrays: checkpoints need it to resume the thermal noise of
+ * Eq. 7, whose variates are keyed by the step.  Asynchronous. */
 pf_status pf_get_state(const pf_ctx *ctx, void *P, void *V, void *phi, void *u, int64_t *step);
 
 /* Advances the state by nsteps (Eq. 19 or forward Euler): per step one
@@ -235,8 +241,8 @@ pf_status pf_get_state(const pf_ctx *ctx, void *P, void *V, void *phi, void *u, 
  * completes), PF_ENONFINITE on NaN/Inf (the state is then undefined). */
 pf_status pf_step(pf_ctx *ctx, int32_t nsteps, pf_step_stats *stats);
 
-/* Poisson solve for a given polarisation P (device, 3N, state precision):
- * div_h(eps grad_h phi) = div_h P (eps = eps_b in the film, eps_air in the
+/* Poisson solve for a given polarisation P (device, 3N, state precision),
+ * Eq. 4-5 discretised as Eq. 17-18 (Sec. III.C): div_h(eps grad_h phi) = div_h P (eps = eps_b in the film, eps_air in the
  * air of the open top) with the boundary values.  phi (device, Np doubles)
  * is the initial guess when warm_start is set and receives the solution
  * (electrode nodes of the open top: their voltage).  Synchronises. */
@@ -265,8 +271,9 @@ pf_status pf_force(pf_ctx *ctx, const void *P, const void *phi, const void *u, v
  * the step (pf_get_state).  Asynchronous. */
 pf_status pf_noise(pf_ctx *ctx, int64_t step, double *xi);
 
-/* Free energy of the current P: out[0..4] = bulk, gradient, electrostatic,
- * elastic, total (host doubles), evaluated in FP64.  Solves phi and u at P
+/* Free energy of the current P (Eq. 1-6 on the grid of Sec. III.A):
+ * out[0..4] = bulk (Eq. 1), gradient (Eq. 2), electrostatic (Eq. 4-5),
+ * elastic (Eq. 6), total (host doubles), evaluated in FP64.  Solves phi and u at P
  * in FP64 (warm-started from the state's solutions, configured
  * tolerances); the electrostatic energy is split into the polarisation
  * part, (h^3/2) rho^T A^-1 rho, and the applied part -h^3 P . E_app (linear
