@@ -914,7 +914,11 @@ pf_status run_cg(pf_ctx* c, int which, int predicted, T* x, T* const pbuf[2], in
     // multigrid cycle) for one more read-back
     batch = std::max(1, predicted / 8);
   }
-  if (h.done != kNonFinite) {
+  // no iteration (the setup met the test): no deferred update, and the
+  // first direction buffer was never written
+  if (h.done != kNonFinite && h.iter == 0) {
+    if (defer) *defer = nullptr;
+  } else if (h.done != kNonFinite) {
     if (defer) *defer = pbuf[h.iter & 1];
     else
       PF_HIP(c, timed(c, PF_KC_FINISH, -1, -1, 3.0 * n * sizeof(T),
@@ -1142,10 +1146,11 @@ std::function<hipError_t(int)> poisson_iteration(pf_ctx* c, const Coefs<T>& cf, 
     const bool mg = mg_on(c, 0);
     T* z = mg ? at<T>(c, c->lay.mg[0].z) : nullptr;
     const double vb = (double)d.N * sizeof(T);
-    // A: r or z, p_old, x read; p_new, x written.  B: p, r read; r written.
-    hipError_t e = timed(c, PF_KC_POISSON_A, 0, k, 5 * vb, [&] {
-      return launch_poisson_cg_a<T>(d, c->tm_p, cf, mg ? z : r, pb[k & 1], pb[(k + 1) & 1], x, sc, part, mg ? 1 : 0,
-                                    strm(c));
+    // A: r or z, p_old, x read; p_new, x written (the first iteration: r or
+    // z read, p_new written).  B: p, r read; r written.
+    hipError_t e = timed(c, PF_KC_POISSON_A, 0, k, (k == 0 ? 2 : 5) * vb, [&] {
+      return launch_poisson_cg_a<T>(d, c->tm_p, cf, mg ? z : r, k == 0 ? nullptr : pb[k & 1], pb[(k + 1) & 1], x,
+                                    sc, part, mg ? 1 : 0, strm(c));
     });
     if (e == hipSuccess) e = reduce(c, part, c->tm_p.nblocks, 1, 0, kRedAlpha, tol, 0, nullptr, 0, k);
     if (e == hipSuccess)
@@ -1171,9 +1176,10 @@ std::function<hipError_t(int)> fem_iteration(pf_ctx* c, T* r, T* const pb[2], T*
     T* z = mg ? at<T>(c, c->lay.mg[1].z) : nullptr;
     // the clamped plane holds no unknowns
     const double vb = 3.0 * (d.N - d.plane) * sizeof(T);
-    hipError_t e = timed(c, PF_KC_FEM_A, 1, k, 5 * vb, [&] {
-      return launch_fem_cg_a<T>(d, c->tm_f, tb, c->gen, mg ? z : r, pb[k & 1], pb[(k + 1) & 1], x, sc, part,
-                                mg ? 1 : 0, strm(c));
+    // the first iteration reads no p_old and leaves x alone
+    hipError_t e = timed(c, PF_KC_FEM_A, 1, k, (k == 0 ? 2 : 5) * vb, [&] {
+      return launch_fem_cg_a<T>(d, c->tm_f, tb, c->gen, mg ? z : r, k == 0 ? nullptr : pb[k & 1], pb[(k + 1) & 1],
+                                x, sc, part, mg ? 1 : 0, strm(c));
     });
     if (e == hipSuccess) e = reduce(c, part, c->tm_f.nblocks, 1, 1, kRedAlpha, tol, 0, nullptr, 1, k);
     if (e == hipSuccess)
@@ -1202,8 +1208,8 @@ pf_status solve_poisson64(pf_ctx* c, int pred, const S* P, const S* V, double cd
   double* r = at<double>(c, c->lay.pr);
   double* const pb[2] = {at<double>(c, c->lay.pp[0]), at<double>(c, c->lay.pp[1])};
   if (!warm) PF_HIP(c, launch_fill<double>(x, d.N, 0.0, strm(c)));
-  // P (and V) read when with_P; x read; r, p written
-  const double sb = (with_P ? 3.0 * c->dims.N * sizeof(S) * (V ? 2 : 1) : 0.0) + 3.0 * d.N * 8;
+  // P (and V) read when with_P; x read; r written
+  const double sb = (with_P ? 3.0 * c->dims.N * sizeof(S) * (V ? 2 : 1) : 0.0) + 2.0 * d.N * 8;
   PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, sb, [&] {
     return launch_poisson_setup<double, S, double>(d, c->tm_p, cf, P, V, cdt, with_P, with_bc, ghost, phi_bottom, emask(c),
                                                    x, r, pb[0], nullptr, part, strm(c));
@@ -1228,9 +1234,9 @@ pf_status solve_fem64(pf_ctx* c, int pred, const S* P, const S* V, double cdt, c
   double* r = at<double>(c, c->lay.fr);
   double* const pb[2] = {at<double>(c, c->lay.fp[0]), at<double>(c, c->lay.fp[1])};
   if (!warm) PF_HIP(c, launch_fill<double>(x, 3 * d.N, 0.0, strm(c)));
-  // P (and V), or W, read; x read; r, p written
+  // P (and V), or W, read; x read; r written
   const double n3 = 3.0 * d.N;
-  const double sb = (W ? n3 * 8 : n3 * sizeof(S) * (V ? 2 : 1)) + 3 * n3 * 8;
+  const double sb = (W ? n3 * 8 : n3 * sizeof(S) * (V ? 2 : 1)) + 2 * n3 * 8;
   PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, sb, [&] {
     return launch_fem_setup<double, S, double>(d, c->tm_f, cf, tb, c->gen, P, V, cdt, W, x, r, pb[0], pb[1], nullptr,
                                                nullptr, part, strm(c));
@@ -1286,17 +1292,17 @@ pf_status solve_refined(pf_ctx* c, bool fem, const S* P, const S* V, double cdt,
     const double n3 = 3.0 * c->dims.N;
     const double sv = 2.0 * sizeof(S);
     if (fem && res->outer == 0) {
-      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, n3 * (sv + 8 + 3 * 4 + 8), [&] {
+      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, n3 * (sv + 8 + 2 * 4 + 8), [&] {
         return launch_fem_setup<double, S, float>(d, c->tm_f, cf64, tb, c->gen, P, V, cdt, nullptr, x64, r, pb[0],
                                                   pb[1], dz, fbody, part, strm(c));
       }));
     } else if (fem) {
-      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, n3 * (8 + 8 + 3 * 4), [&] {
+      PF_HIP(c, timed(c, PF_KC_FEM_SETUP, -1, -1, n3 * (8 + 8 + 2 * 4), [&] {
         return launch_fem_resid<double, float>(d, c->tm_f, tb, c->gen, fbody, x64, r, pb[0], pb[1], dz, part,
                                                strm(c));
       }));
     } else {
-      PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, n3 * sv + (double)d.N * (8 + 3 * 4), [&] {
+      PF_HIP(c, timed(c, PF_KC_POISSON_SETUP, -1, -1, n3 * sv + (double)d.N * (8 + 2 * 4), [&] {
         return launch_poisson_setup<double, S, float>(d, c->tm_p, cf64, P, V, cdt, 1, 1, at<double>(c, c->lay.ghost64),
                                                           c->cfg.phi_bottom, emask(c), x64, r, pb[0], dz, part,
                                                           strm(c));

@@ -486,7 +486,9 @@ __device__ __forceinline__ PlaneEps<T> plane_eps(const Dims& d, const Coefs<T>& 
 }
 
 // b from Pp = P + cdt V (V may be null) and the ghost planes; r = b - A x;
-// p = r / diag; partial (b.b, r.z, r.r).  T: arithmetic and x; S: storage
+// partial (b.b, r.z, r.r) with z = r / diag.  The first direction is not
+// stored (the first iteration forms it from r); p gets zeros on the
+// electrode nodes only.  T: arithmetic and x; S: storage
 // of P and V; R: storage of r and p (FP32 for the inner solve of a
 // refinement sweep, which also clears its correction dz).  Each block
 // marches a 64 x 4 tile up its z-chunk: the values of its own column at the
@@ -565,7 +567,6 @@ __global__ __launch_bounds__(kThreads) void poisson_setup_kernel(
         const T rr = b - Ax;
         const T z = rr * e.w;
         r[n] = (R)rr;
-        p[n] = (R)z;
         if (dz) dz[n] = 0;
         v[0] += (double)b * b;
         v[1] += (double)rr * z;
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(kThreads) void poisson_setup_kernel(
 
 // Iteration kernel A: p_new = z + beta p_old on the tile and its halo, q =
 // A p_new, x += alpha_prev p_old (the deferred update of the previous
-// iteration); partial p_new . q.
+// iteration); partial p_new . q.  p_old null: the first iteration, p_new = z.
 // unit_w: r holds the preconditioned residual z itself (multigrid).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap tm, Coefs<T> cf,
@@ -593,6 +594,8 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
   constexpr int TY = kBY;
   __shared__ T ring[3][1][TY + 2][kHX];
   const T beta = (T)sc->beta, alpha = (T)sc->alpha, c6 = cf.eps_over_h2;
+  // the first iteration (p_old null): p = z, x untouched (alpha, beta zero)
+  const bool first = p_old == nullptr;
   const TileCoord tc = tile_coord(d, tm);
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int i = tc.i0 + lx, j = tc.j0 + ly;
@@ -600,7 +603,7 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
   const int64_t col = valid ? i + (int64_t)d.nx * j : 0;
   auto fetch = [&](int64_t m, int, T* raw) {
     raw[0] = r[m];
-    raw[1] = p_old[m];
+    if (!first) raw[1] = p_old[m];
   };
   auto comb = [&](int kk, const T* raw, T* out) {
     out[0] = raw[0] * (unit_w ? (T)1 : plane_eps(d, cf, kk).w) + beta * raw[1];
@@ -612,7 +615,7 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
   stage_store<TY>(ring, st, tc.k0, comb);
   stage_fetch<TY>(st, d, tc.i0, tc.j0, tc.k0 + 1, fetch);
   T cpo = 0, cx = 0;  // centre p_old, x of the plane being computed
-  if (valid) {
+  if (valid && !first) {
     cpo = p_old[col + d.plane * tc.k0];
     cx = x[col + d.plane * tc.k0];
   }
@@ -621,7 +624,7 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
     stage_store<TY>(ring, st, k + 1, comb);
     if (k + 2 <= tc.k1) stage_fetch<TY>(st, d, tc.i0, tc.j0, k + 2, fetch);
     T npo = 0, nx_ = 0;
-    if (valid && k + 1 < tc.k1) {
+    if (valid && !first && k + 1 < tc.k1) {
       npo = p_old[col + d.plane * (k + 1)];
       nx_ = x[col + d.plane * (k + 1)];
     }
@@ -641,7 +644,7 @@ __global__ __launch_bounds__(kThreads) void poisson_cg_a_kernel(Dims d, TileMap 
       }
       const int64_t n = col + d.plane * k;
       p_new[n] = pc;
-      x[n] = cx + alpha * cpo;
+      if (!first) x[n] = cx + alpha * cpo;
       acc += (double)pc * q;
     }
     cpo = npo;
@@ -957,7 +960,8 @@ __device__ __forceinline__ void landau_hessian_apply(const Coefs<T>& cf, const T
 }  // namespace
 
 // f = body force of the eigenstrain of Pp = P + cdt V (Eq. 15); r = f - K x;
-// p = r / diag.  The clamped plane k = 0 has x = r = p = 0 (both direction
+// partials with z = r / diag (the first iteration forms the first direction
+// itself, so it is not stored).  The clamped plane k = 0 has x = r = p = 0 (both direction
 // buffers).  Partial (f.f, r.z, r.r) per tile.
 // With W non-null the eigenstrain is replaced by its linearisation at Pp in
 // the direction W, deps0 = (d eps0/dP)(Pp) W (the right-hand side of the
@@ -1127,7 +1131,6 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
           const T rr = f0[c] - Kx[c];
           const T z = rr * jw(zt, c);
           r[c * N + n] = (R)rr;
-          p0[c * N + n] = (R)z;
           if (dz) dz[c * N + n] = 0;
           if (fout) fout[c * N + n] = f0[c];
           v[0] += (double)f0[c] * f0[c];
@@ -1150,8 +1153,8 @@ __global__ __launch_bounds__(kThreads, 3) void fem_setup_kernel(
 
 // Residual of a later refinement sweep, r = f - K x, from the body force f
 // that the first sweep's setup stored (fem_setup_kernel with fout), so the
-// eigenstress is not formed again.  Outputs as fem_setup_kernel: r, the
-// Jacobi-weighted p0, zeros in dz (and in x, r, p0, p1 on the clamped plane),
+// eigenstress is not formed again.  Outputs as fem_setup_kernel: r, zeros
+// in dz (and in x, r, p0, p1 on the clamped plane),
 // and the partials (f.f, r.z, r.r) per tile.  x is staged in the three-plane
 // LDS ring; K x is the same apply as in fem_setup_kernel, so the residual is
 // bitwise the one the full setup would form.
@@ -1222,7 +1225,6 @@ __global__ __launch_bounds__(kThreads, 4) void fem_resid_kernel(Dims d, TileMap 
           const T rr = fc - Kx[c];
           const T z = rr * jw(zt, c);
           r[c * N + n] = (R)rr;
-          p0[c * N + n] = (R)z;
           dz[c * N + n] = 0;
           v[0] += (double)fc * fc;
           v[1] += (double)rr * z;
@@ -1237,6 +1239,7 @@ __global__ __launch_bounds__(kThreads, 4) void fem_resid_kernel(Dims d, TileMap 
 
 // Iteration kernel A: p_new = z + beta p_old on the tile and its halo (zero
 // on the clamped plane), q = K p_new, x += alpha_prev p_old; partial p.q.
+// p_old null: the first iteration, p_new = z and x untouched.
 // At most 128 VGPRs: four waves per SIMD, so four 256-thread blocks per CU
 // and the whole tile grid resident at once.
 // unit_w: r holds the preconditioned residual z itself (multigrid), so the
@@ -1250,6 +1253,9 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
   constexpr int TY = kBY;
   __shared__ T ring[3][3][TY + 2][kHX];
   const T beta = (T)sc->beta, alpha = (T)sc->alpha;
+  // the first iteration (p_old null): p = z, no deferred update of x (alpha
+  // and beta are zero), so neither p_old nor x is read or written
+  const bool first = p_old == nullptr;
   // Jacobi weights per component (equal for a cubic stiffness on the grid axes)
   const JacobiW<T, GEN> jw(tb);
   const TileCoord tc = tile_coord(d, tm);
@@ -1261,10 +1267,10 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
   auto fetch = [&](int64_t m, int k, T* raw) {
     if (k == 0) return;  // clamped plane: zero
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      raw[c] = r[c * N + m];
-      raw[3 + c] = p_old[c * N + m];
-    }
+    for (int c = 0; c < 3; c++) raw[c] = r[c * N + m];
+    if (first) return;
+#pragma unroll
+    for (int c = 0; c < 3; c++) raw[3 + c] = p_old[c * N + m];
   };
   auto comb = [&](int k, const T* raw, T* out) {
     const bool top = k == d.nz - 1;
@@ -1275,7 +1281,7 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
   auto centre = [&](int k, T* cv) {
 #pragma unroll
     for (int c = 0; c < 6; c++) cv[c] = 0;
-    if (valid && k > 0 && k < tc.k1) {
+    if (!first && valid && k > 0 && k < tc.k1) {
       const int64_t n = col + d.plane * k;
 #pragma unroll
       for (int c = 0; c < 3; c++) {
@@ -1314,7 +1320,7 @@ __global__ __launch_bounds__(kThreads, 4) void fem_cg_a_kernel(Dims d, TileMap t
       for (int c = 0; c < 3; c++) {
         const T pc = ring[s0][c][ly + 1][lx + 1];
         p_new[c * N + n] = pc;
-        x[c * N + n] = cv[3 + c] + alpha * cv[c];
+        if (!first) x[c * N + n] = cv[3 + c] + alpha * cv[c];
         acc += (double)pc * q[c];
       }
     }
