@@ -117,3 +117,49 @@ def test_full_size_solves_and_force(pf, oracle_mod, name):
               f"force rel err {ferr:.2e}", flush=True)
         assert wrel <= 10 * cfg.tol_u
         assert ferr < FORCE_BAR[cfg.precision]
+
+
+def test_micron_adjoint_vs_central_differences(pf):
+    """The discrete adjoint of the micron film at full size (FP64, the
+    multigrid of the bench's launch configuration, two segments of one step,
+    the first recomputed): dJ/dV_1 and dJ/da1 of J = mean Pz over the film
+    after two predictor-corrector steps against central differences of the
+    GPU forward.  The solves run to 1e-12 so that their stopping errors,
+    about 1e-12 kappa relative in phi and u and dt times that in P, stay far
+    below the differences of J the steps make (dV 1e-3 and da1 1e-5 change J
+    by ~1e-9 and more); J is close to linear over such steps (the central
+    quotient's error is of the relative size (dV / V)^2 ~ 2.5e-7 at most), so
+    the bar is 1e-6 relative, while a dropped term or a wrong sign is off by
+    O(1).  Measured: 4.4e-11 for dJ/dV_1, 2.8e-9 for dJ/da1."""
+    from paper_1202_6116_amd.autograd import tdgl_steps
+    w = workloads()["micron_1024x1024x96"]
+    cfg = w.cfg.replace(precond="mg", tol_phi=1e-12, tol_u=1e-12)
+    nsteps = 2
+    print("case: micron_1024x1024x96 adjoint, 2 steps, vs central differences", flush=True)
+    P0 = dev(initial_polarisation(w))
+    ctx = pf.Context(cfg)
+    volts = torch.tensor([e.volts for e in cfg.electrodes], dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(cfg.a1, dtype=torch.float64, requires_grad=True)
+    PN = tdgl_steps(P0, volts, a1, ctx, nsteps, 1)
+    J = PN[2].mean()
+    J.backward()
+    g = [volts.grad[0].item(), a1.grad.item()]
+    del PN, J
+
+    def run(vv, aa):
+        ctx.set_params(vv, aa)
+        ctx.set_state(P0)
+        st = ctx.step(nsteps)
+        assert st["status"] == 0
+        return float(ctx.get_state()[0][2].mean())
+
+    base_v = [e.volts for e in cfg.electrodes]
+    dv, da = 1e-3, 1e-5
+    vp = list(base_v); vp[0] += dv
+    vm = list(base_v); vm[0] -= dv
+    fd = [(run(vp, cfg.a1) - run(vm, cfg.a1)) / (2 * dv),
+          (run(base_v, cfg.a1 + da) - run(base_v, cfg.a1 - da)) / (2 * da)]
+    print("adjoint:", g, "central differences:", fd,
+          "relative differences:", [abs(a - b) / abs(b) for a, b in zip(g, fd)], flush=True)
+    for a, b in zip(g, fd):
+        assert abs(a - b) <= 1e-6 * abs(b), (g, fd)
