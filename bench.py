@@ -49,9 +49,9 @@ TARGET_FRAC = 0.60
 # commands and figures in profiles/.  Anything else reports null.
 MEASURED_TRAFFIC = {
     ("micron_1024x1024x96", "fp64", "mg_u0"): 5.143e9,
-    ("micron_1024x1024x96_fp32", "fp32_refine", "mg_u0"): 2.078e9,
-    ("lateral_512x512x128_fp32", "fp32_refine", "mg_u0"): 0.774e9,
-    ("lateral_512x512x128_fp32", "fp32_refine", "mg"): 0.650e9,
+    ("micron_1024x1024x96_fp32", "fp32_refine", "mg_u0"): 1.918e9,
+    ("lateral_512x512x128_fp32", "fp32_refine", "mg_u0"): 0.560e9,
+    ("lateral_512x512x128_fp32", "fp32_refine", "mg"): 0.906e9,
 }
 
 
