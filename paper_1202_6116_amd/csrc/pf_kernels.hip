@@ -2662,14 +2662,16 @@ __global__ __launch_bounds__(kThreads, 3) void force_kernel(
           for (int c = 0; c < 3; c++) Vn[c * N + n] = F[c];
           break;
         case kPcStep:
-          // P + dt V' = Pp + dt (V' - V) with Pp = P + dt V the staged
-          // predictor (cdt = dt here): P is not read again
+          // FP64: P + dt V' = Pp + dt (V' - V) with Pp = P + dt V the staged
+          // predictor (cdt = dt here), so P is not read again; FP32 reads P
+          // again, as the extra rounding of Pp would show in the state
 #pragma unroll
           for (int c = 0; c < 3; c++) {
             const T v = V[c * N + n];
             const T vn = (T)0.5 * (v + F[c]);
             Vn[c * N + n] = vn;
-            Pn[c * N + n] = p0[c] + cf.dt * (vn - v);
+            if constexpr (sizeof(T) == sizeof(double)) Pn[c * N + n] = p0[c] + cf.dt * (vn - v);
+            else Pn[c * N + n] = P[c * N + n] + cf.dt * vn;
           }
           break;
         default:  // kEulerStep: Pp = P (cdt = 0, no V)
