@@ -1,7 +1,10 @@
 """Writes the FP64 oracle's states of the 512x512x128 lateral-switching film
-(sampled columns) for the full-size parity test of the FP32 + refinement path.
+(sampled columns) for the full-size parity test of the FP32 + refinement path,
+or (--workload lateral_256x256x64) those of the 256x256x64 film of the FP64
+benchmark leg.
 
     OMP_NUM_THREADS=8 python tests/golden/make_lateral_512_oracle.py [--steps 1 2 3 4]
+    OMP_NUM_THREADS=8 python tests/golden/make_lateral_512_oracle.py --workload lateral_256x256x64 --steps 1 2
 
 Calls only the oracle (oracle/pf_oracle.py) and the seeded input generator.
 The film is the one the benchmark's precision leg runs: 512x512x128 nodes,
@@ -13,7 +16,7 @@ extrapolating the earlier solutions within each call of the oracle's step).
 After or_set_state (the initial rate V0 = F(P0) and its two cold solves) and
 after each chunk of steps, the state (P, V, phi, u) is sampled on the
 columns x = 8 + 32a, y = 16 + 64b (all z) and written to
-lateral_512x512x128_oracle_step<n>.npz together with each field's largest
+lateral_<nx>x<ny>x<nz>_oracle_step<n>.npz together with each field's largest
 magnitude over the whole film (the scale the relative errors are quoted
 against) and the solver's iteration counts.  The oracle's CG takes about
 three seconds per FEM iteration and its FEM right-hand side about two
@@ -36,9 +39,9 @@ sys.path.insert(0, ROOT)
 from oracle.pf_oracle import Oracle  # noqa: E402
 from paper_1202_6116_amd.workloads import initial_polarisation, workloads  # noqa: E402
 
-WORKLOAD = "lateral_512x512x128_fp32"
-XS = np.arange(8, 512, 32)
-YS = np.arange(16, 512, 64)
+WORKLOADS = ("lateral_512x512x128_fp32", "lateral_256x256x64")
+XS = YS = None
+WORKLOAD = PREFIX = None
 
 
 def sample(a):
@@ -47,7 +50,7 @@ def sample(a):
 
 
 def write(step, P, V, phi, u, stats, seconds):
-    out = os.path.join(HERE, f"lateral_512x512x128_oracle_step{step}.npz")
+    out = os.path.join(HERE, f"{PREFIX}_oracle_step{step}.npz")
     tmp = out + ".tmp.npz"
     np.savez_compressed(
         tmp, P=sample(P), V=sample(V), phi=sample(phi), u=sample(u), xs=XS, ys=YS,
@@ -62,8 +65,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, nargs="*", default=[1, 2, 3, 4],
                     help="chunks of steps; a snapshot is written after each")
+    ap.add_argument("--workload", default=WORKLOADS[0], choices=WORKLOADS)
     args = ap.parse_args()
+    global XS, YS, WORKLOAD, PREFIX
+    WORKLOAD = args.workload
     w = workloads()[WORKLOAD]
+    nz, ny, nx = w.cfg.shape
+    PREFIX = f"lateral_{nx}x{ny}x{nz}"
+    XS = np.arange(8, nx, 32)
+    YS = np.arange(16, ny, 64)
     cfg = w.cfg.replace(precision="fp64", precond="jacobi", warm_start=2, maxit=50000)
     o = Oracle(cfg)
     P = initial_polarisation(w)
